@@ -1,0 +1,249 @@
+"""Throughput of the pair-sum hot path on one MI355X.
+
+One step = the whole hot path on the 99,999-atom water box (33,333 rigid
+waters, L = 99.7 A, seeded random start): 10 Metropolis sweeps (333,330
+trial moves, each a minimum-image pair sum against every atom), then the
+exact pair-count histogram over all 4,999,850,001 pairs (1660 bins of
+0.03 A), g(r) and S(Q) at 1000 Q points (Eq. 1).
+
+Prints one JSON line.  `value` is MC moves per second over whole steps
+(histogram and S(Q) time included).  Extra fields report the pair-distance
+rate, the per-kernel roofline of the dominant kernel (timed with HIP events
+inside the timed region), the differentiated form (forward+backward) and
+the oracle on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Peak VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one non-packed FP32 or FP64 lane operation per lane per clock).
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# Minimum VALU lane operations per distance test of the Metropolis scan in
+# fractional coordinates: 3 sub + 3 round + 3 sub (nearest image), 3 for r^2,
+# 1 compare with the cutoff.
+OPS_PER_TEST = 13
+# Minimum VALU lane operations per pair of the exact FP64 histogram:
+# 3 sub, 3 mul, 3 round, 3 fma (nearest image), 3 (r^2), 1 range compare,
+# 4 (candidate bin: cvt, sqrt, mul, cvt), 3 (edge test: fract, compare),
+# 2 (address).
+OPS_PER_PAIR = 25
+PAPER_GPU_STEPS_PER_S_1E5 = 12412.0  # Table "tab_speed", water, 1e5 atoms, Tesla V100
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(box, T, mc):
+    """The FP64 oracle on the host cores, on a bounded sample of the same step."""
+    import numpy as np
+
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    threads = oracle.max_threads()
+    xyz = box.xyz.copy()
+    n_mc = 2000
+    t0 = time.perf_counter()
+    oracle.mc_run(box, T, xyz, mc["kT"], mc["max_disp"], mc["max_rot"], mc["seed"], 0, n_mc)
+    t_mc = time.perf_counter() - t0
+    moves_per_s = n_mc / t_mc
+    # histogram rate on all pairs of the first n_sub atoms (same box and bins)
+    n_sub = 30000
+    sub = np.ascontiguousarray(box.xyz[:, :n_sub])
+    t0 = time.perf_counter()
+    oracle.pair_histogram(sub, mc["dr"], mc["nbins"], L=box.L, species=box.species[:n_sub], n_species=2)
+    t_h = time.perf_counter() - t0
+    n_pairs_sample = n_sub * (n_sub - 1) / 2
+    pairs_per_s = n_pairs_sample / t_h
+    n_trials = 10 * box.n_units
+    n_pairs = box.n_atoms * (box.n_atoms - 1) / 2
+    step_s = n_trials / moves_per_s + n_pairs / pairs_per_s
+    return {
+        "value": n_trials / step_s, "unit": "MC moves/s", "cores": threads, "kind": "oracle",
+        "sample": (f"{n_mc} Metropolis trials on the 99,999-atom water box ({t_mc:.1f} s) and the exact "
+                   f"histogram of its first {n_sub} atoms ({int(n_pairs_sample)} pairs, {t_h:.1f} s); "
+                   f"one whole step's time extrapolated from the two rates"),
+        "mc_moves_per_s": moves_per_s, "hist_pairs_per_s": pairs_per_s,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the forward+backward and SiO2 legs")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the pair-sum path runs on a single MI355X here; "
+              "see DESIGN.md for how it would shard", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1904_08756_amd as nd
+    import synthetic as syn
+
+    torch.cuda.set_device(0)
+    box, T, mc = syn.config_c2()
+    log(f"bench: {box.name} N={box.n_atoms} L={box.L}")
+    g = nd.Box.from_synthetic(box)
+    g.set_tables(T.U, T.h, T.r_cut)
+    g.total_energy()
+    params = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"])
+    n_trials = mc["n_trials"]
+    dr, nbins = mc["dr"], mc["nbins"]
+    npairs = nd.pair_counts_total(g)
+    V = box.L ** 3
+    rho = box.n_atoms / V
+    w, self_term = nd.eq1_weights(g, syn.water_b(0.0))
+    Q = torch.as_tensor(syn.q_grid(), device="cuda")
+    counts = torch.empty((g.P, nbins), dtype=torch.int64, device="cuda")
+    n_tests_per_trial = 2 * 3 * (box.n_atoms - 3)
+    n_pairs = box.n_atoms * (box.n_atoms - 1) // 2
+
+    def step(s):
+        g.mc_sweep(params, mc["seed"], s * n_trials, n_trials, stats=False)
+        nd.pair_histogram(g, dr, nbins, out=counts)
+        gr = nd.gr_normalize(counts, dr, V, npairs)
+        return nd.sq_transform(gr, dr, rho, w, self_term, Q)
+
+    for s in range(args.warmup):
+        step(s)
+        torch.cuda.synchronize()
+        log(f"warmup step {s} done")
+    g.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.warmup, args.warmup + args.steps):
+        S = step(s)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+    prof = {k: g.profile(k) for k in ("mc_scan", "mc_corr", "mc_decide", "mc_propose", "pair_hist")}
+    g.set_profiling(False)
+    assert np.all(np.isfinite(S.cpu().numpy()))
+
+    ms_per_step = 1000.0 * elapsed / args.steps
+    moves_per_s = n_trials * args.steps / elapsed
+    dist_per_s = (n_trials * n_tests_per_trial + n_pairs) * args.steps / elapsed
+
+    scan_n, scan_ms = prof["mc_scan"]
+    tests_per_launch = n_trials * n_tests_per_trial * args.steps / max(scan_n, 1)
+    scan_avg_s = scan_ms / max(scan_n, 1) / 1e3
+    scan_achieved = tests_per_launch * OPS_PER_TEST / scan_avg_s
+    hist_n, hist_ms = prof["pair_hist"]
+    hist_avg_s = hist_ms / max(hist_n, 1) / 1e3
+    hist_achieved = n_pairs * OPS_PER_PAIR / hist_avg_s
+
+    result = {
+        "metric": "MC moves/s + pair distances/s at 100k atoms; fwd+bwd & batched vs plain",
+        "value": moves_per_s,
+        "unit": "MC moves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": moves_per_s / PAPER_GPU_STEPS_PER_S_1E5,
+        "dtype": "f32 pair terms, f64 sums and distances",
+        "data": "synthetic (seeded random rigid-water start; no experimental data)",
+        "config": {"workload": "water 99,999 atoms (33,333 rigid H2O, L=99.7 A): 10 MC sweeps "
+                               "+ exact pair histogram (1660 x 0.03 A bins) + g(r) + S(Q) at 1000 Q",
+                   "n_atoms": box.n_atoms, "trials_per_step": n_trials, "pairs_per_step": n_pairs,
+                   "parallelism": "single GPU"},
+        "pair_distances_per_s": dist_per_s,
+        "roofline": {
+            "kernel": "k_mc_scan (Metropolis pair-sum scan)",
+            "bound": "alu", "achieved": scan_achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "Tlane-op/s", "frac": scan_achieved / PEAK_LANE_OPS, "traffic": None,
+            "launches": scan_n, "avg_launch_us": scan_avg_s * 1e6,
+            "algorithmic_per_launch": f"{tests_per_launch:.4g} distance tests x {OPS_PER_TEST} lane-ops",
+        },
+        "kernels": {
+            k: {"launches": n, "ms_total": ms, "share_of_step_time": ms / (1000.0 * elapsed)}
+            for k, (n, ms) in prof.items()
+        },
+        "roofline_pair_hist": {
+            "bound": "alu", "achieved": hist_achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "Tlane-op/s", "frac": hist_achieved / PEAK_LANE_OPS,
+            "pairs_per_s": n_pairs / hist_avg_s, "avg_launch_ms": hist_avg_s * 1e3,
+        },
+        "paper_context": {"gpu_steps_per_s_1e5_atoms": PAPER_GPU_STEPS_PER_S_1E5,
+                          "hardware": "NVIDIA Tesla V100 (Table tab_speed)",
+                          "cpu_serial_steps_per_s_1e5_atoms": 62.67},
+    }
+
+    if not args.no_extras:
+        # differentiated form on the same box: forward (broadened histogram,
+        # g, S, chi^2) + backward (adjoint, pair gradient), against the plain
+        # histogram + g + S on the same box
+        sig = 0.02
+        target = torch.as_tensor(20.5 + 0.5 * np.sin(syn.q_grid()), device="cuda")
+        x = torch.as_tensor(g.coords_host(), device="cuda")
+
+        def plain():
+            nd.pair_histogram(g, dr, nbins, out=counts)
+            return nd.sq_transform(nd.gr_normalize(counts, dr, V, npairs), dr, rho, w, self_term, Q)
+
+        def fwd_bwd():
+            xx = x.clone().requires_grad_(True)
+            c2 = nd.Chi2Fn.apply(xx, g, dr, nbins, sig, Q, target, syn.water_b(0.0))
+            c2.backward()
+            return xx.grad
+
+        def timeit(fn, reps=3):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            return float(np.median(ts))
+
+        t_plain = timeit(plain)
+        t_fb = timeit(fwd_bwd)
+        t_forces = timeit(lambda: nd.forces(g))
+        result["forms"] = {
+            "plain_hist_g_sq_ms": t_plain * 1e3,
+            "fwd_bwd_ms": t_fb * 1e3,
+            "fwd_bwd_over_plain": t_fb / t_plain,
+            "forces_ms": t_forces * 1e3,
+            "fwd_bwd_pairs_per_s": 2 * n_pairs / t_fb,
+            "batched": None,
+        }
+        log("forms done")
+        # SiO2 box: one sweep of single-atom moves
+        box3, T3, mc3 = syn.config_c3()
+        g3 = nd.Box.from_synthetic(box3)
+        g3.set_tables(T3.U, T3.h, T3.r_cut)
+        p3 = nd.MCParams(mc3["kT"], mc3["max_disp"], 0.0)
+        g3.mc_sweep(p3, mc3["seed"], 0, 20000, stats=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g3.mc_sweep(p3, mc3["seed"], 20000, box3.n_units, stats=False)
+        torch.cuda.synchronize()
+        result["sio2_mc_moves_per_s"] = box3.n_units / (time.perf_counter() - t)
+        log("sio2 done")
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        result["cpu_baseline"] = cpu_baseline(box, T, mc)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,268 @@
+/*
+ * neuda.h - C ABI of the MI355X pair-sum library for EPSR-style structure
+ * refinement (Ma et al., "NeuDATool", arXiv 1904.08756).
+ *
+ * The library computes the data-parallel hot path of the method on one
+ * gfx950 GPU:
+ *   - the minimum-image pair sum that gives the energy change of a trial
+ *     move of one rigid unit against every other atom, followed by the
+ *     Metropolis test (Sec. "Algorithmic Flow", step III; Sec. "Acceleration
+ *     method": the per-step Delta N(r) work that is proportional to N);
+ *   - the all-pairs partial histograms N_ab(r) (Sec. "Acceleration method":
+ *     the N(r) work that is proportional to N^2), their normalisation to
+ *     g_ab(r), and the sine transform to S(Q) of Eq. 1;
+ *   - a Gaussian-broadened histogram with the gradient of a chi^2 misfit in
+ *     S(Q) with respect to every coordinate, and the energy gradient.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an nd_status; ND_OK is 0, errors are negative.
+ *     nd_last_error() returns a thread-local description of the last error
+ *     (valid until the next call on the same thread).  No C++ exception
+ *     crosses this boundary.
+ *   - All arguments are validated before any device work is enqueued.  A
+ *     call that fails leaves the box unchanged unless stated otherwise.
+ *   - Coordinates are float32 in structure-of-arrays order [3][N]: all x,
+ *     then all y, then all z, each in [0, L) of a cubic periodic box.
+ *   - `where` says where a caller pointer lives: ND_HOST (pageable or pinned
+ *     host memory; the call copies and synchronises) or ND_DEVICE (device
+ *     memory on the machine's GPU; the call is asynchronous on the box's stream
+ *     and the caller synchronises before reading results).
+ *   - The caller owns every array it passes.  Host inputs are copied; the
+ *     library keeps no caller pointer after a call returns.
+ *   - Species are 0 .. M-1 with M <= ND_MAX_SPECIES.  The P = M(M+1)/2 pair
+ *     types (a <= b) are ordered (0,0), (0,1), ..., (0,M-1), (1,1), ...: the
+ *     index of (a, b) is a*M - a(a-1)/2 + (b - a).
+ *   - A box is used by one host thread at a time.
+ */
+#ifndef NEUDA_H
+#define NEUDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nd_status;
+
+#define ND_OK 0
+#define ND_E_INVALID (-1)     /* NULL pointer, NaN input, bad size or flag       */
+#define ND_E_RANGE (-2)       /* cutoff or histogram range beyond L/2, species  */
+#define ND_E_OOM (-3)         /* device allocation failed                        */
+#define ND_E_HIP (-4)         /* HIP runtime or kernel launch failure            */
+#define ND_E_STATE (-5)       /* call not valid in the box's state (no tables)   */
+#define ND_E_UNSUPPORTED (-6) /* valid request this build does not implement     */
+
+#define ND_HOST 0
+#define ND_DEVICE 1
+
+#define ND_ORDER_SEQ 0    /* trial t moves unit t mod n_units                    */
+#define ND_ORDER_RANDOM 1 /* trial t moves a unit drawn from the trial's draws   */
+
+#define ND_MAX_SPECIES 4
+#define ND_MAX_UNIT_ATOMS 8
+#define ND_ABI_VERSION 1
+
+typedef struct nd_box nd_box;
+
+/* Description of a periodic box of atoms grouped into rigid units (the
+ * paper's Atom / Molecule / SimBox classes, Sec. "Algorithmic Flow" I).
+ * All pointers are host pointers and are copied by nd_box_create. */
+typedef struct nd_box_desc {
+    int32_t n_atoms;              /* N >= 2                                     */
+    int32_t n_species;            /* M, 1 .. ND_MAX_SPECIES                      */
+    double L;                     /* box edge in Angstrom, > 0                   */
+    const uint8_t *species;       /* [N], values < M                             */
+    int32_t n_units;              /* >= 1                                        */
+    const int32_t *unit_offsets;  /* [n_units + 1], 0 = off[0] < off[1] < ... = N,
+                                     at most ND_MAX_UNIT_ATOMS atoms per unit    */
+    const float *xyz;             /* [3][N] in [0, L)                            */
+    int32_t device;               /* HIP device ordinal                          */
+    void *stream;                 /* hipStream_t for all work, NULL = default   */
+} nd_box_desc;
+
+/* Parameters of a Metropolis run (Sec. "Algorithmic Flow" III). */
+typedef struct nd_mc_params {
+    double kT;          /* kJ/mol, > 0                                            */
+    double max_disp;    /* translation half-width per axis, Angstrom, >= 0        */
+    double max_rot;     /* rotation half-angle, radians, >= 0 (units of >1 atom)  */
+    int32_t order;      /* ND_ORDER_SEQ or ND_ORDER_RANDOM                        */
+    int32_t k_batch;    /* trials evaluated together; 0 = chosen by the library   */
+    double tie_rel;     /* near-tie threshold (see nd_mc_sweep); 0 = 1e-6         */
+} nd_mc_params;
+
+/* Counters of one nd_mc_sweep call. */
+typedef struct nd_mc_stats {
+    int64_t trials;     /* trials evaluated                                       */
+    int64_t accepted;   /* trials accepted                                        */
+    int64_t near_ties;  /* decisions within the near-tie band                     */
+    double E_total;     /* running total energy after the call                    */
+    double dE_sum;      /* sum of accepted energy changes                         */
+} nd_mc_stats;
+
+/* Optional per-trial record of nd_mc_sweep: device arrays of n_trials. */
+typedef struct nd_mc_trace {
+    double *dE;         /* energy change of each trial (accepted or not)          */
+    double *sabs;       /* sum over the trial's pair terms of |U| (old and new)  */
+    uint8_t *accepted;  /* 1 if accepted                                          */
+    int32_t *unit;      /* unit moved by the trial                                */
+} nd_mc_trace;
+
+int32_t nd_abi_version(void);
+const char *nd_last_error(void);
+
+/* Creates a box on desc->device.  Copies species, units and coordinates to
+ * the device.  *out receives the handle; nd_box_destroy releases it.
+ * Errors: ND_E_INVALID (bad sizes, NULL, NaN or out-of-box coordinates,
+ * species >= M, non-increasing offsets, units larger than
+ * ND_MAX_UNIT_ATOMS), ND_E_OOM, ND_E_HIP. */
+nd_status nd_box_create(const nd_box_desc *desc, nd_box **out);
+
+/* Releases the box and its device memory after its stream drains.
+ * NULL is accepted. */
+nd_status nd_box_destroy(nd_box *box);
+
+/* Sets the stream used by later calls on the box (NULL = default stream). */
+nd_status nd_box_set_stream(nd_box *box, void *stream);
+
+/* Replaces all coordinates ([3][N], where = ND_HOST or ND_DEVICE).  Host
+ * input is validated (finite, in [0, L)); device input is taken as is.
+ * keep_energy = 0 marks the running energy stale (nd_box_total_energy
+ * recomputes it); 1 keeps the running value (the caller asserts the
+ * energy did not change). */
+nd_status nd_box_set_coords(nd_box *box, const float *xyz, int32_t where, int32_t keep_energy);
+
+/* Copies the current coordinates ([3][N]) out. */
+nd_status nd_box_get_coords(nd_box *box, float *xyz, int32_t where);
+
+/* Sets the tabulated pair potentials U_p(k h), k = 0 .. n_pts-1 (host
+ * float32 [P][n_pts]): reference potential plus empirical potential per
+ * pair type (Sec. "Algorithmic Principle").  Between grid points the
+ * energy is the linear interpolant; it is zero for r >= r_cut.
+ * Requires h > 0, r_cut <= L/2 and n_pts >= r_cut/h + 1.  Pairs inside one
+ * unit are excluded from all energies.  Errors: ND_E_INVALID, ND_E_RANGE. */
+nd_status nd_box_set_tables(nd_box *box, const float *U, int32_t n_pts, double h, double r_cut);
+
+/* Recomputes the total energy over all pairs in different units from
+ * scratch (FP32 pair terms, FP64 sum), stores it as the running total and
+ * writes it to *E (host).  Synchronises the box's stream. */
+nd_status nd_box_total_energy(nd_box *box, double *E);
+
+/* Reads the running total energy (host).  Synchronises the stream. */
+nd_status nd_box_energy(nd_box *box, double *E);
+
+/* Runs trials first_trial .. first_trial + n_trials - 1 of the Metropolis
+ * chain (Sec. "Algorithmic Flow" III): trial t proposes a translation
+ * (uniform in [-max_disp, max_disp] per axis) and, for units of more than
+ * one atom, a rotation by an angle uniform in [-max_rot, max_rot] about a
+ * uniform axis through the unit's unweighted centroid; the energy change
+ * dE of the unit against every atom outside it decides acceptance:
+ * accept iff dE <= 0 or u < exp(-dE/kT).  Random draws come from
+ * SplitMix64 seeded with `seed` (output 16 t + d is draw d of trial t), so
+ * a run split over several calls equals one call over the same trials.
+ * The result equals the sequential chain; trials are evaluated in batches
+ * whose interactions are corrected exactly.  A decision with
+ * |ln u + dE/kT| < tie_rel * sabs / kT is counted as a near tie.
+ * stats (host, may be NULL) synchronises; trace (device arrays, may be
+ * NULL) records every trial.  Errors: ND_E_INVALID, ND_E_STATE (no
+ * tables), ND_E_UNSUPPORTED (ND_ORDER_RANDOM), ND_E_HIP. */
+nd_status nd_mc_sweep(nd_box *box, const nd_mc_params *params, uint64_t seed,
+                      uint64_t first_trial, int64_t n_trials, nd_mc_stats *stats,
+                      const nd_mc_trace *trace);
+
+/* Pair-count histogram N_p(k) of every unordered pair i < j (atoms of one
+ * unit included), counts uint64 [P][nbins].  Per pair, in FP64: the
+ * nearest-image displacement of the float32 coordinates, r2 =
+ * fma(dz,dz, fma(dy,dy, dx*dx)), and bin k = max{k : (k dr)^2 <= r2},
+ * counted iff r2 < (nbins dr)^2.  Counts are exact.  Requires dr > 0,
+ * nbins >= 1 and nbins*dr < L/2 (1 - 1e-9).  Errors: ND_E_INVALID,
+ * ND_E_RANGE, ND_E_OOM, ND_E_HIP. */
+nd_status nd_pair_histogram(nd_box *box, double dr, int32_t nbins, uint64_t *counts, int32_t where);
+
+/* g_p(k) = n_p(k) / (npairs_p Vshell(k) / V), Vshell(k) = (4 pi/3)((k+1)^3 -
+ * k^3) dr^3, for counts uint64 [P][nbins] and npairs double [P] (host).
+ * Output g double [P][nbins].  counts and g live in `where`. */
+nd_status nd_gr_normalize(const uint64_t *counts, int32_t P, int32_t nbins, double dr, double V,
+                          const double *npairs, double *g, int32_t where, void *stream);
+
+/* As nd_gr_normalize for real-valued counts (double [P][nbins]), such as the
+ * Gaussian-broadened histogram of nd_hist_broad. */
+nd_status nd_gr_normalize_f64(const double *counts, int32_t P, int32_t nbins, double dr, double V,
+                              const double *npairs, double *g, int32_t where, void *stream);
+
+/* Number of distinct atom pairs of each pair type (host double [P]):
+ * N_a (N_a - 1)/2 for like species, N_a N_b for unlike species (the pair
+ * counts that normalise g_ab(r), Eq. 1). */
+nd_status nd_box_pair_counts(nd_box *box, double *npairs);
+
+/* Eq. 1 coefficients of the box for scattering lengths b (host double [M]):
+ * w_p = (2 - delta_ab) c_a c_b b_a b_b (host double [P]) and the flat term
+ * sum_a c_a b_a^2, with c_a = N_a / N the atomic fractions. */
+nd_status nd_eq1_weights(nd_box *box, const double *b, double *w, double *self_term);
+
+/* chi^2 = sum_i (S_i - T_i)^2 over nQ points and its gradient
+ * dchi^2/dS_i = 2 (S_i - T_i).  S, T, grad (double [nQ], grad may be NULL)
+ * and chi2 (double [1]) live in `where`. */
+nd_status nd_chi2(const double *S, const double *T, int32_t nQ, double *chi2, double *grad,
+                  int32_t where, void *stream);
+
+/* Eq. 1 by the midpoint rule on r_k = (k + 1/2) dr:
+ *   S(Q_i) = self_term + sum_p w_p 4 pi rho sum_k r_k^2 (g_p(k) - 1) sinc(Q_i r_k) dr
+ * with w_p = (2 - delta_ab) c_a c_b b_a b_b (host double [P]) and
+ * self_term = sum_a c_a b_a^2.  g double [P][nbins], Q double [nQ] and
+ * S double [nQ] live in `where`.  FP64 throughout. */
+nd_status nd_sq_transform(const double *g, int32_t P, int32_t nbins, double dr, double rho,
+                          const double *w, double self_term, const double *Q, int32_t nQ,
+                          double *S, int32_t where, void *stream);
+
+/* Gaussian-broadened histogram: each pair with r < L/2 adds
+ * Phi((e_{k+1} - r)/sigma) - Phi((e_k - r)/sigma), e_k = k dr, to the bins
+ * that intersect [r - 6 sigma, r + 6 sigma].  nhat double [P][nbins]. */
+nd_status nd_hist_broad(nd_box *box, double dr, int32_t nbins, double sigma, double *nhat,
+                        int32_t where);
+
+/* Adjoint of nd_gr_normalize followed by nd_sq_transform: given dL/dS
+ * (double [nQ]), A_p(k) = sum_i dL/dS_i w_p 4 pi rho r_k^2 sinc(Q_i r_k) dr /
+ * (npairs_p Vshell(k)/V).  dLdS, Q and A ([P][nbins]) live in `where`. */
+nd_status nd_sq_adjoint(const double *dLdS, int32_t P, int32_t nbins, double dr, double rho,
+                        double V, const double *w, const double *npairs, const double *Q,
+                        int32_t nQ, double *A, int32_t where, void *stream);
+
+/* Backward of nd_hist_broad: given A = dL/dnhat (double [P][nbins]), writes
+ * dL/dx (double [3][N]) = sum over pairs of dL/dr (x_i - x_j)/r with
+ * dL/dr = sum_k A_p(k) (phi((e_k - r)/sigma) - phi((e_{k+1} - r)/sigma))/sigma. */
+nd_status nd_hist_broad_backward(nd_box *box, double dr, int32_t nbins, double sigma,
+                                 const double *A, double *dLdx, int32_t where);
+
+/* Energy gradient dE/dx (double [3][N]) over pairs in different units with
+ * r < r_cut, using the slope of the interpolated table, and the total
+ * energy E (host double, may be NULL). */
+nd_status nd_forces(nd_box *box, double *dEdx, double *E, int32_t where);
+
+/* Per-kernel timing with HIP events on the box's stream, for measurement.
+ * Kernel ids for nd_box_profile. */
+#define ND_PROF_MC_SCAN 0       /* pair-sum scan of a batch of trials        */
+#define ND_PROF_MC_CORR 1       /* in-batch interaction corrections           */
+#define ND_PROF_MC_DECIDE 2     /* Metropolis decisions and commit            */
+#define ND_PROF_MC_PROPOSE 3    /* trial proposals                            */
+#define ND_PROF_PAIR_HIST 4     /* pair-count histogram (main kernel)         */
+#define ND_PROF_HIST_BROAD 5    /* broadened histogram (main kernel)          */
+#define ND_PROF_HIST_BROAD_BWD 6 /* broadened histogram backward              */
+#define ND_PROF_FORCES 7        /* energy gradient                            */
+#define ND_PROF_KINDS 8
+
+/* enable = 1 starts recording an event pair around every launch of the
+ * kernels above on this machine and clears the totals; 0 stops recording. */
+nd_status nd_box_set_profiling(nd_box *box, int32_t enable);
+
+/* Synchronises the box's stream and returns the number of recorded launches
+ * of `kernel` and their summed duration in milliseconds since profiling was
+ * enabled.  Errors: ND_E_INVALID for an unknown kernel id. */
+nd_status nd_box_profile(nd_box *box, int32_t kernel, int64_t *launches, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEUDA_H */

@@ -1,0 +1,487 @@
+"""Python binding of the MI355X pair-sum library (include/neuda.h).
+
+Thin ctypes layer: it marshals arguments to the C ABI and allocates device
+outputs with torch; every step of the computation runs in the HIP kernels
+of libneuda.so.  There is no CPU fallback: if the library is missing or no
+GPU is present, the calls raise.
+
+Method: Ma et al., "NeuDATool" (arXiv 1904.08756) -- the Metropolis pair sum
+of Sec. "Algorithmic Flow" III, the N(r) histogram of Sec. "Acceleration
+method", and Eq. 1.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = [
+    "lib", "build", "Box", "MCParams", "pair_histogram", "gr_normalize", "sq_transform",
+    "sq_adjoint", "hist_broad", "hist_broad_backward", "forces", "Chi2Fn", "EnergyFn",
+    "chi2", "gr_normalize_f64", "pair_counts_total", "eq1_weights",
+    "ND_HOST", "ND_DEVICE", "NeudaError",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libneuda.so")
+
+ND_HOST = 0
+ND_DEVICE = 1
+ND_ORDER_SEQ = 0
+ND_ORDER_RANDOM = 1
+PROF = {"mc_scan": 0, "mc_corr": 1, "mc_decide": 2, "mc_propose": 3, "pair_hist": 4,
+        "hist_broad": 5, "hist_broad_bwd": 6, "forces": 7}
+STATUS = {0: "ND_OK", -1: "ND_E_INVALID", -2: "ND_E_RANGE", -3: "ND_E_OOM", -4: "ND_E_HIP",
+          -5: "ND_E_STATE", -6: "ND_E_UNSUPPORTED"}
+
+
+class NeudaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class nd_box_desc(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("n_species", C.c_int32), ("L", C.c_double),
+                ("species", C.c_void_p), ("n_units", C.c_int32), ("unit_offsets", C.c_void_p),
+                ("xyz", C.c_void_p), ("device", C.c_int32), ("stream", C.c_void_p)]
+
+
+class nd_mc_params(C.Structure):
+    _fields_ = [("kT", C.c_double), ("max_disp", C.c_double), ("max_rot", C.c_double),
+                ("order", C.c_int32), ("k_batch", C.c_int32), ("tie_rel", C.c_double)]
+
+
+class nd_mc_stats(C.Structure):
+    _fields_ = [("trials", C.c_int64), ("accepted", C.c_int64), ("near_ties", C.c_int64),
+                ("E_total", C.c_double), ("dE_sum", C.c_double)]
+
+
+class nd_mc_trace(C.Structure):
+    _fields_ = [("dE", C.c_void_p), ("sabs", C.c_void_p), ("accepted", C.c_void_p),
+                ("unit", C.c_void_p)]
+
+
+EXPORTS = {
+    "nd_abi_version": (C.c_int32, []),
+    "nd_last_error": (C.c_char_p, []),
+    "nd_box_create": (C.c_int32, [C.POINTER(nd_box_desc), C.POINTER(C.c_void_p)]),
+    "nd_box_destroy": (C.c_int32, [C.c_void_p]),
+    "nd_box_set_stream": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "nd_box_set_coords": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    "nd_box_get_coords": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "nd_box_set_tables": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double]),
+    "nd_box_total_energy": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double)]),
+    "nd_box_energy": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double)]),
+    "nd_mc_sweep": (C.c_int32, [C.c_void_p, C.POINTER(nd_mc_params), C.c_uint64, C.c_uint64,
+                                C.c_int64, C.POINTER(nd_mc_stats), C.POINTER(nd_mc_trace)]),
+    "nd_pair_histogram": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32, C.c_void_p, C.c_int32]),
+    "nd_gr_normalize": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                    C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "nd_sq_transform": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                    C.c_void_p, C.c_double, C.c_void_p, C.c_int32, C.c_void_p,
+                                    C.c_int32, C.c_void_p]),
+    "nd_hist_broad": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32, C.c_double, C.c_void_p,
+                                  C.c_int32]),
+    "nd_sq_adjoint": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                  C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.c_void_p, C.c_int32, C.c_void_p]),
+    "nd_hist_broad_backward": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32, C.c_double,
+                                           C.c_void_p, C.c_void_p, C.c_int32]),
+    "nd_forces": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_int32]),
+    "nd_gr_normalize_f64": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                        C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "nd_box_pair_counts": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "nd_box_set_profiling": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "nd_box_profile": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double)]),
+    "nd_eq1_weights": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "nd_chi2": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                            C.c_void_p]),
+}
+
+_lib = None
+
+
+def build() -> str:
+    from . import buildlib
+    return buildlib.build()
+
+
+def lib():
+    """The loaded libneuda.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1904_08756_amd.build()")
+    L = C.CDLL(LIB_PATH)
+    for name, (res, args) in EXPORTS.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != 0:
+        raise NeudaError(code, lib().nd_last_error().decode())
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the neuda library needs a HIP GPU; none is visible")
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _host_f64(a, n=None):
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if n is not None and arr.shape[0] != n:
+        raise ValueError("length mismatch")
+    return arr
+
+
+@dataclass
+class MCParams:
+    kT: float
+    max_disp: float
+    max_rot: float = 0.0
+    order: int = ND_ORDER_SEQ
+    k_batch: int = 0
+    tie_rel: float = 0.0
+
+    def c(self):
+        return nd_mc_params(self.kT, self.max_disp, self.max_rot, self.order, self.k_batch,
+                            self.tie_rel)
+
+
+class Box:
+    """A periodic box on one GPU (owns the device state of nd_box)."""
+
+    def __init__(self, xyz, species, unit_offsets, L, n_species, device=0):
+        torch = _torch()
+        xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float32))
+        species = np.ascontiguousarray(np.asarray(species, dtype=np.uint8))
+        offs = np.ascontiguousarray(np.asarray(unit_offsets, dtype=np.int32))
+        if xyz.ndim != 2 or xyz.shape[0] != 3:
+            raise ValueError("xyz must be [3, N]")
+        self.N = int(xyz.shape[1])
+        self.M = int(n_species)
+        self.P = self.M * (self.M + 1) // 2
+        self.L = float(L)
+        self.n_units = int(offs.shape[0] - 1)
+        self.species = species
+        self.unit_offsets = offs
+        self.device = int(device)
+        torch.cuda.set_device(self.device)
+        d = nd_box_desc(self.N, self.M, self.L, species.ctypes.data, self.n_units, offs.ctypes.data,
+                        xyz.ctypes.data, self.device, _stream())
+        h = C.c_void_p()
+        _check(lib().nd_box_create(C.byref(d), C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_synthetic(cls, sbox, device=0):
+        return cls(sbox.xyz, sbox.species, sbox.unit_offsets, sbox.L, sbox.n_species, device)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("box destroyed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().nd_box_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        _check(lib().nd_box_set_stream(self.handle, _stream()))
+
+    # -- measurement
+    def set_profiling(self, enable: bool):
+        self._sync_stream()
+        _check(lib().nd_box_set_profiling(self.handle, int(enable)))
+
+    def profile(self, kernel: str):
+        """(launches, total milliseconds) recorded for a kernel since profiling was enabled."""
+        n = C.c_int64()
+        ms = C.c_double()
+        _check(lib().nd_box_profile(self.handle, PROF[kernel], C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    # -- state
+    def set_tables(self, U, h, r_cut):
+        U = np.ascontiguousarray(np.asarray(U, dtype=np.float32))
+        if U.shape[0] != self.P:
+            raise ValueError("table rows must equal the number of pair types")
+        self._sync_stream()
+        _check(lib().nd_box_set_tables(self.handle, U.ctypes.data, U.shape[1], float(h), float(r_cut)))
+
+    def set_coords(self, xyz, keep_energy=False):
+        torch = _torch()
+        self._sync_stream()
+        if isinstance(xyz, torch.Tensor) and xyz.is_cuda:
+            t = xyz.detach().to(torch.float32).contiguous()
+            _check(lib().nd_box_set_coords(self.handle, _dptr(t), ND_DEVICE, int(keep_energy)))
+        else:
+            a = np.ascontiguousarray(np.asarray(xyz, dtype=np.float32))
+            _check(lib().nd_box_set_coords(self.handle, a.ctypes.data, ND_HOST, int(keep_energy)))
+
+    def coords(self):
+        """Current coordinates as a float32 [3, N] device tensor."""
+        torch = _torch()
+        self._sync_stream()
+        out = torch.empty((3, self.N), dtype=torch.float32, device=f"cuda:{self.device}")
+        _check(lib().nd_box_get_coords(self.handle, _dptr(out), ND_DEVICE))
+        return out
+
+    def coords_host(self):
+        out = np.empty((3, self.N), np.float32)
+        self._sync_stream()
+        _check(lib().nd_box_get_coords(self.handle, out.ctypes.data, ND_HOST))
+        return out
+
+    def total_energy(self):
+        E = C.c_double()
+        self._sync_stream()
+        _check(lib().nd_box_total_energy(self.handle, C.byref(E)))
+        return E.value
+
+    def energy(self):
+        E = C.c_double()
+        self._sync_stream()
+        _check(lib().nd_box_energy(self.handle, C.byref(E)))
+        return E.value
+
+    # -- method
+    def mc_sweep(self, params: MCParams, seed: int, first_trial: int, n_trials: int,
+                 trace: bool = False, stats: bool = True):
+        torch = _torch()
+        self._sync_stream()
+        tr = None
+        tr_t = None
+        if trace:
+            dev = f"cuda:{self.device}"
+            tr_t = dict(dE=torch.empty(n_trials, dtype=torch.float64, device=dev),
+                        sabs=torch.empty(n_trials, dtype=torch.float64, device=dev),
+                        accepted=torch.empty(n_trials, dtype=torch.uint8, device=dev),
+                        unit=torch.empty(n_trials, dtype=torch.int32, device=dev))
+            tr = nd_mc_trace(tr_t["dE"].data_ptr(), tr_t["sabs"].data_ptr(),
+                             tr_t["accepted"].data_ptr(), tr_t["unit"].data_ptr())
+        st = nd_mc_stats() if stats else None
+        p = params.c()
+        _check(lib().nd_mc_sweep(self.handle, C.byref(p), C.c_uint64(seed), C.c_uint64(first_trial),
+                                 int(n_trials), C.byref(st) if st is not None else None,
+                                 C.byref(tr) if tr is not None else None))
+        out = {}
+        if st is not None:
+            out.update(trials=st.trials, accepted=st.accepted, near_ties=st.near_ties,
+                       E_total=st.E_total, dE_sum=st.dE_sum)
+        if tr_t is not None:
+            out["trace"] = tr_t
+        return out
+
+
+def pair_histogram(box: Box, dr: float, nbins: int, out=None):
+    """Exact pair counts [P, nbins] (int64 device tensor holding the uint64 counts)."""
+    torch = _torch()
+    box._sync_stream()
+    if out is None:
+        out = torch.empty((box.P, nbins), dtype=torch.int64, device=f"cuda:{box.device}")
+    _check(lib().nd_pair_histogram(box.handle, float(dr), int(nbins), _dptr(out), ND_DEVICE))
+    return out
+
+
+def gr_normalize(counts, dr, V, npairs):
+    torch = _torch()
+    P, nb = counts.shape
+    g = torch.empty((P, nb), dtype=torch.float64, device=counts.device)
+    npairs = _host_f64(npairs, P)
+    if counts.dtype == torch.int64:
+        _check(lib().nd_gr_normalize(_dptr(counts.contiguous()), P, nb, float(dr), float(V),
+                                     npairs.ctypes.data, _dptr(g), ND_DEVICE, _stream()))
+    else:
+        raise TypeError("counts must be the int64 tensor returned by pair_histogram")
+    return g
+
+
+def sq_transform(g, dr, rho, w, self_term, Q):
+    torch = _torch()
+    g = g.contiguous()
+    P, nb = g.shape
+    Q = Q.to(device=g.device, dtype=torch.float64).contiguous()
+    S = torch.empty(Q.shape[0], dtype=torch.float64, device=g.device)
+    w = _host_f64(w, P)
+    _check(lib().nd_sq_transform(_dptr(g), P, nb, float(dr), float(rho), w.ctypes.data,
+                                 float(self_term), _dptr(Q), Q.shape[0], _dptr(S), ND_DEVICE,
+                                 _stream()))
+    return S
+
+
+def sq_adjoint(dLdS, nbins, dr, rho, V, w, npairs, Q):
+    torch = _torch()
+    dLdS = dLdS.to(torch.float64).contiguous()
+    Q = Q.to(device=dLdS.device, dtype=torch.float64).contiguous()
+    w = _host_f64(w)
+    npairs = _host_f64(npairs, w.shape[0])
+    P = w.shape[0]
+    A = torch.empty((P, nbins), dtype=torch.float64, device=dLdS.device)
+    _check(lib().nd_sq_adjoint(_dptr(dLdS), P, int(nbins), float(dr), float(rho), float(V),
+                               w.ctypes.data, npairs.ctypes.data, _dptr(Q), Q.shape[0], _dptr(A),
+                               ND_DEVICE, _stream()))
+    return A
+
+
+def hist_broad(box: Box, dr, nbins, sigma):
+    torch = _torch()
+    box._sync_stream()
+    out = torch.empty((box.P, nbins), dtype=torch.float64, device=f"cuda:{box.device}")
+    _check(lib().nd_hist_broad(box.handle, float(dr), int(nbins), float(sigma), _dptr(out), ND_DEVICE))
+    return out
+
+
+def hist_broad_backward(box: Box, dr, nbins, sigma, A):
+    torch = _torch()
+    box._sync_stream()
+    A = A.to(torch.float64).contiguous()
+    out = torch.empty((3, box.N), dtype=torch.float64, device=f"cuda:{box.device}")
+    _check(lib().nd_hist_broad_backward(box.handle, float(dr), int(nbins), float(sigma), _dptr(A),
+                                        _dptr(out), ND_DEVICE))
+    return out
+
+
+def forces(box: Box):
+    """(dE/dx [3, N] float64 device tensor, E)."""
+    torch = _torch()
+    box._sync_stream()
+    out = torch.empty((3, box.N), dtype=torch.float64, device=f"cuda:{box.device}")
+    E = C.c_double()
+    _check(lib().nd_forces(box.handle, _dptr(out), C.byref(E), ND_DEVICE))
+    return out, E.value
+
+
+def pair_counts_total(box: Box):
+    """Number of distinct pairs per pair type (nd_box_pair_counts)."""
+    out = np.zeros(box.P)
+    _check(lib().nd_box_pair_counts(box.handle, out.ctypes.data))
+    return out
+
+
+def eq1_weights(box: Box, b):
+    """Eq. 1 partial weights and flat term for scattering lengths b (nd_eq1_weights)."""
+    bb = _host_f64(b, box.M)
+    w = np.zeros(box.P)
+    flat = C.c_double()
+    _check(lib().nd_eq1_weights(box.handle, bb.ctypes.data, w.ctypes.data, C.byref(flat)))
+    return w, flat.value
+
+
+def chi2(S, S_target):
+    """(chi^2 = sum (S - S_t)^2 as a 1-element device tensor, dchi^2/dS)."""
+    torch = _torch()
+    S = S.to(torch.float64).contiguous()
+    St = S_target.to(device=S.device, dtype=torch.float64).contiguous()
+    out = torch.empty(1, dtype=torch.float64, device=S.device)
+    grad = torch.empty_like(S)
+    _check(lib().nd_chi2(_dptr(S), _dptr(St), S.shape[0], _dptr(out), _dptr(grad), ND_DEVICE, _stream()))
+    return out, grad
+
+
+def gr_normalize_f64(counts, dr, V, npairs):
+    torch = _torch()
+    counts = counts.to(torch.float64).contiguous()
+    P, nb = counts.shape
+    g = torch.empty_like(counts)
+    npairs = _host_f64(npairs, P)
+    _check(lib().nd_gr_normalize_f64(_dptr(counts), P, nb, float(dr), float(V), npairs.ctypes.data,
+                                     _dptr(g), ND_DEVICE, _stream()))
+    return g
+
+
+def _make_autograd():
+    import torch
+
+    class Chi2Fn(torch.autograd.Function):
+        """chi^2 of the Gaussian-broadened S(Q) against a target, differentiable in xyz.
+
+        Forward: nd_hist_broad -> nd_gr_normalize_f64 -> nd_sq_transform -> nd_chi2.
+        Backward: dchi^2/dS -> nd_sq_adjoint -> nd_hist_broad_backward.
+        """
+
+        @staticmethod
+        def forward(ctx, xyz, box, dr, nbins, sigma, Q, S_target, b):
+            box.set_coords(xyz, keep_energy=True)
+            nh = hist_broad(box, dr, nbins, sigma)
+            npairs = pair_counts_total(box)
+            V = box.L ** 3
+            rho = box.N / V
+            w, self_term = eq1_weights(box, b)
+            g = gr_normalize_f64(nh, dr, V, npairs)
+            S = sq_transform(g, dr, rho, w, self_term, Q)
+            c2, dS = chi2(S, S_target)
+            ctx.save_for_backward(dS, Q)
+            ctx.box, ctx.dr, ctx.nbins, ctx.sigma = box, dr, nbins, sigma
+            ctx.rho, ctx.V, ctx.w, ctx.npairs = rho, V, w, npairs
+            return c2[0]
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            dS, Q = ctx.saved_tensors
+            A = sq_adjoint(dS, ctx.nbins, ctx.dr, ctx.rho, ctx.V, ctx.w, ctx.npairs, Q)
+            gx = hist_broad_backward(ctx.box, ctx.dr, ctx.nbins, ctx.sigma, A)
+            return (grad_out * gx).to(torch.float32), None, None, None, None, None, None, None
+
+    class EnergyFn(torch.autograd.Function):
+        """Total energy of the box at xyz; backward gives dE/dx from nd_forces."""
+
+        @staticmethod
+        def forward(ctx, xyz, box):
+            box.set_coords(xyz, keep_energy=False)
+            grad, E = forces(box)
+            ctx.save_for_backward(grad)
+            return torch.tensor(E, dtype=torch.float64, device=xyz.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (grad,) = ctx.saved_tensors
+            return (grad_out * grad).to(torch.float32), None
+
+    return Chi2Fn, EnergyFn
+
+
+class _Lazy:
+    def __init__(self, idx):
+        self.idx = idx
+        self._cls = None
+
+    def _get(self):
+        if self._cls is None:
+            self._cls = _make_autograd()[self.idx]
+        return self._cls
+
+    def apply(self, *args):
+        return self._get().apply(*args)
+
+
+Chi2Fn = _Lazy(0)
+EnergyFn = _Lazy(1)

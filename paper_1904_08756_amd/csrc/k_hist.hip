@@ -1,0 +1,340 @@
+// Pair-count histogram N_p(k) over all unordered atom pairs (the paper's
+// N(r), Sec. "Acceleration method") and the full-box total energy.
+//
+// Layout: the i side of a tile pair is held one atom per thread in
+// registers; the j side is staged in LDS (FP64 coordinates plus species) and
+// read by broadcast.  Counts go to an LDS-private u32 histogram per block;
+// each block visits many tile pairs (persistent grid), then writes its
+// histogram to a per-block slice that one reduction kernel sums into u64 in
+// a fixed order, so counts are exact and independent of scheduling.
+#include "nd_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace {
+
+constexpr int TILE = 256;  // atoms per tile = threads per block
+
+__global__ void k_pos4_from_xyz(const float *__restrict__ xyz, const uint8_t *__restrict__ sp, int N,
+                                double invL, float4 *__restrict__ pos4)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    float4 p;
+    p.x = (float)((double)xyz[i] * invL);
+    p.y = (float)((double)xyz[N + i] * invL);
+    p.z = (float)((double)xyz[2 * N + i] * invL);
+    p.w = __int_as_float((int)sp[i]);
+    pos4[i] = p;
+}
+
+// Upper-triangle tile pair t -> (I, J), I <= J < nt, row-major.
+__device__ __forceinline__ void tri_index(long long t, int nt, int &I, int &J)
+{
+    double a = 2.0 * nt + 1.0;
+    int r = (int)floor((a - sqrt(a * a - 8.0 * (double)t)) * 0.5);
+    if (r < 0) r = 0;
+    if (r > nt - 1) r = nt - 1;
+    auto off = [nt](long long i) { return i * nt - i * (i - 1) / 2; };
+    while (r > 0 && off(r) > t) --r;
+    while (r < nt - 1 && off(r + 1) <= t) ++r;
+    I = r;
+    J = r + (int)(t - off(r));
+}
+
+struct HistArgs {
+    const float *xyz;
+    const uint8_t *sp;
+    int N, M, P, nbins, nt;
+    long long ntp;
+    double L, invL, dr, e2max;
+    float inv_dr_f, edge_eps;
+    unsigned *partial;  // [gridDim.x][P * nbins]
+};
+
+__global__ __launch_bounds__(TILE) void k_pair_hist(HistArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nq = a.P * a.nbins;
+    double *jx = reinterpret_cast<double *>(smem);         // [3][TILE]
+    int *js = reinterpret_cast<int *>(jx + 3 * TILE);       // [TILE]  pair-row offsets per i species
+    int *prow = js + TILE;                                  // [M*M]
+    unsigned *hist = reinterpret_cast<unsigned *>(prow + 16);  // [nq]
+    const int tid = threadIdx.x;
+
+    for (int q = tid; q < nq; q += TILE) hist[q] = 0u;
+    if (tid < a.M * a.M) {
+        int s0 = tid / a.M, s1 = tid % a.M;
+        int lo = s0 < s1 ? s0 : s1, hi = s0 < s1 ? s1 : s0;
+        prow[tid] = (lo * a.M - lo * (lo - 1) / 2 + (hi - lo)) * a.nbins;
+    }
+    __syncthreads();
+
+    const int N = a.N;
+    for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
+        int I, J;
+        tri_index(t, a.nt, I, J);
+        const int i = I * TILE + tid;
+        const bool iv = i < N;
+        double xi = 0.0, yi = 0.0, zi = 0.0;
+        int si = 0;
+        if (iv) {
+            xi = (double)a.xyz[i];
+            yi = (double)a.xyz[N + i];
+            zi = (double)a.xyz[2 * N + i];
+            si = a.sp[i];
+        }
+        __syncthreads();  // previous tile's readers are done with jx/js
+        const int j = J * TILE + tid;
+        if (j < N) {
+            jx[tid] = (double)a.xyz[j];
+            jx[TILE + tid] = (double)a.xyz[N + j];
+            jx[2 * TILE + tid] = (double)a.xyz[2 * N + j];
+            js[tid] = a.sp[j];
+        }
+        __syncthreads();
+        const int jn = min(TILE, N - J * TILE);
+        const int jstart = (I == J) ? tid + 1 : 0;  // diagonal tile: pairs j > i only
+        if (!iv) continue;
+        const int rowbase = si * a.M;
+#pragma unroll 4
+        for (int jj = jstart; jj < jn; ++jj) {
+            double dx = jx[jj] - xi;
+            double dy = jx[TILE + jj] - yi;
+            double dz = jx[2 * TILE + jj] - zi;
+            dx = fma(-rint(dx * a.invL), a.L, dx);
+            dy = fma(-rint(dy * a.invL), a.L, dy);
+            dz = fma(-rint(dz * a.invL), a.L, dz);
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            if (r2 < a.e2max) {
+                // candidate bin from an FP32 square root; exact FP64 edge test
+                // only when the candidate lies within edge_eps of a bin edge
+                const float tb = __builtin_amdgcn_sqrtf((float)r2) * a.inv_dr_f;
+                int k = (int)tb;
+                const float fr = tb - (float)k;
+                if (fr < a.edge_eps || fr > 1.0f - a.edge_eps) {
+                    const int kk = (int)rintf(tb);
+                    const double e = (double)kk * a.dr;
+                    k = (r2 >= e * e) ? kk : kk - 1;
+                }
+                atomicAdd(&hist[prow[rowbase + js[jj]] + k], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    unsigned *out = a.partial + (size_t)blockIdx.x * nq;
+    for (int q = tid; q < nq; q += TILE) out[q] = hist[q];
+}
+
+__global__ void k_hist_reduce(const unsigned *__restrict__ partial, int G, int nq, uint64_t *__restrict__ counts)
+{
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    uint64_t s = 0;
+    for (int g = 0; g < G; ++g) s += partial[(size_t)g * nq + q];
+    counts[q] = s;
+}
+
+// ---------------------------------------------------------------- energy
+struct EnergyArgs {
+    const float4 *pos4;
+    const int32_t *unit_of;
+    const float *tab;
+    int N, M, n_pts, nt;
+    long long ntp;
+    float rcf2, tscale;
+    double *partial;  // [gridDim.x][2]
+};
+
+__device__ __forceinline__ float table_lerp(const float *__restrict__ row, float t, int n_pts)
+{
+    int i0 = (int)t;
+    i0 = min(i0, n_pts - 2);
+    const float f = t - (float)i0;
+    const float u0 = row[i0];
+    const float u1 = row[i0 + 1];
+    return fmaf(f, u1 - u0, u0);
+}
+
+__global__ __launch_bounds__(TILE) void k_total_energy(EnergyArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    float4 *jp = reinterpret_cast<float4 *>(smem);      // [TILE]
+    int *ju = reinterpret_cast<int *>(jp + TILE);        // [TILE]
+    int *prow = ju + TILE;                               // [16]
+    float *tab = reinterpret_cast<float *>(prow + 16);   // [P][n_pts]
+    __shared__ double red[2][TILE / 64];
+    const int tid = threadIdx.x;
+    const int P = a.M * (a.M + 1) / 2;
+    for (int q = tid; q < P * a.n_pts; q += TILE) tab[q] = a.tab[q];
+    if (tid < a.M * a.M) {
+        int s0 = tid / a.M, s1 = tid % a.M;
+        int lo = s0 < s1 ? s0 : s1, hi = s0 < s1 ? s1 : s0;
+        prow[tid] = (lo * a.M - lo * (lo - 1) / 2 + (hi - lo)) * a.n_pts;
+    }
+    double e = 0.0, s = 0.0;
+    for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
+        int I, J;
+        tri_index(t, a.nt, I, J);
+        const int i = I * TILE + tid;
+        const bool iv = i < a.N;
+        float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+        int ui = -1;
+        if (iv) {
+            pi = a.pos4[i];
+            ui = a.unit_of[i];
+        }
+        __syncthreads();
+        const int j = J * TILE + tid;
+        if (j < a.N) {
+            jp[tid] = a.pos4[j];
+            ju[tid] = a.unit_of[j];
+        }
+        __syncthreads();
+        const int jn = min(TILE, a.N - J * TILE);
+        const int jstart = (I == J) ? tid + 1 : 0;
+        if (!iv) continue;
+        const int rowbase = __float_as_int(pi.w) * a.M;
+        for (int jj = jstart; jj < jn; ++jj) {
+            const float4 pj = jp[jj];
+            float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+            dx -= rintf(dx);
+            dy -= rintf(dy);
+            dz -= rintf(dz);
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            if (r2 < a.rcf2 && ju[jj] != ui) {
+                const float tt = __builtin_amdgcn_sqrtf(r2) * a.tscale;
+                const float u = table_lerp(tab + prow[rowbase + __float_as_int(pj.w)], tt, a.n_pts);
+                e += (double)u;
+                s += (double)fabsf(u);
+            }
+        }
+    }
+    // block reduction in a fixed order
+    for (int o = 32; o > 0; o >>= 1) {
+        e += __shfl_xor(e, o);
+        s += __shfl_xor(s, o);
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = e;
+        red[1][tid >> 6] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double te = 0.0, ts = 0.0;
+        for (int w = 0; w < TILE / 64; ++w) {
+            te += red[0][w];
+            ts += red[1][w];
+        }
+        a.partial[2 * blockIdx.x] = te;
+        a.partial[2 * blockIdx.x + 1] = ts;
+    }
+}
+
+__global__ void k_energy_reduce(const double *__restrict__ partial, int G, double *__restrict__ E,
+                                double *__restrict__ S)
+{
+    __shared__ double re[256], rs[256];
+    double e = 0.0, s = 0.0;
+    for (int g = threadIdx.x; g < G; g += 256) {
+        e += partial[2 * g];
+        s += partial[2 * g + 1];
+    }
+    re[threadIdx.x] = e;
+    rs[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            re[threadIdx.x] += re[threadIdx.x + w];
+            rs[threadIdx.x] += rs[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (E) *E = re[0];
+        if (S) *S = rs[0];
+    }
+}
+
+}  // namespace
+
+namespace nd {
+
+void launch_pos4_from_xyz(nd_box *b)
+{
+    int threads = 256;
+    int blocks = (b->N + threads - 1) / threads;
+    hipLaunchKernelGGL(k_pos4_from_xyz, dim3(blocks), dim3(threads), 0, b->stream, b->xyz, b->species, b->N,
+                       1.0 / b->L, b->pos4);
+    ND_HIP(hipGetLastError());
+}
+
+void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
+{
+    HistArgs a;
+    a.xyz = b->xyz;
+    a.sp = b->species;
+    a.N = b->N;
+    a.M = b->M;
+    a.P = b->P;
+    a.nbins = nbins;
+    a.nt = (b->N + TILE - 1) / TILE;
+    a.ntp = (long long)a.nt * (a.nt + 1) / 2;
+    a.L = b->L;
+    a.invL = 1.0 / b->L;
+    a.dr = dr;
+    {
+        double e = (double)nbins * dr;
+        a.e2max = e * e;
+    }
+    a.inv_dr_f = (float)(1.0 / dr);
+    // bound on |candidate - sqrt(r2)/dr|: < 2.5e-7 relative, plus margin
+    a.edge_eps = (float)(1e-3 + 4e-7 * (double)nbins);
+    if (!(a.edge_eps < 0.25f)) fail(ND_E_UNSUPPORTED, "nbins too large for the binning kernel");
+    const int nq = a.P * nbins;
+    size_t lds = sizeof(double) * 3 * TILE + sizeof(int) * (TILE + 16) + sizeof(unsigned) * (size_t)nq;
+    if (lds > 160 * 1024) fail(ND_E_UNSUPPORTED, "histogram does not fit in LDS (P*nbins too large)");
+    int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (lds + 1024)));
+    long long G = (long long)cu_count(b->device) * per_cu;
+    if (G > a.ntp) G = a.ntp;
+    // u32 counters: pairs per block must stay below 2^32
+    long long tiles_per_block = (a.ntp + G - 1) / G;
+    if ((double)tiles_per_block * TILE * TILE >= 4294967295.0) fail(ND_E_UNSUPPORTED, "box too large for u32 counters");
+    size_t pbytes = sizeof(unsigned) * (size_t)G * nq;
+    a.partial = static_cast<unsigned *>(workspace(b, pbytes));
+    {
+        ProfScope ps(b, ND_PROF_PAIR_HIST);
+        hipLaunchKernelGGL(k_pair_hist, dim3((unsigned)G), dim3(TILE), lds, b->stream, a);
+        ND_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_hist_reduce, dim3((nq + 255) / 256), dim3(256), 0, b->stream, a.partial, (int)G, nq,
+                       d_counts);
+    ND_HIP(hipGetLastError());
+}
+
+void launch_total_energy(nd_box *b, double *d_E_out, double *d_sabs_out)
+{
+    EnergyArgs a;
+    a.pos4 = b->pos4;
+    a.unit_of = b->unit_of;
+    a.tab = b->tab;
+    a.N = b->N;
+    a.M = b->M;
+    a.n_pts = b->n_pts;
+    a.nt = (b->N + TILE - 1) / TILE;
+    a.ntp = (long long)a.nt * (a.nt + 1) / 2;
+    a.rcf2 = (float)((b->rc / b->L) * (b->rc / b->L));
+    a.tscale = (float)(b->L / b->h);
+    size_t lds = sizeof(float4) * TILE + sizeof(int) * (TILE + 16) + sizeof(float) * (size_t)b->P * b->n_pts;
+    if (lds > 160 * 1024) fail(ND_E_UNSUPPORTED, "potential table does not fit in LDS");
+    long long G = (long long)cu_count(b->device) * 4;
+    if (G > a.ntp) G = a.ntp;
+    a.partial = static_cast<double *>(workspace(b, sizeof(double) * 2 * (size_t)G));
+    hipLaunchKernelGGL(k_total_energy, dim3((unsigned)G), dim3(TILE), lds, b->stream, a);
+    ND_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, b->stream, a.partial, (int)G, d_E_out, d_sabs_out);
+    ND_HIP(hipGetLastError());
+}
+
+}  // namespace nd

@@ -1,0 +1,741 @@
+// C-ABI entry points of the neuda library: argument validation, device
+// memory ownership, host/device staging and error translation.  Every
+// numeric step runs in the kernels of the .hip files.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nd_internal.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+nd_status set_error(nd_status code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+template <class F>
+nd_status guarded(F &&f)
+{
+    try {
+        g_last_error.clear();
+        f();
+        return ND_OK;
+    } catch (const nd::Error &e) {
+        return set_error(e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        return set_error(ND_E_OOM, "host allocation failed");
+    } catch (...) {
+        return set_error(ND_E_INVALID, "unexpected internal error");
+    }
+}
+
+void require(bool cond, nd_status code, const std::string &msg)
+{
+    if (!cond) nd::fail(code, msg);
+}
+
+void check_where(int32_t where)
+{
+    require(where == ND_HOST || where == ND_DEVICE, ND_E_INVALID, "where must be ND_HOST or ND_DEVICE");
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ND_HIP(hipSetDevice(dev));
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Temporary device buffer freed at scope exit (after the stream drains).
+struct Scratch {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    Scratch(size_t bytes, hipStream_t st) : s(st) { p = nd::dmalloc(bytes); }
+    ~Scratch()
+    {
+        if (p) {
+            (void)hipStreamSynchronize(s);
+            nd::dfree(p);
+        }
+    }
+    template <class T>
+    T *as() { return static_cast<T *>(p); }
+};
+
+void validate_xyz_host(const float *xyz, int N, double L)
+{
+    for (size_t i = 0; i < (size_t)3 * N; ++i) {
+        float v = xyz[i];
+        require(std::isfinite(v), ND_E_INVALID, "coordinate is not finite");
+        require(v >= 0.0f && (double)v < L, ND_E_INVALID, "coordinate outside [0, L)");
+    }
+}
+
+void check_box(nd_box *b)
+{
+    require(b != nullptr, ND_E_INVALID, "box is NULL");
+}
+
+}  // namespace
+
+namespace nd {
+
+[[noreturn]] void fail(nd_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) fail(ND_E_OOM, std::string("device allocation failed: ") + what);
+    fail(ND_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *dmalloc(size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (e == hipErrorOutOfMemory) fail(ND_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        fail(ND_E_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return p;
+}
+
+void dfree(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+void *workspace(nd_box *b, size_t bytes)
+{
+    if (bytes <= b->ws_bytes && b->ws) return b->ws;
+    ND_HIP(hipStreamSynchronize(b->stream));
+    dfree(b->ws);
+    b->ws = nullptr;
+    b->ws_bytes = 0;
+    size_t cap = bytes + bytes / 4;
+    b->ws = dmalloc(cap);
+    b->ws_bytes = cap;
+    return b->ws;
+}
+
+int cu_count(int device)
+{
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n <= 0) n = 256;
+    return n;
+}
+
+static hipEvent_t take_event(nd_box *b)
+{
+    if (!b->prof_free.empty()) {
+        hipEvent_t e = b->prof_free.back();
+        b->prof_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    ND_HIP(hipEventCreate(&e));
+    return e;
+}
+
+ProfScope::ProfScope(nd_box *box, int k) : b(box), kind(k)
+{
+    if (!b->prof_on) return;
+    if (b->prof_pending[kind].size() >= 8192) prof_harvest(b);
+    e1 = take_event(b);
+    e2 = take_event(b);
+    ND_HIP(hipEventRecord(e1, b->stream));
+}
+
+ProfScope::~ProfScope()
+{
+    if (!e1) return;
+    if (hipEventRecord(e2, b->stream) == hipSuccess) {
+        b->prof_pending[kind].emplace_back(e1, e2);
+    } else {
+        b->prof_free.push_back(e1);
+        b->prof_free.push_back(e2);
+    }
+}
+
+void prof_harvest(nd_box *b)
+{
+    ND_HIP(hipStreamSynchronize(b->stream));
+    for (int k = 0; k < ND_PROF_KINDS; ++k) {
+        for (auto &pr : b->prof_pending[k]) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+                b->prof_ms[k] += ms;
+                b->prof_n[k] += 1;
+            }
+            b->prof_free.push_back(pr.first);
+            b->prof_free.push_back(pr.second);
+        }
+        b->prof_pending[k].clear();
+    }
+}
+
+void prof_release(nd_box *b)
+{
+    for (int k = 0; k < ND_PROF_KINDS; ++k) {
+        for (auto &pr : b->prof_pending[k]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        b->prof_pending[k].clear();
+    }
+    for (auto e : b->prof_free) (void)hipEventDestroy(e);
+    b->prof_free.clear();
+}
+
+}  // namespace nd
+
+static void free_box(nd_box *b)
+{
+    if (!b) return;
+    nd::prof_release(b);
+    nd::dfree(b->xyz);
+    nd::dfree(b->pos4);
+    nd::dfree(b->species);
+    nd::dfree(b->uoff);
+    nd::dfree(b->unit_of);
+    nd::dfree(b->tab);
+    nd::dfree(b->E);
+    nd::dfree(b->mc.trials);
+    nd::dfree(b->mc.partial);
+    nd::dfree(b->mc.corr_n);
+    nd::dfree(b->mc.corr_off);
+    nd::dfree(b->mc.counters);
+    nd::dfree(b->mc.dsum);
+    nd::dfree(b->mc.pool_m);
+    nd::dfree(b->mc.pool_c);
+    nd::dfree(b->mc.pool_s);
+    nd::dfree(b->ws);
+    delete[] b->h_uoff;
+    delete[] b->h_species;
+    delete b;
+}
+
+extern "C" {
+
+int32_t nd_abi_version(void) { return ND_ABI_VERSION; }
+
+const char *nd_last_error(void) { return g_last_error.c_str(); }
+
+nd_status nd_box_create(const nd_box_desc *d, nd_box **out)
+{
+    return guarded([&] {
+        require(d != nullptr && out != nullptr, ND_E_INVALID, "desc or out is NULL");
+        *out = nullptr;
+        require(d->n_atoms >= 2, ND_E_INVALID, "n_atoms must be >= 2");
+        require(d->n_species >= 1 && d->n_species <= ND_MAX_SPECIES, ND_E_INVALID,
+                "n_species must be in 1..ND_MAX_SPECIES");
+        require(std::isfinite(d->L) && d->L > 0.0, ND_E_INVALID, "L must be finite and > 0");
+        require(d->species && d->unit_offsets && d->xyz, ND_E_INVALID, "species, unit_offsets and xyz are required");
+        require(d->n_units >= 1 && d->n_units <= d->n_atoms, ND_E_INVALID, "n_units out of range");
+        const int N = d->n_atoms;
+        require(d->unit_offsets[0] == 0 && d->unit_offsets[d->n_units] == N, ND_E_INVALID,
+                "unit_offsets must start at 0 and end at n_atoms");
+        int max_na = 0;
+        for (int u = 0; u < d->n_units; ++u) {
+            int na = d->unit_offsets[u + 1] - d->unit_offsets[u];
+            require(na >= 1, ND_E_INVALID, "unit_offsets must be strictly increasing");
+            require(na <= ND_MAX_UNIT_ATOMS, ND_E_INVALID, "unit larger than ND_MAX_UNIT_ATOMS atoms");
+            if (na > max_na) max_na = na;
+        }
+        int64_t cnt[ND_MAX_SPECIES] = {0, 0, 0, 0};
+        for (int i = 0; i < N; ++i) {
+            require(d->species[i] < d->n_species, ND_E_INVALID, "species index >= n_species");
+            cnt[d->species[i]]++;
+        }
+        validate_xyz_host(d->xyz, N, d->L);
+
+        DeviceGuard g(d->device);
+        nd_box *b = new nd_box();
+        try {
+            b->device = d->device;
+            b->stream = static_cast<hipStream_t>(d->stream);
+            b->N = N;
+            b->M = d->n_species;
+            b->P = d->n_species * (d->n_species + 1) / 2;
+            b->n_units = d->n_units;
+            b->max_na = max_na;
+            b->L = d->L;
+            for (int s = 0; s < ND_MAX_SPECIES; ++s) b->species_count[s] = cnt[s];
+            b->h_uoff = new int32_t[d->n_units + 1];
+            std::memcpy(b->h_uoff, d->unit_offsets, sizeof(int32_t) * (d->n_units + 1));
+            b->h_species = new uint8_t[N];
+            std::memcpy(b->h_species, d->species, N);
+            std::vector<int32_t> unit_of(N);
+            for (int u = 0; u < d->n_units; ++u)
+                for (int a = d->unit_offsets[u]; a < d->unit_offsets[u + 1]; ++a) unit_of[a] = u;
+
+            b->xyz = static_cast<float *>(nd::dmalloc(sizeof(float) * 3 * (size_t)N));
+            b->pos4 = static_cast<float4 *>(nd::dmalloc(sizeof(float4) * (size_t)N));
+            b->species = static_cast<uint8_t *>(nd::dmalloc((size_t)N));
+            b->uoff = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * (d->n_units + 1)));
+            b->unit_of = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * (size_t)N));
+            b->E = static_cast<double *>(nd::dmalloc(sizeof(double)));
+            ND_HIP(hipMemcpyAsync(b->xyz, d->xyz, sizeof(float) * 3 * (size_t)N, hipMemcpyHostToDevice, b->stream));
+            ND_HIP(hipMemcpyAsync(b->species, d->species, (size_t)N, hipMemcpyHostToDevice, b->stream));
+            ND_HIP(hipMemcpyAsync(b->uoff, d->unit_offsets, sizeof(int32_t) * (d->n_units + 1),
+                                  hipMemcpyHostToDevice, b->stream));
+            ND_HIP(hipMemcpyAsync(b->unit_of, unit_of.data(), sizeof(int32_t) * (size_t)N,
+                                  hipMemcpyHostToDevice, b->stream));
+            ND_HIP(hipMemsetAsync(b->E, 0, sizeof(double), b->stream));
+            nd::launch_pos4_from_xyz(b);
+            ND_HIP(hipStreamSynchronize(b->stream));
+        } catch (...) {
+            free_box(b);
+            throw;
+        }
+        *out = b;
+    });
+}
+
+nd_status nd_box_destroy(nd_box *b)
+{
+    return guarded([&] {
+        if (!b) return;
+        DeviceGuard g(b->device);
+        (void)hipStreamSynchronize(b->stream);
+        free_box(b);
+    });
+}
+
+nd_status nd_box_set_profiling(nd_box *b, int32_t enable)
+{
+    return guarded([&] {
+        check_box(b);
+        DeviceGuard g(b->device);
+        nd::prof_harvest(b);
+        if (enable) {
+            for (int k = 0; k < ND_PROF_KINDS; ++k) {
+                b->prof_ms[k] = 0.0;
+                b->prof_n[k] = 0;
+            }
+        }
+        b->prof_on = enable != 0;
+    });
+}
+
+nd_status nd_box_profile(nd_box *b, int32_t kernel, int64_t *launches, double *ms)
+{
+    return guarded([&] {
+        check_box(b);
+        require(kernel >= 0 && kernel < ND_PROF_KINDS, ND_E_INVALID, "unknown kernel id");
+        require(launches && ms, ND_E_INVALID, "NULL argument");
+        DeviceGuard g(b->device);
+        nd::prof_harvest(b);
+        *launches = b->prof_n[kernel];
+        *ms = b->prof_ms[kernel];
+    });
+}
+
+nd_status nd_box_set_stream(nd_box *b, void *stream)
+{
+    return guarded([&] {
+        check_box(b);
+        b->stream = static_cast<hipStream_t>(stream);
+    });
+}
+
+nd_status nd_box_set_coords(nd_box *b, const float *xyz, int32_t where, int32_t keep_energy)
+{
+    return guarded([&] {
+        check_box(b);
+        require(xyz != nullptr, ND_E_INVALID, "xyz is NULL");
+        check_where(where);
+        DeviceGuard g(b->device);
+        size_t bytes = sizeof(float) * 3 * (size_t)b->N;
+        if (where == ND_HOST) {
+            validate_xyz_host(xyz, b->N, b->L);
+            ND_HIP(hipMemcpyAsync(b->xyz, xyz, bytes, hipMemcpyHostToDevice, b->stream));
+            nd::launch_pos4_from_xyz(b);
+            ND_HIP(hipStreamSynchronize(b->stream));
+        } else {
+            ND_HIP(hipMemcpyAsync(b->xyz, xyz, bytes, hipMemcpyDeviceToDevice, b->stream));
+            nd::launch_pos4_from_xyz(b);
+        }
+        if (!keep_energy) b->energy_valid = false;
+    });
+}
+
+nd_status nd_box_get_coords(nd_box *b, float *xyz, int32_t where)
+{
+    return guarded([&] {
+        check_box(b);
+        require(xyz != nullptr, ND_E_INVALID, "xyz is NULL");
+        check_where(where);
+        DeviceGuard g(b->device);
+        size_t bytes = sizeof(float) * 3 * (size_t)b->N;
+        if (where == ND_HOST) {
+            ND_HIP(hipMemcpyAsync(xyz, b->xyz, bytes, hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipStreamSynchronize(b->stream));
+        } else {
+            ND_HIP(hipMemcpyAsync(xyz, b->xyz, bytes, hipMemcpyDeviceToDevice, b->stream));
+        }
+    });
+}
+
+nd_status nd_box_set_tables(nd_box *b, const float *U, int32_t n_pts, double h, double r_cut)
+{
+    return guarded([&] {
+        check_box(b);
+        require(U != nullptr, ND_E_INVALID, "U is NULL");
+        require(std::isfinite(h) && h > 0.0, ND_E_INVALID, "h must be > 0");
+        require(std::isfinite(r_cut) && r_cut > 0.0, ND_E_INVALID, "r_cut must be > 0");
+        require(r_cut <= 0.5 * b->L, ND_E_RANGE, "r_cut must be <= L/2");
+        require(n_pts >= 2 && (double)(n_pts - 1) * h >= r_cut * (1.0 - 1e-12), ND_E_INVALID,
+                "n_pts must satisfy (n_pts - 1) h >= r_cut");
+        require(n_pts <= 16384, ND_E_INVALID, "n_pts larger than 16384");
+        size_t cnt = (size_t)b->P * n_pts;
+        for (size_t i = 0; i < cnt; ++i) require(std::isfinite(U[i]), ND_E_INVALID, "table value is not finite");
+        DeviceGuard g(b->device);
+        float *t = static_cast<float *>(nd::dmalloc(sizeof(float) * cnt));
+        hipError_t e = hipMemcpyAsync(t, U, sizeof(float) * cnt, hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) {
+            nd::dfree(t);
+            nd::check_hip(e, "copy tables");
+        }
+        nd::dfree(b->tab);
+        b->tab = t;
+        b->n_pts = n_pts;
+        b->h = h;
+        b->rc = r_cut;
+        b->has_tables = true;
+        b->energy_valid = false;
+    });
+}
+
+nd_status nd_box_total_energy(nd_box *b, double *E)
+{
+    return guarded([&] {
+        check_box(b);
+        require(E != nullptr, ND_E_INVALID, "E is NULL");
+        require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
+        DeviceGuard g(b->device);
+        nd::launch_total_energy(b, b->E, nullptr);
+        ND_HIP(hipMemcpyAsync(E, b->E, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        ND_HIP(hipStreamSynchronize(b->stream));
+        b->energy_valid = true;
+    });
+}
+
+nd_status nd_box_energy(nd_box *b, double *E)
+{
+    return guarded([&] {
+        check_box(b);
+        require(E != nullptr, ND_E_INVALID, "E is NULL");
+        DeviceGuard g(b->device);
+        ND_HIP(hipMemcpyAsync(E, b->E, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        ND_HIP(hipStreamSynchronize(b->stream));
+    });
+}
+
+nd_status nd_mc_sweep(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first_trial,
+                      int64_t n_trials, nd_mc_stats *stats, const nd_mc_trace *trace)
+{
+    return guarded([&] {
+        check_box(b);
+        require(p != nullptr, ND_E_INVALID, "params is NULL");
+        require(n_trials >= 0, ND_E_INVALID, "n_trials must be >= 0");
+        require(std::isfinite(p->kT) && p->kT > 0.0, ND_E_INVALID, "kT must be > 0");
+        require(std::isfinite(p->max_disp) && p->max_disp >= 0.0, ND_E_INVALID, "max_disp must be >= 0");
+        require(std::isfinite(p->max_rot) && p->max_rot >= 0.0, ND_E_INVALID, "max_rot must be >= 0");
+        require(p->max_disp < 0.25 * b->L, ND_E_RANGE, "max_disp must be < L/4");
+        require(p->tie_rel >= 0.0 && std::isfinite(p->tie_rel), ND_E_INVALID, "tie_rel must be >= 0");
+        require(p->k_batch >= 0, ND_E_INVALID, "k_batch must be >= 0");
+        require(p->order == ND_ORDER_SEQ || p->order == ND_ORDER_RANDOM, ND_E_INVALID, "unknown order");
+        if (p->order == ND_ORDER_RANDOM) nd::fail(ND_E_UNSUPPORTED, "ND_ORDER_RANDOM is not implemented");
+        require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
+        DeviceGuard g(b->device);
+        nd::mc_run(b, p, seed, first_trial, n_trials, trace);
+        if (stats) {
+            long long c[2];
+            double s;
+            ND_HIP(hipMemcpyAsync(c, b->mc.counters, sizeof(c), hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipMemcpyAsync(&s, b->mc.dsum, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipMemcpyAsync(&stats->E_total, b->E, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipStreamSynchronize(b->stream));
+            stats->trials = n_trials;
+            stats->accepted = c[0];
+            stats->near_ties = c[1];
+            stats->dE_sum = s;
+        }
+    });
+}
+
+nd_status nd_pair_histogram(nd_box *b, double dr, int32_t nbins, uint64_t *counts, int32_t where)
+{
+    return guarded([&] {
+        check_box(b);
+        require(counts != nullptr, ND_E_INVALID, "counts is NULL");
+        check_where(where);
+        require(std::isfinite(dr) && dr > 0.0, ND_E_INVALID, "dr must be > 0");
+        require(nbins >= 1, ND_E_INVALID, "nbins must be >= 1");
+        require((double)nbins * dr < 0.5 * b->L * (1.0 - 1e-9), ND_E_RANGE, "nbins*dr must be < L/2");
+        DeviceGuard g(b->device);
+        size_t bytes = sizeof(uint64_t) * (size_t)b->P * nbins;
+        if (where == ND_DEVICE) {
+            nd::launch_pair_histogram(b, dr, nbins, counts);
+        } else {
+            Scratch s(bytes, b->stream);
+            nd::launch_pair_histogram(b, dr, nbins, s.as<uint64_t>());
+            ND_HIP(hipMemcpyAsync(counts, s.p, bytes, hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipStreamSynchronize(b->stream));
+        }
+    });
+}
+
+nd_status nd_gr_normalize(const uint64_t *counts, int32_t P, int32_t nbins, double dr, double V,
+                          const double *npairs, double *g, int32_t where, void *stream)
+{
+    return guarded([&] {
+        require(counts && npairs && g, ND_E_INVALID, "NULL argument");
+        check_where(where);
+        require(P >= 1 && P <= ND_MAX_SPECIES * (ND_MAX_SPECIES + 1) / 2, ND_E_INVALID, "P out of range");
+        require(nbins >= 1, ND_E_INVALID, "nbins must be >= 1");
+        require(std::isfinite(dr) && dr > 0.0 && std::isfinite(V) && V > 0.0, ND_E_INVALID, "dr and V must be > 0");
+        for (int p = 0; p < P; ++p)
+            require(std::isfinite(npairs[p]) && npairs[p] > 0.0, ND_E_INVALID, "npairs must be > 0");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        size_t n = (size_t)P * nbins;
+        if (where == ND_DEVICE) {
+            nd::launch_gr_normalize(counts, P, nbins, dr, V, npairs, g, s);
+        } else {
+            Scratch dc(n * sizeof(uint64_t), s), dg(n * sizeof(double), s);
+            ND_HIP(hipMemcpyAsync(dc.p, counts, n * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+            nd::launch_gr_normalize(dc.as<uint64_t>(), P, nbins, dr, V, npairs, dg.as<double>(), s);
+            ND_HIP(hipMemcpyAsync(g, dg.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+            ND_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+nd_status nd_gr_normalize_f64(const double *counts, int32_t P, int32_t nbins, double dr, double V,
+                              const double *npairs, double *g, int32_t where, void *stream)
+{
+    return guarded([&] {
+        require(counts && npairs && g, ND_E_INVALID, "NULL argument");
+        check_where(where);
+        require(P >= 1 && P <= ND_MAX_SPECIES * (ND_MAX_SPECIES + 1) / 2, ND_E_INVALID, "P out of range");
+        require(nbins >= 1, ND_E_INVALID, "nbins must be >= 1");
+        require(std::isfinite(dr) && dr > 0.0 && std::isfinite(V) && V > 0.0, ND_E_INVALID, "dr and V must be > 0");
+        for (int p = 0; p < P; ++p)
+            require(std::isfinite(npairs[p]) && npairs[p] > 0.0, ND_E_INVALID, "npairs must be > 0");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        size_t n = (size_t)P * nbins;
+        if (where == ND_DEVICE) {
+            nd::launch_gr_normalize_f64(counts, P, nbins, dr, V, npairs, g, s);
+        } else {
+            Scratch dc(n * sizeof(double), s), dg(n * sizeof(double), s);
+            ND_HIP(hipMemcpyAsync(dc.p, counts, n * sizeof(double), hipMemcpyHostToDevice, s));
+            nd::launch_gr_normalize_f64(dc.as<double>(), P, nbins, dr, V, npairs, dg.as<double>(), s);
+            ND_HIP(hipMemcpyAsync(g, dg.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+            ND_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+nd_status nd_box_pair_counts(nd_box *b, double *npairs)
+{
+    return guarded([&] {
+        check_box(b);
+        require(npairs != nullptr, ND_E_INVALID, "npairs is NULL");
+        for (int a = 0; a < b->M; ++a)
+            for (int c = a; c < b->M; ++c) {
+                const double na = (double)b->species_count[a], nc = (double)b->species_count[c];
+                npairs[nd::pair_index(a, c, b->M)] = (a == c) ? na * (na - 1.0) / 2.0 : na * nc;
+            }
+    });
+}
+
+nd_status nd_eq1_weights(nd_box *b, const double *bl, double *w, double *self_term)
+{
+    return guarded([&] {
+        check_box(b);
+        require(bl && w && self_term, ND_E_INVALID, "NULL argument");
+        for (int a = 0; a < b->M; ++a) require(std::isfinite(bl[a]), ND_E_INVALID, "b is not finite");
+        double flat = 0.0;
+        for (int a = 0; a < b->M; ++a) {
+            const double ca = (double)b->species_count[a] / (double)b->N;
+            flat += ca * bl[a] * bl[a];
+            for (int c = a; c < b->M; ++c) {
+                const double cc = (double)b->species_count[c] / (double)b->N;
+                w[nd::pair_index(a, c, b->M)] = (a == c ? 1.0 : 2.0) * ca * cc * bl[a] * bl[c];
+            }
+        }
+        *self_term = flat;
+    });
+}
+
+nd_status nd_chi2(const double *S, const double *T, int32_t nQ, double *chi2, double *grad, int32_t where,
+                  void *stream)
+{
+    return guarded([&] {
+        require(S && T && chi2, ND_E_INVALID, "NULL argument");
+        check_where(where);
+        require(nQ >= 1, ND_E_INVALID, "nQ must be >= 1");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (where == ND_DEVICE) {
+            nd::launch_chi2(S, T, nQ, chi2, grad, s);
+        } else {
+            size_t n = (size_t)nQ * sizeof(double);
+            Scratch ds(n, s), dt(n, s), dg(n, s), dc(sizeof(double), s);
+            ND_HIP(hipMemcpyAsync(ds.p, S, n, hipMemcpyHostToDevice, s));
+            ND_HIP(hipMemcpyAsync(dt.p, T, n, hipMemcpyHostToDevice, s));
+            nd::launch_chi2(ds.as<double>(), dt.as<double>(), nQ, dc.as<double>(), dg.as<double>(), s);
+            ND_HIP(hipMemcpyAsync(chi2, dc.p, sizeof(double), hipMemcpyDeviceToHost, s));
+            if (grad) ND_HIP(hipMemcpyAsync(grad, dg.p, n, hipMemcpyDeviceToHost, s));
+            ND_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+nd_status nd_sq_transform(const double *g, int32_t P, int32_t nbins, double dr, double rho,
+                          const double *w, double self_term, const double *Q, int32_t nQ,
+                          double *S, int32_t where, void *stream)
+{
+    return guarded([&] {
+        require(g && w && Q && S, ND_E_INVALID, "NULL argument");
+        check_where(where);
+        require(P >= 1 && P <= ND_MAX_SPECIES * (ND_MAX_SPECIES + 1) / 2, ND_E_INVALID, "P out of range");
+        require(nbins >= 1 && nQ >= 1, ND_E_INVALID, "nbins and nQ must be >= 1");
+        require(std::isfinite(dr) && dr > 0.0, ND_E_INVALID, "dr must be > 0");
+        require(std::isfinite(rho) && rho > 0.0 && std::isfinite(self_term), ND_E_INVALID, "bad rho or self_term");
+        for (int p = 0; p < P; ++p) require(std::isfinite(w[p]), ND_E_INVALID, "weight is not finite");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        size_t n = (size_t)P * nbins;
+        if (where == ND_DEVICE) {
+            nd::launch_sq(g, P, nbins, dr, rho, w, self_term, Q, nQ, S, s);
+        } else {
+            Scratch dg(n * sizeof(double), s), dq(nQ * sizeof(double), s), ds(nQ * sizeof(double), s);
+            ND_HIP(hipMemcpyAsync(dg.p, g, n * sizeof(double), hipMemcpyHostToDevice, s));
+            ND_HIP(hipMemcpyAsync(dq.p, Q, nQ * sizeof(double), hipMemcpyHostToDevice, s));
+            nd::launch_sq(dg.as<double>(), P, nbins, dr, rho, w, self_term, dq.as<double>(), nQ, ds.as<double>(), s);
+            ND_HIP(hipMemcpyAsync(S, ds.p, nQ * sizeof(double), hipMemcpyDeviceToHost, s));
+            ND_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+nd_status nd_hist_broad(nd_box *b, double dr, int32_t nbins, double sigma, double *nhat, int32_t where)
+{
+    return guarded([&] {
+        check_box(b);
+        require(nhat != nullptr, ND_E_INVALID, "nhat is NULL");
+        check_where(where);
+        require(std::isfinite(dr) && dr > 0.0 && nbins >= 1, ND_E_INVALID, "bad dr or nbins");
+        require(std::isfinite(sigma) && sigma > 0.0, ND_E_INVALID, "sigma must be > 0");
+        require(6.0 * sigma < 8.0 * dr, ND_E_UNSUPPORTED, "6 sigma must be < 8 dr");
+        require((double)nbins * dr < 0.5 * b->L * (1.0 - 1e-9), ND_E_RANGE, "nbins*dr must be < L/2");
+        DeviceGuard g(b->device);
+        size_t bytes = sizeof(double) * (size_t)b->P * nbins;
+        if (where == ND_DEVICE) {
+            nd::launch_hist_broad(b, dr, nbins, sigma, nhat);
+        } else {
+            Scratch s(bytes, b->stream);
+            nd::launch_hist_broad(b, dr, nbins, sigma, s.as<double>());
+            ND_HIP(hipMemcpyAsync(nhat, s.p, bytes, hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipStreamSynchronize(b->stream));
+        }
+    });
+}
+
+nd_status nd_sq_adjoint(const double *dLdS, int32_t P, int32_t nbins, double dr, double rho, double V,
+                        const double *w, const double *npairs, const double *Q, int32_t nQ, double *A,
+                        int32_t where, void *stream)
+{
+    return guarded([&] {
+        require(dLdS && w && npairs && Q && A, ND_E_INVALID, "NULL argument");
+        check_where(where);
+        require(P >= 1 && P <= ND_MAX_SPECIES * (ND_MAX_SPECIES + 1) / 2, ND_E_INVALID, "P out of range");
+        require(nbins >= 1 && nQ >= 1, ND_E_INVALID, "nbins and nQ must be >= 1");
+        require(std::isfinite(dr) && dr > 0.0 && std::isfinite(rho) && rho > 0.0 && std::isfinite(V) && V > 0.0,
+                ND_E_INVALID, "dr, rho and V must be > 0");
+        for (int p = 0; p < P; ++p)
+            require(std::isfinite(w[p]) && std::isfinite(npairs[p]) && npairs[p] > 0.0, ND_E_INVALID,
+                    "bad weight or npairs");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        size_t n = (size_t)P * nbins;
+        if (where == ND_DEVICE) {
+            nd::launch_sq_adjoint(dLdS, P, nbins, dr, rho, V, w, npairs, Q, nQ, A, s);
+        } else {
+            Scratch dd(nQ * sizeof(double), s), dq(nQ * sizeof(double), s), da(n * sizeof(double), s);
+            ND_HIP(hipMemcpyAsync(dd.p, dLdS, nQ * sizeof(double), hipMemcpyHostToDevice, s));
+            ND_HIP(hipMemcpyAsync(dq.p, Q, nQ * sizeof(double), hipMemcpyHostToDevice, s));
+            nd::launch_sq_adjoint(dd.as<double>(), P, nbins, dr, rho, V, w, npairs, dq.as<double>(), nQ,
+                                  da.as<double>(), s);
+            ND_HIP(hipMemcpyAsync(A, da.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+            ND_HIP(hipStreamSynchronize(s));
+        }
+    });
+}
+
+nd_status nd_hist_broad_backward(nd_box *b, double dr, int32_t nbins, double sigma, const double *A,
+                                 double *dLdx, int32_t where)
+{
+    return guarded([&] {
+        check_box(b);
+        require(A != nullptr && dLdx != nullptr, ND_E_INVALID, "NULL argument");
+        check_where(where);
+        require(std::isfinite(dr) && dr > 0.0 && nbins >= 1, ND_E_INVALID, "bad dr or nbins");
+        require(std::isfinite(sigma) && sigma > 0.0, ND_E_INVALID, "sigma must be > 0");
+        require(6.0 * sigma < 8.0 * dr, ND_E_UNSUPPORTED, "6 sigma must be < 8 dr");
+        require((double)nbins * dr < 0.5 * b->L * (1.0 - 1e-9), ND_E_RANGE, "nbins*dr must be < L/2");
+        DeviceGuard g(b->device);
+        size_t nA = (size_t)b->P * nbins, nG = (size_t)3 * b->N;
+        if (where == ND_DEVICE) {
+            nd::launch_hist_broad_backward(b, dr, nbins, sigma, A, dLdx);
+        } else {
+            Scratch da(nA * sizeof(double), b->stream), dg(nG * sizeof(double), b->stream);
+            ND_HIP(hipMemcpyAsync(da.p, A, nA * sizeof(double), hipMemcpyHostToDevice, b->stream));
+            nd::launch_hist_broad_backward(b, dr, nbins, sigma, da.as<double>(), dg.as<double>());
+            ND_HIP(hipMemcpyAsync(dLdx, dg.p, nG * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipStreamSynchronize(b->stream));
+        }
+    });
+}
+
+nd_status nd_forces(nd_box *b, double *dEdx, double *E, int32_t where)
+{
+    return guarded([&] {
+        check_box(b);
+        require(dEdx != nullptr, ND_E_INVALID, "dEdx is NULL");
+        check_where(where);
+        require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
+        DeviceGuard g(b->device);
+        size_t nG = (size_t)3 * b->N;
+        Scratch de(sizeof(double), b->stream);
+        if (where == ND_DEVICE) {
+            nd::launch_forces(b, dEdx, de.as<double>());
+        } else {
+            Scratch dg(nG * sizeof(double), b->stream);
+            nd::launch_forces(b, dg.as<double>(), de.as<double>());
+            ND_HIP(hipMemcpyAsync(dEdx, dg.p, nG * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        }
+        if (E) {
+            ND_HIP(hipMemcpyAsync(E, de.p, sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        }
+        ND_HIP(hipStreamSynchronize(b->stream));
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Internal declarations shared by the host runtime and the kernel files of
+// the neuda library.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "neuda.h"
+
+namespace nd {
+
+// Error reporting: the entry points catch nd::Error and turn it into a
+// status plus the thread-local message.
+struct Error {
+    nd_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(nd_status code, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+
+#define ND_HIP(call) ::nd::check_hip((call), #call)
+
+__host__ __device__ inline int pair_index(int a, int b, int M)
+{
+    if (a > b) { int t = a; a = b; b = t; }
+    return a * M - a * (a - 1) / 2 + (b - a);
+}
+
+// Trial record written by the proposal kernel and read by the scan,
+// correction and decision kernels.  Positions are fractional coordinates
+// (x / L) in float32 with the species in .w (int bits).
+struct Trial {
+    float4 old_f[ND_MAX_UNIT_ATOMS];
+    float4 new_f[ND_MAX_UNIT_ATOMS];
+    float new_x[ND_MAX_UNIT_ATOMS][3];  // absolute float32 new positions
+    float cen[3];                       // fractional centre of old+new atoms
+    float rad;                          // fractional radius about cen
+    int32_t unit, a0, na, pad;
+    double u_acc;                       // acceptance draw
+};
+
+struct McWork {
+    int cap_k = 0;
+    int cap_jb = 0;
+    size_t cap_pool = 0;
+    Trial *trials = nullptr;      // [cap_k]
+    double *partial = nullptr;    // [cap_jb][2][cap_k]  (dE, sum |U|) per j-block
+    int32_t *corr_n = nullptr;    // [cap_k] correction entries of trial k
+    int32_t *corr_off = nullptr;  // [cap_k] offset of trial k's entries in the pool
+    int32_t *pool_m = nullptr;    // [cap_pool] earlier trial m of each entry
+    double *pool_c = nullptr;     // [cap_pool] energy correction if m was accepted
+    double *pool_s = nullptr;     // [cap_pool] sum |U| of the correction terms
+    long long *counters = nullptr;   // [0] accepted, [1] near ties, [2] pool fill
+    double *dsum = nullptr;       // accepted dE sum
+};
+
+}  // namespace nd
+
+struct nd_box {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int N = 0, M = 0, P = 0, n_units = 0, max_na = 0;
+    double L = 0.0;
+    // device
+    float *xyz = nullptr;        // [3][N] absolute float32 (canonical state)
+    float4 *pos4 = nullptr;      // [N] fractional float32 + species bits
+    uint8_t *species = nullptr;  // [N]
+    int32_t *uoff = nullptr;     // [n_units + 1]
+    int32_t *unit_of = nullptr;  // [N]
+    // host copies
+    int32_t *h_uoff = nullptr;
+    uint8_t *h_species = nullptr;
+    int64_t species_count[ND_MAX_SPECIES] = {0, 0, 0, 0};
+    // potential tables
+    float *tab = nullptr;        // [P][n_pts]
+    int n_pts = 0;
+    double h = 0.0, rc = 0.0;
+    bool has_tables = false;
+    // running energy
+    double *E = nullptr;         // device [1]
+    bool energy_valid = false;
+    nd::McWork mc;
+    // reusable device workspace for per-block partial results
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    // per-kernel event timing
+    bool prof_on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending[ND_PROF_KINDS];
+    std::vector<hipEvent_t> prof_free;
+    double prof_ms[ND_PROF_KINDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+    long long prof_n[ND_PROF_KINDS] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+namespace nd {
+
+// ---- kernel launchers (defined in the .hip files) ----
+void launch_pos4_from_xyz(nd_box *b);
+void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts);
+void launch_total_energy(nd_box *b, double *d_E_out, double *d_sabs_out);
+void launch_gr_normalize(const uint64_t *counts, int P, int nbins, double dr, double V,
+                         const double *npairs_host, double *g, hipStream_t s);
+void launch_gr_normalize_f64(const double *counts, int P, int nbins, double dr, double V,
+                             const double *npairs_host, double *g, hipStream_t s);
+void launch_chi2(const double *S, const double *T, int nQ, double *chi2, double *grad, hipStream_t s);
+void launch_sq(const double *g, int P, int nbins, double dr, double rho, const double *w_host,
+               double self_term, const double *Q, int nQ, double *S, hipStream_t s);
+void launch_sq_adjoint(const double *dLdS, int P, int nbins, double dr, double rho, double V,
+                       const double *w_host, const double *npairs_host, const double *Q, int nQ,
+                       double *A, hipStream_t s);
+void launch_hist_broad(nd_box *b, double dr, int nbins, double sigma, double *d_nhat);
+void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, const double *d_A,
+                                double *d_grad);
+void launch_forces(nd_box *b, double *d_grad, double *d_E);
+void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n,
+            const nd_mc_trace *trace);
+
+// device memory helpers
+void *dmalloc(size_t bytes);
+void dfree(void *p);
+// Workspace owned by the box, grown on demand (calls on a box are ordered
+// on one stream, so one buffer serves every call).
+void *workspace(nd_box *b, size_t bytes);
+int cu_count(int device);
+
+// Event pair around one kernel launch when profiling is on.
+struct ProfScope {
+    nd_box *b;
+    int kind;
+    hipEvent_t e1 = nullptr, e2 = nullptr;
+    ProfScope(nd_box *box, int k);
+    ~ProfScope();
+};
+void prof_harvest(nd_box *b);
+void prof_release(nd_box *b);
+
+}  // namespace nd

@@ -1,0 +1,319 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+Histograms are compared bit for bit; energies to 1e-6 of the sum of the
+magnitudes of the pair terms involved (the sums are differences of nearly
+equal numbers, so a tolerance relative to the result itself would be
+meaningless); S(Q) to 1e-11 of the magnitude of the Eq. 1 terms; Metropolis
+decisions exactly except inside the near-tie band, where the oracle adopts
+the library's decision and the tie is counted.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+
+
+@pytest.fixture(scope="module")
+def nd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    import paper_1904_08756_amd as nd
+    nd.lib()
+    return nd
+
+
+def _gbox(nd, box, tables=None):
+    g = nd.Box.from_synthetic(box)
+    if tables is not None:
+        g.set_tables(tables.U, tables.h, tables.r_cut)
+    return g
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ histogram
+def test_histogram_c1_bit_exact(nd, orc):
+    box, T, mc = syn.config_c1()
+    g = _gbox(nd, box)
+    got = nd.pair_histogram(g, mc["dr"], mc["nbins"]).cpu().numpy().astype(np.uint64)
+    want, _ = orc.pair_histogram(box, mc["dr"], mc["nbins"])
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n,m,L,seed", [(785, 3, 17.0, 1), (2, 1, 5.0, 2), (257, 4, 9.0, 3),
+                                        (3 * 256 + 1, 2, 40.0, 4), (5000, 2, 35.0, 5)])
+def test_histogram_random_boxes_bit_exact(nd, orc, n, m, L, seed):
+    rng = np.random.default_rng(seed)
+    xyz = (rng.random((3, n)) * L).astype(np.float32)
+    xyz[xyz >= L] = 0.0
+    sp = rng.integers(0, m, n).astype(np.uint8)
+    sbox = syn.Box("r", L, sp, np.arange(n + 1, dtype=np.int32), xyz, m)
+    for dr in (0.1, 0.0371, 0.25):
+        nb = syn.n_bins_for(L / 2 * (1 - 1e-6), dr)
+        got = nd.pair_histogram(_gbox(nd, sbox), dr, nb).cpu().numpy().astype(np.uint64)
+        want, _ = orc.pair_histogram(sbox, dr, nb)
+        assert np.array_equal(got, want), (n, m, dr)
+
+
+def test_histogram_dyadic_edges_and_degenerate_pairs(nd, orc):
+    L = 4.0
+    pts = [(0.0, 0.0, 0.0), (0.75, 0.0, 0.0), (0.0, 0.0, 0.0), (3.5, 0.0, 0.0), (0.25, 0.5, 0.5),
+           (float(np.nextafter(np.float32(4.0), np.float32(0))), 0.0, 0.0), (2.0, 2.0, 2.0),
+           (1.75, 0.0, 0.0), (0.5, 0.5, 0.0), (2.0, 0.0, 0.0)]
+    xyz = np.array(pts, dtype=np.float32).T.copy()
+    n = xyz.shape[1]
+    for m in (1, 2):
+        sp = (np.arange(n) % m).astype(np.uint8)
+        sbox = syn.Box("d", L, sp, np.arange(n + 1, dtype=np.int32), xyz, m)
+        got = nd.pair_histogram(_gbox(nd, sbox), 0.25, 7).cpu().numpy().astype(np.uint64)
+        want, _ = orc.pair_histogram(sbox, 0.25, 7)
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("which", ["c2", "c3"])
+def test_histogram_full_size_bit_exact(nd, which):
+    from make_golden import read_hist
+    cfg = syn.config_c2 if which == "c2" else syn.config_c3
+    box, T, mc = cfg()
+    want, n_out = read_hist(f"{which}_hist.txt")
+    g = _gbox(nd, box)
+    got = nd.pair_histogram(g, mc["dr"], mc["nbins"]).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(got, want)
+    # the same call twice gives the same counts
+    got2 = nd.pair_histogram(g, mc["dr"], mc["nbins"]).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(got, got2)
+
+
+def test_histogram_rejects_range_beyond_half_box(nd):
+    box, T, mc = syn.config_c1()
+    g = _gbox(nd, box)
+    with pytest.raises(nd.NeudaError) as e:
+        nd.pair_histogram(g, 0.03, 347)  # 10.41 > L/2 = 10.4
+    assert e.value.code == -2
+
+
+# ------------------------------------------------------------------ g(r), S(Q)
+def test_gr_and_sq_match_oracle(nd, orc):
+    import torch
+    box, T, mc = syn.config_c1()
+    g = _gbox(nd, box)
+    dr, nb = mc["dr"], mc["nbins"]
+    counts = nd.pair_histogram(g, dr, nb)
+    npairs = nd.pair_counts_total(g)
+    assert np.array_equal(npairs, orc.pair_counts_total(box.species, 2))
+    V = box.L ** 3
+    gr = nd.gr_normalize(counts, dr, V, npairs)
+    gr_o = orc.gr_normalize(counts.cpu().numpy().astype(np.float64), dr, V, npairs)
+    assert np.allclose(gr.cpu().numpy(), gr_o, rtol=1e-14, atol=0)
+    for x in (0.0, 0.64, 1.0):
+        w, self_term = nd.eq1_weights(g, syn.water_b(x))
+        w_o, self_o = orc.eq1_weights(box.species, 2, syn.water_b(x))
+        assert np.allclose(w, w_o, rtol=1e-14) and abs(self_term - self_o) < 1e-13
+        Q = torch.as_tensor(syn.q_grid(), device="cuda")
+        rho = box.n_atoms / V
+        S = nd.sq_transform(gr, dr, rho, w, self_term, Q).cpu().numpy()
+        S_o = orc.sq(gr_o, dr, rho, w, self_term, Q.cpu().numpy())
+        r = (np.arange(nb) + 0.5) * dr
+        scale = np.sum(np.abs(w)[:, None] * 4 * np.pi * rho * r ** 2 * np.abs(gr_o - 1) * dr) + self_o
+        assert np.max(np.abs(S - S_o)) <= 1e-11 * scale
+
+
+def test_sq_flat_for_ideal_gas(nd):
+    import torch
+    g = torch.ones((3, 400), dtype=torch.float64, device="cuda")
+    Q = torch.as_tensor(syn.q_grid(), device="cuda")
+    S = nd.sq_transform(g, 0.03, 0.1, [3.7, -9.6, 6.2], 20.545017, Q).cpu().numpy()
+    assert np.all(S == 20.545017)
+
+
+# ------------------------------------------------------------------ energy
+@pytest.mark.parametrize("cfg", ["c1", "c3cut"])
+def test_total_energy_matches_oracle(nd, orc, cfg):
+    if cfg == "c1":
+        box, T, _ = syn.config_c1()
+    else:
+        box = syn.atomic_box((2000, 4000), 114.7 * (6000 / 99999) ** (1 / 3), 1003, ("Si", "O"))
+        T = syn.sio2_tables()
+    g = _gbox(nd, box, T)
+    E = g.total_energy()
+    E_o, S_o = orc.total_energy(box, T)
+    assert abs(E - E_o) <= 1e-6 * S_o
+    assert g.energy() == E
+
+
+# ------------------------------------------------------------------ Metropolis
+def _mc_parity(nd, orc, box, T, params, seed, first, n, k_batch=0):
+    g = _gbox(nd, box, T)
+    E0 = g.total_energy()
+    p = nd.MCParams(params["kT"], params["max_disp"], params["max_rot"], k_batch=k_batch)
+    say(f"mc parity: {box.name} trials {first}..{first + n} K={k_batch}")
+    res = g.mc_sweep(p, seed, first, n, trace=True)
+    tr = {k: v.cpu().numpy() for k, v in res["trace"].items()}
+    xyz = box.xyz.copy()
+    o = orc.mc_run(box, T, xyz, params["kT"], params["max_disp"], params["max_rot"], seed, first, n,
+                   forced=tr["accepted"])
+    assert np.array_equal(tr["unit"], o["unit"])
+    err = np.abs(tr["dE"] - o["dE"])
+    assert np.all(err <= 1e-6 * o["sabs"]), (np.max(err / o["sabs"]), int(np.argmax(err / o["sabs"])))
+    mism = (tr["accepted"] != o["acc"]) & (o["tie"] == 0)
+    assert not mism.any(), np.nonzero(mism)[0][:10]
+    assert res["accepted"] == int(tr["accepted"].sum())
+    assert res["trials"] == n
+    got_xyz = g.coords_host()
+    # identical except where libm sin/cos differ in the last place (rare)
+    diff = np.abs(got_xyz.astype(np.float64) - xyz.astype(np.float64))
+    diff = np.minimum(diff, box.L - diff)
+    assert np.mean(diff == 0) > 0.999 and diff.max() < 1e-4
+    # running energy against a fresh recompute on both sides
+    E_run = res["E_total"]
+    E_new = g.total_energy()
+    E_o, S_o = orc.total_energy(syn.Box("a", box.L, box.species, box.unit_offsets, xyz, box.n_species), T)
+    assert abs(E_new - E_o) <= 1e-6 * S_o
+    assert abs(E_run - E_new) <= 1e-6 * S_o + 1e-6 * np.sum(o["sabs"])
+    assert abs((E_run - E0) - np.sum(o["dE"][o["acc"] == 1])) <= 1e-6 * np.sum(o["sabs"])
+    return res, o
+
+
+@pytest.mark.parametrize("k_batch", [0, 1, 5, 64, 300])
+def test_mc_c1_matches_sequential_chain(nd, orc, k_batch):
+    box, T, mc = syn.config_c1()
+    res, o = _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, mc["n_trials"], k_batch)
+    assert 0.05 < res["accepted"] / res["trials"] < 0.95
+
+
+def test_mc_c1_split_calls_equal_one_call(nd, orc):
+    box, T, mc = syn.config_c1()
+    p = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"])
+    g1 = _gbox(nd, box, T)
+    g1.mc_sweep(p, 7, 0, 600)
+    g2 = _gbox(nd, box, T)
+    g2.mc_sweep(p, 7, 0, 250)
+    g2.mc_sweep(p, 7, 250, 350)
+    assert np.array_equal(g1.coords_host(), g2.coords_host())
+
+
+def test_mc_zero_potential_accepts_all(nd):
+    box, T, mc = syn.config_c1()
+    Z = syn.Tables(np.zeros_like(T.U), T.h, T.r_cut)
+    g = _gbox(nd, box, Z)
+    res = g.mc_sweep(nd.MCParams(mc["kT"], 0.3, mc["max_rot"]), 3, 0, 500, trace=True)
+    assert res["accepted"] == 500
+    assert np.all(res["trace"]["dE"].cpu().numpy() == 0.0)
+
+
+def test_mc_c2_sample_matches(nd, orc):
+    box, T, mc = syn.config_c2()
+    _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, 3000)
+
+
+def test_mc_c2_later_trials_match(nd, orc):
+    box, T, mc = syn.config_c2()
+    # start mid-sweep: trial numbers far from 0 use the same counter-based draws
+    _mc_parity(nd, orc, box, T, mc, mc["seed"], 1_000_003, 1500)
+
+
+def test_mc_c3_sample_matches(nd, orc):
+    box, T, mc = syn.config_c3()
+    _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, 4000)
+
+
+def test_mc_rejects_missing_tables(nd):
+    box, T, mc = syn.config_c1()
+    g = _gbox(nd, box)
+    with pytest.raises(nd.NeudaError) as e:
+        g.mc_sweep(nd.MCParams(mc["kT"], 0.3, 0.1), 1, 0, 10)
+    assert e.value.code == -5
+
+
+# ------------------------------------------------------------------ differentiated form
+def _broad_box():
+    return syn.water_box(600, 18.0, 21, "broad")
+
+
+def test_hist_broad_matches_oracle(nd, orc):
+    box = _broad_box()
+    dr, sigma = 0.03, 0.02
+    nb = syn.n_bins_for(9.0 * (1 - 1e-6), dr)
+    got = nd.hist_broad(_gbox(nd, box), dr, nb, sigma).cpu().numpy()
+    want = orc.hist_broad(box, dr, nb, sigma)
+    assert np.all(np.abs(got - want) <= 1e-6 * np.maximum(want, 1.0)), np.max(np.abs(got - want))
+    # count conservation against the exact histogram (away from the last bins)
+    counts, _ = orc.pair_histogram(box, dr, nb)
+    assert abs(got[:, :nb - 10].sum() - counts[:, :nb - 10].sum()) < 10
+
+
+def test_hist_broad_backward_matches_oracle(nd, orc):
+    import torch
+    box = _broad_box()
+    dr, sigma = 0.03, 0.02
+    nb = syn.n_bins_for(9.0 * (1 - 1e-6), dr)
+    rng = np.random.default_rng(2)
+    A = rng.normal(size=(3, nb))
+    got = nd.hist_broad_backward(_gbox(nd, box), dr, nb, sigma, torch.as_tensor(A, device="cuda")).cpu().numpy()
+    want = orc.hist_broad_backward(box, dr, nb, sigma, A)
+    scale = np.abs(want).max()
+    assert np.all(np.abs(got - want) <= 1e-5 * scale + 1e-4 * np.abs(want)), np.max(np.abs(got - want)) / scale
+
+
+def test_forces_match_oracle(nd, orc):
+    box = syn.water_box(600, 18.0, 22, "forces")
+    T = syn.water_tables(r_cut=9.0)
+    grad, E = nd.forces(_gbox(nd, box, T))
+    grad = grad.cpu().numpy()
+    want, E_o = orc.forces(box, T)
+    scale = np.abs(want).max()
+    assert np.all(np.abs(grad - want) <= 1e-9 * scale + 1e-9 * np.abs(want))
+    E_t, S_t = orc.total_energy(box, T)
+    assert abs(E - E_o) <= 1e-9 * S_t
+
+
+def test_chi2_autograd_matches_oracle(nd, orc):
+    import torch
+    box = _broad_box()
+    dr, sigma = 0.03, 0.02
+    nb = syn.n_bins_for(9.0 * (1 - 1e-6), dr)
+    Q = syn.q_grid(300)
+    b = syn.water_b(0.0)
+    target = 20.0 + 0.5 * np.sin(Q)
+    g = _gbox(nd, box)
+    x = torch.as_tensor(box.xyz, device="cuda").clone().requires_grad_(True)
+    c2 = nd.Chi2Fn.apply(x, g, dr, nb, sigma, torch.as_tensor(Q, device="cuda"),
+                         torch.as_tensor(target, device="cuda"), b)
+    c2.backward()
+    nh = orc.hist_broad(box, dr, nb, sigma)
+    npairs = orc.pair_counts_total(box.species, 2)
+    V = box.L ** 3
+    w, self_term = orc.eq1_weights(box.species, 2, b)
+    S = orc.sq(orc.gr_normalize(nh, dr, V, npairs), dr, box.n_atoms / V, w, self_term, Q)
+    chi2_o = float(((S - target) ** 2).sum())
+    assert abs(float(c2) - chi2_o) <= 1e-6 * chi2_o
+    A = orc.sq_adjoint(2 * (S - target), nb, dr, box.n_atoms / V, V, w, npairs, Q)
+    want = orc.hist_broad_backward(box, dr, nb, sigma, A)
+    got = x.grad.cpu().numpy().astype(np.float64)
+    scale = np.abs(want).max()
+    assert np.all(np.abs(got - want) <= 1e-4 * scale + 1e-3 * np.abs(want))
+
+
+def test_energy_autograd_gives_forces(nd, orc):
+    import torch
+    box = syn.water_box(300, 16.0, 23, "eg")
+    T = syn.water_tables(r_cut=8.0)
+    g = _gbox(nd, box, T)
+    x = torch.as_tensor(box.xyz, device="cuda").clone().requires_grad_(True)
+    E = nd.EnergyFn.apply(x, g)
+    E.backward()
+    want, E_o = orc.forces(box, T)
+    scale = np.abs(want).max()
+    assert np.all(np.abs(x.grad.cpu().numpy() - want) <= 1e-6 * scale + 1e-6 * np.abs(want))
