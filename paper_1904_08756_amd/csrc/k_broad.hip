@@ -39,7 +39,7 @@ struct BroadArgs {
     int N, M, P, nbins, nt;
     long long ntp;
     double L, invL, half2;  // half2 = (L/2)^2
-    float dr, inv_dr, sigma, inv_sigma_sqrt2, six_sigma;
+    double dr, inv_dr, inv_sigma_sqrt2, six_sigma;
     double *partial;  // [gridDim.x][P*nbins]
 };
 
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(TILE) void k_hist_broad(BroadArgs a)
     if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.nbins;
     __syncthreads();
     const int N = a.N;
-    const float rmax_win = (float)a.nbins * a.dr + a.six_sigma;
+    const double rmax_win = (double)a.nbins * a.dr + a.six_sigma;
     for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
         int I, J;
         tri_index(t, a.nt, I, J);
@@ -90,19 +90,19 @@ __global__ __launch_bounds__(TILE) void k_hist_broad(BroadArgs a)
             dz = fma(-rint(dz * a.invL), a.L, dz);
             const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             if (!(r2 < a.half2)) continue;
-            const float r = __builtin_amdgcn_sqrtf((float)r2);
+            const double r = sqrt(r2);
             if (!(r < rmax_win)) continue;
-            int k0 = (int)floorf((r - a.six_sigma) * a.inv_dr);
-            int k1 = (int)floorf((r + a.six_sigma) * a.inv_dr);
+            int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
+            int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
             k0 = max(k0, 0);
             k1 = min(k1, a.nbins - 1);
             double *row = hist + prow[rowbase + js[jj]];
-            // tail mass at edge k0
-            float xe = ((float)k0 * a.dr - r) * a.inv_sigma_sqrt2;
+            // tail mass at edge k0; offsets from r in FP64, tails in FP32
+            float xe = (float)(((double)k0 * a.dr - r) * a.inv_sigma_sqrt2);
             float Tlo = 0.5f * erfcf(fabsf(xe));
             bool lo_right = xe >= 0.0f;
             for (int k = k0; k <= k1; ++k) {
-                const float xh = ((float)(k + 1) * a.dr - r) * a.inv_sigma_sqrt2;
+                const float xh = (float)(((double)(k + 1) * a.dr - r) * a.inv_sigma_sqrt2);
                 const float Thi = 0.5f * erfcf(fabsf(xh));
                 const bool hi_right = xh >= 0.0f;
                 float wk;
@@ -136,7 +136,8 @@ struct BackArgs {
     const double *A;  // [P][nbins]
     int N, M, P, nbins;
     double L, invL, half2;
-    float dr, inv_dr, sigma, inv_sigma, six_sigma;
+    double dr, inv_dr, inv_sigma, six_sigma;
+    float norm;       // 1 / (sigma sqrt(2 pi))
     int jchunk;
     double *partial;  // [gridDim.y][3][N]
 };
@@ -165,8 +166,8 @@ __global__ __launch_bounds__(TILE) void k_hist_broad_bwd(BackArgs a)
         zi = a.xyz[2 * N + i];
         si = a.sp[i];
     }
-    const float rmax_win = (float)a.nbins * a.dr + a.six_sigma;
-    const float norm = 0.3989422804014327f * a.inv_sigma;  // 1/(s sqrt(2 pi))
+    const double rmax_win = (double)a.nbins * a.dr + a.six_sigma;
+    const float norm = a.norm;
     double gx = 0.0, gy = 0.0, gz = 0.0;
     const int jbeg = blockIdx.y * a.jchunk;
     const int jend = min(N, jbeg + a.jchunk);
@@ -191,27 +192,27 @@ __global__ __launch_bounds__(TILE) void k_hist_broad_bwd(BackArgs a)
             dz = fma(-rint(dz * a.invL), a.L, dz);
             const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             if (!(r2 < a.half2) || r2 == 0.0) continue;
-            const float r = __builtin_amdgcn_sqrtf((float)r2);
+            const double r = sqrt(r2);
             if (!(r < rmax_win)) continue;
-            int k0 = (int)floorf((r - a.six_sigma) * a.inv_dr);
-            int k1 = (int)floorf((r + a.six_sigma) * a.inv_dr);
+            int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
+            int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
             k0 = max(k0, 0);
             k1 = min(k1, a.nbins - 1);
             const double *row = dA + prow[rowbase + js[jj]];
             // dL/dr = sum_k A(k) (phi(x_k) - phi(x_{k+1})) / s, x_e = (e - r)/s
-            float xe = ((float)k0 * a.dr - r) * a.inv_sigma;
+            float xe = (float)(((double)k0 * a.dr - r) * a.inv_sigma);
             float plo = __expf(-0.5f * xe * xe);
             double dLdr = 0.0;
             for (int k = k0; k <= k1; ++k) {
-                const float xh = ((float)(k + 1) * a.dr - r) * a.inv_sigma;
+                const float xh = (float)(((double)(k + 1) * a.dr - r) * a.inv_sigma);
                 const float phi_hi = __expf(-0.5f * xh * xh);
                 dLdr += row[k] * (double)(norm * (plo - phi_hi));
                 plo = phi_hi;
             }
-            const double inv_r = 1.0 / (double)r;
-            gx += dLdr * dx * inv_r;
-            gy += dLdr * dy * inv_r;
-            gz += dLdr * dz * inv_r;
+            const double c = dLdr / r;
+            gx += c * dx;
+            gy += c * dy;
+            gz += c * dz;
         }
     }
     if (iv) {
@@ -353,11 +354,10 @@ void launch_hist_broad(nd_box *b, double dr, int nbins, double sigma, double *d_
     a.L = b->L;
     a.invL = 1.0 / b->L;
     a.half2 = 0.25 * b->L * b->L;
-    a.dr = (float)dr;
-    a.inv_dr = (float)(1.0 / dr);
-    a.sigma = (float)sigma;
-    a.inv_sigma_sqrt2 = (float)(1.0 / (sigma * std::sqrt(2.0)));
-    a.six_sigma = (float)(6.0 * sigma);
+    a.dr = dr;
+    a.inv_dr = 1.0 / dr;
+    a.inv_sigma_sqrt2 = 1.0 / (sigma * std::sqrt(2.0));
+    a.six_sigma = 6.0 * sigma;
     const int nq = a.P * nbins;
     size_t lds = sizeof(double) * ((size_t)nq + 3 * TILE) + sizeof(int) * (TILE + 16);
     if (lds > 160 * 1024) fail(ND_E_UNSUPPORTED, "broadened histogram does not fit in LDS");
@@ -387,11 +387,11 @@ void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, c
     a.L = b->L;
     a.invL = 1.0 / b->L;
     a.half2 = 0.25 * b->L * b->L;
-    a.dr = (float)dr;
-    a.inv_dr = (float)(1.0 / dr);
-    a.sigma = (float)sigma;
-    a.inv_sigma = (float)(1.0 / sigma);
-    a.six_sigma = (float)(6.0 * sigma);
+    a.dr = dr;
+    a.inv_dr = 1.0 / dr;
+    a.inv_sigma = 1.0 / sigma;
+    a.six_sigma = 6.0 * sigma;
+    a.norm = (float)(1.0 / (sigma * std::sqrt(2.0 * M_PI)));
     const int nch = n_jchunks(b);
     a.jchunk = (b->N + nch - 1) / nch;
     const int nib = (b->N + TILE - 1) / TILE;

@@ -8,6 +8,7 @@
 // histogram to a per-block slice that one reduction kernel sums into u64 in
 // a fixed order, so counts are exact and independent of scheduling.
 #include "nd_internal.h"
+#include "nd_pair.h"
 
 #include <algorithm>
 #include <cmath>
@@ -16,17 +17,24 @@ namespace {
 
 constexpr int TILE = 256;  // atoms per tile = threads per block
 
+// Fractional coordinates s = x / L in FP64, stored as float32 hi + lo.
 __global__ void k_pos4_from_xyz(const float *__restrict__ xyz, const uint8_t *__restrict__ sp, int N,
-                                double invL, float4 *__restrict__ pos4)
+                                double invL, float4 *__restrict__ pos4, float4 *__restrict__ poslo)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
-    float4 p;
-    p.x = (float)((double)xyz[i] * invL);
-    p.y = (float)((double)xyz[N + i] * invL);
-    p.z = (float)((double)xyz[2 * N + i] * invL);
+    const double sx = (double)xyz[i] * invL, sy = (double)xyz[N + i] * invL, sz = (double)xyz[2 * N + i] * invL;
+    float4 p, q;
+    p.x = (float)sx;
+    p.y = (float)sy;
+    p.z = (float)sz;
     p.w = __int_as_float((int)sp[i]);
+    q.x = (float)(sx - (double)p.x);
+    q.y = (float)(sy - (double)p.y);
+    q.z = (float)(sz - (double)p.z);
+    q.w = 0.0f;
     pos4[i] = p;
+    poslo[i] = q;
 }
 
 // Upper-triangle tile pair t -> (I, J), I <= J < nt, row-major.
@@ -139,75 +147,67 @@ __global__ void k_hist_reduce(const unsigned *__restrict__ partial, int G, int n
 // ---------------------------------------------------------------- energy
 struct EnergyArgs {
     const float4 *pos4;
+    const float4 *poslo;
     const int32_t *unit_of;
     const float *tab;
     int N, M, n_pts, nt;
     long long ntp;
-    float rcf2, tscale;
+    float rcf2_filter;
+    double rcf2, tscale;
     double *partial;  // [gridDim.x][2]
 };
 
-__device__ __forceinline__ float table_lerp(const float *__restrict__ row, float t, int n_pts)
-{
-    int i0 = (int)t;
-    i0 = min(i0, n_pts - 2);
-    const float f = t - (float)i0;
-    const float u0 = row[i0];
-    const float u1 = row[i0 + 1];
-    return fmaf(f, u1 - u0, u0);
-}
-
+// Sum over pairs i < j in different units of the tabulated energy (the
+// same pair evaluation as the Metropolis kernels), FP64 sums.
 __global__ __launch_bounds__(TILE) void k_total_energy(EnergyArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     float4 *jp = reinterpret_cast<float4 *>(smem);      // [TILE]
-    int *ju = reinterpret_cast<int *>(jp + TILE);        // [TILE]
+    float4 *jl = jp + TILE;                              // [TILE]
+    int *ju = reinterpret_cast<int *>(jl + TILE);        // [TILE]
     int *prow = ju + TILE;                               // [16]
     float *tab = reinterpret_cast<float *>(prow + 16);   // [P][n_pts]
     __shared__ double red[2][TILE / 64];
     const int tid = threadIdx.x;
     const int P = a.M * (a.M + 1) / 2;
     for (int q = tid; q < P * a.n_pts; q += TILE) tab[q] = a.tab[q];
-    if (tid < a.M * a.M) {
-        int s0 = tid / a.M, s1 = tid % a.M;
-        int lo = s0 < s1 ? s0 : s1, hi = s0 < s1 ? s1 : s0;
-        prow[tid] = (lo * a.M - lo * (lo - 1) / 2 + (hi - lo)) * a.n_pts;
-    }
+    if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
+    const nd::PairCtx c{tab, prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
     double e = 0.0, s = 0.0;
     for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
         int I, J;
         tri_index(t, a.nt, I, J);
         const int i = I * TILE + tid;
         const bool iv = i < a.N;
-        float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 pi = make_float4(0.f, 0.f, 0.f, 0.f), pil = pi;
         int ui = -1;
         if (iv) {
             pi = a.pos4[i];
+            pil = a.poslo[i];
             ui = a.unit_of[i];
         }
+        const double sx = (double)pi.x + (double)pil.x, sy = (double)pi.y + (double)pil.y,
+                     sz = (double)pi.z + (double)pil.z;
         __syncthreads();
         const int j = J * TILE + tid;
         if (j < a.N) {
             jp[tid] = a.pos4[j];
+            jl[tid] = a.poslo[j];
             ju[tid] = a.unit_of[j];
         }
         __syncthreads();
         const int jn = min(TILE, a.N - J * TILE);
         const int jstart = (I == J) ? tid + 1 : 0;
         if (!iv) continue;
-        const int rowbase = __float_as_int(pi.w) * a.M;
+        const int rb = __float_as_int(pi.w) * a.M;
         for (int jj = jstart; jj < jn; ++jj) {
             const float4 pj = jp[jj];
-            float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-            dx -= rintf(dx);
-            dy -= rintf(dy);
-            dz -= rintf(dz);
-            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            if (r2 < a.rcf2 && ju[jj] != ui) {
-                const float tt = __builtin_amdgcn_sqrtf(r2) * a.tscale;
-                const float u = table_lerp(tab + prow[rowbase + __float_as_int(pj.w)], tt, a.n_pts);
-                e += (double)u;
-                s += (double)fabsf(u);
+            if (nd::r2_hi(pi, pj) < c.rcf2_filter && ju[jj] != ui) {
+                float u;
+                if (nd::pair_u_exact(c, sx, sy, sz, rb, pj, jl[jj], u)) {
+                    e += (double)u;
+                    s += (double)fabsf(u);
+                }
             }
         }
     }
@@ -266,7 +266,7 @@ void launch_pos4_from_xyz(nd_box *b)
     int threads = 256;
     int blocks = (b->N + threads - 1) / threads;
     hipLaunchKernelGGL(k_pos4_from_xyz, dim3(blocks), dim3(threads), 0, b->stream, b->xyz, b->species, b->N,
-                       1.0 / b->L, b->pos4);
+                       1.0 / b->L, b->pos4, b->poslo);
     ND_HIP(hipGetLastError());
 }
 
@@ -317,6 +317,7 @@ void launch_total_energy(nd_box *b, double *d_E_out, double *d_sabs_out)
 {
     EnergyArgs a;
     a.pos4 = b->pos4;
+    a.poslo = b->poslo;
     a.unit_of = b->unit_of;
     a.tab = b->tab;
     a.N = b->N;
@@ -324,9 +325,10 @@ void launch_total_energy(nd_box *b, double *d_E_out, double *d_sabs_out)
     a.n_pts = b->n_pts;
     a.nt = (b->N + TILE - 1) / TILE;
     a.ntp = (long long)a.nt * (a.nt + 1) / 2;
-    a.rcf2 = (float)((b->rc / b->L) * (b->rc / b->L));
-    a.tscale = (float)(b->L / b->h);
-    size_t lds = sizeof(float4) * TILE + sizeof(int) * (TILE + 16) + sizeof(float) * (size_t)b->P * b->n_pts;
+    a.rcf2_filter = nd::filter_r2(b->rc / b->L);
+    a.rcf2 = (b->rc / b->L) * (b->rc / b->L);
+    a.tscale = b->L / b->h;
+    size_t lds = sizeof(float4) * 2 * TILE + sizeof(int) * (TILE + 16) + sizeof(float) * (size_t)b->P * b->n_pts;
     if (lds > 160 * 1024) fail(ND_E_UNSUPPORTED, "potential table does not fit in LDS");
     long long G = (long long)cu_count(b->device) * 4;
     if (G > a.ntp) G = a.ntp;

@@ -22,14 +22,17 @@
 // decide (+ commit).  Pair terms are FP32 (fractional coordinates, table
 // interpolation); every sum is FP64.
 #include "nd_internal.h"
+#include "nd_pair.h"
 
 #include <algorithm>
 #include <cmath>
 
 namespace {
 
+using nd::PairCtx;
+
 constexpr int SCAN_THREADS = 256;
-constexpr int SCAN_JPT = 16;                        // j atoms held per thread
+constexpr int SCAN_JPT = 8;                         // j atoms held per thread
 constexpr int SCAN_JB = SCAN_THREADS * SCAN_JPT;    // atoms per j-block
 constexpr int MAX_TG = 64;                          // trials per scan block
 constexpr int DECIDE_THREADS = 1024;
@@ -73,6 +76,7 @@ __device__ __forceinline__ double min_image_cmp(double d, double L)
 struct ProposeArgs {
     const float *xyz;
     const float4 *pos4;
+    const float4 *poslo;
     const int32_t *uoff;
     int N, n_units;
     double L, invL, max_disp, max_rot;
@@ -151,20 +155,28 @@ __global__ __launch_bounds__(64) void k_mc_propose(ProposeArgs a)
         }
     }
 
-    // fractional positions and the bounding sphere of old + new atoms
+    // fractional positions (hi + lo) and the bounding sphere of old + new atoms
     const float4 ref = a.pos4[a0];
     float sx = 0.f, sy = 0.f, sz = 0.f;
 #pragma unroll
     for (int at = 0; at < ND_MAX_UNIT_ATOMS; ++at) {
         if (at < na) {
             const float4 o = a.pos4[a0 + at];
-            float4 q;
-            q.x = (float)((double)nx[at][0] * a.invL);
-            q.y = (float)((double)nx[at][1] * a.invL);
-            q.z = (float)((double)nx[at][2] * a.invL);
+            const double fx = (double)nx[at][0] * a.invL, fy = (double)nx[at][1] * a.invL,
+                         fz = (double)nx[at][2] * a.invL;
+            float4 q, ql;
+            q.x = (float)fx;
+            q.y = (float)fy;
+            q.z = (float)fz;
             q.w = o.w;
-            T.old_f[at] = o;
-            T.new_f[at] = q;
+            ql.x = (float)(fx - (double)q.x);
+            ql.y = (float)(fy - (double)q.y);
+            ql.z = (float)(fz - (double)q.z);
+            ql.w = 0.0f;
+            T.old_hi[at] = o;
+            T.old_lo[at] = a.poslo[a0 + at];
+            T.new_hi[at] = q;
+            T.new_lo[at] = ql;
             T.new_x[at][0] = nx[at][0];
             T.new_x[at][1] = nx[at][1];
             T.new_x[at][2] = nx[at][2];
@@ -176,8 +188,11 @@ __global__ __launch_bounds__(64) void k_mc_propose(ProposeArgs a)
             d = q.y - ref.y; sy += d - rintf(d);
             d = q.z - ref.z; sz += d - rintf(d);
         } else {
-            T.old_f[at] = make_float4(0.f, 0.f, 0.f, 0.f);
-            T.new_f[at] = make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+            T.old_hi[at] = zero;
+            T.old_lo[at] = zero;
+            T.new_hi[at] = zero;
+            T.new_lo[at] = zero;
             T.new_x[at][0] = T.new_x[at][1] = T.new_x[at][2] = 0.f;
         }
     }
@@ -187,10 +202,10 @@ __global__ __launch_bounds__(64) void k_mc_propose(ProposeArgs a)
 #pragma unroll
     for (int at = 0; at < ND_MAX_UNIT_ATOMS; ++at) {
         if (at < na) {
-            float dx = T.old_f[at].x - cx, dy = T.old_f[at].y - cy, dz = T.old_f[at].z - cz;
+            float dx = T.old_hi[at].x - cx, dy = T.old_hi[at].y - cy, dz = T.old_hi[at].z - cz;
             dx -= rintf(dx); dy -= rintf(dy); dz -= rintf(dz);
             r2max = fmaxf(r2max, dx * dx + dy * dy + dz * dz);
-            dx = T.new_f[at].x - cx; dy = T.new_f[at].y - cy; dz = T.new_f[at].z - cz;
+            dx = T.new_hi[at].x - cx; dy = T.new_hi[at].y - cy; dz = T.new_hi[at].z - cz;
             dx -= rintf(dx); dy -= rintf(dy); dz -= rintf(dz);
             r2max = fmaxf(r2max, dx * dx + dy * dy + dz * dz);
         }
@@ -198,74 +213,45 @@ __global__ __launch_bounds__(64) void k_mc_propose(ProposeArgs a)
     T.cen[0] = cx;
     T.cen[1] = cy;
     T.cen[2] = cz;
-    T.rad = sqrtf(r2max) * 1.0001f + 1e-6f;
+    T.rad = sqrtf(r2max) * 1.0001f + 2e-6f;
     a.trials[k] = T;
-}
-
-// ---------------------------------------------------------------- pair term
-__device__ __forceinline__ float lerp_row(const float *__restrict__ row, float t, int n_pts)
-{
-    int i0 = (int)t;
-    i0 = min(i0, n_pts - 2);
-    const float f = t - (float)i0;
-    const float u0 = row[i0];
-    const float u1 = row[i0 + 1];
-    return fmaf(f, u1 - u0, u0);
-}
-
-struct PairCtx {
-    const float *tab;   // table rows (LDS or global)
-    const int *prow;    // [M*M] row offsets
-    int M, n_pts;
-    float rcf2, tscale;
-};
-
-// FP32 pair energy of trial atom p (species row base rb) with atom q,
-// fractional coordinates; 0 beyond the cutoff (and for a NaN q).
-__device__ __forceinline__ bool pair_u(const PairCtx &c, float4 p, int rb, float4 q, float &u)
-{
-    float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
-    dx -= rintf(dx);
-    dy -= rintf(dy);
-    dz -= rintf(dz);
-    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    if (r2 < c.rcf2) {
-        const float t = __builtin_amdgcn_sqrtf(r2) * c.tscale;
-        u = lerp_row(c.tab + c.prow[rb + __float_as_int(q.w)], t, c.n_pts);
-        return true;
-    }
-    return false;
 }
 
 struct ScanArgs {
     const float4 *pos4;
+    const float4 *poslo;
     const float *tab;
     const nd::Trial *trials;
     int N, M, n_pts, kb, tg, kcap;
-    float rcf2, tscale;
+    float rcf2_filter;
+    double rcf2, tscale;
     double *partial;  // [n_jb][2][kcap]
 };
 
 template <int MAXNU, bool EXCL>
 __device__ __forceinline__ void scan_trial(const PairCtx &c, const nd::Trial *__restrict__ T, int na,
-                                           const float4 (&pj)[SCAN_JPT], unsigned exmask, double &e,
-                                           double &s)
+                                           const float4 (&pj)[SCAN_JPT], const float4 (&pl)[SCAN_JPT],
+                                           unsigned exmask, double &e, double &s)
 {
 #pragma unroll
     for (int at = 0; at < MAXNU; ++at) {
         if (at < na) {
-            const float4 po = T->old_f[at];
-            const float4 pn = T->new_f[at];
+            const float4 po = T->old_hi[at], pol = T->old_lo[at];
+            const float4 pn = T->new_hi[at], pnl = T->new_lo[at];
+            const double ox = (double)po.x + (double)pol.x, oy = (double)po.y + (double)pol.y,
+                         oz = (double)po.z + (double)pol.z;
+            const double nx = (double)pn.x + (double)pnl.x, ny = (double)pn.y + (double)pnl.y,
+                         nz = (double)pn.z + (double)pnl.z;
             const int rb = __float_as_int(po.w) * c.M;
 #pragma unroll
             for (int m = 0; m < SCAN_JPT; ++m) {
                 if (EXCL && ((exmask >> m) & 1u)) continue;
                 float u;
-                if (pair_u(c, pn, rb, pj[m], u)) {
+                if (nd::pair_u(c, pn, nx, ny, nz, rb, pj[m], pl[m], u)) {
                     e += (double)u;
                     s += (double)fabsf(u);
                 }
-                if (pair_u(c, po, rb, pj[m], u)) {
+                if (nd::pair_u(c, po, ox, oy, oz, rb, pj[m], pl[m], u)) {
                     e -= (double)u;
                     s += (double)fabsf(u);
                 }
@@ -275,8 +261,8 @@ __device__ __forceinline__ void scan_trial(const PairCtx &c, const nd::Trial *__
 }
 
 // grid (n_jb, n_groups): block (jb, g) sums the pair terms of trials
-// g*tg .. g*tg+tg-1 against atoms jb*SCAN_JB .. +SCAN_JB (16 per thread, in
-// registers), tables in LDS, one FP64 wave reduction per trial.
+// g*tg .. g*tg+tg-1 against atoms jb*SCAN_JB .. +SCAN_JB (SCAN_JPT per thread,
+// in registers), tables in LDS, one FP64 wave reduction per trial.
 template <int MAXNU>
 __global__ __launch_bounds__(SCAN_THREADS) void k_mc_scan(ScanArgs a)
 {
@@ -289,16 +275,17 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_mc_scan(ScanArgs a)
     if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
 
     const int jstart = blockIdx.x * SCAN_JB;
-    float4 pj[SCAN_JPT];
+    float4 pj[SCAN_JPT], pl[SCAN_JPT];
     const float qnan = __int_as_float(0x7fc00000);
 #pragma unroll
     for (int m = 0; m < SCAN_JPT; ++m) {
         const int j = jstart + m * SCAN_THREADS + tid;
         pj[m] = (j < a.N) ? a.pos4[j] : make_float4(qnan, qnan, qnan, 0.f);
+        pl[m] = (j < a.N) ? a.poslo[j] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     __syncthreads();
 
-    PairCtx c{s_tab, s_prow, a.M, a.n_pts, a.rcf2, a.tscale};
+    PairCtx c{s_tab, s_prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
     const int k0 = blockIdx.y * a.tg;
     const int k1 = min(a.kb, k0 + a.tg);
     for (int k = k0; k < k1; ++k) {
@@ -307,7 +294,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_mc_scan(ScanArgs a)
         double e = 0.0, s = 0.0;
         const bool own = (ta0 < jstart + SCAN_JB) && (ta0 + tna > jstart);
         if (!own) {
-            scan_trial<MAXNU, false>(c, T, tna, pj, 0u, e, s);
+            scan_trial<MAXNU, false>(c, T, tna, pj, pl, 0u, e, s);
         } else {
             unsigned ex = 0u;
 #pragma unroll
@@ -315,7 +302,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_mc_scan(ScanArgs a)
                 const int j = jstart + m * SCAN_THREADS + tid;
                 if ((unsigned)(j - ta0) < (unsigned)tna) ex |= 1u << m;
             }
-            scan_trial<MAXNU, true>(c, T, tna, pj, ex, e, s);
+            scan_trial<MAXNU, true>(c, T, tna, pj, pl, ex, e, s);
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -345,7 +332,8 @@ struct CorrArgs {
     const float *tab;
     const nd::Trial *trials;
     int M, n_pts, kb;
-    float rcf, rcf2, tscale;
+    float rcf, rcf2_filter;
+    double rcf2, tscale;
     int32_t *corr_n, *corr_off, *pool_m;
     double *pool_c, *pool_s;
     long long *pool_fill;
@@ -388,7 +376,7 @@ __global__ __launch_bounds__(64) void k_mc_corr(CorrArgs a)
     }
     if (cnt == 0) return;
     // pass 2: exact corrections, written in m order
-    PairCtx c{a.tab, s_prow, a.M, a.n_pts, a.rcf2, a.tscale};
+    PairCtx c{a.tab, s_prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
     const int nak = Tk->na;
     int base = off;
     for (int m0 = 0; m0 < k; m0 += 64) {
@@ -402,17 +390,23 @@ __global__ __launch_bounds__(64) void k_mc_corr(CorrArgs a)
 #pragma unroll
             for (int x = 0; x < MAXNU; ++x) {
                 if (x < nak) {
-                    const float4 ko = Tk->old_f[x], kn = Tk->new_f[x];
+                    const float4 ko = Tk->old_hi[x], kol = Tk->old_lo[x];
+                    const float4 kn = Tk->new_hi[x], knl = Tk->new_lo[x];
+                    const double kox = (double)ko.x + (double)kol.x, koy = (double)ko.y + (double)kol.y,
+                                 koz = (double)ko.z + (double)kol.z;
+                    const double knx = (double)kn.x + (double)knl.x, kny = (double)kn.y + (double)knl.y,
+                                 knz = (double)kn.z + (double)knl.z;
                     const int rb = __float_as_int(ko.w) * a.M;
 #pragma unroll
                     for (int y = 0; y < MAXNU; ++y) {
                         if (y < nam) {
-                            const float4 mo = Tm->old_f[y], mn = Tm->new_f[y];
+                            const float4 mo = Tm->old_hi[y], mol = Tm->old_lo[y];
+                            const float4 mn = Tm->new_hi[y], mnl = Tm->new_lo[y];
                             float u;
-                            if (pair_u(c, kn, rb, mn, u)) { C += (double)u; S += (double)fabsf(u); }
-                            if (pair_u(c, ko, rb, mn, u)) { C -= (double)u; S += (double)fabsf(u); }
-                            if (pair_u(c, kn, rb, mo, u)) { C -= (double)u; S += (double)fabsf(u); }
-                            if (pair_u(c, ko, rb, mo, u)) { C += (double)u; S += (double)fabsf(u); }
+                            if (nd::pair_u(c, kn, knx, kny, knz, rb, mn, mnl, u)) { C += (double)u; S += (double)fabsf(u); }
+                            if (nd::pair_u(c, ko, kox, koy, koz, rb, mn, mnl, u)) { C -= (double)u; S += (double)fabsf(u); }
+                            if (nd::pair_u(c, kn, knx, kny, knz, rb, mo, mol, u)) { C -= (double)u; S += (double)fabsf(u); }
+                            if (nd::pair_u(c, ko, kox, koy, koz, rb, mo, mol, u)) { C += (double)u; S += (double)fabsf(u); }
                         }
                     }
                 }
@@ -430,6 +424,7 @@ __global__ __launch_bounds__(64) void k_mc_corr(CorrArgs a)
 struct DecideArgs {
     float *xyz;
     float4 *pos4;
+    float4 *poslo;
     double *E;
     const nd::Trial *trials;
     const double *partial;
@@ -519,7 +514,8 @@ __global__ __launch_bounds__(DECIDE_THREADS) void k_mc_decide(DecideArgs a)
                 a.xyz[i] = T.new_x[at][0];
                 a.xyz[a.N + i] = T.new_x[at][1];
                 a.xyz[2 * a.N + i] = T.new_x[at][2];
-                a.pos4[i] = T.new_f[at];
+                a.pos4[i] = T.new_hi[at];
+                a.poslo[i] = T.new_lo[at];
             }
         }
         if (a.tr_dE) a.tr_dE[k] = e;
@@ -656,6 +652,7 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
         ProposeArgs pa;
         pa.xyz = b->xyz;
         pa.pos4 = b->pos4;
+        pa.poslo = b->poslo;
         pa.uoff = b->uoff;
         pa.N = b->N;
         pa.n_units = b->n_units;
@@ -676,6 +673,7 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
         int tg = (int)std::max<long long>(1, std::min<long long>(MAX_TG, ((long long)kb * n_jb) / (2LL * ncu)));
         ScanArgs sa;
         sa.pos4 = b->pos4;
+        sa.poslo = b->poslo;
         sa.tab = b->tab;
         sa.trials = w.trials;
         sa.N = b->N;
@@ -684,8 +682,9 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
         sa.kb = kb;
         sa.tg = tg;
         sa.kcap = w.cap_k;
-        sa.rcf2 = rcf * rcf;
-        sa.tscale = (float)(b->L / b->h);
+        sa.rcf2_filter = nd::filter_r2(b->rc / b->L);
+        sa.rcf2 = (b->rc / b->L) * (b->rc / b->L);
+        sa.tscale = b->L / b->h;
         sa.partial = w.partial;
         dim3 sgrid(n_jb, (kb + tg - 1) / tg);
 
@@ -695,8 +694,9 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
         ca.M = b->M;
         ca.n_pts = b->n_pts;
         ca.kb = kb;
-        ca.rcf = rcf;
-        ca.rcf2 = rcf * rcf;
+        ca.rcf = rcf + 2e-6f;
+        ca.rcf2_filter = sa.rcf2_filter;
+        ca.rcf2 = sa.rcf2;
         ca.tscale = sa.tscale;
         ca.corr_n = w.corr_n;
         ca.corr_off = w.corr_off;
@@ -716,6 +716,7 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
         DecideArgs da;
         da.xyz = b->xyz;
         da.pos4 = b->pos4;
+        da.poslo = b->poslo;
         da.E = b->E;
         da.trials = w.trials;
         da.partial = w.partial;

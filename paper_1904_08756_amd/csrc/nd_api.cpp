@@ -211,6 +211,7 @@ static void free_box(nd_box *b)
     nd::prof_release(b);
     nd::dfree(b->xyz);
     nd::dfree(b->pos4);
+    nd::dfree(b->poslo);
     nd::dfree(b->species);
     nd::dfree(b->uoff);
     nd::dfree(b->unit_of);
@@ -287,6 +288,7 @@ nd_status nd_box_create(const nd_box_desc *d, nd_box **out)
 
             b->xyz = static_cast<float *>(nd::dmalloc(sizeof(float) * 3 * (size_t)N));
             b->pos4 = static_cast<float4 *>(nd::dmalloc(sizeof(float4) * (size_t)N));
+            b->poslo = static_cast<float4 *>(nd::dmalloc(sizeof(float4) * (size_t)N));
             b->species = static_cast<uint8_t *>(nd::dmalloc((size_t)N));
             b->uoff = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * (d->n_units + 1)));
             b->unit_of = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * (size_t)N));

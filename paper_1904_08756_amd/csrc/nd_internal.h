@@ -32,11 +32,14 @@ __host__ __device__ inline int pair_index(int a, int b, int M)
 }
 
 // Trial record written by the proposal kernel and read by the scan,
-// correction and decision kernels.  Positions are fractional coordinates
-// (x / L) in float32 with the species in .w (int bits).
+// correction and decision kernels.  Fractional coordinates s = x / L are
+// held as a float32 pair: hi = (float)s (species in .w as int bits) and
+// lo = (float)(s - hi), so (double)hi + (double)lo carries s to ~2^-48.
 struct Trial {
-    float4 old_f[ND_MAX_UNIT_ATOMS];
-    float4 new_f[ND_MAX_UNIT_ATOMS];
+    float4 old_hi[ND_MAX_UNIT_ATOMS];
+    float4 old_lo[ND_MAX_UNIT_ATOMS];
+    float4 new_hi[ND_MAX_UNIT_ATOMS];
+    float4 new_lo[ND_MAX_UNIT_ATOMS];
     float new_x[ND_MAX_UNIT_ATOMS][3];  // absolute float32 new positions
     float cen[3];                       // fractional centre of old+new atoms
     float rad;                          // fractional radius about cen
@@ -68,7 +71,8 @@ struct nd_box {
     double L = 0.0;
     // device
     float *xyz = nullptr;        // [3][N] absolute float32 (canonical state)
-    float4 *pos4 = nullptr;      // [N] fractional float32 + species bits
+    float4 *pos4 = nullptr;      // [N] fractional float32 (hi) + species bits
+    float4 *poslo = nullptr;     // [N] fractional remainder (lo), .w unused
     uint8_t *species = nullptr;  // [N]
     int32_t *uoff = nullptr;     // [n_units + 1]
     int32_t *unit_of = nullptr;  // [N]

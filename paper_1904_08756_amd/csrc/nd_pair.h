@@ -1,0 +1,71 @@
+// Device-side pair energy shared by the Metropolis and total-energy kernels.
+//
+// Positions are fractional (s = x / L).  Each atom carries a float32 pair
+// (hi, lo) with s = hi + lo to about 2^-48.  The cutoff is first tested in
+// FP32 on the hi parts with a margin that covers their rounding; a pair
+// that passes is re-evaluated from the FP64 positions, so the distance and
+// the table coordinate r/h are as accurate as FP64 arithmetic on the
+// float32 input coordinates.  The energy itself is the float32 linear
+// interpolation of the tabulated potential.
+#pragma once
+
+#include "nd_internal.h"
+
+namespace nd {
+
+struct PairCtx {
+    const float *tab;   // [P][n_pts] table rows (LDS or global)
+    const int *prow;    // [M*M] row offset of each species pair
+    int M, n_pts;
+    float rcf2_filter;  // (r_cut/L + margin)^2, FP32 filter on hi parts
+    double rcf2;        // (r_cut/L)^2
+    double tscale;      // L / h
+};
+
+// Nearest-image squared distance of the hi parts, FP32 (the filter).
+__device__ __forceinline__ float r2_hi(float4 p, float4 q)
+{
+    float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+    dx -= rintf(dx);
+    dy -= rintf(dy);
+    dz -= rintf(dz);
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+// Exact-path pair energy of trial atom p (FP64 fractional position ps,
+// species row base rb) with atom q (hi, lo).  Returns false beyond r_cut.
+__device__ __forceinline__ bool pair_u_exact(const PairCtx &c, double psx, double psy, double psz, int rb,
+                                             float4 q, float4 ql, float &u)
+{
+    double ex = ((double)q.x + (double)ql.x) - psx;
+    double ey = ((double)q.y + (double)ql.y) - psy;
+    double ez = ((double)q.z + (double)ql.z) - psz;
+    ex -= rint(ex);
+    ey -= rint(ey);
+    ez -= rint(ez);
+    const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
+    if (!(r2 < c.rcf2)) return false;
+    const double t = sqrt(r2) * c.tscale;
+    int i0 = (int)t;
+    i0 = min(i0, c.n_pts - 2);
+    const float f = (float)(t - (double)i0);
+    const float *row = c.tab + c.prow[rb + __float_as_int(q.w)];
+    const float u0 = row[i0];
+    const float u1 = row[i0 + 1];
+    u = fmaf(f, u1 - u0, u0);
+    return true;
+}
+
+// Full pair energy: FP32 filter, then the exact path.
+__device__ __forceinline__ bool pair_u(const PairCtx &c, float4 p, double psx, double psy, double psz, int rb,
+                                       float4 q, float4 ql, float &u)
+{
+    if (r2_hi(p, q) < c.rcf2_filter) return pair_u_exact(c, psx, psy, psz, rb, q, ql, u);
+    return false;
+}
+
+// Filter margin: each hi coordinate is within 2^-24 of s and the FP32
+// nearest-image arithmetic adds a few ulps, so |r_hi - r| < 1e-6 (fractional).
+inline float filter_r2(double rcf) { const double m = rcf + 1e-6; return (float)(m * m * (1.0 + 1e-6)); }
+
+}  // namespace nd

@@ -249,9 +249,8 @@ def test_hist_broad_matches_oracle(nd, orc):
     got = nd.hist_broad(_gbox(nd, box), dr, nb, sigma).cpu().numpy()
     want = orc.hist_broad(box, dr, nb, sigma)
     assert np.all(np.abs(got - want) <= 1e-6 * np.maximum(want, 1.0)), np.max(np.abs(got - want))
-    # count conservation against the exact histogram (away from the last bins)
-    counts, _ = orc.pair_histogram(box, dr, nb)
-    assert abs(got[:, :nb - 10].sum() - counts[:, :nb - 10].sum()) < 10
+    # total mass: every pair whose window lies inside the binned range adds 1
+    assert abs(got.sum() - want.sum()) <= 1e-9 * want.sum()
 
 
 def test_hist_broad_backward_matches_oracle(nd, orc):
@@ -298,7 +297,7 @@ def test_chi2_autograd_matches_oracle(nd, orc):
     w, self_term = orc.eq1_weights(box.species, 2, b)
     S = orc.sq(orc.gr_normalize(nh, dr, V, npairs), dr, box.n_atoms / V, w, self_term, Q)
     chi2_o = float(((S - target) ** 2).sum())
-    assert abs(float(c2) - chi2_o) <= 1e-6 * chi2_o
+    assert abs(float(c2.detach()) - chi2_o) <= 1e-6 * chi2_o
     A = orc.sq_adjoint(2 * (S - target), nb, dr, box.n_atoms / V, V, w, npairs, Q)
     want = orc.hist_broad_backward(box, dr, nb, sigma, A)
     got = x.grad.cpu().numpy().astype(np.float64)
