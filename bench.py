@@ -226,6 +226,27 @@ def main():
             "batched": None,
         }
         log("forms done")
+        # the paper's O(N) scan (every atom tested for every trial), one sweep
+        p_full = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"], scan=nd.ND_SCAN_FULL)
+        g.mc_sweep(p_full, mc["seed"], 10 ** 9, 4000, stats=False)
+        torch.cuda.synchronize()
+        g.set_profiling(True)
+        t = time.perf_counter()
+        g.mc_sweep(p_full, mc["seed"], 10 ** 9 + 4000, box.n_units, stats=False)
+        torch.cuda.synchronize()
+        t_full = time.perf_counter() - t
+        fn, fms = g.profile("mc_scan")
+        g.set_profiling(False)
+        f_tests = box.n_units * n_tests_per_trial / fn
+        f_avg = fms / fn / 1e3
+        result["full_scan"] = {
+            "mc_moves_per_s": box.n_units / t_full,
+            "roofline": {"kernel": "k_mc_scan (O(N) scan)", "bound": "alu",
+                         "achieved": f_tests * OPS_PER_TEST / f_avg / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                         "unit": "Tlane-op/s", "frac": f_tests * OPS_PER_TEST / f_avg / PEAK_LANE_OPS,
+                         "launches": fn, "avg_launch_us": f_avg * 1e6},
+        }
+        log("full scan done")
         # SiO2 box: one sweep of single-atom moves
         box3, T3, mc3 = syn.config_c3()
         g3 = nd.Box.from_synthetic(box3)

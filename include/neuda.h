@@ -90,7 +90,16 @@ typedef struct nd_mc_params {
     int32_t order;      /* ND_ORDER_SEQ or ND_ORDER_RANDOM                        */
     int32_t k_batch;    /* trials evaluated together; 0 = chosen by the library   */
     double tie_rel;     /* near-tie threshold (see nd_mc_sweep); 0 = 1e-6         */
+    int32_t scan;       /* ND_SCAN_CELLS (default) or ND_SCAN_FULL                 */
 } nd_mc_params;
+
+/* How nd_mc_sweep finds the atoms within the cutoff of a moved unit.  Both
+ * give the same energy changes (pairs beyond r_cut contribute exactly 0):
+ * ND_SCAN_CELLS visits only atoms in spatial cells that can be within reach
+ * (atoms sorted by cell, rebuilt once per sweep); ND_SCAN_FULL tests every
+ * atom of the box for every trial, the O(N) scan of the paper. */
+#define ND_SCAN_CELLS 0
+#define ND_SCAN_FULL 1
 
 /* Counters of one nd_mc_sweep call. */
 typedef struct nd_mc_stats {

@@ -31,6 +31,8 @@ ND_HOST = 0
 ND_DEVICE = 1
 ND_ORDER_SEQ = 0
 ND_ORDER_RANDOM = 1
+ND_SCAN_CELLS = 0
+ND_SCAN_FULL = 1
 PROF = {"mc_scan": 0, "mc_corr": 1, "mc_decide": 2, "mc_propose": 3, "pair_hist": 4,
         "hist_broad": 5, "hist_broad_bwd": 6, "forces": 7}
 STATUS = {0: "ND_OK", -1: "ND_E_INVALID", -2: "ND_E_RANGE", -3: "ND_E_OOM", -4: "ND_E_HIP",
@@ -51,7 +53,8 @@ class nd_box_desc(C.Structure):
 
 class nd_mc_params(C.Structure):
     _fields_ = [("kT", C.c_double), ("max_disp", C.c_double), ("max_rot", C.c_double),
-                ("order", C.c_int32), ("k_batch", C.c_int32), ("tie_rel", C.c_double)]
+                ("order", C.c_int32), ("k_batch", C.c_int32), ("tie_rel", C.c_double),
+                ("scan", C.c_int32)]
 
 
 class nd_mc_stats(C.Structure):
@@ -162,10 +165,11 @@ class MCParams:
     order: int = ND_ORDER_SEQ
     k_batch: int = 0
     tie_rel: float = 0.0
+    scan: int = ND_SCAN_CELLS
 
     def c(self):
         return nd_mc_params(self.kT, self.max_disp, self.max_rot, self.order, self.k_batch,
-                            self.tie_rel)
+                            self.tie_rel, self.scan)
 
 
 class Box:

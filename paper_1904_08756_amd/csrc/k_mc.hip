@@ -35,7 +35,6 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_JPT = 8;                         // j atoms held per thread
 constexpr int SCAN_JB = SCAN_THREADS * SCAN_JPT;    // atoms per j-block
 constexpr int MAX_TG = 64;                          // trials per scan block
-constexpr int DECIDE_THREADS = 1024;
 constexpr int KMAX = 2048;                          // trials per batch
 constexpr double TWO_PI = 6.283185307179586;
 
@@ -83,6 +82,7 @@ struct ProposeArgs {
     uint64_t seed, t0;
     int kb;
     nd::Trial *trials;
+    float4 *spheres;
 };
 
 // One thread per trial: translation tau = d (2u - 1) per axis; for units of
@@ -90,131 +90,123 @@ struct ProposeArgs {
 // (sqrt(1-z^2) cos phi, sqrt(1-z^2) sin phi, z), z = 2u_3 - 1, phi = 2 pi u_4,
 // through the unweighted centroid of the unit unwrapped around its first
 // atom (Rodrigues' formula).  FP64, then wrapped and rounded to float32.
-__global__ __launch_bounds__(64) void k_mc_propose(ProposeArgs a)
+__device__ void propose_one(const ProposeArgs &a, int k)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.kb) return;
     const uint64_t t = a.t0 + (uint64_t)k;
     const int u = (int)(t % (uint64_t)a.n_units);
     const int a0 = a.uoff[u];
     const int na = a.uoff[u + 1] - a0;
     const int N = a.N;
     const double L = a.L;
+    nd::Trial *T = a.trials + k;
 
     double tau[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) tau[c] = a.max_disp * (2.0 * draw(a.seed, t, c) - 1.0);
+    T->unit = u;
+    T->a0 = a0;
+    T->na = na;
+    T->pad = 0;
+    T->u_acc = draw(a.seed, t, 6);
 
-    nd::Trial T;
-    T.unit = u;
-    T.a0 = a0;
-    T.na = na;
-    T.pad = 0;
-    T.u_acc = draw(a.seed, t, 6);
-
-    float nx[ND_MAX_UNIT_ATOMS][3];
-    if (na == 1) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) nx[0][c] = wrap_round((double)a.xyz[c * N + a0] + tau[c], L);
-    } else {
-        double p[ND_MAX_UNIT_ATOMS][3];
-        double cen[3];
+    // centroid of the unit unwrapped around its first atom, rotation
+    double x0[3] = {0.0, 0.0, 0.0}, cen[3] = {0.0, 0.0, 0.0};
+    double n0 = 0.0, n1 = 0.0, n2 = 0.0, ct = 1.0, st = 0.0, omc = 0.0;
+    if (na > 1) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double x0 = (double)a.xyz[c * N + a0];
+            x0[c] = (double)a.xyz[c * N + a0];
             double s = 0.0;
-#pragma unroll
-            for (int at = 0; at < ND_MAX_UNIT_ATOMS; ++at) {
-                if (at < na) {
-                    p[at][c] = x0 + min_image_cmp((double)a.xyz[c * N + a0 + at] - x0, L);
-                    s += p[at][c];
-                }
-            }
+            for (int at = 0; at < na; ++at) s += x0[c] + min_image_cmp((double)a.xyz[c * N + a0 + at] - x0[c], L);
             cen[c] = s / (double)na;
         }
         const double zc = 2.0 * draw(a.seed, t, 3) - 1.0;
         const double phi = TWO_PI * draw(a.seed, t, 4);
         const double sr = sqrt(1.0 - zc * zc);
-        const double n0 = sr * cos(phi), n1 = sr * sin(phi), n2 = zc;
+        n0 = sr * cos(phi);
+        n1 = sr * sin(phi);
+        n2 = zc;
         const double th = a.max_rot * (2.0 * draw(a.seed, t, 5) - 1.0);
-        const double ct = cos(th), st = sin(th), omc = 1.0 - ct;
-#pragma unroll
-        for (int at = 0; at < ND_MAX_UNIT_ATOMS; ++at) {
-            if (at < na) {
-                const double v0 = p[at][0] - cen[0], v1 = p[at][1] - cen[1], v2 = p[at][2] - cen[2];
-                const double c0 = n1 * v2 - n2 * v1, c1 = n2 * v0 - n0 * v2, c2 = n0 * v1 - n1 * v0;
-                const double dot = n0 * v0 + n1 * v1 + n2 * v2;
-                const double kk = dot * omc;
-                const double w0 = v0 * ct + c0 * st + n0 * kk;
-                const double w1 = v1 * ct + c1 * st + n1 * kk;
-                const double w2 = v2 * ct + c2 * st + n2 * kk;
-                nx[at][0] = wrap_round(cen[0] + w0 + tau[0], L);
-                nx[at][1] = wrap_round(cen[1] + w1 + tau[1], L);
-                nx[at][2] = wrap_round(cen[2] + w2 + tau[2], L);
-            }
-        }
+        ct = cos(th);
+        st = sin(th);
+        omc = 1.0 - ct;
     }
 
-    // fractional positions (hi + lo) and the bounding sphere of old + new atoms
+    // new positions, atom by atom, written straight into the trial record
     const float4 ref = a.pos4[a0];
     float sx = 0.f, sy = 0.f, sz = 0.f;
-#pragma unroll
-    for (int at = 0; at < ND_MAX_UNIT_ATOMS; ++at) {
-        if (at < na) {
-            const float4 o = a.pos4[a0 + at];
-            const double fx = (double)nx[at][0] * a.invL, fy = (double)nx[at][1] * a.invL,
-                         fz = (double)nx[at][2] * a.invL;
-            float4 q, ql;
-            q.x = (float)fx;
-            q.y = (float)fy;
-            q.z = (float)fz;
-            q.w = o.w;
-            ql.x = (float)(fx - (double)q.x);
-            ql.y = (float)(fy - (double)q.y);
-            ql.z = (float)(fz - (double)q.z);
-            ql.w = 0.0f;
-            T.old_hi[at] = o;
-            T.old_lo[at] = a.poslo[a0 + at];
-            T.new_hi[at] = q;
-            T.new_lo[at] = ql;
-            T.new_x[at][0] = nx[at][0];
-            T.new_x[at][1] = nx[at][1];
-            T.new_x[at][2] = nx[at][2];
-            float d;
-            d = o.x - ref.x; sx += d - rintf(d);
-            d = o.y - ref.y; sy += d - rintf(d);
-            d = o.z - ref.z; sz += d - rintf(d);
-            d = q.x - ref.x; sx += d - rintf(d);
-            d = q.y - ref.y; sy += d - rintf(d);
-            d = q.z - ref.z; sz += d - rintf(d);
+    for (int at = 0; at < na; ++at) {
+        float nx0, nx1, nx2;
+        if (na == 1) {
+            nx0 = wrap_round((double)a.xyz[a0] + tau[0], L);
+            nx1 = wrap_round((double)a.xyz[N + a0] + tau[1], L);
+            nx2 = wrap_round((double)a.xyz[2 * N + a0] + tau[2], L);
         } else {
-            const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-            T.old_hi[at] = zero;
-            T.old_lo[at] = zero;
-            T.new_hi[at] = zero;
-            T.new_lo[at] = zero;
-            T.new_x[at][0] = T.new_x[at][1] = T.new_x[at][2] = 0.f;
+            const double v0 = (x0[0] + min_image_cmp((double)a.xyz[a0 + at] - x0[0], L)) - cen[0];
+            const double v1 = (x0[1] + min_image_cmp((double)a.xyz[N + a0 + at] - x0[1], L)) - cen[1];
+            const double v2 = (x0[2] + min_image_cmp((double)a.xyz[2 * N + a0 + at] - x0[2], L)) - cen[2];
+            // Rodrigues: v cos + (n x v) sin + n (n.v)(1 - cos)
+            const double c0 = n1 * v2 - n2 * v1, c1 = n2 * v0 - n0 * v2, c2 = n0 * v1 - n1 * v0;
+            const double dot = n0 * v0 + n1 * v1 + n2 * v2;
+            const double kk = dot * omc;
+            const double w0 = v0 * ct + c0 * st + n0 * kk;
+            const double w1 = v1 * ct + c1 * st + n1 * kk;
+            const double w2 = v2 * ct + c2 * st + n2 * kk;
+            nx0 = wrap_round(cen[0] + w0 + tau[0], L);
+            nx1 = wrap_round(cen[1] + w1 + tau[1], L);
+            nx2 = wrap_round(cen[2] + w2 + tau[2], L);
         }
+        const float4 o = a.pos4[a0 + at];
+        const double f0 = (double)nx0 * a.invL, f1 = (double)nx1 * a.invL, f2 = (double)nx2 * a.invL;
+        float4 q, ql;
+        q.x = (float)f0;
+        q.y = (float)f1;
+        q.z = (float)f2;
+        q.w = o.w;
+        ql.x = (float)(f0 - (double)q.x);
+        ql.y = (float)(f1 - (double)q.y);
+        ql.z = (float)(f2 - (double)q.z);
+        ql.w = 0.0f;
+        T->old_hi[at] = o;
+        T->old_lo[at] = a.poslo[a0 + at];
+        T->new_hi[at] = q;
+        T->new_lo[at] = ql;
+        T->new_x[at][0] = nx0;
+        T->new_x[at][1] = nx1;
+        T->new_x[at][2] = nx2;
+        float d;
+        d = o.x - ref.x; sx += d - rintf(d);
+        d = o.y - ref.y; sy += d - rintf(d);
+        d = o.z - ref.z; sz += d - rintf(d);
+        d = q.x - ref.x; sx += d - rintf(d);
+        d = q.y - ref.y; sy += d - rintf(d);
+        d = q.z - ref.z; sz += d - rintf(d);
     }
+    // bounding sphere of the old and new atoms (fractional)
     const float inv2n = 1.0f / (float)(2 * na);
     const float cx = ref.x + sx * inv2n, cy = ref.y + sy * inv2n, cz = ref.z + sz * inv2n;
     float r2max = 0.f;
-#pragma unroll
-    for (int at = 0; at < ND_MAX_UNIT_ATOMS; ++at) {
-        if (at < na) {
-            float dx = T.old_hi[at].x - cx, dy = T.old_hi[at].y - cy, dz = T.old_hi[at].z - cz;
-            dx -= rintf(dx); dy -= rintf(dy); dz -= rintf(dz);
-            r2max = fmaxf(r2max, dx * dx + dy * dy + dz * dz);
-            dx = T.new_hi[at].x - cx; dy = T.new_hi[at].y - cy; dz = T.new_hi[at].z - cz;
-            dx -= rintf(dx); dy -= rintf(dy); dz -= rintf(dz);
-            r2max = fmaxf(r2max, dx * dx + dy * dy + dz * dz);
-        }
+    for (int at = 0; at < na; ++at) {
+        const float4 o = T->old_hi[at], q = T->new_hi[at];
+        float dx = o.x - cx, dy = o.y - cy, dz = o.z - cz;
+        dx -= rintf(dx); dy -= rintf(dy); dz -= rintf(dz);
+        r2max = fmaxf(r2max, dx * dx + dy * dy + dz * dz);
+        dx = q.x - cx; dy = q.y - cy; dz = q.z - cz;
+        dx -= rintf(dx); dy -= rintf(dy); dz -= rintf(dz);
+        r2max = fmaxf(r2max, dx * dx + dy * dy + dz * dz);
     }
-    T.cen[0] = cx;
-    T.cen[1] = cy;
-    T.cen[2] = cz;
-    T.rad = sqrtf(r2max) * 1.0001f + 2e-6f;
-    a.trials[k] = T;
+    const float rad = sqrtf(r2max) * 1.0001f + 2e-6f;
+    T->cen[0] = cx;
+    T->cen[1] = cy;
+    T->cen[2] = cz;
+    T->rad = rad;
+    a.spheres[k] = make_float4(cx, cy, cz, rad);
+}
+
+__global__ __launch_bounds__(64) void k_mc_propose(ProposeArgs a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < a.kb) propose_one(a, k);
 }
 
 struct ScanArgs {
@@ -327,234 +319,704 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_mc_scan(ScanArgs a)
     }
 }
 
+// ---------------------------------------------------------------- partial sums
+// full scan: dE0_k = sum over j-blocks of the partial sums (fixed order)
+__global__ void k_mc_reduce(const double *__restrict__ partial, int n_jb, int kcap, int kb, double *__restrict__ dE0,
+                            double *__restrict__ S0)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kb) return;
+    double e = 0.0, s = 0.0;
+    for (int jb = 0; jb < n_jb; ++jb) {
+        e += partial[((size_t)jb * 2 + 0) * kcap + k];
+        s += partial[((size_t)jb * 2 + 1) * kcap + k];
+    }
+    dE0[k] = e;
+    S0[k] = s;
+}
+
 // ---------------------------------------------------------------- corrections
+constexpr int CORR_CAP = 24;  // fixed entry slots per trial (more go to an overflow area)
+constexpr int CORR_TPB = 8;   // trials per correction block (two per wave)
+
 struct CorrArgs {
-    const float *tab;
+    const float *tab;  // table rows read through the caches
     const nd::Trial *trials;
+    const float4 *spheres;
     int M, n_pts, kb;
     float rcf, rcf2_filter;
     double rcf2, tscale;
-    int32_t *corr_n, *corr_off, *pool_m;
-    double *pool_c, *pool_s;
-    long long *pool_fill;
+    int32_t *corr_n, *corr_ptr;  // [K] entries of trial k and where they start
+    float *corr_s;               // [K] sum of |U| over all of trial k's correction terms
+    int32_t *pool_m;             // earlier trial m (increasing within a trial); -1: C_km = 0
+    double *pool_c;              // C_km, the change of k's dE if m was accepted
+    int32_t *ovf_fill;           // overflow entries used in this batch
+    int ovf_base;
 };
 
-__device__ __forceinline__ bool spheres_meet(const nd::Trial *A, const nd::Trial *B, float rcf)
+__device__ __forceinline__ bool spheres_meet(float4 A, float4 B, float rcf)
 {
-    float dx = B->cen[0] - A->cen[0], dy = B->cen[1] - A->cen[1], dz = B->cen[2] - A->cen[2];
+    float dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
     dx -= rintf(dx);
     dy -= rintf(dy);
     dz -= rintf(dz);
-    const float lim = rcf + A->rad + B->rad;
+    const float lim = rcf + A.w + B.w;
     return dx * dx + dy * dy + dz * dz < lim * lim;
 }
 
-// One wave per trial k: entries (m, C_km, S_km) for every earlier trial m of
-// the batch whose unit can interact with k's, in increasing m.
+// One wave: the entries (m, C_km, S_km) of trial k for every earlier trial m
+// of the batch whose bounding sphere comes within r_cut of k's, in increasing
+// m; each C_km = [U(k',m') - U(k,m')] - [U(k',m) - U(k,m)] is evaluated by the
+// whole wave, one lane per (atom of k, atom of m, old/new combination).
 template <int MAXNU>
-__global__ __launch_bounds__(64) void k_mc_corr(CorrArgs a)
+__device__ void corr_trial(const CorrArgs &a, const PairCtx &c, int k, int lane)
 {
-    __shared__ int s_prow[16];
-    const int k = blockIdx.x, lane = threadIdx.x;
-    if (lane < a.M * a.M) s_prow[lane] = nd::pair_index(lane / a.M, lane % a.M, a.M) * a.n_pts;
-    __syncthreads();
-    const nd::Trial *Tk = a.trials + k;
-    // pass 1: count
-    int cnt = 0;
+    const float4 A = a.spheres[k];
+    int n = 0;
     for (int m0 = 0; m0 < k; m0 += 64) {
         const int m = m0 + lane;
-        const bool hit = (m < k) && spheres_meet(Tk, a.trials + m, a.rcf);
-        cnt += __popcll(__ballot(hit));
+        const bool hit = (m < k) && spheres_meet(A, a.spheres[m], a.rcf);
+        n += __popcll(__ballot(hit));
     }
-    int off = 0;
-    if (lane == 0 && cnt > 0) off = (int)atomicAdd(reinterpret_cast<unsigned long long *>(a.pool_fill),
-                                                   (unsigned long long)cnt);
-    off = __shfl(off, 0);
+    int base;
+    if (n <= CORR_CAP) {
+        base = k * CORR_CAP;
+    } else {
+        int o = 0;
+        if (lane == 0) o = atomicAdd(a.ovf_fill, n);
+        base = a.ovf_base + __shfl(o, 0);
+    }
     if (lane == 0) {
-        a.corr_n[k] = cnt;
-        a.corr_off[k] = off;
+        a.corr_n[k] = n;
+        a.corr_ptr[k] = base;
     }
-    if (cnt == 0) return;
-    // pass 2: exact corrections, written in m order
-    PairCtx c{a.tab, s_prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
+    if (n == 0) {
+        if (lane == 0) a.corr_s[k] = 0.0f;
+        return;
+    }
+    const nd::Trial *Tk = a.trials + k;
     const int nak = Tk->na;
-    int base = off;
+    int pos = base;
+    double Sk = 0.0;
     for (int m0 = 0; m0 < k; m0 += 64) {
         const int m = m0 + lane;
-        const bool hit = (m < k) && spheres_meet(Tk, a.trials + m, a.rcf);
-        const unsigned long long bal = __ballot(hit);
-        if (hit) {
-            const nd::Trial *Tm = a.trials + m;
+        const bool hit = (m < k) && spheres_meet(A, a.spheres[m], a.rcf);
+        unsigned long long bal = __ballot(hit);
+        while (bal) {
+            const int hl = __ffsll((long long)bal) - 1;
+            bal &= bal - 1ull;
+            const int mm = m0 + hl;
+            const nd::Trial *Tm = a.trials + mm;
             const int nam = Tm->na;
             double C = 0.0, S = 0.0;
-#pragma unroll
-            for (int x = 0; x < MAXNU; ++x) {
-                if (x < nak) {
-                    const float4 ko = Tk->old_hi[x], kol = Tk->old_lo[x];
-                    const float4 kn = Tk->new_hi[x], knl = Tk->new_lo[x];
-                    const double kox = (double)ko.x + (double)kol.x, koy = (double)ko.y + (double)kol.y,
-                                 koz = (double)ko.z + (double)kol.z;
-                    const double knx = (double)kn.x + (double)knl.x, kny = (double)kn.y + (double)knl.y,
-                                 knz = (double)kn.z + (double)knl.z;
-                    const int rb = __float_as_int(ko.w) * a.M;
-#pragma unroll
-                    for (int y = 0; y < MAXNU; ++y) {
-                        if (y < nam) {
-                            const float4 mo = Tm->old_hi[y], mol = Tm->old_lo[y];
-                            const float4 mn = Tm->new_hi[y], mnl = Tm->new_lo[y];
-                            float u;
-                            if (nd::pair_u(c, kn, knx, kny, knz, rb, mn, mnl, u)) { C += (double)u; S += (double)fabsf(u); }
-                            if (nd::pair_u(c, ko, kox, koy, koz, rb, mn, mnl, u)) { C -= (double)u; S += (double)fabsf(u); }
-                            if (nd::pair_u(c, kn, knx, kny, knz, rb, mo, mol, u)) { C -= (double)u; S += (double)fabsf(u); }
-                            if (nd::pair_u(c, ko, kox, koy, koz, rb, mo, mol, u)) { C += (double)u; S += (double)fabsf(u); }
-                        }
+            for (int t = lane; t < MAXNU * MAXNU * 4; t += 64) {
+                const int x = t / (MAXNU * 4), y = (t >> 2) % MAXNU, sel = t & 3;
+                if (x < nak && y < nam) {
+                    // sel 0: (k', m') +   1: (k, m') -   2: (k', m) -   3: (k, m) +
+                    const float4 p = (sel & 1) ? Tk->old_hi[x] : Tk->new_hi[x];
+                    const float4 pl = (sel & 1) ? Tk->old_lo[x] : Tk->new_lo[x];
+                    const float4 q = (sel & 2) ? Tm->old_hi[y] : Tm->new_hi[y];
+                    const float4 ql = (sel & 2) ? Tm->old_lo[y] : Tm->new_lo[y];
+                    const int rb = __float_as_int(p.w) * c.M;
+                    float u;
+                    if (nd::pair_u(c, p, (double)p.x + (double)pl.x, (double)p.y + (double)pl.y,
+                                   (double)p.z + (double)pl.z, rb, q, ql, u)) {
+                        C += (sel == 0 || sel == 3) ? (double)u : -(double)u;
+                        S += (double)fabsf(u);
                     }
                 }
             }
-            const int rank = __popcll(bal & ((1ull << lane) - 1ull));
-            a.pool_m[base + rank] = m;
-            a.pool_c[base + rank] = C;
-            a.pool_s[base + rank] = S;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                C += __shfl_xor(C, o);
+                S += __shfl_xor(S, o);
+            }
+            if (lane == 0) {
+                a.pool_m[pos] = S > 0.0 ? mm : -1;
+                a.pool_c[pos] = C;
+            }
+            Sk += S;
+            ++pos;
         }
-        base += __popcll(bal);
+    }
+    if (lane == 0) a.corr_s[k] = (float)Sk;
+}
+
+template <int MAXNU>
+__global__ __launch_bounds__(256) void k_mc_corr(CorrArgs a)
+{
+    __shared__ int s_prow[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
+    __syncthreads();
+    const PairCtx c{a.tab, s_prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
+    const int k_begin = blockIdx.x * CORR_TPB, k_end = min(a.kb, k_begin + CORR_TPB);
+    for (int k = k_begin + wave; k < k_end; k += 4) corr_trial<MAXNU>(a, c, k, lane);
+}
+
+// ---------------------------------------------------------------- cell scan
+constexpr int CS_LIST = 512;  // survivors buffered per wave
+
+struct CellScanArgs {
+    const float4 *spos4;
+    const float4 *sposlo;
+    const int32_t *sorted;
+    const int32_t *cstart;
+    const float *tab;
+    const nd::Trial *trials;
+    const float *drift;
+    int M, n_pts, kb, nc;
+    float rcf, rcf2_filter;
+    double rcf2, tscale;
+    double *dE0, *S0;
+};
+
+// Cells [lo, lo + cnt) (mod nc) cover [c - reach, c + reach] along one axis;
+// the whole axis, once, when the interval spans it.
+__device__ __forceinline__ void cell_span(float c, float reach, int nc, int &lo, int &cnt)
+{
+    const int l = (int)floorf((c - reach) * (float)nc);
+    const int h = (int)floorf((c + reach) * (float)nc);
+    if (h - l + 1 >= nc) {
+        lo = 0;
+        cnt = nc;
+    } else {
+        lo = ((l % nc) + nc) % nc;
+        cnt = h - l + 1;
     }
 }
 
+// Trial atoms staged in LDS for the scan: FP64 fractional position and the
+// table-row base of the atom's species, for the old (index 2a) and new
+// (2a + 1) position of atom a.
+struct TrialAtoms {
+    double x[2 * ND_MAX_UNIT_ATOMS], y[2 * ND_MAX_UNIT_ATOMS], z[2 * ND_MAX_UNIT_ATOMS];
+    int rb[2 * ND_MAX_UNIT_ATOMS];
+};
+
+// Exact pair energy from the FP64 fractional displacement d = s_j - s_a
+// (the same arithmetic as pair_u_exact); false beyond r_cut.
+__device__ __forceinline__ bool pair_u_disp(const PairCtx &c, double ex, double ey, double ez, int row, float &u)
+{
+    ex -= rint(ex);
+    ey -= rint(ey);
+    ez -= rint(ez);
+    const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
+    if (!(r2 < c.rcf2)) return false;
+    const double t = sqrt(r2) * c.tscale;
+    int i0 = (int)t;
+    i0 = min(i0, c.n_pts - 2);
+    const float f = (float)(t - (double)i0);
+    const float *tr = c.tab + row;
+    const float u0 = tr[i0];
+    const float u1 = tr[i0 + 1];
+    u = fmaf(f, u1 - u0, u0);
+    return true;
+}
+
+template <int MAXNU>
+__device__ __forceinline__ void cell_flush(const CellScanArgs &a, const PairCtx &c, const TrialAtoms &ta, int ta0,
+                                           int tna, const int *list, int nlist, int lane, double &e, double &s)
+{
+    for (int i = lane; i < nlist; i += 64) {
+        const int sl = list[i];
+        const int id = a.sorted[sl];
+        const float4 q = a.spos4[sl];
+        const float4 ql = a.sposlo[sl];
+        if ((unsigned)(id - ta0) < (unsigned)tna) continue;  // the moved unit itself
+        const double sx = (double)q.x + (double)ql.x, sy = (double)q.y + (double)ql.y,
+                     sz = (double)q.z + (double)ql.z;
+        const int sj = __float_as_int(q.w);
+#pragma unroll
+        for (int at = 0; at < MAXNU; ++at) {
+            if (at < tna) {
+                float u;
+                const int rn = c.prow[ta.rb[2 * at + 1] + sj];
+                if (pair_u_disp(c, sx - ta.x[2 * at + 1], sy - ta.y[2 * at + 1], sz - ta.z[2 * at + 1], rn, u)) {
+                    e += (double)u;
+                    s += (double)fabsf(u);
+                }
+                const int ro = c.prow[ta.rb[2 * at] + sj];
+                if (pair_u_disp(c, sx - ta.x[2 * at], sy - ta.y[2 * at], sz - ta.z[2 * at], ro, u)) {
+                    e -= (double)u;
+                    s += (double)fabsf(u);
+                }
+            }
+        }
+    }
+}
+
+// One block of four waves per trial.  The rows of cells within reach of
+// the trial's bounding sphere (rows along x are contiguous in the sorted
+// arrays, split in two where they wrap) are dealt round-robin to the waves.
+// A wave fetches the slot ranges of up to 64 of its rows at once (one per
+// lane), concatenates them with a prefix sum, and walks the concatenation 64
+// candidates at a time; candidates whose current position is within
+// r_cut + radius of the centre are compacted into LDS and their exact pair
+// terms summed.
+template <int MAXNU>
+__device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k, int *list, double *red,
+                                 TrialAtoms &ta)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const nd::Trial *T = a.trials + k;
+    const int ta0 = T->a0, tna = T->na;
+    if (tid < 2 * tna) {
+        const int at = tid >> 1;
+        const float4 h = (tid & 1) ? T->new_hi[at] : T->old_hi[at];
+        const float4 l = (tid & 1) ? T->new_lo[at] : T->old_lo[at];
+        ta.x[tid] = (double)h.x + (double)l.x;
+        ta.y[tid] = (double)h.y + (double)l.y;
+        ta.z[tid] = (double)h.z + (double)l.z;
+        ta.rb[tid] = __float_as_int(h.w) * c.M;
+    }
+    __syncthreads();
+    const float cx = T->cen[0], cy = T->cen[1], cz = T->cen[2];
+    const float surv = a.rcf + T->rad + 4e-6f;
+    const float surv2 = surv * surv;
+    const float reach = surv + *a.drift + 1e-6f;
+    const int nc = a.nc;
+    int lox, cntx, loy, cnty, loz, cntz;
+    cell_span(cx, reach, nc, lox, cntx);
+    cell_span(cy, reach, nc, loy, cnty);
+    cell_span(cz, reach, nc, loz, cntz);
+    const int xb = lox + cntx;
+    const int runs = xb > nc ? 2 : 1;
+    const int nrows = cntz * cnty;
+    const int my_rows = nrows > wave ? (nrows - wave + 3) / 4 : 0;
+    const int nseg = my_rows * runs;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    double e = 0.0, s = 0.0;
+    int nlist = 0;
+    for (int sp = 0; sp < nseg; sp += 64) {
+        // segment sp + lane: slot range [sbeg, sbeg + len)
+        const int sid = sp + lane;
+        int sbeg = 0, len = 0;
+        if (sid < nseg) {
+            const int r = wave + 4 * (sid / runs);
+            const int run = sid - (sid / runs) * runs;
+            int zz = loz + r / cnty, yy = loy + r % cnty;
+            if (zz >= nc) zz -= nc;
+            if (yy >= nc) yy -= nc;
+            const int rowc = (zz * nc + yy) * nc;
+            const int ra = run == 0 ? lox : 0;
+            const int rb = run == 0 ? min(xb, nc) : xb - nc;
+            sbeg = a.cstart[rowc + ra];
+            len = a.cstart[rowc + rb] - sbeg;
+        }
+        // inclusive prefix of the lengths across the wave
+        int incl = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        const int total = __shfl(incl, 63);
+        const int excl = incl - len;
+        // two candidates per lane per trip, so two loads are in flight
+        for (int c0 = 0; c0 < total; c0 += 128) {
+            int sl[2];
+            bool live[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int cidx = c0 + 64 * h + lane;
+                // segment of candidate cidx: the largest j with excl_j <= cidx
+                // (binary search over lanes; every lane takes part in the shuffles)
+                const int cc = min(cidx, total - 1);
+                int j = 0;
+#pragma unroll
+                for (int step = 32; step > 0; step >>= 1) {
+                    const int cand = j + step;
+                    const int ex = __shfl(excl, cand < 64 ? cand : 63);
+                    if (cand < 64 && ex <= cc) j = cand;
+                }
+                sl[h] = __shfl(sbeg, j) + (cc - __shfl(excl, j));
+                live[h] = cidx < total;
+            }
+            float4 q[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) q[h] = a.spos4[sl[h]];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float dx = q[h].x - cx, dy = q[h].y - cy, dz = q[h].z - cz;
+                dx -= rintf(dx);
+                dy -= rintf(dy);
+                dz -= rintf(dz);
+                const bool hit = live[h] && fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < surv2;
+                const unsigned long long bal = __ballot(hit);
+                if (hit) list[nlist + __popcll(bal & lt)] = sl[h];
+                nlist += __popcll(bal);
+            }
+            if (nlist > CS_LIST - 128) {
+                cell_flush<MAXNU>(a, c, ta, ta0, tna, list, nlist, lane, e, s);
+                nlist = 0;
+            }
+        }
+    }
+    cell_flush<MAXNU>(a, c, ta, ta0, tna, list, nlist, lane, e, s);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        e += __shfl_xor(e, o);
+        s += __shfl_xor(s, o);
+    }
+    if (lane == 0) {
+        red[2 * wave] = e;
+        red[2 * wave + 1] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        a.dE0[k] = (red[0] + red[2]) + (red[4] + red[6]);
+        a.S0[k] = (red[1] + red[3]) + (red[5] + red[7]);
+    }
+}
+
+// Blocks [0, kb): cell scan of trial blockIdx.x.  Then the in-batch
+// corrections (both need only the batch's proposals), then the proposals of
+// the next batch, whose units are disjoint from this batch's.
+template <int MAXNU>
+__global__ __launch_bounds__(256) void k_mc_scan_corr(CellScanArgs a, CorrArgs ca, ProposeArgs next)
+{
+    extern __shared__ float s_tab[];  // [P][n_pts]
+    __shared__ int s_prow[16];
+    __shared__ int s_list[4][CS_LIST];
+    __shared__ double s_red[8];
+    __shared__ TrialAtoms s_ta;
+    const int tid = threadIdx.x;
+    const int n_corr_blocks = (a.kb + CORR_TPB - 1) / CORR_TPB;
+    if ((int)blockIdx.x >= a.kb + n_corr_blocks) {
+        const int k = ((int)blockIdx.x - a.kb - n_corr_blocks) * 256 + tid;
+        if (k < next.kb) propose_one(next, k);
+        return;
+    }
+    if ((int)blockIdx.x >= a.kb) {
+        if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
+        __syncthreads();
+        const PairCtx c{ca.tab, s_prow, ca.M, ca.n_pts, ca.rcf2_filter, ca.rcf2, ca.tscale};
+        const int k_begin = ((int)blockIdx.x - a.kb) * CORR_TPB, k_end = min(ca.kb, k_begin + CORR_TPB);
+        for (int k = k_begin + (tid >> 6); k < k_end; k += 4) corr_trial<MAXNU>(ca, c, k, tid & 63);
+        return;
+    }
+    const int P = a.M * (a.M + 1) / 2;
+    for (int q = tid; q < P * a.n_pts; q += 256) s_tab[q] = a.tab[q];
+    if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
+    __syncthreads();
+    const PairCtx c{s_tab, s_prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
+    scan_cells_block<MAXNU>(a, c, blockIdx.x, s_list[tid >> 6], s_red, s_ta);
+}
+
 // ---------------------------------------------------------------- decide
+constexpr int DEC_THREADS = 512;
+constexpr int DEC_POOL_LDS = 7168;  // correction entries staged in LDS
+constexpr int DEC_UNROLL = 8;
+
 struct DecideArgs {
     float *xyz;
     float4 *pos4;
     float4 *poslo;
     double *E;
     const nd::Trial *trials;
-    const double *partial;
-    const int32_t *corr_n, *corr_off, *pool_m;
-    const double *pool_c, *pool_s;
-    int N, kb, n_jb, kcap;
+    const double *dE0, *S0;
+    const int32_t *corr_n, *corr_ptr, *pool_m;
+    const float *corr_s;
+    const double *pool_c;
+    int32_t *ovf_fill;
+    // cell copies (null when cells are not in use)
+    const int32_t *cell_slot;
+    float4 *spos4, *sposlo;
+    const float4 *sref;
+    float *drift;
+    int N, kb;
     double kT, tie_rel;
-    long long *counters;  // [0] accepted, [1] near ties, [2] pool fill (reset here)
+    long long *counters;  // [0] accepted, [1] near ties
     double *dsum;
     double *tr_dE, *tr_sabs;
     uint8_t *tr_acc;
     int32_t *tr_unit;
 };
 
-__device__ __forceinline__ bool metropolis(double dE, double u, double kT)
+// exclusive prefix sum over the block of one value per thread
+__device__ __forceinline__ int block_exscan(int v, int *s_wave)
 {
-    return (dE <= 0.0) || (u < exp(-dE / kT));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < DEC_THREADS / 64; ++w) {
+            const int t = s_wave[w];
+            s_wave[w] = acc;
+            acc += t;
+        }
+        s_wave[DEC_THREADS / 64] = acc;
+    }
+    __syncthreads();
+    return s_wave[wave] + x - v;
 }
 
-__global__ __launch_bounds__(DECIDE_THREADS) void k_mc_decide(DecideArgs a)
+// Threshold form of the Metropolis test: with u > 0, u < exp(-dE/kT)
+// exactly when dE < -kT ln u (they can differ only by rounding, far inside
+// the near-tie band); u = 0 accepts while exp(-dE/kT) is not 0.
+__device__ __forceinline__ double accept_threshold(double u, double kT)
 {
-    __shared__ double s_dE[KMAX];
-    __shared__ double s_S[KMAX];
+    return u > 0.0 ? -kT * log(u) : 745.13321910194122 * kT;
+}
+
+constexpr int DEC_INTRA = 8;  // intra-chunk correction entries kept in registers per trial
+
+// Decide batch b (acc_k = metropolis(dE0_k + sum_{m<k} acc_m C_km) in trial
+// order) and commit it.  One wave walks the batch in chunks of 64 trials:
+// terms from earlier chunks are final and added in parallel; inside a chunk,
+// lanes whose dependencies are all decided decide together, round by round.
+// When `next.kb` > 0 the next batch is proposed afterwards (used when its
+// units may overlap this batch's).
+__global__ __launch_bounds__(DEC_THREADS) void k_mc_decide(DecideArgs a, ProposeArgs next)
+{
+    __shared__ double s_e[KMAX];
+    __shared__ double s_u[KMAX];  // acceptance threshold -kT ln u
+    __shared__ int s_off[KMAX];
+    __shared__ int s_n[KMAX];
+    __shared__ int s_ptr[KMAX];
     __shared__ unsigned char s_acc[KMAX];
-    __shared__ int s_changed;
-    __shared__ double s_red_d[DECIDE_THREADS / 64];
-    __shared__ long long s_red_a[DECIDE_THREADS / 64], s_red_t[DECIDE_THREADS / 64];
-    const int tid = threadIdx.x;
+    __shared__ int s_pm[DEC_POOL_LDS];
+    __shared__ double s_pc[DEC_POOL_LDS];
+    __shared__ int s_wave[DEC_THREADS / 64 + 1];
+    __shared__ double s_red_d[DEC_THREADS / 64];
+    __shared__ long long s_red_a[DEC_THREADS / 64], s_red_t[DEC_THREADS / 64];
+    __shared__ float s_red_f[DEC_THREADS / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kb = a.kb;
 
-    for (int k = tid; k < kb; k += DECIDE_THREADS) {
-        double e = 0.0, s = 0.0;
-        for (int jb = 0; jb < a.n_jb; ++jb) {
-            e += a.partial[((size_t)jb * 2 + 0) * a.kcap + k];
-            s += a.partial[((size_t)jb * 2 + 1) * a.kcap + k];
-        }
-        s_dE[k] = e;
-        s_S[k] = s;
-        s_acc[k] = metropolis(e, a.trials[k].u_acc, a.kT) ? 1 : 0;
-    }
-    __syncthreads();
-
-    // fixed point of acc_k = metropolis(dE0_k + sum_{m<k} acc_m C_km)
-    for (int it = 0; it <= kb + 1; ++it) {
-        if (tid == 0) s_changed = 0;
-        __syncthreads();
-        for (int k = tid; k < kb; k += DECIDE_THREADS) {
+    if (kb > 0) {
+        // stage per-trial data: each thread owns trials tid, tid + DEC_THREADS, ...
+        int my_n = 0;
+        for (int k = tid; k < kb; k += DEC_THREADS) {
             const int n = a.corr_n[k];
-            if (n == 0) continue;
-            const int off = a.corr_off[k];
-            double e = s_dE[k];
-            for (int i = 0; i < n; ++i)
-                if (s_acc[a.pool_m[off + i]]) e += a.pool_c[off + i];
-            const unsigned char acc = metropolis(e, a.trials[k].u_acc, a.kT) ? 1 : 0;
-            if (acc != s_acc[k]) {
-                s_acc[k] = acc;
-                s_changed = 1;
+            s_n[k] = n;
+            s_ptr[k] = a.corr_ptr[k];
+            s_e[k] = a.dE0[k];
+            s_u[k] = accept_threshold(a.trials[k].u_acc, a.kT);  // -kT ln u
+            s_acc[k] = 0;
+            my_n += n;
+        }
+        const int my_off = block_exscan(my_n, s_wave);
+        int o = my_off;
+        for (int k = tid; k < kb; k += DEC_THREADS) {
+            const int n = s_n[k], ptr = s_ptr[k];
+            s_off[k] = o;
+            for (int i0 = 0; i0 < n && o + i0 < DEC_POOL_LDS; i0 += DEC_UNROLL) {
+                int mm[DEC_UNROLL];
+                double cc[DEC_UNROLL];
+#pragma unroll
+                for (int j = 0; j < DEC_UNROLL; ++j) {
+                    if (i0 + j < n) {
+                        mm[j] = a.pool_m[ptr + i0 + j];
+                        cc[j] = a.pool_c[ptr + i0 + j];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < DEC_UNROLL; ++j) {
+                    if (i0 + j < n && o + i0 + j < DEC_POOL_LDS) {
+                        s_pm[o + i0 + j] = mm[j];
+                        s_pc[o + i0 + j] = cc[j];
+                    }
+                }
             }
+            o += n;
         }
         __syncthreads();
-        const int ch = s_changed;
-        __syncthreads();
-        if (!ch) break;
-    }
+        if (tid == 0) *a.ovf_fill = 0;  // overflow area is free for the next batch
 
-    // finalize: energies, ties, commit, trace
-    double dsum = 0.0;
-    long long nacc = 0, ntie = 0;
-    for (int k = tid; k < kb; k += DECIDE_THREADS) {
-        const int n = a.corr_n[k];
-        const int off = a.corr_off[k];
-        double e = s_dE[k], S = s_S[k];
-        for (int i = 0; i < n; ++i)
-            if (s_acc[a.pool_m[off + i]]) {
-                e += a.pool_c[off + i];
-                S += a.pool_s[off + i];
-            }
-        const nd::Trial &T = a.trials[k];
-        const bool acc = s_acc[k] != 0;
-        const double u = T.u_acc;
-        if (u > 0.0 && fabs(log(u) + e / a.kT) < a.tie_rel * S / a.kT) ++ntie;
-        if (acc) {
-            ++nacc;
-            dsum += e;
-            for (int at = 0; at < T.na; ++at) {
-                const int i = T.a0 + at;
-                a.xyz[i] = T.new_x[at][0];
-                a.xyz[a.N + i] = T.new_x[at][1];
-                a.xyz[2 * a.N + i] = T.new_x[at][2];
-                a.pos4[i] = T.new_hi[at];
-                a.poslo[i] = T.new_lo[at];
+        if (wave == 0) {
+            for (int c0 = 0; c0 < kb; c0 += 64) {
+                const int k = c0 + lane;
+                const bool valid = k < kb;
+                double e = 0.0, thr = 0.0;
+                int n = 0, off = 0, ptr = 0, ni = 0;
+                bool spill = false;
+                unsigned long long dep = 0ull;
+                int im[DEC_INTRA];
+                double ic[DEC_INTRA];
+#pragma unroll
+                for (int j = 0; j < DEC_INTRA; ++j) {
+                    im[j] = 0;
+                    ic[j] = 0.0;
+                }
+                if (valid) {
+                    e = s_e[k];
+                    thr = s_u[k];
+                    n = s_n[k];
+                    off = s_off[k];
+                    ptr = s_ptr[k];
+                }
+                const bool fast = off + n <= DEC_POOL_LDS;
+                // terms from earlier chunks are final; entries inside this
+                // chunk are kept (lane index, C) for the rounds below
+                for (int i0 = 0; i0 < n; i0 += DEC_UNROLL) {
+                    int mm[DEC_UNROLL];
+                    double cc[DEC_UNROLL];
+                    if (fast) {
+                        // all entries in LDS: clamped indices, no branches
+#pragma unroll
+                        for (int j = 0; j < DEC_UNROLL; ++j) {
+                            const int i = off + min(i0 + j, n - 1);
+                            mm[j] = s_pm[i];
+                            cc[j] = s_pc[i];
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < DEC_UNROLL; ++j) {
+                            const int i = min(i0 + j, n - 1);
+                            if (off + i < DEC_POOL_LDS) {
+                                mm[j] = s_pm[off + i];
+                                cc[j] = s_pc[off + i];
+                            } else {
+                                mm[j] = a.pool_m[ptr + i];
+                                cc[j] = a.pool_c[ptr + i];
+                            }
+                        }
+                    }
+                    unsigned char av[DEC_UNROLL];
+#pragma unroll
+                    for (int j = 0; j < DEC_UNROLL; ++j) av[j] = s_acc[min(max(mm[j], 0), KMAX - 1)];
+#pragma unroll
+                    for (int j = 0; j < DEC_UNROLL; ++j) {
+                        const int m = mm[j];
+                        if (i0 + j >= n) continue;
+                        if (m >= 0 && m < c0) {
+                            if (av[j]) e += cc[j];
+                        } else if (m >= c0) {
+                            dep |= 1ull << (m - c0);
+                            if (ni < DEC_INTRA) {
+#pragma unroll
+                                for (int q = 0; q < DEC_INTRA; ++q)
+                                    if (q == ni) {
+                                        im[q] = m - c0;
+                                        ic[q] = cc[j];
+                                    }
+                                ++ni;
+                            } else {
+                                spill = true;
+                            }
+                        }
+                    }
+                }
+                unsigned long long resolved = __ballot(!valid);
+                unsigned long long accmask = 0ull;
+                while (resolved != ~0ull) {
+                    const bool ready = valid && !((resolved >> lane) & 1ull) && ((dep & ~resolved) == 0ull);
+                    bool acc = false;
+                    if (ready) {
+                        if (!spill) {
+#pragma unroll
+                            for (int q = 0; q < DEC_INTRA; ++q)
+                                if (q < ni && ((accmask >> im[q]) & 1ull)) e += ic[q];
+                        } else {
+                            for (int i = 0; i < n; ++i) {
+                                const bool in_lds = off + i < DEC_POOL_LDS;
+                                const int m = in_lds ? s_pm[off + i] : a.pool_m[ptr + i];
+                                if (m >= c0 && ((accmask >> (m - c0)) & 1ull))
+                                    e += in_lds ? s_pc[off + i] : a.pool_c[ptr + i];
+                            }
+                        }
+                        acc = (e <= 0.0) || (e < thr);
+                        s_acc[k] = acc ? 1 : 0;
+                        s_e[k] = e;
+                    }
+                    accmask |= __ballot(ready && acc);
+                    resolved |= __ballot(ready);
+                }
             }
         }
-        if (a.tr_dE) a.tr_dE[k] = e;
-        if (a.tr_sabs) a.tr_sabs[k] = S;
-        if (a.tr_acc) a.tr_acc[k] = acc ? 1 : 0;
-        if (a.tr_unit) a.tr_unit[k] = T.unit;
-    }
-    // block reduction in a fixed order
-    for (int o = 32; o > 0; o >>= 1) {
-        dsum += __shfl_xor(dsum, o);
-        nacc += __shfl_xor(nacc, o);
-        ntie += __shfl_xor(ntie, o);
-    }
-    if ((tid & 63) == 0) {
-        s_red_d[tid >> 6] = dsum;
-        s_red_a[tid >> 6] = nacc;
-        s_red_t[tid >> 6] = ntie;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double d = 0.0;
-        long long na = 0, nt = 0;
-        for (int w = 0; w < DECIDE_THREADS / 64; ++w) {
-            d += s_red_d[w];
-            na += s_red_a[w];
-            nt += s_red_t[w];
+        __syncthreads();
+
+        // commit, trace, counters
+        double dsum = 0.0;
+        long long nacc = 0, ntie = 0;
+        float dmax = 0.0f;
+        for (int k = tid; k < kb; k += DEC_THREADS) {
+            const double e = s_e[k];
+            const double S = a.S0[k] + (double)a.corr_s[k];
+            const bool acc = s_acc[k] != 0;
+            // |ln u + dE/kT| < tie_rel S / kT, i.e. |dE - (-kT ln u)| < tie_rel S
+            if (a.trials[k].u_acc > 0.0 && fabs(e - s_u[k]) < a.tie_rel * S) ++ntie;
+            const nd::Trial &T = a.trials[k];
+            if (acc) {
+                ++nacc;
+                dsum += e;
+                for (int at = 0; at < T.na; ++at) {
+                    const int i = T.a0 + at;
+                    const float4 hi = T.new_hi[at];
+                    const float4 lo = T.new_lo[at];
+                    a.xyz[i] = T.new_x[at][0];
+                    a.xyz[a.N + i] = T.new_x[at][1];
+                    a.xyz[2 * a.N + i] = T.new_x[at][2];
+                    a.pos4[i] = hi;
+                    a.poslo[i] = lo;
+                    if (a.cell_slot) {
+                        const int sl = a.cell_slot[i];
+                        a.spos4[sl] = hi;
+                        a.sposlo[sl] = lo;
+                        const float4 r = a.sref[sl];
+                        float dx = hi.x - r.x, dy = hi.y - r.y, dz = hi.z - r.z;
+                        dx -= rintf(dx);
+                        dy -= rintf(dy);
+                        dz -= rintf(dz);
+                        dmax = fmaxf(dmax, sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1e-6f);
+                    }
+                }
+            }
+            if (a.tr_dE) a.tr_dE[k] = e;
+            if (a.tr_sabs) a.tr_sabs[k] = S;
+            if (a.tr_acc) a.tr_acc[k] = acc ? 1 : 0;
+            if (a.tr_unit) a.tr_unit[k] = T.unit;
         }
-        *a.E += d;
-        *a.dsum += d;
-        a.counters[0] += na;
-        a.counters[1] += nt;
-        a.counters[2] = 0;  // pool is free for the next batch
+        for (int o2 = 32; o2 > 0; o2 >>= 1) {
+            dsum += __shfl_xor(dsum, o2);
+            nacc += __shfl_xor(nacc, o2);
+            ntie += __shfl_xor(ntie, o2);
+            dmax = fmaxf(dmax, __shfl_xor(dmax, o2));
+        }
+        if (lane == 0) {
+            s_red_d[wave] = dsum;
+            s_red_a[wave] = nacc;
+            s_red_t[wave] = ntie;
+            s_red_f[wave] = dmax;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double d = 0.0;
+            long long na = 0, nt = 0;
+            float dm = 0.0f;
+            for (int w = 0; w < DEC_THREADS / 64; ++w) {
+                d += s_red_d[w];
+                na += s_red_a[w];
+                nt += s_red_t[w];
+                dm = fmaxf(dm, s_red_f[w]);
+            }
+            *a.E += d;
+            *a.dsum += d;
+            a.counters[0] += na;
+            a.counters[1] += nt;
+            if (a.drift && dm > 0.0f) atomicMax(reinterpret_cast<unsigned int *>(a.drift), __float_as_uint(dm));
+        }
+        __syncthreads();  // commits are visible to the proposals below
     }
+    for (int k = tid; k < next.kb; k += DEC_THREADS) propose_one(next, k);
 }
 
-__global__ void k_mc_reset(long long *counters, double *dsum)
+__global__ void k_mc_reset(long long *counters, double *dsum, int32_t *ovf_fill)
 {
-    if (threadIdx.x < 3) counters[threadIdx.x] = 0;
-    if (threadIdx.x == 0) *dsum = 0.0;
+    if (threadIdx.x < 2) counters[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        *dsum = 0.0;
+        *ovf_fill = 0;
+    }
 }
 
 int pick_maxnu(int max_na)
@@ -567,48 +1029,59 @@ int pick_maxnu(int max_na)
 }
 
 template <int MAXNU>
-void launch_batch(nd_box *b, const ScanArgs &sa, dim3 sgrid, size_t slds, const CorrArgs &ca)
+void launch_scan_corr(nd_box *b, const CellScanArgs &ca, const CorrArgs &cr, const ProposeArgs &next, size_t slds)
 {
-    {
-        nd::ProfScope ps(b, ND_PROF_MC_SCAN);
-        hipLaunchKernelGGL(k_mc_scan<MAXNU>, sgrid, dim3(SCAN_THREADS), slds, b->stream, sa);
-        ND_HIP(hipGetLastError());
-    }
-    {
-        nd::ProfScope ps(b, ND_PROF_MC_CORR);
-        hipLaunchKernelGGL(k_mc_corr<MAXNU>, dim3(ca.kb), dim3(64), 0, b->stream, ca);
-        ND_HIP(hipGetLastError());
-    }
+    nd::ProfScope ps(b, ND_PROF_MC_SCAN);
+    const int nblk = ca.kb + (ca.kb + CORR_TPB - 1) / CORR_TPB + (next.kb + 255) / 256;
+    hipLaunchKernelGGL(k_mc_scan_corr<MAXNU>, dim3(nblk), dim3(256), slds, b->stream, ca, cr, next);
+    ND_HIP(hipGetLastError());
+}
+
+template <int MAXNU>
+void launch_corr(nd_box *b, const CorrArgs &cr)
+{
+    nd::ProfScope ps(b, ND_PROF_MC_CORR);
+    hipLaunchKernelGGL(k_mc_corr<MAXNU>, dim3((cr.kb + CORR_TPB - 1) / CORR_TPB), dim3(256), 0, b->stream, cr);
+    ND_HIP(hipGetLastError());
 }
 
 void ensure_work(nd_box *b, int K, int n_jb)
 {
     nd::McWork &w = b->mc;
-    size_t pool = (size_t)K * (K - 1) / 2 + 1;
+    size_t pool = (size_t)K * CORR_CAP + (size_t)K * (K - 1) / 2 + 1;
     if (w.trials && w.cap_k >= K && w.cap_jb >= n_jb && w.cap_pool >= pool) return;
     ND_HIP(hipStreamSynchronize(b->stream));
     nd::dfree(w.trials);
+    nd::dfree(w.spheres);
     nd::dfree(w.partial);
+    nd::dfree(w.dE0);
+    nd::dfree(w.S0);
     nd::dfree(w.corr_n);
-    nd::dfree(w.corr_off);
+    nd::dfree(w.corr_ptr);
     nd::dfree(w.pool_m);
     nd::dfree(w.pool_c);
-    nd::dfree(w.pool_s);
-    w.trials = nullptr;
-    w.partial = nullptr;
-    w.corr_n = w.corr_off = w.pool_m = nullptr;
-    w.pool_c = w.pool_s = nullptr;
-    w.cap_k = w.cap_jb = 0;
-    w.cap_pool = 0;
-    w.trials = static_cast<nd::Trial *>(nd::dmalloc(sizeof(nd::Trial) * K));
+    nd::dfree(w.corr_s);
+    long long *counters = w.counters;
+    double *dsum = w.dsum;
+    int32_t *ovf = w.ovf_fill;
+    w = nd::McWork();
+    w.counters = counters;
+    w.dsum = dsum;
+    w.ovf_fill = ovf;
+    // two trial buffers: the batch being decided and the next one
+    w.trials = static_cast<nd::Trial *>(nd::dmalloc(sizeof(nd::Trial) * 2 * K));
+    w.spheres = static_cast<float4 *>(nd::dmalloc(sizeof(float4) * 2 * K));
     w.partial = static_cast<double *>(nd::dmalloc(sizeof(double) * 2 * (size_t)n_jb * K));
+    w.dE0 = static_cast<double *>(nd::dmalloc(sizeof(double) * K));
+    w.S0 = static_cast<double *>(nd::dmalloc(sizeof(double) * K));
     w.corr_n = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * K));
-    w.corr_off = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * K));
+    w.corr_ptr = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * K));
     w.pool_m = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * pool));
     w.pool_c = static_cast<double *>(nd::dmalloc(sizeof(double) * pool));
-    w.pool_s = static_cast<double *>(nd::dmalloc(sizeof(double) * pool));
+    w.corr_s = static_cast<float *>(nd::dmalloc(sizeof(float) * K));
     if (!w.counters) w.counters = static_cast<long long *>(nd::dmalloc(sizeof(long long) * 4));
     if (!w.dsum) w.dsum = static_cast<double *>(nd::dmalloc(sizeof(double)));
+    if (!w.ovf_fill) w.ovf_fill = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t)));
     w.cap_k = K;
     w.cap_jb = n_jb;
     w.cap_pool = pool;
@@ -618,11 +1091,10 @@ void ensure_work(nd_box *b, int K, int n_jb)
 
 namespace nd {
 
-void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n, const nd_mc_trace *trace)
+int mc_batch_size(nd_box *b, const nd_mc_params *p)
 {
-    const int n_jb = (b->N + SCAN_JB - 1) / SCAN_JB;
-    // Batch size: expected number of interacting earlier trials per trial
-    // about 16, at most KMAX and the number of units.
+    // about 12 interacting earlier trials expected for the last trial of a
+    // batch; at most KMAX and half the number of units
     int K;
     if (p->k_batch > 0) {
         K = p->k_batch;
@@ -630,25 +1102,34 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
         const double ext = (b->max_na > 1 ? 1.2 : 0.0) + p->max_disp * 1.8;
         const double reach = b->rc + 2.0 * ext;
         const double f = (4.0 / 3.0) * M_PI * reach * reach * reach / (b->L * b->L * b->L);
-        K = (int)std::min(1e9, 16.0 / std::max(f, 1e-9));
+        K = (int)std::min(1e9, 12.0 / std::max(f, 1e-9));
+        K = std::min(K, std::max(1, b->n_units / 2));
     }
-    K = std::max(1, std::min({K, KMAX, b->n_units}));
+    return std::max(1, std::min({K, KMAX, b->n_units}));
+}
+
+void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n, const nd_mc_trace *trace)
+{
+    const bool full = p->scan == ND_SCAN_FULL;
+    const int n_jb = (b->N + SCAN_JB - 1) / SCAN_JB;
+    const int K = mc_batch_size(b, p);
     ensure_work(b, K, n_jb);
     McWork &w = b->mc;
-    const size_t lds = sizeof(float) * (size_t)b->P * b->n_pts;
-    if (lds > 64 * 1024) fail(ND_E_UNSUPPORTED, "potential table larger than 64 KB");
+    const size_t lds_tab = sizeof(float) * (size_t)b->P * b->n_pts;
+    if (lds_tab > 64 * 1024) fail(ND_E_UNSUPPORTED, "potential table larger than 64 KB");
     const double tie_rel = p->tie_rel > 0.0 ? p->tie_rel : 1e-6;
     const int maxnu = pick_maxnu(b->max_na);
     const int ncu = cu_count(b->device);
-
-    hipLaunchKernelGGL(k_mc_reset, dim3(1), dim3(64), 0, b->stream, w.counters, w.dsum);
-    ND_HIP(hipGetLastError());
-
     const float rcf = (float)(b->rc / b->L);
-    for (int64_t done = 0; done < n;) {
-        const int kb = (int)std::min<int64_t>(K, n - done);
-        const uint64_t t0 = first + (uint64_t)done;
+    const float rcf2_filter = nd::filter_r2(b->rc / b->L);
+    const double rcf2 = (b->rc / b->L) * (b->rc / b->L);
+    const double tscale = b->L / b->h;
 
+    hipLaunchKernelGGL(k_mc_reset, dim3(1), dim3(64), 0, b->stream, w.counters, w.dsum, w.ovf_fill);
+    ND_HIP(hipGetLastError());
+    if (n == 0) return;
+
+    auto proposal_args = [&](int64_t done, int kb, int buf) {
         ProposeArgs pa;
         pa.xyz = b->xyz;
         pa.pos4 = b->pos4;
@@ -661,56 +1142,119 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
         pa.max_disp = p->max_disp;
         pa.max_rot = p->max_rot;
         pa.seed = seed;
-        pa.t0 = t0;
+        pa.t0 = first + (uint64_t)done;
         pa.kb = kb;
-        pa.trials = w.trials;
-        {
-            ProfScope ps(b, ND_PROF_MC_PROPOSE);
-            hipLaunchKernelGGL(k_mc_propose, dim3((kb + 63) / 64), dim3(64), 0, b->stream, pa);
+        pa.trials = w.trials + (size_t)buf * K;
+        pa.spheres = w.spheres + (size_t)buf * K;
+        return pa;
+    };
+
+    int buf = 0;
+    {
+        ProposeArgs pa = proposal_args(0, (int)std::min<int64_t>(K, n), buf);
+        ProfScope ps(b, ND_PROF_MC_PROPOSE);
+        hipLaunchKernelGGL(k_mc_propose, dim3((pa.kb + 63) / 64), dim3(64), 0, b->stream, pa);
+        ND_HIP(hipGetLastError());
+    }
+
+    for (int64_t done = 0; done < n;) {
+        const int kb = (int)std::min<int64_t>(K, n - done);
+        nd::Trial *trials = w.trials + (size_t)buf * K;
+        float4 *spheres = w.spheres + (size_t)buf * K;
+        if (!full && (!b->cells.valid || b->cells.trials_since_build >= b->n_units)) cells_build(b);
+
+        CorrArgs cr;
+        cr.tab = b->tab;
+        cr.trials = trials;
+        cr.spheres = spheres;
+        cr.M = b->M;
+        cr.n_pts = b->n_pts;
+        cr.kb = kb;
+        cr.rcf = rcf + 2e-6f;
+        cr.rcf2_filter = rcf2_filter;
+        cr.rcf2 = rcf2;
+        cr.tscale = tscale;
+        cr.corr_n = w.corr_n;
+        cr.corr_ptr = w.corr_ptr;
+        cr.corr_s = w.corr_s;
+        cr.pool_m = w.pool_m;
+        cr.pool_c = w.pool_c;
+        cr.ovf_fill = w.ovf_fill;
+        cr.ovf_base = K * CORR_CAP;
+
+        const int64_t done_next = done + kb;
+        const int kb_next = (int)std::min<int64_t>(K, n - done_next);
+        ProposeArgs next = proposal_args(done_next, std::max(kb_next, 0), buf ^ 1);
+        // the next batch's units are disjoint from this batch's when 2K <= n_units:
+        // propose it alongside this batch's scan instead of after the commit
+        const bool early_propose = !full && 2 * K <= b->n_units;
+        if (full) {
+            int tg = (int)std::max<long long>(1, std::min<long long>(MAX_TG, ((long long)kb * n_jb) / (2LL * ncu)));
+            ScanArgs sa;
+            sa.pos4 = b->pos4;
+            sa.poslo = b->poslo;
+            sa.tab = b->tab;
+            sa.trials = trials;
+            sa.N = b->N;
+            sa.M = b->M;
+            sa.n_pts = b->n_pts;
+            sa.kb = kb;
+            sa.tg = tg;
+            sa.kcap = w.cap_k;
+            sa.rcf2_filter = rcf2_filter;
+            sa.rcf2 = rcf2;
+            sa.tscale = tscale;
+            sa.partial = w.partial;
+            dim3 sgrid(n_jb, (kb + tg - 1) / tg);
+            {
+                ProfScope ps(b, ND_PROF_MC_SCAN);
+                switch (maxnu) {
+                case 1: hipLaunchKernelGGL(k_mc_scan<1>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
+                case 2: hipLaunchKernelGGL(k_mc_scan<2>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
+                case 3: hipLaunchKernelGGL(k_mc_scan<3>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
+                case 4: hipLaunchKernelGGL(k_mc_scan<4>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
+                default: hipLaunchKernelGGL(k_mc_scan<8>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
+                }
+                ND_HIP(hipGetLastError());
+            }
+            hipLaunchKernelGGL(k_mc_reduce, dim3((kb + 255) / 256), dim3(256), 0, b->stream, w.partial, n_jb,
+                               w.cap_k, kb, w.dE0, w.S0);
             ND_HIP(hipGetLastError());
-        }
-
-        int tg = (int)std::max<long long>(1, std::min<long long>(MAX_TG, ((long long)kb * n_jb) / (2LL * ncu)));
-        ScanArgs sa;
-        sa.pos4 = b->pos4;
-        sa.poslo = b->poslo;
-        sa.tab = b->tab;
-        sa.trials = w.trials;
-        sa.N = b->N;
-        sa.M = b->M;
-        sa.n_pts = b->n_pts;
-        sa.kb = kb;
-        sa.tg = tg;
-        sa.kcap = w.cap_k;
-        sa.rcf2_filter = nd::filter_r2(b->rc / b->L);
-        sa.rcf2 = (b->rc / b->L) * (b->rc / b->L);
-        sa.tscale = b->L / b->h;
-        sa.partial = w.partial;
-        dim3 sgrid(n_jb, (kb + tg - 1) / tg);
-
-        CorrArgs ca;
-        ca.tab = b->tab;
-        ca.trials = w.trials;
-        ca.M = b->M;
-        ca.n_pts = b->n_pts;
-        ca.kb = kb;
-        ca.rcf = rcf + 2e-6f;
-        ca.rcf2_filter = sa.rcf2_filter;
-        ca.rcf2 = sa.rcf2;
-        ca.tscale = sa.tscale;
-        ca.corr_n = w.corr_n;
-        ca.corr_off = w.corr_off;
-        ca.pool_m = w.pool_m;
-        ca.pool_c = w.pool_c;
-        ca.pool_s = w.pool_s;
-        ca.pool_fill = w.counters + 2;
-
-        switch (maxnu) {
-        case 1: launch_batch<1>(b, sa, sgrid, lds, ca); break;
-        case 2: launch_batch<2>(b, sa, sgrid, lds, ca); break;
-        case 3: launch_batch<3>(b, sa, sgrid, lds, ca); break;
-        case 4: launch_batch<4>(b, sa, sgrid, lds, ca); break;
-        default: launch_batch<8>(b, sa, sgrid, lds, ca); break;
+            switch (maxnu) {
+            case 1: launch_corr<1>(b, cr); break;
+            case 2: launch_corr<2>(b, cr); break;
+            case 3: launch_corr<3>(b, cr); break;
+            case 4: launch_corr<4>(b, cr); break;
+            default: launch_corr<8>(b, cr); break;
+            }
+        } else {
+            CellScanArgs ca;
+            ca.spos4 = b->cells.spos4;
+            ca.sposlo = b->cells.sposlo;
+            ca.sorted = b->cells.sorted;
+            ca.cstart = b->cells.start;
+            ca.tab = b->tab;
+            ca.trials = trials;
+            ca.drift = b->cells.drift;
+            ca.M = b->M;
+            ca.n_pts = b->n_pts;
+            ca.kb = kb;
+            ca.nc = b->cells.nc;
+            ca.rcf = rcf;
+            ca.rcf2_filter = rcf2_filter;
+            ca.rcf2 = rcf2;
+            ca.tscale = tscale;
+            ca.dE0 = w.dE0;
+            ca.S0 = w.S0;
+            ProposeArgs nx = next;
+            if (!early_propose) nx.kb = 0;
+            switch (maxnu) {
+            case 1: launch_scan_corr<1>(b, ca, cr, nx, lds_tab); break;
+            case 2: launch_scan_corr<2>(b, ca, cr, nx, lds_tab); break;
+            case 3: launch_scan_corr<3>(b, ca, cr, nx, lds_tab); break;
+            case 4: launch_scan_corr<4>(b, ca, cr, nx, lds_tab); break;
+            default: launch_scan_corr<8>(b, ca, cr, nx, lds_tab); break;
+            }
         }
 
         DecideArgs da;
@@ -718,17 +1262,23 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
         da.pos4 = b->pos4;
         da.poslo = b->poslo;
         da.E = b->E;
-        da.trials = w.trials;
-        da.partial = w.partial;
+        da.trials = trials;
+        da.dE0 = w.dE0;
+        da.S0 = w.S0;
         da.corr_n = w.corr_n;
-        da.corr_off = w.corr_off;
+        da.corr_ptr = w.corr_ptr;
         da.pool_m = w.pool_m;
         da.pool_c = w.pool_c;
-        da.pool_s = w.pool_s;
+        da.corr_s = w.corr_s;
+        da.ovf_fill = w.ovf_fill;
+        const bool cells_live = b->cells.valid;
+        da.cell_slot = cells_live ? b->cells.slot : nullptr;
+        da.spos4 = cells_live ? b->cells.spos4 : nullptr;
+        da.sposlo = cells_live ? b->cells.sposlo : nullptr;
+        da.sref = cells_live ? b->cells.sref : nullptr;
+        da.drift = cells_live ? b->cells.drift : nullptr;
         da.N = b->N;
         da.kb = kb;
-        da.n_jb = n_jb;
-        da.kcap = w.cap_k;
         da.kT = p->kT;
         da.tie_rel = tie_rel;
         da.counters = w.counters;
@@ -737,12 +1287,16 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
         da.tr_sabs = trace && trace->sabs ? trace->sabs + done : nullptr;
         da.tr_acc = trace && trace->accepted ? trace->accepted + done : nullptr;
         da.tr_unit = trace && trace->unit ? trace->unit + done : nullptr;
+        ProposeArgs late = next;
+        if (early_propose) late.kb = 0;
         {
             ProfScope ps(b, ND_PROF_MC_DECIDE);
-            hipLaunchKernelGGL(k_mc_decide, dim3(1), dim3(DECIDE_THREADS), 0, b->stream, da);
+            hipLaunchKernelGGL(k_mc_decide, dim3(1), dim3(DEC_THREADS), 0, b->stream, da, late);
             ND_HIP(hipGetLastError());
         }
-        done += kb;
+        if (b->cells.valid) b->cells.trials_since_build += kb;
+        done = done_next;
+        buf ^= 1;
     }
 }
 

@@ -220,12 +220,17 @@ static void free_box(nd_box *b)
     nd::dfree(b->mc.trials);
     nd::dfree(b->mc.partial);
     nd::dfree(b->mc.corr_n);
-    nd::dfree(b->mc.corr_off);
+    nd::dfree(b->mc.corr_ptr);
+    nd::dfree(b->mc.ovf_fill);
     nd::dfree(b->mc.counters);
     nd::dfree(b->mc.dsum);
     nd::dfree(b->mc.pool_m);
     nd::dfree(b->mc.pool_c);
-    nd::dfree(b->mc.pool_s);
+    nd::dfree(b->mc.corr_s);
+    nd::dfree(b->mc.spheres);
+    nd::dfree(b->mc.dE0);
+    nd::dfree(b->mc.S0);
+    nd::cells_free(b);
     nd::dfree(b->ws);
     delete[] b->h_uoff;
     delete[] b->h_species;
@@ -375,6 +380,7 @@ nd_status nd_box_set_coords(nd_box *b, const float *xyz, int32_t where, int32_t 
             nd::launch_pos4_from_xyz(b);
         }
         if (!keep_energy) b->energy_valid = false;
+        b->cells.valid = false;
     });
 }
 
@@ -465,6 +471,7 @@ nd_status nd_mc_sweep(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t 
         require(p->tie_rel >= 0.0 && std::isfinite(p->tie_rel), ND_E_INVALID, "tie_rel must be >= 0");
         require(p->k_batch >= 0, ND_E_INVALID, "k_batch must be >= 0");
         require(p->order == ND_ORDER_SEQ || p->order == ND_ORDER_RANDOM, ND_E_INVALID, "unknown order");
+        require(p->scan == ND_SCAN_CELLS || p->scan == ND_SCAN_FULL, ND_E_INVALID, "unknown scan mode");
         if (p->order == ND_ORDER_RANDOM) nd::fail(ND_E_UNSUPPORTED, "ND_ORDER_RANDOM is not implemented");
         require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
         DeviceGuard g(b->device);

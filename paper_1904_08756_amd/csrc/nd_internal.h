@@ -51,15 +51,36 @@ struct McWork {
     int cap_k = 0;
     int cap_jb = 0;
     size_t cap_pool = 0;
-    Trial *trials = nullptr;      // [cap_k]
-    double *partial = nullptr;    // [cap_jb][2][cap_k]  (dE, sum |U|) per j-block
+    Trial *trials = nullptr;      // [2][cap_k] batch being decided, next batch
+    float4 *spheres = nullptr;    // [2][cap_k] bounding sphere of each trial (fractional)
+    double *partial = nullptr;    // [cap_jb][2][cap_k]  (dE, sum |U|) per j-block (full scan)
+    double *dE0 = nullptr;        // [cap_k] energy change against the batch-start configuration
+    double *S0 = nullptr;         // [cap_k] sum of |U| of those pair terms
     int32_t *corr_n = nullptr;    // [cap_k] correction entries of trial k
-    int32_t *corr_off = nullptr;  // [cap_k] offset of trial k's entries in the pool
-    int32_t *pool_m = nullptr;    // [cap_pool] earlier trial m of each entry
+    int32_t *corr_ptr = nullptr;  // [cap_k] first entry of trial k in the pool
+    float *corr_s = nullptr;      // [cap_k] sum |U| over trial k's correction terms
+    int32_t *pool_m = nullptr;    // [cap_pool] earlier trial m of each entry (increasing), -1 if C = 0
     double *pool_c = nullptr;     // [cap_pool] energy correction if m was accepted
-    double *pool_s = nullptr;     // [cap_pool] sum |U| of the correction terms
-    long long *counters = nullptr;   // [0] accepted, [1] near ties, [2] pool fill
+    int32_t *ovf_fill = nullptr;  // entries used in the pool's overflow area
+    long long *counters = nullptr;   // [0] accepted, [1] near ties
     double *dsum = nullptr;       // accepted dE sum
+};
+
+// Atoms sorted into spatial cells (see k_cells.hip).
+struct Cells {
+    int nc = 0, ncell = 0, cap_n = 0;
+    int32_t *start = nullptr;     // [ncell + 1] first sorted slot of each cell
+    int32_t *sorted = nullptr;    // [N] slot -> atom
+    int32_t *slot = nullptr;      // [N] atom -> slot
+    float4 *spos4 = nullptr;      // [N] current hi + species, sorted order
+    float4 *sposlo = nullptr;     // [N] current lo, sorted order
+    float4 *sref = nullptr;       // [N] hi at the last rebuild
+    uint64_t *keys_in = nullptr, *keys_out = nullptr;
+    void *sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
+    float *drift = nullptr;       // device: max distance moved since the rebuild (fractional)
+    bool valid = false;
+    long long trials_since_build = 0;
 };
 
 }  // namespace nd
@@ -89,6 +110,7 @@ struct nd_box {
     double *E = nullptr;         // device [1]
     bool energy_valid = false;
     nd::McWork mc;
+    nd::Cells cells;
     // reusable device workspace for per-block partial results
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -122,6 +144,8 @@ void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, c
 void launch_forces(nd_box *b, double *d_grad, double *d_E);
 void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n,
             const nd_mc_trace *trace);
+void cells_build(nd_box *b);
+void cells_free(nd_box *b);
 
 // device memory helpers
 void *dmalloc(size_t bytes);

@@ -154,11 +154,11 @@ def test_total_energy_matches_oracle(nd, orc, cfg):
 
 
 # ------------------------------------------------------------------ Metropolis
-def _mc_parity(nd, orc, box, T, params, seed, first, n, k_batch=0):
+def _mc_parity(nd, orc, box, T, params, seed, first, n, k_batch=0, scan=0):
     g = _gbox(nd, box, T)
     E0 = g.total_energy()
-    p = nd.MCParams(params["kT"], params["max_disp"], params["max_rot"], k_batch=k_batch)
-    say(f"mc parity: {box.name} trials {first}..{first + n} K={k_batch}")
+    p = nd.MCParams(params["kT"], params["max_disp"], params["max_rot"], k_batch=k_batch, scan=scan)
+    say(f"mc parity: {box.name} trials {first}..{first + n} K={k_batch} scan={scan}")
     res = g.mc_sweep(p, seed, first, n, trace=True)
     tr = {k: v.cpu().numpy() for k, v in res["trace"].items()}
     xyz = box.xyz.copy()
@@ -186,10 +186,10 @@ def _mc_parity(nd, orc, box, T, params, seed, first, n, k_batch=0):
     return res, o
 
 
-@pytest.mark.parametrize("k_batch", [0, 1, 5, 64, 300])
-def test_mc_c1_matches_sequential_chain(nd, orc, k_batch):
+@pytest.mark.parametrize("k_batch,scan", [(0, 0), (1, 0), (5, 0), (64, 0), (300, 0), (0, 1), (77, 1)])
+def test_mc_c1_matches_sequential_chain(nd, orc, k_batch, scan):
     box, T, mc = syn.config_c1()
-    res, o = _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, mc["n_trials"], k_batch)
+    res, o = _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, mc["n_trials"], k_batch, scan)
     assert 0.05 < res["accepted"] / res["trials"] < 0.95
 
 
@@ -213,9 +213,10 @@ def test_mc_zero_potential_accepts_all(nd):
     assert np.all(res["trace"]["dE"].cpu().numpy() == 0.0)
 
 
-def test_mc_c2_sample_matches(nd, orc):
+@pytest.mark.parametrize("scan", [0, 1])
+def test_mc_c2_sample_matches(nd, orc, scan):
     box, T, mc = syn.config_c2()
-    _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, 3000)
+    _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, 3000, scan=scan)
 
 
 def test_mc_c2_later_trials_match(nd, orc):
@@ -224,9 +225,37 @@ def test_mc_c2_later_trials_match(nd, orc):
     _mc_parity(nd, orc, box, T, mc, mc["seed"], 1_000_003, 1500)
 
 
-def test_mc_c3_sample_matches(nd, orc):
+@pytest.mark.parametrize("scan", [0, 1])
+def test_mc_c3_sample_matches(nd, orc, scan):
     box, T, mc = syn.config_c3()
-    _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, 4000)
+    _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, 4000, scan=scan)
+
+
+def test_mc_cells_rebuild_across_sweeps(nd, orc):
+    """A run longer than one sweep rebuilds the cells between batches; small
+    box, many sweeps: the chain still matches the oracle trial by trial."""
+    box = syn.water_box(120, 16.0, 31, "rebuild")
+    T = syn.water_tables(r_cut=7.0)
+    params = dict(kT=syn.kT_at(298.0), max_disp=0.3, max_rot=math.radians(10.0))
+    _mc_parity(nd, orc, box, T, params, 5, 0, 120 * 6, k_batch=50)
+
+
+def test_mc_scan_modes_agree(nd):
+    box, T, mc = syn.config_c2()
+    p_c = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"], scan=0)
+    p_f = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"], scan=1)
+    g1 = _gbox(nd, box, T)
+    g2 = _gbox(nd, box, T)
+    r1 = g1.mc_sweep(p_c, 9, 0, 40000, trace=True)
+    r2 = g2.mc_sweep(p_f, 9, 0, 40000, trace=True)
+    d1 = r1["trace"]["dE"].cpu().numpy()
+    d2 = r2["trace"]["dE"].cpu().numpy()
+    s1 = r1["trace"]["sabs"].cpu().numpy()
+    a1 = r1["trace"]["accepted"].cpu().numpy()
+    a2 = r2["trace"]["accepted"].cpu().numpy()
+    # identical decisions (a differing near tie would show up here first)
+    assert np.array_equal(a1, a2)
+    assert np.all(np.abs(d1 - d2) <= 1e-6 * s1)
 
 
 def test_mc_rejects_missing_tables(nd):
