@@ -249,6 +249,60 @@ nd_status nd_hist_broad_backward(nd_box *box, double dr, int32_t nbins, double s
  * energy E (host double, may be NULL). */
 nd_status nd_forces(nd_box *box, double *dEdx, double *E, int32_t where);
 
+/* ---- Batched form: several independent boxes in one graph launch.
+ * The boxes may differ in size, box length, tables and Eq. 1 weighting
+ * (e.g. isotope substitutions; Sec. "Neutron scattering" and Eq. 1).  One
+ * run does, for every box, `sweeps` Metropolis sweeps (n_units trials per
+ * sweep, as nd_mc_sweep with the cell scan), then the pair histogram, g(r)
+ * and S(Q) as nd_pair_histogram, nd_gr_normalize and nd_sq_transform.  Each
+ * launch of the run covers every box at once (one grid row per box; the
+ * histogram is one persistent launch over the tile pairs of all boxes).
+ * The launches are captured into a HIP graph on the first run and the graph
+ * is replayed by later runs with the same launch structure (same boxes,
+ * sweeps, batch sizes, bin counts and output arrays); other arguments
+ * (seeds, trial counters, weights) may change between replays.  Every run
+ * rebuilds the boxes' cell lists first.
+ *
+ * The batch keeps pointers to the boxes: destroy the batch before any of
+ * its boxes, and do not run nd_* calls on its boxes while a run is in
+ * flight except on the boxes' own streams (the run waits for work already
+ * queued on each box's stream and work queued on them afterwards waits for
+ * the run). */
+typedef struct nd_batch nd_batch;
+
+typedef struct nd_batch_plan {
+    int32_t sweeps;               /* Metropolis sweeps per box, 0 = none          */
+    const nd_mc_params *mc;       /* host [n]: scan must be ND_SCAN_CELLS         */
+    const uint64_t *seed;         /* host [n]                                     */
+    const uint64_t *first_trial;  /* host [n]: counter of each box's first trial  */
+    double dr;                    /* histogram bin width (Angstrom)               */
+    const int32_t *nbins;         /* host [n]: bins of box i, nbins*dr < L_i/2    */
+    const double *w;              /* host [n][P]: Eq. 1 weights of box i          */
+    const double *self_term;      /* host [n]: sum_a c_a b_a^2 of box i           */
+    const double *Q;              /* device [nQ], shared by all boxes             */
+    int32_t nQ;
+    uint64_t *const *counts;      /* host [n] of device [P][nbins_i]; NULL: no histogram */
+    double *const *g;             /* host [n] of device [P][nbins_i]; NULL: no g or S    */
+    double *const *S;             /* host [n] of device [nQ]; NULL or nQ = 0: no S       */
+} nd_batch_plan;
+
+/* Groups n >= 1 distinct boxes on one device with the same number of
+ * species.  Errors: ND_E_INVALID, ND_E_HIP. */
+nd_status nd_batch_create(nd_box *const *boxes, int32_t n, nd_batch **out);
+
+/* NULL-safe; waits for the batch's work to finish. */
+nd_status nd_batch_destroy(nd_batch *batch);
+
+/* One run of the plan (see above), asynchronous on the batch's own stream.
+ * stats: host [n] or NULL; when given, the call waits for the run and fills
+ * the counters of each box's sweeps.  Errors: ND_E_INVALID, ND_E_RANGE,
+ * ND_E_STATE (a box without tables), ND_E_UNSUPPORTED (ND_SCAN_FULL,
+ * ND_ORDER_RANDOM), ND_E_OOM, ND_E_HIP. */
+nd_status nd_batch_run(nd_batch *batch, const nd_batch_plan *plan, nd_mc_stats *stats);
+
+/* Number of graph captures and of graph launches of the batch so far. */
+nd_status nd_batch_info(const nd_batch *batch, int64_t *captures, int64_t *launches);
+
 /* Per-kernel timing with HIP events on the box's stream, for measurement.
  * Kernel ids for nd_box_profile. */
 #define ND_PROF_MC_SCAN 0       /* pair-sum scan of a batch of trials        */

@@ -20,7 +20,7 @@ import numpy as np
 __all__ = [
     "lib", "build", "Box", "MCParams", "pair_histogram", "gr_normalize", "sq_transform",
     "sq_adjoint", "hist_broad", "hist_broad_backward", "forces", "Chi2Fn", "EnergyFn",
-    "chi2", "gr_normalize_f64", "pair_counts_total", "eq1_weights",
+    "chi2", "gr_normalize_f64", "pair_counts_total", "eq1_weights", "Batch",
     "ND_HOST", "ND_DEVICE", "NeudaError",
 ]
 
@@ -67,6 +67,13 @@ class nd_mc_trace(C.Structure):
                 ("unit", C.c_void_p)]
 
 
+class nd_batch_plan(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("mc", C.c_void_p), ("seed", C.c_void_p),
+                ("first_trial", C.c_void_p), ("dr", C.c_double), ("nbins", C.c_void_p),
+                ("w", C.c_void_p), ("self_term", C.c_void_p), ("Q", C.c_void_p), ("nQ", C.c_int32),
+                ("counts", C.c_void_p), ("g", C.c_void_p), ("S", C.c_void_p)]
+
+
 EXPORTS = {
     "nd_abi_version": (C.c_int32, []),
     "nd_last_error": (C.c_char_p, []),
@@ -103,6 +110,10 @@ EXPORTS = {
     "nd_eq1_weights": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "nd_chi2": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                             C.c_void_p]),
+    "nd_batch_create": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "nd_batch_destroy": (C.c_int32, [C.c_void_p]),
+    "nd_batch_run": (C.c_int32, [C.c_void_p, C.POINTER(nd_batch_plan), C.c_void_p]),
+    "nd_batch_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
 }
 
 _lib = None
@@ -304,6 +315,88 @@ class Box:
         if tr_t is not None:
             out["trace"] = tr_t
         return out
+
+
+class Batch:
+    """Several boxes run as one HIP graph (nd_batch_*): Metropolis sweeps,
+    pair histograms, g(r) and S(Q) of every box in shared launches."""
+
+    def __init__(self, boxes):
+        self.boxes = list(boxes)
+        n = len(self.boxes)
+        for b in self.boxes:
+            b._sync_stream()
+        arr = (C.c_void_p * n)(*[b.handle.value for b in self.boxes])
+        h = C.c_void_p()
+        _check(lib().nd_batch_create(arr, n, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().nd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        """(graph captures, graph launches) so far."""
+        c = C.c_int64()
+        n = C.c_int64()
+        _check(lib().nd_batch_info(self._h, C.byref(c), C.byref(n)))
+        return c.value, n.value
+
+    def run(self, sweeps, params, seeds, first_trials, dr=None, nbins=None, w=None, self_term=None,
+            Q=None, counts=None, g=None, S=None, stats=False):
+        """One run.  params/seeds/first_trials/nbins/self_term: one per box; w: [n, P];
+        counts/g/S: lists of device tensors ([P, nbins_i] int64, [P, nbins_i] float64,
+        [nQ] float64), or None to skip that stage."""
+        torch = _torch()
+        n = len(self.boxes)
+        for b in self.boxes:
+            b._sync_stream()
+        keep = []
+        pl = nd_batch_plan()
+        pl.sweeps = int(sweeps)
+        if sweeps > 0:
+            mcs = (nd_mc_params * n)(*[p.c() for p in params])
+            sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+            ft = np.ascontiguousarray(np.asarray(first_trials, dtype=np.uint64))
+            keep += [mcs, sd, ft]
+            pl.mc = C.cast(mcs, C.c_void_p)
+            pl.seed = sd.ctypes.data
+            pl.first_trial = ft.ctypes.data
+        if counts is not None:
+            nb = np.ascontiguousarray(np.asarray(nbins, dtype=np.int32))
+            cp = (C.c_void_p * n)(*[c.data_ptr() for c in counts])
+            keep += [nb, cp]
+            pl.dr = float(dr)
+            pl.nbins = nb.ctypes.data
+            pl.counts = C.cast(cp, C.c_void_p)
+            if g is not None:
+                gp = (C.c_void_p * n)(*[x.data_ptr() for x in g])
+                keep.append(gp)
+                pl.g = C.cast(gp, C.c_void_p)
+                if S is not None and Q is not None:
+                    Qd = Q.to(dtype=torch.float64).contiguous()
+                    ww = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+                    st = np.ascontiguousarray(np.asarray(self_term, dtype=np.float64))
+                    sp = (C.c_void_p * n)(*[x.data_ptr() for x in S])
+                    keep += [Qd, ww, st, sp]
+                    pl.Q = Qd.data_ptr()
+                    pl.nQ = int(Qd.shape[0])
+                    pl.w = ww.ctypes.data
+                    pl.self_term = st.ctypes.data
+                    pl.S = C.cast(sp, C.c_void_p)
+        sts = (nd_mc_stats * n)() if stats else None
+        _check(lib().nd_batch_run(self._h, C.byref(pl), C.cast(sts, C.c_void_p) if sts is not None else None))
+        if sts is None:
+            return None
+        return [dict(trials=x.trials, accepted=x.accepted, near_ties=x.near_ties, E_total=x.E_total,
+                     dE_sum=x.dE_sum) for x in sts]
 
 
 def pair_histogram(box: Box, dr: float, nbins: int, out=None):

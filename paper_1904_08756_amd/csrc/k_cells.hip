@@ -1,57 +1,136 @@
 // Spatial cells for the Metropolis scan: atoms sorted by the cell of their
 // position (x fastest), so every row of cells along x is one contiguous range
-// of the sorted arrays.  The sort is a stable radix sort of the keys
-// (cell << abits | atom), so the order inside a cell is the atom order and
-// every rebuild is deterministic.  Between rebuilds atoms keep their sorted
-// slot while they move; the distance any atom has moved from its position at
-// the last rebuild ("drift", fractional units) is tracked by the commit step
-// and widens the cell search so no neighbour is missed.
+// of the sorted arrays.  Inside a cell the atoms are in increasing atom
+// order, so every rebuild is deterministic.  Between rebuilds atoms keep
+// their sorted slot while they move; the distance any atom has moved from
+// its position at the last rebuild ("drift", fractional units) is tracked by
+// the commit step and widens the cell search so no neighbour is missed.
+//
+// The build is a counting sort in four launches with no library calls, no
+// memset and no host synchronisation, so it can be captured in a graph:
+// count (atomic arrival rank per cell), scan (cell starts; the counters are
+// cleared for the next build), scatter, and a per-cell pass that puts each
+// cell's atoms in atom order and gathers the sorted copies.  Every kernel
+// takes an array of box descriptors indexed by blockIdx.y, so one launch
+// rebuilds the cells of several boxes.
 #include "nd_internal.h"
-
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cmath>
 
 namespace {
 
-__global__ void k_cell_keys(const float4 *__restrict__ pos4, int N, int nc, int abits, uint64_t *__restrict__ keys)
+constexpr int CB_THREADS = 256;
+constexpr int CB_SCAN_THREADS = 1024;
+// A cell holding more atoms than this keeps its atomic arrival order (still
+// a valid cell list; only the summation order, hence the last bits of the
+// energy sums, then depends on scheduling).  Bounds the per-cell sort.
+constexpr int CB_SORT_MAX = 512;
+
+__device__ __forceinline__ int cell_of(float4 p, int nc)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const float4 p = pos4[i];
     const int cx = min(max((int)(p.x * (float)nc), 0), nc - 1);
     const int cy = min(max((int)(p.y * (float)nc), 0), nc - 1);
     const int cz = min(max((int)(p.z * (float)nc), 0), nc - 1);
-    const uint64_t c = (uint64_t)((cz * nc + cy) * nc + cx);
-    keys[i] = (c << abits) | (uint64_t)i;
+    return (cz * nc + cy) * nc + cx;
 }
 
-__global__ void k_cell_gather(const uint64_t *__restrict__ keys, int N, int abits, int ncell,
-                              const float4 *__restrict__ pos4, const float4 *__restrict__ poslo,
-                              int32_t *__restrict__ sorted, int32_t *__restrict__ slot, float4 *__restrict__ spos4,
-                              float4 *__restrict__ sposlo, float4 *__restrict__ sref, int32_t *__restrict__ start)
+__global__ __launch_bounds__(CB_THREADS) void k_cb_count(const nd::CellBuildArgs *__restrict__ args)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= N) return;
-    const uint64_t key = keys[s];
-    const int atom = (int)(key & ((1ull << abits) - 1ull));
-    const int c = (int)(key >> abits);
-    sorted[s] = atom;
-    slot[atom] = s;
-    const float4 p = pos4[atom];
-    spos4[s] = p;
-    sposlo[s] = poslo[atom];
-    sref[s] = p;
-    // start[cc] = first slot of cell cc; cells between the previous atom's
-    // cell and this one are empty and start here
-    const int cprev = s > 0 ? (int)(keys[s - 1] >> abits) : -1;
-    for (int cc = cprev + 1; cc <= c; ++cc) start[cc] = s;
-    if (s == N - 1)
-        for (int cc = c + 1; cc <= ncell; ++cc) start[cc] = N;
+    const nd::CellBuildArgs &A = args[blockIdx.y];
+    const int i = blockIdx.x * CB_THREADS + threadIdx.x;
+    if (i >= A.N) return;
+    const int c = cell_of(A.pos4[i], A.nc);
+    A.cellof[i] = c;
+    A.rank[i] = atomicAdd(&A.count[c], 1);
 }
 
-__global__ void k_zero_f32(float *p) { *p = 0.0f; }
+// One block per box: start[c] = sum of count[0..c), start[ncell] = N; the
+// counters are cleared behind the scan and the drift is reset.
+__global__ __launch_bounds__(CB_SCAN_THREADS) void k_cb_scan(const nd::CellBuildArgs *__restrict__ args)
+{
+    __shared__ int s_w[CB_SCAN_THREADS / 64];
+    __shared__ int s_total;
+    const nd::CellBuildArgs &A = args[blockIdx.y];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int carry = 0;
+    for (int base = 0; base < A.ncell; base += CB_SCAN_THREADS) {
+        const int j = base + tid;
+        const int v = j < A.ncell ? A.count[j] : 0;
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_w[wave] = x;
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int w = 0; w < CB_SCAN_THREADS / 64; ++w) {
+                const int t = s_w[w];
+                s_w[w] = acc;
+                acc += t;
+            }
+            s_total = acc;
+        }
+        __syncthreads();
+        if (j < A.ncell) {
+            A.start[j] = carry + s_w[wave] + x - v;
+            A.count[j] = 0;
+        }
+        carry += s_total;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        A.start[A.ncell] = carry;
+        *A.drift = 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(CB_THREADS) void k_cb_scatter(const nd::CellBuildArgs *__restrict__ args)
+{
+    const nd::CellBuildArgs &A = args[blockIdx.y];
+    const int i = blockIdx.x * CB_THREADS + threadIdx.x;
+    if (i >= A.N) return;
+    A.sorted[A.start[A.cellof[i]] + A.rank[i]] = i;
+}
+
+// One thread per cell: insertion sort of the cell's atoms (a few per cell),
+// then the inverse map and the sorted copies of the positions.
+__global__ __launch_bounds__(CB_THREADS) void k_cb_finish(const nd::CellBuildArgs *__restrict__ args)
+{
+    const nd::CellBuildArgs &A = args[blockIdx.y];
+    const int c = blockIdx.x * CB_THREADS + threadIdx.x;
+    if (c >= A.ncell) return;
+    const int b = A.start[c], e = A.start[c + 1];
+    int32_t *s = A.sorted;
+    if (e - b <= CB_SORT_MAX) {
+        for (int x = b + 1; x < e; ++x) {
+            const int v = s[x];
+            int y = x - 1;
+            while (y >= b && s[y] > v) {
+                s[y + 1] = s[y];
+                --y;
+            }
+            s[y + 1] = v;
+        }
+    }
+    for (int x = b; x < e; ++x) {
+        const int atom = s[x];
+        A.slot[atom] = x;
+        const float4 p = A.pos4[atom];
+        A.spos4[x] = p;
+        A.sposlo[x] = A.poslo[atom];
+        A.sref[x] = p;
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int n, int v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
 
 }  // namespace
 
@@ -66,59 +145,75 @@ void cells_free(nd_box *b)
     dfree(c.spos4);
     dfree(c.sposlo);
     dfree(c.sref);
-    dfree(c.keys_in);
-    dfree(c.keys_out);
-    dfree(c.sort_tmp);
+    dfree(c.cellof);
+    dfree(c.rank);
+    dfree(c.count);
     dfree(c.drift);
+    dfree(c.d_args);
     c = Cells();
+}
+
+// Cell grid of about four atoms per cell, at least one and at most 128 cells
+// per axis.
+static int cells_per_axis(const nd_box *b)
+{
+    const double rho = (double)b->N / (b->L * b->L * b->L);
+    const double edge = std::cbrt(4.0 / rho);
+    const int nc = (int)std::floor(b->L / edge);
+    return std::max(1, std::min(nc, 128));
+}
+
+void cells_ensure(nd_box *b)
+{
+    Cells &c = b->cells;
+    const int N = b->N;
+    const int nc = cells_per_axis(b);
+    const int ncell = nc * nc * nc;
+    if (c.d_args && c.cap_n >= N && c.ncell == ncell) return;
+    ND_HIP(hipStreamSynchronize(b->stream));
+    cells_free(b);
+    c.start = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * (ncell + 1)));
+    c.sorted = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * N));
+    c.slot = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * N));
+    c.spos4 = static_cast<float4 *>(dmalloc(sizeof(float4) * N));
+    c.sposlo = static_cast<float4 *>(dmalloc(sizeof(float4) * N));
+    c.sref = static_cast<float4 *>(dmalloc(sizeof(float4) * N));
+    c.cellof = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * N));
+    c.rank = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * N));
+    c.count = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * ncell));
+    c.drift = static_cast<float *>(dmalloc(sizeof(float)));
+    c.d_args = static_cast<CellBuildArgs *>(dmalloc(sizeof(CellBuildArgs)));
+    c.cap_n = N;
+    c.nc = nc;
+    c.ncell = ncell;
+    c.args = CellBuildArgs{b->pos4, b->poslo, N, nc, ncell, 0, c.cellof, c.rank, c.count, c.start,
+                           c.sorted, c.slot, c.spos4, c.sposlo, c.sref, c.drift};
+    hipLaunchKernelGGL(k_fill_i32, dim3((ncell + 255) / 256), dim3(256), 0, b->stream, c.count, ncell, 0);
+    ND_HIP(hipGetLastError());
+    ND_HIP(hipMemcpyAsync(c.d_args, &c.args, sizeof(CellBuildArgs), hipMemcpyHostToDevice, b->stream));
+    ND_HIP(hipStreamSynchronize(b->stream));
+}
+
+void cells_rebuild_launch(hipStream_t s, const CellBuildArgs *d_args, int n_boxes, int max_n, int max_ncell)
+{
+    if (n_boxes <= 0) return;
+    const dim3 ga((max_n + CB_THREADS - 1) / CB_THREADS, n_boxes);
+    const dim3 gc((max_ncell + CB_THREADS - 1) / CB_THREADS, n_boxes);
+    hipLaunchKernelGGL(k_cb_count, ga, dim3(CB_THREADS), 0, s, d_args);
+    ND_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_cb_scan, dim3(1, n_boxes), dim3(CB_SCAN_THREADS), 0, s, d_args);
+    ND_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_cb_scatter, ga, dim3(CB_THREADS), 0, s, d_args);
+    ND_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_cb_finish, gc, dim3(CB_THREADS), 0, s, d_args);
+    ND_HIP(hipGetLastError());
 }
 
 void cells_build(nd_box *b)
 {
+    cells_ensure(b);
     Cells &c = b->cells;
-    const int N = b->N;
-    // about four atoms per cell, at least one cell per axis
-    const double rho = (double)N / (b->L * b->L * b->L);
-    const double edge = std::cbrt(4.0 / rho);
-    int nc = (int)std::floor(b->L / edge);
-    nc = std::max(1, std::min(nc, 128));
-    const int ncell = nc * nc * nc;
-    int abits = 1;
-    while ((1ll << abits) < (long long)N) ++abits;
-    int cbits = 1;
-    while ((1ll << cbits) < (long long)ncell) ++cbits;
-    if (c.cap_n < N || c.ncell != ncell) {
-        ND_HIP(hipStreamSynchronize(b->stream));
-        cells_free(b);
-        c.start = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * (ncell + 1)));
-        c.sorted = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * N));
-        c.slot = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * N));
-        c.spos4 = static_cast<float4 *>(dmalloc(sizeof(float4) * N));
-        c.sposlo = static_cast<float4 *>(dmalloc(sizeof(float4) * N));
-        c.sref = static_cast<float4 *>(dmalloc(sizeof(float4) * N));
-        c.keys_in = static_cast<uint64_t *>(dmalloc(sizeof(uint64_t) * N));
-        c.keys_out = static_cast<uint64_t *>(dmalloc(sizeof(uint64_t) * N));
-        c.drift = static_cast<float *>(dmalloc(sizeof(float)));
-        size_t tmp = 0;
-        ND_HIP(rocprim::radix_sort_keys(nullptr, tmp, c.keys_in, c.keys_out, (unsigned)N, 0u,
-                                        (unsigned)(abits + cbits), b->stream));
-        c.sort_tmp = dmalloc(tmp);
-        c.sort_tmp_bytes = tmp;
-        c.cap_n = N;
-        c.ncell = ncell;
-    }
-    c.nc = nc;
-    const int threads = 256, blocks = (N + threads - 1) / threads;
-    hipLaunchKernelGGL(k_cell_keys, dim3(blocks), dim3(threads), 0, b->stream, b->pos4, N, nc, abits, c.keys_in);
-    ND_HIP(hipGetLastError());
-    size_t tmp = c.sort_tmp_bytes;
-    ND_HIP(rocprim::radix_sort_keys(c.sort_tmp, tmp, c.keys_in, c.keys_out, (unsigned)N, 0u,
-                                    (unsigned)(abits + cbits), b->stream));
-    hipLaunchKernelGGL(k_cell_gather, dim3(blocks), dim3(threads), 0, b->stream, c.keys_out, N, abits, ncell, b->pos4,
-                       b->poslo, c.sorted, c.slot, c.spos4, c.sposlo, c.sref, c.start);
-    ND_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(1), 0, b->stream, c.drift);
-    ND_HIP(hipGetLastError());
+    cells_rebuild_launch(b->stream, c.d_args, 1, b->N, c.ncell);
     c.valid = true;
     c.trials_since_build = 0;
 }

@@ -58,81 +58,167 @@ struct HistArgs {
     long long ntp;
     double L, invL, dr, e2max;
     float inv_dr_f, edge_eps;
-    unsigned *partial;  // [gridDim.x][P * nbins]
+    unsigned *partial;      // [gridDim.x][P * nbins] (one box per launch)
+    unsigned long long *out;  // [P * nbins] counts, accumulated atomically (several boxes per launch)
+    long long tile0;        // first global tile-pair index of this box (several boxes per launch)
 };
+
+// LDS layout of the histogram kernels.
+struct HistLds {
+    double *jx;      // [3][TILE] j-tile coordinates
+    int *js;         // [TILE] j-tile species
+    int *prow;       // [16] partial row offset of each species pair
+    unsigned *hist;  // [P * nbins]
+};
+
+__device__ __forceinline__ HistLds hist_lds(unsigned char *smem)
+{
+    HistLds h;
+    h.jx = reinterpret_cast<double *>(smem);
+    h.js = reinterpret_cast<int *>(h.jx + 3 * TILE);
+    h.prow = h.js + TILE;
+    h.hist = reinterpret_cast<unsigned *>(h.prow + 16);
+    return h;
+}
+
+// Zero the LDS histogram and set the species-pair row offsets of box a.
+__device__ __forceinline__ void hist_begin(const HistArgs &a, const HistLds &h)
+{
+    const int tid = threadIdx.x;
+    for (int q = tid; q < a.P * a.nbins; q += TILE) h.hist[q] = 0u;
+    if (tid < a.M * a.M) {
+        int s0 = tid / a.M, s1 = tid % a.M;
+        int lo = s0 < s1 ? s0 : s1, hi = s0 < s1 ? s1 : s0;
+        h.prow[tid] = (lo * a.M - lo * (lo - 1) / 2 + (hi - lo)) * a.nbins;
+    }
+    __syncthreads();
+}
+
+// Every pair (i, j) of tile pair (I, J), i < j on the diagonal: nearest
+// image in FP64, r2 = fma(dz,dz, fma(dy,dy, dx*dx)), bin by the exact edge
+// test, one LDS atomic per counted pair.
+__device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, int I, int J)
+{
+    const int tid = threadIdx.x;
+    const int N = a.N;
+    const int i = I * TILE + tid;
+    const bool iv = i < N;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    int si = 0;
+    if (iv) {
+        xi = (double)a.xyz[i];
+        yi = (double)a.xyz[N + i];
+        zi = (double)a.xyz[2 * N + i];
+        si = a.sp[i];
+    }
+    __syncthreads();  // previous tile's readers are done with jx/js
+    const int j = J * TILE + tid;
+    if (j < N) {
+        h.jx[tid] = (double)a.xyz[j];
+        h.jx[TILE + tid] = (double)a.xyz[N + j];
+        h.jx[2 * TILE + tid] = (double)a.xyz[2 * N + j];
+        h.js[tid] = a.sp[j];
+    }
+    __syncthreads();
+    const int jn = min(TILE, N - J * TILE);
+    const int jstart = (I == J) ? tid + 1 : 0;  // diagonal tile: pairs j > i only
+    if (!iv) return;
+    const int rowbase = si * a.M;
+    const double *jx = h.jx;
+#pragma unroll 4
+    for (int jj = jstart; jj < jn; ++jj) {
+        double dx = jx[jj] - xi;
+        double dy = jx[TILE + jj] - yi;
+        double dz = jx[2 * TILE + jj] - zi;
+        dx = fma(-rint(dx * a.invL), a.L, dx);
+        dy = fma(-rint(dy * a.invL), a.L, dy);
+        dz = fma(-rint(dz * a.invL), a.L, dz);
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        if (r2 < a.e2max) {
+            // candidate bin from an FP32 square root; exact FP64 edge test
+            // only when the candidate lies within edge_eps of a bin edge
+            const float tb = __builtin_amdgcn_sqrtf((float)r2) * a.inv_dr_f;
+            int k = (int)tb;
+            const float fr = tb - (float)k;
+            if (fr < a.edge_eps || fr > 1.0f - a.edge_eps) {
+                const int kk = (int)rintf(tb);
+                const double e = (double)kk * a.dr;
+                k = (r2 >= e * e) ? kk : kk - 1;
+            }
+            atomicAdd(&h.hist[h.prow[rowbase + h.js[jj]] + k], 1u);
+        }
+    }
+}
 
 __global__ __launch_bounds__(TILE) void k_pair_hist(HistArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    const HistLds h = hist_lds(smem);
     const int nq = a.P * a.nbins;
-    double *jx = reinterpret_cast<double *>(smem);         // [3][TILE]
-    int *js = reinterpret_cast<int *>(jx + 3 * TILE);       // [TILE]  pair-row offsets per i species
-    int *prow = js + TILE;                                  // [M*M]
-    unsigned *hist = reinterpret_cast<unsigned *>(prow + 16);  // [nq]
     const int tid = threadIdx.x;
-
-    for (int q = tid; q < nq; q += TILE) hist[q] = 0u;
-    if (tid < a.M * a.M) {
-        int s0 = tid / a.M, s1 = tid % a.M;
-        int lo = s0 < s1 ? s0 : s1, hi = s0 < s1 ? s1 : s0;
-        prow[tid] = (lo * a.M - lo * (lo - 1) / 2 + (hi - lo)) * a.nbins;
-    }
-    __syncthreads();
-
-    const int N = a.N;
+    hist_begin(a, h);
     for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
         int I, J;
         tri_index(t, a.nt, I, J);
-        const int i = I * TILE + tid;
-        const bool iv = i < N;
-        double xi = 0.0, yi = 0.0, zi = 0.0;
-        int si = 0;
-        if (iv) {
-            xi = (double)a.xyz[i];
-            yi = (double)a.xyz[N + i];
-            zi = (double)a.xyz[2 * N + i];
-            si = a.sp[i];
-        }
-        __syncthreads();  // previous tile's readers are done with jx/js
-        const int j = J * TILE + tid;
-        if (j < N) {
-            jx[tid] = (double)a.xyz[j];
-            jx[TILE + tid] = (double)a.xyz[N + j];
-            jx[2 * TILE + tid] = (double)a.xyz[2 * N + j];
-            js[tid] = a.sp[j];
-        }
-        __syncthreads();
-        const int jn = min(TILE, N - J * TILE);
-        const int jstart = (I == J) ? tid + 1 : 0;  // diagonal tile: pairs j > i only
-        if (!iv) continue;
-        const int rowbase = si * a.M;
-#pragma unroll 4
-        for (int jj = jstart; jj < jn; ++jj) {
-            double dx = jx[jj] - xi;
-            double dy = jx[TILE + jj] - yi;
-            double dz = jx[2 * TILE + jj] - zi;
-            dx = fma(-rint(dx * a.invL), a.L, dx);
-            dy = fma(-rint(dy * a.invL), a.L, dy);
-            dz = fma(-rint(dz * a.invL), a.L, dz);
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            if (r2 < a.e2max) {
-                // candidate bin from an FP32 square root; exact FP64 edge test
-                // only when the candidate lies within edge_eps of a bin edge
-                const float tb = __builtin_amdgcn_sqrtf((float)r2) * a.inv_dr_f;
-                int k = (int)tb;
-                const float fr = tb - (float)k;
-                if (fr < a.edge_eps || fr > 1.0f - a.edge_eps) {
-                    const int kk = (int)rintf(tb);
-                    const double e = (double)kk * a.dr;
-                    k = (r2 >= e * e) ? kk : kk - 1;
-                }
-                atomicAdd(&hist[prow[rowbase + js[jj]] + k], 1u);
-            }
-        }
+        hist_tile(a, h, I, J);
     }
     __syncthreads();
     unsigned *out = a.partial + (size_t)blockIdx.x * nq;
-    for (int q = tid; q < nq; q += TILE) out[q] = hist[q];
+    for (int q = tid; q < nq; q += TILE) out[q] = h.hist[q];
+}
+
+// Several boxes in one persistent launch.  The tile pairs of all boxes form
+// one index range (box after box); block b takes the contiguous slice
+// [b per, (b + 1) per) of it, so it meets one or two boxes, and adds its LDS
+// histogram to a box's counts with integer atomics when it leaves the box
+// (exact, so the counts do not depend on the order of the blocks).
+__global__ __launch_bounds__(TILE) void k_pair_hist_multi(const HistArgs *__restrict__ boxes, int n_boxes,
+                                                          long long total, long long per)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const HistLds h = hist_lds(smem);
+    const int tid = threadIdx.x;
+    long long t = (long long)blockIdx.x * per;
+    const long long t_end = min(total, t + per);
+    if (t >= t_end) return;
+    // box holding tile pair t: the last box whose first tile is <= t
+    int bi = 0;
+    {
+        int lo = 0, hi = n_boxes - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (boxes[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+        }
+        bi = lo;
+    }
+    while (t < t_end) {
+        const HistArgs &a = boxes[bi];
+        const long long box_end = min(t_end, a.tile0 + a.ntp);
+        if (t < box_end) {
+            hist_begin(a, h);
+            for (; t < box_end; ++t) {
+                int I, J;
+                tri_index(t - a.tile0, a.nt, I, J);
+                hist_tile(a, h, I, J);
+            }
+            __syncthreads();
+            const int nq = a.P * a.nbins;
+            for (int q = tid; q < nq; q += TILE) {
+                const unsigned v = h.hist[q];
+                if (v) atomicAdd(&a.out[q], (unsigned long long)v);
+            }
+            __syncthreads();
+        }
+        ++bi;
+        if (bi >= n_boxes) break;
+    }
+}
+
+__global__ void k_zero_u64_multi(const HistArgs *__restrict__ boxes)
+{
+    const HistArgs &a = boxes[blockIdx.y];
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < a.P * a.nbins) a.out[q] = 0ull;
 }
 
 __global__ void k_hist_reduce(const unsigned *__restrict__ partial, int G, int nq, uint64_t *__restrict__ counts)
@@ -270,9 +356,13 @@ void launch_pos4_from_xyz(nd_box *b)
     ND_HIP(hipGetLastError());
 }
 
-void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
+}  // namespace nd
+
+namespace {
+
+HistArgs make_hist_args(const nd_box *b, double dr, int nbins)
 {
-    HistArgs a;
+    HistArgs a{};
     a.xyz = b->xyz;
     a.sp = b->species;
     a.N = b->N;
@@ -291,10 +381,26 @@ void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
     a.inv_dr_f = (float)(1.0 / dr);
     // bound on |candidate - sqrt(r2)/dr|: < 2.5e-7 relative, plus margin
     a.edge_eps = (float)(1e-3 + 4e-7 * (double)nbins);
-    if (!(a.edge_eps < 0.25f)) fail(ND_E_UNSUPPORTED, "nbins too large for the binning kernel");
+    if (!(a.edge_eps < 0.25f)) nd::fail(ND_E_UNSUPPORTED, "nbins too large for the binning kernel");
+    return a;
+}
+
+size_t hist_lds_bytes(int nq)
+{
+    const size_t lds = sizeof(double) * 3 * TILE + sizeof(int) * (TILE + 16) + sizeof(unsigned) * (size_t)nq;
+    if (lds > 160 * 1024) nd::fail(ND_E_UNSUPPORTED, "histogram does not fit in LDS (P*nbins too large)");
+    return lds;
+}
+
+}  // namespace
+
+namespace nd {
+
+void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
+{
+    HistArgs a = make_hist_args(b, dr, nbins);
     const int nq = a.P * nbins;
-    size_t lds = sizeof(double) * 3 * TILE + sizeof(int) * (TILE + 16) + sizeof(unsigned) * (size_t)nq;
-    if (lds > 160 * 1024) fail(ND_E_UNSUPPORTED, "histogram does not fit in LDS (P*nbins too large)");
+    const size_t lds = hist_lds_bytes(nq);
     int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (lds + 1024)));
     long long G = (long long)cu_count(b->device) * per_cu;
     if (G > a.ntp) G = a.ntp;
@@ -310,6 +416,76 @@ void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
     }
     hipLaunchKernelGGL(k_hist_reduce, dim3((nq + 255) / 256), dim3(256), 0, b->stream, a.partial, (int)G, nq,
                        d_counts);
+    ND_HIP(hipGetLastError());
+}
+
+// ---- several boxes in one launch (the batched form)
+struct HistMulti {
+    std::vector<HistArgs> boxes;
+    HistArgs *d_boxes = nullptr;
+    size_t cap = 0;
+    long long total = 0, per = 0;
+    int G = 0, max_nq = 0;
+    size_t lds = 0;
+};
+
+HistMulti *hist_multi_create() { return new HistMulti(); }
+
+void hist_multi_destroy(HistMulti *m)
+{
+    if (!m) return;
+    dfree(m->d_boxes);
+    delete m;
+}
+
+void hist_multi_plan(HistMulti *m, nd_box *const *boxes, int n, double dr, const int32_t *nbins,
+                     uint64_t *const *counts, std::vector<long long> &sig)
+{
+    m->boxes.clear();
+    m->total = 0;
+    m->max_nq = 0;
+    for (int i = 0; i < n; ++i) {
+        HistArgs a = make_hist_args(boxes[i], dr, nbins[i]);
+        a.out = reinterpret_cast<unsigned long long *>(counts[i]);
+        a.tile0 = m->total;
+        m->total += a.ntp;
+        m->max_nq = std::max(m->max_nq, a.P * a.nbins);
+        m->boxes.push_back(a);
+    }
+    m->lds = hist_lds_bytes(m->max_nq);
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (m->lds + 1024)));
+    long long G = (long long)cu_count(boxes[0]->device) * per_cu;
+    if (G > m->total) G = m->total;
+    m->per = (m->total + G - 1) / G;
+    m->G = (int)((m->total + m->per - 1) / m->per);
+    if ((double)m->per * TILE * TILE >= 4294967295.0) fail(ND_E_UNSUPPORTED, "boxes too large for u32 counters");
+    if (m->cap < m->boxes.size() || !m->d_boxes) {
+        dfree(m->d_boxes);
+        m->d_boxes = static_cast<HistArgs *>(dmalloc(sizeof(HistArgs) * m->boxes.size()));
+        m->cap = m->boxes.size();
+    }
+    sig.push_back(0x4849);
+    sig.push_back(n);
+    sig.push_back(m->G);
+    sig.push_back(m->per);
+    sig.push_back(m->total);
+    sig.push_back(m->max_nq);
+    sig.push_back((long long)m->lds);
+    sig.push_back((long long)(uintptr_t)m->d_boxes);
+}
+
+void hist_multi_upload(HistMulti *m, hipStream_t s)
+{
+    ND_HIP(hipMemcpyAsync(m->d_boxes, m->boxes.data(), sizeof(HistArgs) * m->boxes.size(), hipMemcpyHostToDevice, s));
+    ND_HIP(hipStreamSynchronize(s));
+}
+
+void hist_multi_enqueue(HistMulti *m, hipStream_t s)
+{
+    const int n = (int)m->boxes.size();
+    hipLaunchKernelGGL(k_zero_u64_multi, dim3((m->max_nq + 255) / 256, n), dim3(256), 0, s, m->d_boxes);
+    ND_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_pair_hist_multi, dim3(m->G), dim3(TILE), m->lds, s, m->d_boxes, n, m->total, m->per);
     ND_HIP(hipGetLastError());
 }
 

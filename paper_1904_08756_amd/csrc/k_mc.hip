@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace {
 
@@ -90,7 +91,7 @@ struct ProposeArgs {
 // (sqrt(1-z^2) cos phi, sqrt(1-z^2) sin phi, z), z = 2u_3 - 1, phi = 2 pi u_4,
 // through the unweighted centroid of the unit unwrapped around its first
 // atom (Rodrigues' formula).  FP64, then wrapped and rounded to float32.
-__device__ void propose_one(const ProposeArgs &a, int k)
+__device__ __forceinline__ void propose_one(const ProposeArgs &a, int k)
 {
     const uint64_t t = a.t0 + (uint64_t)k;
     const int u = (int)(t % (uint64_t)a.n_units);
@@ -674,7 +675,8 @@ __device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k,
 // corrections (both need only the batch's proposals), then the proposals of
 // the next batch, whose units are disjoint from this batch's.
 template <int MAXNU>
-__global__ __launch_bounds__(256) void k_mc_scan_corr(CellScanArgs a, CorrArgs ca, ProposeArgs next)
+__device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const CorrArgs &ca, const ProposeArgs &next,
+                                               int bx)
 {
     extern __shared__ float s_tab[];  // [P][n_pts]
     __shared__ int s_prow[16];
@@ -683,16 +685,16 @@ __global__ __launch_bounds__(256) void k_mc_scan_corr(CellScanArgs a, CorrArgs c
     __shared__ TrialAtoms s_ta;
     const int tid = threadIdx.x;
     const int n_corr_blocks = (a.kb + CORR_TPB - 1) / CORR_TPB;
-    if ((int)blockIdx.x >= a.kb + n_corr_blocks) {
-        const int k = ((int)blockIdx.x - a.kb - n_corr_blocks) * 256 + tid;
+    if (bx >= a.kb + n_corr_blocks) {
+        const int k = (bx - a.kb - n_corr_blocks) * 256 + tid;
         if (k < next.kb) propose_one(next, k);
         return;
     }
-    if ((int)blockIdx.x >= a.kb) {
+    if (bx >= a.kb) {
         if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
         __syncthreads();
         const PairCtx c{ca.tab, s_prow, ca.M, ca.n_pts, ca.rcf2_filter, ca.rcf2, ca.tscale};
-        const int k_begin = ((int)blockIdx.x - a.kb) * CORR_TPB, k_end = min(ca.kb, k_begin + CORR_TPB);
+        const int k_begin = (bx - a.kb) * CORR_TPB, k_end = min(ca.kb, k_begin + CORR_TPB);
         for (int k = k_begin + (tid >> 6); k < k_end; k += 4) corr_trial<MAXNU>(ca, c, k, tid & 63);
         return;
     }
@@ -701,7 +703,13 @@ __global__ __launch_bounds__(256) void k_mc_scan_corr(CellScanArgs a, CorrArgs c
     if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
     __syncthreads();
     const PairCtx c{s_tab, s_prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
-    scan_cells_block<MAXNU>(a, c, blockIdx.x, s_list[tid >> 6], s_red, s_ta);
+    scan_cells_block<MAXNU>(a, c, bx, s_list[tid >> 6], s_red, s_ta);
+}
+
+template <int MAXNU>
+__global__ __launch_bounds__(256) void k_mc_scan_corr(CellScanArgs a, CorrArgs ca, ProposeArgs next)
+{
+    scan_corr_body<MAXNU>(a, ca, next, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- decide
@@ -775,7 +783,7 @@ constexpr int DEC_INTRA = 8;  // intra-chunk correction entries kept in register
 // lanes whose dependencies are all decided decide together, round by round.
 // When `next.kb` > 0 the next batch is proposed afterwards (used when its
 // units may overlap this batch's).
-__global__ __launch_bounds__(DEC_THREADS) void k_mc_decide(DecideArgs a, ProposeArgs next)
+__device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeArgs &next)
 {
     __shared__ double s_e[KMAX];
     __shared__ double s_u[KMAX];  // acceptance threshold -kT ln u
@@ -1010,12 +1018,60 @@ __global__ __launch_bounds__(DEC_THREADS) void k_mc_decide(DecideArgs a, Propose
     for (int k = tid; k < next.kb; k += DEC_THREADS) propose_one(next, k);
 }
 
+__global__ __launch_bounds__(DEC_THREADS) void k_mc_decide(DecideArgs a, ProposeArgs next) { decide_body(a, next); }
+
 __global__ void k_mc_reset(long long *counters, double *dsum, int32_t *ovf_fill)
 {
     if (threadIdx.x < 2) counters[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         *dsum = 0.0;
         *ovf_fill = 0;
+    }
+}
+
+// ---------------------------------------------------------------- several boxes
+// One batch of one box: the arguments of its scan launch (cell scan,
+// corrections, early proposals of the next batch) and of its decision launch.
+struct McLaunch {
+    CellScanArgs ca;
+    CorrArgs cr;
+    ProposeArgs next;  // next batch proposed by the scan launch (kb = 0: not there)
+    DecideArgs da;
+    ProposeArgs late;  // next batch proposed after the commit (kb = 0: not there)
+    int nblk;          // blocks of the scan launch
+    int rebuild;       // cells rebuilt before this batch
+};
+
+// The same kernels over several boxes at once: blockIdx.y selects the box's
+// batch descriptor, blocks past a box's own grid return at once.
+template <int MAXNU>
+__global__ __launch_bounds__(256) void k_mc_scan_corr_multi(const McLaunch *__restrict__ L)
+{
+    const McLaunch &e = L[blockIdx.y];
+    if ((int)blockIdx.x >= e.nblk) return;
+    scan_corr_body<MAXNU>(e.ca, e.cr, e.next, blockIdx.x);
+}
+
+__global__ __launch_bounds__(DEC_THREADS) void k_mc_decide_multi(const McLaunch *__restrict__ L)
+{
+    const McLaunch &e = L[blockIdx.y];
+    decide_body(e.da, e.late);
+}
+
+__global__ __launch_bounds__(64) void k_mc_propose_multi(const ProposeArgs *__restrict__ P)
+{
+    const ProposeArgs &a = P[blockIdx.y];
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k < a.kb) propose_one(a, k);
+}
+
+__global__ void k_mc_reset_multi(const McLaunch *__restrict__ L)
+{
+    const DecideArgs &d = L[blockIdx.y].da;
+    if (threadIdx.x < 2) d.counters[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        *d.dsum = 0.0;
+        *d.ovf_fill = 0;
     }
 }
 
@@ -1108,195 +1164,467 @@ int mc_batch_size(nd_box *b, const nd_mc_params *p)
     return std::max(1, std::min({K, KMAX, b->n_units}));
 }
 
-void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n, const nd_mc_trace *trace)
+}  // namespace nd
+
+namespace {
+
+using nd::McWork;
+
+struct McConsts {
+    float rcf, rcf2_filter;
+    double rcf2, tscale, tie_rel;
+};
+
+McConsts mc_consts(const nd_box *b, const nd_mc_params *p)
 {
-    const bool full = p->scan == ND_SCAN_FULL;
+    McConsts c;
+    c.rcf = (float)(b->rc / b->L);
+    c.rcf2_filter = nd::filter_r2(b->rc / b->L);
+    c.rcf2 = (b->rc / b->L) * (b->rc / b->L);
+    c.tscale = b->L / b->h;
+    c.tie_rel = p->tie_rel > 0.0 ? p->tie_rel : 1e-6;
+    return c;
+}
+
+size_t mc_table_lds(const nd_box *b)
+{
+    const size_t lds_tab = sizeof(float) * (size_t)b->P * b->n_pts;
+    if (lds_tab > 64 * 1024) nd::fail(ND_E_UNSUPPORTED, "potential table larger than 64 KB");
+    return lds_tab;
+}
+
+ProposeArgs proposal_args(const nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t t0, int kb, int buf, int K)
+{
+    const McWork &w = b->mc;
+    ProposeArgs pa;
+    pa.xyz = b->xyz;
+    pa.pos4 = b->pos4;
+    pa.poslo = b->poslo;
+    pa.uoff = b->uoff;
+    pa.N = b->N;
+    pa.n_units = b->n_units;
+    pa.L = b->L;
+    pa.invL = 1.0 / b->L;
+    pa.max_disp = p->max_disp;
+    pa.max_rot = p->max_rot;
+    pa.seed = seed;
+    pa.t0 = t0;
+    pa.kb = kb;
+    pa.trials = w.trials + (size_t)buf * K;
+    pa.spheres = w.spheres + (size_t)buf * K;
+    return pa;
+}
+
+CorrArgs corr_args(const nd_box *b, const McConsts &k, const nd::Trial *trials, const float4 *spheres, int kb, int K)
+{
+    const McWork &w = b->mc;
+    CorrArgs cr;
+    cr.tab = b->tab;
+    cr.trials = trials;
+    cr.spheres = spheres;
+    cr.M = b->M;
+    cr.n_pts = b->n_pts;
+    cr.kb = kb;
+    cr.rcf = k.rcf + 2e-6f;
+    cr.rcf2_filter = k.rcf2_filter;
+    cr.rcf2 = k.rcf2;
+    cr.tscale = k.tscale;
+    cr.corr_n = w.corr_n;
+    cr.corr_ptr = w.corr_ptr;
+    cr.corr_s = w.corr_s;
+    cr.pool_m = w.pool_m;
+    cr.pool_c = w.pool_c;
+    cr.ovf_fill = w.ovf_fill;
+    cr.ovf_base = K * CORR_CAP;
+    return cr;
+}
+
+DecideArgs decide_args(const nd_box *b, const nd_mc_params *p, const McConsts &k, const nd::Trial *trials, int kb,
+                       int64_t done, const nd_mc_trace *trace, bool cells_live)
+{
+    const McWork &w = b->mc;
+    DecideArgs da;
+    da.xyz = b->xyz;
+    da.pos4 = b->pos4;
+    da.poslo = b->poslo;
+    da.E = b->E;
+    da.trials = trials;
+    da.dE0 = w.dE0;
+    da.S0 = w.S0;
+    da.corr_n = w.corr_n;
+    da.corr_ptr = w.corr_ptr;
+    da.pool_m = w.pool_m;
+    da.pool_c = w.pool_c;
+    da.corr_s = w.corr_s;
+    da.ovf_fill = w.ovf_fill;
+    da.cell_slot = cells_live ? b->cells.slot : nullptr;
+    da.spos4 = cells_live ? b->cells.spos4 : nullptr;
+    da.sposlo = cells_live ? b->cells.sposlo : nullptr;
+    da.sref = cells_live ? b->cells.sref : nullptr;
+    da.drift = cells_live ? b->cells.drift : nullptr;
+    da.N = b->N;
+    da.kb = kb;
+    da.kT = p->kT;
+    da.tie_rel = k.tie_rel;
+    da.counters = w.counters;
+    da.dsum = w.dsum;
+    da.tr_dE = trace && trace->dE ? trace->dE + done : nullptr;
+    da.tr_sabs = trace && trace->sabs ? trace->sabs + done : nullptr;
+    da.tr_acc = trace && trace->accepted ? trace->accepted + done : nullptr;
+    da.tr_unit = trace && trace->unit ? trace->unit + done : nullptr;
+    return da;
+}
+
+// Plan of n trials of one box with the cell scan.
+struct McPlan {
+    int K = 0, maxnu = 1;
+    size_t lds = 0;
+    ProposeArgs first;               // proposals of the first batch
+    std::vector<McLaunch> batches;
+};
+
+// Every batch's launch arguments and cell rebuild points, in order.  The
+// box's cell bookkeeping is advanced as the launches will advance it.
+void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n,
+                   const nd_mc_trace *trace, bool force_rebuild, McPlan &pl)
+{
+    const int K = nd::mc_batch_size(b, p);
+    ensure_work(b, K, 1);
+    nd::cells_ensure(b);
+    const McWork &w = b->mc;
+    const McConsts k = mc_consts(b, p);
+    pl.K = K;
+    pl.maxnu = pick_maxnu(b->max_na);
+    pl.lds = mc_table_lds(b);
+    pl.batches.clear();
+    pl.first = proposal_args(b, p, seed, first, (int)std::min<int64_t>(K, n), 0, K);
+    if (force_rebuild) b->cells.valid = false;
+    // the next batch's units are disjoint from this batch's when 2K <= n_units:
+    // propose it alongside this batch's scan instead of after the commit
+    const bool early_propose = 2 * K <= b->n_units;
+    int buf = 0;
+    for (int64_t done = 0; done < n;) {
+        const int kb = (int)std::min<int64_t>(K, n - done);
+        const nd::Trial *trials = w.trials + (size_t)buf * K;
+        const float4 *spheres = w.spheres + (size_t)buf * K;
+        McLaunch L;
+        L.rebuild = (!b->cells.valid || b->cells.trials_since_build >= b->n_units) ? 1 : 0;
+        if (L.rebuild) {
+            b->cells.valid = true;
+            b->cells.trials_since_build = 0;
+        }
+        L.cr = corr_args(b, k, trials, spheres, kb, K);
+        CellScanArgs &ca = L.ca;
+        ca.spos4 = b->cells.spos4;
+        ca.sposlo = b->cells.sposlo;
+        ca.sorted = b->cells.sorted;
+        ca.cstart = b->cells.start;
+        ca.tab = b->tab;
+        ca.trials = trials;
+        ca.drift = b->cells.drift;
+        ca.M = b->M;
+        ca.n_pts = b->n_pts;
+        ca.kb = kb;
+        ca.nc = b->cells.nc;
+        ca.rcf = k.rcf;
+        ca.rcf2_filter = k.rcf2_filter;
+        ca.rcf2 = k.rcf2;
+        ca.tscale = k.tscale;
+        ca.dE0 = w.dE0;
+        ca.S0 = w.S0;
+        const int64_t done_next = done + kb;
+        const int kb_next = (int)std::max<int64_t>(0, std::min<int64_t>(K, n - done_next));
+        const ProposeArgs nx = proposal_args(b, p, seed, first + (uint64_t)done_next, kb_next, buf ^ 1, K);
+        L.next = nx;
+        L.late = nx;
+        if (early_propose)
+            L.late.kb = 0;
+        else
+            L.next.kb = 0;
+        L.da = decide_args(b, p, k, trials, kb, done, trace, true);
+        L.nblk = kb + (kb + CORR_TPB - 1) / CORR_TPB + (L.next.kb + 255) / 256;
+        b->cells.trials_since_build += kb;
+        pl.batches.push_back(L);
+        done = done_next;
+        buf ^= 1;
+    }
+}
+
+template <int MAXNU>
+void launch_scan_corr_multi(hipStream_t s, const McLaunch *d_L, int n_boxes, int max_blk, size_t lds)
+{
+    hipLaunchKernelGGL(k_mc_scan_corr_multi<MAXNU>, dim3(max_blk, n_boxes), dim3(256), lds, s, d_L);
+    ND_HIP(hipGetLastError());
+}
+
+void scan_corr_multi(int maxnu, hipStream_t s, const McLaunch *d_L, int n_boxes, int max_blk, size_t lds)
+{
+    switch (maxnu) {
+    case 1: launch_scan_corr_multi<1>(s, d_L, n_boxes, max_blk, lds); break;
+    case 2: launch_scan_corr_multi<2>(s, d_L, n_boxes, max_blk, lds); break;
+    case 3: launch_scan_corr_multi<3>(s, d_L, n_boxes, max_blk, lds); break;
+    case 4: launch_scan_corr_multi<4>(s, d_L, n_boxes, max_blk, lds); break;
+    default: launch_scan_corr_multi<8>(s, d_L, n_boxes, max_blk, lds); break;
+    }
+}
+
+// The O(N) scan of every atom per trial (ND_SCAN_FULL).
+void mc_run_full(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n, const nd_mc_trace *trace)
+{
     const int n_jb = (b->N + SCAN_JB - 1) / SCAN_JB;
-    const int K = mc_batch_size(b, p);
+    const int K = nd::mc_batch_size(b, p);
     ensure_work(b, K, n_jb);
     McWork &w = b->mc;
-    const size_t lds_tab = sizeof(float) * (size_t)b->P * b->n_pts;
-    if (lds_tab > 64 * 1024) fail(ND_E_UNSUPPORTED, "potential table larger than 64 KB");
-    const double tie_rel = p->tie_rel > 0.0 ? p->tie_rel : 1e-6;
+    const size_t lds_tab = mc_table_lds(b);
+    const McConsts k = mc_consts(b, p);
     const int maxnu = pick_maxnu(b->max_na);
-    const int ncu = cu_count(b->device);
-    const float rcf = (float)(b->rc / b->L);
-    const float rcf2_filter = nd::filter_r2(b->rc / b->L);
-    const double rcf2 = (b->rc / b->L) * (b->rc / b->L);
-    const double tscale = b->L / b->h;
+    const int ncu = nd::cu_count(b->device);
 
     hipLaunchKernelGGL(k_mc_reset, dim3(1), dim3(64), 0, b->stream, w.counters, w.dsum, w.ovf_fill);
     ND_HIP(hipGetLastError());
     if (n == 0) return;
-
-    auto proposal_args = [&](int64_t done, int kb, int buf) {
-        ProposeArgs pa;
-        pa.xyz = b->xyz;
-        pa.pos4 = b->pos4;
-        pa.poslo = b->poslo;
-        pa.uoff = b->uoff;
-        pa.N = b->N;
-        pa.n_units = b->n_units;
-        pa.L = b->L;
-        pa.invL = 1.0 / b->L;
-        pa.max_disp = p->max_disp;
-        pa.max_rot = p->max_rot;
-        pa.seed = seed;
-        pa.t0 = first + (uint64_t)done;
-        pa.kb = kb;
-        pa.trials = w.trials + (size_t)buf * K;
-        pa.spheres = w.spheres + (size_t)buf * K;
-        return pa;
-    };
-
     int buf = 0;
     {
-        ProposeArgs pa = proposal_args(0, (int)std::min<int64_t>(K, n), buf);
-        ProfScope ps(b, ND_PROF_MC_PROPOSE);
+        ProposeArgs pa = proposal_args(b, p, seed, first, (int)std::min<int64_t>(K, n), buf, K);
+        nd::ProfScope ps(b, ND_PROF_MC_PROPOSE);
         hipLaunchKernelGGL(k_mc_propose, dim3((pa.kb + 63) / 64), dim3(64), 0, b->stream, pa);
         ND_HIP(hipGetLastError());
     }
-
     for (int64_t done = 0; done < n;) {
         const int kb = (int)std::min<int64_t>(K, n - done);
         nd::Trial *trials = w.trials + (size_t)buf * K;
         float4 *spheres = w.spheres + (size_t)buf * K;
-        if (!full && (!b->cells.valid || b->cells.trials_since_build >= b->n_units)) cells_build(b);
-
-        CorrArgs cr;
-        cr.tab = b->tab;
-        cr.trials = trials;
-        cr.spheres = spheres;
-        cr.M = b->M;
-        cr.n_pts = b->n_pts;
-        cr.kb = kb;
-        cr.rcf = rcf + 2e-6f;
-        cr.rcf2_filter = rcf2_filter;
-        cr.rcf2 = rcf2;
-        cr.tscale = tscale;
-        cr.corr_n = w.corr_n;
-        cr.corr_ptr = w.corr_ptr;
-        cr.corr_s = w.corr_s;
-        cr.pool_m = w.pool_m;
-        cr.pool_c = w.pool_c;
-        cr.ovf_fill = w.ovf_fill;
-        cr.ovf_base = K * CORR_CAP;
-
+        const CorrArgs cr = corr_args(b, k, trials, spheres, kb, K);
         const int64_t done_next = done + kb;
-        const int kb_next = (int)std::min<int64_t>(K, n - done_next);
-        ProposeArgs next = proposal_args(done_next, std::max(kb_next, 0), buf ^ 1);
-        // the next batch's units are disjoint from this batch's when 2K <= n_units:
-        // propose it alongside this batch's scan instead of after the commit
-        const bool early_propose = !full && 2 * K <= b->n_units;
-        if (full) {
-            int tg = (int)std::max<long long>(1, std::min<long long>(MAX_TG, ((long long)kb * n_jb) / (2LL * ncu)));
-            ScanArgs sa;
-            sa.pos4 = b->pos4;
-            sa.poslo = b->poslo;
-            sa.tab = b->tab;
-            sa.trials = trials;
-            sa.N = b->N;
-            sa.M = b->M;
-            sa.n_pts = b->n_pts;
-            sa.kb = kb;
-            sa.tg = tg;
-            sa.kcap = w.cap_k;
-            sa.rcf2_filter = rcf2_filter;
-            sa.rcf2 = rcf2;
-            sa.tscale = tscale;
-            sa.partial = w.partial;
-            dim3 sgrid(n_jb, (kb + tg - 1) / tg);
-            {
-                ProfScope ps(b, ND_PROF_MC_SCAN);
-                switch (maxnu) {
-                case 1: hipLaunchKernelGGL(k_mc_scan<1>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
-                case 2: hipLaunchKernelGGL(k_mc_scan<2>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
-                case 3: hipLaunchKernelGGL(k_mc_scan<3>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
-                case 4: hipLaunchKernelGGL(k_mc_scan<4>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
-                default: hipLaunchKernelGGL(k_mc_scan<8>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
-                }
-                ND_HIP(hipGetLastError());
-            }
-            hipLaunchKernelGGL(k_mc_reduce, dim3((kb + 255) / 256), dim3(256), 0, b->stream, w.partial, n_jb,
-                               w.cap_k, kb, w.dE0, w.S0);
-            ND_HIP(hipGetLastError());
-            switch (maxnu) {
-            case 1: launch_corr<1>(b, cr); break;
-            case 2: launch_corr<2>(b, cr); break;
-            case 3: launch_corr<3>(b, cr); break;
-            case 4: launch_corr<4>(b, cr); break;
-            default: launch_corr<8>(b, cr); break;
-            }
-        } else {
-            CellScanArgs ca;
-            ca.spos4 = b->cells.spos4;
-            ca.sposlo = b->cells.sposlo;
-            ca.sorted = b->cells.sorted;
-            ca.cstart = b->cells.start;
-            ca.tab = b->tab;
-            ca.trials = trials;
-            ca.drift = b->cells.drift;
-            ca.M = b->M;
-            ca.n_pts = b->n_pts;
-            ca.kb = kb;
-            ca.nc = b->cells.nc;
-            ca.rcf = rcf;
-            ca.rcf2_filter = rcf2_filter;
-            ca.rcf2 = rcf2;
-            ca.tscale = tscale;
-            ca.dE0 = w.dE0;
-            ca.S0 = w.S0;
-            ProposeArgs nx = next;
-            if (!early_propose) nx.kb = 0;
-            switch (maxnu) {
-            case 1: launch_scan_corr<1>(b, ca, cr, nx, lds_tab); break;
-            case 2: launch_scan_corr<2>(b, ca, cr, nx, lds_tab); break;
-            case 3: launch_scan_corr<3>(b, ca, cr, nx, lds_tab); break;
-            case 4: launch_scan_corr<4>(b, ca, cr, nx, lds_tab); break;
-            default: launch_scan_corr<8>(b, ca, cr, nx, lds_tab); break;
-            }
-        }
-
-        DecideArgs da;
-        da.xyz = b->xyz;
-        da.pos4 = b->pos4;
-        da.poslo = b->poslo;
-        da.E = b->E;
-        da.trials = trials;
-        da.dE0 = w.dE0;
-        da.S0 = w.S0;
-        da.corr_n = w.corr_n;
-        da.corr_ptr = w.corr_ptr;
-        da.pool_m = w.pool_m;
-        da.pool_c = w.pool_c;
-        da.corr_s = w.corr_s;
-        da.ovf_fill = w.ovf_fill;
-        const bool cells_live = b->cells.valid;
-        da.cell_slot = cells_live ? b->cells.slot : nullptr;
-        da.spos4 = cells_live ? b->cells.spos4 : nullptr;
-        da.sposlo = cells_live ? b->cells.sposlo : nullptr;
-        da.sref = cells_live ? b->cells.sref : nullptr;
-        da.drift = cells_live ? b->cells.drift : nullptr;
-        da.N = b->N;
-        da.kb = kb;
-        da.kT = p->kT;
-        da.tie_rel = tie_rel;
-        da.counters = w.counters;
-        da.dsum = w.dsum;
-        da.tr_dE = trace && trace->dE ? trace->dE + done : nullptr;
-        da.tr_sabs = trace && trace->sabs ? trace->sabs + done : nullptr;
-        da.tr_acc = trace && trace->accepted ? trace->accepted + done : nullptr;
-        da.tr_unit = trace && trace->unit ? trace->unit + done : nullptr;
-        ProposeArgs late = next;
-        if (early_propose) late.kb = 0;
+        const int kb_next = (int)std::max<int64_t>(0, std::min<int64_t>(K, n - done_next));
+        const ProposeArgs late = proposal_args(b, p, seed, first + (uint64_t)done_next, kb_next, buf ^ 1, K);
+        const int tg = (int)std::max<long long>(1, std::min<long long>(MAX_TG, ((long long)kb * n_jb) / (2LL * ncu)));
+        ScanArgs sa;
+        sa.pos4 = b->pos4;
+        sa.poslo = b->poslo;
+        sa.tab = b->tab;
+        sa.trials = trials;
+        sa.N = b->N;
+        sa.M = b->M;
+        sa.n_pts = b->n_pts;
+        sa.kb = kb;
+        sa.tg = tg;
+        sa.kcap = w.cap_k;
+        sa.rcf2_filter = k.rcf2_filter;
+        sa.rcf2 = k.rcf2;
+        sa.tscale = k.tscale;
+        sa.partial = w.partial;
+        const dim3 sgrid(n_jb, (kb + tg - 1) / tg);
         {
-            ProfScope ps(b, ND_PROF_MC_DECIDE);
+            nd::ProfScope ps(b, ND_PROF_MC_SCAN);
+            switch (maxnu) {
+            case 1: hipLaunchKernelGGL(k_mc_scan<1>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
+            case 2: hipLaunchKernelGGL(k_mc_scan<2>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
+            case 3: hipLaunchKernelGGL(k_mc_scan<3>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
+            case 4: hipLaunchKernelGGL(k_mc_scan<4>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
+            default: hipLaunchKernelGGL(k_mc_scan<8>, sgrid, dim3(SCAN_THREADS), lds_tab, b->stream, sa); break;
+            }
+            ND_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_mc_reduce, dim3((kb + 255) / 256), dim3(256), 0, b->stream, w.partial, n_jb, w.cap_k, kb,
+                           w.dE0, w.S0);
+        ND_HIP(hipGetLastError());
+        switch (maxnu) {
+        case 1: launch_corr<1>(b, cr); break;
+        case 2: launch_corr<2>(b, cr); break;
+        case 3: launch_corr<3>(b, cr); break;
+        case 4: launch_corr<4>(b, cr); break;
+        default: launch_corr<8>(b, cr); break;
+        }
+        // cells kept consistent when they are live from an earlier cell-scan call
+        const DecideArgs da = decide_args(b, p, k, trials, kb, done, trace, b->cells.valid);
+        {
+            nd::ProfScope ps(b, ND_PROF_MC_DECIDE);
             hipLaunchKernelGGL(k_mc_decide, dim3(1), dim3(DEC_THREADS), 0, b->stream, da, late);
             ND_HIP(hipGetLastError());
         }
         if (b->cells.valid) b->cells.trials_since_build += kb;
         done = done_next;
         buf ^= 1;
+    }
+}
+
+}  // namespace
+
+namespace nd {
+
+void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n, const nd_mc_trace *trace)
+{
+    if (p->scan == ND_SCAN_FULL) {
+        mc_run_full(b, p, seed, first, n, trace);
+        return;
+    }
+    McPlan pl;
+    mc_plan_cells(b, p, seed, first, n, trace, false, pl);
+    McWork &w = b->mc;
+    hipLaunchKernelGGL(k_mc_reset, dim3(1), dim3(64), 0, b->stream, w.counters, w.dsum, w.ovf_fill);
+    ND_HIP(hipGetLastError());
+    if (pl.batches.empty()) return;
+    {
+        ProfScope ps(b, ND_PROF_MC_PROPOSE);
+        hipLaunchKernelGGL(k_mc_propose, dim3((pl.first.kb + 63) / 64), dim3(64), 0, b->stream, pl.first);
+        ND_HIP(hipGetLastError());
+    }
+    for (const McLaunch &L : pl.batches) {
+        if (L.rebuild) cells_rebuild_launch(b->stream, b->cells.d_args, 1, b->N, b->cells.ncell);
+        switch (pl.maxnu) {
+        case 1: launch_scan_corr<1>(b, L.ca, L.cr, L.next, pl.lds); break;
+        case 2: launch_scan_corr<2>(b, L.ca, L.cr, L.next, pl.lds); break;
+        case 3: launch_scan_corr<3>(b, L.ca, L.cr, L.next, pl.lds); break;
+        case 4: launch_scan_corr<4>(b, L.ca, L.cr, L.next, pl.lds); break;
+        default: launch_scan_corr<8>(b, L.ca, L.cr, L.next, pl.lds); break;
+        }
+        {
+            ProfScope ps(b, ND_PROF_MC_DECIDE);
+            hipLaunchKernelGGL(k_mc_decide, dim3(1), dim3(DEC_THREADS), 0, b->stream, L.da, L.late);
+            ND_HIP(hipGetLastError());
+        }
+    }
+}
+
+// ---- several boxes in one stream of launches (the batched form)
+struct McMulti {
+    int maxnu = 1, n_rounds = 0, n_first = 0, max_kb0 = 0;
+    size_t lds = 0;
+    std::vector<McLaunch> launches;  // round after round, the active boxes of each
+    std::vector<int> r_off, r_n, r_maxblk;
+    std::vector<CellBuildArgs> cb;   // per round, the boxes whose cells are rebuilt first
+    std::vector<int> cb_off, cb_n, cb_maxn, cb_maxcell;
+    std::vector<ProposeArgs> first;  // first proposals of every box with trials
+    McLaunch *d_launch = nullptr;
+    CellBuildArgs *d_cb = nullptr;
+    ProposeArgs *d_first = nullptr;
+    size_t cap_launch = 0, cap_cb = 0, cap_first = 0;
+};
+
+McMulti *mc_multi_create() { return new McMulti(); }
+
+void mc_multi_destroy(McMulti *m)
+{
+    if (!m) return;
+    dfree(m->d_launch);
+    dfree(m->d_cb);
+    dfree(m->d_first);
+    delete m;
+}
+
+void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *params, const uint64_t *seed,
+                   const uint64_t *first, const int64_t *n_trials, std::vector<long long> &sig)
+{
+    std::vector<McPlan> plans(n);
+    m->maxnu = 1;
+    m->lds = 0;
+    int n_rounds = 0;
+    for (int i = 0; i < n; ++i) {
+        nd_box *b = boxes[i];
+        // every run starts from freshly built cells, so the launch structure
+        // depends only on the trial counts and batch sizes
+        mc_plan_cells(b, &params[i], seed[i], first[i], n_trials[i], nullptr, true, plans[i]);
+        m->maxnu = std::max(m->maxnu, plans[i].maxnu);
+        m->lds = std::max(m->lds, plans[i].lds);
+        n_rounds = std::max(n_rounds, (int)plans[i].batches.size());
+    }
+    m->n_rounds = n_rounds;
+    m->launches.clear();
+    m->r_off.assign(n_rounds, 0);
+    m->r_n.assign(n_rounds, 0);
+    m->r_maxblk.assign(n_rounds, 0);
+    m->cb.clear();
+    m->cb_off.assign(n_rounds, 0);
+    m->cb_n.assign(n_rounds, 0);
+    m->cb_maxn.assign(n_rounds, 0);
+    m->cb_maxcell.assign(n_rounds, 0);
+    m->first.clear();
+    m->max_kb0 = 0;
+    for (int i = 0; i < n; ++i) {
+        if (plans[i].batches.empty()) continue;
+        m->first.push_back(plans[i].first);
+        m->max_kb0 = std::max(m->max_kb0, plans[i].first.kb);
+    }
+    m->n_first = (int)m->first.size();
+    for (int r = 0; r < n_rounds; ++r) {
+        m->r_off[r] = (int)m->launches.size();
+        m->cb_off[r] = (int)m->cb.size();
+        for (int i = 0; i < n; ++i) {
+            if (r >= (int)plans[i].batches.size()) continue;
+            const McLaunch &L = plans[i].batches[r];
+            m->launches.push_back(L);
+            m->r_maxblk[r] = std::max(m->r_maxblk[r], L.nblk);
+            if (L.rebuild) {
+                m->cb.push_back(boxes[i]->cells.args);
+                m->cb_maxn[r] = std::max(m->cb_maxn[r], boxes[i]->N);
+                m->cb_maxcell[r] = std::max(m->cb_maxcell[r], boxes[i]->cells.ncell);
+            }
+        }
+        m->r_n[r] = (int)m->launches.size() - m->r_off[r];
+        m->cb_n[r] = (int)m->cb.size() - m->cb_off[r];
+    }
+    // device copies of the descriptors (grow only; the addresses are part of
+    // the launch structure)
+    auto grow = [](auto *&ptr, size_t &cap, size_t need) {
+        using T = std::remove_reference_t<decltype(*ptr)>;
+        if (cap >= need && ptr) return;
+        dfree(ptr);
+        ptr = static_cast<T *>(dmalloc(sizeof(T) * std::max<size_t>(need, 1)));
+        cap = std::max<size_t>(need, 1);
+    };
+    grow(m->d_launch, m->cap_launch, m->launches.size());
+    grow(m->d_cb, m->cap_cb, m->cb.size());
+    grow(m->d_first, m->cap_first, m->first.size());
+    sig.push_back(0x4d43);
+    sig.push_back(m->maxnu);
+    sig.push_back((long long)m->lds);
+    sig.push_back(n_rounds);
+    sig.push_back(m->n_first);
+    sig.push_back(m->max_kb0);
+    sig.push_back((long long)(uintptr_t)m->d_launch);
+    sig.push_back((long long)(uintptr_t)m->d_cb);
+    sig.push_back((long long)(uintptr_t)m->d_first);
+    for (int r = 0; r < n_rounds; ++r) {
+        sig.push_back(m->r_off[r]);
+        sig.push_back(m->r_n[r]);
+        sig.push_back(m->r_maxblk[r]);
+        sig.push_back(m->cb_off[r]);
+        sig.push_back(m->cb_n[r]);
+        sig.push_back(m->cb_maxn[r]);
+        sig.push_back(m->cb_maxcell[r]);
+    }
+}
+
+void mc_multi_upload(McMulti *m, hipStream_t s)
+{
+    if (!m->launches.empty())
+        ND_HIP(hipMemcpyAsync(m->d_launch, m->launches.data(), sizeof(McLaunch) * m->launches.size(),
+                              hipMemcpyHostToDevice, s));
+    if (!m->cb.empty())
+        ND_HIP(hipMemcpyAsync(m->d_cb, m->cb.data(), sizeof(CellBuildArgs) * m->cb.size(), hipMemcpyHostToDevice, s));
+    if (!m->first.empty())
+        ND_HIP(hipMemcpyAsync(m->d_first, m->first.data(), sizeof(ProposeArgs) * m->first.size(),
+                              hipMemcpyHostToDevice, s));
+    // the host vectors are reused by the next plan: wait for the copies
+    ND_HIP(hipStreamSynchronize(s));
+}
+
+void mc_multi_enqueue(McMulti *m, hipStream_t s)
+{
+    if (m->n_rounds == 0) return;
+    // round 0 holds every box that has trials
+    hipLaunchKernelGGL(k_mc_reset_multi, dim3(1, m->r_n[0]), dim3(64), 0, s, m->d_launch);
+    ND_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_mc_propose_multi, dim3((m->max_kb0 + 63) / 64, m->n_first), dim3(64), 0, s, m->d_first);
+    ND_HIP(hipGetLastError());
+    for (int r = 0; r < m->n_rounds; ++r) {
+        const McLaunch *Lr = m->d_launch + m->r_off[r];
+        if (m->cb_n[r] > 0)
+            cells_rebuild_launch(s, m->d_cb + m->cb_off[r], m->cb_n[r], m->cb_maxn[r], m->cb_maxcell[r]);
+        scan_corr_multi(m->maxnu, s, Lr, m->r_n[r], m->r_maxblk[r], m->lds);
+        hipLaunchKernelGGL(k_mc_decide_multi, dim3(1, m->r_n[r]), dim3(DEC_THREADS), 0, s, Lr);
+        ND_HIP(hipGetLastError());
     }
 }
 

@@ -8,6 +8,7 @@
 // one sine instead of one per pair type.
 #include "nd_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace {
@@ -36,25 +37,47 @@ __global__ void k_gr_normalize(const T *__restrict__ counts, int P, int nbins, d
 
 __device__ __forceinline__ double sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
 
-// one block per Q point, threads over r; the partial-type sum
-// h(k) = r_k^2 dr sum_p w_p (g_p(k) - 1) is formed on the fly
-__global__ __launch_bounds__(256) void k_sq(const double *__restrict__ g, int P, int nbins, double dr, PVec w,
-                                            double four_pi_rho, double self_term, const double *__restrict__ Q,
-                                            double *__restrict__ S)
+// S at one Q point by one block of 256 threads (threads over r); the
+// partial-type sum h(k) = r_k^2 dr sum_p w_p (g_p(k) - 1) is formed on the fly
+__device__ __forceinline__ void sq_point(const double *__restrict__ g, int P, int nbins, double dr, const double *w,
+                                         double four_pi_rho, double self_term, double q, double *out)
 {
     __shared__ double red[256 / 64];
-    const double q = Q[blockIdx.x];
     double s = 0.0;
     for (int k = threadIdx.x; k < nbins; k += 256) {
         const double r = ((double)k + 0.5) * dr;
         double hk = 0.0;
-        for (int p = 0; p < P; ++p) hk += w.v[p] * (g[(size_t)p * nbins + k] - 1.0);
+        for (int p = 0; p < P; ++p) hk += w[p] * (g[(size_t)p * nbins + k] - 1.0);
         s += r * r * dr * hk * sinc(q * r);
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) S[blockIdx.x] = self_term + four_pi_rho * ((red[0] + red[1]) + (red[2] + red[3]));
+    if (threadIdx.x == 0) *out = self_term + four_pi_rho * ((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+// one block per Q point
+__global__ __launch_bounds__(256) void k_sq(const double *__restrict__ g, int P, int nbins, double dr, PVec w,
+                                            double four_pi_rho, double self_term, const double *__restrict__ Q,
+                                            double *__restrict__ S)
+{
+    sq_point(g, P, nbins, dr, w.v, four_pi_rho, self_term, Q[blockIdx.x], S + blockIdx.x);
+}
+
+// Several boxes per launch: blockIdx.y selects the box.
+__global__ void k_gr_normalize_multi(const nd::SqBoxDesc *__restrict__ d)
+{
+    const nd::SqBoxDesc &b = d[blockIdx.y];
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= b.P * b.nbins) return;
+    const int p = q / b.nbins, k = q - p * b.nbins;
+    b.g[q] = (double)b.counts[q] / (b.npairs[p] * shell_volume(k, b.dr) / b.V);
+}
+
+__global__ __launch_bounds__(256) void k_sq_multi(const nd::SqBoxDesc *__restrict__ d, const double *__restrict__ Q)
+{
+    const nd::SqBoxDesc &b = d[blockIdx.y];
+    sq_point(b.g, b.P, b.nbins, b.dr, b.w, b.four_pi_rho, b.self_term, Q[blockIdx.x], b.S + blockIdx.x);
 }
 
 // A_p(k) = [sum_i dLdS_i sinc(Q_i r_k)] w_p 4 pi rho r_k^2 dr / (npairs_p Vshell(k)/V)
@@ -142,6 +165,61 @@ void launch_sq_adjoint(const double *dLdS, int P, int nbins, double dr, double r
     hipLaunchKernelGGL(k_sq_adjoint, dim3(nbins), dim3(256), 0, s, dLdS, Q, nQ, P, nbins, dr, 4.0 * M_PI * rho, V,
                        make_pvec(w_host, P), make_pvec(npairs_host, P), A);
     ND_HIP(hipGetLastError());
+}
+
+// ---- several boxes (the batched form)
+struct SqMulti {
+    std::vector<SqBoxDesc> boxes;
+    SqBoxDesc *d_boxes = nullptr;
+    size_t cap = 0;
+    const double *Q = nullptr;
+    int nQ = 0, max_nq = 0;
+};
+
+SqMulti *sq_multi_create() { return new SqMulti(); }
+
+void sq_multi_destroy(SqMulti *m)
+{
+    if (!m) return;
+    dfree(m->d_boxes);
+    delete m;
+}
+
+void sq_multi_plan(SqMulti *m, const SqBoxDesc *descs, int n, const double *Q, int nQ, std::vector<long long> &sig)
+{
+    m->boxes.assign(descs, descs + n);
+    m->Q = Q;
+    m->nQ = nQ;
+    m->max_nq = 0;
+    for (int i = 0; i < n; ++i) m->max_nq = std::max(m->max_nq, descs[i].P * descs[i].nbins);
+    if (m->cap < (size_t)n || !m->d_boxes) {
+        dfree(m->d_boxes);
+        m->d_boxes = static_cast<SqBoxDesc *>(dmalloc(sizeof(SqBoxDesc) * n));
+        m->cap = n;
+    }
+    sig.push_back(0x5351);
+    sig.push_back(n);
+    sig.push_back(nQ);
+    sig.push_back(m->max_nq);
+    sig.push_back((long long)(uintptr_t)Q);
+    sig.push_back((long long)(uintptr_t)m->d_boxes);
+}
+
+void sq_multi_upload(SqMulti *m, hipStream_t s)
+{
+    ND_HIP(hipMemcpyAsync(m->d_boxes, m->boxes.data(), sizeof(SqBoxDesc) * m->boxes.size(), hipMemcpyHostToDevice, s));
+    ND_HIP(hipStreamSynchronize(s));
+}
+
+void sq_multi_enqueue(SqMulti *m, hipStream_t s)
+{
+    const int n = (int)m->boxes.size();
+    hipLaunchKernelGGL(k_gr_normalize_multi, dim3((m->max_nq + 255) / 256, n), dim3(256), 0, s, m->d_boxes);
+    ND_HIP(hipGetLastError());
+    if (m->nQ > 0) {
+        hipLaunchKernelGGL(k_sq_multi, dim3(m->nQ, n), dim3(256), 0, s, m->d_boxes, m->Q);
+        ND_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace nd

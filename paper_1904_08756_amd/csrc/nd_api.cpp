@@ -90,6 +90,37 @@ void check_box(nd_box *b)
     require(b != nullptr, ND_E_INVALID, "box is NULL");
 }
 
+void check_mc_params(const nd_box *b, const nd_mc_params *p)
+{
+    require(p != nullptr, ND_E_INVALID, "params is NULL");
+    require(std::isfinite(p->kT) && p->kT > 0.0, ND_E_INVALID, "kT must be > 0");
+    require(std::isfinite(p->max_disp) && p->max_disp >= 0.0, ND_E_INVALID, "max_disp must be >= 0");
+    require(std::isfinite(p->max_rot) && p->max_rot >= 0.0, ND_E_INVALID, "max_rot must be >= 0");
+    require(p->max_disp < 0.25 * b->L, ND_E_RANGE, "max_disp must be < L/4");
+    require(p->tie_rel >= 0.0 && std::isfinite(p->tie_rel), ND_E_INVALID, "tie_rel must be >= 0");
+    require(p->k_batch >= 0, ND_E_INVALID, "k_batch must be >= 0");
+    require(p->order == ND_ORDER_SEQ || p->order == ND_ORDER_RANDOM, ND_E_INVALID, "unknown order");
+    require(p->scan == ND_SCAN_CELLS || p->scan == ND_SCAN_FULL, ND_E_INVALID, "unknown scan mode");
+    if (p->order == ND_ORDER_RANDOM) nd::fail(ND_E_UNSUPPORTED, "ND_ORDER_RANDOM is not implemented");
+    require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
+}
+
+void check_hist_range(const nd_box *b, double dr, int32_t nbins)
+{
+    require(std::isfinite(dr) && dr > 0.0, ND_E_INVALID, "dr must be > 0");
+    require(nbins >= 1, ND_E_INVALID, "nbins must be >= 1");
+    require((double)nbins * dr < 0.5 * b->L * (1.0 - 1e-9), ND_E_RANGE, "nbins*dr must be < L/2");
+}
+
+void box_npairs(const nd_box *b, double *npairs)
+{
+    for (int a = 0; a < b->M; ++a)
+        for (int c = a; c < b->M; ++c) {
+            const double na = (double)b->species_count[a], nc = (double)b->species_count[c];
+            npairs[nd::pair_index(a, c, b->M)] = (a == c) ? na * (na - 1.0) / 2.0 : na * nc;
+        }
+}
+
 }  // namespace
 
 namespace nd {
@@ -235,6 +266,37 @@ static void free_box(nd_box *b)
     delete[] b->h_uoff;
     delete[] b->h_species;
     delete b;
+}
+
+// Several boxes run as one graph of launches (the batched form).
+struct nd_batch {
+    std::vector<nd_box *> boxes;
+    int device = 0;
+    hipStream_t stream = nullptr;  // owned; graphs are captured and replayed on it
+    hipEvent_t ev_done = nullptr;
+    std::vector<hipEvent_t> ev_in;  // one per box
+    nd::McMulti *mc = nullptr;
+    nd::HistMulti *hist = nullptr;
+    nd::SqMulti *sq = nullptr;
+    std::vector<long long> sig;     // launch structure of the captured graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    long long captures = 0, launches = 0;
+};
+
+static void free_batch(nd_batch *t)
+{
+    if (!t) return;
+    if (t->stream) (void)hipStreamSynchronize(t->stream);
+    if (t->exec) (void)hipGraphExecDestroy(t->exec);
+    if (t->graph) (void)hipGraphDestroy(t->graph);
+    nd::mc_multi_destroy(t->mc);
+    nd::hist_multi_destroy(t->hist);
+    nd::sq_multi_destroy(t->sq);
+    for (auto e : t->ev_in) (void)hipEventDestroy(e);
+    if (t->ev_done) (void)hipEventDestroy(t->ev_done);
+    if (t->stream) (void)hipStreamDestroy(t->stream);
+    delete t;
 }
 
 extern "C" {
@@ -462,18 +524,8 @@ nd_status nd_mc_sweep(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t 
 {
     return guarded([&] {
         check_box(b);
-        require(p != nullptr, ND_E_INVALID, "params is NULL");
         require(n_trials >= 0, ND_E_INVALID, "n_trials must be >= 0");
-        require(std::isfinite(p->kT) && p->kT > 0.0, ND_E_INVALID, "kT must be > 0");
-        require(std::isfinite(p->max_disp) && p->max_disp >= 0.0, ND_E_INVALID, "max_disp must be >= 0");
-        require(std::isfinite(p->max_rot) && p->max_rot >= 0.0, ND_E_INVALID, "max_rot must be >= 0");
-        require(p->max_disp < 0.25 * b->L, ND_E_RANGE, "max_disp must be < L/4");
-        require(p->tie_rel >= 0.0 && std::isfinite(p->tie_rel), ND_E_INVALID, "tie_rel must be >= 0");
-        require(p->k_batch >= 0, ND_E_INVALID, "k_batch must be >= 0");
-        require(p->order == ND_ORDER_SEQ || p->order == ND_ORDER_RANDOM, ND_E_INVALID, "unknown order");
-        require(p->scan == ND_SCAN_CELLS || p->scan == ND_SCAN_FULL, ND_E_INVALID, "unknown scan mode");
-        if (p->order == ND_ORDER_RANDOM) nd::fail(ND_E_UNSUPPORTED, "ND_ORDER_RANDOM is not implemented");
-        require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
+        check_mc_params(b, p);
         DeviceGuard g(b->device);
         nd::mc_run(b, p, seed, first_trial, n_trials, trace);
         if (stats) {
@@ -497,9 +549,7 @@ nd_status nd_pair_histogram(nd_box *b, double dr, int32_t nbins, uint64_t *count
         check_box(b);
         require(counts != nullptr, ND_E_INVALID, "counts is NULL");
         check_where(where);
-        require(std::isfinite(dr) && dr > 0.0, ND_E_INVALID, "dr must be > 0");
-        require(nbins >= 1, ND_E_INVALID, "nbins must be >= 1");
-        require((double)nbins * dr < 0.5 * b->L * (1.0 - 1e-9), ND_E_RANGE, "nbins*dr must be < L/2");
+        check_hist_range(b, dr, nbins);
         DeviceGuard g(b->device);
         size_t bytes = sizeof(uint64_t) * (size_t)b->P * nbins;
         if (where == ND_DEVICE) {
@@ -568,11 +618,7 @@ nd_status nd_box_pair_counts(nd_box *b, double *npairs)
     return guarded([&] {
         check_box(b);
         require(npairs != nullptr, ND_E_INVALID, "npairs is NULL");
-        for (int a = 0; a < b->M; ++a)
-            for (int c = a; c < b->M; ++c) {
-                const double na = (double)b->species_count[a], nc = (double)b->species_count[c];
-                npairs[nd::pair_index(a, c, b->M)] = (a == c) ? na * (na - 1.0) / 2.0 : na * nc;
-            }
+        box_npairs(b, npairs);
     });
 }
 
@@ -744,6 +790,191 @@ nd_status nd_forces(nd_box *b, double *dEdx, double *E, int32_t where)
             ND_HIP(hipMemcpyAsync(E, de.p, sizeof(double), hipMemcpyDeviceToHost, b->stream));
         }
         ND_HIP(hipStreamSynchronize(b->stream));
+    });
+}
+
+nd_status nd_batch_create(nd_box *const *boxes, int32_t n, nd_batch **out)
+{
+    return guarded([&] {
+        require(out != nullptr, ND_E_INVALID, "out is NULL");
+        *out = nullptr;
+        require(boxes != nullptr && n >= 1, ND_E_INVALID, "boxes is NULL or n < 1");
+        for (int i = 0; i < n; ++i) {
+            check_box(boxes[i]);
+            require(boxes[i]->device == boxes[0]->device, ND_E_INVALID, "boxes are on different devices");
+            require(boxes[i]->M == boxes[0]->M, ND_E_INVALID, "boxes have different species counts");
+            for (int j = 0; j < i; ++j) require(boxes[j] != boxes[i], ND_E_INVALID, "a box appears twice");
+        }
+        DeviceGuard g(boxes[0]->device);
+        nd_batch *t = new nd_batch();
+        try {
+            t->boxes.assign(boxes, boxes + n);
+            t->device = boxes[0]->device;
+            ND_HIP(hipStreamCreateWithFlags(&t->stream, hipStreamNonBlocking));
+            ND_HIP(hipEventCreateWithFlags(&t->ev_done, hipEventDisableTiming));
+            t->ev_in.resize(n, nullptr);
+            for (int i = 0; i < n; ++i) ND_HIP(hipEventCreateWithFlags(&t->ev_in[i], hipEventDisableTiming));
+            t->mc = nd::mc_multi_create();
+            t->hist = nd::hist_multi_create();
+            t->sq = nd::sq_multi_create();
+        } catch (...) {
+            free_batch(t);
+            throw;
+        }
+        *out = t;
+    });
+}
+
+nd_status nd_batch_destroy(nd_batch *t)
+{
+    if (!t) return ND_OK;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(t->device);
+    free_batch(t);
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return ND_OK;
+}
+
+nd_status nd_batch_run(nd_batch *t, const nd_batch_plan *pl, nd_mc_stats *stats)
+{
+    return guarded([&] {
+        require(t != nullptr, ND_E_INVALID, "batch is NULL");
+        require(pl != nullptr, ND_E_INVALID, "plan is NULL");
+        const int n = (int)t->boxes.size();
+        nd_box *const *boxes = t->boxes.data();
+        // ---- validation, before any device work
+        require(pl->sweeps >= 0, ND_E_INVALID, "sweeps must be >= 0");
+        if (pl->sweeps > 0) {
+            require(pl->mc && pl->seed && pl->first_trial, ND_E_INVALID, "mc, seed and first_trial are required");
+            for (int i = 0; i < n; ++i) {
+                check_mc_params(boxes[i], &pl->mc[i]);
+                require(pl->mc[i].scan == ND_SCAN_CELLS, ND_E_UNSUPPORTED, "the batched form runs the cell scan only");
+            }
+        }
+        const bool do_hist = pl->counts != nullptr;
+        const bool do_g = do_hist && pl->g != nullptr;
+        const bool do_s = do_g && pl->S != nullptr && pl->nQ > 0;
+        if (do_hist) {
+            require(pl->nbins != nullptr, ND_E_INVALID, "nbins is NULL");
+            for (int i = 0; i < n; ++i) {
+                check_hist_range(boxes[i], pl->dr, pl->nbins[i]);
+                require(pl->counts[i] != nullptr, ND_E_INVALID, "counts[i] is NULL");
+                if (do_g) require(pl->g[i] != nullptr, ND_E_INVALID, "g[i] is NULL");
+            }
+        }
+        if (do_s) {
+            require(pl->Q && pl->w && pl->self_term, ND_E_INVALID, "Q, w and self_term are required for S");
+            for (int i = 0; i < n; ++i) {
+                require(pl->S[i] != nullptr, ND_E_INVALID, "S[i] is NULL");
+                require(std::isfinite(pl->self_term[i]), ND_E_INVALID, "self_term is not finite");
+                for (int p = 0; p < boxes[i]->P; ++p)
+                    require(std::isfinite(pl->w[(size_t)i * boxes[i]->P + p]), ND_E_INVALID, "w is not finite");
+            }
+        }
+        DeviceGuard g(t->device);
+        hipStream_t s = t->stream;
+        // the previous run has finished reading the descriptors
+        ND_HIP(hipStreamSynchronize(s));
+        // ---- host plan and descriptor upload
+        std::vector<long long> sig;
+        if (pl->sweeps > 0) {
+            std::vector<int64_t> nt(n);
+            for (int i = 0; i < n; ++i) nt[i] = (int64_t)pl->sweeps * boxes[i]->n_units;
+            nd::mc_multi_plan(t->mc, boxes, n, pl->mc, pl->seed, pl->first_trial, nt.data(), sig);
+            nd::mc_multi_upload(t->mc, s);
+        }
+        sig.push_back(-1);
+        if (do_hist) {
+            nd::hist_multi_plan(t->hist, boxes, n, pl->dr, pl->nbins, pl->counts, sig);
+            nd::hist_multi_upload(t->hist, s);
+        }
+        sig.push_back(-2);
+        if (do_g) {
+            std::vector<nd::SqBoxDesc> d(n);
+            for (int i = 0; i < n; ++i) {
+                const nd_box *b = boxes[i];
+                nd::SqBoxDesc &x = d[i];
+                std::memset(&x, 0, sizeof(x));
+                x.counts = pl->counts[i];
+                x.g = pl->g[i];
+                x.S = do_s ? pl->S[i] : nullptr;
+                x.P = b->P;
+                x.nbins = pl->nbins[i];
+                x.dr = pl->dr;
+                x.V = b->L * b->L * b->L;
+                x.four_pi_rho = 4.0 * M_PI * ((double)b->N / x.V);
+                x.self_term = do_s ? pl->self_term[i] : 0.0;
+                box_npairs(b, x.npairs);
+                if (do_s)
+                    for (int p = 0; p < b->P; ++p) x.w[p] = pl->w[(size_t)i * b->P + p];
+            }
+            nd::sq_multi_plan(t->sq, d.data(), n, do_s ? pl->Q : nullptr, do_s ? pl->nQ : 0, sig);
+            nd::sq_multi_upload(t->sq, s);
+        }
+        // ---- order after pending work on the boxes' streams
+        for (int i = 0; i < n; ++i) {
+            ND_HIP(hipEventRecord(t->ev_in[i], boxes[i]->stream));
+            ND_HIP(hipStreamWaitEvent(s, t->ev_in[i], 0));
+        }
+        // ---- capture once per launch structure, then replay
+        if (!t->exec || sig != t->sig) {
+            if (t->exec) {
+                ND_HIP(hipGraphExecDestroy(t->exec));
+                t->exec = nullptr;
+            }
+            if (t->graph) {
+                ND_HIP(hipGraphDestroy(t->graph));
+                t->graph = nullptr;
+            }
+            t->sig.clear();
+            ND_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                if (pl->sweeps > 0) nd::mc_multi_enqueue(t->mc, s);
+                if (do_hist) nd::hist_multi_enqueue(t->hist, s);
+                if (do_g) nd::sq_multi_enqueue(t->sq, s);
+            } catch (...) {
+                hipGraph_t junk = nullptr;
+                (void)hipStreamEndCapture(s, &junk);
+                if (junk) (void)hipGraphDestroy(junk);
+                throw;
+            }
+            ND_HIP(hipStreamEndCapture(s, &t->graph));
+            ND_HIP(hipGraphInstantiate(&t->exec, t->graph, nullptr, nullptr, 0));
+            t->sig = sig;
+            ++t->captures;
+        }
+        ND_HIP(hipGraphLaunch(t->exec, s));
+        ++t->launches;
+        // later work on the boxes' streams comes after the batch
+        ND_HIP(hipEventRecord(t->ev_done, s));
+        for (int i = 0; i < n; ++i) ND_HIP(hipStreamWaitEvent(boxes[i]->stream, t->ev_done, 0));
+        if (stats) {
+            ND_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i < n; ++i) {
+                nd_box *b = boxes[i];
+                nd_mc_stats &st = stats[i];
+                std::memset(&st, 0, sizeof(st));
+                if (pl->sweeps > 0) {
+                    long long c[2];
+                    ND_HIP(hipMemcpy(c, b->mc.counters, sizeof(c), hipMemcpyDeviceToHost));
+                    ND_HIP(hipMemcpy(&st.dE_sum, b->mc.dsum, sizeof(double), hipMemcpyDeviceToHost));
+                    st.trials = (int64_t)pl->sweeps * b->n_units;
+                    st.accepted = c[0];
+                    st.near_ties = c[1];
+                }
+                ND_HIP(hipMemcpy(&st.E_total, b->E, sizeof(double), hipMemcpyDeviceToHost));
+            }
+        }
+    });
+}
+
+nd_status nd_batch_info(const nd_batch *t, int64_t *captures, int64_t *launches)
+{
+    return guarded([&] {
+        require(t != nullptr, ND_E_INVALID, "batch is NULL");
+        if (captures) *captures = t->captures;
+        if (launches) *launches = t->launches;
     });
 }
 

@@ -66,6 +66,20 @@ struct McWork {
     double *dsum = nullptr;       // accepted dE sum
 };
 
+// Device view of one box's cell arrays, read by the cell-build kernels
+// (one descriptor per box, so a launch can rebuild several boxes).
+struct CellBuildArgs {
+    const float4 *pos4, *poslo;
+    int N, nc, ncell, pad;
+    int32_t *cellof;  // [N] cell of each atom
+    int32_t *rank;    // [N] arrival rank inside the cell
+    int32_t *count;   // [ncell] atoms per cell; zero between builds
+    int32_t *start;   // [ncell + 1] first sorted slot of each cell
+    int32_t *sorted, *slot;
+    float4 *spos4, *sposlo, *sref;
+    float *drift;
+};
+
 // Atoms sorted into spatial cells (see k_cells.hip).
 struct Cells {
     int nc = 0, ncell = 0, cap_n = 0;
@@ -75,10 +89,10 @@ struct Cells {
     float4 *spos4 = nullptr;      // [N] current hi + species, sorted order
     float4 *sposlo = nullptr;     // [N] current lo, sorted order
     float4 *sref = nullptr;       // [N] hi at the last rebuild
-    uint64_t *keys_in = nullptr, *keys_out = nullptr;
-    void *sort_tmp = nullptr;
-    size_t sort_tmp_bytes = 0;
+    int32_t *cellof = nullptr, *rank = nullptr, *count = nullptr;
     float *drift = nullptr;       // device: max distance moved since the rebuild (fractional)
+    CellBuildArgs args;           // host copy of the descriptor
+    CellBuildArgs *d_args = nullptr;  // device copy
     bool valid = false;
     long long trials_since_build = 0;
 };
@@ -144,7 +158,51 @@ void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, c
 void launch_forces(nd_box *b, double *d_grad, double *d_E);
 void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n,
             const nd_mc_trace *trace);
+int mc_batch_size(nd_box *b, const nd_mc_params *p);
+
+// Metropolis runs of several boxes as one sequence of launches, each launch
+// covering every box that still has batches (k_mc.hip).  plan: host-side
+// descriptors of every batch of every box (allocates workspaces; appends the
+// launch structure to sig); upload: descriptors to the device (synchronous);
+// enqueue: the launches only, so they can be captured in a graph.
+struct McMulti;
+McMulti *mc_multi_create();
+void mc_multi_destroy(McMulti *m);
+void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *params, const uint64_t *seed,
+                   const uint64_t *first, const int64_t *n_trials, std::vector<long long> &sig);
+void mc_multi_upload(McMulti *m, hipStream_t s);
+void mc_multi_enqueue(McMulti *m, hipStream_t s);
+
+// Pair histograms of several boxes in one persistent launch (k_hist.hip);
+// counts[i] is a device array [P][nbins[i]] of box i, cleared by the launch.
+struct HistMulti;
+HistMulti *hist_multi_create();
+void hist_multi_destroy(HistMulti *m);
+void hist_multi_plan(HistMulti *m, nd_box *const *boxes, int n, double dr, const int32_t *nbins,
+                     uint64_t *const *counts, std::vector<long long> &sig);
+void hist_multi_upload(HistMulti *m, hipStream_t s);
+void hist_multi_enqueue(HistMulti *m, hipStream_t s);
+
+// g(r) and S(Q) of several boxes, one launch each (k_sq.hip).
+constexpr int MAX_PARTIALS = ND_MAX_SPECIES * (ND_MAX_SPECIES + 1) / 2;
+struct SqBoxDesc {
+    const uint64_t *counts;  // [P][nbins]
+    double *g;               // [P][nbins]
+    double *S;               // [nQ]
+    int P, nbins;
+    double dr, V, four_pi_rho, self_term;
+    double npairs[MAX_PARTIALS];
+    double w[MAX_PARTIALS];
+};
+struct SqMulti;
+SqMulti *sq_multi_create();
+void sq_multi_destroy(SqMulti *m);
+void sq_multi_plan(SqMulti *m, const SqBoxDesc *descs, int n, const double *Q, int nQ, std::vector<long long> &sig);
+void sq_multi_upload(SqMulti *m, hipStream_t s);
+void sq_multi_enqueue(SqMulti *m, hipStream_t s);
 void cells_build(nd_box *b);
+void cells_ensure(nd_box *b);
+void cells_rebuild_launch(hipStream_t s, const CellBuildArgs *d_args, int n_boxes, int max_n, int max_ncell);
 void cells_free(nd_box *b);
 
 // device memory helpers

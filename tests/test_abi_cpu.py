@@ -103,6 +103,12 @@ def test_stateless_entry_points_validate(L):
     assert L.nd_pair_histogram(None, 0.1, 10, c.ctypes.data, 0) == -1
     assert L.nd_mc_sweep(None, None, 0, 0, 1, None, None) == -1
     assert L.nd_box_destroy(None) == 0
+    h = C.c_void_p()
+    assert L.nd_batch_create(None, 0, C.byref(h)) == -1 and h.value is None
+    assert L.nd_batch_create(None, 3, C.byref(h)) == -1
+    assert L.nd_batch_run(None, None, None) == -1
+    assert L.nd_batch_info(None, None, None) == -1
+    assert L.nd_batch_destroy(None) == 0
 
 
 def test_product_path_does_not_import_oracle():

@@ -1,0 +1,188 @@
+"""Batched form: several water boxes of uneven size and H/D weighting run as
+one graph of shared launches give, box by box, the results of the plain
+entry points (which the other GPU tests check against the oracle).
+
+Both sides run the same kernels on the same inputs, so coordinates,
+histograms, g(r), energies and acceptance counts agree bit for bit; S(Q)
+is held to the same bound as the plain path (1e-11 of its magnitude scale),
+and is in practice identical.  Every plain call is preceded by a reset of
+the box's cell lists (set_coords with the box's own coordinates), because
+every batched run starts from freshly built cells.
+"""
+import numpy as np
+import pytest
+
+import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+
+# smallest three, two in the middle and the largest two of the 64 sizes
+PICK = (0, 1, 2, 31, 32, 62, 63)
+
+
+@pytest.fixture(scope="module")
+def nd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    import paper_1904_08756_amd as nd
+    nd.lib()
+    return nd
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _subset():
+    boxes, T, mc = syn.config_c4()
+    order = np.argsort([b.n_atoms for b in boxes], kind="stable")
+    return [boxes[int(order[i])] for i in PICK], T, mc
+
+
+def _make(nd, sboxes, T):
+    out = []
+    for sb in sboxes:
+        g = nd.Box.from_synthetic(sb)
+        g.set_tables(T.U, T.h, T.r_cut)
+        g.total_energy()
+        out.append(g)
+    return out
+
+
+class Setup:
+    def __init__(self, nd, sweeps=2):
+        import torch
+        self.sboxes, self.T, mc = _subset()
+        self.mc = mc
+        self.sweeps = sweeps
+        self.params = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"])
+        self.seeds = [mc["seed"] * 1000 + i for i in range(len(self.sboxes))]
+        self.dr = mc["dr"]
+        self.nbins = [sb.meta["nbins"] for sb in self.sboxes]
+        self.Q = torch.as_tensor(syn.q_grid(), device="cuda")
+
+    def weights(self, nd, gboxes):
+        w, st = [], []
+        for sb, g in zip(self.sboxes, gboxes):
+            wi, si = nd.eq1_weights(g, syn.water_b(sb.meta["d_fraction"]))
+            w.append(wi)
+            st.append(si)
+        return np.array(w), np.array(st)
+
+
+def _plain_step(nd, S, gboxes, firsts, w, st):
+    res = []
+    for i, g in enumerate(gboxes):
+        g.set_coords(g.coords(), keep_energy=True)  # fresh cells, as every batched run
+        r = g.mc_sweep(S.params, S.seeds[i], firsts[i], S.sweeps * g.n_units)
+        counts = nd.pair_histogram(g, S.dr, S.nbins[i])
+        V = g.L * g.L * g.L  # the library's own expression for the volume
+        gr = nd.gr_normalize(counts, S.dr, V, nd.pair_counts_total(g))
+        sq = nd.sq_transform(gr, S.dr, g.N / V, w[i], st[i], S.Q)
+        res.append(dict(xyz=g.coords_host(), counts=counts.cpu().numpy(), g=gr.cpu().numpy(),
+                        S=sq.cpu().numpy(), accepted=r["accepted"], E=r["E_total"]))
+    return res
+
+
+def _alloc(nd, S, gboxes):
+    import torch
+    counts = [torch.empty((g.P, nb), dtype=torch.int64, device="cuda") for g, nb in zip(gboxes, S.nbins)]
+    gr = [torch.empty((g.P, nb), dtype=torch.float64, device="cuda") for g, nb in zip(gboxes, S.nbins)]
+    sq = [torch.empty(S.Q.shape[0], dtype=torch.float64, device="cuda") for _ in gboxes]
+    return counts, gr, sq
+
+
+def _batched_step(S, batch, gboxes, firsts, w, st, outs):
+    counts, gr, sq = outs
+    stats = batch.run(S.sweeps, [S.params] * len(gboxes), S.seeds, firsts, S.dr, S.nbins, w, st, S.Q,
+                      counts, gr, sq, stats=True)
+    res = []
+    for i, g in enumerate(gboxes):
+        res.append(dict(xyz=g.coords_host(), counts=counts[i].cpu().numpy(), g=gr[i].cpu().numpy(),
+                        S=sq[i].cpu().numpy(), accepted=stats[i]["accepted"], E=stats[i]["E_total"],
+                        trials=stats[i]["trials"]))
+    return res
+
+
+def _compare(a, b, gboxes, sweeps):
+    for i, (x, y) in enumerate(zip(a, b)):
+        assert y["trials"] == sweeps * gboxes[i].n_units
+        assert np.array_equal(x["xyz"], y["xyz"]), f"box {i}: coordinates differ"
+        assert x["accepted"] == y["accepted"], f"box {i}"
+        assert x["E"] == y["E"], f"box {i}: {x['E']} vs {y['E']}"
+        assert np.array_equal(x["counts"], y["counts"]), f"box {i}: histogram differs"
+        assert np.array_equal(x["g"], y["g"]), f"box {i}: g differs"
+        scale = np.abs(x["S"]).max() + 1.0
+        assert np.max(np.abs(x["S"] - y["S"])) <= 1e-11 * scale, f"box {i}: S differs"
+
+
+def test_batch_sizes_and_weightings(nd):
+    sb, _, _ = _subset()
+    n_atoms = [b.n_atoms for b in sb]
+    say("batch box atoms", n_atoms)
+    assert n_atoms[0] < 2000 and n_atoms[-1] > 40000
+    assert len({b.meta["d_fraction"] for b in sb}) >= 3
+
+
+def test_batch_equals_plain_and_graph_replays(nd):
+    import torch
+    S = Setup(nd)
+    plain = _make(nd, S.sboxes, S.T)
+    batched = _make(nd, S.sboxes, S.T)
+    w, st = S.weights(nd, plain)
+    batch = nd.Batch(batched)
+    outs = _alloc(nd, S, batched)
+    for rep in range(3):
+        firsts = [rep * S.sweeps * g.n_units for g in plain]
+        say(f"batch replay {rep}: plain")
+        a = _plain_step(nd, S, plain, firsts, w, st)
+        say(f"batch replay {rep}: batched")
+        b = _batched_step(S, batch, batched, firsts, w, st, outs)
+        torch.cuda.synchronize()
+        _compare(a, b, batched, S.sweeps)
+        say(f"batch replay {rep}: equal; accepted", [x["accepted"] for x in b])
+    captures, launches = batch.info()
+    assert (captures, launches) == (1, 3)
+    batch.close()
+
+
+def test_batch_histogram_only_and_recapture(nd):
+    import torch
+    S = Setup(nd)
+    gb = _make(nd, S.sboxes[:4], S.T)
+    S.sboxes = S.sboxes[:4]
+    S.nbins = S.nbins[:4]
+    batch = nd.Batch(gb)
+    counts = [torch.empty((g.P, nb), dtype=torch.int64, device="cuda") for g, nb in zip(gb, S.nbins)]
+    say("batch histogram only")
+    batch.run(0, None, None, None, S.dr, S.nbins, counts=counts)
+    torch.cuda.synchronize()
+    for g, c, nb in zip(gb, counts, S.nbins):
+        want = nd.pair_histogram(g, S.dr, nb)
+        assert torch.equal(c, want)
+    # a different bin count changes the launch structure: captured again
+    nb2 = [n - 7 for n in S.nbins]
+    counts2 = [torch.empty((g.P, nb), dtype=torch.int64, device="cuda") for g, nb in zip(gb, nb2)]
+    batch.run(0, None, None, None, S.dr, nb2, counts=counts2)
+    torch.cuda.synchronize()
+    for g, c, nb in zip(gb, counts2, nb2):
+        assert torch.equal(c, nd.pair_histogram(g, S.dr, nb))
+    assert batch.info() == (2, 2)
+    batch.close()
+
+
+def test_batch_rejects_bad_plans(nd):
+    import torch
+    S = Setup(nd)
+    gb = _make(nd, S.sboxes[:2], S.T)
+    batch = nd.Batch(gb)
+    full = nd.MCParams(S.mc["kT"], S.mc["max_disp"], S.mc["max_rot"], scan=nd.ND_SCAN_FULL)
+    with pytest.raises(nd.NeudaError, match="UNSUPPORTED"):
+        batch.run(1, [full, full], [1, 2], [0, 0])
+    counts = [torch.empty((g.P, 10), dtype=torch.int64, device="cuda") for g in gb]
+    with pytest.raises(nd.NeudaError, match="RANGE"):
+        batch.run(0, None, None, None, 0.03, [10, 10 ** 6], counts=counts)
+    with pytest.raises(nd.NeudaError):
+        nd.Batch([gb[0], gb[0]])
+    batch.close()
