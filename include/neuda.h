@@ -249,6 +249,20 @@ nd_status nd_hist_broad_backward(nd_box *box, double dr, int32_t nbins, double s
  * energy E (host double, may be NULL). */
 nd_status nd_forces(nd_box *box, double *dEdx, double *E, int32_t where);
 
+/* Checkpoint of a box's Metropolis state: coordinates, running energy and
+ * (when live) the cell lists, so that a run resumed from the checkpoint
+ * repeats the uninterrupted run bit for bit.  The image is a flat byte
+ * buffer owned by the caller, ending in an FNV-1a 64-bit hash.
+ * nd_box_save with buf = NULL stores the needed size in *len; otherwise
+ * *len is the buffer size on entry and the bytes written on return
+ * (ND_E_INVALID if too small).  Synchronises the box's stream.
+ * nd_box_load restores an image into a box with the same atom count,
+ * species count, unit count and L (tables are not part of the image);
+ * errors: ND_E_INVALID (not an image, other box, truncated, hash mismatch,
+ * corrupt cell order), ND_E_HIP. */
+nd_status nd_box_save(nd_box *box, void *buf, size_t *len);
+nd_status nd_box_load(nd_box *box, const void *buf, size_t len);
+
 /* ---- Batched form: several independent boxes in one graph launch.
  * The boxes may differ in size, box length, tables and Eq. 1 weighting
  * (e.g. isotope substitutions; Sec. "Neutron scattering" and Eq. 1).  One

@@ -110,6 +110,8 @@ EXPORTS = {
     "nd_eq1_weights": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "nd_chi2": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                             C.c_void_p]),
+    "nd_box_save": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
+    "nd_box_load": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "nd_batch_create": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "nd_batch_destroy": (C.c_int32, [C.c_void_p]),
     "nd_batch_run": (C.c_int32, [C.c_void_p, C.POINTER(nd_batch_plan), C.c_void_p]),
@@ -275,6 +277,21 @@ class Box:
         self._sync_stream()
         _check(lib().nd_box_get_coords(self.handle, out.ctypes.data, ND_HOST))
         return out
+
+    def save(self) -> bytes:
+        """Checkpoint image of the box's Metropolis state (nd_box_save)."""
+        self._sync_stream()
+        n = C.c_size_t()
+        _check(lib().nd_box_save(self.handle, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().nd_box_save(self.handle, buf, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def load(self, image: bytes):
+        """Restore a checkpoint made by save() (nd_box_load)."""
+        self._sync_stream()
+        buf = C.create_string_buffer(bytes(image), len(image))
+        _check(lib().nd_box_load(self.handle, buf, len(image)))
 
     def total_energy(self):
         E = C.c_double()

@@ -126,6 +126,17 @@ __global__ __launch_bounds__(CB_THREADS) void k_cb_finish(const nd::CellBuildArg
     }
 }
 
+// Sorted copies of the current positions for a restored slot order.
+__global__ void k_cb_gather(const nd::CellBuildArgs *__restrict__ args)
+{
+    const nd::CellBuildArgs &A = args[blockIdx.y];
+    const int x = blockIdx.x * CB_THREADS + threadIdx.x;
+    if (x >= A.N) return;
+    const int atom = A.sorted[x];
+    A.spos4[x] = A.pos4[atom];
+    A.sposlo[x] = A.poslo[atom];
+}
+
 __global__ void k_fill_i32(int32_t *p, int n, int v)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -216,6 +227,25 @@ void cells_build(nd_box *b)
     cells_rebuild_launch(b->stream, c.d_args, 1, b->N, c.ncell);
     c.valid = true;
     c.trials_since_build = 0;
+}
+
+void cells_restore(nd_box *b, const CellState &st)
+{
+    cells_ensure(b);
+    Cells &c = b->cells;
+    if (st.nc != c.nc) fail(ND_E_INVALID, "checkpoint cell grid does not match the box");
+    const size_t N = (size_t)b->N;
+    ND_HIP(hipMemcpyAsync(c.sorted, st.sorted, sizeof(int32_t) * N, hipMemcpyHostToDevice, b->stream));
+    ND_HIP(hipMemcpyAsync(c.slot, st.slot, sizeof(int32_t) * N, hipMemcpyHostToDevice, b->stream));
+    ND_HIP(hipMemcpyAsync(c.sref, st.sref, sizeof(float4) * N, hipMemcpyHostToDevice, b->stream));
+    ND_HIP(hipMemcpyAsync(c.start, st.start, sizeof(int32_t) * (c.ncell + 1), hipMemcpyHostToDevice, b->stream));
+    ND_HIP(hipMemcpyAsync(c.drift, &st.drift, sizeof(float), hipMemcpyHostToDevice, b->stream));
+    hipLaunchKernelGGL(k_cb_gather, dim3((b->N + CB_THREADS - 1) / CB_THREADS, 1), dim3(CB_THREADS), 0, b->stream,
+                       c.d_args);
+    ND_HIP(hipGetLastError());
+    ND_HIP(hipStreamSynchronize(b->stream));
+    c.valid = true;
+    c.trials_since_build = st.trials_since_build;
 }
 
 }  // namespace nd

@@ -121,6 +121,41 @@ void box_npairs(const nd_box *b, double *npairs)
         }
 }
 
+// ---- checkpoint image (nd_box_save / nd_box_load)
+// Little-endian layout: a fixed header, then the coordinates and, when the
+// cell lists are live, their slot order, start table and rebuild
+// positions, and last an FNV-1a 64-bit hash of everything before it.
+constexpr char CKPT_MAGIC[8] = {'N', 'D', 'B', 'O', 'X', 'C', 'K', '1'};
+
+struct CkptHeader {
+    char magic[8];
+    int32_t version, n_atoms, n_species, n_units;
+    double L;
+    double E;
+    int32_t energy_valid, cells_valid, nc, ncell;
+    int64_t trials_since_build;
+    float drift;
+    int32_t pad;
+};
+
+uint64_t fnv1a(const unsigned char *p, size_t n)
+{
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+size_t ckpt_size(const nd_box *b, bool cells, int ncell)
+{
+    size_t n = sizeof(CkptHeader) + sizeof(float) * 3 * (size_t)b->N;
+    if (cells) n += sizeof(int32_t) * 2 * (size_t)b->N + sizeof(int32_t) * (size_t)(ncell + 1) +
+                    sizeof(float4) * (size_t)b->N;
+    return n + sizeof(uint64_t);
+}
+
 }  // namespace
 
 namespace nd {
@@ -975,6 +1010,117 @@ nd_status nd_batch_info(const nd_batch *t, int64_t *captures, int64_t *launches)
         require(t != nullptr, ND_E_INVALID, "batch is NULL");
         if (captures) *captures = t->captures;
         if (launches) *launches = t->launches;
+    });
+}
+
+nd_status nd_box_save(nd_box *b, void *buf, size_t *len)
+{
+    return guarded([&] {
+        check_box(b);
+        require(len != nullptr, ND_E_INVALID, "len is NULL");
+        const bool cells = b->cells.valid;
+        const size_t need = ckpt_size(b, cells, b->cells.ncell);
+        if (buf == nullptr) {
+            *len = need;
+            return;
+        }
+        require(*len >= need, ND_E_INVALID, "buffer too small for the checkpoint");
+        DeviceGuard g(b->device);
+        ND_HIP(hipStreamSynchronize(b->stream));
+        unsigned char *p = static_cast<unsigned char *>(buf);
+        CkptHeader h;
+        std::memset(&h, 0, sizeof(h));
+        std::memcpy(h.magic, CKPT_MAGIC, 8);
+        h.version = 1;
+        h.n_atoms = b->N;
+        h.n_species = b->M;
+        h.n_units = b->n_units;
+        h.L = b->L;
+        ND_HIP(hipMemcpy(&h.E, b->E, sizeof(double), hipMemcpyDeviceToHost));
+        h.energy_valid = b->energy_valid ? 1 : 0;
+        h.cells_valid = cells ? 1 : 0;
+        h.nc = cells ? b->cells.nc : 0;
+        h.ncell = cells ? b->cells.ncell : 0;
+        h.trials_since_build = cells ? b->cells.trials_since_build : 0;
+        if (cells) ND_HIP(hipMemcpy(&h.drift, b->cells.drift, sizeof(float), hipMemcpyDeviceToHost));
+        std::memcpy(p, &h, sizeof(h));
+        size_t off = sizeof(h);
+        const size_t N = (size_t)b->N;
+        ND_HIP(hipMemcpy(p + off, b->xyz, sizeof(float) * 3 * N, hipMemcpyDeviceToHost));
+        off += sizeof(float) * 3 * N;
+        if (cells) {
+            const nd::Cells &c = b->cells;
+            ND_HIP(hipMemcpy(p + off, c.sorted, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+            off += sizeof(int32_t) * N;
+            ND_HIP(hipMemcpy(p + off, c.slot, sizeof(int32_t) * N, hipMemcpyDeviceToHost));
+            off += sizeof(int32_t) * N;
+            ND_HIP(hipMemcpy(p + off, c.start, sizeof(int32_t) * (c.ncell + 1), hipMemcpyDeviceToHost));
+            off += sizeof(int32_t) * (c.ncell + 1);
+            ND_HIP(hipMemcpy(p + off, c.sref, sizeof(float4) * N, hipMemcpyDeviceToHost));
+            off += sizeof(float4) * N;
+        }
+        const uint64_t hash = fnv1a(p, off);
+        std::memcpy(p + off, &hash, sizeof(hash));
+        *len = off + sizeof(hash);
+    });
+}
+
+nd_status nd_box_load(nd_box *b, const void *buf, size_t len)
+{
+    return guarded([&] {
+        check_box(b);
+        require(buf != nullptr, ND_E_INVALID, "buffer is NULL");
+        const unsigned char *p = static_cast<const unsigned char *>(buf);
+        require(len >= sizeof(CkptHeader) + sizeof(uint64_t), ND_E_INVALID, "checkpoint truncated");
+        CkptHeader h;
+        std::memcpy(&h, p, sizeof(h));
+        require(std::memcmp(h.magic, CKPT_MAGIC, 8) == 0 && h.version == 1, ND_E_INVALID, "not a box checkpoint");
+        require(h.n_atoms == b->N && h.n_species == b->M && h.n_units == b->n_units && h.L == b->L,
+                ND_E_INVALID, "checkpoint is of a different box");
+        const bool cells = h.cells_valid != 0;
+        require(!cells || (h.ncell == h.nc * h.nc * h.nc && h.nc >= 1), ND_E_INVALID, "bad cell grid");
+        const size_t need = ckpt_size(b, cells, h.ncell);
+        require(len >= need, ND_E_INVALID, "checkpoint truncated");
+        uint64_t hash;
+        std::memcpy(&hash, p + need - sizeof(hash), sizeof(hash));
+        require(hash == fnv1a(p, need - sizeof(hash)), ND_E_INVALID, "checkpoint hash mismatch");
+        const size_t N = (size_t)b->N;
+        const float *xyz = reinterpret_cast<const float *>(p + sizeof(h));
+        validate_xyz_host(xyz, b->N, b->L);
+        DeviceGuard g(b->device);
+        ND_HIP(hipStreamSynchronize(b->stream));
+        ND_HIP(hipMemcpy(b->xyz, xyz, sizeof(float) * 3 * N, hipMemcpyHostToDevice));
+        nd::launch_pos4_from_xyz(b);
+        ND_HIP(hipMemcpyAsync(b->E, &h.E, sizeof(double), hipMemcpyHostToDevice, b->stream));
+        ND_HIP(hipStreamSynchronize(b->stream));
+        b->energy_valid = h.energy_valid != 0;
+        b->cells.valid = false;
+        if (cells) {
+            size_t off = sizeof(h) + sizeof(float) * 3 * N;
+            nd::CellState st;
+            st.nc = h.nc;
+            st.trials_since_build = h.trials_since_build;
+            st.drift = h.drift;
+            st.sorted = reinterpret_cast<const int32_t *>(p + off);
+            off += sizeof(int32_t) * N;
+            st.slot = reinterpret_cast<const int32_t *>(p + off);
+            off += sizeof(int32_t) * N;
+            st.start = reinterpret_cast<const int32_t *>(p + off);
+            off += sizeof(int32_t) * (h.ncell + 1);
+            st.sref = reinterpret_cast<const float4 *>(p + off);
+            // a permutation with matching inverse, and a monotone start table
+            std::vector<char> seen(N, 0);
+            for (size_t x = 0; x < N; ++x) {
+                const int32_t a = st.sorted[x];
+                require(a >= 0 && (size_t)a < N && !seen[a] && st.slot[a] == (int32_t)x, ND_E_INVALID,
+                        "checkpoint cell order is corrupt");
+                seen[a] = 1;
+            }
+            require(st.start[0] == 0 && st.start[h.ncell] == b->N, ND_E_INVALID, "checkpoint cell table is corrupt");
+            for (int c = 0; c < h.ncell; ++c)
+                require(st.start[c] <= st.start[c + 1], ND_E_INVALID, "checkpoint cell table is corrupt");
+            nd::cells_restore(b, st);
+        }
     });
 }
 

@@ -204,6 +204,15 @@ void cells_build(nd_box *b);
 void cells_ensure(nd_box *b);
 void cells_rebuild_launch(hipStream_t s, const CellBuildArgs *d_args, int n_boxes, int max_n, int max_ncell);
 void cells_free(nd_box *b);
+// Host image of a box's cell lists (checkpoint).
+struct CellState {
+    int nc;
+    long long trials_since_build;
+    float drift;
+    const int32_t *sorted, *slot, *start;  // [N], [N], [ncell + 1]
+    const float4 *sref;                    // [N]
+};
+void cells_restore(nd_box *b, const CellState &st);
 
 // device memory helpers
 void *dmalloc(size_t bytes);

@@ -109,6 +109,9 @@ def test_stateless_entry_points_validate(L):
     assert L.nd_batch_run(None, None, None) == -1
     assert L.nd_batch_info(None, None, None) == -1
     assert L.nd_batch_destroy(None) == 0
+    n = C.c_size_t(0)
+    assert L.nd_box_save(None, None, C.byref(n)) == -1
+    assert L.nd_box_load(None, None, 0) == -1
 
 
 def test_product_path_does_not_import_oracle():
