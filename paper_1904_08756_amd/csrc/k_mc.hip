@@ -713,9 +713,8 @@ __global__ __launch_bounds__(256) void k_mc_scan_corr(CellScanArgs a, CorrArgs c
 }
 
 // ---------------------------------------------------------------- decide
-constexpr int DEC_THREADS = 512;
+constexpr int DEC_THREADS = 1024;
 constexpr int DEC_POOL_LDS = 7168;  // correction entries staged in LDS
-constexpr int DEC_UNROLL = 8;
 
 struct DecideArgs {
     float *xyz;
@@ -733,7 +732,7 @@ struct DecideArgs {
     float4 *spos4, *sposlo;
     const float4 *sref;
     float *drift;
-    int N, kb;
+    int N, kb, max_na;
     double kT, tie_rel;
     long long *counters;  // [0] accepted, [1] near ties
     double *dsum;
@@ -775,22 +774,33 @@ __device__ __forceinline__ double accept_threshold(double u, double kT)
     return u > 0.0 ? -kT * log(u) : 745.13321910194122 * kT;
 }
 
-constexpr int DEC_INTRA = 8;  // intra-chunk correction entries kept in registers per trial
+__device__ __forceinline__ bool metropolis(double e, double thr) { return e <= 0.0 || e < thr; }
 
-// Decide batch b (acc_k = metropolis(dE0_k + sum_{m<k} acc_m C_km) in trial
-// order) and commit it.  One wave walks the batch in chunks of 64 trials:
-// terms from earlier chunks are final and added in parallel; inside a chunk,
-// lanes whose dependencies are all decided decide together, round by round.
+constexpr unsigned char ST_OPEN = 0, ST_REJ = 1, ST_ACC = 2;
+
+// Decide batch b -- acc_k = metropolis(dE0_k + sum_{m<k} acc_m C_km), which
+// is the sequential chain -- and commit it.
+//
+// Passes over all open trials at once: a trial whose earlier interacting
+// trials are all decided gets its exact dE and is decided; otherwise its
+// dE lies between the sums with the open terms' negative (resp. positive)
+// parts, and when the test gives the same answer at both ends (with a
+// margin far above the rounding of the sums) that is its decision whatever
+// the open trials do.  Every pass decides at least the earliest open trial,
+// so the loop ends; decisions do not depend on the pass in which they are
+// made, so the result is deterministic and equals the in-order chain.
 // When `next.kb` > 0 the next batch is proposed afterwards (used when its
 // units may overlap this batch's).
 __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeArgs &next)
 {
-    __shared__ double s_e[KMAX];
-    __shared__ double s_u[KMAX];  // acceptance threshold -kT ln u
-    __shared__ int s_off[KMAX];
+    __shared__ double s_e[KMAX];     // dE0, then the final dE
+    __shared__ double s_u[KMAX];     // acceptance threshold -kT ln u
+    __shared__ int s_off[KMAX];      // first entry of trial k in the LDS pool
     __shared__ int s_n[KMAX];
-    __shared__ int s_ptr[KMAX];
-    __shared__ unsigned char s_acc[KMAX];
+    __shared__ int s_ptr[KMAX];      // first entry of trial k in the global pool
+    __shared__ int s_a0[KMAX];
+    __shared__ unsigned char s_st[KMAX];
+    __shared__ unsigned char s_nx[KMAX];
     __shared__ int s_pm[DEC_POOL_LDS];
     __shared__ double s_pc[DEC_POOL_LDS];
     __shared__ int s_wave[DEC_THREADS / 64 + 1];
@@ -801,15 +811,17 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
     const int kb = a.kb;
 
     if (kb > 0) {
-        // stage per-trial data: each thread owns trials tid, tid + DEC_THREADS, ...
+        // stage per-trial data; each thread owns trials tid, tid + DEC_THREADS, ...
         int my_n = 0;
         for (int k = tid; k < kb; k += DEC_THREADS) {
             const int n = a.corr_n[k];
+            const int4 ids = *reinterpret_cast<const int4 *>(&a.trials[k].unit);
             s_n[k] = n;
             s_ptr[k] = a.corr_ptr[k];
             s_e[k] = a.dE0[k];
-            s_u[k] = accept_threshold(a.trials[k].u_acc, a.kT);  // -kT ln u
-            s_acc[k] = 0;
+            s_u[k] = accept_threshold(a.trials[k].u_acc, a.kT);
+            s_a0[k] = ids.y;
+            s_st[k] = ST_OPEN;
             my_n += n;
         }
         const int my_off = block_exscan(my_n, s_wave);
@@ -817,172 +829,121 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
         for (int k = tid; k < kb; k += DEC_THREADS) {
             const int n = s_n[k], ptr = s_ptr[k];
             s_off[k] = o;
-            for (int i0 = 0; i0 < n && o + i0 < DEC_POOL_LDS; i0 += DEC_UNROLL) {
-                int mm[DEC_UNROLL];
-                double cc[DEC_UNROLL];
-#pragma unroll
-                for (int j = 0; j < DEC_UNROLL; ++j) {
-                    if (i0 + j < n) {
-                        mm[j] = a.pool_m[ptr + i0 + j];
-                        cc[j] = a.pool_c[ptr + i0 + j];
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < DEC_UNROLL; ++j) {
-                    if (i0 + j < n && o + i0 + j < DEC_POOL_LDS) {
-                        s_pm[o + i0 + j] = mm[j];
-                        s_pc[o + i0 + j] = cc[j];
-                    }
-                }
+            for (int i = 0; i < n && o + i < DEC_POOL_LDS; ++i) {
+                s_pm[o + i] = a.pool_m[ptr + i];
+                s_pc[o + i] = a.pool_c[ptr + i];
             }
             o += n;
         }
         __syncthreads();
         if (tid == 0) *a.ovf_fill = 0;  // overflow area is free for the next batch
 
-        if (wave == 0) {
-            for (int c0 = 0; c0 < kb; c0 += 64) {
-                const int k = c0 + lane;
-                const bool valid = k < kb;
-                double e = 0.0, thr = 0.0;
-                int n = 0, off = 0, ptr = 0, ni = 0;
-                bool spill = false;
-                unsigned long long dep = 0ull;
-                int im[DEC_INTRA];
-                double ic[DEC_INTRA];
-#pragma unroll
-                for (int j = 0; j < DEC_INTRA; ++j) {
-                    im[j] = 0;
-                    ic[j] = 0.0;
-                }
-                if (valid) {
-                    e = s_e[k];
-                    thr = s_u[k];
-                    n = s_n[k];
-                    off = s_off[k];
-                    ptr = s_ptr[k];
-                }
-                const bool fast = off + n <= DEC_POOL_LDS;
-                // terms from earlier chunks are final; entries inside this
-                // chunk are kept (lane index, C) for the rounds below
-                for (int i0 = 0; i0 < n; i0 += DEC_UNROLL) {
-                    int mm[DEC_UNROLL];
-                    double cc[DEC_UNROLL];
-                    if (fast) {
-                        // all entries in LDS: clamped indices, no branches
-#pragma unroll
-                        for (int j = 0; j < DEC_UNROLL; ++j) {
-                            const int i = off + min(i0 + j, n - 1);
-                            mm[j] = s_pm[i];
-                            cc[j] = s_pc[i];
-                        }
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < DEC_UNROLL; ++j) {
-                            const int i = min(i0 + j, n - 1);
-                            if (off + i < DEC_POOL_LDS) {
-                                mm[j] = s_pm[off + i];
-                                cc[j] = s_pc[off + i];
-                            } else {
-                                mm[j] = a.pool_m[ptr + i];
-                                cc[j] = a.pool_c[ptr + i];
-                            }
-                        }
-                    }
-                    unsigned char av[DEC_UNROLL];
-#pragma unroll
-                    for (int j = 0; j < DEC_UNROLL; ++j) av[j] = s_acc[min(max(mm[j], 0), KMAX - 1)];
-#pragma unroll
-                    for (int j = 0; j < DEC_UNROLL; ++j) {
-                        const int m = mm[j];
-                        if (i0 + j >= n) continue;
-                        if (m >= 0 && m < c0) {
-                            if (av[j]) e += cc[j];
-                        } else if (m >= c0) {
-                            dep |= 1ull << (m - c0);
-                            if (ni < DEC_INTRA) {
-#pragma unroll
-                                for (int q = 0; q < DEC_INTRA; ++q)
-                                    if (q == ni) {
-                                        im[q] = m - c0;
-                                        ic[q] = cc[j];
-                                    }
-                                ++ni;
-                            } else {
-                                spill = true;
-                            }
-                        }
-                    }
-                }
-                unsigned long long resolved = __ballot(!valid);
-                unsigned long long accmask = 0ull;
-                while (resolved != ~0ull) {
-                    const bool ready = valid && !((resolved >> lane) & 1ull) && ((dep & ~resolved) == 0ull);
-                    bool acc = false;
-                    if (ready) {
-                        if (!spill) {
-#pragma unroll
-                            for (int q = 0; q < DEC_INTRA; ++q)
-                                if (q < ni && ((accmask >> im[q]) & 1ull)) e += ic[q];
-                        } else {
-                            for (int i = 0; i < n; ++i) {
-                                const bool in_lds = off + i < DEC_POOL_LDS;
-                                const int m = in_lds ? s_pm[off + i] : a.pool_m[ptr + i];
-                                if (m >= c0 && ((accmask >> (m - c0)) & 1ull))
-                                    e += in_lds ? s_pc[off + i] : a.pool_c[ptr + i];
-                            }
-                        }
-                        acc = (e <= 0.0) || (e < thr);
-                        s_acc[k] = acc ? 1 : 0;
-                        s_e[k] = e;
-                    }
-                    accmask |= __ballot(ready && acc);
-                    resolved |= __ballot(ready);
-                }
+        // entry i of trial k: from LDS when staged, else from the global pool
+        auto entry = [&](int k, int i, int &m, double &c) {
+            const int li = s_off[k] + i;
+            if (li < DEC_POOL_LDS) {
+                m = s_pm[li];
+                c = s_pc[li];
+            } else {
+                m = a.pool_m[s_ptr[k] + i];
+                c = a.pool_c[s_ptr[k] + i];
             }
-        }
-        __syncthreads();
+        };
 
-        // commit, trace, counters
+        for (;;) {
+            int open_left = 0;
+            for (int k = tid; k < kb; k += DEC_THREADS) {
+                if (s_st[k] != ST_OPEN) continue;
+                const int n = s_n[k];
+                double e = s_e[k], lo = 0.0, hi = 0.0, mag = fabs(e);
+                bool all = true;
+                for (int i = 0; i < n; ++i) {
+                    int m;
+                    double c;
+                    entry(k, i, m, c);
+                    if (m < 0) continue;
+                    const unsigned char st = s_st[m];
+                    if (st == ST_ACC) {
+                        e += c;
+                    } else if (st == ST_OPEN) {
+                        all = false;
+                        if (c < 0.0) lo += c; else hi += c;
+                    }
+                    mag += fabs(c);
+                }
+                const double thr = s_u[k];
+                unsigned char d = ST_OPEN;
+                if (all) {
+                    d = metropolis(e, thr) ? ST_ACC : ST_REJ;
+                } else {
+                    const double eps = 1e-12 * mag;
+                    const bool alo = metropolis(e + lo - eps, thr), ahi = metropolis(e + hi + eps, thr);
+                    if (alo == ahi) d = alo ? ST_ACC : ST_REJ;
+                }
+                s_nx[k] = d;
+                open_left |= (d == ST_OPEN);
+            }
+            __syncthreads();
+            for (int k = tid; k < kb; k += DEC_THREADS)
+                if (s_st[k] == ST_OPEN) s_st[k] = s_nx[k];
+            if (!__syncthreads_or(open_left)) break;
+        }
+
+        // final dE (the same in-order sum as an exact decision), counters, trace
         double dsum = 0.0;
         long long nacc = 0, ntie = 0;
-        float dmax = 0.0f;
         for (int k = tid; k < kb; k += DEC_THREADS) {
-            const double e = s_e[k];
+            double e = s_e[k];
+            const int n = s_n[k];
+            for (int i = 0; i < n; ++i) {
+                int m;
+                double c;
+                entry(k, i, m, c);
+                if (m >= 0 && s_st[m] == ST_ACC) e += c;
+            }
+            s_e[k] = e;
+            const bool acc = s_st[k] == ST_ACC;
             const double S = a.S0[k] + (double)a.corr_s[k];
-            const bool acc = s_acc[k] != 0;
-            // |ln u + dE/kT| < tie_rel S / kT, i.e. |dE - (-kT ln u)| < tie_rel S
-            if (a.trials[k].u_acc > 0.0 && fabs(e - s_u[k]) < a.tie_rel * S) ++ntie;
-            const nd::Trial &T = a.trials[k];
+            const double thr = s_u[k];
+            // |ln u + dE/kT| < tie_rel S / kT, i.e. |dE - (-kT ln u)| < tie_rel S (u > 0)
+            if (thr != 745.13321910194122 * a.kT && fabs(e - thr) < a.tie_rel * S) ++ntie;
             if (acc) {
                 ++nacc;
                 dsum += e;
-                for (int at = 0; at < T.na; ++at) {
-                    const int i = T.a0 + at;
-                    const float4 hi = T.new_hi[at];
-                    const float4 lo = T.new_lo[at];
-                    a.xyz[i] = T.new_x[at][0];
-                    a.xyz[a.N + i] = T.new_x[at][1];
-                    a.xyz[2 * a.N + i] = T.new_x[at][2];
-                    a.pos4[i] = hi;
-                    a.poslo[i] = lo;
-                    if (a.cell_slot) {
-                        const int sl = a.cell_slot[i];
-                        a.spos4[sl] = hi;
-                        a.sposlo[sl] = lo;
-                        const float4 r = a.sref[sl];
-                        float dx = hi.x - r.x, dy = hi.y - r.y, dz = hi.z - r.z;
-                        dx -= rintf(dx);
-                        dy -= rintf(dy);
-                        dz -= rintf(dz);
-                        dmax = fmaxf(dmax, sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1e-6f);
-                    }
-                }
             }
             if (a.tr_dE) a.tr_dE[k] = e;
             if (a.tr_sabs) a.tr_sabs[k] = S;
             if (a.tr_acc) a.tr_acc[k] = acc ? 1 : 0;
-            if (a.tr_unit) a.tr_unit[k] = T.unit;
+            if (a.tr_unit) a.tr_unit[k] = a.trials[k].unit;
+        }
+        // commit: one item per (trial, atom)
+        float dmax = 0.0f;
+        const int max_na = a.max_na;
+        for (int it = tid; it < kb * max_na; it += DEC_THREADS) {
+            const int k = it / max_na, at = it - k * max_na;
+            if (s_st[k] != ST_ACC) continue;
+            const nd::Trial &T = a.trials[k];
+            if (at >= T.na) continue;
+            const int i = s_a0[k] + at;
+            const float4 hi = T.new_hi[at];
+            const float4 lo = T.new_lo[at];
+            const float x0 = T.new_x[at][0], x1 = T.new_x[at][1], x2 = T.new_x[at][2];
+            a.xyz[i] = x0;
+            a.xyz[a.N + i] = x1;
+            a.xyz[2 * a.N + i] = x2;
+            a.pos4[i] = hi;
+            a.poslo[i] = lo;
+            if (a.cell_slot) {
+                const int sl = a.cell_slot[i];
+                a.spos4[sl] = hi;
+                a.sposlo[sl] = lo;
+                const float4 r = a.sref[sl];
+                float dx = hi.x - r.x, dy = hi.y - r.y, dz = hi.z - r.z;
+                dx -= rintf(dx);
+                dy -= rintf(dy);
+                dz -= rintf(dz);
+                dmax = fmaxf(dmax, sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1e-6f);
+            }
         }
         for (int o2 = 32; o2 > 0; o2 >>= 1) {
             dsum += __shfl_xor(dsum, o2);
@@ -1263,6 +1224,7 @@ DecideArgs decide_args(const nd_box *b, const nd_mc_params *p, const McConsts &k
     da.sref = cells_live ? b->cells.sref : nullptr;
     da.drift = cells_live ? b->cells.drift : nullptr;
     da.N = b->N;
+    da.max_na = b->max_na;
     da.kb = kb;
     da.kT = p->kT;
     da.tie_rel = k.tie_rel;
