@@ -37,6 +37,7 @@ constexpr int SCAN_JPT = 8;                         // j atoms held per thread
 constexpr int SCAN_JB = SCAN_THREADS * SCAN_JPT;    // atoms per j-block
 constexpr int MAX_TG = 64;                          // trials per scan block
 constexpr int KMAX = 2048;                          // trials per batch
+constexpr int N_SLAB = 8;                           // spatial slabs along z, one per XCD
 constexpr double TWO_PI = 6.283185307179586;
 
 // ---------------------------------------------------------------- RNG
@@ -81,9 +82,10 @@ struct ProposeArgs {
     int N, n_units;
     double L, invL, max_disp, max_rot;
     uint64_t seed, t0;
-    int kb;
+    int kb, kcap;
     nd::Trial *trials;
     float4 *spheres;
+    int32_t *slab;  // [N_SLAB] counts (zero beforehand), then [N_SLAB][kcap] trial lists
 };
 
 // One thread per trial: translation tau = d (2u - 1) per axis; for units of
@@ -202,6 +204,11 @@ __device__ __forceinline__ void propose_one(const ProposeArgs &a, int k)
     T->cen[2] = cz;
     T->rad = rad;
     a.spheres[k] = make_float4(cx, cy, cz, rad);
+    // z-slab of the centre, for the XCD-aware assignment of scan blocks
+    const float zw = cz - floorf(cz);
+    const int sb = min(max((int)(zw * (float)N_SLAB), 0), N_SLAB - 1);
+    const int pos = atomicAdd(&a.slab[sb], 1);
+    a.slab[N_SLAB + sb * a.kcap + pos] = k;
 }
 
 __global__ __launch_bounds__(64) void k_mc_propose(ProposeArgs a)
@@ -336,9 +343,29 @@ __global__ void k_mc_reduce(const double *__restrict__ partial, int n_jb, int kc
     S0[k] = s;
 }
 
+// Exact pair energy from the FP64 fractional displacement d = s_j - s_a
+// (the same arithmetic as pair_u_exact); false beyond r_cut.
+__device__ __forceinline__ bool pair_u_disp(const PairCtx &c, double ex, double ey, double ez, int row, float &u)
+{
+    ex -= rint(ex);
+    ey -= rint(ey);
+    ez -= rint(ez);
+    const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
+    if (!(r2 < c.rcf2)) return false;
+    const double t = sqrt(r2) * c.tscale;
+    int i0 = (int)t;
+    i0 = min(i0, c.n_pts - 2);
+    const float f = (float)(t - (double)i0);
+    const float *tr = c.tab + row;
+    const float u0 = tr[i0];
+    const float u1 = tr[i0 + 1];
+    u = fmaf(f, u1 - u0, u0);
+    return true;
+}
+
 // ---------------------------------------------------------------- corrections
 constexpr int CORR_CAP = 24;  // fixed entry slots per trial (more go to an overflow area)
-constexpr int CORR_TPB = 8;   // trials per correction block (two per wave)
+constexpr int CORR_TPB = 4;   // trials per correction block (one per wave)
 
 struct CorrArgs {
     const float *tab;  // table rows read through the caches
@@ -365,19 +392,77 @@ __device__ __forceinline__ bool spheres_meet(float4 A, float4 B, float rcf)
     return dx * dx + dy * dy + dz * dz < lim * lim;
 }
 
-// One wave: the entries (m, C_km, S_km) of trial k for every earlier trial m
-// of the batch whose bounding sphere comes within r_cut of k's, in increasing
-// m; each C_km = [U(k',m') - U(k,m')] - [U(k',m) - U(k,m)] is evaluated by the
-// whole wave, one lane per (atom of k, atom of m, old/new combination).
+constexpr int CORR_LIST = 192;  // hits buffered per wave
+
+// Per-wave LDS scratch of the correction step: the hit list and trial k's
+// atoms (FP64 fractional positions and species, old at 2a, new at 2a + 1).
+struct CorrScratch {
+    int wl[CORR_LIST];
+    double x[2 * ND_MAX_UNIT_ATOMS], y[2 * ND_MAX_UNIT_ATOMS], z[2 * ND_MAX_UNIT_ATOMS];
+    int sp[2 * ND_MAX_UNIT_ATOMS];
+};
+
+// C_km = [U(k',m') - U(k,m')] - [U(k',m) - U(k,m)] (and the sum of |U| of its
+// terms) for the hit m of this lane; pair terms by the exact path.
 template <int MAXNU>
-__device__ void corr_trial(const CorrArgs &a, const PairCtx &c, int k, int lane)
+__device__ __forceinline__ void corr_pair(const CorrArgs &a, const PairCtx &c, const CorrScratch &cs, int nak, int m,
+                                          double &C, double &S)
 {
+    const nd::Trial *Tm = a.trials + m;
+    const int nam = Tm->na;
+    float4 mh[2 * MAXNU], ml[2 * MAXNU];
+#pragma unroll
+    for (int y = 0; y < MAXNU; ++y) {
+        if (y < nam) {
+            mh[2 * y] = Tm->old_hi[y];
+            ml[2 * y] = Tm->old_lo[y];
+            mh[2 * y + 1] = Tm->new_hi[y];
+            ml[2 * y + 1] = Tm->new_lo[y];
+        }
+    }
+    C = 0.0;
+    S = 0.0;
+#pragma unroll
+    for (int y = 0; y < MAXNU; ++y) {
+        if (y >= nam) continue;
+#pragma unroll
+        for (int om = 0; om < 2; ++om) {  // om 0: m old, 1: m new
+            const float4 q = mh[2 * y + om], ql = ml[2 * y + om];
+            const double qx = (double)q.x + (double)ql.x, qy = (double)q.y + (double)ql.y,
+                         qz = (double)q.z + (double)ql.z;
+            const int sq = __float_as_int(q.w);
+            for (int x = 0; x < nak; ++x) {
+#pragma unroll
+                for (int ok = 0; ok < 2; ++ok) {  // ok 0: k old, 1: k new
+                    const int ia = 2 * x + ok;
+                    float u;
+                    if (pair_u_disp(c, qx - cs.x[ia], qy - cs.y[ia], qz - cs.z[ia], c.prow[cs.sp[ia] * c.M + sq], u)) {
+                        // + (k', m') and (k, m); - (k, m') and (k', m)
+                        C += (ok == om) ? (double)u : -(double)u;
+                        S += (double)fabsf(u);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// One wave: the entries (m, C_km) of trial k for every earlier trial m of
+// the batch whose bounding sphere comes within r_cut of k's, in increasing
+// m.  The hits are collected 64 at a time and each lane evaluates one hit,
+// so the pair terms of all hits are computed at once.
+template <int MAXNU>
+__device__ void corr_trial(const CorrArgs &a, const PairCtx &c, int k, int lane, CorrScratch &cs)
+{
+    const unsigned long long lt = (1ull << lane) - 1ull;
     const float4 A = a.spheres[k];
     int n = 0;
-    for (int m0 = 0; m0 < k; m0 += 64) {
-        const int m = m0 + lane;
-        const bool hit = (m < k) && spheres_meet(A, a.spheres[m], a.rcf);
-        n += __popcll(__ballot(hit));
+    for (int m0 = 0; m0 < k; m0 += 256) {
+        float4 B[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) B[h] = a.spheres[min(m0 + 64 * h + lane, k - 1)];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) n += __popcll(__ballot(m0 + 64 * h + lane < k && spheres_meet(A, B[h], a.rcf)));
     }
     int base;
     if (n <= CORR_CAP) {
@@ -397,49 +482,48 @@ __device__ void corr_trial(const CorrArgs &a, const PairCtx &c, int k, int lane)
     }
     const nd::Trial *Tk = a.trials + k;
     const int nak = Tk->na;
-    int pos = base;
+    if (lane < 2 * nak) {
+        const int at = lane >> 1;
+        const float4 h = (lane & 1) ? Tk->new_hi[at] : Tk->old_hi[at];
+        const float4 l = (lane & 1) ? Tk->new_lo[at] : Tk->old_lo[at];
+        cs.x[lane] = (double)h.x + (double)l.x;
+        cs.y[lane] = (double)h.y + (double)l.y;
+        cs.z[lane] = (double)h.z + (double)l.z;
+        cs.sp[lane] = __float_as_int(h.w);
+    }
+    __builtin_amdgcn_wave_barrier();
     double Sk = 0.0;
+    int got = 0, done = 0;
+    auto flush = [&](int take) {
+        double C = 0.0, S = 0.0;
+        int m = -1;
+        if (lane < take) {
+            m = cs.wl[lane];
+            corr_pair<MAXNU>(a, c, cs, nak, m, C, S);
+            a.pool_m[base + done + lane] = S > 0.0 ? m : -1;
+            a.pool_c[base + done + lane] = C;
+        }
+        Sk += S;
+        done += take;
+        const int rem = got - take;
+        const int v = lane < rem ? cs.wl[take + lane] : 0;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rem) cs.wl[lane] = v;
+        __builtin_amdgcn_wave_barrier();
+        got = rem;
+    };
     for (int m0 = 0; m0 < k; m0 += 64) {
         const int m = m0 + lane;
-        const bool hit = (m < k) && spheres_meet(A, a.spheres[m], a.rcf);
-        unsigned long long bal = __ballot(hit);
-        while (bal) {
-            const int hl = __ffsll((long long)bal) - 1;
-            bal &= bal - 1ull;
-            const int mm = m0 + hl;
-            const nd::Trial *Tm = a.trials + mm;
-            const int nam = Tm->na;
-            double C = 0.0, S = 0.0;
-            for (int t = lane; t < MAXNU * MAXNU * 4; t += 64) {
-                const int x = t / (MAXNU * 4), y = (t >> 2) % MAXNU, sel = t & 3;
-                if (x < nak && y < nam) {
-                    // sel 0: (k', m') +   1: (k, m') -   2: (k', m) -   3: (k, m) +
-                    const float4 p = (sel & 1) ? Tk->old_hi[x] : Tk->new_hi[x];
-                    const float4 pl = (sel & 1) ? Tk->old_lo[x] : Tk->new_lo[x];
-                    const float4 q = (sel & 2) ? Tm->old_hi[y] : Tm->new_hi[y];
-                    const float4 ql = (sel & 2) ? Tm->old_lo[y] : Tm->new_lo[y];
-                    const int rb = __float_as_int(p.w) * c.M;
-                    float u;
-                    if (nd::pair_u(c, p, (double)p.x + (double)pl.x, (double)p.y + (double)pl.y,
-                                   (double)p.z + (double)pl.z, rb, q, ql, u)) {
-                        C += (sel == 0 || sel == 3) ? (double)u : -(double)u;
-                        S += (double)fabsf(u);
-                    }
-                }
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                C += __shfl_xor(C, o);
-                S += __shfl_xor(S, o);
-            }
-            if (lane == 0) {
-                a.pool_m[pos] = S > 0.0 ? mm : -1;
-                a.pool_c[pos] = C;
-            }
-            Sk += S;
-            ++pos;
-        }
+        const bool hit = m < k && spheres_meet(A, a.spheres[min(m, k - 1)], a.rcf);
+        const unsigned long long bal = __ballot(hit);
+        if (hit) cs.wl[got + __popcll(bal & lt)] = m;
+        __builtin_amdgcn_wave_barrier();
+        got += __popcll(bal);
+        if (got >= 64) flush(64);
     }
+    while (got > 0) flush(min(got, 64));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) Sk += __shfl_xor(Sk, o);
     if (lane == 0) a.corr_s[k] = (float)Sk;
 }
 
@@ -451,83 +535,51 @@ __global__ __launch_bounds__(256) void k_mc_corr(CorrArgs a)
     if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
     __syncthreads();
     const PairCtx c{a.tab, s_prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
+    __shared__ CorrScratch s_cs[4];
     const int k_begin = blockIdx.x * CORR_TPB, k_end = min(a.kb, k_begin + CORR_TPB);
-    for (int k = k_begin + wave; k < k_end; k += 4) corr_trial<MAXNU>(a, c, k, lane);
+    for (int k = k_begin + wave; k < k_end; k += 4) corr_trial<MAXNU>(a, c, k, lane, s_cs[wave]);
 }
 
 // ---------------------------------------------------------------- cell scan
-constexpr int CS_LIST = 512;  // survivors buffered per wave
+constexpr int CS_LIST = 256;  // survivors buffered per wave
 
 struct CellScanArgs {
     const float4 *spos4;
     const float4 *sposlo;
-    const int32_t *sorted;
+    const int32_t *slot;     // atom -> sorted slot
     const int32_t *cstart;
     const float *tab;
     const nd::Trial *trials;
     const float *drift;
-    int M, n_pts, kb, nc;
+    const int32_t *slab;     // [N_SLAB] counts, then [N_SLAB][kcap] trial lists
+    int M, n_pts, kb, nc, kcap, per_slab;
     float rcf, rcf2_filter;
     double rcf2, tscale;
     double *dE0, *S0;
 };
 
-// Cells [lo, lo + cnt) (mod nc) cover [c - reach, c + reach] along one axis;
-// the whole axis, once, when the interval spans it.
-__device__ __forceinline__ void cell_span(float c, float reach, int nc, int &lo, int &cnt)
-{
-    const int l = (int)floorf((c - reach) * (float)nc);
-    const int h = (int)floorf((c + reach) * (float)nc);
-    if (h - l + 1 >= nc) {
-        lo = 0;
-        cnt = nc;
-    } else {
-        lo = ((l % nc) + nc) % nc;
-        cnt = h - l + 1;
-    }
-}
-
 // Trial atoms staged in LDS for the scan: FP64 fractional position and the
 // table-row base of the atom's species, for the old (index 2a) and new
-// (2a + 1) position of atom a.
+// (2a + 1) position of atom a, and the sorted slots of the unit's atoms.
 struct TrialAtoms {
     double x[2 * ND_MAX_UNIT_ATOMS], y[2 * ND_MAX_UNIT_ATOMS], z[2 * ND_MAX_UNIT_ATOMS];
     int rb[2 * ND_MAX_UNIT_ATOMS];
+    int sl[ND_MAX_UNIT_ATOMS];
 };
 
-// Exact pair energy from the FP64 fractional displacement d = s_j - s_a
-// (the same arithmetic as pair_u_exact); false beyond r_cut.
-__device__ __forceinline__ bool pair_u_disp(const PairCtx &c, double ex, double ey, double ez, int row, float &u)
-{
-    ex -= rint(ex);
-    ey -= rint(ey);
-    ez -= rint(ez);
-    const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
-    if (!(r2 < c.rcf2)) return false;
-    const double t = sqrt(r2) * c.tscale;
-    int i0 = (int)t;
-    i0 = min(i0, c.n_pts - 2);
-    const float f = (float)(t - (double)i0);
-    const float *tr = c.tab + row;
-    const float u0 = tr[i0];
-    const float u1 = tr[i0 + 1];
-    u = fmaf(f, u1 - u0, u0);
-    return true;
-}
-
+// Survivors are kept as their current hi position with .w = slot << 2 |
+// species (slot < 2^29).
 template <int MAXNU>
-__device__ __forceinline__ void cell_flush(const CellScanArgs &a, const PairCtx &c, const TrialAtoms &ta, int ta0,
-                                           int tna, const int *list, int nlist, int lane, double &e, double &s)
+__device__ __forceinline__ void cell_flush(const CellScanArgs &a, const PairCtx &c, const TrialAtoms &ta, int tna,
+                                           const float4 *list, int nlist, int lane, double &e, double &s)
 {
     for (int i = lane; i < nlist; i += 64) {
-        const int sl = list[i];
-        const int id = a.sorted[sl];
-        const float4 q = a.spos4[sl];
-        const float4 ql = a.sposlo[sl];
-        if ((unsigned)(id - ta0) < (unsigned)tna) continue;  // the moved unit itself
+        const float4 q = list[i];
+        const int w = __float_as_int(q.w);
+        const float4 ql = a.sposlo[w >> 2];
         const double sx = (double)q.x + (double)ql.x, sy = (double)q.y + (double)ql.y,
                      sz = (double)q.z + (double)ql.z;
-        const int sj = __float_as_int(q.w);
+        const int sj = w & 3;
 #pragma unroll
         for (int at = 0; at < MAXNU; ++at) {
             if (at < tna) {
@@ -547,16 +599,26 @@ __device__ __forceinline__ void cell_flush(const CellScanArgs &a, const PairCtx 
     }
 }
 
-// One block of four waves per trial.  The rows of cells within reach of
-// the trial's bounding sphere (rows along x are contiguous in the sorted
-// arrays, split in two where they wrap) are dealt round-robin to the waves.
-// A wave fetches the slot ranges of up to 64 of its rows at once (one per
-// lane), concatenates them with a prefix sum, and walks the concatenation 64
-// candidates at a time; candidates whose current position is within
-// r_cut + radius of the centre are compacted into LDS and their exact pair
-// terms summed.
+// Distance from c to the nearest periodic image of the cell interval
+// [i/nc, (i+1)/nc) along one axis.
+__device__ __forceinline__ float gap_to_cell(float c, int i, float inv_nc)
+{
+    float d = ((float)i + 0.5f) * inv_nc - c;
+    d -= rintf(d);
+    return fmaxf(0.0f, fabsf(d) - 0.5f * inv_nc);
+}
+
+// Trial k by one block of four waves.  The cell rows (z, y) within reach
+// of the trial's bounding sphere are dealt round-robin to the waves; each
+// row is cut to the chord of the reach sphere at the row's nearest point
+// (rows that miss the sphere are skipped) and split in two slot ranges
+// where it wraps.  A wave fetches up to 64 rows at once (one per lane),
+// concatenates their slot ranges with a prefix sum, and walks the
+// concatenation 128 candidates at a time; candidates whose current position
+// lies within r_cut + radius of the centre (atoms of the moved unit aside)
+// are compacted into LDS and their exact pair terms summed.
 template <int MAXNU>
-__device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k, int *list, double *red,
+__device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k, float4 *list, double *red,
                                  TrialAtoms &ta)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -571,40 +633,60 @@ __device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k,
         ta.z[tid] = (double)h.z + (double)l.z;
         ta.rb[tid] = __float_as_int(h.w) * c.M;
     }
+    if (tid < tna) ta.sl[tid] = a.slot[ta0 + tid];
     __syncthreads();
+    int own[MAXNU];
+#pragma unroll
+    for (int at = 0; at < MAXNU; ++at) own[at] = at < tna ? ta.sl[at] : -1;
     const float cx = T->cen[0], cy = T->cen[1], cz = T->cen[2];
     const float surv = a.rcf + T->rad + 4e-6f;
     const float surv2 = surv * surv;
     const float reach = surv + *a.drift + 1e-6f;
+    const float reach2 = reach * reach;
     const int nc = a.nc;
-    int lox, cntx, loy, cnty, loz, cntz;
-    cell_span(cx, reach, nc, lox, cntx);
-    cell_span(cy, reach, nc, loy, cnty);
-    cell_span(cz, reach, nc, loz, cntz);
-    const int xb = lox + cntx;
-    const int runs = xb > nc ? 2 : 1;
-    const int nrows = cntz * cnty;
+    const float fnc = (float)nc, inv_nc = 1.0f / fnc;
+    // rows: z in [lz, hz], y in [ly, hy] (unwrapped cell indices)
+    const int lz = (int)floorf((cz - reach) * fnc), hz = min((int)floorf((cz + reach) * fnc), lz + nc - 1);
+    const int ly = (int)floorf((cy - reach) * fnc), hy = min((int)floorf((cy + reach) * fnc), ly + nc - 1);
+    const int cnty = hy - ly + 1;
+    const int nrows = (hz - lz + 1) * cnty;
     const int my_rows = nrows > wave ? (nrows - wave + 3) / 4 : 0;
-    const int nseg = my_rows * runs;
     const unsigned long long lt = (1ull << lane) - 1ull;
     double e = 0.0, s = 0.0;
     int nlist = 0;
-    for (int sp = 0; sp < nseg; sp += 64) {
-        // segment sp + lane: slot range [sbeg, sbeg + len)
+    for (int sp = 0; sp < my_rows; sp += 64) {
+        // row sp + lane: slot ranges [b0, b0 + n0) and [b1, b1 + n1)
         const int sid = sp + lane;
-        int sbeg = 0, len = 0;
-        if (sid < nseg) {
-            const int r = wave + 4 * (sid / runs);
-            const int run = sid - (sid / runs) * runs;
-            int zz = loz + r / cnty, yy = loy + r % cnty;
-            if (zz >= nc) zz -= nc;
-            if (yy >= nc) yy -= nc;
-            const int rowc = (zz * nc + yy) * nc;
-            const int ra = run == 0 ? lox : 0;
-            const int rb = run == 0 ? min(xb, nc) : xb - nc;
-            sbeg = a.cstart[rowc + ra];
-            len = a.cstart[rowc + rb] - sbeg;
+        int b0 = 0, n0 = 0, b1 = 0, n1 = 0;
+        if (sid < my_rows) {
+            const int r = wave + 4 * sid;
+            const int zu = lz + r / cnty, yu = ly + r % cnty;
+            const float gz = gap_to_cell(cz, zu, inv_nc), gy = gap_to_cell(cy, yu, inv_nc);
+            const float d2 = gz * gz + gy * gy;
+            if (d2 < reach2) {
+                const float half = sqrtf(reach2 - d2) * 1.0000005f + 1e-7f;
+                int l = (int)floorf((cx - half) * fnc);
+                int h = (int)floorf((cx + half) * fnc);
+                int lo, cnt;
+                if (h - l + 1 >= nc) {
+                    lo = 0;
+                    cnt = nc;
+                } else {
+                    lo = ((l % nc) + nc) % nc;
+                    cnt = h - l + 1;
+                }
+                const int zz = ((zu % nc) + nc) % nc, yy = ((yu % nc) + nc) % nc;
+                const int rowc = (zz * nc + yy) * nc;
+                const int e0 = min(lo + cnt, nc);
+                b0 = a.cstart[rowc + lo];
+                n0 = a.cstart[rowc + e0] - b0;
+                if (lo + cnt > nc) {
+                    b1 = a.cstart[rowc];
+                    n1 = a.cstart[rowc + lo + cnt - nc] - b1;
+                }
+            }
         }
+        const int len = n0 + n1;
         // inclusive prefix of the lengths across the wave
         int incl = len;
 #pragma unroll
@@ -621,7 +703,7 @@ __device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k,
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int cidx = c0 + 64 * h + lane;
-                // segment of candidate cidx: the largest j with excl_j <= cidx
+                // row of candidate cidx: the largest j with excl_j <= cidx
                 // (binary search over lanes; every lane takes part in the shuffles)
                 const int cc = min(cidx, total - 1);
                 int j = 0;
@@ -631,7 +713,12 @@ __device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k,
                     const int ex = __shfl(excl, cand < 64 ? cand : 63);
                     if (cand < 64 && ex <= cc) j = cand;
                 }
-                sl[h] = __shfl(sbeg, j) + (cc - __shfl(excl, j));
+                // every lane shuffles every value: no shuffle under a branch
+                const int off = cc - __shfl(excl, j);
+                const int jn0 = __shfl(n0, j);
+                const int jb0 = __shfl(b0, j);
+                const int jb1 = __shfl(b1, j);
+                sl[h] = off < jn0 ? jb0 + off : jb1 + (off - jn0);
                 live[h] = cidx < total;
             }
             float4 q[2];
@@ -643,18 +730,25 @@ __device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k,
                 dx -= rintf(dx);
                 dy -= rintf(dy);
                 dz -= rintf(dz);
-                const bool hit = live[h] && fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < surv2;
+                bool mine = false;
+#pragma unroll
+                for (int at = 0; at < MAXNU; ++at) mine |= sl[h] == own[at];
+                const bool hit = live[h] && !mine && fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < surv2;
                 const unsigned long long bal = __ballot(hit);
-                if (hit) list[nlist + __popcll(bal & lt)] = sl[h];
+                if (hit) {
+                    float4 v = q[h];
+                    v.w = __int_as_float((sl[h] << 2) | (__float_as_int(q[h].w) & 3));
+                    list[nlist + __popcll(bal & lt)] = v;
+                }
                 nlist += __popcll(bal);
             }
             if (nlist > CS_LIST - 128) {
-                cell_flush<MAXNU>(a, c, ta, ta0, tna, list, nlist, lane, e, s);
+                cell_flush<MAXNU>(a, c, ta, tna, list, nlist, lane, e, s);
                 nlist = 0;
             }
         }
     }
-    cell_flush<MAXNU>(a, c, ta, ta0, tna, list, nlist, lane, e, s);
+    cell_flush<MAXNU>(a, c, ta, tna, list, nlist, lane, e, s);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         e += __shfl_xor(e, o);
@@ -671,43 +765,66 @@ __device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k,
     }
 }
 
-// Blocks [0, kb): cell scan of trial blockIdx.x.  Then the in-batch
-// corrections (both need only the batch's proposals), then the proposals of
-// the next batch, whose units are disjoint from this batch's.
+// Blocks of one launch, in dispatch order: the proposals of the next
+// batch (its units are disjoint from this batch's) and the in-batch
+// corrections, which are few and long, so they start first; padding to a
+// multiple of 8; then the cell scans, block b of them on XCD b mod 8 taking
+// the trials whose centre lies in z-slab b mod 8, so each XCD's L2 holds
+// about one slab of the cell data instead of all of it.
+__host__ __device__ inline int scan_front_blocks(int kb, int kb_next)
+{
+    const int n = (kb_next + 255) / 256 + (kb + CORR_TPB - 1) / CORR_TPB;
+    return (n + N_SLAB - 1) / N_SLAB * N_SLAB;
+}
+
+static_assert(sizeof(CorrScratch) <= sizeof(float4) * CS_LIST, "correction scratch must fit a wave's survivor list");
+
 template <int MAXNU>
 __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const CorrArgs &ca, const ProposeArgs &next,
                                                int bx)
 {
     extern __shared__ float s_tab[];  // [P][n_pts]
     __shared__ int s_prow[16];
-    __shared__ int s_list[4][CS_LIST];
+    __shared__ float4 s_list[4][CS_LIST];
     __shared__ double s_red[8];
     __shared__ TrialAtoms s_ta;
     const int tid = threadIdx.x;
-    const int n_corr_blocks = (a.kb + CORR_TPB - 1) / CORR_TPB;
-    if (bx >= a.kb + n_corr_blocks) {
-        const int k = (bx - a.kb - n_corr_blocks) * 256 + tid;
+    const int n_prop = (next.kb + 255) / 256;
+    const int n_corr = (a.kb + CORR_TPB - 1) / CORR_TPB;
+    const int n_front = scan_front_blocks(a.kb, next.kb);
+    if (bx < n_prop) {
+        const int k = bx * 256 + tid;
         if (k < next.kb) propose_one(next, k);
         return;
     }
-    if (bx >= a.kb) {
+    if (bx < n_prop + n_corr) {
         if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
         __syncthreads();
         const PairCtx c{ca.tab, s_prow, ca.M, ca.n_pts, ca.rcf2_filter, ca.rcf2, ca.tscale};
-        const int k_begin = (bx - a.kb) * CORR_TPB, k_end = min(ca.kb, k_begin + CORR_TPB);
-        for (int k = k_begin + (tid >> 6); k < k_end; k += 4) corr_trial<MAXNU>(ca, c, k, tid & 63);
+        CorrScratch &cs = *reinterpret_cast<CorrScratch *>(s_list[tid >> 6]);
+        const int k = (bx - n_prop) * CORR_TPB + (tid >> 6);
+        if (k < ca.kb) corr_trial<MAXNU>(ca, c, k, tid & 63, cs);
         return;
     }
+    if (bx < n_front) return;
+    const int sb = bx - n_front;
+    const int slab = sb & (N_SLAB - 1);
+    const int cnt = a.slab[slab];
+    const int i0 = sb >> 3;
+    if (i0 >= cnt) return;
     const int P = a.M * (a.M + 1) / 2;
     for (int q = tid; q < P * a.n_pts; q += 256) s_tab[q] = a.tab[q];
     if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
-    __syncthreads();
     const PairCtx c{s_tab, s_prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
-    scan_cells_block<MAXNU>(a, c, bx, s_list[tid >> 6], s_red, s_ta);
+    const int32_t *lst = a.slab + N_SLAB + slab * a.kcap;
+    for (int i = i0; i < cnt; i += a.per_slab) {
+        __syncthreads();  // tables staged; the previous trial is done with s_ta and s_red
+        scan_cells_block<MAXNU>(a, c, lst[i], s_list[tid >> 6], s_red, s_ta);
+    }
 }
 
 template <int MAXNU>
-__global__ __launch_bounds__(256) void k_mc_scan_corr(CellScanArgs a, CorrArgs ca, ProposeArgs next)
+__global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void k_mc_scan_corr(CellScanArgs a, CorrArgs ca, ProposeArgs next)
 {
     scan_corr_body<MAXNU>(a, ca, next, blockIdx.x);
 }
@@ -732,6 +849,7 @@ struct DecideArgs {
     float4 *spos4, *sposlo;
     const float4 *sref;
     float *drift;
+    int32_t *slab_cnt;  // [N_SLAB] slab counts of this batch's buffer, cleared here
     int N, kb, max_na;
     double kT, tie_rel;
     long long *counters;  // [0] accepted, [1] near ties
@@ -837,6 +955,7 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
         }
         __syncthreads();
         if (tid == 0) *a.ovf_fill = 0;  // overflow area is free for the next batch
+        if (tid < N_SLAB) a.slab_cnt[tid] = 0;  // the scan of this batch is done with its lists
 
         // entry i of trial k: from LDS when staged, else from the global pool
         auto entry = [&](int k, int i, int &m, double &c) {
@@ -981,8 +1100,12 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
 
 __global__ __launch_bounds__(DEC_THREADS) void k_mc_decide(DecideArgs a, ProposeArgs next) { decide_body(a, next); }
 
-__global__ void k_mc_reset(long long *counters, double *dsum, int32_t *ovf_fill)
+__global__ void k_mc_reset(long long *counters, double *dsum, int32_t *ovf_fill, int32_t *slab0, int32_t *slab1)
 {
+    if (threadIdx.x < N_SLAB) {
+        slab0[threadIdx.x] = 0;
+        slab1[threadIdx.x] = 0;
+    }
     if (threadIdx.x < 2) counters[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         *dsum = 0.0;
@@ -999,6 +1122,7 @@ struct McLaunch {
     ProposeArgs next;  // next batch proposed by the scan launch (kb = 0: not there)
     DecideArgs da;
     ProposeArgs late;  // next batch proposed after the commit (kb = 0: not there)
+    int32_t *slab0, *slab1;  // slab counts of the two trial buffers (cleared by the reset)
     int nblk;          // blocks of the scan launch
     int rebuild;       // cells rebuilt before this batch
 };
@@ -1006,7 +1130,7 @@ struct McLaunch {
 // The same kernels over several boxes at once: blockIdx.y selects the box's
 // batch descriptor, blocks past a box's own grid return at once.
 template <int MAXNU>
-__global__ __launch_bounds__(256) void k_mc_scan_corr_multi(const McLaunch *__restrict__ L)
+__global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void k_mc_scan_corr_multi(const McLaunch *__restrict__ L)
 {
     const McLaunch &e = L[blockIdx.y];
     if ((int)blockIdx.x >= e.nblk) return;
@@ -1028,7 +1152,12 @@ __global__ __launch_bounds__(64) void k_mc_propose_multi(const ProposeArgs *__re
 
 __global__ void k_mc_reset_multi(const McLaunch *__restrict__ L)
 {
-    const DecideArgs &d = L[blockIdx.y].da;
+    const McLaunch &e = L[blockIdx.y];
+    const DecideArgs &d = e.da;
+    if (threadIdx.x < N_SLAB) {
+        e.slab0[threadIdx.x] = 0;
+        e.slab1[threadIdx.x] = 0;
+    }
     if (threadIdx.x < 2) d.counters[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         *d.dsum = 0.0;
@@ -1049,7 +1178,7 @@ template <int MAXNU>
 void launch_scan_corr(nd_box *b, const CellScanArgs &ca, const CorrArgs &cr, const ProposeArgs &next, size_t slds)
 {
     nd::ProfScope ps(b, ND_PROF_MC_SCAN);
-    const int nblk = ca.kb + (ca.kb + CORR_TPB - 1) / CORR_TPB + (next.kb + 255) / 256;
+    const int nblk = scan_front_blocks(ca.kb, next.kb) + N_SLAB * ca.per_slab;
     hipLaunchKernelGGL(k_mc_scan_corr<MAXNU>, dim3(nblk), dim3(256), slds, b->stream, ca, cr, next);
     ND_HIP(hipGetLastError());
 }
@@ -1078,6 +1207,7 @@ void ensure_work(nd_box *b, int K, int n_jb)
     nd::dfree(w.pool_m);
     nd::dfree(w.pool_c);
     nd::dfree(w.corr_s);
+    nd::dfree(w.slab);
     long long *counters = w.counters;
     double *dsum = w.dsum;
     int32_t *ovf = w.ovf_fill;
@@ -1096,6 +1226,7 @@ void ensure_work(nd_box *b, int K, int n_jb)
     w.pool_m = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * pool));
     w.pool_c = static_cast<double *>(nd::dmalloc(sizeof(double) * pool));
     w.corr_s = static_cast<float *>(nd::dmalloc(sizeof(float) * K));
+    w.slab = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * 2 * (size_t)(N_SLAB + N_SLAB * K)));
     if (!w.counters) w.counters = static_cast<long long *>(nd::dmalloc(sizeof(long long) * 4));
     if (!w.dsum) w.dsum = static_cast<double *>(nd::dmalloc(sizeof(double)));
     if (!w.ovf_fill) w.ovf_fill = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t)));
@@ -1154,6 +1285,20 @@ size_t mc_table_lds(const nd_box *b)
     return lds_tab;
 }
 
+int32_t *slab_buffer(const nd_box *b, int buf)
+{
+    const McWork &w = b->mc;
+    return w.slab + (size_t)buf * (N_SLAB + (size_t)N_SLAB * w.cap_k);
+}
+
+// Scan blocks per slab: the mean count of a slab plus three standard
+// deviations, so that a block rarely takes a second trial.
+int per_slab_blocks(int kb)
+{
+    const double m = (double)kb / N_SLAB;
+    return std::max(1, (int)std::ceil(m + 3.0 * std::sqrt(m)));
+}
+
 ProposeArgs proposal_args(const nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t t0, int kb, int buf, int K)
 {
     const McWork &w = b->mc;
@@ -1173,6 +1318,8 @@ ProposeArgs proposal_args(const nd_box *b, const nd_mc_params *p, uint64_t seed,
     pa.kb = kb;
     pa.trials = w.trials + (size_t)buf * K;
     pa.spheres = w.spheres + (size_t)buf * K;
+    pa.kcap = w.cap_k;
+    pa.slab = slab_buffer(b, buf);
     return pa;
 }
 
@@ -1201,7 +1348,7 @@ CorrArgs corr_args(const nd_box *b, const McConsts &k, const nd::Trial *trials, 
 }
 
 DecideArgs decide_args(const nd_box *b, const nd_mc_params *p, const McConsts &k, const nd::Trial *trials, int kb,
-                       int64_t done, const nd_mc_trace *trace, bool cells_live)
+                       int64_t done, const nd_mc_trace *trace, bool cells_live, int buf)
 {
     const McWork &w = b->mc;
     DecideArgs da;
@@ -1223,6 +1370,7 @@ DecideArgs decide_args(const nd_box *b, const nd_mc_params *p, const McConsts &k
     da.sposlo = cells_live ? b->cells.sposlo : nullptr;
     da.sref = cells_live ? b->cells.sref : nullptr;
     da.drift = cells_live ? b->cells.drift : nullptr;
+    da.slab_cnt = slab_buffer(b, buf);
     da.N = b->N;
     da.max_na = b->max_na;
     da.kb = kb;
@@ -1279,7 +1427,10 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         CellScanArgs &ca = L.ca;
         ca.spos4 = b->cells.spos4;
         ca.sposlo = b->cells.sposlo;
-        ca.sorted = b->cells.sorted;
+        ca.slot = b->cells.slot;
+        ca.slab = slab_buffer(b, buf);
+        ca.kcap = w.cap_k;
+        ca.per_slab = per_slab_blocks(kb);
         ca.cstart = b->cells.start;
         ca.tab = b->tab;
         ca.trials = trials;
@@ -1303,8 +1454,10 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
             L.late.kb = 0;
         else
             L.next.kb = 0;
-        L.da = decide_args(b, p, k, trials, kb, done, trace, true);
-        L.nblk = kb + (kb + CORR_TPB - 1) / CORR_TPB + (L.next.kb + 255) / 256;
+        L.da = decide_args(b, p, k, trials, kb, done, trace, true, buf);
+        L.nblk = scan_front_blocks(kb, L.next.kb) + N_SLAB * ca.per_slab;
+        L.slab0 = slab_buffer(b, 0);
+        L.slab1 = slab_buffer(b, 1);
         b->cells.trials_since_build += kb;
         pl.batches.push_back(L);
         done = done_next;
@@ -1342,7 +1495,8 @@ void mc_run_full(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first
     const int maxnu = pick_maxnu(b->max_na);
     const int ncu = nd::cu_count(b->device);
 
-    hipLaunchKernelGGL(k_mc_reset, dim3(1), dim3(64), 0, b->stream, w.counters, w.dsum, w.ovf_fill);
+    hipLaunchKernelGGL(k_mc_reset, dim3(1), dim3(64), 0, b->stream, w.counters, w.dsum, w.ovf_fill,
+                       slab_buffer(b, 0), slab_buffer(b, 1));
     ND_HIP(hipGetLastError());
     if (n == 0) return;
     int buf = 0;
@@ -1399,7 +1553,7 @@ void mc_run_full(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first
         default: launch_corr<8>(b, cr); break;
         }
         // cells kept consistent when they are live from an earlier cell-scan call
-        const DecideArgs da = decide_args(b, p, k, trials, kb, done, trace, b->cells.valid);
+        const DecideArgs da = decide_args(b, p, k, trials, kb, done, trace, b->cells.valid, buf);
         {
             nd::ProfScope ps(b, ND_PROF_MC_DECIDE);
             hipLaunchKernelGGL(k_mc_decide, dim3(1), dim3(DEC_THREADS), 0, b->stream, da, late);
@@ -1424,7 +1578,8 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
     McPlan pl;
     mc_plan_cells(b, p, seed, first, n, trace, false, pl);
     McWork &w = b->mc;
-    hipLaunchKernelGGL(k_mc_reset, dim3(1), dim3(64), 0, b->stream, w.counters, w.dsum, w.ovf_fill);
+    hipLaunchKernelGGL(k_mc_reset, dim3(1), dim3(64), 0, b->stream, w.counters, w.dsum, w.ovf_fill,
+                       slab_buffer(b, 0), slab_buffer(b, 1));
     ND_HIP(hipGetLastError());
     if (pl.batches.empty()) return;
     {
@@ -1516,7 +1671,8 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
             if (r >= (int)plans[i].batches.size()) continue;
             const McLaunch &L = plans[i].batches[r];
             m->launches.push_back(L);
-            m->r_maxblk[r] = std::max(m->r_maxblk[r], L.nblk);
+            // a multiple of N_SLAB, so block x of every box row lands on XCD x mod 8
+            m->r_maxblk[r] = std::max(m->r_maxblk[r], (L.nblk + N_SLAB - 1) / N_SLAB * N_SLAB);
             if (L.rebuild) {
                 m->cb.push_back(boxes[i]->cells.args);
                 m->cb_maxn[r] = std::max(m->cb_maxn[r], boxes[i]->N);

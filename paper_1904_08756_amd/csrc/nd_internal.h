@@ -62,6 +62,7 @@ struct McWork {
     int32_t *pool_m = nullptr;    // [cap_pool] earlier trial m of each entry (increasing), -1 if C = 0
     double *pool_c = nullptr;     // [cap_pool] energy correction if m was accepted
     int32_t *ovf_fill = nullptr;  // entries used in the pool's overflow area
+    int32_t *slab = nullptr;      // [2][8 + 8 cap_k] per buffer: z-slab counts, then trial lists
     long long *counters = nullptr;   // [0] accepted, [1] near ties
     double *dsum = nullptr;       // accepted dE sum
 };
