@@ -12,6 +12,7 @@
 // Distances are FP64 from the float32 coordinates; per-pair weights FP32;
 // sums FP64.
 #include "nd_internal.h"
+#include "nd_pair.h"
 
 #include <algorithm>
 #include <cmath>
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(TILE) void k_forces(ForceArgs a)
     int *prow = js + TILE;                                                  // [16]
     __shared__ double red[TILE / 64];
     const int tid = threadIdx.x;
-    for (int q = tid; q < P * a.n_pts; q += TILE) tab[q] = a.tab[q];
+    nd::stage_floats<TILE>(tab, a.tab, P * a.n_pts);
     if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
     const int N = a.N;
     const int i = blockIdx.x * TILE + tid;

@@ -256,7 +256,7 @@ __global__ __launch_bounds__(TILE) void k_total_energy(EnergyArgs a)
     __shared__ double red[2][TILE / 64];
     const int tid = threadIdx.x;
     const int P = a.M * (a.M + 1) / 2;
-    for (int q = tid; q < P * a.n_pts; q += TILE) tab[q] = a.tab[q];
+    nd::stage_floats<TILE>(tab, a.tab, P * a.n_pts);
     if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
     const nd::PairCtx c{tab, prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
     double e = 0.0, s = 0.0;

@@ -31,6 +31,9 @@
 namespace {
 
 using nd::PairCtx;
+using nd::ld4;
+using nd::ldg;
+using nd::stg;
 
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_JPT = 8;                         // j atoms held per thread
@@ -266,12 +269,12 @@ __device__ __forceinline__ void scan_trial(const PairCtx &c, const nd::Trial *__
 template <int MAXNU>
 __global__ __launch_bounds__(SCAN_THREADS) void k_mc_scan(ScanArgs a)
 {
-    extern __shared__ float s_tab[];  // [P][n_pts]
+    extern __shared__ __align__(16) float s_tab[];  // [P][n_pts]
     __shared__ int s_prow[16];
     __shared__ double s_red[2][SCAN_THREADS / 64][MAX_TG];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int P = a.M * (a.M + 1) / 2;
-    for (int q = tid; q < P * a.n_pts; q += SCAN_THREADS) s_tab[q] = a.tab[q];
+    nd::stage_floats<SCAN_THREADS>(s_tab, a.tab, P * a.n_pts);
     if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
 
     const int jstart = blockIdx.x * SCAN_JB;
@@ -392,78 +395,53 @@ __device__ __forceinline__ bool spheres_meet(float4 A, float4 B, float rcf)
     return dx * dx + dy * dy + dz * dz < lim * lim;
 }
 
-constexpr int CORR_LIST = 192;  // hits buffered per wave
+constexpr int CORR_LIST = 512;  // hits listed per wave at a time
 
-// Per-wave LDS scratch of the correction step: the hit list and trial k's
-// atoms (FP64 fractional positions and species, old at 2a, new at 2a + 1).
+// Per-wave LDS scratch of the correction step: the hit list, per-lane
+// partial sums, and trial k's atoms (FP64 fractional positions and species,
+// old at 2a, new at 2a + 1).
 struct CorrScratch {
     int wl[CORR_LIST];
+    double pc[64], ps[64];
     double x[2 * ND_MAX_UNIT_ATOMS], y[2 * ND_MAX_UNIT_ATOMS], z[2 * ND_MAX_UNIT_ATOMS];
     int sp[2 * ND_MAX_UNIT_ATOMS];
 };
 
-// C_km = [U(k',m') - U(k,m')] - [U(k',m) - U(k,m)] (and the sum of |U| of its
-// terms) for the hit m of this lane; pair terms by the exact path.
-template <int MAXNU>
-__device__ __forceinline__ void corr_pair(const CorrArgs &a, const PairCtx &c, const CorrScratch &cs, int nak, int m,
-                                          double &C, double &S)
-{
-    const nd::Trial *Tm = a.trials + m;
-    const int nam = Tm->na;
-    float4 mh[2 * MAXNU], ml[2 * MAXNU];
-#pragma unroll
-    for (int y = 0; y < MAXNU; ++y) {
-        if (y < nam) {
-            mh[2 * y] = Tm->old_hi[y];
-            ml[2 * y] = Tm->old_lo[y];
-            mh[2 * y + 1] = Tm->new_hi[y];
-            ml[2 * y + 1] = Tm->new_lo[y];
-        }
-    }
-    C = 0.0;
-    S = 0.0;
-#pragma unroll
-    for (int y = 0; y < MAXNU; ++y) {
-        if (y >= nam) continue;
-#pragma unroll
-        for (int om = 0; om < 2; ++om) {  // om 0: m old, 1: m new
-            const float4 q = mh[2 * y + om], ql = ml[2 * y + om];
-            const double qx = (double)q.x + (double)ql.x, qy = (double)q.y + (double)ql.y,
-                         qz = (double)q.z + (double)ql.z;
-            const int sq = __float_as_int(q.w);
-            for (int x = 0; x < nak; ++x) {
-#pragma unroll
-                for (int ok = 0; ok < 2; ++ok) {  // ok 0: k old, 1: k new
-                    const int ia = 2 * x + ok;
-                    float u;
-                    if (pair_u_disp(c, qx - cs.x[ia], qy - cs.y[ia], qz - cs.z[ia], c.prow[cs.sp[ia] * c.M + sq], u)) {
-                        // + (k', m') and (k, m); - (k, m') and (k', m)
-                        C += (ok == om) ? (double)u : -(double)u;
-                        S += (double)fabsf(u);
-                    }
-                }
-            }
-        }
-    }
-}
-
-// One wave: the entries (m, C_km) of trial k for every earlier trial m of
-// the batch whose bounding sphere comes within r_cut of k's, in increasing
-// m.  The hits are collected 64 at a time and each lane evaluates one hit,
-// so the pair terms of all hits are computed at once.
-template <int MAXNU>
-__device__ void corr_trial(const CorrArgs &a, const PairCtx &c, int k, int lane, CorrScratch &cs)
+// List the hits of ranks [first, first + CORR_LIST): earlier trials m < k of
+// the batch whose bounding sphere comes within r_cut of k's, in increasing m.
+// Returns the total number of hits.
+__device__ __forceinline__ int corr_collect(const CorrArgs &a, float4 A, int k, int lane, int first, int *wl)
 {
     const unsigned long long lt = (1ull << lane) - 1ull;
-    const float4 A = a.spheres[k];
     int n = 0;
     for (int m0 = 0; m0 < k; m0 += 256) {
         float4 B[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) B[h] = a.spheres[min(m0 + 64 * h + lane, k - 1)];
+        for (int h = 0; h < 4; ++h) B[h] = ld4(a.spheres + min(m0 + 64 * h + lane, k - 1));
 #pragma unroll
-        for (int h = 0; h < 4; ++h) n += __popcll(__ballot(m0 + 64 * h + lane < k && spheres_meet(A, B[h], a.rcf)));
+        for (int h = 0; h < 4; ++h) {
+            const int m = m0 + 64 * h + lane;
+            const bool hit = m < k && spheres_meet(A, B[h], a.rcf);
+            const unsigned long long bal = __ballot(hit);
+            const int idx = n + __popcll(bal & lt) - first;
+            if (hit && idx >= 0 && idx < CORR_LIST) wl[idx] = m;
+            n += __popcll(bal);
+        }
     }
+    __builtin_amdgcn_wave_barrier();
+    return n;
+}
+
+// One wave: the entries (m, C_km) of trial k for every hit m, in increasing
+// m, with C_km = [U(k',m') - U(k,m')] - [U(k',m) - U(k,m)].  The pair terms
+// are spread over the lanes: one lane per (hit, atom of m, old/new of m),
+// each summing over k's atoms old and new; the lane of each hit then adds
+// its items' partial sums in a fixed order.
+template <int MAXNU>
+__device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, int k, int lane, CorrScratch &cs)
+{
+    const float4 A = a.spheres[k];
+    const int n = k > 0 ? corr_collect(a, A, k, lane, 0, cs.wl) : 0;
     int base;
     if (n <= CORR_CAP) {
         base = k * CORR_CAP;
@@ -492,36 +470,62 @@ __device__ void corr_trial(const CorrArgs &a, const PairCtx &c, int k, int lane,
         cs.sp[lane] = __float_as_int(h.w);
     }
     __builtin_amdgcn_wave_barrier();
+    constexpr int IPH = 2 * MAXNU;   // items per hit
+    constexpr int HPR = 64 / IPH;    // hits per round
+    const int hl = lane / IPH, r = lane - hl * IPH;
+    const int y = r >> 1, om = r & 1;  // atom of m; 0: m old, 1: m new
     double Sk = 0.0;
-    int got = 0, done = 0;
-    auto flush = [&](int take) {
-        double C = 0.0, S = 0.0;
-        int m = -1;
-        if (lane < take) {
-            m = cs.wl[lane];
-            corr_pair<MAXNU>(a, c, cs, nak, m, C, S);
-            a.pool_m[base + done + lane] = S > 0.0 ? m : -1;
-            a.pool_c[base + done + lane] = C;
+    int wbase = 0;
+    for (int h0 = 0; h0 < n; h0 += HPR) {
+        if (h0 + HPR > wbase + CORR_LIST) {
+            // more hits than the list holds (rare): list the next window
+            wbase = h0;
+            corr_collect(a, A, k, lane, wbase, cs.wl);
         }
-        Sk += S;
-        done += take;
-        const int rem = got - take;
-        const int v = lane < rem ? cs.wl[take + lane] : 0;
+        const int h = h0 + hl;
+        double pc = 0.0, ps = 0.0;
+        if (hl < HPR && h < n) {
+            const int m = cs.wl[h - wbase];
+            const nd::Trial *Tm = a.trials + m;
+            const int nam = ldg(&Tm->na);
+            const float4 q = ld4(om ? &Tm->new_hi[y] : &Tm->old_hi[y]);
+            const float4 ql = ld4(om ? &Tm->new_lo[y] : &Tm->old_lo[y]);
+            if (y < nam) {
+                const double qx = (double)q.x + (double)ql.x, qy = (double)q.y + (double)ql.y,
+                             qz = (double)q.z + (double)ql.z;
+                const int sq = __float_as_int(q.w);
+                for (int x = 0; x < nak; ++x) {
+#pragma unroll
+                    for (int ok = 0; ok < 2; ++ok) {  // ok 0: k old, 1: k new
+                        const int ia = 2 * x + ok;
+                        float u;
+                        if (pair_u_disp(c, qx - cs.x[ia], qy - cs.y[ia], qz - cs.z[ia],
+                                        c.prow[cs.sp[ia] * c.M + sq], u)) {
+                            // + (k', m') and (k, m); - (k, m') and (k', m)
+                            pc += (ok == om) ? (double)u : -(double)u;
+                            ps += (double)fabsf(u);
+                        }
+                    }
+                }
+            }
+        }
+        cs.pc[lane] = pc;
+        cs.ps[lane] = ps;
         __builtin_amdgcn_wave_barrier();
-        if (lane < rem) cs.wl[lane] = v;
+        if (lane < HPR && h0 + lane < n) {
+            double C = 0.0, S = 0.0;
+#pragma unroll
+            for (int q = 0; q < IPH; ++q) {
+                C += cs.pc[lane * IPH + q];
+                S += cs.ps[lane * IPH + q];
+            }
+            const int m = cs.wl[h0 + lane - wbase];
+            stg(a.pool_m + base + h0 + lane, S > 0.0 ? m : -1);
+            stg(a.pool_c + base + h0 + lane, C);
+            Sk += S;
+        }
         __builtin_amdgcn_wave_barrier();
-        got = rem;
-    };
-    for (int m0 = 0; m0 < k; m0 += 64) {
-        const int m = m0 + lane;
-        const bool hit = m < k && spheres_meet(A, a.spheres[min(m, k - 1)], a.rcf);
-        const unsigned long long bal = __ballot(hit);
-        if (hit) cs.wl[got + __popcll(bal & lt)] = m;
-        __builtin_amdgcn_wave_barrier();
-        got += __popcll(bal);
-        if (got >= 64) flush(64);
     }
-    while (got > 0) flush(min(got, 64));
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) Sk += __shfl_xor(Sk, o);
     if (lane == 0) a.corr_s[k] = (float)Sk;
@@ -541,7 +545,7 @@ __global__ __launch_bounds__(256) void k_mc_corr(CorrArgs a)
 }
 
 // ---------------------------------------------------------------- cell scan
-constexpr int CS_LIST = 256;  // survivors buffered per wave
+constexpr int CS_LIST = 192;  // survivors buffered per wave
 
 struct CellScanArgs {
     const float4 *spos4;
@@ -567,16 +571,16 @@ struct TrialAtoms {
     int sl[ND_MAX_UNIT_ATOMS];
 };
 
-// Survivors are kept as their current hi position with .w = slot << 2 |
-// species (slot < 2^29).
+// Survivors are kept in LDS as their current position, hi (with .w =
+// slot << 2 | species, slot < 2^29) and lo.
 template <int MAXNU>
-__device__ __forceinline__ void cell_flush(const CellScanArgs &a, const PairCtx &c, const TrialAtoms &ta, int tna,
-                                           const float4 *list, int nlist, int lane, double &e, double &s)
+__device__ __forceinline__ void cell_flush(const PairCtx &c, const TrialAtoms &ta, int tna, const float4 *list,
+                                           const float4 *listlo, int nlist, int lane, double &e, double &s)
 {
     for (int i = lane; i < nlist; i += 64) {
         const float4 q = list[i];
         const int w = __float_as_int(q.w);
-        const float4 ql = a.sposlo[w >> 2];
+        const float4 ql = listlo[i];
         const double sx = (double)q.x + (double)ql.x, sy = (double)q.y + (double)ql.y,
                      sz = (double)q.z + (double)ql.z;
         const int sj = w & 3;
@@ -618,22 +622,22 @@ __device__ __forceinline__ float gap_to_cell(float c, int i, float inv_nc)
 // lies within r_cut + radius of the centre (atoms of the moved unit aside)
 // are compacted into LDS and their exact pair terms summed.
 template <int MAXNU>
-__device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k, float4 *list, double *red,
-                                 TrialAtoms &ta)
+__device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k, float4 *list, float4 *listlo,
+                                 double *red, TrialAtoms &ta)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const nd::Trial *T = a.trials + k;
     const int ta0 = T->a0, tna = T->na;
     if (tid < 2 * tna) {
         const int at = tid >> 1;
-        const float4 h = (tid & 1) ? T->new_hi[at] : T->old_hi[at];
-        const float4 l = (tid & 1) ? T->new_lo[at] : T->old_lo[at];
+        const float4 h = ld4((tid & 1) ? &T->new_hi[at] : &T->old_hi[at]);
+        const float4 l = ld4((tid & 1) ? &T->new_lo[at] : &T->old_lo[at]);
         ta.x[tid] = (double)h.x + (double)l.x;
         ta.y[tid] = (double)h.y + (double)l.y;
         ta.z[tid] = (double)h.z + (double)l.z;
         ta.rb[tid] = __float_as_int(h.w) * c.M;
     }
-    if (tid < tna) ta.sl[tid] = a.slot[ta0 + tid];
+    if (tid < tna) ta.sl[tid] = ldg(a.slot + ta0 + tid);
     __syncthreads();
     int own[MAXNU];
 #pragma unroll
@@ -678,11 +682,11 @@ __device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k,
                 const int zz = ((zu % nc) + nc) % nc, yy = ((yu % nc) + nc) % nc;
                 const int rowc = (zz * nc + yy) * nc;
                 const int e0 = min(lo + cnt, nc);
-                b0 = a.cstart[rowc + lo];
-                n0 = a.cstart[rowc + e0] - b0;
+                b0 = ldg(a.cstart + rowc + lo);
+                n0 = ldg(a.cstart + rowc + e0) - b0;
                 if (lo + cnt > nc) {
-                    b1 = a.cstart[rowc];
-                    n1 = a.cstart[rowc + lo + cnt - nc] - b1;
+                    b1 = ldg(a.cstart + rowc);
+                    n1 = ldg(a.cstart + rowc + lo + cnt - nc) - b1;
                 }
             }
         }
@@ -721,9 +725,12 @@ __device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k,
                 sl[h] = off < jn0 ? jb0 + off : jb1 + (off - jn0);
                 live[h] = cidx < total;
             }
-            float4 q[2];
+            float4 q[2], ql[2];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) q[h] = a.spos4[sl[h]];
+            for (int h = 0; h < 2; ++h) {
+                q[h] = ld4(a.spos4 + sl[h]);
+                ql[h] = ld4(a.sposlo + sl[h]);
+            }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 float dx = q[h].x - cx, dy = q[h].y - cy, dz = q[h].z - cz;
@@ -738,17 +745,22 @@ __device__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k,
                 if (hit) {
                     float4 v = q[h];
                     v.w = __int_as_float((sl[h] << 2) | (__float_as_int(q[h].w) & 3));
-                    list[nlist + __popcll(bal & lt)] = v;
+                    const int idx = nlist + __popcll(bal & lt);
+                    list[idx] = v;
+                    listlo[idx] = ql[h];
                 }
                 nlist += __popcll(bal);
             }
             if (nlist > CS_LIST - 128) {
-                cell_flush<MAXNU>(a, c, ta, tna, list, nlist, lane, e, s);
+                __builtin_amdgcn_wave_barrier();
+                cell_flush<MAXNU>(c, ta, tna, list, listlo, nlist, lane, e, s);
+                __builtin_amdgcn_wave_barrier();
                 nlist = 0;
             }
         }
     }
-    cell_flush<MAXNU>(a, c, ta, tna, list, nlist, lane, e, s);
+    __builtin_amdgcn_wave_barrier();
+    cell_flush<MAXNU>(c, ta, tna, list, listlo, nlist, lane, e, s);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         e += __shfl_xor(e, o);
@@ -777,15 +789,15 @@ __host__ __device__ inline int scan_front_blocks(int kb, int kb_next)
     return (n + N_SLAB - 1) / N_SLAB * N_SLAB;
 }
 
-static_assert(sizeof(CorrScratch) <= sizeof(float4) * CS_LIST, "correction scratch must fit a wave's survivor list");
+static_assert(sizeof(CorrScratch) <= 2 * sizeof(float4) * CS_LIST, "correction scratch must fit a wave's survivor lists");
 
 template <int MAXNU>
 __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const CorrArgs &ca, const ProposeArgs &next,
                                                int bx)
 {
-    extern __shared__ float s_tab[];  // [P][n_pts]
+    extern __shared__ __align__(16) float s_tab[];  // [P][n_pts]
     __shared__ int s_prow[16];
-    __shared__ float4 s_list[4][CS_LIST];
+    __shared__ float4 s_list[4][2][CS_LIST];  // per wave: survivors hi, then lo
     __shared__ double s_red[8];
     __shared__ TrialAtoms s_ta;
     const int tid = threadIdx.x;
@@ -801,7 +813,7 @@ __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const Corr
         if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
         __syncthreads();
         const PairCtx c{ca.tab, s_prow, ca.M, ca.n_pts, ca.rcf2_filter, ca.rcf2, ca.tscale};
-        CorrScratch &cs = *reinterpret_cast<CorrScratch *>(s_list[tid >> 6]);
+        CorrScratch &cs = *reinterpret_cast<CorrScratch *>(&s_list[tid >> 6][0][0]);
         const int k = (bx - n_prop) * CORR_TPB + (tid >> 6);
         if (k < ca.kb) corr_trial<MAXNU>(ca, c, k, tid & 63, cs);
         return;
@@ -813,13 +825,13 @@ __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const Corr
     const int i0 = sb >> 3;
     if (i0 >= cnt) return;
     const int P = a.M * (a.M + 1) / 2;
-    for (int q = tid; q < P * a.n_pts; q += 256) s_tab[q] = a.tab[q];
+    nd::stage_floats<256>(s_tab, a.tab, P * a.n_pts);
     if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
     const PairCtx c{s_tab, s_prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
     const int32_t *lst = a.slab + N_SLAB + slab * a.kcap;
     for (int i = i0; i < cnt; i += a.per_slab) {
         __syncthreads();  // tables staged; the previous trial is done with s_ta and s_red
-        scan_cells_block<MAXNU>(a, c, lst[i], s_list[tid >> 6], s_red, s_ta);
+        scan_cells_block<MAXNU>(a, c, lst[i], s_list[tid >> 6][0], s_list[tid >> 6][1], s_red, s_ta);
     }
 }
 

@@ -13,6 +13,54 @@
 
 namespace nd {
 
+// Loads and stores through the global address space.  Pointers read from a
+// descriptor in device memory (rather than from kernel arguments) are
+// generic to the compiler, and generic (flat) accesses also count against
+// the LDS wait counter, so every LDS wait would wait for them too.
+#define ND_GLOBAL_AS __attribute__((address_space(1)))
+typedef float nd_v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 ld4(const float4 *p)
+{
+    const nd_v4f v = *(const ND_GLOBAL_AS nd_v4f *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+template <class T>
+__device__ __forceinline__ T ldg(const T *p)
+{
+    return *(const ND_GLOBAL_AS T *)p;
+}
+
+template <class T>
+__device__ __forceinline__ void stg(T *p, T v)
+{
+    *(ND_GLOBAL_AS T *)p = v;
+}
+
+// Block-wide copy of n floats from global memory to 16-byte aligned LDS
+// (src 16-byte aligned): all wide loads of a thread are issued before its
+// LDS writes, so the copy costs about one memory latency, not one per
+// element.
+template <int THREADS>
+__device__ __forceinline__ void stage_floats(float *dst, const float *src, int n)
+{
+    constexpr int U = 4;
+    const int n4 = n >> 2;
+    const float4 *s4 = reinterpret_cast<const float4 *>(src);
+    float4 *d4 = reinterpret_cast<float4 *>(dst);
+    for (int base = (int)threadIdx.x; base < n4; base += THREADS * U) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + u * THREADS < n4) v[u] = ld4(s4 + base + u * THREADS);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (base + u * THREADS < n4) d4[base + u * THREADS] = v[u];
+    }
+    for (int i = 4 * n4 + (int)threadIdx.x; i < n; i += THREADS) dst[i] = ldg(src + i);
+}
+
 struct PairCtx {
     const float *tab;   // [P][n_pts] table rows (LDS or global)
     const int *prow;    // [M*M] row offset of each species pair
