@@ -33,6 +33,8 @@ namespace {
 using nd::PairCtx;
 using nd::ld4;
 using nd::ldg;
+using nd::ld_i4;
+using nd::ld_d2;
 using nd::stg;
 
 constexpr int SCAN_THREADS = 256;
@@ -843,7 +845,6 @@ __global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void 
 
 // ---------------------------------------------------------------- decide
 constexpr int DEC_THREADS = 1024;
-constexpr int DEC_POOL_LDS = 7168;  // correction entries staged in LDS
 
 struct DecideArgs {
     float *xyz;
@@ -908,31 +909,68 @@ __device__ __forceinline__ bool metropolis(double e, double thr) { return e <= 0
 
 constexpr unsigned char ST_OPEN = 0, ST_REJ = 1, ST_ACC = 2;
 
+// Correction entries of trial k: fixed slots [k CORR_CAP, k CORR_CAP + n)
+// when n <= CORR_CAP (read with wide loads, all at once), else n entries at
+// ptr in the overflow area.  f(m, c) is called for every entry in order.
+template <class F>
+__device__ __forceinline__ void for_entries(const DecideArgs &a, int k, int n, int ptr, F &&f)
+{
+    if (n <= CORR_CAP) {
+        int m[CORR_CAP];
+        double c[CORR_CAP];
+        const int4 *pm = reinterpret_cast<const int4 *>(a.pool_m + (size_t)k * CORR_CAP);
+        const double2 *pc = reinterpret_cast<const double2 *>(a.pool_c + (size_t)k * CORR_CAP);
+#pragma unroll
+        for (int i = 0; i < CORR_CAP / 4; ++i) {
+            if (4 * i < n) {
+                const int4 v = ld_i4(pm + i);
+                m[4 * i] = v.x;
+                m[4 * i + 1] = v.y;
+                m[4 * i + 2] = v.z;
+                m[4 * i + 3] = v.w;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < CORR_CAP / 2; ++i) {
+            if (2 * i < n) {
+                const double2 v = ld_d2(pc + i);
+                c[2 * i] = v.x;
+                c[2 * i + 1] = v.y;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < CORR_CAP; ++i)
+            if (i < n) f(m[i], c[i]);
+    } else {
+        for (int i = 0; i < n; ++i) f(ldg(a.pool_m + ptr + i), ldg(a.pool_c + ptr + i));
+    }
+}
+
 // Decide batch b -- acc_k = metropolis(dE0_k + sum_{m<k} acc_m C_km), which
 // is the sequential chain -- and commit it.
 //
-// Passes over all open trials at once: a trial whose earlier interacting
-// trials are all decided gets its exact dE and is decided; otherwise its
-// dE lies between the sums with the open terms' negative (resp. positive)
-// parts, and when the test gives the same answer at both ends (with a
-// margin far above the rounding of the sums) that is its decision whatever
-// the open trials do.  Every pass decides at least the earliest open trial,
-// so the loop ends; decisions do not depend on the pass in which they are
-// made, so the result is deterministic and equals the in-order chain.
-// When `next.kb` > 0 the next batch is proposed afterwards (used when its
-// units may overlap this batch's).
+// A trial whose earlier interacting trials are all decided gets its exact
+// dE and is decided; otherwise its dE lies between the sums with the open
+// terms' negative (resp. positive) parts, and when the test gives the same
+// answer at both ends (with a margin far above the rounding of the sums)
+// that is its decision whatever the open trials do.  The first pass needs
+// no other decision and runs while the entries are loaded; later passes
+// visit only the open trials.  Every pass decides at least the earliest
+// open trial, so the loop ends; decisions do not depend on the pass in which
+// they are made, so the result is deterministic and equals the in-order
+// chain.  When `next.kb` > 0 the next batch is proposed afterwards (used
+// when its units may overlap this batch's).
 __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeArgs &next)
 {
-    __shared__ double s_e[KMAX];     // dE0, then the final dE
-    __shared__ double s_u[KMAX];     // acceptance threshold -kT ln u
-    __shared__ int s_off[KMAX];      // first entry of trial k in the LDS pool
+    __shared__ double s_e[KMAX];      // dE0, then the final dE
+    __shared__ double s_u[KMAX];      // acceptance threshold -kT ln u
     __shared__ int s_n[KMAX];
-    __shared__ int s_ptr[KMAX];      // first entry of trial k in the global pool
+    __shared__ int s_ptr[KMAX];
     __shared__ int s_a0[KMAX];
+    __shared__ unsigned char s_na[KMAX];
     __shared__ unsigned char s_st[KMAX];
     __shared__ unsigned char s_nx[KMAX];
-    __shared__ int s_pm[DEC_POOL_LDS];
-    __shared__ double s_pc[DEC_POOL_LDS];
+    __shared__ unsigned short s_open[KMAX];
     __shared__ int s_wave[DEC_THREADS / 64 + 1];
     __shared__ double s_red_d[DEC_THREADS / 64];
     __shared__ long long s_red_a[DEC_THREADS / 64], s_red_t[DEC_THREADS / 64];
@@ -941,67 +979,69 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
     const int kb = a.kb;
 
     if (kb > 0) {
-        // stage per-trial data; each thread owns trials tid, tid + DEC_THREADS, ...
-        int my_n = 0;
+        // trial data and the first pass (needs no other decision)
+        int my_open = 0;
         for (int k = tid; k < kb; k += DEC_THREADS) {
-            const int n = a.corr_n[k];
-            const int4 ids = *reinterpret_cast<const int4 *>(&a.trials[k].unit);
-            s_n[k] = n;
-            s_ptr[k] = a.corr_ptr[k];
-            s_e[k] = a.dE0[k];
-            s_u[k] = accept_threshold(a.trials[k].u_acc, a.kT);
-            s_a0[k] = ids.y;
-            s_st[k] = ST_OPEN;
-            my_n += n;
-        }
-        const int my_off = block_exscan(my_n, s_wave);
-        int o = my_off;
-        for (int k = tid; k < kb; k += DEC_THREADS) {
-            const int n = s_n[k], ptr = s_ptr[k];
-            s_off[k] = o;
-            for (int i = 0; i < n && o + i < DEC_POOL_LDS; ++i) {
-                s_pm[o + i] = a.pool_m[ptr + i];
-                s_pc[o + i] = a.pool_c[ptr + i];
+            const int n = ldg(a.corr_n + k);
+            const int ptr = ldg(a.corr_ptr + k);
+            const double e0 = ldg(a.dE0 + k);
+            const nd::Trial &T = a.trials[k];
+            const int4 ids = ld_i4(reinterpret_cast<const int4 *>(&T.unit));
+            const double thr = accept_threshold(ldg(&T.u_acc), a.kT);
+            double lo = 0.0, hi = 0.0, mag = fabs(e0);
+            bool any = false;
+            for_entries(a, k, n, ptr, [&](int m, double c) {
+                const bool v = m >= 0;
+                any |= v;
+                lo += v ? fmin(c, 0.0) : 0.0;
+                hi += v ? fmax(c, 0.0) : 0.0;
+                mag += v ? fabs(c) : 0.0;
+            });
+            unsigned char d;
+            if (!any) {
+                d = metropolis(e0, thr) ? ST_ACC : ST_REJ;
+            } else {
+                const double eps = 1e-12 * mag;
+                const bool alo = metropolis(e0 + lo - eps, thr), ahi = metropolis(e0 + hi + eps, thr);
+                d = alo == ahi ? (alo ? ST_ACC : ST_REJ) : ST_OPEN;
             }
-            o += n;
+            s_e[k] = e0;
+            s_u[k] = thr;
+            s_n[k] = n;
+            s_ptr[k] = ptr;
+            s_a0[k] = ids.y;
+            s_na[k] = (unsigned char)ids.z;
+            s_st[k] = d;
+            my_open += d == ST_OPEN;
         }
-        __syncthreads();
         if (tid == 0) *a.ovf_fill = 0;  // overflow area is free for the next batch
         if (tid < N_SLAB) a.slab_cnt[tid] = 0;  // the scan of this batch is done with its lists
 
-        // entry i of trial k: from LDS when staged, else from the global pool
-        auto entry = [&](int k, int i, int &m, double &c) {
-            const int li = s_off[k] + i;
-            if (li < DEC_POOL_LDS) {
-                m = s_pm[li];
-                c = s_pc[li];
-            } else {
-                m = a.pool_m[s_ptr[k] + i];
-                c = a.pool_c[s_ptr[k] + i];
-            }
-        };
-
+        // later passes over the open trials only
         for (;;) {
-            int open_left = 0;
-            for (int k = tid; k < kb; k += DEC_THREADS) {
-                if (s_st[k] != ST_OPEN) continue;
-                const int n = s_n[k];
+            // list the open trials (in trial order)
+            const int off = block_exscan(my_open, s_wave);  // ends with a barrier
+            const int n_open = s_wave[DEC_THREADS / 64];
+            if (n_open == 0) break;
+            {
+                int o = off;
+                for (int k = tid; k < kb; k += DEC_THREADS)
+                    if (s_st[k] == ST_OPEN) s_open[o++] = (unsigned short)k;
+            }
+            __syncthreads();
+            for (int i = tid; i < n_open; i += DEC_THREADS) {
+                const int k = s_open[i];
                 double e = s_e[k], lo = 0.0, hi = 0.0, mag = fabs(e);
                 bool all = true;
-                for (int i = 0; i < n; ++i) {
-                    int m;
-                    double c;
-                    entry(k, i, m, c);
-                    if (m < 0) continue;
-                    const unsigned char st = s_st[m];
-                    if (st == ST_ACC) {
-                        e += c;
-                    } else if (st == ST_OPEN) {
-                        all = false;
-                        if (c < 0.0) lo += c; else hi += c;
-                    }
-                    mag += fabs(c);
-                }
+                for_entries(a, k, s_n[k], s_ptr[k], [&](int m, double c) {
+                    const unsigned char st = m >= 0 ? s_st[m] : ST_REJ;
+                    const bool open = m >= 0 && st == ST_OPEN;
+                    e += (m >= 0 && st == ST_ACC) ? c : 0.0;
+                    all &= !open;
+                    lo += open ? fmin(c, 0.0) : 0.0;
+                    hi += open ? fmax(c, 0.0) : 0.0;
+                    mag += m >= 0 ? fabs(c) : 0.0;
+                });
                 const double thr = s_u[k];
                 unsigned char d = ST_OPEN;
                 if (all) {
@@ -1012,12 +1052,15 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                     if (alo == ahi) d = alo ? ST_ACC : ST_REJ;
                 }
                 s_nx[k] = d;
-                open_left |= (d == ST_OPEN);
             }
             __syncthreads();
-            for (int k = tid; k < kb; k += DEC_THREADS)
-                if (s_st[k] == ST_OPEN) s_st[k] = s_nx[k];
-            if (!__syncthreads_or(open_left)) break;
+            my_open = 0;
+            for (int i = tid; i < n_open; i += DEC_THREADS) {
+                const int k = s_open[i];
+                s_st[k] = s_nx[k];
+            }
+            __syncthreads();
+            for (int k = tid; k < kb; k += DEC_THREADS) my_open += s_st[k] == ST_OPEN;
         }
 
         // final dE (the same in-order sum as an exact decision), counters, trace
@@ -1025,16 +1068,11 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
         long long nacc = 0, ntie = 0;
         for (int k = tid; k < kb; k += DEC_THREADS) {
             double e = s_e[k];
-            const int n = s_n[k];
-            for (int i = 0; i < n; ++i) {
-                int m;
-                double c;
-                entry(k, i, m, c);
-                if (m >= 0 && s_st[m] == ST_ACC) e += c;
-            }
-            s_e[k] = e;
+            for_entries(a, k, s_n[k], s_ptr[k], [&](int m, double c) {
+                e += (m >= 0 && s_st[m] == ST_ACC) ? c : 0.0;
+            });
             const bool acc = s_st[k] == ST_ACC;
-            const double S = a.S0[k] + (double)a.corr_s[k];
+            const double S = ldg(a.S0 + k) + (double)ldg(a.corr_s + k);
             const double thr = s_u[k];
             // |ln u + dE/kT| < tie_rel S / kT, i.e. |dE - (-kT ln u)| < tie_rel S (u > 0)
             if (thr != 745.13321910194122 * a.kT && fabs(e - thr) < a.tie_rel * S) ++ntie;
@@ -1047,33 +1085,53 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
             if (a.tr_acc) a.tr_acc[k] = acc ? 1 : 0;
             if (a.tr_unit) a.tr_unit[k] = a.trials[k].unit;
         }
-        // commit: one item per (trial, atom)
+        // commit: one item per (trial, atom), loads of four items issued together
         float dmax = 0.0f;
         const int max_na = a.max_na;
-        for (int it = tid; it < kb * max_na; it += DEC_THREADS) {
-            const int k = it / max_na, at = it - k * max_na;
-            if (s_st[k] != ST_ACC) continue;
-            const nd::Trial &T = a.trials[k];
-            if (at >= T.na) continue;
-            const int i = s_a0[k] + at;
-            const float4 hi = T.new_hi[at];
-            const float4 lo = T.new_lo[at];
-            const float x0 = T.new_x[at][0], x1 = T.new_x[at][1], x2 = T.new_x[at][2];
-            a.xyz[i] = x0;
-            a.xyz[a.N + i] = x1;
-            a.xyz[2 * a.N + i] = x2;
-            a.pos4[i] = hi;
-            a.poslo[i] = lo;
-            if (a.cell_slot) {
-                const int sl = a.cell_slot[i];
-                a.spos4[sl] = hi;
-                a.sposlo[sl] = lo;
-                const float4 r = a.sref[sl];
-                float dx = hi.x - r.x, dy = hi.y - r.y, dz = hi.z - r.z;
-                dx -= rintf(dx);
-                dy -= rintf(dy);
-                dz -= rintf(dz);
-                dmax = fmaxf(dmax, sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1e-6f);
+        const int n_items = kb * max_na;
+        constexpr int CU = 4;
+        for (int base = tid; base < n_items; base += CU * DEC_THREADS) {
+            int idx[CU], slot[CU];
+            float4 hi[CU], lo[CU];
+            float nx[CU][3];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                const int it = base + u * DEC_THREADS;
+                idx[u] = -1;
+                if (it < n_items) {
+                    const int k = it / max_na, at = it - k * max_na;
+                    if (s_st[k] == ST_ACC && at < s_na[k]) {
+                        const nd::Trial &T = a.trials[k];
+                        idx[u] = s_a0[k] + at;
+                        hi[u] = ld4(&T.new_hi[at]);
+                        lo[u] = ld4(&T.new_lo[at]);
+                        nx[u][0] = ldg(&T.new_x[at][0]);
+                        nx[u][1] = ldg(&T.new_x[at][1]);
+                        nx[u][2] = ldg(&T.new_x[at][2]);
+                        slot[u] = a.cell_slot ? ldg(a.cell_slot + idx[u]) : 0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                const int i = idx[u];
+                if (i < 0) continue;
+                a.xyz[i] = nx[u][0];
+                a.xyz[a.N + i] = nx[u][1];
+                a.xyz[2 * a.N + i] = nx[u][2];
+                a.pos4[i] = hi[u];
+                a.poslo[i] = lo[u];
+                if (a.cell_slot) {
+                    const int sl = slot[u];
+                    a.spos4[sl] = hi[u];
+                    a.sposlo[sl] = lo[u];
+                    const float4 r = ld4(a.sref + sl);
+                    float dx = hi[u].x - r.x, dy = hi[u].y - r.y, dz = hi[u].z - r.z;
+                    dx -= rintf(dx);
+                    dy -= rintf(dy);
+                    dz -= rintf(dz);
+                    dmax = fmaxf(dmax, sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1e-6f);
+                }
             }
         }
         for (int o2 = 32; o2 > 0; o2 >>= 1) {
@@ -1253,7 +1311,7 @@ namespace nd {
 
 int mc_batch_size(nd_box *b, const nd_mc_params *p)
 {
-    // about 12 interacting earlier trials expected for the last trial of a
+    // about 18 interacting earlier trials expected for the last trial of a
     // batch; at most KMAX and half the number of units
     int K;
     if (p->k_batch > 0) {
@@ -1262,7 +1320,7 @@ int mc_batch_size(nd_box *b, const nd_mc_params *p)
         const double ext = (b->max_na > 1 ? 1.2 : 0.0) + p->max_disp * 1.8;
         const double reach = b->rc + 2.0 * ext;
         const double f = (4.0 / 3.0) * M_PI * reach * reach * reach / (b->L * b->L * b->L);
-        K = (int)std::min(1e9, 12.0 / std::max(f, 1e-9));
+        K = (int)std::min(1e9, 18.0 / std::max(f, 1e-9));
         K = std::min(K, std::max(1, b->n_units / 2));
     }
     return std::max(1, std::min({K, KMAX, b->n_units}));

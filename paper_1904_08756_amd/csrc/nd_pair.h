@@ -26,6 +26,20 @@ __device__ __forceinline__ float4 ld4(const float4 *p)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+__device__ __forceinline__ int4 ld_i4(const int4 *p)
+{
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i v = *(const ND_GLOBAL_AS v4i *)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ double2 ld_d2(const double2 *p)
+{
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    const v2d v = *(const ND_GLOBAL_AS v2d *)p;
+    return make_double2(v.x, v.y);
+}
+
 template <class T>
 __device__ __forceinline__ T ldg(const T *p)
 {
