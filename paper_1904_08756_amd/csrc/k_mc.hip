@@ -350,14 +350,11 @@ __global__ void k_mc_reduce(const double *__restrict__ partial, int n_jb, int kc
 
 // Exact pair energy from the FP64 fractional displacement d = s_j - s_a
 // (the same arithmetic as pair_u_exact); false beyond r_cut.
-__device__ __forceinline__ bool pair_u_disp(const PairCtx &c, double ex, double ey, double ez, int row, float &u)
+__device__ __forceinline__ bool pair_u_img(const PairCtx &c, double ex, double ey, double ez, int row, float &u)
 {
-    ex -= rint(ex);
-    ey -= rint(ey);
-    ez -= rint(ez);
     const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
     if (!(r2 < c.rcf2)) return false;
-    const double t = sqrt(r2) * c.tscale;
+    const double t = nd::sqrt_nr(r2) * c.tscale;
     int i0 = (int)t;
     i0 = min(i0, c.n_pts - 2);
     const float f = (float)(t - (double)i0);
@@ -366,6 +363,14 @@ __device__ __forceinline__ bool pair_u_disp(const PairCtx &c, double ex, double 
     const float u1 = tr[i0 + 1];
     u = fmaf(f, u1 - u0, u0);
     return true;
+}
+
+__device__ __forceinline__ bool pair_u_disp(const PairCtx &c, double ex, double ey, double ez, int row, float &u)
+{
+    ex -= rint(ex);
+    ey -= rint(ey);
+    ez -= rint(ez);
+    return pair_u_img(c, ex, ey, ez, row, u);
 }
 
 // ---------------------------------------------------------------- corrections
@@ -574,35 +579,58 @@ struct TrialAtoms {
 };
 
 // Survivors are kept in LDS as their current position, hi (with .w =
-// slot << 2 | species, slot < 2^29) and lo.
-template <int MAXNU>
+// slot << 2 | species, slot < 2^29) and lo.  CIMG: the trial's atoms (taken
+// at their images nearest the centre) lie within rad of the centre and
+// r_cut + 2 rad < L/2, so the survivor's image nearest the centre is its
+// nearest image to every atom of the trial along each axis, and the
+// per-pair image shift is dropped (the displacements differ from the
+// per-pair ones only by the rounding of the shifted positions, ~1e-16).
+template <int MAXNU, bool CIMG>
 __device__ __forceinline__ void cell_flush(const PairCtx &c, const TrialAtoms &ta, int tna, const float4 *list,
-                                           const float4 *listlo, int nlist, int lane, double &e, double &s)
+                                           const float4 *listlo, int nlist, int lane, double &e, double &s,
+                                           double cx, double cy, double cz)
 {
     for (int i = lane; i < nlist; i += 64) {
         const float4 q = list[i];
         const int w = __float_as_int(q.w);
         const float4 ql = listlo[i];
-        const double sx = (double)q.x + (double)ql.x, sy = (double)q.y + (double)ql.y,
-                     sz = (double)q.z + (double)ql.z;
+        double sx = (double)q.x + (double)ql.x, sy = (double)q.y + (double)ql.y, sz = (double)q.z + (double)ql.z;
+        if (CIMG) {
+            sx -= rint(sx - cx);
+            sy -= rint(sy - cy);
+            sz -= rint(sz - cz);
+        }
         const int sj = w & 3;
 #pragma unroll
         for (int at = 0; at < MAXNU; ++at) {
             if (at < tna) {
                 float u;
                 const int rn = c.prow[ta.rb[2 * at + 1] + sj];
-                if (pair_u_disp(c, sx - ta.x[2 * at + 1], sy - ta.y[2 * at + 1], sz - ta.z[2 * at + 1], rn, u)) {
+                const double nx = sx - ta.x[2 * at + 1], ny = sy - ta.y[2 * at + 1], nz = sz - ta.z[2 * at + 1];
+                if (CIMG ? pair_u_img(c, nx, ny, nz, rn, u) : pair_u_disp(c, nx, ny, nz, rn, u)) {
                     e += (double)u;
                     s += (double)fabsf(u);
                 }
                 const int ro = c.prow[ta.rb[2 * at] + sj];
-                if (pair_u_disp(c, sx - ta.x[2 * at], sy - ta.y[2 * at], sz - ta.z[2 * at], ro, u)) {
+                const double ox = sx - ta.x[2 * at], oy = sy - ta.y[2 * at], oz = sz - ta.z[2 * at];
+                if (CIMG ? pair_u_img(c, ox, oy, oz, ro, u) : pair_u_disp(c, ox, oy, oz, ro, u)) {
                     e -= (double)u;
                     s += (double)fabsf(u);
                 }
             }
         }
     }
+}
+
+template <int MAXNU>
+__device__ __forceinline__ void cell_flush_any(bool cimg, const PairCtx &c, const TrialAtoms &ta, int tna,
+                                               const float4 *list, const float4 *listlo, int nlist, int lane,
+                                               double &e, double &s, double cx, double cy, double cz)
+{
+    if (cimg)
+        cell_flush<MAXNU, true>(c, ta, tna, list, listlo, nlist, lane, e, s, cx, cy, cz);
+    else
+        cell_flush<MAXNU, false>(c, ta, tna, list, listlo, nlist, lane, e, s, cx, cy, cz);
 }
 
 // Distance from c to the nearest periodic image of the cell interval
@@ -630,13 +658,26 @@ __device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const Pa
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const nd::Trial *T = a.trials + k;
     const int ta0 = T->a0, tna = T->na;
+    const float cx = T->cen[0], cy = T->cen[1], cz = T->cen[2];
+    const float surv = a.rcf + T->rad + 4e-6f;
+    const float surv2 = surv * surv;
+    // r_cut + 2 rad < L/2: every pair term of the trial can take the nearest
+    // image of its survivor relative to the centre (see cell_flush)
+    const bool cimg = a.rcf + 2.0f * T->rad + 1e-4f < 0.5f;
     if (tid < 2 * tna) {
         const int at = tid >> 1;
         const float4 h = ld4((tid & 1) ? &T->new_hi[at] : &T->old_hi[at]);
         const float4 l = ld4((tid & 1) ? &T->new_lo[at] : &T->old_lo[at]);
-        ta.x[tid] = (double)h.x + (double)l.x;
-        ta.y[tid] = (double)h.y + (double)l.y;
-        ta.z[tid] = (double)h.z + (double)l.z;
+        double x = (double)h.x + (double)l.x, y = (double)h.y + (double)l.y, z = (double)h.z + (double)l.z;
+        if (cimg) {
+            // the atom's image nearest the centre (atoms are wrapped one by one)
+            x -= rint(x - (double)cx);
+            y -= rint(y - (double)cy);
+            z -= rint(z - (double)cz);
+        }
+        ta.x[tid] = x;
+        ta.y[tid] = y;
+        ta.z[tid] = z;
         ta.rb[tid] = __float_as_int(h.w) * c.M;
     }
     if (tid < tna) ta.sl[tid] = ldg(a.slot + ta0 + tid);
@@ -644,9 +685,6 @@ __device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const Pa
     int own[MAXNU];
 #pragma unroll
     for (int at = 0; at < MAXNU; ++at) own[at] = at < tna ? ta.sl[at] : -1;
-    const float cx = T->cen[0], cy = T->cen[1], cz = T->cen[2];
-    const float surv = a.rcf + T->rad + 4e-6f;
-    const float surv2 = surv * surv;
     const float reach = surv + *a.drift + 1e-6f;
     const float reach2 = reach * reach;
     const int nc = a.nc;
@@ -755,14 +793,14 @@ __device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const Pa
             }
             if (nlist > CS_LIST - 128) {
                 __builtin_amdgcn_wave_barrier();
-                cell_flush<MAXNU>(c, ta, tna, list, listlo, nlist, lane, e, s);
+                cell_flush_any<MAXNU>(cimg, c, ta, tna, list, listlo, nlist, lane, e, s, cx, cy, cz);
                 __builtin_amdgcn_wave_barrier();
                 nlist = 0;
             }
         }
     }
     __builtin_amdgcn_wave_barrier();
-    cell_flush<MAXNU>(c, ta, tna, list, listlo, nlist, lane, e, s);
+    cell_flush_any<MAXNU>(cimg, c, ta, tna, list, listlo, nlist, lane, e, s, cx, cy, cz);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         e += __shfl_xor(e, o);

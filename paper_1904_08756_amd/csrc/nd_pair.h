@@ -94,6 +94,18 @@ __device__ __forceinline__ float r2_hi(float4 p, float4 q)
     return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
+// Square root of a non-negative FP64 value to about 2e-14 relative: the
+// FP32 square root refined by one Newton step in FP64 (the step's 1/(2 r0)
+// from the FP32 reciprocal).  0 when the FP32 root is 0.
+__device__ __forceinline__ double sqrt_nr(double r2)
+{
+    const float rf = __builtin_amdgcn_sqrtf((float)r2);
+    const double r0 = (double)rf;
+    const double d = fma(-r0, r0, r2);
+    const double r = fma(d, (double)(0.5f * __builtin_amdgcn_rcpf(rf)), r0);
+    return rf > 0.0f ? r : 0.0;
+}
+
 // Exact-path pair energy of trial atom p (FP64 fractional position ps,
 // species row base rb) with atom q (hi, lo).  Returns false beyond r_cut.
 __device__ __forceinline__ bool pair_u_exact(const PairCtx &c, double psx, double psy, double psz, int rb,
@@ -107,7 +119,7 @@ __device__ __forceinline__ bool pair_u_exact(const PairCtx &c, double psx, doubl
     ez -= rint(ez);
     const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
     if (!(r2 < c.rcf2)) return false;
-    const double t = sqrt(r2) * c.tscale;
+    const double t = sqrt_nr(r2) * c.tscale;
     int i0 = (int)t;
     i0 = min(i0, c.n_pts - 2);
     const float f = (float)(t - (double)i0);
