@@ -160,6 +160,35 @@ def atomic_box(counts, L: float, seed: int, names=(), name: str = "atomic") -> B
                tuple(names), {"seed": seed})
 
 
+def mixed_unit_box(n_units: int, L: float, seed: int, max_atoms: int = 4, n_species: int = 3,
+                   name: str = "mixed") -> Box:
+    """Rigid units of 1..max_atoms atoms (uniform), species uniform per atom.
+
+    Each unit's atoms sit at random offsets of length 0.8-1.2 A around a
+    uniform centre; atoms are wrapped into [0, L) one by one, so units
+    straddle the box faces.  A stand-in for molecules of several sizes.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = rng.integers(1, max_atoms + 1, n_units)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    n = int(offs[-1])
+    pos = np.empty((3, n))
+    for u in range(n_units):
+        c = rng.random(3) * L
+        for a in range(offs[u], offs[u + 1]):
+            v = rng.normal(size=3)
+            v *= rng.uniform(0.8, 1.2) / np.linalg.norm(v)
+            pos[:, a] = c + (v if a > offs[u] else 0.0)
+    species = rng.integers(0, n_species, n).astype(np.uint8)
+    xyz = _wrap_f32(pos, L)
+    return Box(name, float(L), species, offs, np.ascontiguousarray(xyz), n_species, (), {"seed": seed})
+
+
+def mixed_tables(r_cut: float = 8.0, h: float = 0.01) -> Tables:
+    """Three species with LJ (3.0/0.5, 3.4/0.3, 2.5/0.8 A, kJ/mol), charges +0.5, -0.3, -0.2 e."""
+    return potential_table(3, r_cut, h, [(3.0, 0.5), (3.4, 0.3), (2.5, 0.8)], [0.5, -0.3, -0.2])
+
+
 def potential_table(m: int, r_cut: float, h: float, lj, charges, r_min: float = 0.5,
                     shift_lj: bool = True, emp=None) -> Tables:
     """Tabulate Lennard-Jones + truncated-shifted Coulomb (+ optional EMP).

@@ -240,6 +240,24 @@ def test_mc_cells_rebuild_across_sweeps(nd, orc):
     _mc_parity(nd, orc, box, T, params, 5, 0, 120 * 6, k_batch=50)
 
 
+@pytest.mark.parametrize("k_batch,scan", [(0, 0), (7, 0), (0, 1)])
+def test_mc_mixed_unit_sizes_match(nd, orc, k_batch, scan):
+    """Units of 1 to 4 atoms and three species (the widest unit template),
+    units straddling the box faces, r_cut + 2 rad < L/2."""
+    box = syn.mixed_unit_box(600, 30.0, 77)
+    T = syn.mixed_tables()
+    params = dict(kT=syn.kT_at(298.0), max_disp=0.25, max_rot=math.radians(12.0))
+    _mc_parity(nd, orc, box, T, params, 11, 0, 1500, k_batch=k_batch, scan=scan)
+
+
+def test_mc_mixed_units_small_box(nd, orc):
+    """Same mix where r_cut + 2 rad >= L/2 (every pair takes its own image)."""
+    box = syn.mixed_unit_box(150, 17.0, 78)
+    T = syn.mixed_tables()
+    params = dict(kT=syn.kT_at(298.0), max_disp=0.25, max_rot=math.radians(12.0))
+    _mc_parity(nd, orc, box, T, params, 12, 0, 600)
+
+
 def test_mc_scan_modes_agree(nd):
     box, T, mc = syn.config_c2()
     p_c = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"], scan=0)
