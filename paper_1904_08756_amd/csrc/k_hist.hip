@@ -66,7 +66,7 @@ struct HistArgs {
 // LDS layout of the histogram kernels.
 struct HistLds {
     double *jx;      // [3][TILE] j-tile coordinates
-    int *js;         // [TILE] j-tile species
+    int *jrow;       // [ND_MAX_SPECIES][TILE] byte offset of the histogram row of (species s, atom j)
     int *prow;       // [16] partial row offset of each species pair
     unsigned *hist;  // [P * nbins]
 };
@@ -75,11 +75,13 @@ __device__ __forceinline__ HistLds hist_lds(unsigned char *smem)
 {
     HistLds h;
     h.jx = reinterpret_cast<double *>(smem);
-    h.js = reinterpret_cast<int *>(h.jx + 3 * TILE);
-    h.prow = h.js + TILE;
+    h.jrow = reinterpret_cast<int *>(h.jx + 3 * TILE);
+    h.prow = h.jrow + ND_MAX_SPECIES * TILE;
     h.hist = reinterpret_cast<unsigned *>(h.prow + 16);
     return h;
 }
+
+constexpr size_t HIST_LDS_FIXED = sizeof(double) * 3 * TILE + sizeof(int) * (ND_MAX_SPECIES * TILE + 16);
 
 // Zero the LDS histogram and set the species-pair row offsets of box a.
 __device__ __forceinline__ void hist_begin(const HistArgs &a, const HistLds &h)
@@ -94,9 +96,12 @@ __device__ __forceinline__ void hist_begin(const HistArgs &a, const HistLds &h)
     __syncthreads();
 }
 
-// Every pair (i, j) of tile pair (I, J), i < j on the diagonal: nearest
-// image in FP64, r2 = fma(dz,dz, fma(dy,dy, dx*dx)), bin by the exact edge
-// test, one LDS atomic per counted pair.
+// Every pair (i, j) of tile pair (I, J), i < j on the diagonal, in FP64:
+// d = x_j - x_i per axis and its nearest-image length min(|d|, L - |d|)
+// (the same number as d, or d -/+ L past +/-L/2, up to sign), r2 =
+// fma(dz,dz, fma(dy,dy, dx*dx)); bin from an FP32 square root, settled by
+// the exact FP64 edge test when it lies near an edge; one LDS atomic per
+// counted pair.
 __device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, int I, int J)
 {
     const int tid = threadIdx.x;
@@ -111,41 +116,43 @@ __device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, i
         zi = (double)a.xyz[2 * N + i];
         si = a.sp[i];
     }
-    __syncthreads();  // previous tile's readers are done with jx/js
+    __syncthreads();  // previous tile's readers are done with jx/jrow
     const int j = J * TILE + tid;
     if (j < N) {
         h.jx[tid] = (double)a.xyz[j];
         h.jx[TILE + tid] = (double)a.xyz[N + j];
         h.jx[2 * TILE + tid] = (double)a.xyz[2 * N + j];
-        h.js[tid] = a.sp[j];
+        const int sj = a.sp[j];
+        for (int s = 0; s < a.M; ++s) h.jrow[s * TILE + tid] = h.prow[s * a.M + sj] * (int)sizeof(unsigned);
     }
     __syncthreads();
     const int jn = min(TILE, N - J * TILE);
     const int jstart = (I == J) ? tid + 1 : 0;  // diagonal tile: pairs j > i only
     if (!iv) return;
-    const int rowbase = si * a.M;
     const double *jx = h.jx;
+    const int *jrow = h.jrow + si * TILE;
+    const double L = a.L;
 #pragma unroll 4
     for (int jj = jstart; jj < jn; ++jj) {
-        double dx = jx[jj] - xi;
-        double dy = jx[TILE + jj] - yi;
-        double dz = jx[2 * TILE + jj] - zi;
-        dx = fma(-rint(dx * a.invL), a.L, dx);
-        dy = fma(-rint(dy * a.invL), a.L, dy);
-        dz = fma(-rint(dz * a.invL), a.L, dz);
-        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        const double ax = fabs(jx[jj] - xi);
+        const double ay = fabs(jx[TILE + jj] - yi);
+        const double az = fabs(jx[2 * TILE + jj] - zi);
+        const double mx = fmin(ax, L - ax);
+        const double my = fmin(ay, L - ay);
+        const double mz = fmin(az, L - az);
+        const double r2 = fma(mz, mz, fma(my, my, mx * mx));
         if (r2 < a.e2max) {
             // candidate bin from an FP32 square root; exact FP64 edge test
             // only when the candidate lies within edge_eps of a bin edge
             const float tb = __builtin_amdgcn_sqrtf((float)r2) * a.inv_dr_f;
             int k = (int)tb;
-            const float fr = tb - (float)k;
-            if (fr < a.edge_eps || fr > 1.0f - a.edge_eps) {
+            const float fr = __builtin_amdgcn_fractf(tb);
+            if (fabsf(fr - 0.5f) > 0.5f - a.edge_eps) {
                 const int kk = (int)rintf(tb);
                 const double e = (double)kk * a.dr;
                 k = (r2 >= e * e) ? kk : kk - 1;
             }
-            atomicAdd(&h.hist[h.prow[rowbase + h.js[jj]] + k], 1u);
+            atomicAdd(reinterpret_cast<unsigned *>(reinterpret_cast<unsigned char *>(h.hist) + jrow[jj]) + k, 1u);
         }
     }
 }
@@ -387,7 +394,7 @@ HistArgs make_hist_args(const nd_box *b, double dr, int nbins)
 
 size_t hist_lds_bytes(int nq)
 {
-    const size_t lds = sizeof(double) * 3 * TILE + sizeof(int) * (TILE + 16) + sizeof(unsigned) * (size_t)nq;
+    const size_t lds = HIST_LDS_FIXED + sizeof(unsigned) * (size_t)nq;
     if (lds > 160 * 1024) nd::fail(ND_E_UNSUPPORTED, "histogram does not fit in LDS (P*nbins too large)");
     return lds;
 }
