@@ -280,12 +280,20 @@ def main():
         t_plain = timeit(plain)
         t_fb = timeit(fwd_bwd)
         t_forces = timeit(lambda: nd.forces(g))
+        g.set_profiling(True)
+        fwd_bwd()
+        torch.cuda.synchronize()
+        k_fwd = g.profile("hist_broad")[1]
+        k_bwd = g.profile("hist_broad_bwd")[1]
+        g.set_profiling(False)
         result["forms"] = {
             "plain_hist_g_sq_ms": t_plain * 1e3,
             "fwd_bwd_ms": t_fb * 1e3,
             "fwd_bwd_over_plain": t_fb / t_plain,
             "forces_ms": t_forces * 1e3,
             "fwd_bwd_pairs_per_s": 2 * n_pairs / t_fb,
+            "k_hist_broad_ms": k_fwd,
+            "k_hist_broad_bwd_ms": k_bwd,
         }
         log("forms done")
         result["forms"]["batched"] = batched_leg(nd, syn, np, torch)

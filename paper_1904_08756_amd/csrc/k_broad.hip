@@ -5,21 +5,58 @@
 // Broadening: a pair at distance r adds to bin k the Gaussian mass between
 // its edges, w_k(r) = Phi((e_{k+1}-r)/s) - Phi((e_k-r)/s), e_k = k dr, for
 // the bins that intersect [r - 6s, r + 6s].  Each edge needs one tail mass
-// T(e) = Phi(-|e - r|/s) = erfc(|e - r|/(s sqrt 2))/2, from which every bin
-// weight follows without cancellation:
-//   bin right of r: T(e_k) - T(e_{k+1});  left of r: T(e_{k+1}) - T(e_k);
-//   bin containing r: 1 - T(e_k) - T(e_{k+1}).
-// Distances are FP64 from the float32 coordinates; per-pair weights FP32;
-// sums FP64.
+// T(x) = Phi(-|x|), x = (e - r)/s, from which every bin weight follows
+// without cancellation:
+//   bin right of r: T(x_k) - T(x_{k+1});  left of r: T(x_{k+1}) - T(x_k);
+//   bin containing r: 1 - T(x_k) - T(x_{k+1}).
+// The tail is taken as T(x) = phi(x) R(x) with phi the Gaussian density
+// and R the Mills ratio T/phi, a smooth function tabulated on [0, 8] (step
+// 1/32, cubic Taylor coefficients from R' = xR - 1; beyond 8, T < 7e-16 is
+// dropped).  Edge offsets x = (k - k_r - f) dr/s come from the pair's bin
+// k_r and fraction f of r/dr.  Distances are FP64 from the float32
+// coordinates; per-pair weights FP32; sums FP64.
 #include "nd_internal.h"
 #include "nd_pair.h"
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace {
 
 constexpr int TILE = 256;
+constexpr int MILLS_PER_UNIT = 32;                   // table points per unit of x
+constexpr float MILLS_XMAX = 8.0f;
+constexpr int MILLS_N = 8 * MILLS_PER_UNIT + 1;      // points 0, 1/32, ..., 8
+constexpr float NEG_HALF_LOG2E = -0.72134752044448170f;  // -log2(e)/2
+constexpr float INV_SQRT_2PI = 0.39894228040143268f;
+
+// Upper-tail mass Phi(-ax) for ax >= 0 from the Mills-ratio table in LDS
+// (c.x..c.w: R and its first three Taylor coefficients at the nearest point).
+__device__ __forceinline__ float gauss_tail(float ax, const float4 *mills)
+{
+    const float phi = __builtin_amdgcn_exp2f(ax * ax * NEG_HALF_LOG2E) * INV_SQRT_2PI;
+    const int i = min((int)fmaf(ax, (float)MILLS_PER_UNIT, 0.5f), MILLS_N - 1);
+    const float4 c = mills[i];
+    const float d = ax - (float)i * (1.0f / MILLS_PER_UNIT);
+    const float R = fmaf(d, fmaf(d, fmaf(d, c.w, c.z), c.y), c.x);
+    return ax < MILLS_XMAX ? phi * R : 0.0f;
+}
+
+// Gaussian density at x (any sign).
+__device__ __forceinline__ float gauss_pdf(float x)
+{
+    return __builtin_amdgcn_exp2f(x * x * NEG_HALF_LOG2E) * INV_SQRT_2PI;
+}
+
+// Nearest-image distance of float32 positions in FP64 (min(|d|, L - |d|)
+// per axis) and the displacement d = x_i - x_j with the sign of that image.
+__device__ __forceinline__ double nearest_r2(double dx, double dy, double dz, double L)
+{
+    const double ax = fabs(dx), ay = fabs(dy), az = fabs(dz);
+    const double mx = fmin(ax, L - ax), my = fmin(ay, L - ay), mz = fmin(az, L - az);
+    return fma(mz, mz, fma(my, my, mx * mx));
+}
 
 __device__ __forceinline__ void tri_index(long long t, int nt, int &I, int &J)
 {
@@ -40,7 +77,9 @@ struct BroadArgs {
     int N, M, P, nbins, nt;
     long long ntp;
     double L, invL, half2;  // half2 = (L/2)^2
-    double dr, inv_dr, inv_sigma_sqrt2, six_sigma;
+    double dr, inv_dr, six_sigma;
+    float beta;              // dr / sigma
+    const float4 *mills;     // [MILLS_N] Mills-ratio table
     double *partial;  // [gridDim.x][P*nbins]
 };
 
@@ -49,15 +88,18 @@ __global__ __launch_bounds__(TILE) void k_hist_broad(BroadArgs a)
     extern __shared__ __align__(16) unsigned char smem[];
     double *hist = reinterpret_cast<double *>(smem);                   // [P*nbins]
     double *jx = hist + (size_t)a.P * a.nbins;                          // [3][TILE]
-    int *js = reinterpret_cast<int *>(jx + 3 * TILE);                  // [TILE]
+    float4 *mills = reinterpret_cast<float4 *>(jx + 3 * TILE);         // [MILLS_N]
+    int *js = reinterpret_cast<int *>(mills + MILLS_N);                 // [TILE]
     int *prow = js + TILE;                                              // [16]
     const int tid = threadIdx.x;
     const int nq = a.P * a.nbins;
     for (int q = tid; q < nq; q += TILE) hist[q] = 0.0;
+    for (int q = tid; q < MILLS_N; q += TILE) mills[q] = nd::ld4(a.mills + q);
     if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.nbins;
     __syncthreads();
     const int N = a.N;
     const double rmax_win = (double)a.nbins * a.dr + a.six_sigma;
+    const float beta = a.beta;
     for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
         int I, J;
         tri_index(t, a.nt, I, J);
@@ -85,34 +127,30 @@ __global__ __launch_bounds__(TILE) void k_hist_broad(BroadArgs a)
         if (!iv) continue;
         const int rowbase = si * a.M;
         for (int jj = jstart; jj < jn; ++jj) {
-            double dx = jx[jj] - xi, dy = jx[TILE + jj] - yi, dz = jx[2 * TILE + jj] - zi;
-            dx = fma(-rint(dx * a.invL), a.L, dx);
-            dy = fma(-rint(dy * a.invL), a.L, dy);
-            dz = fma(-rint(dz * a.invL), a.L, dz);
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            const double r2 = nearest_r2(jx[jj] - xi, jx[TILE + jj] - yi, jx[2 * TILE + jj] - zi, a.L);
             if (!(r2 < a.half2)) continue;
-            const double r = sqrt(r2);
+            const double r = nd::sqrt_nr(r2);
             if (!(r < rmax_win)) continue;
             int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
             int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
             k0 = max(k0, 0);
             k1 = min(k1, a.nbins - 1);
+            const double u = r * a.inv_dr;
+            const int kr = (int)u;
+            const float f = (float)(u - (double)kr);
             double *row = hist + prow[rowbase + js[jj]];
-            // tail mass at edge k0; offsets from r in FP64, tails in FP32
-            float xe = (float)(((double)k0 * a.dr - r) * a.inv_sigma_sqrt2);
-            float Tlo = 0.5f * erfcf(fabsf(xe));
-            bool lo_right = xe >= 0.0f;
+            // tail mass at edge k0: x = (e - r) / s
+            float x = ((float)(k0 - kr) - f) * beta;
+            float T = gauss_tail(fabsf(x), mills);
+            bool right = x >= 0.0f;
             for (int k = k0; k <= k1; ++k) {
-                const float xh = (float)(((double)(k + 1) * a.dr - r) * a.inv_sigma_sqrt2);
-                const float Thi = 0.5f * erfcf(fabsf(xh));
-                const bool hi_right = xh >= 0.0f;
-                float wk;
-                if (lo_right) wk = Tlo - Thi;
-                else if (!hi_right) wk = Thi - Tlo;
-                else wk = 1.0f - Tlo - Thi;
+                const float xh = ((float)(k + 1 - kr) - f) * beta;
+                const float Th = gauss_tail(fabsf(xh), mills);
+                const bool rh = xh >= 0.0f;
+                const float wk = right ? T - Th : (rh ? 1.0f - T - Th : Th - T);
                 atomicAdd(&row[k], (double)wk);
-                Tlo = Thi;
-                lo_right = hi_right;
+                T = Th;
+                right = rh;
             }
         }
     }
@@ -138,7 +176,7 @@ struct BackArgs {
     int N, M, P, nbins;
     double L, invL, half2;
     double dr, inv_dr, inv_sigma, six_sigma;
-    float norm;       // 1 / (sigma sqrt(2 pi))
+    float beta;       // dr / sigma
     int jchunk;
     double *partial;  // [gridDim.y][3][N]
 };
@@ -168,7 +206,7 @@ __global__ __launch_bounds__(TILE) void k_hist_broad_bwd(BackArgs a)
         si = a.sp[i];
     }
     const double rmax_win = (double)a.nbins * a.dr + a.six_sigma;
-    const float norm = a.norm;
+    const float beta = a.beta;
     double gx = 0.0, gy = 0.0, gz = 0.0;
     const int jbeg = blockIdx.y * a.jchunk;
     const int jend = min(N, jbeg + a.jchunk);
@@ -188,29 +226,31 @@ __global__ __launch_bounds__(TILE) void k_hist_broad_bwd(BackArgs a)
         for (int jj = 0; jj < jn; ++jj) {
             if (jt + jj == i) continue;
             double dx = xi - jx[jj], dy = yi - jx[TILE + jj], dz = zi - jx[2 * TILE + jj];
+            const double r2 = nearest_r2(dx, dy, dz, a.L);
+            if (!(r2 < a.half2) || r2 == 0.0) continue;
+            const double r = nd::sqrt_nr(r2);
+            if (!(r < rmax_win)) continue;
+            // signed nearest-image displacement x_i - x_j
             dx = fma(-rint(dx * a.invL), a.L, dx);
             dy = fma(-rint(dy * a.invL), a.L, dy);
             dz = fma(-rint(dz * a.invL), a.L, dz);
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            if (!(r2 < a.half2) || r2 == 0.0) continue;
-            const double r = sqrt(r2);
-            if (!(r < rmax_win)) continue;
             int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
             int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
             k0 = max(k0, 0);
             k1 = min(k1, a.nbins - 1);
+            const double u = r * a.inv_dr;
+            const int kr = (int)u;
+            const float f = (float)(u - (double)kr);
             const double *row = dA + prow[rowbase + js[jj]];
-            // dL/dr = sum_k A(k) (phi(x_k) - phi(x_{k+1})) / s, x_e = (e - r)/s
-            float xe = (float)(((double)k0 * a.dr - r) * a.inv_sigma);
-            float plo = __expf(-0.5f * xe * xe);
+            // dL/dr = sum_k A(k) (phi(x_k) - phi(x_{k+1})) / s, x = (e - r)/s
+            float plo = gauss_pdf(((float)(k0 - kr) - f) * beta);
             double dLdr = 0.0;
             for (int k = k0; k <= k1; ++k) {
-                const float xh = (float)(((double)(k + 1) * a.dr - r) * a.inv_sigma);
-                const float phi_hi = __expf(-0.5f * xh * xh);
-                dLdr += row[k] * (double)(norm * (plo - phi_hi));
+                const float phi_hi = gauss_pdf(((float)(k + 1 - kr) - f) * beta);
+                dLdr = fma(row[k], (double)(plo - phi_hi), dLdr);
                 plo = phi_hi;
             }
-            const double c = dLdr / r;
+            const double c = dLdr * a.inv_sigma / r;
             gx += c * dx;
             gy += c * dy;
             gz += c * dz;
@@ -337,6 +377,32 @@ int n_jchunks(nd_box *b)
     return want;
 }
 
+// Mills ratio R(x) = T(x)/phi(x), T the upper Gaussian tail, with its Taylor
+// coefficients R', R''/2 and R'''/6 at x = i/32, from R' = xR - 1,
+// R'' = (1 + x^2) R - x and R''' = (x^3 + 3x) R - x^2 - 2; computed in FP64
+// on the host and kept on each device for the life of the process.
+const float4 *mills_table(nd_box *b)
+{
+    static const float4 *dev_table[64] = {nullptr};
+    if (b->device < 0 || b->device >= 64) nd::fail(ND_E_INVALID, "device index out of range");
+    if (dev_table[b->device]) return dev_table[b->device];
+    std::vector<float4> h(MILLS_N);
+    for (int i = 0; i < MILLS_N; ++i) {
+        const double x = (double)i / MILLS_PER_UNIT;
+        const double T = 0.5 * std::erfc(x / std::sqrt(2.0));
+        const double phi = std::exp(-0.5 * x * x) / std::sqrt(2.0 * M_PI);
+        const double R = T / phi;
+        const double R1 = x * R - 1.0;
+        const double R2 = (1.0 + x * x) * R - x;
+        const double R3 = (x * x * x + 3.0 * x) * R - x * x - 2.0;
+        h[i] = make_float4((float)R, (float)R1, (float)(R2 / 2.0), (float)(R3 / 6.0));
+    }
+    float4 *d = static_cast<float4 *>(nd::dmalloc(sizeof(float4) * MILLS_N));
+    ND_HIP(hipMemcpy(d, h.data(), sizeof(float4) * MILLS_N, hipMemcpyHostToDevice));
+    dev_table[b->device] = d;
+    return d;
+}
+
 }  // namespace
 
 namespace nd {
@@ -357,10 +423,11 @@ void launch_hist_broad(nd_box *b, double dr, int nbins, double sigma, double *d_
     a.half2 = 0.25 * b->L * b->L;
     a.dr = dr;
     a.inv_dr = 1.0 / dr;
-    a.inv_sigma_sqrt2 = 1.0 / (sigma * std::sqrt(2.0));
     a.six_sigma = 6.0 * sigma;
+    a.beta = (float)(dr / sigma);
+    a.mills = mills_table(b);
     const int nq = a.P * nbins;
-    size_t lds = sizeof(double) * ((size_t)nq + 3 * TILE) + sizeof(int) * (TILE + 16);
+    size_t lds = sizeof(double) * ((size_t)nq + 3 * TILE) + sizeof(float4) * MILLS_N + sizeof(int) * (TILE + 16);
     if (lds > 160 * 1024) fail(ND_E_UNSUPPORTED, "broadened histogram does not fit in LDS");
     int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (lds + 1024)));
     long long G = (long long)cu_count(b->device) * per_cu;
@@ -392,7 +459,7 @@ void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, c
     a.inv_dr = 1.0 / dr;
     a.inv_sigma = 1.0 / sigma;
     a.six_sigma = 6.0 * sigma;
-    a.norm = (float)(1.0 / (sigma * std::sqrt(2.0 * M_PI)));
+    a.beta = (float)(dr / sigma);
     const int nch = n_jchunks(b);
     a.jchunk = (b->N + nch - 1) / nch;
     const int nib = (b->N + TILE - 1) / TILE;
