@@ -14,7 +14,9 @@
 // 1/32, cubic Taylor coefficients from R' = xR - 1; beyond 8, T < 7e-16 is
 // dropped).  Edge offsets x = (k - k_r - f) dr/s come from the pair's bin
 // k_r and fraction f of r/dr.  Distances are FP64 from the float32
-// coordinates; per-pair weights FP32; sums FP64.
+// coordinates; per-pair weights FP32; a block sums them as integers in
+// units of 2^-32 (exact and independent of order), the blocks' sums are
+// added in FP64.
 #include "nd_internal.h"
 #include "nd_pair.h"
 
@@ -86,14 +88,14 @@ struct BroadArgs {
 __global__ __launch_bounds__(TILE) void k_hist_broad(BroadArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    double *hist = reinterpret_cast<double *>(smem);                   // [P*nbins]
-    double *jx = hist + (size_t)a.P * a.nbins;                          // [3][TILE]
-    float4 *mills = reinterpret_cast<float4 *>(jx + 3 * TILE);         // [MILLS_N]
-    int *js = reinterpret_cast<int *>(mills + MILLS_N);                 // [TILE]
-    int *prow = js + TILE;                                              // [16]
+    unsigned long long *hist = reinterpret_cast<unsigned long long *>(smem);  // [P*nbins] weights x 2^32
+    double *jx = reinterpret_cast<double *>(hist + (size_t)a.P * a.nbins);   // [3][TILE]
+    float4 *mills = reinterpret_cast<float4 *>(jx + 3 * TILE);               // [MILLS_N]
+    int *js = reinterpret_cast<int *>(mills + MILLS_N);                       // [TILE]
+    int *prow = js + TILE;                                                    // [16]
     const int tid = threadIdx.x;
     const int nq = a.P * a.nbins;
-    for (int q = tid; q < nq; q += TILE) hist[q] = 0.0;
+    for (int q = tid; q < nq; q += TILE) hist[q] = 0ull;
     for (int q = tid; q < MILLS_N; q += TILE) mills[q] = nd::ld4(a.mills + q);
     if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.nbins;
     __syncthreads();
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(TILE) void k_hist_broad(BroadArgs a)
             const double u = r * a.inv_dr;
             const int kr = (int)u;
             const float f = (float)(u - (double)kr);
-            double *row = hist + prow[rowbase + js[jj]];
+            unsigned long long *row = hist + prow[rowbase + js[jj]];
             // tail mass at edge k0: x = (e - r) / s
             float x = ((float)(k0 - kr) - f) * beta;
             float T = gauss_tail(fabsf(x), mills);
@@ -148,7 +150,8 @@ __global__ __launch_bounds__(TILE) void k_hist_broad(BroadArgs a)
                 const float Th = gauss_tail(fabsf(xh), mills);
                 const bool rh = xh >= 0.0f;
                 const float wk = right ? T - Th : (rh ? 1.0f - T - Th : Th - T);
-                atomicAdd(&row[k], (double)wk);
+                // weight in units of 2^-32 (exact integer sums, deterministic)
+                atomicAdd(&row[k], (unsigned long long)__float2uint_rn(wk * 4294967296.0f));
                 T = Th;
                 right = rh;
             }
@@ -156,7 +159,7 @@ __global__ __launch_bounds__(TILE) void k_hist_broad(BroadArgs a)
     }
     __syncthreads();
     double *out = a.partial + (size_t)blockIdx.x * nq;
-    for (int q = tid; q < nq; q += TILE) out[q] = hist[q];
+    for (int q = tid; q < nq; q += TILE) out[q] = (double)hist[q] * 2.3283064365386963e-10;
 }
 
 __global__ void k_reduce_f64(const double *__restrict__ partial, int G, int n, double *__restrict__ out)
@@ -177,6 +180,8 @@ struct BackArgs {
     double L, invL, half2;
     double dr, inv_dr, inv_sigma, six_sigma;
     float beta;       // dr / sigma
+    float rho_step;   // exp(-beta^2)
+    int recur;        // 1: Gaussian density by recurrence along the edges (beta <= 4)
     int jchunk;
     double *partial;  // [gridDim.y][3][N]
 };
@@ -186,13 +191,15 @@ struct BackArgs {
 __global__ __launch_bounds__(TILE) void k_hist_broad_bwd(BackArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    double *dA = reinterpret_cast<double *>(smem);                      // [P*nbins]
-    double *jx = dA + (size_t)a.P * a.nbins;                            // [3][TILE]
+    double *jx = reinterpret_cast<double *>(smem);                      // [3][TILE]
     int *js = reinterpret_cast<int *>(jx + 3 * TILE);                  // [TILE]
     int *prow = js + TILE;                                              // [16]
+    float *dA = reinterpret_cast<float *>(prow + 16);                  // [P*nbins]
     const int tid = threadIdx.x;
     const int nq = a.P * a.nbins;
-    for (int q = tid; q < nq; q += TILE) dA[q] = a.A[q];
+    // the adjoint in FP32: each pair's dL/dr is a sum of ~10 such terms
+    // (relative error ~1e-7 of the sum of their magnitudes)
+    for (int q = tid; q < nq; q += TILE) dA[q] = (float)a.A[q];
     if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.nbins;
     const int N = a.N;
     const int i = blockIdx.x * TILE + tid;
@@ -241,16 +248,29 @@ __global__ __launch_bounds__(TILE) void k_hist_broad_bwd(BackArgs a)
             const double u = r * a.inv_dr;
             const int kr = (int)u;
             const float f = (float)(u - (double)kr);
-            const double *row = dA + prow[rowbase + js[jj]];
+            const float *row = dA + prow[rowbase + js[jj]];
             // dL/dr = sum_k A(k) (phi(x_k) - phi(x_{k+1})) / s, x = (e - r)/s
-            float plo = gauss_pdf(((float)(k0 - kr) - f) * beta);
-            double dLdr = 0.0;
-            for (int k = k0; k <= k1; ++k) {
-                const float phi_hi = gauss_pdf(((float)(k + 1 - kr) - f) * beta);
-                dLdr = fma(row[k], (double)(plo - phi_hi), dLdr);
-                plo = phi_hi;
+            const float x0 = ((float)(k0 - kr) - f) * beta;
+            float plo = gauss_pdf(x0);
+            float dLdr = 0.0f;
+            if (a.recur) {
+                // phi(x + beta) = phi(x) rho, rho = exp(-beta x - beta^2/2); rho
+                // itself steps by the constant factor exp(-beta^2)
+                float rho = __builtin_amdgcn_exp2f((x0 + 0.5f * beta) * beta * -1.4426950408889634f);
+                for (int k = k0; k <= k1; ++k) {
+                    const float phi_hi = plo * rho;
+                    dLdr = fmaf(row[k], plo - phi_hi, dLdr);
+                    plo = phi_hi;
+                    rho *= a.rho_step;
+                }
+            } else {
+                for (int k = k0; k <= k1; ++k) {
+                    const float phi_hi = gauss_pdf(((float)(k + 1 - kr) - f) * beta);
+                    dLdr = fmaf(row[k], plo - phi_hi, dLdr);
+                    plo = phi_hi;
+                }
             }
-            const double c = dLdr * a.inv_sigma / r;
+            const double c = (double)dLdr * a.inv_sigma / r;
             gx += c * dx;
             gy += c * dy;
             gz += c * dz;
@@ -432,6 +452,9 @@ void launch_hist_broad(nd_box *b, double dr, int nbins, double sigma, double *d_
     int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (lds + 1024)));
     long long G = (long long)cu_count(b->device) * per_cu;
     if (G > a.ntp) G = a.ntp;
+    // a block's integer sum of weights < 1 per pair stays below 2^64
+    if ((double)((a.ntp + G - 1) / G) * TILE * TILE >= 4294967295.0)
+        fail(ND_E_UNSUPPORTED, "box too large for the broadened histogram's block sums");
     a.partial = static_cast<double *>(workspace(b, sizeof(double) * (size_t)G * nq));
     {
         ProfScope ps(b, ND_PROF_HIST_BROAD);
@@ -460,10 +483,13 @@ void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, c
     a.inv_sigma = 1.0 / sigma;
     a.six_sigma = 6.0 * sigma;
     a.beta = (float)(dr / sigma);
+    a.rho_step = (float)std::exp(-(dr / sigma) * (dr / sigma));
+    // the first step factor exp(beta (6 + beta/2 + 1)) stays far inside FP32 range
+    a.recur = dr / sigma <= 4.0 ? 1 : 0;
     const int nch = n_jchunks(b);
     a.jchunk = (b->N + nch - 1) / nch;
     const int nib = (b->N + TILE - 1) / TILE;
-    size_t lds = sizeof(double) * ((size_t)b->P * nbins + 3 * TILE) + sizeof(int) * (TILE + 16);
+    size_t lds = sizeof(double) * 3 * TILE + sizeof(int) * (TILE + 16) + sizeof(float) * (size_t)b->P * nbins;
     if (lds > 160 * 1024) fail(ND_E_UNSUPPORTED, "adjoint table does not fit in LDS");
     a.partial = static_cast<double *>(workspace(b, sizeof(double) * (size_t)nch * 3 * b->N));
     {
