@@ -32,6 +32,12 @@ OPS_PER_TEST = 16
 # 9 nearest image (mul, round, fma per axis), 3 for r^2, 6 for the bin
 # (cvt, sqrt, mul, cvt, edge compare, fix-up), 2 range check and address.
 OPS_PER_PAIR = 23
+# HBM bytes one k_pair_hist launch moves on the 99,999-atom water box, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch scaled by a 1 GiB copy
+# (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 9830.4 + 19936.0
+# KiB.  profiles/k_pair_hist_water99999.md holds the counters and commands;
+# set to None whenever the kernel changes until they are taken again.
+HIST_TRAFFIC_BYTES = (2 * 9830.4 + 19936.0) * 1024
 PAPER_GPU_STEPS_PER_S_1E5 = 12412.0  # Table "tab_speed", water, 1e5 atoms, Tesla V100
 
 
@@ -233,7 +239,8 @@ def main():
         "roofline": {
             "kernel": "k_pair_hist (exact pair-count histogram, all N(N-1)/2 pairs)",
             "bound": "alu", "achieved": hist_achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "Tlane-op/s", "frac": hist_achieved / PEAK_LANE_OPS, "traffic": None,
+            "unit": "Tlane-op/s", "frac": hist_achieved / PEAK_LANE_OPS,
+            "traffic": HIST_TRAFFIC_BYTES, "traffic_unit": "bytes per launch",
             "launches": hist_n, "avg_launch_ms": hist_avg_s * 1e3,
             "algorithmic_per_launch": f"{n_pairs} pairs x {OPS_PER_PAIR} lane-ops",
             "pairs_per_s": n_pairs / hist_avg_s,
