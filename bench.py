@@ -37,7 +37,7 @@ OPS_PER_PAIR = 23
 # (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 9830.4 + 19936.0
 # KiB.  profiles/k_pair_hist_water99999.md holds the counters and commands;
 # set to None whenever the kernel changes until they are taken again.
-HIST_TRAFFIC_BYTES = (2 * 9830.4 + 19936.0) * 1024
+HIST_TRAFFIC_BYTES = None
 PAPER_GPU_STEPS_PER_S_1E5 = 12412.0  # Table "tab_speed", water, 1e5 atoms, Tesla V100
 
 

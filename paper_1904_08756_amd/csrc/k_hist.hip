@@ -17,9 +17,11 @@ namespace {
 
 constexpr int TILE = 256;  // atoms per tile = threads per block
 
-// Fractional coordinates s = x / L in FP64, stored as float32 hi + lo.
-__global__ void k_pos4_from_xyz(const float *__restrict__ xyz, const uint8_t *__restrict__ sp, int N,
-                                double invL, float4 *__restrict__ pos4, float4 *__restrict__ poslo)
+// Fractional coordinates s = x / L in FP64, stored as float32 hi + lo;
+// hi.w holds the species and lo.w the atom's rigid unit, both as int bits.
+__global__ void k_pos4_from_xyz(const float *__restrict__ xyz, const uint8_t *__restrict__ sp,
+                                const int32_t *__restrict__ unit_of, int N, double invL, float4 *__restrict__ pos4,
+                                float4 *__restrict__ poslo)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
@@ -32,7 +34,7 @@ __global__ void k_pos4_from_xyz(const float *__restrict__ xyz, const uint8_t *__
     q.x = (float)(sx - (double)p.x);
     q.y = (float)(sy - (double)p.y);
     q.z = (float)(sz - (double)p.z);
-    q.w = 0.0f;
+    q.w = __int_as_float(unit_of[i]);  // read by the Metropolis cell scan
     pos4[i] = p;
     poslo[i] = q;
 }
@@ -56,8 +58,10 @@ struct HistArgs {
     const uint8_t *sp;
     int N, M, P, nbins, nt;
     long long ntp;
-    double L, invL, dr, e2max;
-    float inv_dr_f, edge_eps;
+    double L, invL, dr;
+    float fix_scale;        // (L / 2^32) / dr: fixed-point length to bins
+    float nb_hi;            // nbins + edge_eps: candidates beyond are out of range
+    float edge_eps;
     unsigned *partial;      // [gridDim.x][P * nbins] (one box per launch)
     unsigned long long *out;  // [P * nbins] counts, accumulated atomically (several boxes per launch)
     long long tile0;        // first global tile-pair index of this box (several boxes per launch)
@@ -65,23 +69,34 @@ struct HistArgs {
 
 // LDS layout of the histogram kernels.
 struct HistLds {
-    double *jx;      // [3][TILE] j-tile coordinates
+    int4 *jq;        // [TILE] j-tile fixed-point coordinates (.w unused)
+    float *jf;       // [3][TILE] j-tile float32 coordinates
     int *jrow;       // [ND_MAX_SPECIES][TILE] byte offset of the histogram row of (species s, atom j)
     int *prow;       // [16] partial row offset of each species pair
-    unsigned *hist;  // [P * nbins]
+    unsigned *hist;  // [P * nbins + 1]: the last word takes pairs just past the range
 };
 
 __device__ __forceinline__ HistLds hist_lds(unsigned char *smem)
 {
     HistLds h;
-    h.jx = reinterpret_cast<double *>(smem);
-    h.jrow = reinterpret_cast<int *>(h.jx + 3 * TILE);
+    h.jq = reinterpret_cast<int4 *>(smem);
+    h.jf = reinterpret_cast<float *>(h.jq + TILE);
+    h.jrow = reinterpret_cast<int *>(h.jf + 3 * TILE);
     h.prow = h.jrow + ND_MAX_SPECIES * TILE;
     h.hist = reinterpret_cast<unsigned *>(h.prow + 16);
     return h;
 }
 
-constexpr size_t HIST_LDS_FIXED = sizeof(double) * 3 * TILE + sizeof(int) * (ND_MAX_SPECIES * TILE + 16);
+constexpr size_t HIST_LDS_FIXED =
+    sizeof(int4) * TILE + sizeof(float) * 3 * TILE + sizeof(int) * (ND_MAX_SPECIES * TILE + 16);
+
+// Fixed-point fractional coordinate: round(x / L 2^32) mod 2^32.  The
+// difference of two of them, read as a signed 32-bit integer, is the
+// nearest-image displacement in units of L / 2^32.
+__device__ __forceinline__ int fixed_coord(float x, double invL)
+{
+    return (int)(unsigned)(long long)rint((double)x * invL * 4294967296.0);
+}
 
 // Zero the LDS histogram and set the species-pair row offsets of box a.
 __device__ __forceinline__ void hist_begin(const HistArgs &a, const HistLds &h)
@@ -96,32 +111,40 @@ __device__ __forceinline__ void hist_begin(const HistArgs &a, const HistLds &h)
     __syncthreads();
 }
 
-// Every pair (i, j) of tile pair (I, J), i < j on the diagonal, in FP64:
-// d = x_j - x_i per axis and its nearest-image length min(|d|, L - |d|)
-// (the same number as d, or d -/+ L past +/-L/2, up to sign), r2 =
-// fma(dz,dz, fma(dy,dy, dx*dx)); bin from an FP32 square root, settled by
-// the exact FP64 edge test when it lies near an edge; one LDS atomic per
-// counted pair.
+// Every pair (i, j) of tile pair (I, J), i < j on the diagonal.  The bin
+// is the exact rule: k = max{k : (k dr)^2 <= r2}, counted iff k < nbins,
+// with r2 = fma(dz,dz, fma(dy,dy, dx*dx)) in FP64 from the float32
+// coordinates, d per axis taken at its nearest-image length min(|d|, L-|d|).
+// A candidate comes from the fixed-point coordinates: the 32-bit difference
+// is the nearest-image displacement, its FP32 length times (L/2^32)/dr is
+// r/dr to within 4e-7 relative (conversion, squares, square root and scale
+// each round once).  When the candidate lies within edge_eps of an integer
+// (a bin edge or the end of the range) the FP64 r2 is formed and compared
+// with (k dr)^2; otherwise the candidate's floor is the bin.  One LDS atomic
+// per counted pair.
 __device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, int I, int J)
 {
     const int tid = threadIdx.x;
     const int N = a.N;
     const int i = I * TILE + tid;
     const bool iv = i < N;
-    double xi = 0.0, yi = 0.0, zi = 0.0;
+    float xi = 0.f, yi = 0.f, zi = 0.f;
     int si = 0;
     if (iv) {
-        xi = (double)a.xyz[i];
-        yi = (double)a.xyz[N + i];
-        zi = (double)a.xyz[2 * N + i];
+        xi = a.xyz[i];
+        yi = a.xyz[N + i];
+        zi = a.xyz[2 * N + i];
         si = a.sp[i];
     }
-    __syncthreads();  // previous tile's readers are done with jx/jrow
+    const int qx = fixed_coord(xi, a.invL), qy = fixed_coord(yi, a.invL), qz = fixed_coord(zi, a.invL);
+    __syncthreads();  // previous tile's readers are done with the j arrays
     const int j = J * TILE + tid;
     if (j < N) {
-        h.jx[tid] = (double)a.xyz[j];
-        h.jx[TILE + tid] = (double)a.xyz[N + j];
-        h.jx[2 * TILE + tid] = (double)a.xyz[2 * N + j];
+        const float x = a.xyz[j], y = a.xyz[N + j], z = a.xyz[2 * N + j];
+        h.jq[tid] = make_int4(fixed_coord(x, a.invL), fixed_coord(y, a.invL), fixed_coord(z, a.invL), 0);
+        h.jf[tid] = x;
+        h.jf[TILE + tid] = y;
+        h.jf[2 * TILE + tid] = z;
         const int sj = a.sp[j];
         for (int s = 0; s < a.M; ++s) h.jrow[s * TILE + tid] = h.prow[s * a.M + sj] * (int)sizeof(unsigned);
     }
@@ -129,30 +152,38 @@ __device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, i
     const int jn = min(TILE, N - J * TILE);
     const int jstart = (I == J) ? tid + 1 : 0;  // diagonal tile: pairs j > i only
     if (!iv) return;
-    const double *jx = h.jx;
     const int *jrow = h.jrow + si * TILE;
-    const double L = a.L;
+    const float scale = a.fix_scale, nb_hi = a.nb_hi, eps = a.edge_eps;
 #pragma unroll 4
     for (int jj = jstart; jj < jn; ++jj) {
-        const double ax = fabs(jx[jj] - xi);
-        const double ay = fabs(jx[TILE + jj] - yi);
-        const double az = fabs(jx[2 * TILE + jj] - zi);
-        const double mx = fmin(ax, L - ax);
-        const double my = fmin(ay, L - ay);
-        const double mz = fmin(az, L - az);
-        const double r2 = fma(mz, mz, fma(my, my, mx * mx));
-        if (r2 < a.e2max) {
-            // candidate bin from an FP32 square root; exact FP64 edge test
-            // only when the candidate lies within edge_eps of a bin edge
-            const float tb = __builtin_amdgcn_sqrtf((float)r2) * a.inv_dr_f;
+        const int4 q = h.jq[jj];
+        const int row = jrow[jj];
+        // 32-bit wrap-around differences
+        const float dx = (float)(int)((unsigned)q.x - (unsigned)qx);
+        const float dy = (float)(int)((unsigned)q.y - (unsigned)qy);
+        const float dz = (float)(int)((unsigned)q.z - (unsigned)qz);
+        const float tb = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))) * scale;
+        if (tb < nb_hi) {
             int k = (int)tb;
-            const float fr = __builtin_amdgcn_fractf(tb);
-            if (fabsf(fr - 0.5f) > 0.5f - a.edge_eps) {
+            int rw = row;
+            if (fabsf(__builtin_amdgcn_fractf(tb) - 0.5f) > 0.5f - eps) {
+                // near an edge: the exact FP64 rule
+                const double L = a.L;
+                const double ax = fabs((double)h.jf[jj] - (double)xi);
+                const double ay = fabs((double)h.jf[TILE + jj] - (double)yi);
+                const double az = fabs((double)h.jf[2 * TILE + jj] - (double)zi);
+                const double mx = fmin(ax, L - ax), my = fmin(ay, L - ay), mz = fmin(az, L - az);
+                const double r2 = fma(mz, mz, fma(my, my, mx * mx));
                 const int kk = (int)rintf(tb);
                 const double e = (double)kk * a.dr;
                 k = (r2 >= e * e) ? kk : kk - 1;
+                if (k >= a.nbins) {
+                    // past the range: count into the spare word after the histogram
+                    rw = a.P * a.nbins * (int)sizeof(unsigned);
+                    k = 0;
+                }
             }
-            atomicAdd(reinterpret_cast<unsigned *>(reinterpret_cast<unsigned char *>(h.hist) + jrow[jj]) + k, 1u);
+            atomicAdd(reinterpret_cast<unsigned *>(reinterpret_cast<unsigned char *>(h.hist) + (rw + (k << 2))), 1u);
         }
     }
 }
@@ -358,8 +389,8 @@ void launch_pos4_from_xyz(nd_box *b)
 {
     int threads = 256;
     int blocks = (b->N + threads - 1) / threads;
-    hipLaunchKernelGGL(k_pos4_from_xyz, dim3(blocks), dim3(threads), 0, b->stream, b->xyz, b->species, b->N,
-                       1.0 / b->L, b->pos4, b->poslo);
+    hipLaunchKernelGGL(k_pos4_from_xyz, dim3(blocks), dim3(threads), 0, b->stream, b->xyz, b->species, b->unit_of,
+                       b->N, 1.0 / b->L, b->pos4, b->poslo);
     ND_HIP(hipGetLastError());
 }
 
@@ -381,20 +412,18 @@ HistArgs make_hist_args(const nd_box *b, double dr, int nbins)
     a.L = b->L;
     a.invL = 1.0 / b->L;
     a.dr = dr;
-    {
-        double e = (double)nbins * dr;
-        a.e2max = e * e;
-    }
-    a.inv_dr_f = (float)(1.0 / dr);
-    // bound on |candidate - sqrt(r2)/dr|: < 2.5e-7 relative, plus margin
-    a.edge_eps = (float)(1e-3 + 4e-7 * (double)nbins);
+    a.fix_scale = (float)(b->L / 4294967296.0 / dr);
+    // bound on |candidate - sqrt(r2)/dr|: < 4e-7 relative plus the
+    // fixed-point rounding of the coordinates (L / 2^32 each); margin kept
+    a.edge_eps = (float)(2e-3 + 6e-7 * (double)nbins);
     if (!(a.edge_eps < 0.25f)) nd::fail(ND_E_UNSUPPORTED, "nbins too large for the binning kernel");
+    a.nb_hi = (float)nbins + a.edge_eps;
     return a;
 }
 
 size_t hist_lds_bytes(int nq)
 {
-    const size_t lds = HIST_LDS_FIXED + sizeof(unsigned) * (size_t)nq;
+    const size_t lds = HIST_LDS_FIXED + sizeof(unsigned) * ((size_t)nq + 1);
     if (lds > 160 * 1024) nd::fail(ND_E_UNSUPPORTED, "histogram does not fit in LDS (P*nbins too large)");
     return lds;
 }

@@ -174,7 +174,7 @@ __device__ __forceinline__ void propose_one(const ProposeArgs &a, int k)
         ql.x = (float)(f0 - (double)q.x);
         ql.y = (float)(f1 - (double)q.y);
         ql.z = (float)(f2 - (double)q.z);
-        ql.w = 0.0f;
+        ql.w = __int_as_float(u);
         T->old_hi[at] = o;
         T->old_lo[at] = a.poslo[a0 + at];
         T->new_hi[at] = q;
@@ -556,8 +556,7 @@ constexpr int CS_LIST = 192;  // survivors buffered per wave
 
 struct CellScanArgs {
     const float4 *spos4;
-    const float4 *sposlo;
-    const int32_t *slot;     // atom -> sorted slot
+    const float4 *sposlo;    // .w: unit
     const int32_t *cstart;
     const float *tab;
     const nd::Trial *trials;
@@ -571,15 +570,14 @@ struct CellScanArgs {
 
 // Trial atoms staged in LDS for the scan: FP64 fractional position and the
 // table-row base of the atom's species, for the old (index 2a) and new
-// (2a + 1) position of atom a, and the sorted slots of the unit's atoms.
+// (2a + 1) position of atom a.
 struct TrialAtoms {
     double x[2 * ND_MAX_UNIT_ATOMS], y[2 * ND_MAX_UNIT_ATOMS], z[2 * ND_MAX_UNIT_ATOMS];
     int rb[2 * ND_MAX_UNIT_ATOMS];
-    int sl[ND_MAX_UNIT_ATOMS];
 };
 
 // Survivors are kept in LDS as their current position, hi (with .w =
-// slot << 2 | species, slot < 2^29) and lo.  CIMG: the trial's atoms (taken
+// species) and lo.  CIMG: the trial's atoms (taken
 // at their images nearest the centre) lie within rad of the centre and
 // r_cut + 2 rad < L/2, so the survivor's image nearest the centre is its
 // nearest image to every atom of the trial along each axis, and the
@@ -600,7 +598,7 @@ __device__ __forceinline__ void cell_flush(const PairCtx &c, const TrialAtoms &t
             sy -= rint(sy - cy);
             sz -= rint(sz - cz);
         }
-        const int sj = w & 3;
+        const int sj = w;
 #pragma unroll
         for (int at = 0; at < MAXNU; ++at) {
             if (at < tna) {
@@ -649,15 +647,16 @@ __device__ __forceinline__ float gap_to_cell(float c, int i, float inv_nc)
 // where it wraps.  A wave fetches up to 64 rows at once (one per lane),
 // concatenates their slot ranges with a prefix sum, and walks the
 // concatenation 128 candidates at a time; candidates whose current position
-// lies within r_cut + radius of the centre (atoms of the moved unit aside)
-// are compacted into LDS and their exact pair terms summed.
+// lies within r_cut + radius of the centre (atoms of the moved unit, known
+// by the unit in lo.w, aside) are compacted into LDS and their exact pair
+// terms summed.
 template <int MAXNU>
 __device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k, float4 *list, float4 *listlo,
                                  double *red, TrialAtoms &ta)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const nd::Trial *T = a.trials + k;
-    const int ta0 = T->a0, tna = T->na;
+    const int tna = T->na, tunit = T->unit;
     const float cx = T->cen[0], cy = T->cen[1], cz = T->cen[2];
     const float surv = a.rcf + T->rad + 4e-6f;
     const float surv2 = surv * surv;
@@ -680,11 +679,7 @@ __device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const Pa
         ta.z[tid] = z;
         ta.rb[tid] = __float_as_int(h.w) * c.M;
     }
-    if (tid < tna) ta.sl[tid] = ldg(a.slot + ta0 + tid);
     __syncthreads();
-    int own[MAXNU];
-#pragma unroll
-    for (int at = 0; at < MAXNU; ++at) own[at] = at < tna ? ta.sl[at] : -1;
     const float reach = surv + *a.drift + 1e-6f;
     const float reach2 = reach * reach;
     const int nc = a.nc;
@@ -777,16 +772,12 @@ __device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const Pa
                 dx -= rintf(dx);
                 dy -= rintf(dy);
                 dz -= rintf(dz);
-                bool mine = false;
-#pragma unroll
-                for (int at = 0; at < MAXNU; ++at) mine |= sl[h] == own[at];
+                const bool mine = __float_as_int(ql[h].w) == tunit;
                 const bool hit = live[h] && !mine && fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < surv2;
                 const unsigned long long bal = __ballot(hit);
                 if (hit) {
-                    float4 v = q[h];
-                    v.w = __int_as_float((sl[h] << 2) | (__float_as_int(q[h].w) & 3));
                     const int idx = nlist + __popcll(bal & lt);
-                    list[idx] = v;
+                    list[idx] = q[h];
                     listlo[idx] = ql[h];
                 }
                 nlist += __popcll(bal);
@@ -1535,7 +1526,6 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         CellScanArgs &ca = L.ca;
         ca.spos4 = b->cells.spos4;
         ca.sposlo = b->cells.sposlo;
-        ca.slot = b->cells.slot;
         ca.slab = slab_buffer(b, buf);
         ca.kcap = w.cap_k;
         ca.per_slab = per_slab_blocks(kb);

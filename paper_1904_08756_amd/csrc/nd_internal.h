@@ -34,7 +34,8 @@ __host__ __device__ inline int pair_index(int a, int b, int M)
 // Trial record written by the proposal kernel and read by the scan,
 // correction and decision kernels.  Fractional coordinates s = x / L are
 // held as a float32 pair: hi = (float)s (species in .w as int bits) and
-// lo = (float)(s - hi), so (double)hi + (double)lo carries s to ~2^-48.
+// lo = (float)(s - hi) (the atom's unit in .w as int bits), so (double)hi +
+// (double)lo carries s to ~2^-48.
 struct Trial {
     float4 old_hi[ND_MAX_UNIT_ATOMS];
     float4 old_lo[ND_MAX_UNIT_ATOMS];
@@ -108,7 +109,7 @@ struct nd_box {
     // device
     float *xyz = nullptr;        // [3][N] absolute float32 (canonical state)
     float4 *pos4 = nullptr;      // [N] fractional float32 (hi) + species bits
-    float4 *poslo = nullptr;     // [N] fractional remainder (lo), .w unused
+    float4 *poslo = nullptr;     // [N] fractional remainder (lo), .w = unit (int bits)
     uint8_t *species = nullptr;  // [N]
     int32_t *uoff = nullptr;     // [n_units + 1]
     int32_t *unit_of = nullptr;  // [N]
