@@ -60,18 +60,19 @@ struct HistArgs {
     long long ntp;
     double L, invL, dr;
     float fix_scale;        // (L / 2^32) / dr: fixed-point length to bins
-    float nb_hi;            // nbins + edge_eps: candidates beyond are out of range
+    float nb_hi;            // nbins + 2 edge_eps: shifted candidates beyond are out of range
     float edge_eps;
     unsigned *partial;      // [gridDim.x][P * nbins] (one box per launch)
+    unsigned long long *zero_out;  // counts cleared by block 0 for the reduction that follows (or null)
     unsigned long long *out;  // [P * nbins] counts, accumulated atomically (several boxes per launch)
     long long tile0;        // first global tile-pair index of this box (several boxes per launch)
 };
 
 // LDS layout of the histogram kernels.
 struct HistLds {
-    int4 *jq;        // [TILE] j-tile fixed-point coordinates (.w unused)
+    int4 *jq;        // [TILE] j-tile fixed-point coordinates; .w: row word offsets (16 bits per species, M <= 2)
     float *jf;       // [3][TILE] j-tile float32 coordinates
-    int *jrow;       // [ND_MAX_SPECIES][TILE] byte offset of the histogram row of (species s, atom j)
+    int *jrow;       // [ND_MAX_SPECIES][TILE] word offset of the histogram row of (species s, atom j)
     int *prow;       // [16] partial row offset of each species pair
     unsigned *hist;  // [P * nbins + 1]: the last word takes pairs just past the range
 };
@@ -116,12 +117,13 @@ __device__ __forceinline__ void hist_begin(const HistArgs &a, const HistLds &h)
 // with r2 = fma(dz,dz, fma(dy,dy, dx*dx)) in FP64 from the float32
 // coordinates, d per axis taken at its nearest-image length min(|d|, L-|d|).
 // A candidate comes from the fixed-point coordinates: the 32-bit difference
-// is the nearest-image displacement, its FP32 length times (L/2^32)/dr is
-// r/dr to within 4e-7 relative (conversion, squares, square root and scale
-// each round once).  When the candidate lies within edge_eps of an integer
-// (a bin edge or the end of the range) the FP64 r2 is formed and compared
-// with (k dr)^2; otherwise the candidate's floor is the bin.  One LDS atomic
-// per counted pair.
+// is the nearest-image displacement, and its FP32 length times (L/2^32)/dr
+// is r/dr to within the error bound below edge_eps (make_hist_args).  When
+// the candidate lies within edge_eps of an integer K (a bin edge or the end
+// of the range) the bin is K - 1 or K, and the FP64 r2 compared with
+// (K dr)^2 decides; otherwise the candidate's floor is the bin.  One LDS
+// atomic per counted pair.
+template <bool PACKED>
 __device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, int I, int J)
 {
     const int tid = threadIdx.x;
@@ -141,32 +143,44 @@ __device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, i
     const int j = J * TILE + tid;
     if (j < N) {
         const float x = a.xyz[j], y = a.xyz[N + j], z = a.xyz[2 * N + j];
-        h.jq[tid] = make_int4(fixed_coord(x, a.invL), fixed_coord(y, a.invL), fixed_coord(z, a.invL), 0);
+        const int sj = a.sp[j];
+        int w = 0;
+        if (PACKED) {
+            for (int s = 0; s < a.M; ++s) w |= h.prow[s * a.M + sj] << (16 * s);
+        } else {
+            for (int s = 0; s < a.M; ++s) h.jrow[s * TILE + tid] = h.prow[s * a.M + sj];
+        }
+        h.jq[tid] = make_int4(fixed_coord(x, a.invL), fixed_coord(y, a.invL), fixed_coord(z, a.invL), w);
         h.jf[tid] = x;
         h.jf[TILE + tid] = y;
         h.jf[2 * TILE + tid] = z;
-        const int sj = a.sp[j];
-        for (int s = 0; s < a.M; ++s) h.jrow[s * TILE + tid] = h.prow[s * a.M + sj] * (int)sizeof(unsigned);
     }
     __syncthreads();
     const int jn = min(TILE, N - J * TILE);
     const int jstart = (I == J) ? tid + 1 : 0;  // diagonal tile: pairs j > i only
     if (!iv) return;
     const int *jrow = h.jrow + si * TILE;
-    const float scale = a.fix_scale, nb_hi = a.nb_hi, eps = a.edge_eps;
+    const int sh = 16 * si;
+    const float scale = a.fix_scale, nb_hi = a.nb_hi, eps2 = 2.0f * a.edge_eps;
+    float eps = a.edge_eps;
+    asm volatile("" : "+v"(eps));  // held in a vector register: the fma below takes one scalar operand
 #pragma unroll 4
     for (int jj = jstart; jj < jn; ++jj) {
         const int4 q = h.jq[jj];
-        const int row = jrow[jj];
         // 32-bit wrap-around differences
         const float dx = (float)(int)((unsigned)q.x - (unsigned)qx);
         const float dy = (float)(int)((unsigned)q.y - (unsigned)qy);
         const float dz = (float)(int)((unsigned)q.z - (unsigned)qz);
-        const float tb = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))) * scale;
+        // the candidate r/dr shifted up by eps: within eps of an integer K
+        // exactly when its fraction is below 2 eps, and otherwise its floor
+        // is the floor of the candidate
+        const float tb = fmaf(__builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))), scale, eps);
         if (tb < nb_hi) {
-            int k = (int)tb;
-            int rw = row;
-            if (fabsf(__builtin_amdgcn_fractf(tb) - 0.5f) > 0.5f - eps) {
+            // word offset of the (si, sj) histogram row, plus the bin
+            const int rw = PACKED ? (int)__builtin_amdgcn_ubfe((unsigned)q.w, (unsigned)sh, 16u) : jrow[jj];
+            const int kk = (int)tb;
+            int idx = rw + kk;
+            if (__builtin_amdgcn_fractf(tb) < eps2) {
                 // near an edge: the exact FP64 rule
                 const double L = a.L;
                 const double ax = fabs((double)h.jf[jj] - (double)xi);
@@ -174,31 +188,30 @@ __device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, i
                 const double az = fabs((double)h.jf[2 * TILE + jj] - (double)zi);
                 const double mx = fmin(ax, L - ax), my = fmin(ay, L - ay), mz = fmin(az, L - az);
                 const double r2 = fma(mz, mz, fma(my, my, mx * mx));
-                const int kk = (int)rintf(tb);
                 const double e = (double)kk * a.dr;
-                k = (r2 >= e * e) ? kk : kk - 1;
-                if (k >= a.nbins) {
-                    // past the range: count into the spare word after the histogram
-                    rw = a.P * a.nbins * (int)sizeof(unsigned);
-                    k = 0;
-                }
+                const int k = (r2 >= e * e) ? kk : kk - 1;
+                // past the range: count into the spare word after the histogram
+                idx = k < a.nbins ? rw + k : a.P * a.nbins;
             }
-            atomicAdd(reinterpret_cast<unsigned *>(reinterpret_cast<unsigned char *>(h.hist) + (rw + (k << 2))), 1u);
+            atomicAdd(reinterpret_cast<unsigned *>(reinterpret_cast<unsigned char *>(h.hist) + ((unsigned)idx << 2)), 1u);
         }
     }
 }
 
+template <bool PACKED>
 __global__ __launch_bounds__(TILE) void k_pair_hist(HistArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const HistLds h = hist_lds(smem);
     const int nq = a.P * a.nbins;
     const int tid = threadIdx.x;
+    if (blockIdx.x == 0 && a.zero_out)
+        for (int q = tid; q < nq; q += TILE) a.zero_out[q] = 0ull;
     hist_begin(a, h);
     for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
         int I, J;
         tri_index(t, a.nt, I, J);
-        hist_tile(a, h, I, J);
+        hist_tile<PACKED>(a, h, I, J);
     }
     __syncthreads();
     unsigned *out = a.partial + (size_t)blockIdx.x * nq;
@@ -210,6 +223,7 @@ __global__ __launch_bounds__(TILE) void k_pair_hist(HistArgs a)
 // [b per, (b + 1) per) of it, so it meets one or two boxes, and adds its LDS
 // histogram to a box's counts with integer atomics when it leaves the box
 // (exact, so the counts do not depend on the order of the blocks).
+template <bool PACKED>
 __global__ __launch_bounds__(TILE) void k_pair_hist_multi(const HistArgs *__restrict__ boxes, int n_boxes,
                                                           long long total, long long per)
 {
@@ -237,7 +251,7 @@ __global__ __launch_bounds__(TILE) void k_pair_hist_multi(const HistArgs *__rest
             for (; t < box_end; ++t) {
                 int I, J;
                 tri_index(t - a.tile0, a.nt, I, J);
-                hist_tile(a, h, I, J);
+                hist_tile<PACKED>(a, h, I, J);
             }
             __syncthreads();
             const int nq = a.P * a.nbins;
@@ -259,13 +273,16 @@ __global__ void k_zero_u64_multi(const HistArgs *__restrict__ boxes)
     if (q < a.P * a.nbins) a.out[q] = 0ull;
 }
 
+// Sum of the per-block partial histograms: block (x, y) adds partials y,
+// y + gridDim.y, ... of counters 256 x .. 256 x + 255 and adds the sum to
+// the (cleared) u64 counts with an integer atomic -- exact in any order.
 __global__ void k_hist_reduce(const unsigned *__restrict__ partial, int G, int nq, uint64_t *__restrict__ counts)
 {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq) return;
     uint64_t s = 0;
-    for (int g = 0; g < G; ++g) s += partial[(size_t)g * nq + q];
-    counts[q] = s;
+    for (int g = blockIdx.y; g < G; g += gridDim.y) s += partial[(size_t)g * nq + q];
+    if (s) atomicAdd(reinterpret_cast<unsigned long long *>(counts) + q, (unsigned long long)s);
 }
 
 // ---------------------------------------------------------------- energy
@@ -413,13 +430,18 @@ HistArgs make_hist_args(const nd_box *b, double dr, int nbins)
     a.invL = 1.0 / b->L;
     a.dr = dr;
     a.fix_scale = (float)(b->L / 4294967296.0 / dr);
-    // bound on |candidate - sqrt(r2)/dr|: < 4e-7 relative plus the
-    // fixed-point rounding of the coordinates (L / 2^32 each); margin kept
-    a.edge_eps = (float)(2e-3 + 6e-7 * (double)nbins);
+    // |candidate - r/dr| <= 8.5 u tb + sqrt(3) (L / 2^32) / dr, u = 2^-24:
+    // conversion (squared: 2u), the square and two fma (3u), square root
+    // (2 ulp: 2u, halved by the root of the rest), scale and product (2u);
+    // the second term is the fixed-point rounding of the coordinates
+    a.edge_eps = (float)(6e-7 * ((double)nbins + 1.0) + 2.0 * b->L / 4294967296.0 / dr + 1e-5);
     if (!(a.edge_eps < 0.25f)) nd::fail(ND_E_UNSUPPORTED, "nbins too large for the binning kernel");
-    a.nb_hi = (float)nbins + a.edge_eps;
+    a.nb_hi = (float)nbins + 2.0f * a.edge_eps;
     return a;
 }
+
+// Whether the packed layout holds: at most two species, row offsets < 2^16.
+bool hist_packed(int M, int nq) { return M <= 2 && nq < 65536; }
 
 size_t hist_lds_bytes(int nq)
 {
@@ -437,7 +459,7 @@ void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
     HistArgs a = make_hist_args(b, dr, nbins);
     const int nq = a.P * nbins;
     const size_t lds = hist_lds_bytes(nq);
-    int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (lds + 1024)));
+    int per_cu = (int)std::max<size_t>(1, std::min<size_t>(5, (160 * 1024) / lds));
     long long G = (long long)cu_count(b->device) * per_cu;
     if (G > a.ntp) G = a.ntp;
     // u32 counters: pairs per block must stay below 2^32
@@ -445,12 +467,18 @@ void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
     if ((double)tiles_per_block * TILE * TILE >= 4294967295.0) fail(ND_E_UNSUPPORTED, "box too large for u32 counters");
     size_t pbytes = sizeof(unsigned) * (size_t)G * nq;
     a.partial = static_cast<unsigned *>(workspace(b, pbytes));
+    a.zero_out = reinterpret_cast<unsigned long long *>(d_counts);
     {
         ProfScope ps(b, ND_PROF_PAIR_HIST);
-        hipLaunchKernelGGL(k_pair_hist, dim3((unsigned)G), dim3(TILE), lds, b->stream, a);
+        // row offsets of up to two species fit the spare lane of the j records
+        if (hist_packed(a.M, nq))
+            hipLaunchKernelGGL(k_pair_hist<true>, dim3((unsigned)G), dim3(TILE), lds, b->stream, a);
+        else
+            hipLaunchKernelGGL(k_pair_hist<false>, dim3((unsigned)G), dim3(TILE), lds, b->stream, a);
         ND_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_hist_reduce, dim3((nq + 255) / 256), dim3(256), 0, b->stream, a.partial, (int)G, nq,
+    const int slices = (int)std::min<long long>(G, 64);
+    hipLaunchKernelGGL(k_hist_reduce, dim3((nq + 255) / 256, slices), dim3(256), 0, b->stream, a.partial, (int)G, nq,
                        d_counts);
     ND_HIP(hipGetLastError());
 }
@@ -461,7 +489,7 @@ struct HistMulti {
     HistArgs *d_boxes = nullptr;
     size_t cap = 0;
     long long total = 0, per = 0;
-    int G = 0, max_nq = 0;
+    int G = 0, max_nq = 0, max_m = 0;
     size_t lds = 0;
 };
 
@@ -480,16 +508,18 @@ void hist_multi_plan(HistMulti *m, nd_box *const *boxes, int n, double dr, const
     m->boxes.clear();
     m->total = 0;
     m->max_nq = 0;
+    m->max_m = 0;
     for (int i = 0; i < n; ++i) {
         HistArgs a = make_hist_args(boxes[i], dr, nbins[i]);
         a.out = reinterpret_cast<unsigned long long *>(counts[i]);
         a.tile0 = m->total;
         m->total += a.ntp;
         m->max_nq = std::max(m->max_nq, a.P * a.nbins);
+        m->max_m = std::max(m->max_m, a.M);
         m->boxes.push_back(a);
     }
     m->lds = hist_lds_bytes(m->max_nq);
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (m->lds + 1024)));
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(5, (160 * 1024) / m->lds));
     long long G = (long long)cu_count(boxes[0]->device) * per_cu;
     if (G > m->total) G = m->total;
     m->per = (m->total + G - 1) / G;
@@ -506,6 +536,7 @@ void hist_multi_plan(HistMulti *m, nd_box *const *boxes, int n, double dr, const
     sig.push_back(m->per);
     sig.push_back(m->total);
     sig.push_back(m->max_nq);
+    sig.push_back(m->max_m);
     sig.push_back((long long)m->lds);
     sig.push_back((long long)(uintptr_t)m->d_boxes);
 }
@@ -521,7 +552,12 @@ void hist_multi_enqueue(HistMulti *m, hipStream_t s)
     const int n = (int)m->boxes.size();
     hipLaunchKernelGGL(k_zero_u64_multi, dim3((m->max_nq + 255) / 256, n), dim3(256), 0, s, m->d_boxes);
     ND_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_pair_hist_multi, dim3(m->G), dim3(TILE), m->lds, s, m->d_boxes, n, m->total, m->per);
+    if (hist_packed(m->max_m, m->max_nq))
+        hipLaunchKernelGGL(k_pair_hist_multi<true>, dim3(m->G), dim3(TILE), m->lds, s, m->d_boxes, n, m->total,
+                           m->per);
+    else
+        hipLaunchKernelGGL(k_pair_hist_multi<false>, dim3(m->G), dim3(TILE), m->lds, s, m->d_boxes, n, m->total,
+                           m->per);
     ND_HIP(hipGetLastError());
 }
 
