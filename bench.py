@@ -28,16 +28,18 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # Minimum VALU lane operations per distance test of the Metropolis scan:
 # 3 sub, 9 nearest image, 3 for r^2, 1 compare with the cutoff.
 OPS_PER_TEST = 16
-# Minimum VALU lane operations per pair of the exact FP64 histogram: 3 sub,
-# 9 nearest image (mul, round, fma per axis), 3 for r^2, 6 for the bin
-# (cvt, sqrt, mul, cvt, edge compare, fix-up), 2 range check and address.
+# Algorithmic VALU lane operations per pair of the exact histogram, as the
+# work unit of its roofline: 3 sub, 9 nearest image (mul, round, fma per
+# axis), 3 for r^2, 6 for the bin (cvt, sqrt, mul, cvt, edge compare,
+# fix-up), 2 range check and address.  The kernel's fixed-point candidate
+# path issues about 18 per pair plus the rare exact edge test.
 OPS_PER_PAIR = 23
 # HBM bytes one k_pair_hist launch moves on the 99,999-atom water box, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch scaled by a 1 GiB copy
-# (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 9830.4 + 19936.0
+# (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 9661.6 + 24958.9
 # KiB.  profiles/k_pair_hist_water99999.md holds the counters and commands;
 # set to None whenever the kernel changes until they are taken again.
-HIST_TRAFFIC_BYTES = None
+HIST_TRAFFIC_BYTES = (2 * 9661.6 + 24958.9) * 1024
 PAPER_GPU_STEPS_PER_S_1E5 = 12412.0  # Table "tab_speed", water, 1e5 atoms, Tesla V100
 
 
@@ -244,7 +246,6 @@ def main():
             "launches": hist_n, "avg_launch_ms": hist_avg_s * 1e3,
             "algorithmic_per_launch": f"{n_pairs} pairs x {OPS_PER_PAIR} lane-ops",
             "pairs_per_s": n_pairs / hist_avg_s,
-            "fp64_flop_frac": n_pairs * 11 / hist_avg_s / 78.6e12,
         },
         "kernels": {
             k: {"launches": n, "ms_total": ms, "share_of_step_time": ms / (1000.0 * elapsed)}
