@@ -58,6 +58,8 @@ def _load():
         "orc_hist_broad_backward": (None, [_i, _d, _i, _p, _p, _d, _i, _d, _p, _p]),
         "orc_sq_adjoint": (None, [_p, _i, _i, _d, _d, _d, _p, _p, _p, _i, _p]),
         "orc_forces": (None, [_i, _d, _i, _p, _p, _p, _p, _i, _d, _d, _p, _p]),
+        "orc_hist_broad_backward_atoms": (None, [_i, _d, _i, _p, _p, _d, _i, _d, _p, _i, _p, _p]),
+        "orc_forces_atoms": (None, [_i, _d, _i, _p, _p, _p, _p, _i, _d, _d, _i, _p, _p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -238,6 +240,19 @@ def hist_broad_backward(box, dr, nbins, sigma, A, xyz=None):
     return grad
 
 
+def hist_broad_backward_atoms(box, dr, nbins, sigma, A, sel, xyz=None):
+    """hist_broad_backward for the atoms sel only (each a sum over all N
+    partners): [3][len(sel)]."""
+    xyz = _c(box.xyz if xyz is None else xyz, np.float32)
+    sp = _c(box.species, np.uint8)
+    A = _c(A, np.float64)
+    sel = _c(sel, np.int32)
+    grad = np.zeros((3, sel.shape[0]))
+    _load().orc_hist_broad_backward_atoms(box.n_atoms, box.L, box.n_species, _ptr(sp), _ptr(xyz), dr,
+                                          int(nbins), sigma, _ptr(A), sel.shape[0], _ptr(sel), _ptr(grad))
+    return grad
+
+
 def sq_adjoint(dLdS, nbins, dr, rho, V, w, npairs, Q):
     dLdS = _c(dLdS, np.float64)
     w = _c(w, np.float64)
@@ -260,6 +275,19 @@ def forces(box, tables, xyz=None):
     _load().orc_forces(box.n_atoms, box.L, box.n_species, _ptr(sp), _ptr(uo), _ptr(xyz), _ptr(U),
                        U.shape[1], tables.h, tables.r_cut, _ptr(grad), C.byref(E))
     return grad, E.value
+
+
+def forces_atoms(box, tables, sel, xyz=None):
+    """The energy gradient of forces() for the atoms sel only: [3][len(sel)]."""
+    xyz = _c(box.xyz if xyz is None else xyz, np.float32)
+    sp = _c(box.species, np.uint8)
+    uo = unit_of_atom(box.unit_offsets)
+    U = _c(tables.U, np.float32)
+    sel = _c(sel, np.int32)
+    grad = np.zeros((3, sel.shape[0]))
+    _load().orc_forces_atoms(box.n_atoms, box.L, box.n_species, _ptr(sp), _ptr(uo), _ptr(xyz), _ptr(U),
+                             U.shape[1], tables.h, tables.r_cut, sel.shape[0], _ptr(sel), _ptr(grad))
+    return grad
 
 
 # ----------------------------------------------------------------------

@@ -469,33 +469,58 @@ void orc_hist_broad(int N, double L, int M, const uint8_t *species, const float 
  * [P][nbins], each pair contributes dL/dr = sum_k A_p(k) dw_k/dr with
  * dw_k/dr = (phi((e_k - r)/s) - phi((e_{k+1} - r)/s)) / s, and
  * dL/dx_i += dL/dr (x_i - x_j)/r, dL/dx_j -= the same.  grad [3][N]. */
+static void broad_grad_atom(int i, int N, double L, int M, const uint8_t *species, const float *xyz,
+                            double dr, int nbins, double sigma, const double *A, double g[3])
+{
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        double d[3];
+        double r = pair_r(xyz, N, L, i, j, d);
+        if (!(r < 0.5 * L) || r == 0.0) continue;
+        int k0, k1;
+        bin_window(r, dr, sigma, nbins, &k0, &k1);
+        int p = orc_pair_index(species[i], species[j], M);
+        double dLdr = 0.0;
+        for (int k = k0; k <= k1; ++k) {
+            double e0 = (double)k * dr, e1 = (double)(k + 1) * dr;
+            dLdr += A[(size_t)p * nbins + k] * (phi((e0 - r) / sigma) - phi((e1 - r) / sigma)) / sigma;
+        }
+        gx += dLdr * d[0] / r;
+        gy += dLdr * d[1] / r;
+        gz += dLdr * d[2] / r;
+    }
+    g[0] = gx;
+    g[1] = gy;
+    g[2] = gz;
+}
+
 void orc_hist_broad_backward(int N, double L, int M, const uint8_t *species, const float *xyz,
                              double dr, int nbins, double sigma, const double *A, double *grad)
 {
-    memset(grad, 0, sizeof(double) * 3 * (size_t)N);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int i = 0; i < N; ++i) {
-        double gx = 0.0, gy = 0.0, gz = 0.0;
-        for (int j = 0; j < N; ++j) {
-            if (j == i) continue;
-            double d[3];
-            double r = pair_r(xyz, N, L, i, j, d);
-            if (!(r < 0.5 * L) || r == 0.0) continue;
-            int k0, k1;
-            bin_window(r, dr, sigma, nbins, &k0, &k1);
-            int p = orc_pair_index(species[i], species[j], M);
-            double dLdr = 0.0;
-            for (int k = k0; k <= k1; ++k) {
-                double e0 = (double)k * dr, e1 = (double)(k + 1) * dr;
-                dLdr += A[(size_t)p * nbins + k] * (phi((e0 - r) / sigma) - phi((e1 - r) / sigma)) / sigma;
-            }
-            gx += dLdr * d[0] / r;
-            gy += dLdr * d[1] / r;
-            gz += dLdr * d[2] / r;
-        }
-        grad[i] = gx;
-        grad[N + i] = gy;
-        grad[2 * N + i] = gz;
+        double g[3];
+        broad_grad_atom(i, N, L, M, species, xyz, dr, nbins, sigma, A, g);
+        grad[i] = g[0];
+        grad[N + i] = g[1];
+        grad[2 * N + i] = g[2];
+    }
+}
+
+/* The same gradient for the atoms sel[0 .. n_sel-1] only (each is a sum over
+ * all N partners): grad_sel [3][n_sel]. */
+void orc_hist_broad_backward_atoms(int N, double L, int M, const uint8_t *species, const float *xyz,
+                                   double dr, int nbins, double sigma, const double *A, int n_sel,
+                                   const int32_t *sel, double *grad_sel)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int q = 0; q < n_sel; ++q) {
+        double g[3];
+        broad_grad_atom(sel[q], N, L, M, species, xyz, dr, nbins, sigma, A, g);
+        grad_sel[q] = g[0];
+        grad_sel[n_sel + q] = g[1];
+        grad_sel[2 * n_sel + q] = g[2];
     }
 }
 
@@ -516,6 +541,30 @@ void orc_sq_adjoint(const double *dLdS, int P, int nbins, double dr, double rho,
     }
 }
 
+/* dE/dx of atom i and half its pair energy (see orc_forces). */
+static void force_atom(int i, int N, double L, int M, const uint8_t *species, const int32_t *unit_of,
+                       const float *xyz, const float *tab, int n_pts, double h, double r_cut, double g[3],
+                       double *e_half)
+{
+    double gx = 0.0, gy = 0.0, gz = 0.0, e = 0.0;
+    for (int j = 0; j < N; ++j) {
+        if (unit_of[i] == unit_of[j]) continue;
+        double d[3];
+        double r = pair_r(xyz, N, L, i, j, d);
+        if (!(r < r_cut) || r == 0.0) continue;
+        const float *row = tab + (size_t)orc_pair_index(species[i], species[j], M) * n_pts;
+        double du = orc_table_du(row, n_pts, h, r_cut, r);
+        e += 0.5 * orc_table_u(row, n_pts, h, r_cut, r);
+        gx += du * d[0] / r;
+        gy += du * d[1] / r;
+        gz += du * d[2] / r;
+    }
+    g[0] = gx;
+    g[1] = gy;
+    g[2] = gz;
+    *e_half = e;
+}
+
 /* Gradient of the total energy: dE/dx_i = sum over j in other units of
  * U'(r) (x_i - x_j)/r, with U' the slope of the table interpolant. */
 void orc_forces(int N, double L, int M, const uint8_t *species, const int32_t *unit_of,
@@ -525,22 +574,27 @@ void orc_forces(int N, double L, int M, const uint8_t *species, const int32_t *u
     double E = 0.0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : E)
     for (int i = 0; i < N; ++i) {
-        double gx = 0.0, gy = 0.0, gz = 0.0;
-        for (int j = 0; j < N; ++j) {
-            if (unit_of[i] == unit_of[j]) continue;
-            double d[3];
-            double r = pair_r(xyz, N, L, i, j, d);
-            if (!(r < r_cut) || r == 0.0) continue;
-            const float *row = tab + (size_t)orc_pair_index(species[i], species[j], M) * n_pts;
-            double du = orc_table_du(row, n_pts, h, r_cut, r);
-            E += 0.5 * orc_table_u(row, n_pts, h, r_cut, r);
-            gx += du * d[0] / r;
-            gy += du * d[1] / r;
-            gz += du * d[2] / r;
-        }
-        grad[i] = gx;
-        grad[N + i] = gy;
-        grad[2 * N + i] = gz;
+        double g[3], e;
+        force_atom(i, N, L, M, species, unit_of, xyz, tab, n_pts, h, r_cut, g, &e);
+        E += e;
+        grad[i] = g[0];
+        grad[N + i] = g[1];
+        grad[2 * N + i] = g[2];
     }
     if (E_out) *E_out = E;
+}
+
+/* The same gradient for the atoms sel[0 .. n_sel-1] only: grad_sel [3][n_sel]. */
+void orc_forces_atoms(int N, double L, int M, const uint8_t *species, const int32_t *unit_of, const float *xyz,
+                      const float *tab, int n_pts, double h, double r_cut, int n_sel, const int32_t *sel,
+                      double *grad_sel)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int q = 0; q < n_sel; ++q) {
+        double g[3], e;
+        force_atom(sel[q], N, L, M, species, unit_of, xyz, tab, n_pts, h, r_cut, g, &e);
+        grad_sel[q] = g[0];
+        grad_sel[n_sel + q] = g[1];
+        grad_sel[2 * n_sel + q] = g[2];
+    }
 }

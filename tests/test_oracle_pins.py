@@ -504,6 +504,24 @@ def test_chi2_gradient_finite_differences(orc):
             assert abs(fd - grad[c, i]) <= 1e-3 * abs(grad[c, i]) + 1e-5 * scale, (i, c, fd, grad[c, i])
 
 
+def test_subset_gradients_equal_full_rows(orc):
+    """The per-atom forms used at full box size give exactly the rows of the
+    full gradients (the same sum over partners, atom by atom)."""
+    box = syn.water_box(60, 12.0, 13)
+    T = syn.water_tables(r_cut=5.5)
+    sigma, dr = 0.02, 0.03
+    nb = syn.n_bins_for(6.0 - 1e-6, dr)
+    rng = np.random.default_rng(14)
+    A = rng.normal(size=(3, nb))
+    sel = np.array([0, 7, 33, 90, 179, 5], np.int32)
+    full = orc.hist_broad_backward(box, dr, nb, sigma, A)
+    sub = orc.hist_broad_backward_atoms(box, dr, nb, sigma, A, sel)
+    assert np.array_equal(sub, full[:, sel])
+    fg, _ = orc.forces(box, T)
+    fs = orc.forces_atoms(box, T, sel)
+    assert np.array_equal(fs, fg[:, sel])
+
+
 def test_sq_adjoint_is_transpose(orc):
     rng = np.random.default_rng(8)
     P, nb, dr, rho, V = 3, 120, 0.05, 0.1, 1000.0
