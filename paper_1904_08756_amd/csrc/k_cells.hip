@@ -9,8 +9,9 @@
 // The build is a counting sort in four launches with no library calls, no
 // memset and no host synchronisation, so it can be captured in a graph:
 // count (atomic arrival rank per cell), scan (cell starts; the counters are
-// cleared for the next build), scatter, and a per-cell pass that puts each
-// cell's atoms in atom order and gathers the sorted copies.  Every kernel
+// cleared for the next build), scatter in arrival order, and a pass with one
+// thread per atom that finds the atom's place in atom order inside its cell
+// by ranking it among the cell's atoms, and gathers the sorted copies.  Every kernel
 // takes an array of box descriptors indexed by blockIdx.y, so one launch
 // rebuilds the cells of several boxes.
 #include "nd_internal.h"
@@ -24,7 +25,7 @@ constexpr int CB_THREADS = 256;
 constexpr int CB_SCAN_THREADS = 1024;
 // A cell holding more atoms than this keeps its atomic arrival order (still
 // a valid cell list; only the summation order, hence the last bits of the
-// energy sums, then depends on scheduling).  Bounds the per-cell sort.
+// energy sums, then depends on scheduling).  Bounds the per-atom ranking.
 constexpr int CB_SORT_MAX = 512;
 
 __device__ __forceinline__ int cell_of(float4 p, int nc)
@@ -46,45 +47,43 @@ __global__ __launch_bounds__(CB_THREADS) void k_cb_count(const nd::CellBuildArgs
 }
 
 // One block per box: start[c] = sum of count[0..c), start[ncell] = N; the
-// counters are cleared behind the scan and the drift is reset.
+// counters are cleared behind the scan and the drift is reset.  Each thread
+// takes a contiguous run of cells: its total, one block-wide exclusive scan
+// of the totals, then the run's starts.
 __global__ __launch_bounds__(CB_SCAN_THREADS) void k_cb_scan(const nd::CellBuildArgs *__restrict__ args)
 {
     __shared__ int s_w[CB_SCAN_THREADS / 64];
-    __shared__ int s_total;
     const nd::CellBuildArgs &A = args[blockIdx.y];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int carry = 0;
-    for (int base = 0; base < A.ncell; base += CB_SCAN_THREADS) {
-        const int j = base + tid;
-        const int v = j < A.ncell ? A.count[j] : 0;
-        int x = v;
+    const int per = (A.ncell + CB_SCAN_THREADS - 1) / CB_SCAN_THREADS;
+    const int c0 = min(tid * per, A.ncell), c1 = min(c0 + per, A.ncell);
+    int v = 0;
+    for (int c = c0; c < c1; ++c) v += A.count[c];
+    int x = v;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(x, o);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) s_w[wave] = x;
-        __syncthreads();
-        if (tid == 0) {
-            int acc = 0;
-            for (int w = 0; w < CB_SCAN_THREADS / 64; ++w) {
-                const int t = s_w[w];
-                s_w[w] = acc;
-                acc += t;
-            }
-            s_total = acc;
-        }
-        __syncthreads();
-        if (j < A.ncell) {
-            A.start[j] = carry + s_w[wave] + x - v;
-            A.count[j] = 0;
-        }
-        carry += s_total;
-        __syncthreads();
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
     if (tid == 0) {
-        A.start[A.ncell] = carry;
+        int acc = 0;
+        for (int w = 0; w < CB_SCAN_THREADS / 64; ++w) {
+            const int t = s_w[w];
+            s_w[w] = acc;
+            acc += t;
+        }
+        A.start[A.ncell] = acc;
         *A.drift = 0.0f;
+    }
+    __syncthreads();
+    int run = s_w[wave] + x - v;
+    for (int c = c0; c < c1; ++c) {
+        const int n = A.count[c];
+        A.start[c] = run;
+        A.count[c] = 0;
+        run += n;
     }
 }
 
@@ -93,37 +92,30 @@ __global__ __launch_bounds__(CB_THREADS) void k_cb_scatter(const nd::CellBuildAr
     const nd::CellBuildArgs &A = args[blockIdx.y];
     const int i = blockIdx.x * CB_THREADS + threadIdx.x;
     if (i >= A.N) return;
-    A.sorted[A.start[A.cellof[i]] + A.rank[i]] = i;
+    A.arrival[A.start[A.cellof[i]] + A.rank[i]] = i;
 }
 
-// One thread per cell: insertion sort of the cell's atoms (a few per cell),
-// then the inverse map and the sorted copies of the positions.
+// One thread per atom: its slot is the cell's start plus the number of the
+// cell's atoms with a smaller index (arrival order for a cell too large to
+// rank); then the inverse map and the sorted copies of the positions.
 __global__ __launch_bounds__(CB_THREADS) void k_cb_finish(const nd::CellBuildArgs *__restrict__ args)
 {
     const nd::CellBuildArgs &A = args[blockIdx.y];
-    const int c = blockIdx.x * CB_THREADS + threadIdx.x;
-    if (c >= A.ncell) return;
+    const int i = blockIdx.x * CB_THREADS + threadIdx.x;
+    if (i >= A.N) return;
+    const int c = A.cellof[i];
     const int b = A.start[c], e = A.start[c + 1];
-    int32_t *s = A.sorted;
+    int x = b + A.rank[i];
     if (e - b <= CB_SORT_MAX) {
-        for (int x = b + 1; x < e; ++x) {
-            const int v = s[x];
-            int y = x - 1;
-            while (y >= b && s[y] > v) {
-                s[y + 1] = s[y];
-                --y;
-            }
-            s[y + 1] = v;
-        }
+        x = b;
+        for (int y = b; y < e; ++y) x += A.arrival[y] < i;
     }
-    for (int x = b; x < e; ++x) {
-        const int atom = s[x];
-        A.slot[atom] = x;
-        const float4 p = A.pos4[atom];
-        A.spos4[x] = p;
-        A.sposlo[x] = A.poslo[atom];
-        A.sref[x] = p;
-    }
+    A.sorted[x] = i;
+    A.slot[i] = x;
+    const float4 p = A.pos4[i];
+    A.spos4[x] = p;
+    A.sposlo[x] = A.poslo[i];
+    A.sref[x] = p;
 }
 
 // Sorted copies of the current positions for a restored slot order.
@@ -158,6 +150,7 @@ void cells_free(nd_box *b)
     dfree(c.sref);
     dfree(c.cellof);
     dfree(c.rank);
+    dfree(c.arrival);
     dfree(c.count);
     dfree(c.drift);
     dfree(c.d_args);
@@ -191,6 +184,7 @@ void cells_ensure(nd_box *b)
     c.sref = static_cast<float4 *>(dmalloc(sizeof(float4) * N));
     c.cellof = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * N));
     c.rank = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * N));
+    c.arrival = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * N));
     c.count = static_cast<int32_t *>(dmalloc(sizeof(int32_t) * ncell));
     c.drift = static_cast<float *>(dmalloc(sizeof(float)));
     c.d_args = static_cast<CellBuildArgs *>(dmalloc(sizeof(CellBuildArgs)));
@@ -198,7 +192,7 @@ void cells_ensure(nd_box *b)
     c.nc = nc;
     c.ncell = ncell;
     c.args = CellBuildArgs{b->pos4, b->poslo, N, nc, ncell, 0, c.cellof, c.rank, c.count, c.start,
-                           c.sorted, c.slot, c.spos4, c.sposlo, c.sref, c.drift};
+                           c.arrival, c.sorted, c.slot, c.spos4, c.sposlo, c.sref, c.drift};
     hipLaunchKernelGGL(k_fill_i32, dim3((ncell + 255) / 256), dim3(256), 0, b->stream, c.count, ncell, 0);
     ND_HIP(hipGetLastError());
     ND_HIP(hipMemcpyAsync(c.d_args, &c.args, sizeof(CellBuildArgs), hipMemcpyHostToDevice, b->stream));
@@ -208,15 +202,15 @@ void cells_ensure(nd_box *b)
 void cells_rebuild_launch(hipStream_t s, const CellBuildArgs *d_args, int n_boxes, int max_n, int max_ncell)
 {
     if (n_boxes <= 0) return;
+    (void)max_ncell;
     const dim3 ga((max_n + CB_THREADS - 1) / CB_THREADS, n_boxes);
-    const dim3 gc((max_ncell + CB_THREADS - 1) / CB_THREADS, n_boxes);
     hipLaunchKernelGGL(k_cb_count, ga, dim3(CB_THREADS), 0, s, d_args);
     ND_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_cb_scan, dim3(1, n_boxes), dim3(CB_SCAN_THREADS), 0, s, d_args);
     ND_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_cb_scatter, ga, dim3(CB_THREADS), 0, s, d_args);
     ND_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_cb_finish, gc, dim3(CB_THREADS), 0, s, d_args);
+    hipLaunchKernelGGL(k_cb_finish, ga, dim3(CB_THREADS), 0, s, d_args);
     ND_HIP(hipGetLastError());
 }
 

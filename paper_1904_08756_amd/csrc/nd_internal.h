@@ -77,6 +77,7 @@ struct CellBuildArgs {
     int32_t *rank;    // [N] arrival rank inside the cell
     int32_t *count;   // [ncell] atoms per cell; zero between builds
     int32_t *start;   // [ncell + 1] first sorted slot of each cell
+    int32_t *arrival; // [N] atoms in cell order, arrival order inside a cell
     int32_t *sorted, *slot;
     float4 *spos4, *sposlo, *sref;
     float *drift;
@@ -91,7 +92,7 @@ struct Cells {
     float4 *spos4 = nullptr;      // [N] current hi + species, sorted order
     float4 *sposlo = nullptr;     // [N] current lo, sorted order
     float4 *sref = nullptr;       // [N] hi at the last rebuild
-    int32_t *cellof = nullptr, *rank = nullptr, *count = nullptr;
+    int32_t *cellof = nullptr, *rank = nullptr, *count = nullptr, *arrival = nullptr;
     float *drift = nullptr;       // device: max distance moved since the rebuild (fractional)
     CellBuildArgs args;           // host copy of the descriptor
     CellBuildArgs *d_args = nullptr;  // device copy
