@@ -45,6 +45,16 @@ __device__ __forceinline__ float gauss_tail(float ax, const float4 *mills)
     return ax < MILLS_XMAX ? phi * R : 0.0f;
 }
 
+// Tail mass phi R(ax) for ax >= 0 given the density phi at ax.
+__device__ __forceinline__ float gauss_tail_phi(float ax, float phi, const float4 *mills)
+{
+    const int i = min((int)fmaf(ax, (float)MILLS_PER_UNIT, 0.5f), MILLS_N - 1);
+    const float4 c = mills[i];
+    const float d = ax - (float)i * (1.0f / MILLS_PER_UNIT);
+    const float R = fmaf(d, fmaf(d, fmaf(d, c.w, c.z), c.y), c.x);
+    return ax < MILLS_XMAX ? phi * R : 0.0f;
+}
+
 // Gaussian density at x (any sign).
 __device__ __forceinline__ float gauss_pdf(float x)
 {
@@ -85,27 +95,69 @@ struct BroadArgs {
     double *partial;  // [gridDim.x][P*nbins]
 };
 
-__global__ __launch_bounds__(TILE) void k_hist_broad(BroadArgs a)
+constexpr int BQ = 128;     // pairs queued per wave
+constexpr int FTILE = 512;  // atoms per tile of the forward: eight waves share one LDS histogram
+
+// The window of one pair at distance r (r < L/2) into the u64 row h: bin
+// weights as differences of the edges' tail masses, in units of 2^-32.  Each
+// edge's density is evaluated directly: a recurrence along the window would
+// raise the rounding of its first factor to the power of the step count,
+// which biases every pair's far bins alike.
+__device__ __forceinline__ void broad_pair(const BroadArgs &a, const float4 *mills, unsigned long long *h, double r)
+{
+    int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
+    int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
+    k0 = max(k0, 0);
+    k1 = min(k1, a.nbins - 1);
+    const double u = r * a.inv_dr;
+    const int kr = (int)u;
+    const float f = (float)(u - (double)kr);
+    const float beta = a.beta;
+    const float x = ((float)(k0 - kr) - f) * beta;
+    float T = gauss_tail_phi(fabsf(x), gauss_pdf(x), mills);
+    bool right = x >= 0.0f;
+    for (int k = k0; k <= k1; ++k) {
+        const float xh = ((float)(k + 1 - kr) - f) * beta;
+        const float Th = gauss_tail_phi(fabsf(xh), gauss_pdf(xh), mills);
+        const bool rh = xh >= 0.0f;
+        const float wk = right ? T - Th : (rh ? 1.0f - T - Th : Th - T);
+        // weight in units of 2^-32 (exact integer sums, deterministic)
+        atomicAdd(&h[k], (unsigned long long)__float2uint_rn(wk * 4294967296.0f));
+        T = Th;
+        right = rh;
+    }
+}
+
+// Each lane owns atom i of the I tile and tests it against the J tile; the
+// pairs inside the window range are queued per wave in LDS and their windows
+// are evaluated 64 at a time, one per lane, so no lane idles on the pairs
+// past L/2.  Integer sums: the result does not depend on the order.
+__global__ __launch_bounds__(FTILE) void k_hist_broad(BroadArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long *hist = reinterpret_cast<unsigned long long *>(smem);  // [P*nbins] weights x 2^32
-    double *jx = reinterpret_cast<double *>(hist + (size_t)a.P * a.nbins);   // [3][TILE]
-    float4 *mills = reinterpret_cast<float4 *>(jx + 3 * TILE);               // [MILLS_N]
-    int *js = reinterpret_cast<int *>(mills + MILLS_N);                       // [TILE]
-    int *prow = js + TILE;                                                    // [16]
-    const int tid = threadIdx.x;
+    double *jx = reinterpret_cast<double *>(hist + (size_t)a.P * a.nbins);   // [3][FTILE]
+    float4 *mills = reinterpret_cast<float4 *>(jx + 3 * FTILE);               // [MILLS_N]
+    int *js = reinterpret_cast<int *>(mills + MILLS_N);                       // [FTILE]
+    int *prow = js + FTILE;                                                    // [16]
+    __shared__ double s_qr[FTILE / 64][BQ];
+    __shared__ int s_qrow[FTILE / 64][BQ];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
     const int nq = a.P * a.nbins;
-    for (int q = tid; q < nq; q += TILE) hist[q] = 0ull;
-    for (int q = tid; q < MILLS_N; q += TILE) mills[q] = nd::ld4(a.mills + q);
+    for (int q = tid; q < nq; q += FTILE) hist[q] = 0ull;
+    for (int q = tid; q < MILLS_N; q += FTILE) mills[q] = nd::ld4(a.mills + q);
     if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.nbins;
     __syncthreads();
     const int N = a.N;
     const double rmax_win = (double)a.nbins * a.dr + a.six_sigma;
-    const float beta = a.beta;
+    double *qr = s_qr[wave];
+    int *qrow = s_qrow[wave];
+    int nqw = 0;  // queued pairs of this wave
     for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
         int I, J;
         tri_index(t, a.nt, I, J);
-        const int i = I * TILE + tid;
+        const int i = I * FTILE + tid;
         const bool iv = i < N;
         double xi = 0.0, yi = 0.0, zi = 0.0;
         int si = 0;
@@ -116,50 +168,49 @@ __global__ __launch_bounds__(TILE) void k_hist_broad(BroadArgs a)
             si = a.sp[i];
         }
         __syncthreads();
-        const int j = J * TILE + tid;
+        const int j = J * FTILE + tid;
         if (j < N) {
             jx[tid] = a.xyz[j];
-            jx[TILE + tid] = a.xyz[N + j];
-            jx[2 * TILE + tid] = a.xyz[2 * N + j];
+            jx[FTILE + tid] = a.xyz[N + j];
+            jx[2 * FTILE + tid] = a.xyz[2 * N + j];
             js[tid] = a.sp[j];
         }
         __syncthreads();
-        const int jn = min(TILE, N - J * TILE);
+        const int jn = min(FTILE, N - J * FTILE);
         const int jstart = (I == J) ? tid + 1 : 0;
-        if (!iv) continue;
         const int rowbase = si * a.M;
-        for (int jj = jstart; jj < jn; ++jj) {
-            const double r2 = nearest_r2(jx[jj] - xi, jx[TILE + jj] - yi, jx[2 * TILE + jj] - zi, a.L);
-            if (!(r2 < a.half2)) continue;
-            const double r = nd::sqrt_nr(r2);
-            if (!(r < rmax_win)) continue;
-            int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
-            int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
-            k0 = max(k0, 0);
-            k1 = min(k1, a.nbins - 1);
-            const double u = r * a.inv_dr;
-            const int kr = (int)u;
-            const float f = (float)(u - (double)kr);
-            unsigned long long *row = hist + prow[rowbase + js[jj]];
-            // tail mass at edge k0: x = (e - r) / s
-            float x = ((float)(k0 - kr) - f) * beta;
-            float T = gauss_tail(fabsf(x), mills);
-            bool right = x >= 0.0f;
-            for (int k = k0; k <= k1; ++k) {
-                const float xh = ((float)(k + 1 - kr) - f) * beta;
-                const float Th = gauss_tail(fabsf(xh), mills);
-                const bool rh = xh >= 0.0f;
-                const float wk = right ? T - Th : (rh ? 1.0f - T - Th : Th - T);
-                // weight in units of 2^-32 (exact integer sums, deterministic)
-                atomicAdd(&row[k], (unsigned long long)__float2uint_rn(wk * 4294967296.0f));
-                T = Th;
-                right = rh;
+        for (int jj = 0; jj < jn; ++jj) {
+            const double r2 = nearest_r2(jx[jj] - xi, jx[FTILE + jj] - yi, jx[2 * FTILE + jj] - zi, a.L);
+            bool in = iv && jj >= jstart && r2 < a.half2;
+            const double r = nd::sqrt_nr(in ? r2 : 1.0);
+            in = in && r < rmax_win;
+            const unsigned long long bal = __ballot(in);
+            if (in) {
+                const int q = nqw + __popcll(bal & lt);
+                qr[q] = r;
+                qrow[q] = prow[rowbase + js[jj]];
+            }
+            nqw += __popcll(bal);
+            if (nqw >= 64) {
+                __builtin_amdgcn_wave_barrier();
+                const double rq = qr[lane];
+                const int rowq = qrow[lane];
+                __builtin_amdgcn_wave_barrier();
+                if (lane < nqw - 64) {
+                    qr[lane] = qr[64 + lane];
+                    qrow[lane] = qrow[64 + lane];
+                }
+                nqw -= 64;
+                __builtin_amdgcn_wave_barrier();
+                broad_pair(a, mills, hist + rowq, rq);
             }
         }
     }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < nqw) broad_pair(a, mills, hist + qrow[lane], qr[lane]);
     __syncthreads();
     double *out = a.partial + (size_t)blockIdx.x * nq;
-    for (int q = tid; q < nq; q += TILE) out[q] = (double)hist[q] * 2.3283064365386963e-10;
+    for (int q = tid; q < nq; q += FTILE) out[q] = (double)hist[q] * 2.3283064365386963e-10;
 }
 
 __global__ void k_reduce_f64(const double *__restrict__ partial, int G, int n, double *__restrict__ out)
@@ -436,7 +487,7 @@ void launch_hist_broad(nd_box *b, double dr, int nbins, double sigma, double *d_
     a.M = b->M;
     a.P = b->P;
     a.nbins = nbins;
-    a.nt = (b->N + TILE - 1) / TILE;
+    a.nt = (b->N + FTILE - 1) / FTILE;
     a.ntp = (long long)a.nt * (a.nt + 1) / 2;
     a.L = b->L;
     a.invL = 1.0 / b->L;
@@ -447,18 +498,19 @@ void launch_hist_broad(nd_box *b, double dr, int nbins, double sigma, double *d_
     a.beta = (float)(dr / sigma);
     a.mills = mills_table(b);
     const int nq = a.P * nbins;
-    size_t lds = sizeof(double) * ((size_t)nq + 3 * TILE) + sizeof(float4) * MILLS_N + sizeof(int) * (TILE + 16);
-    if (lds > 160 * 1024) fail(ND_E_UNSUPPORTED, "broadened histogram does not fit in LDS");
-    int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (lds + 1024)));
+    size_t lds = sizeof(double) * ((size_t)nq + 3 * FTILE) + sizeof(float4) * MILLS_N + sizeof(int) * (FTILE + 16);
+    const size_t lds_queue = (sizeof(double) + sizeof(int)) * BQ * (FTILE / 64);  // static, in the kernel
+    if (lds + lds_queue > 160 * 1024) fail(ND_E_UNSUPPORTED, "broadened histogram does not fit in LDS");
+    int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (lds + lds_queue + 1024)));
     long long G = (long long)cu_count(b->device) * per_cu;
     if (G > a.ntp) G = a.ntp;
     // a block's integer sum of weights < 1 per pair stays below 2^64
-    if ((double)((a.ntp + G - 1) / G) * TILE * TILE >= 4294967295.0)
+    if ((double)((a.ntp + G - 1) / G) * FTILE * FTILE >= 4294967295.0)
         fail(ND_E_UNSUPPORTED, "box too large for the broadened histogram's block sums");
     a.partial = static_cast<double *>(workspace(b, sizeof(double) * (size_t)G * nq));
     {
         ProfScope ps(b, ND_PROF_HIST_BROAD);
-        hipLaunchKernelGGL(k_hist_broad, dim3((unsigned)G), dim3(TILE), lds, b->stream, a);
+        hipLaunchKernelGGL(k_hist_broad, dim3((unsigned)G), dim3(FTILE), lds, b->stream, a);
         ND_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_reduce_f64, dim3((nq + 255) / 256), dim3(256), 0, b->stream, a.partial, (int)G, nq, d_nhat);
