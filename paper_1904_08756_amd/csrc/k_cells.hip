@@ -115,7 +115,7 @@ __global__ __launch_bounds__(CB_THREADS) void k_cb_finish(const nd::CellBuildArg
     const float4 p = A.pos4[i];
     A.spos4[x] = p;
     A.sposlo[x] = A.poslo[i];
-    A.sref[x] = p;
+    A.sref[i] = p;
 }
 
 // Sorted copies of the current positions for a restored slot order.

@@ -386,6 +386,7 @@ struct CorrArgs {
     double rcf2, tscale;
     int32_t *corr_n, *corr_ptr;  // [K] entries of trial k and where they start
     float *corr_s;               // [K] sum of |U| over all of trial k's correction terms
+    double2 *corr_b;             // [2K] (lo, hi), (mag, count) of trial k's entries with m >= 0
     int32_t *pool_m;             // earlier trial m (increasing within a trial); -1: C_km = 0
     double *pool_c;              // C_km, the change of k's dE if m was accepted
     int32_t *ovf_fill;           // overflow entries used in this batch
@@ -462,7 +463,11 @@ __device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, 
         a.corr_ptr[k] = base;
     }
     if (n == 0) {
-        if (lane == 0) a.corr_s[k] = 0.0f;
+        if (lane == 0) {
+            a.corr_s[k] = 0.0f;
+            nd::st_d2(a.corr_b + 2 * k, make_double2(0.0, 0.0));
+            nd::st_d2(a.corr_b + 2 * k + 1, make_double2(0.0, 0.0));
+        }
         return;
     }
     const nd::Trial *Tk = a.trials + k;
@@ -482,6 +487,7 @@ __device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, 
     const int hl = lane / IPH, r = lane - hl * IPH;
     const int y = r >> 1, om = r & 1;  // atom of m; 0: m old, 1: m new
     double Sk = 0.0;
+    double blo = 0.0, bhi = 0.0, bmag = 0.0, bnv = 0.0;  // bracket summary of the entries with m >= 0
     int wbase = 0;
     for (int h0 = 0; h0 < n; h0 += HPR) {
         if (h0 + HPR > wbase + CORR_LIST) {
@@ -527,15 +533,30 @@ __device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, 
                 S += cs.ps[lane * IPH + q];
             }
             const int m = cs.wl[h0 + lane - wbase];
-            stg(a.pool_m + base + h0 + lane, S > 0.0 ? m : -1);
+            const bool v = S > 0.0;
+            stg(a.pool_m + base + h0 + lane, v ? m : -1);
             stg(a.pool_c + base + h0 + lane, C);
             Sk += S;
+            blo += v ? fmin(C, 0.0) : 0.0;
+            bhi += v ? fmax(C, 0.0) : 0.0;
+            bmag += v ? fabs(C) : 0.0;
+            bnv += v ? 1.0 : 0.0;
         }
         __builtin_amdgcn_wave_barrier();
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) Sk += __shfl_xor(Sk, o);
-    if (lane == 0) a.corr_s[k] = (float)Sk;
+    for (int o = 32; o > 0; o >>= 1) {
+        Sk += __shfl_xor(Sk, o);
+        blo += __shfl_xor(blo, o);
+        bhi += __shfl_xor(bhi, o);
+        bmag += __shfl_xor(bmag, o);
+        bnv += __shfl_xor(bnv, o);
+    }
+    if (lane == 0) {
+        a.corr_s[k] = (float)Sk;
+        nd::st_d2(a.corr_b + 2 * k, make_double2(blo, bhi));
+        nd::st_d2(a.corr_b + 2 * k + 1, make_double2(bmag, bnv));
+    }
 }
 
 template <int MAXNU>
@@ -874,6 +895,7 @@ __global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void 
 
 // ---------------------------------------------------------------- decide
 constexpr int DEC_THREADS = 1024;
+static_assert(KMAX <= 2 * DEC_THREADS, "a decide thread holds at most two trials");
 
 struct DecideArgs {
     float *xyz;
@@ -884,6 +906,7 @@ struct DecideArgs {
     const double *dE0, *S0;
     const int32_t *corr_n, *corr_ptr, *pool_m;
     const float *corr_s;
+    const double2 *corr_b;
     const double *pool_c;
     int32_t *ovf_fill;
     // cell copies (null when cells are not in use)
@@ -993,7 +1016,8 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
 {
     __shared__ double s_e[KMAX];      // dE0, then the final dE
     __shared__ double s_u[KMAX];      // acceptance threshold -kT ln u
-    __shared__ int s_n[KMAX];
+    __shared__ double s_S[KMAX];      // sum of |U| over the trial's pair terms
+    __shared__ int s_n[KMAX];         // entries to read (0 when none has m >= 0)
     __shared__ int s_ptr[KMAX];
     __shared__ int s_a0[KMAX];
     __shared__ unsigned char s_na[KMAX];
@@ -1008,40 +1032,55 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
     const int kb = a.kb;
 
     if (kb > 0) {
-        // trial data and the first pass (needs no other decision)
+        // trial data and the first pass (needs no other decision): a thread
+        // holds trials tid and tid + DEC_THREADS and issues all their loads
+        // before using any; the bracket of the open terms is the summary the
+        // correction step wrote, so no entry is read here
         int my_open = 0;
-        for (int k = tid; k < kb; k += DEC_THREADS) {
-            const int n = ldg(a.corr_n + k);
-            const int ptr = ldg(a.corr_ptr + k);
-            const double e0 = ldg(a.dE0 + k);
-            const nd::Trial &T = a.trials[k];
-            const int4 ids = ld_i4(reinterpret_cast<const int4 *>(&T.unit));
-            const double thr = accept_threshold(ldg(&T.u_acc), a.kT);
-            double lo = 0.0, hi = 0.0, mag = fabs(e0);
-            bool any = false;
-            for_entries(a, k, n, ptr, [&](int m, double c) {
-                const bool v = m >= 0;
-                any |= v;
-                lo += v ? fmin(c, 0.0) : 0.0;
-                hi += v ? fmax(c, 0.0) : 0.0;
-                mag += v ? fabs(c) : 0.0;
-            });
-            unsigned char d;
-            if (!any) {
-                d = metropolis(e0, thr) ? ST_ACC : ST_REJ;
-            } else {
-                const double eps = 1e-12 * mag;
-                const bool alo = metropolis(e0 + lo - eps, thr), ahi = metropolis(e0 + hi + eps, thr);
-                d = alo == ahi ? (alo ? ST_ACC : ST_REJ) : ST_OPEN;
+        int n[2], ptr[2];
+        double e0[2], u[2], S[2];
+        double2 blh[2], bmc[2];
+        int4 ids[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = tid + h * DEC_THREADS;
+            if (k < kb) {
+                n[h] = ldg(a.corr_n + k);
+                ptr[h] = ldg(a.corr_ptr + k);
+                e0[h] = ldg(a.dE0 + k);
+                const nd::Trial &T = a.trials[k];
+                ids[h] = ld_i4(reinterpret_cast<const int4 *>(&T.unit));
+                u[h] = ldg(&T.u_acc);
+                S[h] = ldg(a.S0 + k) + (double)ldg(a.corr_s + k);
+                blh[h] = ld_d2(a.corr_b + 2 * k);
+                bmc[h] = ld_d2(a.corr_b + 2 * k + 1);
             }
-            s_e[k] = e0;
-            s_u[k] = thr;
-            s_n[k] = n;
-            s_ptr[k] = ptr;
-            s_a0[k] = ids.y;
-            s_na[k] = (unsigned char)ids.z;
-            s_st[k] = d;
-            my_open += d == ST_OPEN;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = tid + h * DEC_THREADS;
+            if (k < kb) {
+                const double thr = accept_threshold(u[h], a.kT);
+                const bool any = bmc[h].y > 0.0;
+                unsigned char d;
+                if (!any) {
+                    d = metropolis(e0[h], thr) ? ST_ACC : ST_REJ;
+                } else {
+                    const double eps = 1e-12 * (fabs(e0[h]) + bmc[h].x);
+                    const bool alo = metropolis(e0[h] + blh[h].x - eps, thr),
+                               ahi = metropolis(e0[h] + blh[h].y + eps, thr);
+                    d = alo == ahi ? (alo ? ST_ACC : ST_REJ) : ST_OPEN;
+                }
+                s_e[k] = e0[h];
+                s_u[k] = thr;
+                s_S[k] = S[h];
+                s_n[k] = any ? n[h] : 0;
+                s_ptr[k] = ptr[h];
+                s_a0[k] = ids[h].y;
+                s_na[k] = (unsigned char)ids[h].z;
+                s_st[k] = d;
+                my_open += d == ST_OPEN;
+            }
         }
         if (tid == 0) *a.ovf_fill = 0;  // overflow area is free for the next batch
         if (tid < N_SLAB) a.slab_cnt[tid] = 0;  // the scan of this batch is done with its lists
@@ -1101,7 +1140,7 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                 e += (m >= 0 && s_st[m] == ST_ACC) ? c : 0.0;
             });
             const bool acc = s_st[k] == ST_ACC;
-            const double S = ldg(a.S0 + k) + (double)ldg(a.corr_s + k);
+            const double S = s_S[k];
             const double thr = s_u[k];
             // |ln u + dE/kT| < tie_rel S / kT, i.e. |dE - (-kT ln u)| < tie_rel S (u > 0)
             if (thr != 745.13321910194122 * a.kT && fabs(e - thr) < a.tie_rel * S) ++ntie;
@@ -1121,7 +1160,7 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
         constexpr int CU = 4;
         for (int base = tid; base < n_items; base += CU * DEC_THREADS) {
             int idx[CU], slot[CU];
-            float4 hi[CU], lo[CU];
+            float4 hi[CU], lo[CU], ref[CU];
             float nx[CU][3];
 #pragma unroll
             for (int u = 0; u < CU; ++u) {
@@ -1137,7 +1176,10 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                         nx[u][0] = ldg(&T.new_x[at][0]);
                         nx[u][1] = ldg(&T.new_x[at][1]);
                         nx[u][2] = ldg(&T.new_x[at][2]);
-                        slot[u] = a.cell_slot ? ldg(a.cell_slot + idx[u]) : 0;
+                        if (a.cell_slot) {
+                            slot[u] = ldg(a.cell_slot + idx[u]);
+                            ref[u] = ld4(a.sref + idx[u]);
+                        }
                     }
                 }
             }
@@ -1154,7 +1196,7 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                     const int sl = slot[u];
                     a.spos4[sl] = hi[u];
                     a.sposlo[sl] = lo[u];
-                    const float4 r = ld4(a.sref + sl);
+                    const float4 r = ref[u];
                     float dx = hi[u].x - r.x, dy = hi[u].y - r.y, dz = hi[u].z - r.z;
                     dx -= rintf(dx);
                     dy -= rintf(dy);
@@ -1306,6 +1348,7 @@ void ensure_work(nd_box *b, int K, int n_jb)
     nd::dfree(w.pool_m);
     nd::dfree(w.pool_c);
     nd::dfree(w.corr_s);
+    nd::dfree(w.corr_b);
     nd::dfree(w.slab);
     long long *counters = w.counters;
     double *dsum = w.dsum;
@@ -1325,6 +1368,7 @@ void ensure_work(nd_box *b, int K, int n_jb)
     w.pool_m = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * pool));
     w.pool_c = static_cast<double *>(nd::dmalloc(sizeof(double) * pool));
     w.corr_s = static_cast<float *>(nd::dmalloc(sizeof(float) * K));
+    w.corr_b = static_cast<double2 *>(nd::dmalloc(sizeof(double2) * 2 * K));
     w.slab = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * 2 * (size_t)(N_SLAB + N_SLAB * K)));
     if (!w.counters) w.counters = static_cast<long long *>(nd::dmalloc(sizeof(long long) * 4));
     if (!w.dsum) w.dsum = static_cast<double *>(nd::dmalloc(sizeof(double)));
@@ -1439,6 +1483,7 @@ CorrArgs corr_args(const nd_box *b, const McConsts &k, const nd::Trial *trials, 
     cr.corr_n = w.corr_n;
     cr.corr_ptr = w.corr_ptr;
     cr.corr_s = w.corr_s;
+    cr.corr_b = w.corr_b;
     cr.pool_m = w.pool_m;
     cr.pool_c = w.pool_c;
     cr.ovf_fill = w.ovf_fill;
@@ -1463,6 +1508,7 @@ DecideArgs decide_args(const nd_box *b, const nd_mc_params *p, const McConsts &k
     da.pool_m = w.pool_m;
     da.pool_c = w.pool_c;
     da.corr_s = w.corr_s;
+    da.corr_b = w.corr_b;
     da.ovf_fill = w.ovf_fill;
     da.cell_slot = cells_live ? b->cells.slot : nullptr;
     da.spos4 = cells_live ? b->cells.spos4 : nullptr;

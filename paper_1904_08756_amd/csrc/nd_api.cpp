@@ -293,6 +293,7 @@ static void free_box(nd_box *b)
     nd::dfree(b->mc.pool_m);
     nd::dfree(b->mc.pool_c);
     nd::dfree(b->mc.corr_s);
+    nd::dfree(b->mc.corr_b);
     nd::dfree(b->mc.spheres);
     nd::dfree(b->mc.dE0);
     nd::dfree(b->mc.S0);

@@ -60,6 +60,7 @@ struct McWork {
     int32_t *corr_n = nullptr;    // [cap_k] correction entries of trial k
     int32_t *corr_ptr = nullptr;  // [cap_k] first entry of trial k in the pool
     float *corr_s = nullptr;      // [cap_k] sum |U| over trial k's correction terms
+    double2 *corr_b = nullptr;    // [2 cap_k] (lo, hi), (mag, count) of trial k's entries with m >= 0
     int32_t *pool_m = nullptr;    // [cap_pool] earlier trial m of each entry (increasing), -1 if C = 0
     double *pool_c = nullptr;     // [cap_pool] energy correction if m was accepted
     int32_t *ovf_fill = nullptr;  // entries used in the pool's overflow area
@@ -91,7 +92,7 @@ struct Cells {
     int32_t *slot = nullptr;      // [N] atom -> slot
     float4 *spos4 = nullptr;      // [N] current hi + species, sorted order
     float4 *sposlo = nullptr;     // [N] current lo, sorted order
-    float4 *sref = nullptr;       // [N] hi at the last rebuild
+    float4 *sref = nullptr;       // [N] hi at the last rebuild, by atom
     int32_t *cellof = nullptr, *rank = nullptr, *count = nullptr, *arrival = nullptr;
     float *drift = nullptr;       // device: max distance moved since the rebuild (fractional)
     CellBuildArgs args;           // host copy of the descriptor
@@ -213,7 +214,7 @@ struct CellState {
     long long trials_since_build;
     float drift;
     const int32_t *sorted, *slot, *start;  // [N], [N], [ncell + 1]
-    const float4 *sref;                    // [N]
+    const float4 *sref;                    // [N] by atom
 };
 void cells_restore(nd_box *b, const CellState &st);
 

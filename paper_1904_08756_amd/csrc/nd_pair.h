@@ -52,6 +52,15 @@ __device__ __forceinline__ void stg(T *p, T v)
     *(ND_GLOBAL_AS T *)p = v;
 }
 
+__device__ __forceinline__ void st_d2(double2 *p, double2 v)
+{
+    typedef double v2d __attribute__((ext_vector_type(2)));
+    v2d x;
+    x.x = v.x;
+    x.y = v.y;
+    *(ND_GLOBAL_AS v2d *)p = x;
+}
+
 // Block-wide copy of n floats from global memory to 16-byte aligned LDS
 // (src 16-byte aligned): all wide loads of a thread are issued before its
 // LDS writes, so the copy costs about one memory latency, not one per
