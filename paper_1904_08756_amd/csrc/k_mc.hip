@@ -584,6 +584,7 @@ struct CellScanArgs {
     const float *drift;
     const int32_t *slab;     // [N_SLAB] counts, then [N_SLAB][kcap] trial lists
     int M, n_pts, kb, nc, kcap, per_slab;
+    int nw;                  // waves per trial (1, 2 or 4; picks the kernel)
     float rcf, rcf2_filter;
     double rcf2, tscale;
     double *dE0, *S0;
@@ -661,9 +662,9 @@ __device__ __forceinline__ float gap_to_cell(float c, int i, float inv_nc)
     return fmaxf(0.0f, fabsf(d) - 0.5f * inv_nc);
 }
 
-// Trial k by one block of four waves.  The cell rows (z, y) within reach
-// of the trial's bounding sphere are dealt round-robin to the waves; each
-// row is cut to the chord of the reach sphere at the row's nearest point
+// Trial k by NW waves (wsub = the wave's rank among them).  The cell rows
+// (z, y) within reach of the trial's bounding sphere are dealt round-robin
+// to the waves; each row is cut to the chord of the reach sphere at the row's nearest point
 // (rows that miss the sphere are skipped) and split in two slot ranges
 // where it wraps.  A wave fetches up to 64 rows at once (one per lane),
 // concatenates their slot ranges with a prefix sum, and walks the
@@ -671,11 +672,28 @@ __device__ __forceinline__ float gap_to_cell(float c, int i, float inv_nc)
 // lies within r_cut + radius of the centre (atoms of the moved unit, known
 // by the unit in lo.w, aside) are compacted into LDS and their exact pair
 // terms summed.
-template <int MAXNU>
-__device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const PairCtx &c, int k, float4 *list, float4 *listlo,
-                                 double *red, TrialAtoms &ta)
+template <int NW>
+__device__ __forceinline__ void scan_sync()
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (NW == 1)
+        __builtin_amdgcn_wave_barrier();
+    else
+        __syncthreads();
+}
+
+// With NW > 1 every wave of the block calls this the same number of times
+// (active false: a wave with no trial in this round, which only takes part
+// in the barriers).
+template <int MAXNU, int NW>
+__device__ __forceinline__ void scan_cells_group(const CellScanArgs &a, const PairCtx &c, int k, bool active, int wsub,
+                                                 int lane, float4 *list, float4 *listlo, double *red, TrialAtoms &ta)
+{
+    scan_sync<NW>();  // the previous trial is done with ta, red and the lists
+    if (!active) {
+        scan_sync<NW>();
+        scan_sync<NW>();
+        return;
+    }
     const nd::Trial *T = a.trials + k;
     const int tna = T->na, tunit = T->unit;
     const float cx = T->cen[0], cy = T->cen[1], cz = T->cen[2];
@@ -684,10 +702,10 @@ __device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const Pa
     // r_cut + 2 rad < L/2: every pair term of the trial can take the nearest
     // image of its survivor relative to the centre (see cell_flush)
     const bool cimg = a.rcf + 2.0f * T->rad + 1e-4f < 0.5f;
-    if (tid < 2 * tna) {
-        const int at = tid >> 1;
-        const float4 h = ld4((tid & 1) ? &T->new_hi[at] : &T->old_hi[at]);
-        const float4 l = ld4((tid & 1) ? &T->new_lo[at] : &T->old_lo[at]);
+    if (wsub == 0 && lane < 2 * tna) {
+        const int at = lane >> 1;
+        const float4 h = ld4((lane & 1) ? &T->new_hi[at] : &T->old_hi[at]);
+        const float4 l = ld4((lane & 1) ? &T->new_lo[at] : &T->old_lo[at]);
         double x = (double)h.x + (double)l.x, y = (double)h.y + (double)l.y, z = (double)h.z + (double)l.z;
         if (cimg) {
             // the atom's image nearest the centre (atoms are wrapped one by one)
@@ -695,12 +713,12 @@ __device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const Pa
             y -= rint(y - (double)cy);
             z -= rint(z - (double)cz);
         }
-        ta.x[tid] = x;
-        ta.y[tid] = y;
-        ta.z[tid] = z;
-        ta.rb[tid] = __float_as_int(h.w) * c.M;
+        ta.x[lane] = x;
+        ta.y[lane] = y;
+        ta.z[lane] = z;
+        ta.rb[lane] = __float_as_int(h.w) * c.M;
     }
-    __syncthreads();
+    scan_sync<NW>();
     const float reach = surv + *a.drift + 1e-6f;
     const float reach2 = reach * reach;
     const int nc = a.nc;
@@ -710,7 +728,7 @@ __device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const Pa
     const int ly = (int)floorf((cy - reach) * fnc), hy = min((int)floorf((cy + reach) * fnc), ly + nc - 1);
     const int cnty = hy - ly + 1;
     const int nrows = (hz - lz + 1) * cnty;
-    const int my_rows = nrows > wave ? (nrows - wave + 3) / 4 : 0;
+    const int my_rows = nrows > wsub ? (nrows - wsub + NW - 1) / NW : 0;
     const unsigned long long lt = (1ull << lane) - 1ull;
     double e = 0.0, s = 0.0;
     int nlist = 0;
@@ -719,7 +737,7 @@ __device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const Pa
         const int sid = sp + lane;
         int b0 = 0, n0 = 0, b1 = 0, n1 = 0;
         if (sid < my_rows) {
-            const int r = wave + 4 * sid;
+            const int r = wsub + NW * sid;
             const int zu = lz + r / cnty, yu = ly + r % cnty;
             const float gz = gap_to_cell(cz, zu, inv_nc), gy = gap_to_cell(cy, yu, inv_nc);
             const float d2 = gz * gz + gy * gy;
@@ -818,21 +836,34 @@ __device__ __forceinline__ void scan_cells_block(const CellScanArgs &a, const Pa
         e += __shfl_xor(e, o);
         s += __shfl_xor(s, o);
     }
-    if (lane == 0) {
-        red[2 * wave] = e;
-        red[2 * wave + 1] = s;
+    if (NW == 1) {
+        if (lane == 0) {
+            a.dE0[k] = e;
+            a.S0[k] = s;
+        }
+        return;
     }
-    __syncthreads();
-    if (tid == 0) {
-        a.dE0[k] = (red[0] + red[2]) + (red[4] + red[6]);
-        a.S0[k] = (red[1] + red[3]) + (red[5] + red[7]);
+    if (lane == 0) {
+        red[2 * wsub] = e;
+        red[2 * wsub + 1] = s;
+    }
+    scan_sync<NW>();
+    if (wsub == 0 && lane == 0) {
+        double E = red[0], S = red[1];
+        for (int w = 1; w < NW; ++w) {
+            E += red[2 * w];
+            S += red[2 * w + 1];
+        }
+        a.dE0[k] = E;
+        a.S0[k] = S;
     }
 }
 
 // Blocks of one launch, in dispatch order: the proposals of the next
 // batch (its units are disjoint from this batch's) and the in-batch
 // corrections, which are few and long, so they start first; padding to a
-// multiple of 8; then the cell scans, block b of them on XCD b mod 8 taking
+// multiple of 8; then the cell scans, 4/NW trials per block (NW waves
+// each, sharing the staged tables), block b of them on XCD b mod 8 taking
 // the trials whose centre lies in z-slab b mod 8, so each XCD's L2 holds
 // about one slab of the cell data instead of all of it.
 __host__ __device__ inline int scan_front_blocks(int kb, int kb_next)
@@ -843,15 +874,16 @@ __host__ __device__ inline int scan_front_blocks(int kb, int kb_next)
 
 static_assert(sizeof(CorrScratch) <= 2 * sizeof(float4) * CS_LIST, "correction scratch must fit a wave's survivor lists");
 
-template <int MAXNU>
+template <int MAXNU, int NW>
 __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const CorrArgs &ca, const ProposeArgs &next,
                                                int bx)
 {
+    constexpr int TPB = 4 / NW;  // trials per block
     extern __shared__ __align__(16) float s_tab[];  // [P][n_pts]
     __shared__ int s_prow[16];
     __shared__ float4 s_list[4][2][CS_LIST];  // per wave: survivors hi, then lo
-    __shared__ double s_red[8];
-    __shared__ TrialAtoms s_ta;
+    __shared__ TrialAtoms s_ta[TPB];
+    __shared__ double s_red[TPB][2 * NW];
     const int tid = threadIdx.x;
     const int n_prop = (next.kb + 255) / 256;
     const int n_corr = (a.kb + CORR_TPB - 1) / CORR_TPB;
@@ -874,23 +906,30 @@ __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const Corr
     const int sb = bx - n_front;
     const int slab = sb & (N_SLAB - 1);
     const int cnt = a.slab[slab];
-    const int i0 = sb >> 3;
+    const int i0 = (sb >> 3) * TPB;
     if (i0 >= cnt) return;
     const int P = a.M * (a.M + 1) / 2;
     nd::stage_floats<256>(s_tab, a.tab, P * a.n_pts);
     if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
+    __syncthreads();  // tables staged
     const PairCtx c{s_tab, s_prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
     const int32_t *lst = a.slab + N_SLAB + slab * a.kcap;
-    for (int i = i0; i < cnt; i += a.per_slab) {
-        __syncthreads();  // tables staged; the previous trial is done with s_ta and s_red
-        scan_cells_block<MAXNU>(a, c, lst[i], s_list[tid >> 6][0], s_list[tid >> 6][1], s_red, s_ta);
+    const int wave = tid >> 6, grp = wave / NW, wsub = wave % NW;
+    const int stride = a.per_slab * TPB;
+    // rounds of the block (the same for all its waves): group 0 has the most
+    const int rounds = (cnt - i0 + stride - 1) / stride;
+    for (int it = 0; it < rounds; ++it) {
+        const int i = i0 + grp + it * stride;
+        const bool active = i < cnt;
+        scan_cells_group<MAXNU, NW>(a, c, active ? lst[i] : 0, active, wsub, tid & 63, s_list[wave][0],
+                                     s_list[wave][1], s_red[grp], s_ta[grp]);
     }
 }
 
-template <int MAXNU>
+template <int MAXNU, int NW>
 __global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void k_mc_scan_corr(CellScanArgs a, CorrArgs ca, ProposeArgs next)
 {
-    scan_corr_body<MAXNU>(a, ca, next, blockIdx.x);
+    scan_corr_body<MAXNU, NW>(a, ca, next, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- decide
@@ -1270,12 +1309,12 @@ struct McLaunch {
 
 // The same kernels over several boxes at once: blockIdx.y selects the box's
 // batch descriptor, blocks past a box's own grid return at once.
-template <int MAXNU>
+template <int MAXNU, int NW>
 __global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void k_mc_scan_corr_multi(const McLaunch *__restrict__ L)
 {
     const McLaunch &e = L[blockIdx.y];
     if ((int)blockIdx.x >= e.nblk) return;
-    scan_corr_body<MAXNU>(e.ca, e.cr, e.next, blockIdx.x);
+    scan_corr_body<MAXNU, NW>(e.ca, e.cr, e.next, blockIdx.x);
 }
 
 __global__ __launch_bounds__(DEC_THREADS) void k_mc_decide_multi(const McLaunch *__restrict__ L)
@@ -1320,7 +1359,11 @@ void launch_scan_corr(nd_box *b, const CellScanArgs &ca, const CorrArgs &cr, con
 {
     nd::ProfScope ps(b, ND_PROF_MC_SCAN);
     const int nblk = scan_front_blocks(ca.kb, next.kb) + N_SLAB * ca.per_slab;
-    hipLaunchKernelGGL(k_mc_scan_corr<MAXNU>, dim3(nblk), dim3(256), slds, b->stream, ca, cr, next);
+    switch (ca.nw) {
+    case 1: hipLaunchKernelGGL((k_mc_scan_corr<MAXNU, 1>), dim3(nblk), dim3(256), slds, b->stream, ca, cr, next); break;
+    case 2: hipLaunchKernelGGL((k_mc_scan_corr<MAXNU, 2>), dim3(nblk), dim3(256), slds, b->stream, ca, cr, next); break;
+    default: hipLaunchKernelGGL((k_mc_scan_corr<MAXNU, 4>), dim3(nblk), dim3(256), slds, b->stream, ca, cr, next); break;
+    }
     ND_HIP(hipGetLastError());
 }
 
@@ -1434,12 +1477,26 @@ int32_t *slab_buffer(const nd_box *b, int buf)
     return w.slab + (size_t)buf * (N_SLAB + (size_t)N_SLAB * w.cap_k);
 }
 
-// Scan blocks per slab: the mean count of a slab plus three standard
-// deviations, so that a block rarely takes a second trial.
-int per_slab_blocks(int kb)
+// Scan blocks per slab: room for the mean count of a slab plus three
+// standard deviations, so that a wave rarely takes a second trial.
+int per_slab_blocks(int kb, int nw)
 {
     const double m = (double)kb / N_SLAB;
-    return std::max(1, (int)std::ceil(m + 3.0 * std::sqrt(m)));
+    return std::max(1, (int)std::ceil((m + 3.0 * std::sqrt(m)) * nw / 4.0));
+}
+
+// Waves per trial of a scan launch holding `trials` trials: the most of
+// 4, 2, 1 that keeps all of them in flight at once (16 waves per CU at the
+// kernel's register use, with a quarter to spare for the correction
+// blocks).  A trial's chain of dependent loads is shorter with more waves;
+// more trials at once beat that when the GPU would otherwise take them in
+// several rounds.
+int pick_scan_nw(long long trials, int ncu)
+{
+    const long long slots = 16LL * ncu * 5 / 4;
+    if (4 * trials <= slots) return 4;
+    if (2 * trials <= slots) return 2;
+    return 1;
 }
 
 ProposeArgs proposal_args(const nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t t0, int kb, int buf, int K)
@@ -1574,7 +1631,8 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         ca.sposlo = b->cells.sposlo;
         ca.slab = slab_buffer(b, buf);
         ca.kcap = w.cap_k;
-        ca.per_slab = per_slab_blocks(kb);
+        ca.nw = pick_scan_nw(kb, nd::cu_count(b->device));
+        ca.per_slab = per_slab_blocks(kb, ca.nw);
         ca.cstart = b->cells.start;
         ca.tab = b->tab;
         ca.trials = trials;
@@ -1610,20 +1668,25 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
 }
 
 template <int MAXNU>
-void launch_scan_corr_multi(hipStream_t s, const McLaunch *d_L, int n_boxes, int max_blk, size_t lds)
+void launch_scan_corr_multi(hipStream_t s, int nw, const McLaunch *d_L, int n_boxes, int max_blk, size_t lds)
 {
-    hipLaunchKernelGGL(k_mc_scan_corr_multi<MAXNU>, dim3(max_blk, n_boxes), dim3(256), lds, s, d_L);
+    const dim3 grid(max_blk, n_boxes);
+    switch (nw) {
+    case 1: hipLaunchKernelGGL((k_mc_scan_corr_multi<MAXNU, 1>), grid, dim3(256), lds, s, d_L); break;
+    case 2: hipLaunchKernelGGL((k_mc_scan_corr_multi<MAXNU, 2>), grid, dim3(256), lds, s, d_L); break;
+    default: hipLaunchKernelGGL((k_mc_scan_corr_multi<MAXNU, 4>), grid, dim3(256), lds, s, d_L); break;
+    }
     ND_HIP(hipGetLastError());
 }
 
-void scan_corr_multi(int maxnu, hipStream_t s, const McLaunch *d_L, int n_boxes, int max_blk, size_t lds)
+void scan_corr_multi(int maxnu, int nw, hipStream_t s, const McLaunch *d_L, int n_boxes, int max_blk, size_t lds)
 {
     switch (maxnu) {
-    case 1: launch_scan_corr_multi<1>(s, d_L, n_boxes, max_blk, lds); break;
-    case 2: launch_scan_corr_multi<2>(s, d_L, n_boxes, max_blk, lds); break;
-    case 3: launch_scan_corr_multi<3>(s, d_L, n_boxes, max_blk, lds); break;
-    case 4: launch_scan_corr_multi<4>(s, d_L, n_boxes, max_blk, lds); break;
-    default: launch_scan_corr_multi<8>(s, d_L, n_boxes, max_blk, lds); break;
+    case 1: launch_scan_corr_multi<1>(s, nw, d_L, n_boxes, max_blk, lds); break;
+    case 2: launch_scan_corr_multi<2>(s, nw, d_L, n_boxes, max_blk, lds); break;
+    case 3: launch_scan_corr_multi<3>(s, nw, d_L, n_boxes, max_blk, lds); break;
+    case 4: launch_scan_corr_multi<4>(s, nw, d_L, n_boxes, max_blk, lds); break;
+    default: launch_scan_corr_multi<8>(s, nw, d_L, n_boxes, max_blk, lds); break;
     }
 }
 
@@ -1753,7 +1816,7 @@ struct McMulti {
     int maxnu = 1, n_rounds = 0, n_first = 0, max_kb0 = 0;
     size_t lds = 0;
     std::vector<McLaunch> launches;  // round after round, the active boxes of each
-    std::vector<int> r_off, r_n, r_maxblk;
+    std::vector<int> r_off, r_n, r_maxblk, r_nw;
     std::vector<CellBuildArgs> cb;   // per round, the boxes whose cells are rebuilt first
     std::vector<int> cb_off, cb_n, cb_maxn, cb_maxcell;
     std::vector<ProposeArgs> first;  // first proposals of every box with trials
@@ -1795,6 +1858,8 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
     m->r_off.assign(n_rounds, 0);
     m->r_n.assign(n_rounds, 0);
     m->r_maxblk.assign(n_rounds, 0);
+    m->r_nw.assign(n_rounds, 4);
+    const int ncu = n > 0 ? cu_count(boxes[0]->device) : 1;
     m->cb.clear();
     m->cb_off.assign(n_rounds, 0);
     m->cb_n.assign(n_rounds, 0);
@@ -1811,9 +1876,19 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
     for (int r = 0; r < n_rounds; ++r) {
         m->r_off[r] = (int)m->launches.size();
         m->cb_off[r] = (int)m->cb.size();
+        // one scan launch takes the round's trials of every box: its waves
+        // per trial follow their total
+        long long round_trials = 0;
+        for (int i = 0; i < n; ++i)
+            if (r < (int)plans[i].batches.size()) round_trials += plans[i].batches[r].ca.kb;
+        const int nw = pick_scan_nw(round_trials, ncu);
+        m->r_nw[r] = nw;
         for (int i = 0; i < n; ++i) {
             if (r >= (int)plans[i].batches.size()) continue;
-            const McLaunch &L = plans[i].batches[r];
+            McLaunch L = plans[i].batches[r];
+            L.ca.nw = nw;
+            L.ca.per_slab = per_slab_blocks(L.ca.kb, nw);
+            L.nblk = scan_front_blocks(L.ca.kb, L.next.kb) + N_SLAB * L.ca.per_slab;
             m->launches.push_back(L);
             // a multiple of N_SLAB, so block x of every box row lands on XCD x mod 8
             m->r_maxblk[r] = std::max(m->r_maxblk[r], (L.nblk + N_SLAB - 1) / N_SLAB * N_SLAB);
@@ -1851,6 +1926,7 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
         sig.push_back(m->r_off[r]);
         sig.push_back(m->r_n[r]);
         sig.push_back(m->r_maxblk[r]);
+        sig.push_back(m->r_nw[r]);
         sig.push_back(m->cb_off[r]);
         sig.push_back(m->cb_n[r]);
         sig.push_back(m->cb_maxn[r]);
@@ -1884,7 +1960,7 @@ void mc_multi_enqueue(McMulti *m, hipStream_t s)
         const McLaunch *Lr = m->d_launch + m->r_off[r];
         if (m->cb_n[r] > 0)
             cells_rebuild_launch(s, m->d_cb + m->cb_off[r], m->cb_n[r], m->cb_maxn[r], m->cb_maxcell[r]);
-        scan_corr_multi(m->maxnu, s, Lr, m->r_n[r], m->r_maxblk[r], m->lds);
+        scan_corr_multi(m->maxnu, m->r_nw[r], s, Lr, m->r_n[r], m->r_maxblk[r], m->lds);
         hipLaunchKernelGGL(k_mc_decide_multi, dim3(1, m->r_n[r]), dim3(DEC_THREADS), 0, s, Lr);
         ND_HIP(hipGetLastError());
     }

@@ -3,9 +3,13 @@ one graph of shared launches give, box by box, the results of the plain
 entry points (which the other GPU tests check against the oracle).
 
 Both sides run the same kernels on the same inputs, so coordinates,
-histograms, g(r), energies and acceptance counts agree bit for bit; S(Q)
-is held to the same bound as the plain path (1e-11 of its magnitude scale),
-and is in practice identical.  Every plain call is preceded by a reset of
+histograms, g(r) and acceptance counts agree bit for bit.  The running
+energy agrees to rounding (1e-12 relative): the cell scan splits a trial's
+pair terms over 1, 2 or 4 waves according to how many trials its launch
+holds (one box alone, or every box of a round), and that changes the order
+of the FP64 partial sums of a trial's energy change.  S(Q) is held to the
+same bound as the plain path (1e-11 of its magnitude scale), and is in
+practice identical.  Every plain call is preceded by a reset of
 the box's cell lists (set_coords with the box's own coordinates), because
 every batched run starts from freshly built cells.
 """
@@ -110,7 +114,7 @@ def _compare(a, b, gboxes, sweeps):
         assert y["trials"] == sweeps * gboxes[i].n_units
         assert np.array_equal(x["xyz"], y["xyz"]), f"box {i}: coordinates differ"
         assert x["accepted"] == y["accepted"], f"box {i}"
-        assert x["E"] == y["E"], f"box {i}: {x['E']} vs {y['E']}"
+        assert abs(x["E"] - y["E"]) <= 1e-12 * max(1.0, abs(x["E"])), f"box {i}: {x['E']} vs {y['E']}"
         assert np.array_equal(x["counts"], y["counts"]), f"box {i}: histogram differs"
         assert np.array_equal(x["g"], y["g"]), f"box {i}: g differs"
         scale = np.abs(x["S"]).max() + 1.0
