@@ -472,7 +472,7 @@ __device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, 
     }
     const nd::Trial *Tk = a.trials + k;
     const int nak = Tk->na;
-    if (lane < 2 * nak) {
+    if (lane < 2 * MAXNU) {  // slots past na are read but not used
         const int at = lane >> 1;
         const float4 h = (lane & 1) ? Tk->new_hi[at] : Tk->old_hi[at];
         const float4 l = (lane & 1) ? Tk->new_lo[at] : Tk->old_lo[at];
@@ -702,7 +702,9 @@ __device__ __forceinline__ void scan_cells_group(const CellScanArgs &a, const Pa
     // r_cut + 2 rad < L/2: every pair term of the trial can take the nearest
     // image of its survivor relative to the centre (see cell_flush)
     const bool cimg = a.rcf + 2.0f * T->rad + 1e-4f < 0.5f;
-    if (wsub == 0 && lane < 2 * tna) {
+    // every slot up to MAXNU is read (in bounds, unused past na), so these
+    // loads do not wait for na
+    if (wsub == 0 && lane < 2 * MAXNU) {
         const int at = lane >> 1;
         const float4 h = ld4((lane & 1) ? &T->new_hi[at] : &T->old_hi[at]);
         const float4 l = ld4((lane & 1) ? &T->new_lo[at] : &T->old_lo[at]);
