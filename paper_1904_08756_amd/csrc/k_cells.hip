@@ -47,43 +47,76 @@ __global__ __launch_bounds__(CB_THREADS) void k_cb_count(const nd::CellBuildArgs
 }
 
 // One block per box: start[c] = sum of count[0..c), start[ncell] = N; the
-// counters are cleared behind the scan and the drift is reset.  Each thread
-// takes a contiguous run of cells: its total, one block-wide exclusive scan
-// of the totals, then the run's starts.
+// counters are cleared behind the scan and the drift is reset.  The cells
+// go in tiles of CB_SCAN_PER per thread: coalesced loads into LDS, each
+// thread's contiguous run summed from LDS (one pad word per run spreads the
+// runs over the banks), one block-wide exclusive scan of the run totals,
+// the starts written back in place, then coalesced stores.
+constexpr int CB_SCAN_PER = 16;
+constexpr int CB_SCAN_TILE = CB_SCAN_THREADS * CB_SCAN_PER;
+
+__device__ __forceinline__ int cb_pad(int p) { return p + p / CB_SCAN_PER; }
+
 __global__ __launch_bounds__(CB_SCAN_THREADS) void k_cb_scan(const nd::CellBuildArgs *__restrict__ args)
 {
     __shared__ int s_w[CB_SCAN_THREADS / 64];
+    __shared__ int s_c[CB_SCAN_TILE + CB_SCAN_TILE / CB_SCAN_PER];
     const nd::CellBuildArgs &A = args[blockIdx.y];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int per = (A.ncell + CB_SCAN_THREADS - 1) / CB_SCAN_THREADS;
-    const int c0 = min(tid * per, A.ncell), c1 = min(c0 + per, A.ncell);
-    int v = 0;
-    for (int c = c0; c < c1; ++c) v += A.count[c];
-    int x = v;
+    const int ncell = A.ncell;
+    int32_t *cnt = A.count;
+    int32_t *start = A.start;
+    int carry = 0;
+    for (int t0 = 0; t0 < ncell; t0 += CB_SCAN_TILE) {
+        int t[CB_SCAN_PER];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) s_w[wave] = x;
-    __syncthreads();
-    if (tid == 0) {
-        int acc = 0;
-        for (int w = 0; w < CB_SCAN_THREADS / 64; ++w) {
-            const int t = s_w[w];
-            s_w[w] = acc;
-            acc += t;
+        for (int u = 0; u < CB_SCAN_PER; ++u) {
+            const int c = t0 + u * CB_SCAN_THREADS + tid;
+            t[u] = c < ncell ? cnt[c] : 0;
         }
-        A.start[A.ncell] = acc;
-        *A.drift = 0.0f;
+#pragma unroll
+        for (int u = 0; u < CB_SCAN_PER; ++u) s_c[cb_pad(u * CB_SCAN_THREADS + tid)] = t[u];
+        __syncthreads();
+        const int r0 = cb_pad(tid * CB_SCAN_PER);  // the run's CB_SCAN_PER words are contiguous
+        int v = 0;
+#pragma unroll
+        for (int u = 0; u < CB_SCAN_PER; ++u) v += s_c[r0 + u];
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) s_w[wave] = x;
+        __syncthreads();
+        int wbase = 0, total = 0;
+        for (int w = 0; w < CB_SCAN_THREADS / 64; ++w) {
+            const int tw = s_w[w];
+            wbase += w < wave ? tw : 0;
+            total += tw;
+        }
+        int run = carry + wbase + x - v;
+#pragma unroll
+        for (int u = 0; u < CB_SCAN_PER; ++u) {
+            const int n = s_c[r0 + u];
+            s_c[r0 + u] = run;
+            run += n;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < CB_SCAN_PER; ++u) {
+            const int c = t0 + u * CB_SCAN_THREADS + tid;
+            if (c < ncell) {
+                start[c] = s_c[cb_pad(u * CB_SCAN_THREADS + tid)];
+                cnt[c] = 0;
+            }
+        }
+        carry += total;
+        __syncthreads();  // s_c and s_w are reused by the next tile
     }
-    __syncthreads();
-    int run = s_w[wave] + x - v;
-    for (int c = c0; c < c1; ++c) {
-        const int n = A.count[c];
-        A.start[c] = run;
-        A.count[c] = 0;
-        run += n;
+    if (tid == 0) {
+        start[ncell] = carry;
+        *A.drift = 0.0f;
     }
 }
 
