@@ -868,9 +868,9 @@ __device__ __forceinline__ void scan_cells_group(const CellScanArgs &a, const Pa
 // each, sharing the staged tables), block b of them on XCD b mod 8 taking
 // the trials whose centre lies in z-slab b mod 8, so each XCD's L2 holds
 // about one slab of the cell data instead of all of it.
-__host__ __device__ inline int scan_front_blocks(int kb, int kb_next)
+__host__ __device__ inline int scan_front_blocks(int kb_corr, int kb_next)
 {
-    const int n = (kb_next + 255) / 256 + (kb + CORR_TPB - 1) / CORR_TPB;
+    const int n = (kb_next + 255) / 256 + (kb_corr + CORR_TPB - 1) / CORR_TPB;
     return (n + N_SLAB - 1) / N_SLAB * N_SLAB;
 }
 
@@ -888,8 +888,8 @@ __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const Corr
     __shared__ double s_red[TPB][2 * NW];
     const int tid = threadIdx.x;
     const int n_prop = (next.kb + 255) / 256;
-    const int n_corr = (a.kb + CORR_TPB - 1) / CORR_TPB;
-    const int n_front = scan_front_blocks(a.kb, next.kb);
+    const int n_corr = (ca.kb + CORR_TPB - 1) / CORR_TPB;
+    const int n_front = scan_front_blocks(ca.kb, next.kb);
     if (bx < n_prop) {
         const int k = bx * 256 + tid;
         if (k < next.kb) propose_one(next, k);
@@ -1280,7 +1280,33 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
     for (int k = tid; k < next.kb; k += DEC_THREADS) propose_one(next, k);
 }
 
-__global__ __launch_bounds__(DEC_THREADS) void k_mc_decide(DecideArgs a, ProposeArgs next) { decide_body(a, next); }
+// Blocks 1.. of a decision launch: the corrections of the next batch, one
+// trial per wave.  They need only the next batch's trial records (its units
+// are disjoint from this batch's, so the commit does not touch them) and
+// run on the CUs the one-block decision leaves idle.
+constexpr int DEC_CORR_TRIALS = DEC_THREADS / 64;
+
+template <int MAXNU>
+__device__ __forceinline__ void next_corr_block(const CorrArgs &cn, int bx)
+{
+    __shared__ int s_prow[16];
+    __shared__ CorrScratch s_cs[DEC_CORR_TRIALS];
+    const int tid = threadIdx.x;
+    if (tid < cn.M * cn.M) s_prow[tid] = nd::pair_index(tid / cn.M, tid % cn.M, cn.M) * cn.n_pts;
+    __syncthreads();
+    const PairCtx c{cn.tab, s_prow, cn.M, cn.n_pts, cn.rcf2_filter, cn.rcf2, cn.tscale};
+    const int k = (bx - 1) * DEC_CORR_TRIALS + (tid >> 6);
+    if (k < cn.kb) corr_trial<MAXNU>(cn, c, k, tid & 63, s_cs[tid >> 6]);
+}
+
+template <int MAXNU>
+__global__ __launch_bounds__(DEC_THREADS) void k_mc_decide(DecideArgs a, ProposeArgs next, CorrArgs cn)
+{
+    if (blockIdx.x == 0)
+        decide_body(a, next);
+    else
+        next_corr_block<MAXNU>(cn, blockIdx.x);
+}
 
 __global__ void k_mc_reset(long long *counters, double *dsum, int32_t *ovf_fill, int32_t *slab0, int32_t *slab1)
 {
@@ -1288,11 +1314,11 @@ __global__ void k_mc_reset(long long *counters, double *dsum, int32_t *ovf_fill,
         slab0[threadIdx.x] = 0;
         slab1[threadIdx.x] = 0;
     }
-    if (threadIdx.x < 2) counters[threadIdx.x] = 0;
-    if (threadIdx.x == 0) {
-        *dsum = 0.0;
-        *ovf_fill = 0;
+    if (threadIdx.x < 2) {
+        counters[threadIdx.x] = 0;
+        ovf_fill[threadIdx.x] = 0;  // one per correction buffer
     }
+    if (threadIdx.x == 0) *dsum = 0.0;
 }
 
 // ---------------------------------------------------------------- several boxes
@@ -1304,8 +1330,11 @@ struct McLaunch {
     ProposeArgs next;  // next batch proposed by the scan launch (kb = 0: not there)
     DecideArgs da;
     ProposeArgs late;  // next batch proposed after the commit (kb = 0: not there)
+    CorrArgs cn;       // corrections of the next batch, run by the decision launch (kb = 0: none)
+    int32_t *ovf0;     // overflow fills of the two correction buffers (cleared by the reset)
     int32_t *slab0, *slab1;  // slab counts of the two trial buffers (cleared by the reset)
     int nblk;          // blocks of the scan launch
+    int dblk;          // blocks of the decision launch
     int rebuild;       // cells rebuilt before this batch
 };
 
@@ -1319,10 +1348,14 @@ __global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void 
     scan_corr_body<MAXNU, NW>(e.ca, e.cr, e.next, blockIdx.x);
 }
 
+template <int MAXNU>
 __global__ __launch_bounds__(DEC_THREADS) void k_mc_decide_multi(const McLaunch *__restrict__ L)
 {
     const McLaunch &e = L[blockIdx.y];
-    decide_body(e.da, e.late);
+    if (blockIdx.x == 0)
+        decide_body(e.da, e.late);
+    else
+        next_corr_block<MAXNU>(e.cn, blockIdx.x);
 }
 
 __global__ __launch_bounds__(64) void k_mc_propose_multi(const ProposeArgs *__restrict__ P)
@@ -1340,11 +1373,11 @@ __global__ void k_mc_reset_multi(const McLaunch *__restrict__ L)
         e.slab0[threadIdx.x] = 0;
         e.slab1[threadIdx.x] = 0;
     }
-    if (threadIdx.x < 2) d.counters[threadIdx.x] = 0;
-    if (threadIdx.x == 0) {
-        *d.dsum = 0.0;
-        *d.ovf_fill = 0;
+    if (threadIdx.x < 2) {
+        d.counters[threadIdx.x] = 0;
+        e.ovf0[threadIdx.x] = 0;  // one per correction buffer
     }
+    if (threadIdx.x == 0) *d.dsum = 0.0;
 }
 
 int pick_maxnu(int max_na)
@@ -1360,7 +1393,7 @@ template <int MAXNU>
 void launch_scan_corr(nd_box *b, const CellScanArgs &ca, const CorrArgs &cr, const ProposeArgs &next, size_t slds)
 {
     nd::ProfScope ps(b, ND_PROF_MC_SCAN);
-    const int nblk = scan_front_blocks(ca.kb, next.kb) + N_SLAB * ca.per_slab;
+    const int nblk = scan_front_blocks(cr.kb, next.kb) + N_SLAB * ca.per_slab;
     switch (ca.nw) {
     case 1: hipLaunchKernelGGL((k_mc_scan_corr<MAXNU, 1>), dim3(nblk), dim3(256), slds, b->stream, ca, cr, next); break;
     case 2: hipLaunchKernelGGL((k_mc_scan_corr<MAXNU, 2>), dim3(nblk), dim3(256), slds, b->stream, ca, cr, next); break;
@@ -1408,16 +1441,17 @@ void ensure_work(nd_box *b, int K, int n_jb)
     w.partial = static_cast<double *>(nd::dmalloc(sizeof(double) * 2 * (size_t)n_jb * K));
     w.dE0 = static_cast<double *>(nd::dmalloc(sizeof(double) * K));
     w.S0 = static_cast<double *>(nd::dmalloc(sizeof(double) * K));
-    w.corr_n = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * K));
-    w.corr_ptr = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * K));
-    w.pool_m = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * pool));
-    w.pool_c = static_cast<double *>(nd::dmalloc(sizeof(double) * pool));
-    w.corr_s = static_cast<float *>(nd::dmalloc(sizeof(float) * K));
-    w.corr_b = static_cast<double2 *>(nd::dmalloc(sizeof(double2) * 2 * K));
+    // two correction buffers: the batch being decided and the next one
+    w.corr_n = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * 2 * K));
+    w.corr_ptr = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * 2 * K));
+    w.pool_m = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * 2 * pool));
+    w.pool_c = static_cast<double *>(nd::dmalloc(sizeof(double) * 2 * pool));
+    w.corr_s = static_cast<float *>(nd::dmalloc(sizeof(float) * 2 * K));
+    w.corr_b = static_cast<double2 *>(nd::dmalloc(sizeof(double2) * 4 * K));
     w.slab = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * 2 * (size_t)(N_SLAB + N_SLAB * K)));
     if (!w.counters) w.counters = static_cast<long long *>(nd::dmalloc(sizeof(long long) * 4));
     if (!w.dsum) w.dsum = static_cast<double *>(nd::dmalloc(sizeof(double)));
-    if (!w.ovf_fill) w.ovf_fill = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t)));
+    if (!w.ovf_fill) w.ovf_fill = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * 2));
     w.cap_k = K;
     w.cap_jb = n_jb;
     w.cap_pool = pool;
@@ -1525,7 +1559,8 @@ ProposeArgs proposal_args(const nd_box *b, const nd_mc_params *p, uint64_t seed,
     return pa;
 }
 
-CorrArgs corr_args(const nd_box *b, const McConsts &k, const nd::Trial *trials, const float4 *spheres, int kb, int K)
+CorrArgs corr_args(const nd_box *b, const McConsts &k, const nd::Trial *trials, const float4 *spheres, int kb, int K,
+                   int buf)
 {
     const McWork &w = b->mc;
     CorrArgs cr;
@@ -1539,13 +1574,13 @@ CorrArgs corr_args(const nd_box *b, const McConsts &k, const nd::Trial *trials, 
     cr.rcf2_filter = k.rcf2_filter;
     cr.rcf2 = k.rcf2;
     cr.tscale = k.tscale;
-    cr.corr_n = w.corr_n;
-    cr.corr_ptr = w.corr_ptr;
-    cr.corr_s = w.corr_s;
-    cr.corr_b = w.corr_b;
-    cr.pool_m = w.pool_m;
-    cr.pool_c = w.pool_c;
-    cr.ovf_fill = w.ovf_fill;
+    cr.corr_n = w.corr_n + (size_t)buf * w.cap_k;
+    cr.corr_ptr = w.corr_ptr + (size_t)buf * w.cap_k;
+    cr.corr_s = w.corr_s + (size_t)buf * w.cap_k;
+    cr.corr_b = w.corr_b + (size_t)buf * 2 * w.cap_k;
+    cr.pool_m = w.pool_m + (size_t)buf * w.cap_pool;
+    cr.pool_c = w.pool_c + (size_t)buf * w.cap_pool;
+    cr.ovf_fill = w.ovf_fill + buf;
     cr.ovf_base = K * CORR_CAP;
     return cr;
 }
@@ -1562,13 +1597,13 @@ DecideArgs decide_args(const nd_box *b, const nd_mc_params *p, const McConsts &k
     da.trials = trials;
     da.dE0 = w.dE0;
     da.S0 = w.S0;
-    da.corr_n = w.corr_n;
-    da.corr_ptr = w.corr_ptr;
-    da.pool_m = w.pool_m;
-    da.pool_c = w.pool_c;
-    da.corr_s = w.corr_s;
-    da.corr_b = w.corr_b;
-    da.ovf_fill = w.ovf_fill;
+    da.corr_n = w.corr_n + (size_t)buf * w.cap_k;
+    da.corr_ptr = w.corr_ptr + (size_t)buf * w.cap_k;
+    da.pool_m = w.pool_m + (size_t)buf * w.cap_pool;
+    da.pool_c = w.pool_c + (size_t)buf * w.cap_pool;
+    da.corr_s = w.corr_s + (size_t)buf * w.cap_k;
+    da.corr_b = w.corr_b + (size_t)buf * 2 * w.cap_k;
+    da.ovf_fill = w.ovf_fill + buf;
     da.cell_slot = cells_live ? b->cells.slot : nullptr;
     da.spos4 = cells_live ? b->cells.spos4 : nullptr;
     da.sposlo = cells_live ? b->cells.sposlo : nullptr;
@@ -1627,7 +1662,10 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
             b->cells.valid = true;
             b->cells.trials_since_build = 0;
         }
-        L.cr = corr_args(b, k, trials, spheres, kb, K);
+        // with early proposals a batch's corrections (but the first's) run in
+        // the previous batch's decision launch
+        L.cr = corr_args(b, k, trials, spheres, kb, K, buf);
+        if (early_propose && done > 0) L.cr.kb = 0;
         CellScanArgs &ca = L.ca;
         ca.spos4 = b->cells.spos4;
         ca.sposlo = b->cells.sposlo;
@@ -1659,7 +1697,12 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         else
             L.next.kb = 0;
         L.da = decide_args(b, p, k, trials, kb, done, trace, true, buf);
-        L.nblk = scan_front_blocks(kb, L.next.kb) + N_SLAB * ca.per_slab;
+        L.cn = corr_args(b, k, w.trials + (size_t)(buf ^ 1) * K, w.spheres + (size_t)(buf ^ 1) * K, kb_next, K,
+                         buf ^ 1);
+        if (!early_propose) L.cn.kb = 0;
+        L.dblk = 1 + (L.cn.kb + DEC_CORR_TRIALS - 1) / DEC_CORR_TRIALS;
+        L.ovf0 = w.ovf_fill;
+        L.nblk = scan_front_blocks(L.cr.kb, L.next.kb) + N_SLAB * ca.per_slab;
         L.slab0 = slab_buffer(b, 0);
         L.slab1 = slab_buffer(b, 1);
         b->cells.trials_since_build += kb;
@@ -1692,6 +1735,33 @@ void scan_corr_multi(int maxnu, int nw, hipStream_t s, const McLaunch *d_L, int 
     }
 }
 
+void launch_decide(nd_box *b, int maxnu, int nblk, const DecideArgs &da, const ProposeArgs &late, const CorrArgs &cn)
+{
+    nd::ProfScope ps(b, ND_PROF_MC_DECIDE);
+    const dim3 g(nblk), t(DEC_THREADS);
+    switch (maxnu) {
+    case 1: hipLaunchKernelGGL(k_mc_decide<1>, g, t, 0, b->stream, da, late, cn); break;
+    case 2: hipLaunchKernelGGL(k_mc_decide<2>, g, t, 0, b->stream, da, late, cn); break;
+    case 3: hipLaunchKernelGGL(k_mc_decide<3>, g, t, 0, b->stream, da, late, cn); break;
+    case 4: hipLaunchKernelGGL(k_mc_decide<4>, g, t, 0, b->stream, da, late, cn); break;
+    default: hipLaunchKernelGGL(k_mc_decide<8>, g, t, 0, b->stream, da, late, cn); break;
+    }
+    ND_HIP(hipGetLastError());
+}
+
+void decide_multi(int maxnu, hipStream_t s, const McLaunch *d_L, int n_boxes, int nblk)
+{
+    const dim3 g(nblk, n_boxes), t(DEC_THREADS);
+    switch (maxnu) {
+    case 1: hipLaunchKernelGGL(k_mc_decide_multi<1>, g, t, 0, s, d_L); break;
+    case 2: hipLaunchKernelGGL(k_mc_decide_multi<2>, g, t, 0, s, d_L); break;
+    case 3: hipLaunchKernelGGL(k_mc_decide_multi<3>, g, t, 0, s, d_L); break;
+    case 4: hipLaunchKernelGGL(k_mc_decide_multi<4>, g, t, 0, s, d_L); break;
+    default: hipLaunchKernelGGL(k_mc_decide_multi<8>, g, t, 0, s, d_L); break;
+    }
+    ND_HIP(hipGetLastError());
+}
+
 // The O(N) scan of every atom per trial (ND_SCAN_FULL).
 void mc_run_full(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n, const nd_mc_trace *trace)
 {
@@ -1719,7 +1789,7 @@ void mc_run_full(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first
         const int kb = (int)std::min<int64_t>(K, n - done);
         nd::Trial *trials = w.trials + (size_t)buf * K;
         float4 *spheres = w.spheres + (size_t)buf * K;
-        const CorrArgs cr = corr_args(b, k, trials, spheres, kb, K);
+        const CorrArgs cr = corr_args(b, k, trials, spheres, kb, K, buf);
         const int64_t done_next = done + kb;
         const int kb_next = (int)std::max<int64_t>(0, std::min<int64_t>(K, n - done_next));
         const ProposeArgs late = proposal_args(b, p, seed, first + (uint64_t)done_next, kb_next, buf ^ 1, K);
@@ -1763,11 +1833,9 @@ void mc_run_full(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first
         }
         // cells kept consistent when they are live from an earlier cell-scan call
         const DecideArgs da = decide_args(b, p, k, trials, kb, done, trace, b->cells.valid, buf);
-        {
-            nd::ProfScope ps(b, ND_PROF_MC_DECIDE);
-            hipLaunchKernelGGL(k_mc_decide, dim3(1), dim3(DEC_THREADS), 0, b->stream, da, late);
-            ND_HIP(hipGetLastError());
-        }
+        CorrArgs none{};
+        none.kb = 0;
+        launch_decide(b, maxnu, 1, da, late, none);
         if (b->cells.valid) b->cells.trials_since_build += kb;
         done = done_next;
         buf ^= 1;
@@ -1805,11 +1873,7 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
         case 4: launch_scan_corr<4>(b, L.ca, L.cr, L.next, pl.lds); break;
         default: launch_scan_corr<8>(b, L.ca, L.cr, L.next, pl.lds); break;
         }
-        {
-            ProfScope ps(b, ND_PROF_MC_DECIDE);
-            hipLaunchKernelGGL(k_mc_decide, dim3(1), dim3(DEC_THREADS), 0, b->stream, L.da, L.late);
-            ND_HIP(hipGetLastError());
-        }
+        launch_decide(b, pl.maxnu, L.dblk, L.da, L.late, L.cn);
     }
 }
 
@@ -1818,7 +1882,7 @@ struct McMulti {
     int maxnu = 1, n_rounds = 0, n_first = 0, max_kb0 = 0;
     size_t lds = 0;
     std::vector<McLaunch> launches;  // round after round, the active boxes of each
-    std::vector<int> r_off, r_n, r_maxblk, r_nw;
+    std::vector<int> r_off, r_n, r_maxblk, r_nw, r_dblk;
     std::vector<CellBuildArgs> cb;   // per round, the boxes whose cells are rebuilt first
     std::vector<int> cb_off, cb_n, cb_maxn, cb_maxcell;
     std::vector<ProposeArgs> first;  // first proposals of every box with trials
@@ -1861,6 +1925,7 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
     m->r_n.assign(n_rounds, 0);
     m->r_maxblk.assign(n_rounds, 0);
     m->r_nw.assign(n_rounds, 4);
+    m->r_dblk.assign(n_rounds, 1);
     const int ncu = n > 0 ? cu_count(boxes[0]->device) : 1;
     m->cb.clear();
     m->cb_off.assign(n_rounds, 0);
@@ -1890,10 +1955,11 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
             McLaunch L = plans[i].batches[r];
             L.ca.nw = nw;
             L.ca.per_slab = per_slab_blocks(L.ca.kb, nw);
-            L.nblk = scan_front_blocks(L.ca.kb, L.next.kb) + N_SLAB * L.ca.per_slab;
+            L.nblk = scan_front_blocks(L.cr.kb, L.next.kb) + N_SLAB * L.ca.per_slab;
             m->launches.push_back(L);
             // a multiple of N_SLAB, so block x of every box row lands on XCD x mod 8
             m->r_maxblk[r] = std::max(m->r_maxblk[r], (L.nblk + N_SLAB - 1) / N_SLAB * N_SLAB);
+            m->r_dblk[r] = std::max(m->r_dblk[r], L.dblk);
             if (L.rebuild) {
                 m->cb.push_back(boxes[i]->cells.args);
                 m->cb_maxn[r] = std::max(m->cb_maxn[r], boxes[i]->N);
@@ -1929,6 +1995,7 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
         sig.push_back(m->r_n[r]);
         sig.push_back(m->r_maxblk[r]);
         sig.push_back(m->r_nw[r]);
+        sig.push_back(m->r_dblk[r]);
         sig.push_back(m->cb_off[r]);
         sig.push_back(m->cb_n[r]);
         sig.push_back(m->cb_maxn[r]);
@@ -1963,8 +2030,7 @@ void mc_multi_enqueue(McMulti *m, hipStream_t s)
         if (m->cb_n[r] > 0)
             cells_rebuild_launch(s, m->d_cb + m->cb_off[r], m->cb_n[r], m->cb_maxn[r], m->cb_maxcell[r]);
         scan_corr_multi(m->maxnu, m->r_nw[r], s, Lr, m->r_n[r], m->r_maxblk[r], m->lds);
-        hipLaunchKernelGGL(k_mc_decide_multi, dim3(1, m->r_n[r]), dim3(DEC_THREADS), 0, s, Lr);
-        ND_HIP(hipGetLastError());
+        decide_multi(m->maxnu, s, Lr, m->r_n[r], m->r_dblk[r]);
     }
 }
 
