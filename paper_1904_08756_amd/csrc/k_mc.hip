@@ -1348,14 +1348,16 @@ __global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void 
     scan_corr_body<MAXNU, NW>(e.ca, e.cr, e.next, blockIdx.x);
 }
 
+// blockIdx.x selects the box and blockIdx.y the role (0: its decision), so
+// the decisions of every box are dispatched before any correction block.
 template <int MAXNU>
 __global__ __launch_bounds__(DEC_THREADS) void k_mc_decide_multi(const McLaunch *__restrict__ L)
 {
-    const McLaunch &e = L[blockIdx.y];
-    if (blockIdx.x == 0)
+    const McLaunch &e = L[blockIdx.x];
+    if (blockIdx.y == 0)
         decide_body(e.da, e.late);
-    else
-        next_corr_block<MAXNU>(e.cn, blockIdx.x);
+    else if ((int)blockIdx.y < e.dblk)
+        next_corr_block<MAXNU>(e.cn, blockIdx.y);
 }
 
 __global__ __launch_bounds__(64) void k_mc_propose_multi(const ProposeArgs *__restrict__ P)
@@ -1751,7 +1753,7 @@ void launch_decide(nd_box *b, int maxnu, int nblk, const DecideArgs &da, const P
 
 void decide_multi(int maxnu, hipStream_t s, const McLaunch *d_L, int n_boxes, int nblk)
 {
-    const dim3 g(nblk, n_boxes), t(DEC_THREADS);
+    const dim3 g(n_boxes, nblk), t(DEC_THREADS);
     switch (maxnu) {
     case 1: hipLaunchKernelGGL(k_mc_decide_multi<1>, g, t, 0, s, d_L); break;
     case 2: hipLaunchKernelGGL(k_mc_decide_multi<2>, g, t, 0, s, d_L); break;
@@ -1953,6 +1955,12 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
         for (int i = 0; i < n; ++i) {
             if (r >= (int)plans[i].batches.size()) continue;
             McLaunch L = plans[i].batches[r];
+            // corrections stay in the scan launch: there they run as small
+            // blocks, four per CU, while a decision-launch block takes a whole
+            // CU, and a round's boxes bring thousands of them
+            L.cr.kb = L.ca.kb;
+            L.cn.kb = 0;
+            L.dblk = 1;
             L.ca.nw = nw;
             L.ca.per_slab = per_slab_blocks(L.ca.kb, nw);
             L.nblk = scan_front_blocks(L.cr.kb, L.next.kb) + N_SLAB * L.ca.per_slab;
