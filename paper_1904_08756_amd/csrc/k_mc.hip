@@ -393,6 +393,25 @@ struct CorrArgs {
     int ovf_base;
 };
 
+// A decided batch's final dE sums, counters and trace (k_mc_final's body,
+// run as the first block of the next scan launch): its entries, ΔE⁰ and
+// |U| sums by buffer, and what the decision stored.
+struct FinalArgs {
+    const double *dE0, *S0, *thr;
+    const float *corr_s;
+    const int32_t *corr_n, *corr_ptr, *pool_m;
+    const double *pool_c;
+    const uint8_t *acc;
+    int kb;  // 0: nothing to do
+    double kT, tie_rel;
+    double *E, *dsum;
+    long long *counters;
+    double *tr_dE, *tr_sabs;
+    uint8_t *tr_acc;
+};
+constexpr int FIN_THREADS = 256;
+__device__ void final_body(const FinalArgs &f, unsigned char *lds);
+
 __device__ __forceinline__ bool spheres_meet(float4 A, float4 B, float rcf)
 {
     float dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
@@ -861,16 +880,17 @@ __device__ __forceinline__ void scan_cells_group(const CellScanArgs &a, const Pa
     }
 }
 
-// Blocks of one launch, in dispatch order: the proposals of the next
-// batch (its units are disjoint from this batch's) and the in-batch
-// corrections, which are few and long, so they start first; padding to a
+// Blocks of one launch, in dispatch order: the previous batch's final sums
+// (when the decision left them), the proposals of the next batch (its units
+// are disjoint from this batch's) and the in-batch corrections, which are
+// few and long, so they start first; padding to a
 // multiple of 8; then the cell scans, 4/NW trials per block (NW waves
 // each, sharing the staged tables), block b of them on XCD b mod 8 taking
 // the trials whose centre lies in z-slab b mod 8, so each XCD's L2 holds
 // about one slab of the cell data instead of all of it.
-__host__ __device__ inline int scan_front_blocks(int kb_corr, int kb_next)
+__host__ __device__ inline int scan_front_blocks(int kb_corr, int kb_next, int n_fin)
 {
-    const int n = (kb_next + 255) / 256 + (kb_corr + CORR_TPB - 1) / CORR_TPB;
+    const int n = n_fin + (kb_next + 255) / 256 + (kb_corr + CORR_TPB - 1) / CORR_TPB;
     return (n + N_SLAB - 1) / N_SLAB * N_SLAB;
 }
 
@@ -878,7 +898,7 @@ static_assert(sizeof(CorrScratch) <= 2 * sizeof(float4) * CS_LIST, "correction s
 
 template <int MAXNU, int NW>
 __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const CorrArgs &ca, const ProposeArgs &next,
-                                               int bx)
+                                               const FinalArgs &fin, int bx)
 {
     constexpr int TPB = 4 / NW;  // trials per block
     extern __shared__ __align__(16) float s_tab[];  // [P][n_pts]
@@ -887,20 +907,25 @@ __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const Corr
     __shared__ TrialAtoms s_ta[TPB];
     __shared__ double s_red[TPB][2 * NW];
     const int tid = threadIdx.x;
+    const int n_fin = fin.kb > 0 ? 1 : 0;
     const int n_prop = (next.kb + 255) / 256;
     const int n_corr = (ca.kb + CORR_TPB - 1) / CORR_TPB;
-    const int n_front = scan_front_blocks(ca.kb, next.kb);
-    if (bx < n_prop) {
-        const int k = bx * 256 + tid;
+    const int n_front = scan_front_blocks(ca.kb, next.kb, n_fin);
+    if (bx < n_fin) {
+        final_body(fin, reinterpret_cast<unsigned char *>(&s_list[0][0][0]));
+        return;
+    }
+    if (bx < n_fin + n_prop) {
+        const int k = (bx - n_fin) * 256 + tid;
         if (k < next.kb) propose_one(next, k);
         return;
     }
-    if (bx < n_prop + n_corr) {
+    if (bx < n_fin + n_prop + n_corr) {
         if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
         __syncthreads();
         const PairCtx c{ca.tab, s_prow, ca.M, ca.n_pts, ca.rcf2_filter, ca.rcf2, ca.tscale};
         CorrScratch &cs = *reinterpret_cast<CorrScratch *>(&s_list[tid >> 6][0][0]);
-        const int k = (bx - n_prop) * CORR_TPB + (tid >> 6);
+        const int k = (bx - n_fin - n_prop) * CORR_TPB + (tid >> 6);
         if (k < ca.kb) corr_trial<MAXNU>(ca, c, k, tid & 63, cs);
         return;
     }
@@ -929,9 +954,10 @@ __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const Corr
 }
 
 template <int MAXNU, int NW>
-__global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void k_mc_scan_corr(CellScanArgs a, CorrArgs ca, ProposeArgs next)
+__global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void k_mc_scan_corr(CellScanArgs a, CorrArgs ca, ProposeArgs next,
+                                                                                         FinalArgs fin)
 {
-    scan_corr_body<MAXNU, NW>(a, ca, next, blockIdx.x);
+    scan_corr_body<MAXNU, NW>(a, ca, next, fin, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- decide
@@ -963,6 +989,11 @@ struct DecideArgs {
     double *tr_dE, *tr_sabs;
     uint8_t *tr_acc;
     int32_t *tr_unit;
+    // defer: the final dE sums, counters and trace are left to a later launch
+    // (k_mc_final's body); the decision stores what they need
+    int defer;
+    uint8_t *acc_out;  // [kb] 1: accepted
+    double *thr_out;   // [kb] acceptance threshold -kT ln u
 };
 
 // exclusive prefix sum over the block of one value per thread
@@ -1006,13 +1037,13 @@ constexpr unsigned char ST_OPEN = 0, ST_REJ = 1, ST_ACC = 2;
 // when n <= CORR_CAP (read with wide loads, all at once), else n entries at
 // ptr in the overflow area.  f(m, c) is called for every entry in order.
 template <class F>
-__device__ __forceinline__ void for_entries(const DecideArgs &a, int k, int n, int ptr, F &&f)
+__device__ __forceinline__ void for_entries(const int32_t *pool_m, const double *pool_c, int k, int n, int ptr, F &&f)
 {
     if (n <= CORR_CAP) {
         int m[CORR_CAP];
         double c[CORR_CAP];
-        const int4 *pm = reinterpret_cast<const int4 *>(a.pool_m + (size_t)k * CORR_CAP);
-        const double2 *pc = reinterpret_cast<const double2 *>(a.pool_c + (size_t)k * CORR_CAP);
+        const int4 *pm = reinterpret_cast<const int4 *>(pool_m + (size_t)k * CORR_CAP);
+        const double2 *pc = reinterpret_cast<const double2 *>(pool_c + (size_t)k * CORR_CAP);
 #pragma unroll
         for (int i = 0; i < CORR_CAP / 4; ++i) {
             if (4 * i < n) {
@@ -1035,7 +1066,7 @@ __device__ __forceinline__ void for_entries(const DecideArgs &a, int k, int n, i
         for (int i = 0; i < CORR_CAP; ++i)
             if (i < n) f(m[i], c[i]);
     } else {
-        for (int i = 0; i < n; ++i) f(ldg(a.pool_m + ptr + i), ldg(a.pool_c + ptr + i));
+        for (int i = 0; i < n; ++i) f(ldg(pool_m + ptr + i), ldg(pool_c + ptr + i));
     }
 }
 
@@ -1114,6 +1145,10 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                 }
                 s_e[k] = e0[h];
                 s_u[k] = thr;
+                if (a.defer) {
+                    a.thr_out[k] = thr;
+                    if (a.tr_unit) a.tr_unit[k] = ids[h].x;
+                }
                 s_S[k] = S[h];
                 s_n[k] = any ? n[h] : 0;
                 s_ptr[k] = ptr[h];
@@ -1142,7 +1177,7 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                 const int k = s_open[i];
                 double e = s_e[k], lo = 0.0, hi = 0.0, mag = fabs(e);
                 bool all = true;
-                for_entries(a, k, s_n[k], s_ptr[k], [&](int m, double c) {
+                for_entries(a.pool_m, a.pool_c, k, s_n[k], s_ptr[k], [&](int m, double c) {
                     const unsigned char st = m >= 0 ? s_st[m] : ST_REJ;
                     const bool open = m >= 0 && st == ST_OPEN;
                     e += (m >= 0 && st == ST_ACC) ? c : 0.0;
@@ -1175,9 +1210,11 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
         // final dE (the same in-order sum as an exact decision), counters, trace
         double dsum = 0.0;
         long long nacc = 0, ntie = 0;
-        for (int k = tid; k < kb; k += DEC_THREADS) {
+        if (a.defer)
+            for (int k = tid; k < kb; k += DEC_THREADS) a.acc_out[k] = s_st[k] == ST_ACC ? 1 : 0;
+        for (int k = tid; k < kb && !a.defer; k += DEC_THREADS) {
             double e = s_e[k];
-            for_entries(a, k, s_n[k], s_ptr[k], [&](int m, double c) {
+            for_entries(a.pool_m, a.pool_c, k, s_n[k], s_ptr[k], [&](int m, double c) {
                 e += (m >= 0 && s_st[m] == ST_ACC) ? c : 0.0;
             });
             const bool acc = s_st[k] == ST_ACC;
@@ -1269,10 +1306,12 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                 nt += s_red_t[w];
                 dm = fmaxf(dm, s_red_f[w]);
             }
-            *a.E += d;
-            *a.dsum += d;
-            a.counters[0] += na;
-            a.counters[1] += nt;
+            if (!a.defer) {
+                *a.E += d;
+                *a.dsum += d;
+                a.counters[0] += na;
+                a.counters[1] += nt;
+            }
             if (a.drift && dm > 0.0f) atomicMax(reinterpret_cast<unsigned int *>(a.drift), __float_as_uint(dm));
         }
         __syncthreads();  // commits are visible to the proposals below
@@ -1297,6 +1336,72 @@ __device__ __forceinline__ void next_corr_block(const CorrArgs &cn, int bx)
     const PairCtx c{cn.tab, s_prow, cn.M, cn.n_pts, cn.rcf2_filter, cn.rcf2, cn.tscale};
     const int k = (bx - 1) * DEC_CORR_TRIALS + (tid >> 6);
     if (k < cn.kb) corr_trial<MAXNU>(cn, c, k, tid & 63, s_cs[tid >> 6]);
+}
+
+// The final dE of every trial of a decided batch (the same in-order sum as
+// the decision's own final pass: ΔE⁰ plus the entries of accepted earlier
+// trials), the near-tie count, the trace, and the running energy and
+// counters, updated by one thread after a fixed-order block reduction.
+__device__ void final_body(const FinalArgs &f, unsigned char *lds)
+{
+    unsigned char *s_acc = lds;                                        // [KMAX]
+    double *s_rd = reinterpret_cast<double *>(lds + KMAX);             // [FIN_THREADS / 64]
+    long long *s_ra = reinterpret_cast<long long *>(s_rd + FIN_THREADS / 64);
+    long long *s_rt = s_ra + FIN_THREADS / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int k = tid; k < f.kb; k += FIN_THREADS) s_acc[k] = ldg(f.acc + k);
+    __syncthreads();
+    double dsum = 0.0;
+    long long nacc = 0, ntie = 0;
+    for (int k = tid; k < f.kb; k += FIN_THREADS) {
+        double e = ldg(f.dE0 + k);
+        for_entries(f.pool_m, f.pool_c, k, ldg(f.corr_n + k), ldg(f.corr_ptr + k),
+                    [&](int m, double c) { e += (m >= 0 && s_acc[m]) ? c : 0.0; });
+        const bool acc = s_acc[k] != 0;
+        const double S = ldg(f.S0 + k) + (double)ldg(f.corr_s + k);
+        const double thr = ldg(f.thr + k);
+        // |ln u + dE/kT| < tie_rel S / kT, i.e. |dE - (-kT ln u)| < tie_rel S (u > 0)
+        if (thr != 745.13321910194122 * f.kT && fabs(e - thr) < f.tie_rel * S) ++ntie;
+        if (acc) {
+            ++nacc;
+            dsum += e;
+        }
+        if (f.tr_dE) f.tr_dE[k] = e;
+        if (f.tr_sabs) f.tr_sabs[k] = S;
+        if (f.tr_acc) f.tr_acc[k] = acc ? 1 : 0;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        dsum += __shfl_xor(dsum, o);
+        nacc += __shfl_xor(nacc, o);
+        ntie += __shfl_xor(ntie, o);
+    }
+    if (lane == 0) {
+        s_rd[wave] = dsum;
+        s_ra[wave] = nacc;
+        s_rt[wave] = ntie;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double d = 0.0;
+        long long na = 0, nt = 0;
+        for (int w = 0; w < FIN_THREADS / 64; ++w) {
+            d += s_rd[w];
+            na += s_ra[w];
+            nt += s_rt[w];
+        }
+        *f.E += d;
+        *f.dsum += d;
+        f.counters[0] += na;
+        f.counters[1] += nt;
+    }
+}
+
+// The last batch's final sums (no scan launch follows it).
+__global__ __launch_bounds__(FIN_THREADS) void k_mc_final(FinalArgs f)
+{
+    __shared__ __align__(16) unsigned char s_lds[KMAX + 3 * sizeof(double) * (FIN_THREADS / 64)];
+    final_body(f, s_lds);
 }
 
 template <int MAXNU>
@@ -1331,6 +1436,7 @@ struct McLaunch {
     DecideArgs da;
     ProposeArgs late;  // next batch proposed after the commit (kb = 0: not there)
     CorrArgs cn;       // corrections of the next batch, run by the decision launch (kb = 0: none)
+    FinalArgs fin;     // the previous batch's final sums, run by the scan launch (kb = 0: none)
     int32_t *ovf0;     // overflow fills of the two correction buffers (cleared by the reset)
     int32_t *slab0, *slab1;  // slab counts of the two trial buffers (cleared by the reset)
     int nblk;          // blocks of the scan launch
@@ -1345,7 +1451,7 @@ __global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void 
 {
     const McLaunch &e = L[blockIdx.y];
     if ((int)blockIdx.x >= e.nblk) return;
-    scan_corr_body<MAXNU, NW>(e.ca, e.cr, e.next, blockIdx.x);
+    scan_corr_body<MAXNU, NW>(e.ca, e.cr, e.next, e.fin, blockIdx.x);
 }
 
 // blockIdx.x selects the box and blockIdx.y the role (0: its decision), so
@@ -1392,14 +1498,16 @@ int pick_maxnu(int max_na)
 }
 
 template <int MAXNU>
-void launch_scan_corr(nd_box *b, const CellScanArgs &ca, const CorrArgs &cr, const ProposeArgs &next, size_t slds)
+void launch_scan_corr(nd_box *b, const CellScanArgs &ca, const CorrArgs &cr, const ProposeArgs &next,
+                      const FinalArgs &fin, size_t slds)
 {
     nd::ProfScope ps(b, ND_PROF_MC_SCAN);
-    const int nblk = scan_front_blocks(cr.kb, next.kb) + N_SLAB * ca.per_slab;
+    const int nblk = scan_front_blocks(cr.kb, next.kb, fin.kb > 0 ? 1 : 0) + N_SLAB * ca.per_slab;
+    const dim3 g(nblk), t(256);
     switch (ca.nw) {
-    case 1: hipLaunchKernelGGL((k_mc_scan_corr<MAXNU, 1>), dim3(nblk), dim3(256), slds, b->stream, ca, cr, next); break;
-    case 2: hipLaunchKernelGGL((k_mc_scan_corr<MAXNU, 2>), dim3(nblk), dim3(256), slds, b->stream, ca, cr, next); break;
-    default: hipLaunchKernelGGL((k_mc_scan_corr<MAXNU, 4>), dim3(nblk), dim3(256), slds, b->stream, ca, cr, next); break;
+    case 1: hipLaunchKernelGGL((k_mc_scan_corr<MAXNU, 1>), g, t, slds, b->stream, ca, cr, next, fin); break;
+    case 2: hipLaunchKernelGGL((k_mc_scan_corr<MAXNU, 2>), g, t, slds, b->stream, ca, cr, next, fin); break;
+    default: hipLaunchKernelGGL((k_mc_scan_corr<MAXNU, 4>), g, t, slds, b->stream, ca, cr, next, fin); break;
     }
     ND_HIP(hipGetLastError());
 }
@@ -1423,6 +1531,8 @@ void ensure_work(nd_box *b, int K, int n_jb)
     nd::dfree(w.partial);
     nd::dfree(w.dE0);
     nd::dfree(w.S0);
+    nd::dfree(w.thr);
+    nd::dfree(w.acc_flags);
     nd::dfree(w.corr_n);
     nd::dfree(w.corr_ptr);
     nd::dfree(w.pool_m);
@@ -1441,8 +1551,11 @@ void ensure_work(nd_box *b, int K, int n_jb)
     w.trials = static_cast<nd::Trial *>(nd::dmalloc(sizeof(nd::Trial) * 2 * K));
     w.spheres = static_cast<float4 *>(nd::dmalloc(sizeof(float4) * 2 * K));
     w.partial = static_cast<double *>(nd::dmalloc(sizeof(double) * 2 * (size_t)n_jb * K));
-    w.dE0 = static_cast<double *>(nd::dmalloc(sizeof(double) * K));
-    w.S0 = static_cast<double *>(nd::dmalloc(sizeof(double) * K));
+    // by buffer: the final sums of a batch read them beside the next batch's scan
+    w.dE0 = static_cast<double *>(nd::dmalloc(sizeof(double) * 2 * K));
+    w.S0 = static_cast<double *>(nd::dmalloc(sizeof(double) * 2 * K));
+    w.thr = static_cast<double *>(nd::dmalloc(sizeof(double) * 2 * K));
+    w.acc_flags = static_cast<uint8_t *>(nd::dmalloc(sizeof(uint8_t) * 2 * K));
     // two correction buffers: the batch being decided and the next one
     w.corr_n = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * 2 * K));
     w.corr_ptr = static_cast<int32_t *>(nd::dmalloc(sizeof(int32_t) * 2 * K));
@@ -1597,8 +1710,8 @@ DecideArgs decide_args(const nd_box *b, const nd_mc_params *p, const McConsts &k
     da.poslo = b->poslo;
     da.E = b->E;
     da.trials = trials;
-    da.dE0 = w.dE0;
-    da.S0 = w.S0;
+    da.dE0 = w.dE0 + (size_t)buf * w.cap_k;
+    da.S0 = w.S0 + (size_t)buf * w.cap_k;
     da.corr_n = w.corr_n + (size_t)buf * w.cap_k;
     da.corr_ptr = w.corr_ptr + (size_t)buf * w.cap_k;
     da.pool_m = w.pool_m + (size_t)buf * w.cap_pool;
@@ -1623,7 +1736,37 @@ DecideArgs decide_args(const nd_box *b, const nd_mc_params *p, const McConsts &k
     da.tr_sabs = trace && trace->sabs ? trace->sabs + done : nullptr;
     da.tr_acc = trace && trace->accepted ? trace->accepted + done : nullptr;
     da.tr_unit = trace && trace->unit ? trace->unit + done : nullptr;
+    da.defer = 0;
+    da.acc_out = nullptr;
+    da.thr_out = nullptr;
     return da;
+}
+
+FinalArgs final_args(const nd_box *b, const nd_mc_params *p, const McConsts &k, int kb, int64_t done,
+                     const nd_mc_trace *trace, int buf)
+{
+    const McWork &w = b->mc;
+    const size_t o = (size_t)buf * w.cap_k;
+    FinalArgs f;
+    f.dE0 = w.dE0 + o;
+    f.S0 = w.S0 + o;
+    f.thr = w.thr + o;
+    f.corr_s = w.corr_s + o;
+    f.corr_n = w.corr_n + o;
+    f.corr_ptr = w.corr_ptr + o;
+    f.pool_m = w.pool_m + (size_t)buf * w.cap_pool;
+    f.pool_c = w.pool_c + (size_t)buf * w.cap_pool;
+    f.acc = w.acc_flags + o;
+    f.kb = kb;
+    f.kT = p->kT;
+    f.tie_rel = k.tie_rel;
+    f.E = b->E;
+    f.dsum = w.dsum;
+    f.counters = w.counters;
+    f.tr_dE = trace && trace->dE ? trace->dE + done : nullptr;
+    f.tr_sabs = trace && trace->sabs ? trace->sabs + done : nullptr;
+    f.tr_acc = trace && trace->accepted ? trace->accepted + done : nullptr;
+    return f;
 }
 
 // Plan of n trials of one box with the cell scan.
@@ -1632,6 +1775,7 @@ struct McPlan {
     size_t lds = 0;
     ProposeArgs first;               // proposals of the first batch
     std::vector<McLaunch> batches;
+    FinalArgs last_fin;              // the last batch's final sums (kb = 0: none)
 };
 
 // Every batch's launch arguments and cell rebuild points, in order.  The
@@ -1653,6 +1797,8 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
     // the next batch's units are disjoint from this batch's when 2K <= n_units:
     // propose it alongside this batch's scan instead of after the commit
     const bool early_propose = 2 * K <= b->n_units;
+    FinalArgs prev_fin{};
+    prev_fin.kb = 0;
     int buf = 0;
     for (int64_t done = 0; done < n;) {
         const int kb = (int)std::min<int64_t>(K, n - done);
@@ -1687,8 +1833,8 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         ca.rcf2_filter = k.rcf2_filter;
         ca.rcf2 = k.rcf2;
         ca.tscale = k.tscale;
-        ca.dE0 = w.dE0;
-        ca.S0 = w.S0;
+        ca.dE0 = w.dE0 + (size_t)buf * w.cap_k;
+        ca.S0 = w.S0 + (size_t)buf * w.cap_k;
         const int64_t done_next = done + kb;
         const int kb_next = (int)std::max<int64_t>(0, std::min<int64_t>(K, n - done_next));
         const ProposeArgs nx = proposal_args(b, p, seed, first + (uint64_t)done_next, kb_next, buf ^ 1, K);
@@ -1704,7 +1850,13 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         if (!early_propose) L.cn.kb = 0;
         L.dblk = 1 + (L.cn.kb + DEC_CORR_TRIALS - 1) / DEC_CORR_TRIALS;
         L.ovf0 = w.ovf_fill;
-        L.nblk = scan_front_blocks(L.cr.kb, L.next.kb) + N_SLAB * ca.per_slab;
+        // the final sums of each batch run beside the next batch's scan
+        L.da.defer = 1;
+        L.da.acc_out = w.acc_flags + (size_t)buf * w.cap_k;
+        L.da.thr_out = w.thr + (size_t)buf * w.cap_k;
+        L.fin = prev_fin;
+        prev_fin = final_args(b, p, k, kb, done, trace, buf);
+        L.nblk = scan_front_blocks(L.cr.kb, L.next.kb, L.fin.kb > 0 ? 1 : 0) + N_SLAB * ca.per_slab;
         L.slab0 = slab_buffer(b, 0);
         L.slab1 = slab_buffer(b, 1);
         b->cells.trials_since_build += kb;
@@ -1712,6 +1864,7 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         done = done_next;
         buf ^= 1;
     }
+    pl.last_fin = prev_fin;
 }
 
 template <int MAXNU>
@@ -1824,7 +1977,7 @@ void mc_run_full(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first
             ND_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(k_mc_reduce, dim3((kb + 255) / 256), dim3(256), 0, b->stream, w.partial, n_jb, w.cap_k, kb,
-                           w.dE0, w.S0);
+                           w.dE0 + (size_t)buf * w.cap_k, w.S0 + (size_t)buf * w.cap_k);
         ND_HIP(hipGetLastError());
         switch (maxnu) {
         case 1: launch_corr<1>(b, cr); break;
@@ -1869,13 +2022,17 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
     for (const McLaunch &L : pl.batches) {
         if (L.rebuild) cells_rebuild_launch(b->stream, b->cells.d_args, 1, b->N, b->cells.ncell);
         switch (pl.maxnu) {
-        case 1: launch_scan_corr<1>(b, L.ca, L.cr, L.next, pl.lds); break;
-        case 2: launch_scan_corr<2>(b, L.ca, L.cr, L.next, pl.lds); break;
-        case 3: launch_scan_corr<3>(b, L.ca, L.cr, L.next, pl.lds); break;
-        case 4: launch_scan_corr<4>(b, L.ca, L.cr, L.next, pl.lds); break;
-        default: launch_scan_corr<8>(b, L.ca, L.cr, L.next, pl.lds); break;
+        case 1: launch_scan_corr<1>(b, L.ca, L.cr, L.next, L.fin, pl.lds); break;
+        case 2: launch_scan_corr<2>(b, L.ca, L.cr, L.next, L.fin, pl.lds); break;
+        case 3: launch_scan_corr<3>(b, L.ca, L.cr, L.next, L.fin, pl.lds); break;
+        case 4: launch_scan_corr<4>(b, L.ca, L.cr, L.next, L.fin, pl.lds); break;
+        default: launch_scan_corr<8>(b, L.ca, L.cr, L.next, L.fin, pl.lds); break;
         }
         launch_decide(b, pl.maxnu, L.dblk, L.da, L.late, L.cn);
+    }
+    if (pl.last_fin.kb > 0) {
+        hipLaunchKernelGGL(k_mc_final, dim3(1), dim3(FIN_THREADS), 0, b->stream, pl.last_fin);
+        ND_HIP(hipGetLastError());
     }
 }
 
@@ -1961,9 +2118,12 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
             L.cr.kb = L.ca.kb;
             L.cn.kb = 0;
             L.dblk = 1;
+            // each box's decision keeps its own final sums
+            L.da.defer = 0;
+            L.fin.kb = 0;
             L.ca.nw = nw;
             L.ca.per_slab = per_slab_blocks(L.ca.kb, nw);
-            L.nblk = scan_front_blocks(L.cr.kb, L.next.kb) + N_SLAB * L.ca.per_slab;
+            L.nblk = scan_front_blocks(L.cr.kb, L.next.kb, 0) + N_SLAB * L.ca.per_slab;
             m->launches.push_back(L);
             // a multiple of N_SLAB, so block x of every box row lands on XCD x mod 8
             m->r_maxblk[r] = std::max(m->r_maxblk[r], (L.nblk + N_SLAB - 1) / N_SLAB * N_SLAB);

@@ -297,6 +297,8 @@ static void free_box(nd_box *b)
     nd::dfree(b->mc.spheres);
     nd::dfree(b->mc.dE0);
     nd::dfree(b->mc.S0);
+    nd::dfree(b->mc.thr);
+    nd::dfree(b->mc.acc_flags);
     nd::cells_free(b);
     nd::dfree(b->ws);
     delete[] b->h_uoff;

@@ -55,15 +55,18 @@ struct McWork {
     Trial *trials = nullptr;      // [2][cap_k] batch being decided, next batch
     float4 *spheres = nullptr;    // [2][cap_k] bounding sphere of each trial (fractional)
     double *partial = nullptr;    // [cap_jb][2][cap_k]  (dE, sum |U|) per j-block (full scan)
-    double *dE0 = nullptr;        // [cap_k] energy change against the batch-start configuration
-    double *S0 = nullptr;         // [cap_k] sum of |U| of those pair terms
-    int32_t *corr_n = nullptr;    // [cap_k] correction entries of trial k
-    int32_t *corr_ptr = nullptr;  // [cap_k] first entry of trial k in the pool
-    float *corr_s = nullptr;      // [cap_k] sum |U| over trial k's correction terms
-    double2 *corr_b = nullptr;    // [2 cap_k] (lo, hi), (mag, count) of trial k's entries with m >= 0
-    int32_t *pool_m = nullptr;    // [cap_pool] earlier trial m of each entry (increasing), -1 if C = 0
-    double *pool_c = nullptr;     // [cap_pool] energy correction if m was accepted
-    int32_t *ovf_fill = nullptr;  // entries used in the pool's overflow area
+    double *dE0 = nullptr;        // [2][cap_k] energy change against the batch-start configuration
+    double *S0 = nullptr;         // [2][cap_k] sum of |U| of those pair terms
+    double *thr = nullptr;        // [2][cap_k] acceptance threshold -kT ln u, stored by the decision
+    uint8_t *acc_flags = nullptr; // [2][cap_k] decisions, for the deferred final sums
+    // correction buffers, one per batch parity: [2][cap_k] unless stated
+    int32_t *corr_n = nullptr;    // correction entries of trial k
+    int32_t *corr_ptr = nullptr;  // first entry of trial k in its buffer's pool
+    float *corr_s = nullptr;      // sum |U| over trial k's correction terms
+    double2 *corr_b = nullptr;    // [2][2 cap_k] (lo, hi), (mag, count) of trial k's entries with m >= 0
+    int32_t *pool_m = nullptr;    // [2][cap_pool] earlier trial m of each entry (increasing), -1 if C = 0
+    double *pool_c = nullptr;     // [2][cap_pool] energy correction if m was accepted
+    int32_t *ovf_fill = nullptr;  // [2] entries used in each pool's overflow area
     int32_t *slab = nullptr;      // [2][8 + 8 cap_k] per buffer: z-slab counts, then trial lists
     long long *counters = nullptr;   // [0] accepted, [1] near ties
     double *dsum = nullptr;       // accepted dE sum
