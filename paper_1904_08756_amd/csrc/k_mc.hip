@@ -85,13 +85,21 @@ struct ProposeArgs {
     const float4 *poslo;
     const int32_t *uoff;
     int N, n_units;
-    double L, invL, max_disp, max_rot;
+    double L, invL, max_disp, max_rot, kT;
     uint64_t seed, t0;
     int kb, kcap;
     nd::Trial *trials;
     float4 *spheres;
     int32_t *slab;  // [N_SLAB] counts (zero beforehand), then [N_SLAB][kcap] trial lists
 };
+
+// Threshold form of the Metropolis test: with u > 0, u < exp(-dE/kT)
+// exactly when dE < -kT ln u (they can differ only by rounding, far inside
+// the near-tie band); u = 0 accepts while exp(-dE/kT) is not 0.
+__device__ __forceinline__ double accept_threshold(double u, double kT)
+{
+    return u > 0.0 ? -kT * log(u) : 745.13321910194122 * kT;
+}
 
 // One thread per trial: translation tau = d (2u - 1) per axis; for units of
 // several atoms a rotation by theta = r (2u_5 - 1) about the axis
@@ -115,7 +123,7 @@ __device__ __forceinline__ void propose_one(const ProposeArgs &a, int k)
     T->a0 = a0;
     T->na = na;
     T->pad = 0;
-    T->u_acc = draw(a.seed, t, 6);
+    T->thr = accept_threshold(draw(a.seed, t, 6), a.kT);
 
     // centroid of the unit unwrapped around its first atom, rotation
     double x0[3] = {0.0, 0.0, 0.0}, cen[3] = {0.0, 0.0, 0.0};
@@ -1021,14 +1029,6 @@ __device__ __forceinline__ int block_exscan(int v, int *s_wave)
     return s_wave[wave] + x - v;
 }
 
-// Threshold form of the Metropolis test: with u > 0, u < exp(-dE/kT)
-// exactly when dE < -kT ln u (they can differ only by rounding, far inside
-// the near-tie band); u = 0 accepts while exp(-dE/kT) is not 0.
-__device__ __forceinline__ double accept_threshold(double u, double kT)
-{
-    return u > 0.0 ? -kT * log(u) : 745.13321910194122 * kT;
-}
-
 __device__ __forceinline__ bool metropolis(double e, double thr) { return e <= 0.0 || e < thr; }
 
 constexpr unsigned char ST_OPEN = 0, ST_REJ = 1, ST_ACC = 2;
@@ -1110,7 +1110,7 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
         // correction step wrote, so no entry is read here
         int my_open = 0;
         int n[2], ptr[2];
-        double e0[2], u[2], S[2];
+        double e0[2], thr_k[2], S[2];
         double2 blh[2], bmc[2];
         int4 ids[2];
 #pragma unroll
@@ -1122,7 +1122,7 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                 e0[h] = ldg(a.dE0 + k);
                 const nd::Trial &T = a.trials[k];
                 ids[h] = ld_i4(reinterpret_cast<const int4 *>(&T.unit));
-                u[h] = ldg(&T.u_acc);
+                thr_k[h] = ldg(&T.thr);
                 S[h] = ldg(a.S0 + k) + (double)ldg(a.corr_s + k);
                 blh[h] = ld_d2(a.corr_b + 2 * k);
                 bmc[h] = ld_d2(a.corr_b + 2 * k + 1);
@@ -1132,7 +1132,7 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
         for (int h = 0; h < 2; ++h) {
             const int k = tid + h * DEC_THREADS;
             if (k < kb) {
-                const double thr = accept_threshold(u[h], a.kT);
+                const double thr = thr_k[h];
                 const bool any = bmc[h].y > 0.0;
                 unsigned char d;
                 if (!any) {
@@ -1231,7 +1231,9 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
             if (a.tr_acc) a.tr_acc[k] = acc ? 1 : 0;
             if (a.tr_unit) a.tr_unit[k] = a.trials[k].unit;
         }
-        // commit: one item per (trial, atom), loads of four items issued together
+        // commit: one item per (trial, atom), consecutive items on consecutive
+        // lanes (a trial's atoms share cache lines), the loads of four items
+        // issued together
         float dmax = 0.0f;
         const int max_na = a.max_na;
         const int n_items = kb * max_na;
@@ -1664,6 +1666,7 @@ ProposeArgs proposal_args(const nd_box *b, const nd_mc_params *p, uint64_t seed,
     pa.invL = 1.0 / b->L;
     pa.max_disp = p->max_disp;
     pa.max_rot = p->max_rot;
+    pa.kT = p->kT;
     pa.seed = seed;
     pa.t0 = t0;
     pa.kb = kb;

@@ -45,7 +45,7 @@ struct Trial {
     float cen[3];                       // fractional centre of old+new atoms
     float rad;                          // fractional radius about cen
     int32_t unit, a0, na, pad;
-    double u_acc;                       // acceptance draw
+    double thr;                         // acceptance threshold -kT ln u of the trial's draw u
 };
 
 struct McWork {
