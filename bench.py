@@ -36,10 +36,10 @@ OPS_PER_TEST = 16
 OPS_PER_PAIR = 23
 # HBM bytes one k_pair_hist launch moves on the 99,999-atom water box, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch scaled by a 1 GiB copy
-# (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 9722.3 + 24958.9
+# (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 7426.0 + 24958.9
 # KiB.  profiles/k_pair_hist_water99999.md holds the counters and commands;
 # set to None whenever the kernel changes until they are taken again.
-HIST_TRAFFIC_BYTES = (2 * 9722.3 + 24958.9) * 1024
+HIST_TRAFFIC_BYTES = (2 * 7426.0 + 24958.9) * 1024
 PAPER_GPU_STEPS_PER_S_1E5 = 12412.0  # Table "tab_speed", water, 1e5 atoms, Tesla V100
 
 
@@ -195,7 +195,10 @@ def main():
         step(s)
         torch.cuda.synchronize()
         log(f"warmup step {s} done")
-    g.set_profiling(True)
+    # timed steps: an event pair around each k_pair_hist launch only (the
+    # roofline's kernel time); events around the ~400 Metropolis launches of
+    # a step would add a few microseconds to each
+    g.set_profiling(True, kernels=("pair_hist",))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.warmup, args.warmup + args.steps):
@@ -203,15 +206,26 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
-    prof = {k: g.profile(k) for k in ("mc_scan", "mc_corr", "mc_decide", "mc_propose", "pair_hist")}
+    hist_n, hist_ms = g.profile("pair_hist")
     g.set_profiling(False)
     assert np.all(np.isfinite(S.cpu().numpy()))
+    # kernel time shares: the same number of further steps with an event pair
+    # around every launch (not part of the timed figure)
+    g.set_profiling(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in range(args.warmup + args.steps, args.warmup + 2 * args.steps):
+        step(s)
+    torch.cuda.synchronize()
+    elapsed_prof = time.perf_counter() - t1
+    prof = {k: g.profile(k) for k in ("mc_scan", "mc_corr", "mc_decide", "mc_propose", "pair_hist")}
+    g.set_profiling(False)
+    log(f"profiled {args.steps} steps in {elapsed_prof:.3f} s")
 
     ms_per_step = 1000.0 * elapsed / args.steps
     moves_per_s = n_trials * args.steps / elapsed
     dist_per_s = (n_trials * n_tests_per_trial + n_pairs) * args.steps / elapsed
 
-    hist_n, hist_ms = prof["pair_hist"]
     hist_avg_s = hist_ms / max(hist_n, 1) / 1e3
     hist_achieved = n_pairs * OPS_PER_PAIR / hist_avg_s
 
@@ -248,9 +262,11 @@ def main():
             "pairs_per_s": n_pairs / hist_avg_s,
         },
         "kernels": {
-            k: {"launches": n, "ms_total": ms, "share_of_step_time": ms / (1000.0 * elapsed)}
+            k: {"launches": n, "ms_total": ms, "share_of_step_time": ms / (1000.0 * elapsed_prof)}
             for k, (n, ms) in prof.items()
         },
+        "kernels_note": (f"{args.steps} further steps with an event pair around every launch "
+                         f"({1000.0 * elapsed_prof / args.steps:.2f} ms per step with the events)"),
         "paper_context": {"gpu_steps_per_s_1e5_atoms": PAPER_GPU_STEPS_PER_S_1E5,
                           "hardware": "NVIDIA Tesla V100 (Table tab_speed)",
                           "cpu_serial_steps_per_s_1e5_atoms": 62.67},

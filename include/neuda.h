@@ -333,6 +333,12 @@ nd_status nd_batch_info(const nd_batch *batch, int64_t *captures, int64_t *launc
  * kernels above on this machine and clears the totals; 0 stops recording. */
 nd_status nd_box_set_profiling(nd_box *box, int32_t enable);
 
+/* The same for a subset: bit k of `kernels` (1 << ND_PROF_*) selects kernel
+ * id k; the other kernels launch without events (an event pair adds a few
+ * microseconds to a launch on the stream).  0 stops recording.  Errors:
+ * ND_E_INVALID for bits past ND_PROF_KINDS. */
+nd_status nd_box_set_profiling_mask(nd_box *box, uint32_t kernels);
+
 /* Synchronises the box's stream and returns the number of recorded launches
  * of `kernel` and their summed duration in milliseconds since profiling was
  * enabled.  Errors: ND_E_INVALID for an unknown kernel id. */

@@ -105,6 +105,7 @@ EXPORTS = {
                                         C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "nd_box_pair_counts": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "nd_box_set_profiling": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "nd_box_set_profiling_mask": (C.c_int32, [C.c_void_p, C.c_uint32]),
     "nd_box_profile": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]),
     "nd_eq1_weights": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
@@ -235,9 +236,17 @@ class Box:
         _check(lib().nd_box_set_stream(self.handle, _stream()))
 
     # -- measurement
-    def set_profiling(self, enable: bool):
+    def set_profiling(self, enable: bool, kernels=None):
+        """Event pairs around every profiled launch (kernels: names of PROF to
+        restrict them to; the others launch without events)."""
         self._sync_stream()
-        _check(lib().nd_box_set_profiling(self.handle, int(enable)))
+        if kernels is None:
+            _check(lib().nd_box_set_profiling(self.handle, int(enable)))
+        else:
+            mask = 0
+            for k in kernels:
+                mask |= 1 << PROF[k]
+            _check(lib().nd_box_set_profiling_mask(self.handle, mask if enable else 0))
 
     def profile(self, kernel: str):
         """(launches, total milliseconds) recorded for a kernel since profiling was enabled."""

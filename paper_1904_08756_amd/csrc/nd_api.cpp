@@ -221,7 +221,7 @@ static hipEvent_t take_event(nd_box *b)
 
 ProfScope::ProfScope(nd_box *box, int k) : b(box), kind(k)
 {
-    if (!b->prof_on) return;
+    if (!(b->prof_mask & (1u << kind))) return;
     if (b->prof_pending[kind].size() >= 8192) prof_harvest(b);
     e1 = take_event(b);
     e2 = take_event(b);
@@ -425,20 +425,26 @@ nd_status nd_box_destroy(nd_box *b)
     });
 }
 
-nd_status nd_box_set_profiling(nd_box *b, int32_t enable)
+nd_status nd_box_set_profiling_mask(nd_box *b, uint32_t kernels)
 {
     return guarded([&] {
         check_box(b);
+        require((kernels >> ND_PROF_KINDS) == 0, ND_E_INVALID, "unknown kernel bit");
         DeviceGuard g(b->device);
         nd::prof_harvest(b);
-        if (enable) {
+        if (kernels) {
             for (int k = 0; k < ND_PROF_KINDS; ++k) {
                 b->prof_ms[k] = 0.0;
                 b->prof_n[k] = 0;
             }
         }
-        b->prof_on = enable != 0;
+        b->prof_mask = kernels;
     });
+}
+
+nd_status nd_box_set_profiling(nd_box *b, int32_t enable)
+{
+    return nd_box_set_profiling_mask(b, enable ? (1u << ND_PROF_KINDS) - 1u : 0u);
 }
 
 nd_status nd_box_profile(nd_box *b, int32_t kernel, int64_t *launches, double *ms)

@@ -136,7 +136,7 @@ struct nd_box {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     // per-kernel event timing
-    bool prof_on = false;
+    uint32_t prof_mask = 0;  // bit k: event pairs around launches of kernel id k
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending[ND_PROF_KINDS];
     std::vector<hipEvent_t> prof_free;
     double prof_ms[ND_PROF_KINDS] = {0, 0, 0, 0, 0, 0, 0, 0};
