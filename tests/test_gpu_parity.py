@@ -284,6 +284,27 @@ def test_mc_rejects_missing_tables(nd):
     assert e.value.code == -5
 
 
+def test_profiling_mask_selects_kernels(nd):
+    # events only around the kernels of the mask; the others launch bare
+    box, T, mc = syn.config_c1()
+    g = _gbox(nd, box, T)
+    p = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"])
+    g.set_profiling(True, kernels=("pair_hist",))
+    g.mc_sweep(p, 3, 0, box.n_units)
+    nd.pair_histogram(g, mc["dr"], mc["nbins"])
+    n_scan, ms_scan = g.profile("mc_scan")
+    n_hist, ms_hist = g.profile("pair_hist")
+    g.set_profiling(False)
+    assert (n_scan, ms_scan) == (0, 0.0)
+    assert n_hist == 1 and ms_hist > 0.0
+    g.set_profiling(True)
+    g.mc_sweep(p, 3, box.n_units, box.n_units)
+    assert g.profile("mc_scan")[0] > 0 and g.profile("mc_decide")[0] > 0
+    g.set_profiling(False)
+    # a bit past the kernel ids is an error
+    assert nd.lib().nd_box_set_profiling_mask(g.handle, 1 << 8) == -1  # ND_E_INVALID
+
+
 # ------------------------------------------------------------------ differentiated form
 def _broad_box():
     return syn.water_box(600, 18.0, 21, "broad")
