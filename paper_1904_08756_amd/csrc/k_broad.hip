@@ -92,11 +92,47 @@ struct BroadArgs {
     double dr, inv_dr, six_sigma;
     float beta;              // dr / sigma
     const float4 *mills;     // [MILLS_N] Mills-ratio table
+    // bin-mass table (wt_nm > 0): the mass of bin kr + m, m = wt_m0 + mi, of
+    // a unit Gaussian at fraction f of bin kr, as a cubic in f about the
+    // centre of each of WT_NP pieces: wt0 the value (FP64), wt1.xyz the
+    // first three Taylor coefficients
+    const double *wt0;       // [wt_nm][WT_NP]
+    const float4 *wt1;       // [wt_nm][WT_NP]
+    int wt_m0, wt_nm;
     double *partial;  // [gridDim.x][P*nbins]
 };
 
+constexpr int WT_NP = 32;             // pieces of the bin-mass table per unit of f
+constexpr int WT_MAX_BYTES = 16384;   // the table path is taken when the table fits this
+
 constexpr int BQ = 128;     // pairs queued per wave
 constexpr int FTILE = 512;  // atoms per tile of the forward: eight waves share one LDS histogram
+
+// The window of one pair at distance r (r < L/2) into the u64 row h from the
+// bin-mass table: one entry per bin of the window, the value in FP64 plus
+// the FP32 Taylor terms (at most a few 1e-3), in units of 2^-32.  Bins past
+// the table (masses below 1e-13) are left out.
+__device__ __forceinline__ void broad_pair_tab(const BroadArgs &a, const double *t0, const float4 *t1,
+                                               unsigned long long *h, double r)
+{
+    int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
+    int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
+    k0 = max(k0, 0);
+    k1 = min(k1, a.nbins - 1);
+    const double u = r * a.inv_dr;
+    const int kr = (int)u;
+    const float f = (float)(u - (double)kr);
+    const int pc = min((int)(f * (float)WT_NP), WT_NP - 1);
+    const float d = f - ((float)pc + 0.5f) * (1.0f / WT_NP);
+    for (int k = k0; k <= k1; ++k) {
+        const int mi = k - kr - a.wt_m0;
+        if ((unsigned)mi >= (unsigned)a.wt_nm) continue;
+        const int e = mi * WT_NP + pc;
+        const float4 c = t1[e];
+        const double w = t0[e] + (double)(d * fmaf(d, fmaf(d, c.z, c.y), c.x));
+        atomicAdd(&h[k], (unsigned long long)__double2uint_rn(w * 4294967296.0));
+    }
+}
 
 // The window of one pair at distance r (r < L/2) into the u64 row h: bin
 // weights as differences of the edges' tail masses, in units of 2^-32.  Each
@@ -132,13 +168,18 @@ __device__ __forceinline__ void broad_pair(const BroadArgs &a, const float4 *mil
 // pairs inside the window range are queued per wave in LDS and their windows
 // are evaluated 64 at a time, one per lane, so no lane idles on the pairs
 // past L/2.  Integer sums: the result does not depend on the order.
+template <bool TAB>
 __global__ __launch_bounds__(FTILE) void k_hist_broad(BroadArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long *hist = reinterpret_cast<unsigned long long *>(smem);  // [P*nbins] weights x 2^32
     double *jx = reinterpret_cast<double *>(hist + (size_t)a.P * a.nbins);   // [3][FTILE]
+    // the bin-mass table (TAB) or the Mills-ratio table
+    const int ntab = TAB ? a.wt_nm * WT_NP : 0;
+    double *t0 = jx + 3 * FTILE;                                                // [ntab]
+    float4 *t1 = reinterpret_cast<float4 *>(t0 + ntab);                        // [ntab]
     float4 *mills = reinterpret_cast<float4 *>(jx + 3 * FTILE);               // [MILLS_N]
-    int *js = reinterpret_cast<int *>(mills + MILLS_N);                       // [FTILE]
+    int *js = TAB ? reinterpret_cast<int *>(t1 + ntab) : reinterpret_cast<int *>(mills + MILLS_N);  // [FTILE]
     int *prow = js + FTILE;                                                    // [16]
     __shared__ double s_qr[FTILE / 64][BQ];
     __shared__ int s_qrow[FTILE / 64][BQ];
@@ -146,7 +187,14 @@ __global__ __launch_bounds__(FTILE) void k_hist_broad(BroadArgs a)
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int nq = a.P * a.nbins;
     for (int q = tid; q < nq; q += FTILE) hist[q] = 0ull;
-    for (int q = tid; q < MILLS_N; q += FTILE) mills[q] = nd::ld4(a.mills + q);
+    if (TAB) {
+        for (int q = tid; q < ntab; q += FTILE) {
+            t0[q] = a.wt0[q];
+            t1[q] = nd::ld4(a.wt1 + q);
+        }
+    } else {
+        for (int q = tid; q < MILLS_N; q += FTILE) mills[q] = nd::ld4(a.mills + q);
+    }
     if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.nbins;
     __syncthreads();
     const int N = a.N;
@@ -202,12 +250,20 @@ __global__ __launch_bounds__(FTILE) void k_hist_broad(BroadArgs a)
                 }
                 nqw -= 64;
                 __builtin_amdgcn_wave_barrier();
-                broad_pair(a, mills, hist + rowq, rq);
+                if (TAB)
+                    broad_pair_tab(a, t0, t1, hist + rowq, rq);
+                else
+                    broad_pair(a, mills, hist + rowq, rq);
             }
         }
     }
     __builtin_amdgcn_wave_barrier();
-    if (lane < nqw) broad_pair(a, mills, hist + qrow[lane], qr[lane]);
+    if (lane < nqw) {
+        if (TAB)
+            broad_pair_tab(a, t0, t1, hist + qrow[lane], qr[lane]);
+        else
+            broad_pair(a, mills, hist + qrow[lane], qr[lane]);
+    }
     __syncthreads();
     double *out = a.partial + (size_t)blockIdx.x * nq;
     for (int q = tid; q < nq; q += FTILE) out[q] = (double)hist[q] * 2.3283064365386963e-10;
@@ -474,6 +530,64 @@ const float4 *mills_table(nd_box *b)
     return d;
 }
 
+// Mass of [b, a] under the unit Gaussian, from the tails so that neither
+// side cancels.
+double gauss_mass(double b, double a)
+{
+    auto Q = [](double x) { return 0.5 * std::erfc(x / std::sqrt(2.0)); };  // upper tail
+    if (b >= 0.0) return Q(b) - Q(a);
+    if (a <= 0.0) return Q(-a) - Q(-b);
+    return 1.0 - Q(a) - Q(-b);
+}
+
+// The bin-mass table for beta = dr/sigma and s = 6 sigma/dr (FP64 on the
+// host, kept per box until the parameters change): for bin offset m and
+// piece centre fc, w(f) = Phi((m+1-f) beta) - Phi((m-f) beta) and its
+// derivatives in f, w' = -beta [phi(a) - phi(b)], w'' = beta^2 [phi'(a) -
+// phi'(b)], w''' = -beta^3 [phi''(a) - phi''(b)], with a = (m+1-fc) beta,
+// b = (m-fc) beta, phi' = -x phi, phi'' = (x^2 - 1) phi.  Returns false when
+// the table would not fit.
+bool bin_mass_table(nd_box *b, double dr, double sigma, BroadArgs &a)
+{
+    const double beta = dr / sigma, s = 6.0 * sigma / dr;
+    const int m0 = (int)std::floor(-s) - 1, m1 = (int)std::ceil(s) + 1;
+    const int nm = m1 - m0 + 1;
+    const size_t bytes = (sizeof(double) + sizeof(float4)) * (size_t)nm * WT_NP;
+    if (bytes > (size_t)WT_MAX_BYTES) return false;
+    if (!(b->bt_dev && b->bt_beta == beta && b->bt_s == s)) {
+        std::vector<double> h0((size_t)nm * WT_NP);
+        std::vector<float4> h1((size_t)nm * WT_NP);
+        const double c = 1.0 / std::sqrt(2.0 * M_PI);
+        auto phi = [c](double x) { return c * std::exp(-0.5 * x * x); };
+        for (int mi = 0; mi < nm; ++mi) {
+            const int m = m0 + mi;
+            for (int p = 0; p < WT_NP; ++p) {
+                const double fc = (p + 0.5) / WT_NP;
+                const double xa = (m + 1 - fc) * beta, xb = (m - fc) * beta;
+                const double pa = phi(xa), pb = phi(xb);
+                const double w1 = -beta * (pa - pb);
+                const double w2 = beta * beta * (-xa * pa + xb * pb);
+                const double w3 = -beta * beta * beta * ((xa * xa - 1.0) * pa - (xb * xb - 1.0) * pb);
+                h0[(size_t)mi * WT_NP + p] = gauss_mass(xb, xa);
+                h1[(size_t)mi * WT_NP + p] = make_float4((float)w1, (float)(w2 / 2.0), (float)(w3 / 6.0), 0.0f);
+            }
+        }
+        ND_HIP(hipStreamSynchronize(b->stream));
+        nd::dfree(b->bt_dev);
+        b->bt_dev = nd::dmalloc(bytes);
+        ND_HIP(hipMemcpy(b->bt_dev, h0.data(), sizeof(double) * h0.size(), hipMemcpyHostToDevice));
+        ND_HIP(hipMemcpy(static_cast<char *>(b->bt_dev) + sizeof(double) * h0.size(), h1.data(),
+                         sizeof(float4) * h1.size(), hipMemcpyHostToDevice));
+        b->bt_beta = beta;
+        b->bt_s = s;
+    }
+    a.wt0 = static_cast<const double *>(b->bt_dev);
+    a.wt1 = reinterpret_cast<const float4 *>(static_cast<const char *>(b->bt_dev) + sizeof(double) * (size_t)nm * WT_NP);
+    a.wt_m0 = m0;
+    a.wt_nm = nm;
+    return true;
+}
+
 }  // namespace
 
 namespace nd {
@@ -497,8 +611,14 @@ void launch_hist_broad(nd_box *b, double dr, int nbins, double sigma, double *d_
     a.six_sigma = 6.0 * sigma;
     a.beta = (float)(dr / sigma);
     a.mills = mills_table(b);
+    a.wt0 = nullptr;
+    a.wt1 = nullptr;
+    a.wt_m0 = 0;
+    a.wt_nm = 0;
+    const bool tab = bin_mass_table(b, dr, sigma, a);
     const int nq = a.P * nbins;
-    size_t lds = sizeof(double) * ((size_t)nq + 3 * FTILE) + sizeof(float4) * MILLS_N + sizeof(int) * (FTILE + 16);
+    const size_t lds_tab = tab ? (sizeof(double) + sizeof(float4)) * (size_t)a.wt_nm * WT_NP : sizeof(float4) * MILLS_N;
+    size_t lds = sizeof(double) * ((size_t)nq + 3 * FTILE) + lds_tab + sizeof(int) * (FTILE + 16);
     const size_t lds_queue = (sizeof(double) + sizeof(int)) * BQ * (FTILE / 64);  // static, in the kernel
     if (lds + lds_queue > 160 * 1024) fail(ND_E_UNSUPPORTED, "broadened histogram does not fit in LDS");
     int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (lds + lds_queue + 1024)));
@@ -510,7 +630,10 @@ void launch_hist_broad(nd_box *b, double dr, int nbins, double sigma, double *d_
     a.partial = static_cast<double *>(workspace(b, sizeof(double) * (size_t)G * nq));
     {
         ProfScope ps(b, ND_PROF_HIST_BROAD);
-        hipLaunchKernelGGL(k_hist_broad, dim3((unsigned)G), dim3(FTILE), lds, b->stream, a);
+        if (tab)
+            hipLaunchKernelGGL(k_hist_broad<true>, dim3((unsigned)G), dim3(FTILE), lds, b->stream, a);
+        else
+            hipLaunchKernelGGL(k_hist_broad<false>, dim3((unsigned)G), dim3(FTILE), lds, b->stream, a);
         ND_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_reduce_f64, dim3((nq + 255) / 256), dim3(256), 0, b->stream, a.partial, (int)G, nq, d_nhat);

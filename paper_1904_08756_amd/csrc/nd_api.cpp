@@ -298,6 +298,7 @@ static void free_box(nd_box *b)
     nd::dfree(b->mc.dE0);
     nd::dfree(b->mc.S0);
     nd::dfree(b->mc.thr);
+    nd::dfree(b->bt_dev);
     nd::dfree(b->mc.acc_flags);
     nd::cells_free(b);
     nd::dfree(b->ws);

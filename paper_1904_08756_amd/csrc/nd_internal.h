@@ -137,6 +137,9 @@ struct nd_box {
     size_t ws_bytes = 0;
     // per-kernel event timing
     uint32_t prof_mask = 0;  // bit k: event pairs around launches of kernel id k
+    // bin-mass table of the broadened histogram, for (beta, s) = (dr/sigma, 6 sigma/dr)
+    void *bt_dev = nullptr;
+    double bt_beta = 0.0, bt_s = 0.0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending[ND_PROF_KINDS];
     std::vector<hipEvent_t> prof_free;
     double prof_ms[ND_PROF_KINDS] = {0, 0, 0, 0, 0, 0, 0, 0};
