@@ -93,27 +93,25 @@ struct BroadArgs {
     float beta;              // dr / sigma
     const float4 *mills;     // [MILLS_N] Mills-ratio table
     // bin-mass table (wt_nm > 0): the mass of bin kr + m, m = wt_m0 + mi, of
-    // a unit Gaussian at fraction f of bin kr, as a cubic in f about the
-    // centre of each of WT_NP pieces: wt0 the value (FP64), wt1.xyz the
-    // first three Taylor coefficients
-    const double *wt0;       // [wt_nm][WT_NP]
-    const float4 *wt1;       // [wt_nm][WT_NP]
+    // a unit Gaussian at fraction f of bin kr, as a quadratic in f about the
+    // centre of each of WT_NP pieces: (value as two floats, hi + lo, and the
+    // first two Taylor coefficients), one 16-byte read per bin
+    const float4 *wt;        // [wt_nm][WT_NP]
     int wt_m0, wt_nm;
     double *partial;  // [gridDim.x][P*nbins]
 };
 
-constexpr int WT_NP = 32;             // pieces of the bin-mass table per unit of f
+constexpr int WT_NP = 64;             // pieces of the bin-mass table per unit of f
 constexpr int WT_MAX_BYTES = 16384;   // the table path is taken when the table fits this
 
 constexpr int BQ = 128;     // pairs queued per wave
 constexpr int FTILE = 512;  // atoms per tile of the forward: eight waves share one LDS histogram
 
 // The window of one pair at distance r (r < L/2) into the u64 row h from the
-// bin-mass table: one entry per bin of the window, the value in FP64 plus
-// the FP32 Taylor terms (at most a few 1e-3), in units of 2^-32.  Bins past
-// the table (masses below 1e-13) are left out.
-__device__ __forceinline__ void broad_pair_tab(const BroadArgs &a, const double *t0, const float4 *t1,
-                                               unsigned long long *h, double r)
+// bin-mass table: one entry per bin of the window, the value (hi + lo,
+// summed in FP64) plus the FP32 Taylor terms (at most a few 1e-3), in units
+// of 2^-32.  Bins past the table (masses below 1e-13) are left out.
+__device__ __forceinline__ void broad_pair_tab(const BroadArgs &a, const float4 *t, unsigned long long *h, double r)
 {
     int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
     int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
@@ -127,9 +125,8 @@ __device__ __forceinline__ void broad_pair_tab(const BroadArgs &a, const double 
     for (int k = k0; k <= k1; ++k) {
         const int mi = k - kr - a.wt_m0;
         if ((unsigned)mi >= (unsigned)a.wt_nm) continue;
-        const int e = mi * WT_NP + pc;
-        const float4 c = t1[e];
-        const double w = t0[e] + (double)(d * fmaf(d, fmaf(d, c.z, c.y), c.x));
+        const float4 c = t[mi * WT_NP + pc];
+        const double w = (double)c.x + ((double)c.y + (double)(d * fmaf(d, c.w, c.z)));
         atomicAdd(&h[k], (unsigned long long)__double2uint_rn(w * 4294967296.0));
     }
 }
@@ -175,11 +172,9 @@ __global__ __launch_bounds__(FTILE) void k_hist_broad(BroadArgs a)
     unsigned long long *hist = reinterpret_cast<unsigned long long *>(smem);  // [P*nbins] weights x 2^32
     double *jx = reinterpret_cast<double *>(hist + (size_t)a.P * a.nbins);   // [3][FTILE]
     // the bin-mass table (TAB) or the Mills-ratio table
-    const int ntab = TAB ? a.wt_nm * WT_NP : 0;
-    double *t0 = jx + 3 * FTILE;                                                // [ntab]
-    float4 *t1 = reinterpret_cast<float4 *>(t0 + ntab);                        // [ntab]
-    float4 *mills = reinterpret_cast<float4 *>(jx + 3 * FTILE);               // [MILLS_N]
-    int *js = TAB ? reinterpret_cast<int *>(t1 + ntab) : reinterpret_cast<int *>(mills + MILLS_N);  // [FTILE]
+    const int ntab = TAB ? a.wt_nm * WT_NP : MILLS_N;
+    float4 *tab = reinterpret_cast<float4 *>(jx + 3 * FTILE);                 // [ntab]
+    int *js = reinterpret_cast<int *>(tab + ntab);                            // [FTILE]
     int *prow = js + FTILE;                                                    // [16]
     __shared__ double s_qr[FTILE / 64][BQ];
     __shared__ int s_qrow[FTILE / 64][BQ];
@@ -187,14 +182,7 @@ __global__ __launch_bounds__(FTILE) void k_hist_broad(BroadArgs a)
     const unsigned long long lt = (1ull << lane) - 1ull;
     const int nq = a.P * a.nbins;
     for (int q = tid; q < nq; q += FTILE) hist[q] = 0ull;
-    if (TAB) {
-        for (int q = tid; q < ntab; q += FTILE) {
-            t0[q] = a.wt0[q];
-            t1[q] = nd::ld4(a.wt1 + q);
-        }
-    } else {
-        for (int q = tid; q < MILLS_N; q += FTILE) mills[q] = nd::ld4(a.mills + q);
-    }
+    for (int q = tid; q < ntab; q += FTILE) tab[q] = nd::ld4((TAB ? a.wt : a.mills) + q);
     if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.nbins;
     __syncthreads();
     const int N = a.N;
@@ -251,18 +239,18 @@ __global__ __launch_bounds__(FTILE) void k_hist_broad(BroadArgs a)
                 nqw -= 64;
                 __builtin_amdgcn_wave_barrier();
                 if (TAB)
-                    broad_pair_tab(a, t0, t1, hist + rowq, rq);
+                    broad_pair_tab(a, tab, hist + rowq, rq);
                 else
-                    broad_pair(a, mills, hist + rowq, rq);
+                    broad_pair(a, tab, hist + rowq, rq);
             }
         }
     }
     __builtin_amdgcn_wave_barrier();
     if (lane < nqw) {
         if (TAB)
-            broad_pair_tab(a, t0, t1, hist + qrow[lane], qr[lane]);
+            broad_pair_tab(a, tab, hist + qrow[lane], qr[lane]);
         else
-            broad_pair(a, mills, hist + qrow[lane], qr[lane]);
+            broad_pair(a, tab, hist + qrow[lane], qr[lane]);
     }
     __syncthreads();
     double *out = a.partial + (size_t)blockIdx.x * nq;
@@ -543,20 +531,20 @@ double gauss_mass(double b, double a)
 // The bin-mass table for beta = dr/sigma and s = 6 sigma/dr (FP64 on the
 // host, kept per box until the parameters change): for bin offset m and
 // piece centre fc, w(f) = Phi((m+1-f) beta) - Phi((m-f) beta) and its
-// derivatives in f, w' = -beta [phi(a) - phi(b)], w'' = beta^2 [phi'(a) -
-// phi'(b)], w''' = -beta^3 [phi''(a) - phi''(b)], with a = (m+1-fc) beta,
-// b = (m-fc) beta, phi' = -x phi, phi'' = (x^2 - 1) phi.  Returns false when
-// the table would not fit.
+// derivatives in f, w' = -beta [phi(a) - phi(b)] and w'' = beta^2 [phi'(a) -
+// phi'(b)], with a = (m+1-fc) beta, b = (m-fc) beta, phi' = -x phi.  The
+// cubic term left out, w''' d^3 / 6 with |d| <= 1/128, is odd in d: at most
+// ~1e-7 of a pair's mass in a bin, with no mean over a piece.  Returns false
+// when the table would not fit.
 bool bin_mass_table(nd_box *b, double dr, double sigma, BroadArgs &a)
 {
     const double beta = dr / sigma, s = 6.0 * sigma / dr;
     const int m0 = (int)std::floor(-s) - 1, m1 = (int)std::ceil(s) + 1;
     const int nm = m1 - m0 + 1;
-    const size_t bytes = (sizeof(double) + sizeof(float4)) * (size_t)nm * WT_NP;
+    const size_t bytes = sizeof(float4) * (size_t)nm * WT_NP;
     if (bytes > (size_t)WT_MAX_BYTES) return false;
     if (!(b->bt_dev && b->bt_beta == beta && b->bt_s == s)) {
-        std::vector<double> h0((size_t)nm * WT_NP);
-        std::vector<float4> h1((size_t)nm * WT_NP);
+        std::vector<float4> h((size_t)nm * WT_NP);
         const double c = 1.0 / std::sqrt(2.0 * M_PI);
         auto phi = [c](double x) { return c * std::exp(-0.5 * x * x); };
         for (int mi = 0; mi < nm; ++mi) {
@@ -565,24 +553,21 @@ bool bin_mass_table(nd_box *b, double dr, double sigma, BroadArgs &a)
                 const double fc = (p + 0.5) / WT_NP;
                 const double xa = (m + 1 - fc) * beta, xb = (m - fc) * beta;
                 const double pa = phi(xa), pb = phi(xb);
+                const double w0 = gauss_mass(xb, xa);
                 const double w1 = -beta * (pa - pb);
                 const double w2 = beta * beta * (-xa * pa + xb * pb);
-                const double w3 = -beta * beta * beta * ((xa * xa - 1.0) * pa - (xb * xb - 1.0) * pb);
-                h0[(size_t)mi * WT_NP + p] = gauss_mass(xb, xa);
-                h1[(size_t)mi * WT_NP + p] = make_float4((float)w1, (float)(w2 / 2.0), (float)(w3 / 6.0), 0.0f);
+                const float hi = (float)w0;
+                h[(size_t)mi * WT_NP + p] = make_float4(hi, (float)(w0 - (double)hi), (float)w1, (float)(w2 / 2.0));
             }
         }
         ND_HIP(hipStreamSynchronize(b->stream));
         nd::dfree(b->bt_dev);
         b->bt_dev = nd::dmalloc(bytes);
-        ND_HIP(hipMemcpy(b->bt_dev, h0.data(), sizeof(double) * h0.size(), hipMemcpyHostToDevice));
-        ND_HIP(hipMemcpy(static_cast<char *>(b->bt_dev) + sizeof(double) * h0.size(), h1.data(),
-                         sizeof(float4) * h1.size(), hipMemcpyHostToDevice));
+        ND_HIP(hipMemcpy(b->bt_dev, h.data(), bytes, hipMemcpyHostToDevice));
         b->bt_beta = beta;
         b->bt_s = s;
     }
-    a.wt0 = static_cast<const double *>(b->bt_dev);
-    a.wt1 = reinterpret_cast<const float4 *>(static_cast<const char *>(b->bt_dev) + sizeof(double) * (size_t)nm * WT_NP);
+    a.wt = static_cast<const float4 *>(b->bt_dev);
     a.wt_m0 = m0;
     a.wt_nm = nm;
     return true;
@@ -611,13 +596,12 @@ void launch_hist_broad(nd_box *b, double dr, int nbins, double sigma, double *d_
     a.six_sigma = 6.0 * sigma;
     a.beta = (float)(dr / sigma);
     a.mills = mills_table(b);
-    a.wt0 = nullptr;
-    a.wt1 = nullptr;
+    a.wt = nullptr;
     a.wt_m0 = 0;
     a.wt_nm = 0;
     const bool tab = bin_mass_table(b, dr, sigma, a);
     const int nq = a.P * nbins;
-    const size_t lds_tab = tab ? (sizeof(double) + sizeof(float4)) * (size_t)a.wt_nm * WT_NP : sizeof(float4) * MILLS_N;
+    const size_t lds_tab = sizeof(float4) * (tab ? (size_t)a.wt_nm * WT_NP : (size_t)MILLS_N);
     size_t lds = sizeof(double) * ((size_t)nq + 3 * FTILE) + lds_tab + sizeof(int) * (FTILE + 16);
     const size_t lds_queue = (sizeof(double) + sizeof(int)) * BQ * (FTILE / 64);  // static, in the kernel
     if (lds + lds_queue > 160 * 1024) fail(ND_E_UNSUPPORTED, "broadened histogram does not fit in LDS");
