@@ -365,7 +365,9 @@ __global__ __launch_bounds__(TILE) void k_hist_broad_bwd(BackArgs a)
                     plo = phi_hi;
                 }
             }
-            const double c = (double)dLdr * a.inv_sigma / r;
+            // 1/r from the FP32 reciprocal: relative error ~1e-7, far below
+            // the gradient's FP32 pair weights
+            const double c = (double)dLdr * a.inv_sigma * (double)__builtin_amdgcn_rcpf((float)r);
             gx += c * dx;
             gy += c * dy;
             gz += c * dz;
