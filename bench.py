@@ -157,8 +157,8 @@ def main():
                          "kernel of known size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the pair-sum path runs on a single MI355X here; "
-              "see DESIGN.md for how it would shard", file=sys.stderr)
+        print("bench.py measures one GPU only: the pair-sum path runs on a single MI355X; "
+              "a run over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

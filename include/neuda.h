@@ -52,7 +52,7 @@ typedef int32_t nd_status;
 #define ND_E_OOM (-3)         /* device allocation failed                        */
 #define ND_E_HIP (-4)         /* HIP runtime or kernel launch failure            */
 #define ND_E_STATE (-5)       /* call not valid in the box's state (no tables)   */
-#define ND_E_UNSUPPORTED (-6) /* valid request this build does not implement     */
+#define ND_E_UNSUPPORTED (-6) /* valid request the library does not implement    */
 
 #define ND_HOST 0
 #define ND_DEVICE 1
