@@ -91,6 +91,8 @@ struct ProposeArgs {
     nd::Trial *trials;
     float4 *spheres;
     int32_t *slab;  // [N_SLAB] counts (zero beforehand), then [N_SLAB][kcap] trial lists
+    int4 *head;     // [kb] unit, first atom, atoms, 0 of each trial (compact copy for the decision)
+    double *hthr;   // [kb] acceptance threshold of each trial (compact copy)
 };
 
 // Threshold form of the Metropolis test: with u > 0, u < exp(-dE/kT)
@@ -124,6 +126,8 @@ __device__ __forceinline__ void propose_one(const ProposeArgs &a, int k)
     T->na = na;
     T->pad = 0;
     T->thr = accept_threshold(draw(a.seed, t, 6), a.kT);
+    a.head[k] = make_int4(u, a0, na, 0);
+    a.hthr[k] = T->thr;
 
     // centroid of the unit unwrapped around its first atom, rotation
     double x0[3] = {0.0, 0.0, 0.0}, cen[3] = {0.0, 0.0, 0.0};
@@ -990,6 +994,8 @@ struct DecideArgs {
     const float4 *sref;
     float *drift;
     int32_t *slab_cnt;  // [N_SLAB] slab counts of this batch's buffer, cleared here
+    const int4 *head;   // [kb] unit, first atom, atoms of each trial
+    const double *hthr; // [kb] acceptance thresholds
     int N, kb, max_na;
     double kT, tie_rel;
     long long *counters;  // [0] accepted, [1] near ties
@@ -1120,9 +1126,8 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                 n[h] = ldg(a.corr_n + k);
                 ptr[h] = ldg(a.corr_ptr + k);
                 e0[h] = ldg(a.dE0 + k);
-                const nd::Trial &T = a.trials[k];
-                ids[h] = ld_i4(reinterpret_cast<const int4 *>(&T.unit));
-                thr_k[h] = ldg(&T.thr);
+                ids[h] = ld_i4(a.head + k);  // compact per-trial copies: coalesced loads
+                thr_k[h] = ldg(a.hthr + k);
                 S[h] = ldg(a.S0 + k) + (double)ldg(a.corr_s + k);
                 blh[h] = ld_d2(a.corr_b + 2 * k);
                 bmc[h] = ld_d2(a.corr_b + 2 * k + 1);
@@ -1530,6 +1535,8 @@ void ensure_work(nd_box *b, int K, int n_jb)
     ND_HIP(hipStreamSynchronize(b->stream));
     nd::dfree(w.trials);
     nd::dfree(w.spheres);
+    nd::dfree(w.head);
+    nd::dfree(w.hthr);
     nd::dfree(w.partial);
     nd::dfree(w.dE0);
     nd::dfree(w.S0);
@@ -1552,6 +1559,8 @@ void ensure_work(nd_box *b, int K, int n_jb)
     // two trial buffers: the batch being decided and the next one
     w.trials = static_cast<nd::Trial *>(nd::dmalloc(sizeof(nd::Trial) * 2 * K));
     w.spheres = static_cast<float4 *>(nd::dmalloc(sizeof(float4) * 2 * K));
+    w.head = static_cast<int4 *>(nd::dmalloc(sizeof(int4) * 2 * K));
+    w.hthr = static_cast<double *>(nd::dmalloc(sizeof(double) * 2 * K));
     w.partial = static_cast<double *>(nd::dmalloc(sizeof(double) * 2 * (size_t)n_jb * K));
     // by buffer: the final sums of a batch read them beside the next batch's scan
     w.dE0 = static_cast<double *>(nd::dmalloc(sizeof(double) * 2 * K));
@@ -1674,6 +1683,8 @@ ProposeArgs proposal_args(const nd_box *b, const nd_mc_params *p, uint64_t seed,
     pa.spheres = w.spheres + (size_t)buf * K;
     pa.kcap = w.cap_k;
     pa.slab = slab_buffer(b, buf);
+    pa.head = w.head + (size_t)buf * K;
+    pa.hthr = w.hthr + (size_t)buf * K;
     return pa;
 }
 
@@ -1728,6 +1739,9 @@ DecideArgs decide_args(const nd_box *b, const nd_mc_params *p, const McConsts &k
     da.sref = cells_live ? b->cells.sref : nullptr;
     da.drift = cells_live ? b->cells.drift : nullptr;
     da.slab_cnt = slab_buffer(b, buf);
+    // the compact copies sit at the trial records' own offset (buffer x K)
+    da.head = w.head + (trials - w.trials);
+    da.hthr = w.hthr + (trials - w.trials);
     da.N = b->N;
     da.max_na = b->max_na;
     da.kb = kb;

@@ -295,6 +295,8 @@ static void free_box(nd_box *b)
     nd::dfree(b->mc.corr_s);
     nd::dfree(b->mc.corr_b);
     nd::dfree(b->mc.spheres);
+    nd::dfree(b->mc.head);
+    nd::dfree(b->mc.hthr);
     nd::dfree(b->mc.dE0);
     nd::dfree(b->mc.S0);
     nd::dfree(b->mc.thr);

@@ -54,6 +54,8 @@ struct McWork {
     size_t cap_pool = 0;
     Trial *trials = nullptr;      // [2][cap_k] batch being decided, next batch
     float4 *spheres = nullptr;    // [2][cap_k] bounding sphere of each trial (fractional)
+    int4 *head = nullptr;         // [2][cap_k] unit, first atom, atoms of each trial (compact)
+    double *hthr = nullptr;       // [2][cap_k] acceptance thresholds (compact)
     double *partial = nullptr;    // [cap_jb][2][cap_k]  (dE, sum |U|) per j-block (full scan)
     double *dE0 = nullptr;        // [2][cap_k] energy change against the batch-start configuration
     double *S0 = nullptr;         // [2][cap_k] sum of |U| of those pair terms
