@@ -535,12 +535,14 @@ double gauss_mass(double b, double a)
 // piece centre fc, w(f) = Phi((m+1-f) beta) - Phi((m-f) beta) and its
 // derivatives in f, w' = -beta [phi(a) - phi(b)] and w'' = beta^2 [phi'(a) -
 // phi'(b)], with a = (m+1-fc) beta, b = (m-fc) beta, phi' = -x phi.  The
-// cubic term left out, w''' d^3 / 6 with |d| <= 1/128, is odd in d: at most
-// ~1e-7 of a pair's mass in a bin, with no mean over a piece.  Returns false
-// when the table would not fit.
+// cubic term left out, w''' d^3 / 6 with |d| <= 1/128 and |w'''| <= 0.8
+// beta^3, is odd in d (no mean over a piece) and at most 6.4e-8 beta^3 of a
+// pair's mass in a bin; the table is taken for beta <= 2 (5e-7).  Returns
+// false for sharper windows or when the table would not fit.
 bool bin_mass_table(nd_box *b, double dr, double sigma, BroadArgs &a)
 {
     const double beta = dr / sigma, s = 6.0 * sigma / dr;
+    if (beta > 2.0) return false;
     const int m0 = (int)std::floor(-s) - 1, m1 = (int)std::ceil(s) + 1;
     const int nm = m1 - m0 + 1;
     const size_t bytes = sizeof(float4) * (size_t)nm * WT_NP;

@@ -334,6 +334,27 @@ def test_hist_broad_backward_matches_oracle(nd, orc):
     assert np.all(np.abs(got - want) <= 1e-5 * scale + 1e-4 * np.abs(want)), np.max(np.abs(got - want)) / scale
 
 
+@pytest.mark.parametrize("sigma", [0.006, 0.036])
+def test_hist_broad_other_widths(nd, orc, sigma):
+    # both take the forward's tail-mass path (sigma = 0.006 A: dr/sigma = 5,
+    # too sharp for the bin-mass table; 0.036 A: 6 sigma = 7.2 dr, too wide
+    # for it); at 0.006 A the backward evaluates each edge's density directly
+    # (no recurrence)
+    import torch
+    box = _broad_box()
+    dr = 0.03
+    nb = syn.n_bins_for(8.5 * (1 - 1e-6), dr)
+    g = _gbox(nd, box)
+    got = nd.hist_broad(g, dr, nb, sigma).cpu().numpy()
+    want = orc.hist_broad(box, dr, nb, sigma)
+    assert np.all(np.abs(got - want) <= 1e-6 * np.maximum(want, 1.0)), np.max(np.abs(got - want))
+    A = np.random.default_rng(3).normal(size=(3, nb))
+    gb = nd.hist_broad_backward(g, dr, nb, sigma, torch.as_tensor(A, device="cuda")).cpu().numpy()
+    wb = orc.hist_broad_backward(box, dr, nb, sigma, A)
+    scale = np.abs(wb).max()
+    assert np.all(np.abs(gb - wb) <= 1e-5 * scale + 1e-4 * np.abs(wb)), np.max(np.abs(gb - wb)) / scale
+
+
 def test_forces_match_oracle(nd, orc):
     box = syn.water_box(600, 18.0, 22, "forces")
     T = syn.water_tables(r_cut=9.0)
