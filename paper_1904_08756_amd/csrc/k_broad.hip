@@ -21,6 +21,7 @@
 #include "nd_pair.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <vector>
 
@@ -267,118 +268,229 @@ __global__ void k_reduce_f64(const double *__restrict__ partial, int G, int n, d
 }
 
 // ---------------------------------------------------------------- backward
+constexpr int BTILE = 512;  // atoms per tile of the backward: eight waves
+constexpr int BBQ = 128;    // pairs queued per wave
+
 struct BackArgs {
     const float *xyz;
     const uint8_t *sp;
     const double *A;  // [P][nbins]
-    int N, M, P, nbins;
-    double L, invL, half2;
+    int N, M, P, nbins, nt;
+    long long ntp;
+    double L, half, half2;  // half = L/2, half2 = (L/2)^2
     double dr, inv_dr, inv_sigma, six_sigma;
     float beta;       // dr / sigma
     float rho_step;   // exp(-beta^2)
     int recur;        // 1: Gaussian density by recurrence along the edges (beta <= 4)
-    int jchunk;
-    double *partial;  // [gridDim.y][3][N]
+    int kp;           // a pair's scaled term stays below 2^kp, an atom's total below 2^62
+    long long *gsum;  // [3][N] gradient in units of 2^-sh, cleared before the launch
+    int *shift;       // sh, written by block 0 (INT_MIN: the adjoint is not finite)
 };
 
-// grid (i-blocks, j-chunks): each thread owns atom i and sums over the j of
-// its chunk (j != i); no atomics, partial gradients reduced afterwards.
-__global__ __launch_bounds__(TILE) void k_hist_broad_bwd(BackArgs a)
+// Nearest integer of y for |y| < 2^51: adding 1.5 * 2^52 leaves the rounded
+// value in the low bits of the FP64 sum.
+__device__ __forceinline__ long long nearest_ll(double y)
+{
+    return __double_as_longlong(y + 6755399441055744.0) - 0x4338000000000000LL;
+}
+
+// dL/dr of one pair at distance r (r < L/2) and its gradient on both atoms:
+// dL/dr = sum_k A(k) (phi(x_k) - phi(x_{k+1})) / s with x = (e - r)/s, then
+// +c d on atom i (LDS row il of the I tile) and -c d on atom j (row jl of
+// the J tile), c = (dL/dr) / r and d = x_i - x_j, each as an integer in
+// units of 1/S.
+__device__ __forceinline__ void bwd_pair(const BackArgs &a, const float *dA, unsigned long long *gacc, double S,
+                                         double r, float dx, float dy, float dz, int row, int ij)
+{
+    int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
+    int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
+    k0 = max(k0, 0);
+    k1 = min(k1, a.nbins - 1);
+    const double u = r * a.inv_dr;
+    const int kr = (int)u;
+    const float f = (float)(u - (double)kr);
+    const float beta = a.beta;
+    const float *rowp = dA + row;
+    const float x0 = ((float)(k0 - kr) - f) * beta;
+    float plo = gauss_pdf(x0);
+    float dLdr = 0.0f;
+    if (a.recur) {
+        // phi(x + beta) = phi(x) rho, rho = exp(-beta x - beta^2/2); rho
+        // itself steps by the constant factor exp(-beta^2)
+        float rho = __builtin_amdgcn_exp2f((x0 + 0.5f * beta) * beta * -1.4426950408889634f);
+        for (int k = k0; k <= k1; ++k) {
+            const float phi_hi = plo * rho;
+            dLdr = fmaf(rowp[k], plo - phi_hi, dLdr);
+            plo = phi_hi;
+            rho *= a.rho_step;
+        }
+    } else {
+        for (int k = k0; k <= k1; ++k) {
+            const float phi_hi = gauss_pdf(((float)(k + 1 - kr) - f) * beta);
+            dLdr = fmaf(rowp[k], plo - phi_hi, dLdr);
+            plo = phi_hi;
+        }
+    }
+    // 1/r from the FP32 reciprocal: relative error ~1e-7, far below the
+    // gradient's FP32 pair weights
+    const double c = (double)dLdr * a.inv_sigma * (double)__builtin_amdgcn_rcpf((float)r);
+    const double cs = c * S;
+    const unsigned long long qx = (unsigned long long)nearest_ll(cs * (double)dx);
+    const unsigned long long qy = (unsigned long long)nearest_ll(cs * (double)dy);
+    const unsigned long long qz = (unsigned long long)nearest_ll(cs * (double)dz);
+    const int il = ij & 0xffff, jl = ij >> 16;
+    __hip_atomic_fetch_add(gacc + il, qx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(gacc + BTILE + il, qy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(gacc + 2 * BTILE + il, qz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(gacc + 3 * BTILE + jl, 0ull - qx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(gacc + 4 * BTILE + jl, 0ull - qy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(gacc + 5 * BTILE + jl, 0ull - qz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Each unordered pair once: blocks take tile pairs (I <= J) as the forward
+// does, each lane owns atom i of the I tile and tests it against the J
+// tile; the pairs inside the window range are queued per wave in LDS and
+// evaluated 64 at a time, one per lane.  A pair's gradient goes to both of
+// its atoms as integers in units of 1/S, S = 2^sh a power of two chosen from
+// max |A| so that no sum can overflow: summed in LDS per tile and added to
+// the [3][N] totals with device atomics when the tile pair is done.  Integer
+// sums: the result does not depend on the order.
+__global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    double *jx = reinterpret_cast<double *>(smem);                      // [3][TILE]
-    int *js = reinterpret_cast<int *>(jx + 3 * TILE);                  // [TILE]
-    int *prow = js + TILE;                                              // [16]
-    float *dA = reinterpret_cast<float *>(prow + 16);                  // [P*nbins]
-    const int tid = threadIdx.x;
+    unsigned long long *gacc = reinterpret_cast<unsigned long long *>(smem);  // [2][3][BTILE] I tile, J tile
+    double *jx = reinterpret_cast<double *>(gacc + 6 * BTILE);               // [3][BTILE]
+    int *js = reinterpret_cast<int *>(jx + 3 * BTILE);               // [BTILE]
+    int *prow = js + BTILE;                                           // [16]
+    float *dA = reinterpret_cast<float *>(prow + 16);                // [P*nbins]
+    __shared__ double s_qr[BTILE / 64][BBQ];
+    __shared__ float4 s_qd[BTILE / 64][BBQ];  // displacement, row offset (int bits)
+    __shared__ int s_qij[BTILE / 64][BBQ];
+    __shared__ double s_amax[BTILE / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
     const int nq = a.P * a.nbins;
     // the adjoint in FP32: each pair's dL/dr is a sum of ~10 such terms
-    // (relative error ~1e-7 of the sum of their magnitudes)
-    for (int q = tid; q < nq; q += TILE) dA[q] = (float)a.A[q];
-    if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.nbins;
-    const int N = a.N;
-    const int i = blockIdx.x * TILE + tid;
-    const bool iv = i < N;
-    double xi = 0.0, yi = 0.0, zi = 0.0;
-    int si = 0;
-    if (iv) {
-        xi = a.xyz[i];
-        yi = a.xyz[N + i];
-        zi = a.xyz[2 * N + i];
-        si = a.sp[i];
+    // (relative error ~1e-7 of the sum of their magnitudes); its largest
+    // magnitude (infinite if any entry is not finite) sets the scale
+    double amax = 0.0;
+    for (int q = tid; q < nq; q += BTILE) {
+        const double v = a.A[q];
+        dA[q] = (float)v;
+        amax = fmax(amax, v == v ? fabs(v) : HUGE_VAL);
     }
+    for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o));
+    if (lane == 0) s_amax[wave] = amax;
+    if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.nbins;
+    __syncthreads();
+    amax = s_amax[0];
+    for (int w = 1; w < BTILE / 64; ++w) amax = fmax(amax, s_amax[w]);
+    // |a pair's term| <= |dL/dr| / s <= max|A| 2 phi(0) / s < 2^e
+    const double bound = amax * a.inv_sigma;
+    const bool finite = bound <= 1.0e300;
+    const int e = finite && bound > 0.0 ? ilogb(bound) + 1 : 0;
+    const int sh = a.kp - e;
+    const double S = ldexp(1.0, sh);
+    if (blockIdx.x == 0 && tid == 0) *a.shift = finite ? sh : INT_MIN;
+    if (!finite) return;
+    const int N = a.N;
     const double rmax_win = (double)a.nbins * a.dr + a.six_sigma;
-    const float beta = a.beta;
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-    const int jbeg = blockIdx.y * a.jchunk;
-    const int jend = min(N, jbeg + a.jchunk);
-    for (int jt = jbeg; jt < jend; jt += TILE) {
-        __syncthreads();
-        const int j = jt + tid;
-        if (j < jend) {
+    double *qr = s_qr[wave];
+    float4 *qd = s_qd[wave];
+    int *qij = s_qij[wave];
+    for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
+        int I, J;
+        tri_index(t, a.nt, I, J);
+        const int i = I * BTILE + tid;
+        const bool iv = i < N;
+        double xi = 0.0, yi = 0.0, zi = 0.0;
+        int si = 0;
+        if (iv) {
+            xi = a.xyz[i];
+            yi = a.xyz[N + i];
+            zi = a.xyz[2 * N + i];
+            si = a.sp[i];
+        }
+        __syncthreads();  // the previous tile pair's sums are out
+        const int j = J * BTILE + tid;
+        if (j < N) {
             jx[tid] = a.xyz[j];
-            jx[TILE + tid] = a.xyz[N + j];
-            jx[2 * TILE + tid] = a.xyz[2 * N + j];
+            jx[BTILE + tid] = a.xyz[N + j];
+            jx[2 * BTILE + tid] = a.xyz[2 * N + j];
             js[tid] = a.sp[j];
         }
+        for (int q = tid; q < 6 * BTILE; q += BTILE) gacc[q] = 0ull;
         __syncthreads();
-        if (!iv) continue;
-        const int jn = min(TILE, jend - jt);
+        const int jn = min(BTILE, N - J * BTILE);
         const int rowbase = si * a.M;
-        for (int jj = 0; jj < jn; ++jj) {
-            if (jt + jj == i) continue;
-            double dx = xi - jx[jj], dy = yi - jx[TILE + jj], dz = zi - jx[2 * TILE + jj];
-            const double r2 = nearest_r2(dx, dy, dz, a.L);
-            if (!(r2 < a.half2) || r2 == 0.0) continue;
-            const double r = nd::sqrt_nr(r2);
-            if (!(r < rmax_win)) continue;
-            // signed nearest-image displacement x_i - x_j
-            dx = fma(-rint(dx * a.invL), a.L, dx);
-            dy = fma(-rint(dy * a.invL), a.L, dy);
-            dz = fma(-rint(dz * a.invL), a.L, dz);
-            int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
-            int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
-            k0 = max(k0, 0);
-            k1 = min(k1, a.nbins - 1);
-            const double u = r * a.inv_dr;
-            const int kr = (int)u;
-            const float f = (float)(u - (double)kr);
-            const float *row = dA + prow[rowbase + js[jj]];
-            // dL/dr = sum_k A(k) (phi(x_k) - phi(x_{k+1})) / s, x = (e - r)/s
-            const float x0 = ((float)(k0 - kr) - f) * beta;
-            float plo = gauss_pdf(x0);
-            float dLdr = 0.0f;
-            if (a.recur) {
-                // phi(x + beta) = phi(x) rho, rho = exp(-beta x - beta^2/2); rho
-                // itself steps by the constant factor exp(-beta^2)
-                float rho = __builtin_amdgcn_exp2f((x0 + 0.5f * beta) * beta * -1.4426950408889634f);
-                for (int k = k0; k <= k1; ++k) {
-                    const float phi_hi = plo * rho;
-                    dLdr = fmaf(row[k], plo - phi_hi, dLdr);
-                    plo = phi_hi;
-                    rho *= a.rho_step;
+        int nqw = 0, qh = 0;  // queued pairs of this wave, first slot of the ring
+        // the J tile in blocks of 64, each walked along its diagonals: at
+        // step st lane l takes j = jb + (l + st) mod 64, so the pairs of one
+        // step have distinct i and distinct j and the sums of a batch of 64
+        // queued pairs meet at most two to an address
+        for (int jb = 0; jb < jn; jb += 64) {
+            for (int st = 0; st < 64; ++st) {
+                const int jj = jb + ((lane + st) & 63);
+                const double dx = xi - jx[jj], dy = yi - jx[BTILE + jj], dz = zi - jx[2 * BTILE + jj];
+                const double r2 = nearest_r2(dx, dy, dz, a.L);
+                // coincident atoms (r = 0) have no direction and are left out
+                bool in = iv && jj < jn && (I != J || jj > tid) && r2 < a.half2 && r2 > 0.0;
+                const double r = nd::sqrt_nr(in ? r2 : 1.0);
+                in = in && r < rmax_win;
+                const unsigned long long bal = __ballot(in);
+                if (in) {
+                    const int q = (qh + nqw + __popcll(bal & lt)) & (BBQ - 1);
+                    qr[q] = r;
+                    // signed nearest-image displacement x_i - x_j
+                    qd[q] = make_float4((float)(fabs(dx) <= a.half ? dx : dx - copysign(a.L, dx)),
+                                        (float)(fabs(dy) <= a.half ? dy : dy - copysign(a.L, dy)),
+                                        (float)(fabs(dz) <= a.half ? dz : dz - copysign(a.L, dz)),
+                                        __int_as_float(prow[rowbase + js[jj]]));
+                    qij[q] = tid | (jj << 16);
                 }
-            } else {
-                for (int k = k0; k <= k1; ++k) {
-                    const float phi_hi = gauss_pdf(((float)(k + 1 - kr) - f) * beta);
-                    dLdr = fmaf(row[k], plo - phi_hi, dLdr);
-                    plo = phi_hi;
+                nqw += __popcll(bal);
+                if (nqw >= 64) {
+                    __builtin_amdgcn_wave_barrier();
+                    const int q = (qh + lane) & (BBQ - 1);
+                    const double rq = qr[q];
+                    const float4 e = qd[q];
+                    const int ijq = qij[q];
+                    qh = (qh + 64) & (BBQ - 1);
+                    nqw -= 64;
+                    __builtin_amdgcn_wave_barrier();
+                    bwd_pair(a, dA, gacc, S, rq, e.x, e.y, e.z, __float_as_int(e.w), ijq);
                 }
             }
-            // 1/r from the FP32 reciprocal: relative error ~1e-7, far below
-            // the gradient's FP32 pair weights
-            const double c = (double)dLdr * a.inv_sigma * (double)__builtin_amdgcn_rcpf((float)r);
-            gx += c * dx;
-            gy += c * dy;
-            gz += c * dz;
         }
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nqw) {
+            const int q = (qh + lane) & (BBQ - 1);
+            const float4 e = qd[q];
+            bwd_pair(a, dA, gacc, S, qr[q], e.x, e.y, e.z, __float_as_int(e.w), qij[q]);
+        }
+        __syncthreads();
+        unsigned long long *gs = reinterpret_cast<unsigned long long *>(a.gsum);
+        if (iv)
+            for (int c = 0; c < 3; ++c) atomicAdd(gs + (size_t)c * N + i, gacc[c * BTILE + tid]);
+        if (j < N)
+            for (int c = 0; c < 3; ++c) atomicAdd(gs + (size_t)c * N + j, gacc[(3 + c) * BTILE + tid]);
     }
-    if (iv) {
-        double *out = a.partial + (size_t)blockIdx.y * 3 * N;
-        out[i] = gx;
-        out[N + i] = gy;
-        out[2 * N + i] = gz;
-    }
+}
+
+// The integer totals back to FP64 (NaN where the adjoint was not finite).
+__global__ void k_fixed_to_f64(const long long *__restrict__ v, long long n, const int *__restrict__ shift,
+                               double *__restrict__ out)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int sh = *shift;
+    out[q] = sh == INT_MIN ? __builtin_nan("") : ldexp((double)v[q], -sh);
+}
+
+__global__ void k_fill_zero_f64(double *__restrict__ p, long long n)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) p[q] = 0.0;
 }
 
 // ---------------------------------------------------------------- forces
@@ -638,8 +750,10 @@ void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, c
     a.M = b->M;
     a.P = b->P;
     a.nbins = nbins;
+    a.nt = (b->N + BTILE - 1) / BTILE;
+    a.ntp = (long long)a.nt * (a.nt + 1) / 2;
     a.L = b->L;
-    a.invL = 1.0 / b->L;
+    a.half = 0.5 * b->L;
     a.half2 = 0.25 * b->L * b->L;
     a.dr = dr;
     a.inv_dr = 1.0 / dr;
@@ -649,19 +763,33 @@ void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, c
     a.rho_step = (float)std::exp(-(dr / sigma) * (dr / sigma));
     // the first step factor exp(beta (6 + beta/2 + 1)) stays far inside FP32 range
     a.recur = dr / sigma <= 4.0 ? 1 : 0;
-    const int nch = n_jchunks(b);
-    a.jchunk = (b->N + nch - 1) / nch;
-    const int nib = (b->N + TILE - 1) / TILE;
-    size_t lds = sizeof(double) * 3 * TILE + sizeof(int) * (TILE + 16) + sizeof(float) * (size_t)b->P * nbins;
-    if (lds > 160 * 1024) fail(ND_E_UNSUPPORTED, "adjoint table does not fit in LDS");
-    a.partial = static_cast<double *>(workspace(b, sizeof(double) * (size_t)nch * 3 * b->N));
+    // a pair's term below 2^kp, so that the N - 1 terms of an atom stay
+    // below 2^62 and nearest_ll stays exact
+    int lg = 0;
+    while ((1LL << lg) < (long long)b->N) ++lg;
+    a.kp = std::min(51, 62 - lg);
+    // summed in the box's workspace, then converted into the caller's array
+    char *ws = static_cast<char *>(workspace(b, sizeof(long long) * 3 * (size_t)b->N + 256));
+    a.gsum = reinterpret_cast<long long *>(ws);
+    a.shift = reinterpret_cast<int *>(ws + sizeof(long long) * 3 * (size_t)b->N);
+    const size_t lds = sizeof(double) * 9 * BTILE + sizeof(int) * (BTILE + 16) + sizeof(float) * (size_t)b->P * nbins;
+    const size_t lds_queue = (sizeof(double) + sizeof(float4) + sizeof(int)) * BBQ * (BTILE / 64) +
+                             sizeof(double) * (BTILE / 64);  // static
+    if (lds + lds_queue > 160 * 1024) fail(ND_E_UNSUPPORTED, "adjoint table does not fit in LDS");
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (lds + lds_queue + 1024)));
+    long long G = (long long)cu_count(b->device) * per_cu;
+    if (G > a.ntp) G = a.ntp;
+    const long long n = 3LL * b->N;
+    hipLaunchKernelGGL(k_fill_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream,
+                       reinterpret_cast<double *>(a.gsum), n);
+    ND_HIP(hipGetLastError());
     {
         ProfScope ps(b, ND_PROF_HIST_BROAD_BWD);
-        hipLaunchKernelGGL(k_hist_broad_bwd, dim3(nib, nch), dim3(TILE), lds, b->stream, a);
+        hipLaunchKernelGGL(k_hist_broad_bwd, dim3((unsigned)G), dim3(BTILE), lds, b->stream, a);
         ND_HIP(hipGetLastError());
     }
-    const int n = 3 * b->N;
-    hipLaunchKernelGGL(k_reduce_f64, dim3((n + 255) / 256), dim3(256), 0, b->stream, a.partial, nch, n, d_grad);
+    hipLaunchKernelGGL(k_fixed_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream, a.gsum, n, a.shift,
+                       d_grad);
     ND_HIP(hipGetLastError());
 }
 
