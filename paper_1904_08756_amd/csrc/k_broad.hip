@@ -112,8 +112,9 @@ constexpr int FTILE = 512;  // atoms per tile of the forward: eight waves share 
 // bin-mass table: one entry per bin of the window, the value (hi + lo,
 // summed in FP64) plus the FP32 Taylor terms (at most a few 1e-3), in units
 // of 2^-32.  Bins past the table (masses below 1e-13) are left out.
-__device__ __forceinline__ void broad_pair_tab(const BroadArgs &a, const float4 *t, unsigned long long *h, double r)
+__device__ __forceinline__ void broad_pair_tab(const BroadArgs &a, const float4 *t, unsigned long long *h, double r2)
 {
+    const double r = nd::sqrt_nr(r2);
     int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
     int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
     k0 = max(k0, 0);
@@ -123,13 +124,26 @@ __device__ __forceinline__ void broad_pair_tab(const BroadArgs &a, const float4 
     const float f = (float)(u - (double)kr);
     const int pc = min((int)(f * (float)WT_NP), WT_NP - 1);
     const float d = f - ((float)pc + 0.5f) * (1.0f / WT_NP);
-    for (int k = k0; k <= k1; ++k) {
-        const int mi = k - kr - a.wt_m0;
-        if ((unsigned)mi >= (unsigned)a.wt_nm) continue;
-        const float4 c = t[mi * WT_NP + pc];
-        const double w = (double)c.x + ((double)c.y + (double)(d * fmaf(d, c.w, c.z)));
-        atomicAdd(&h[k], (unsigned long long)__double2uint_rn(w * 4294967296.0));
+    // offsets k - kr stay inside the table's range (it has a bin of margin
+    // on each side); the clamps only guard that
+    int m = k0 - kr - a.wt_m0;
+    if (m < 0) {
+        k0 -= m;
+        m = 0;
     }
+    k1 = min(k1, k0 + (a.wt_nm - 1 - m));
+    const float4 *tp = t + m * WT_NP + pc;
+    auto bin = [&](const float4 c) {
+        const double w = (double)c.x + ((double)c.y + (double)(d * fmaf(d, c.w, c.z)));
+        return (unsigned long long)__double2uint_rn(w * 4294967296.0);
+    };
+    int k = k0;
+    for (; k < k1; k += 2, tp += 2 * WT_NP) {
+        const float4 c0 = tp[0], c1 = tp[WT_NP];
+        atomicAdd(&h[k], bin(c0));
+        atomicAdd(&h[k + 1], bin(c1));
+    }
+    if (k == k1) atomicAdd(&h[k], bin(tp[0]));
 }
 
 // The window of one pair at distance r (r < L/2) into the u64 row h: bin
@@ -137,8 +151,9 @@ __device__ __forceinline__ void broad_pair_tab(const BroadArgs &a, const float4 
 // edge's density is evaluated directly: a recurrence along the window would
 // raise the rounding of its first factor to the power of the step count,
 // which biases every pair's far bins alike.
-__device__ __forceinline__ void broad_pair(const BroadArgs &a, const float4 *mills, unsigned long long *h, double r)
+__device__ __forceinline__ void broad_pair(const BroadArgs &a, const float4 *mills, unsigned long long *h, double r2)
 {
+    const double r = nd::sqrt_nr(r2);
     int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
     int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
     k0 = max(k0, 0);
@@ -188,9 +203,10 @@ __global__ __launch_bounds__(FTILE) void k_hist_broad(BroadArgs a)
     __syncthreads();
     const int N = a.N;
     const double rmax_win = (double)a.nbins * a.dr + a.six_sigma;
-    double *qr = s_qr[wave];
+    const double rwin2 = rmax_win * rmax_win;
+    double *qr = s_qr[wave];  // r^2 of the queued pairs (a ring of BQ)
     int *qrow = s_qrow[wave];
-    int nqw = 0;  // queued pairs of this wave
+    int nqw = 0, qh = 0;  // queued pairs of this wave, first slot of the ring
     for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
         int I, J;
         tri_index(t, a.nt, I, J);
@@ -218,25 +234,20 @@ __global__ __launch_bounds__(FTILE) void k_hist_broad(BroadArgs a)
         const int rowbase = si * a.M;
         for (int jj = 0; jj < jn; ++jj) {
             const double r2 = nearest_r2(jx[jj] - xi, jx[FTILE + jj] - yi, jx[2 * FTILE + jj] - zi, a.L);
-            bool in = iv && jj >= jstart && r2 < a.half2;
-            const double r = nd::sqrt_nr(in ? r2 : 1.0);
-            in = in && r < rmax_win;
+            const bool in = iv && jj >= jstart && r2 < a.half2 && r2 < rwin2;
             const unsigned long long bal = __ballot(in);
             if (in) {
-                const int q = nqw + __popcll(bal & lt);
-                qr[q] = r;
+                const int q = (qh + nqw + __popcll(bal & lt)) & (BQ - 1);
+                qr[q] = r2;
                 qrow[q] = prow[rowbase + js[jj]];
             }
             nqw += __popcll(bal);
             if (nqw >= 64) {
                 __builtin_amdgcn_wave_barrier();
-                const double rq = qr[lane];
-                const int rowq = qrow[lane];
-                __builtin_amdgcn_wave_barrier();
-                if (lane < nqw - 64) {
-                    qr[lane] = qr[64 + lane];
-                    qrow[lane] = qrow[64 + lane];
-                }
+                const int q = (qh + lane) & (BQ - 1);
+                const double rq = qr[q];
+                const int rowq = qrow[q];
+                qh = (qh + 64) & (BQ - 1);
                 nqw -= 64;
                 __builtin_amdgcn_wave_barrier();
                 if (TAB)
@@ -248,10 +259,11 @@ __global__ __launch_bounds__(FTILE) void k_hist_broad(BroadArgs a)
     }
     __builtin_amdgcn_wave_barrier();
     if (lane < nqw) {
+        const int q = (qh + lane) & (BQ - 1);
         if (TAB)
-            broad_pair_tab(a, tab, hist + qrow[lane], qr[lane]);
+            broad_pair_tab(a, tab, hist + qrow[q], qr[q]);
         else
-            broad_pair(a, tab, hist + qrow[lane], qr[lane]);
+            broad_pair(a, tab, hist + qrow[q], qr[q]);
     }
     __syncthreads();
     double *out = a.partial + (size_t)blockIdx.x * nq;
