@@ -312,8 +312,9 @@ __device__ __forceinline__ long long nearest_ll(double y)
 // the J tile), c = (dL/dr) / r and d = x_i - x_j, each as an integer in
 // units of 1/S.
 __device__ __forceinline__ void bwd_pair(const BackArgs &a, const float *dA, unsigned long long *gacc, double S,
-                                         double r, float dx, float dy, float dz, int row, int ij)
+                                         double r2, float dx, float dy, float dz, int row, int ij)
 {
+    const double r = nd::sqrt_nr(r2);
     int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
     int k1 = (int)floor((r + a.six_sigma) * a.inv_dr);
     k0 = max(k0, 0);
@@ -328,14 +329,21 @@ __device__ __forceinline__ void bwd_pair(const BackArgs &a, const float *dA, uns
     float dLdr = 0.0f;
     if (a.recur) {
         // phi(x + beta) = phi(x) rho, rho = exp(-beta x - beta^2/2); rho
-        // itself steps by the constant factor exp(-beta^2)
+        // itself steps by the constant factor exp(-beta^2); two bins a trip
         float rho = __builtin_amdgcn_exp2f((x0 + 0.5f * beta) * beta * -1.4426950408889634f);
-        for (int k = k0; k <= k1; ++k) {
-            const float phi_hi = plo * rho;
-            dLdr = fmaf(rowp[k], plo - phi_hi, dLdr);
-            plo = phi_hi;
-            rho *= a.rho_step;
+        const float step = a.rho_step;
+        int k = k0;
+        for (; k < k1; k += 2) {
+            const float A0 = rowp[k], A1 = rowp[k + 1];
+            const float p1 = plo * rho;
+            rho *= step;
+            const float p2 = p1 * rho;
+            rho *= step;
+            dLdr = fmaf(A0, plo - p1, dLdr);
+            dLdr = fmaf(A1, p1 - p2, dLdr);
+            plo = p2;
         }
+        if (k == k1) dLdr = fmaf(rowp[k], plo - plo * rho, dLdr);
     } else {
         for (int k = k0; k <= k1; ++k) {
             const float phi_hi = gauss_pdf(((float)(k + 1 - kr) - f) * beta);
@@ -407,7 +415,8 @@ __global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
     if (!finite) return;
     const int N = a.N;
     const double rmax_win = (double)a.nbins * a.dr + a.six_sigma;
-    double *qr = s_qr[wave];
+    const double rwin2 = rmax_win * rmax_win;
+    double *qr = s_qr[wave];  // r^2 of the queued pairs
     float4 *qd = s_qd[wave];
     int *qij = s_qij[wave];
     for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
@@ -446,13 +455,11 @@ __global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
                 const double dx = xi - jx[jj], dy = yi - jx[BTILE + jj], dz = zi - jx[2 * BTILE + jj];
                 const double r2 = nearest_r2(dx, dy, dz, a.L);
                 // coincident atoms (r = 0) have no direction and are left out
-                bool in = iv && jj < jn && (I != J || jj > tid) && r2 < a.half2 && r2 > 0.0;
-                const double r = nd::sqrt_nr(in ? r2 : 1.0);
-                in = in && r < rmax_win;
+                const bool in = iv && jj < jn && (I != J || jj > tid) && r2 < a.half2 && r2 < rwin2 && r2 > 0.0;
                 const unsigned long long bal = __ballot(in);
                 if (in) {
                     const int q = (qh + nqw + __popcll(bal & lt)) & (BBQ - 1);
-                    qr[q] = r;
+                    qr[q] = r2;
                     // signed nearest-image displacement x_i - x_j
                     qd[q] = make_float4((float)(fabs(dx) <= a.half ? dx : dx - copysign(a.L, dx)),
                                         (float)(fabs(dy) <= a.half ? dy : dy - copysign(a.L, dy)),
