@@ -240,13 +240,20 @@ nd_status nd_sq_adjoint(const double *dLdS, int32_t P, int32_t nbins, double dr,
 
 /* Backward of nd_hist_broad: given A = dL/dnhat (double [P][nbins]), writes
  * dL/dx (double [3][N]) = sum over pairs of dL/dr (x_i - x_j)/r with
- * dL/dr = sum_k A_p(k) (phi((e_k - r)/sigma) - phi((e_{k+1} - r)/sigma))/sigma. */
+ * dL/dr = sum_k A_p(k) (phi((e_k - r)/sigma) - phi((e_{k+1} - r)/sigma))/sigma
+ * (coincident atoms, r = 0, contribute nothing).  The pair terms are summed
+ * as integers in units of a power of two set by max |A|, so the result does
+ * not depend on the order of the sums (repeated calls agree bit for bit);
+ * if A holds a NaN or an infinity every output is NaN. */
 nd_status nd_hist_broad_backward(nd_box *box, double dr, int32_t nbins, double sigma,
                                  const double *A, double *dLdx, int32_t where);
 
 /* Energy gradient dE/dx (double [3][N]) over pairs in different units with
  * r < r_cut, using the slope of the interpolated table, and the total
- * energy E (host double, may be NULL). */
+ * energy E (host double, may be NULL).  The gradient's pair terms are summed
+ * as integers in units of a power of two set by the table's steepest step
+ * and the energy in a fixed order, so repeated calls agree bit for bit; a
+ * table holding a NaN or an infinity gives NaN everywhere. */
 nd_status nd_forces(nd_box *box, double *dEdx, double *E, int32_t where);
 
 /* Checkpoint of a box's Metropolis state: coordinates, running energy and

@@ -27,7 +27,6 @@
 
 namespace {
 
-constexpr int TILE = 256;
 constexpr int MILLS_PER_UNIT = 32;                   // table points per unit of x
 constexpr float MILLS_XMAX = 8.0f;
 constexpr int MILLS_N = 8 * MILLS_PER_UNIT + 1;      // points 0, 1/32, ..., 8
@@ -513,93 +512,180 @@ __global__ void k_fill_zero_f64(double *__restrict__ p, long long n)
 }
 
 // ---------------------------------------------------------------- forces
+constexpr int GTILE = 256;  // atoms per tile of the forces: four waves
+constexpr int GQ = 128;     // pairs queued per wave
+
 struct ForceArgs {
     const float *xyz;
     const uint8_t *sp;
     const int32_t *unit_of;
     const float *tab;
-    int N, M, n_pts;
-    double L, invL, rc2, inv_h;
-    int jchunk;
-    double *partial;   // [gridDim.y][3][N]
-    double *epart;     // [gridDim.y][gridDim.x]
+    int N, M, P, n_pts, nt;
+    long long ntp;
+    double L, invL, half2, rc2, inv_h;
+    int kp;           // a pair's scaled term stays below 2^kp, an atom's total below 2^62
+    long long *gsum;  // [3][N] gradient in units of 2^-sh, cleared before the launch
+    int *shift;       // sh, written by block 0 (INT_MIN: the table is not finite)
+    double *epart;    // [gridDim.x] energy of each block's pairs
 };
 
-__global__ __launch_bounds__(TILE) void k_forces(ForceArgs a)
+// One queued pair within the cutoff: the tabulated U(r) (linear between
+// points) into e, and +dU/dr (x_i - x_j)/r on atom i, the negative on atom
+// j, as integers in units of 1/S.  The displacement is taken again in FP64
+// from the tiles' coordinates.
+__device__ __forceinline__ void force_pair(const ForceArgs &a, const float *tab, const double *ix, const double *jx,
+                                           unsigned long long *gacc, double S, double r2, int row, int ij,
+                                           double &e)
+{
+    const int il = ij & 0xffff, jl = ij >> 16;
+    double dx = ix[il] - jx[jl], dy = ix[GTILE + il] - jx[GTILE + jl], dz = ix[2 * GTILE + il] - jx[2 * GTILE + jl];
+    dx = fma(-rint(dx * a.invL), a.L, dx);
+    dy = fma(-rint(dy * a.invL), a.L, dy);
+    dz = fma(-rint(dz * a.invL), a.L, dz);
+    const double r = sqrt(r2);
+    const double t = r * a.inv_h;
+    const int i0 = min((int)t, a.n_pts - 2);
+    const float *rowp = tab + row;
+    const double u0 = rowp[i0], u1 = rowp[i0 + 1];
+    const double slope = (u1 - u0) * a.inv_h;
+    const double f = t - (double)i0;
+    e += u0 + f * (u1 - u0);
+    const double cs = slope / r * S;
+    const unsigned long long qx = (unsigned long long)nearest_ll(cs * dx);
+    const unsigned long long qy = (unsigned long long)nearest_ll(cs * dy);
+    const unsigned long long qz = (unsigned long long)nearest_ll(cs * dz);
+    __hip_atomic_fetch_add(gacc + il, qx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(gacc + GTILE + il, qy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(gacc + 2 * GTILE + il, qz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(gacc + 3 * GTILE + jl, 0ull - qx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(gacc + 4 * GTILE + jl, 0ull - qy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(gacc + 5 * GTILE + jl, 0ull - qz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Gradient of the tabulated total energy and the energy itself, each
+// unordered pair of different units once: tile pairs I <= J as in the
+// broadened backward, the J tile walked along its diagonals, the pairs
+// within the cutoff queued per wave and evaluated 64 at a time.  Gradient
+// sums are integers in units of 1/S, S = 2^sh chosen from the table's
+// steepest step so that no sum can overflow (the result does not depend on
+// the order); the energy is summed per lane in queue order, per block,
+// then over blocks in block order.
+__global__ __launch_bounds__(GTILE) void k_forces(ForceArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    float *tab = reinterpret_cast<float *>(smem);                          // [P][n_pts]
-    const int P = a.M * (a.M + 1) / 2;
-    double *jx = reinterpret_cast<double *>(tab + ((P * a.n_pts + 3) & ~3)); // [3][TILE]
-    int *ju = reinterpret_cast<int *>(jx + 3 * TILE);                      // [TILE]
-    int *js = ju + TILE;                                                    // [TILE]
-    int *prow = js + TILE;                                                  // [16]
-    __shared__ double red[TILE / 64];
-    const int tid = threadIdx.x;
-    nd::stage_floats<TILE>(tab, a.tab, P * a.n_pts);
-    if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
-    const int N = a.N;
-    const int i = blockIdx.x * TILE + tid;
-    const bool iv = i < N;
-    double xi = 0.0, yi = 0.0, zi = 0.0;
-    int si = 0, ui = -1;
-    if (iv) {
-        xi = a.xyz[i];
-        yi = a.xyz[N + i];
-        zi = a.xyz[2 * N + i];
-        si = a.sp[i];
-        ui = a.unit_of[i];
-    }
-    double gx = 0.0, gy = 0.0, gz = 0.0, e = 0.0;
-    const int jbeg = blockIdx.y * a.jchunk;
-    const int jend = min(N, jbeg + a.jchunk);
-    for (int jt = jbeg; jt < jend; jt += TILE) {
-        __syncthreads();
-        const int j = jt + tid;
-        if (j < jend) {
-            jx[tid] = a.xyz[j];
-            jx[TILE + tid] = a.xyz[N + j];
-            jx[2 * TILE + tid] = a.xyz[2 * N + j];
-            ju[tid] = a.unit_of[j];
-            js[tid] = a.sp[j];
+    unsigned long long *gacc = reinterpret_cast<unsigned long long *>(smem);  // [2][3][GTILE] I tile, J tile
+    double *ix = reinterpret_cast<double *>(gacc + 6 * GTILE);                // [3][GTILE]
+    double *jx = ix + 3 * GTILE;                                                // [3][GTILE]
+    int *js = reinterpret_cast<int *>(jx + 3 * GTILE);                       // [GTILE]
+    int *ju = js + GTILE;                                                       // [GTILE]
+    int *prow = ju + GTILE;                                                     // [16]
+    float *tab = reinterpret_cast<float *>(prow + 16);                        // [P][n_pts]
+    __shared__ double s_qr[GTILE / 64][GQ];
+    __shared__ int s_qrow[GTILE / 64][GQ];
+    __shared__ int s_qij[GTILE / 64][GQ];
+    __shared__ double s_red[GTILE / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    // the tables, and their steepest step (infinite if any value is not finite)
+    const int ntab = a.P * a.n_pts;
+    double smax = 0.0;
+    for (int q = tid; q < ntab; q += GTILE) {
+        const float v = a.tab[q];
+        tab[q] = v;
+        if (q % a.n_pts != a.n_pts - 1) {
+            const double s = fabs(((double)a.tab[q + 1] - (double)v) * a.inv_h);
+            smax = fmax(smax, s == s ? s : HUGE_VAL);
         }
+    }
+    for (int o = 32; o > 0; o >>= 1) smax = fmax(smax, __shfl_xor(smax, o));
+    if (lane == 0) s_red[wave] = smax;
+    if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
+    __syncthreads();
+    smax = s_red[0];
+    for (int w = 1; w < GTILE / 64; ++w) smax = fmax(smax, s_red[w]);
+    // |a pair's term| <= |dU/dr| <= smax < 2^e
+    const bool finite = smax <= 1.0e300;
+    const int e2 = finite && smax > 0.0 ? ilogb(smax) + 1 : 0;
+    const int sh = a.kp - e2;
+    const double S = ldexp(1.0, sh);
+    if (blockIdx.x == 0 && tid == 0) *a.shift = finite ? sh : INT_MIN;
+    const int N = a.N;
+    double *qr = s_qr[wave];
+    int *qrow = s_qrow[wave], *qij = s_qij[wave];
+    double e = 0.0;
+    for (long long t = finite ? blockIdx.x : a.ntp; t < a.ntp; t += gridDim.x) {
+        int I, J;
+        tri_index(t, a.nt, I, J);
+        const int i = I * GTILE + tid;
+        const bool iv = i < N;
+        double xi = 0.0, yi = 0.0, zi = 0.0;
+        int si = 0, ui = -1;
+        if (iv) {
+            xi = a.xyz[i];
+            yi = a.xyz[N + i];
+            zi = a.xyz[2 * N + i];
+            si = a.sp[i];
+            ui = a.unit_of[i];
+        }
+        __syncthreads();  // the previous tile pair's sums are out
+        ix[tid] = xi;
+        ix[GTILE + tid] = yi;
+        ix[2 * GTILE + tid] = zi;
+        const int j = J * GTILE + tid;
+        if (j < N) {
+            jx[tid] = a.xyz[j];
+            jx[GTILE + tid] = a.xyz[N + j];
+            jx[2 * GTILE + tid] = a.xyz[2 * N + j];
+            js[tid] = a.sp[j];
+            ju[tid] = a.unit_of[j];
+        }
+        for (int q = tid; q < 6 * GTILE; q += GTILE) gacc[q] = 0ull;
         __syncthreads();
-        if (!iv) continue;
-        const int jn = min(TILE, jend - jt);
+        const int jn = min(GTILE, N - J * GTILE);
         const int rowbase = si * a.M;
-        for (int jj = 0; jj < jn; ++jj) {
-            double dx = xi - jx[jj], dy = yi - jx[TILE + jj], dz = zi - jx[2 * TILE + jj];
-            dx = fma(-rint(dx * a.invL), a.L, dx);
-            dy = fma(-rint(dy * a.invL), a.L, dy);
-            dz = fma(-rint(dz * a.invL), a.L, dz);
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            if (r2 < a.rc2 && r2 > 0.0 && ju[jj] != ui) {
-                const double r = sqrt(r2);
-                const double t = r * a.inv_h;
-                int i0 = (int)t;
-                i0 = min(i0, a.n_pts - 2);
-                const float *row = tab + prow[rowbase + js[jj]];
-                const double u0 = row[i0], u1 = row[i0 + 1];
-                const double slope = (u1 - u0) * a.inv_h;
-                const double f = t - (double)i0;
-                e += 0.5 * (u0 + f * (u1 - u0));
-                const double c = slope / r;
-                gx += c * dx;
-                gy += c * dy;
-                gz += c * dz;
+        int nqw = 0, qh = 0;  // queued pairs of this wave, first slot of the ring
+        for (int jb = 0; jb < jn; jb += 64) {
+            for (int st = 0; st < 64; ++st) {
+                const int jj = jb + ((lane + st) & 63);
+                const double r2 = nearest_r2(xi - jx[jj], yi - jx[GTILE + jj], zi - jx[2 * GTILE + jj], a.L);
+                const bool in = iv && jj < jn && (I != J || jj > tid) && r2 < a.rc2 && r2 > 0.0 && ju[jj] != ui;
+                const unsigned long long bal = __ballot(in);
+                if (in) {
+                    const int q = (qh + nqw + __popcll(bal & lt)) & (GQ - 1);
+                    qr[q] = r2;
+                    qrow[q] = prow[rowbase + js[jj]];
+                    qij[q] = tid | (jj << 16);
+                }
+                nqw += __popcll(bal);
+                if (nqw >= 64) {
+                    __builtin_amdgcn_wave_barrier();
+                    const int q = (qh + lane) & (GQ - 1);
+                    const double rq = qr[q];
+                    const int rowq = qrow[q], ijq = qij[q];
+                    qh = (qh + 64) & (GQ - 1);
+                    nqw -= 64;
+                    __builtin_amdgcn_wave_barrier();
+                    force_pair(a, tab, ix, jx, gacc, S, rq, rowq, ijq, e);
+                }
             }
         }
-    }
-    if (iv) {
-        double *out = a.partial + (size_t)blockIdx.y * 3 * N;
-        out[i] = gx;
-        out[N + i] = gy;
-        out[2 * N + i] = gz;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nqw) {
+            const int q = (qh + lane) & (GQ - 1);
+            force_pair(a, tab, ix, jx, gacc, S, qr[q], qrow[q], qij[q], e);
+        }
+        __syncthreads();
+        unsigned long long *gs = reinterpret_cast<unsigned long long *>(a.gsum);
+        if (iv)
+            for (int c = 0; c < 3; ++c) atomicAdd(gs + (size_t)c * N + i, gacc[c * GTILE + tid]);
+        if (j < N)
+            for (int c = 0; c < 3; ++c) atomicAdd(gs + (size_t)c * N + j, gacc[(3 + c) * GTILE + tid]);
     }
     for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
-    if ((tid & 63) == 0) red[tid >> 6] = e;
     __syncthreads();
-    if (tid == 0) a.epart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (lane == 0) s_red[wave] = e;
+    __syncthreads();
+    if (tid == 0) a.epart[blockIdx.x] = finite ? (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]) : __builtin_nan("");
 }
 
 __global__ void k_sum_serial(const double *__restrict__ v, int n, double *__restrict__ out)
@@ -614,15 +700,6 @@ __global__ void k_sum_serial(const double *__restrict__ v, int n, double *__rest
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = red[0];
-}
-
-int n_jchunks(nd_box *b)
-{
-    // enough blocks to fill the chip with about 4 blocks per CU
-    const int nib = (b->N + TILE - 1) / TILE;
-    int want = (4 * nd::cu_count(b->device) + nib - 1) / nib;
-    want = std::max(1, std::min(want, 64));
-    return want;
 }
 
 // Mills ratio R(x) = T(x)/phi(x), T the upper Gaussian tail, with its Taylor
@@ -821,32 +898,42 @@ void launch_forces(nd_box *b, double *d_grad, double *d_E)
     a.tab = b->tab;
     a.N = b->N;
     a.M = b->M;
+    a.P = b->P;
     a.n_pts = b->n_pts;
+    a.nt = (b->N + GTILE - 1) / GTILE;
+    a.ntp = (long long)a.nt * (a.nt + 1) / 2;
     a.L = b->L;
     a.invL = 1.0 / b->L;
+    a.half2 = 0.25 * b->L * b->L;
     a.rc2 = b->rc * b->rc;
     a.inv_h = 1.0 / b->h;
-    const int nch = n_jchunks(b);
-    a.jchunk = (b->N + nch - 1) / nch;
-    const int nib = (b->N + TILE - 1) / TILE;
-    const int P = b->P;
-    size_t lds = sizeof(float) * (size_t)((P * b->n_pts + 3) & ~3) + sizeof(double) * 3 * TILE +
-                 sizeof(int) * (2 * TILE + 16);
-    if (lds > 160 * 1024) fail(ND_E_UNSUPPORTED, "potential table does not fit in LDS");
-    size_t gbytes = sizeof(double) * (size_t)nch * 3 * b->N;
-    size_t ebytes = sizeof(double) * (size_t)nch * nib;
-    char *ws = static_cast<char *>(workspace(b, gbytes + ebytes));
-    a.partial = reinterpret_cast<double *>(ws);
-    a.epart = reinterpret_cast<double *>(ws + gbytes);
+    int lg = 0;
+    while ((1LL << lg) < (long long)b->N) ++lg;
+    a.kp = std::min(51, 62 - lg);
+    const size_t lds = sizeof(unsigned long long) * 6 * GTILE + sizeof(double) * 6 * GTILE +
+                       sizeof(int) * (2 * GTILE + 16) + sizeof(float) * (size_t)a.P * a.n_pts;
+    const size_t lds_queue = (sizeof(double) + 2 * sizeof(int)) * GQ * (GTILE / 64) + sizeof(double) * (GTILE / 64);
+    if (lds + lds_queue > 160 * 1024) fail(ND_E_UNSUPPORTED, "potential table does not fit in LDS");
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / (lds + lds_queue + 1024)));
+    long long G = (long long)cu_count(b->device) * per_cu;
+    if (G > a.ntp) G = a.ntp;
+    const long long n = 3LL * b->N;
+    char *ws = static_cast<char *>(workspace(b, sizeof(long long) * (size_t)n + sizeof(double) * (size_t)G + 256));
+    a.gsum = reinterpret_cast<long long *>(ws);
+    a.epart = reinterpret_cast<double *>(ws + sizeof(long long) * (size_t)n);
+    a.shift = reinterpret_cast<int *>(ws + sizeof(long long) * (size_t)n + sizeof(double) * (size_t)G);
+    hipLaunchKernelGGL(k_fill_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream,
+                       reinterpret_cast<double *>(a.gsum), n);
+    ND_HIP(hipGetLastError());
     {
         ProfScope ps(b, ND_PROF_FORCES);
-        hipLaunchKernelGGL(k_forces, dim3(nib, nch), dim3(TILE), lds, b->stream, a);
+        hipLaunchKernelGGL(k_forces, dim3((unsigned)G), dim3(GTILE), lds, b->stream, a);
         ND_HIP(hipGetLastError());
     }
-    const int n = 3 * b->N;
-    hipLaunchKernelGGL(k_reduce_f64, dim3((n + 255) / 256), dim3(256), 0, b->stream, a.partial, nch, n, d_grad);
+    hipLaunchKernelGGL(k_fixed_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream, a.gsum, n, a.shift,
+                       d_grad);
     ND_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_serial, dim3(1), dim3(256), 0, b->stream, a.epart, nch * nib, d_E);
+    hipLaunchKernelGGL(k_sum_serial, dim3(1), dim3(256), 0, b->stream, a.epart, (int)G, d_E);
     ND_HIP(hipGetLastError());
 }
 

@@ -355,6 +355,39 @@ def test_hist_broad_other_widths(nd, orc, sigma):
     assert np.all(np.abs(gb - wb) <= 1e-5 * scale + 1e-4 * np.abs(wb)), np.max(np.abs(gb - wb)) / scale
 
 
+def test_hist_broad_backward_repeatable_and_nonfinite(nd, orc):
+    # integer sums: two calls agree bit for bit; a non-finite adjoint gives
+    # NaN everywhere instead of a silently wrong gradient
+    import torch
+    box = _broad_box()
+    dr, sigma = 0.03, 0.02
+    nb = syn.n_bins_for(8.5 * (1 - 1e-6), dr)
+    g = _gbox(nd, box)
+    A = torch.as_tensor(np.random.default_rng(5).normal(size=(3, nb)), device="cuda")
+    g1 = nd.hist_broad_backward(g, dr, nb, sigma, A).cpu().numpy()
+    g2 = nd.hist_broad_backward(g, dr, nb, sigma, A).cpu().numpy()
+    assert np.array_equal(g1, g2)
+    A[1, nb // 2] = float("inf")
+    g3 = nd.hist_broad_backward(g, dr, nb, sigma, A).cpu().numpy()
+    assert np.all(np.isnan(g3))
+    A[1, nb // 2] = float("nan")
+    g4 = nd.hist_broad_backward(g, dr, nb, sigma, A).cpu().numpy()
+    assert np.all(np.isnan(g4))
+    A[1, nb // 2] = 0.0
+    g5 = nd.hist_broad_backward(g, dr, nb, sigma, A).cpu().numpy()
+    assert np.all(np.isfinite(g5))
+
+
+def test_forces_repeatable(nd, orc):
+    # integer gradient sums and a fixed energy order: repeated calls agree bit for bit
+    box = syn.water_box(600, 18.0, 22, "forces")
+    T = syn.water_tables(r_cut=9.0)
+    g = _gbox(nd, box, T)
+    g1, E1 = nd.forces(g)
+    g2, E2 = nd.forces(g)
+    assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy()) and E1 == E2
+
+
 def test_forces_match_oracle(nd, orc):
     box = syn.water_box(600, 18.0, 22, "forces")
     T = syn.water_tables(r_cut=9.0)
