@@ -495,6 +495,17 @@ __global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
     }
 }
 
+// Two-word integer totals (hi 2^32 + lo, units of 2^ue) back to FP64 (NaN
+// where the table was not finite).
+__global__ void k_words_to_f64(const long long *__restrict__ v, long long n, const int *__restrict__ shift,
+                               double *__restrict__ out)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int ue = *shift;
+    out[q] = ue == INT_MIN ? __builtin_nan("") : ldexp((double)v[q], 32 + ue) + ldexp((double)v[n + q], ue);
+}
+
 // The integer totals back to FP64 (NaN where the adjoint was not finite).
 __global__ void k_fixed_to_f64(const long long *__restrict__ v, long long n, const int *__restrict__ shift,
                                double *__restrict__ out)
@@ -512,7 +523,7 @@ __global__ void k_fill_zero_f64(double *__restrict__ p, long long n)
 }
 
 // ---------------------------------------------------------------- forces
-constexpr int GTILE = 256;  // atoms per tile of the forces: four waves
+constexpr int GTILE = 512;  // atoms per tile of the forces: eight waves
 constexpr int GQ = 128;     // pairs queued per wave
 
 struct ForceArgs {
@@ -523,16 +534,24 @@ struct ForceArgs {
     int N, M, P, n_pts, nt;
     long long ntp;
     double L, invL, half2, rc2, inv_h;
-    int kp;           // a pair's scaled term stays below 2^kp, an atom's total below 2^62
-    long long *gsum;  // [3][N] gradient in units of 2^-sh, cleared before the launch
-    int *shift;       // sh, written by block 0 (INT_MIN: the table is not finite)
+    long long *gsum;  // [2][3][N] gradient as two integer words (hi 2^32 + lo) in units of 2^ue
+    int *shift;       // ue, written by block 0 (INT_MIN: the table is not finite)
     double *epart;    // [gridDim.x] energy of each block's pairs
 };
 
+// y = hi 2^32 + lo with hi, lo integers and 0 <= lo <= 2^32 (|y| < 2^70):
+// each word is summed on its own, so no carry passes between them.
+__device__ __forceinline__ void split_words(double y, unsigned long long &hi, unsigned long long &lo)
+{
+    const double h = floor(y * 2.3283064365386963e-10);
+    hi = (unsigned long long)nearest_ll(h);
+    lo = (unsigned long long)nearest_ll(fma(-h, 4294967296.0, y));
+}
+
 // One queued pair within the cutoff: the tabulated U(r) (linear between
 // points) into e, and +dU/dr (x_i - x_j)/r on atom i, the negative on atom
-// j, as integers in units of 1/S.  The displacement is taken again in FP64
-// from the tiles' coordinates.
+// j, as two integer words in units of 1/S.  The displacement is taken again
+// in FP64 from the tiles' coordinates.
 __device__ __forceinline__ void force_pair(const ForceArgs &a, const float *tab, const double *ix, const double *jx,
                                            unsigned long long *gacc, double S, double r2, int row, int ij,
                                            double &e)
@@ -551,30 +570,33 @@ __device__ __forceinline__ void force_pair(const ForceArgs &a, const float *tab,
     const double f = t - (double)i0;
     e += u0 + f * (u1 - u0);
     const double cs = slope / r * S;
-    const unsigned long long qx = (unsigned long long)nearest_ll(cs * dx);
-    const unsigned long long qy = (unsigned long long)nearest_ll(cs * dy);
-    const unsigned long long qz = (unsigned long long)nearest_ll(cs * dz);
-    __hip_atomic_fetch_add(gacc + il, qx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_add(gacc + GTILE + il, qy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_add(gacc + 2 * GTILE + il, qz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_add(gacc + 3 * GTILE + jl, 0ull - qx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_add(gacc + 4 * GTILE + jl, 0ull - qy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_add(gacc + 5 * GTILE + jl, 0ull - qz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const double comp[3] = {cs * dx, cs * dy, cs * dz};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        unsigned long long hi, lo;
+        split_words(comp[c], hi, lo);
+        __hip_atomic_fetch_add(gacc + c * GTILE + il, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(gacc + (6 + c) * GTILE + il, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(gacc + (3 + c) * GTILE + jl, 0ull - hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(gacc + (9 + c) * GTILE + jl, 0ull - lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
 }
 
 // Gradient of the tabulated total energy and the energy itself, each
 // unordered pair of different units once: tile pairs I <= J as in the
 // broadened backward, the J tile walked along its diagonals, the pairs
 // within the cutoff queued per wave and evaluated 64 at a time.  Gradient
-// sums are integers in units of 1/S, S = 2^sh chosen from the table's
-// steepest step so that no sum can overflow (the result does not depend on
-// the order); the energy is summed per lane in queue order, per block,
-// then over blocks in block order.
+// terms are integers in units of 2^ue, ue = e - 70 with 2^e above the
+// table's steepest step, held as two words (hi 2^32 + lo) summed
+// separately: 70 bits of range for the steep short-range end of the table
+// and a quantum of 2^-71 of that bound, sums exact and independent of
+// order; the energy is summed per lane in queue order, per block, then
+// over blocks in block order.
 __global__ __launch_bounds__(GTILE) void k_forces(ForceArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    unsigned long long *gacc = reinterpret_cast<unsigned long long *>(smem);  // [2][3][GTILE] I tile, J tile
-    double *ix = reinterpret_cast<double *>(gacc + 6 * GTILE);                // [3][GTILE]
+    unsigned long long *gacc = reinterpret_cast<unsigned long long *>(smem);  // [hi, lo][I, J tile][3][GTILE]
+    double *ix = reinterpret_cast<double *>(gacc + 12 * GTILE);               // [3][GTILE]
     double *jx = ix + 3 * GTILE;                                                // [3][GTILE]
     int *js = reinterpret_cast<int *>(jx + 3 * GTILE);                       // [GTILE]
     int *ju = js + GTILE;                                                       // [GTILE]
@@ -606,9 +628,9 @@ __global__ __launch_bounds__(GTILE) void k_forces(ForceArgs a)
     // |a pair's term| <= |dU/dr| <= smax < 2^e
     const bool finite = smax <= 1.0e300;
     const int e2 = finite && smax > 0.0 ? ilogb(smax) + 1 : 0;
-    const int sh = a.kp - e2;
-    const double S = ldexp(1.0, sh);
-    if (blockIdx.x == 0 && tid == 0) *a.shift = finite ? sh : INT_MIN;
+    const int ue = e2 - 70;
+    const double S = ldexp(1.0, -ue);
+    if (blockIdx.x == 0 && tid == 0) *a.shift = finite ? ue : INT_MIN;
     const int N = a.N;
     double *qr = s_qr[wave];
     int *qrow = s_qrow[wave], *qij = s_qij[wave];
@@ -639,7 +661,7 @@ __global__ __launch_bounds__(GTILE) void k_forces(ForceArgs a)
             js[tid] = a.sp[j];
             ju[tid] = a.unit_of[j];
         }
-        for (int q = tid; q < 6 * GTILE; q += GTILE) gacc[q] = 0ull;
+        for (int q = tid; q < 12 * GTILE; q += GTILE) gacc[q] = 0ull;
         __syncthreads();
         const int jn = min(GTILE, N - J * GTILE);
         const int rowbase = si * a.M;
@@ -676,16 +698,25 @@ __global__ __launch_bounds__(GTILE) void k_forces(ForceArgs a)
         }
         __syncthreads();
         unsigned long long *gs = reinterpret_cast<unsigned long long *>(a.gsum);
-        if (iv)
-            for (int c = 0; c < 3; ++c) atomicAdd(gs + (size_t)c * N + i, gacc[c * GTILE + tid]);
-        if (j < N)
-            for (int c = 0; c < 3; ++c) atomicAdd(gs + (size_t)c * N + j, gacc[(3 + c) * GTILE + tid]);
+        for (int w = 0; w < 2; ++w) {
+            unsigned long long *gw = gs + (size_t)w * 3 * N;
+            const unsigned long long *aw = gacc + w * 6 * GTILE;
+            for (int c = 0; c < 3; ++c) {
+                const unsigned long long vi = aw[c * GTILE + tid], vj = aw[(3 + c) * GTILE + tid];
+                if (iv && vi) atomicAdd(gw + (size_t)c * N + i, vi);
+                if (j < N && vj) atomicAdd(gw + (size_t)c * N + j, vj);
+            }
+        }
     }
     for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
     __syncthreads();
     if (lane == 0) s_red[wave] = e;
     __syncthreads();
-    if (tid == 0) a.epart[blockIdx.x] = finite ? (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]) : __builtin_nan("");
+    if (tid == 0) {
+        double eb = s_red[0];
+        for (int w = 1; w < GTILE / 64; ++w) eb += s_red[w];
+        a.epart[blockIdx.x] = finite ? eb : __builtin_nan("");
+    }
 }
 
 __global__ void k_sum_serial(const double *__restrict__ v, int n, double *__restrict__ out)
@@ -907,10 +938,9 @@ void launch_forces(nd_box *b, double *d_grad, double *d_E)
     a.half2 = 0.25 * b->L * b->L;
     a.rc2 = b->rc * b->rc;
     a.inv_h = 1.0 / b->h;
-    int lg = 0;
-    while ((1LL << lg) < (long long)b->N) ++lg;
-    a.kp = std::min(51, 62 - lg);
-    const size_t lds = sizeof(unsigned long long) * 6 * GTILE + sizeof(double) * 6 * GTILE +
+    // a word's sum over an atom's N - 1 pairs: hi below 2^38 N, lo below 2^32 N
+    if (b->N > (1 << 24)) fail(ND_E_UNSUPPORTED, "too many atoms for the forces' gradient sums");
+    const size_t lds = sizeof(unsigned long long) * 12 * GTILE + sizeof(double) * 6 * GTILE +
                        sizeof(int) * (2 * GTILE + 16) + sizeof(float) * (size_t)a.P * a.n_pts;
     const size_t lds_queue = (sizeof(double) + 2 * sizeof(int)) * GQ * (GTILE / 64) + sizeof(double) * (GTILE / 64);
     if (lds + lds_queue > 160 * 1024) fail(ND_E_UNSUPPORTED, "potential table does not fit in LDS");
@@ -918,19 +948,19 @@ void launch_forces(nd_box *b, double *d_grad, double *d_E)
     long long G = (long long)cu_count(b->device) * per_cu;
     if (G > a.ntp) G = a.ntp;
     const long long n = 3LL * b->N;
-    char *ws = static_cast<char *>(workspace(b, sizeof(long long) * (size_t)n + sizeof(double) * (size_t)G + 256));
+    char *ws = static_cast<char *>(workspace(b, sizeof(long long) * 2 * (size_t)n + sizeof(double) * (size_t)G + 256));
     a.gsum = reinterpret_cast<long long *>(ws);
-    a.epart = reinterpret_cast<double *>(ws + sizeof(long long) * (size_t)n);
-    a.shift = reinterpret_cast<int *>(ws + sizeof(long long) * (size_t)n + sizeof(double) * (size_t)G);
-    hipLaunchKernelGGL(k_fill_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream,
-                       reinterpret_cast<double *>(a.gsum), n);
+    a.epart = reinterpret_cast<double *>(ws + sizeof(long long) * 2 * (size_t)n);
+    a.shift = reinterpret_cast<int *>(ws + sizeof(long long) * 2 * (size_t)n + sizeof(double) * (size_t)G);
+    hipLaunchKernelGGL(k_fill_zero_f64, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, b->stream,
+                       reinterpret_cast<double *>(a.gsum), 2 * n);
     ND_HIP(hipGetLastError());
     {
         ProfScope ps(b, ND_PROF_FORCES);
         hipLaunchKernelGGL(k_forces, dim3((unsigned)G), dim3(GTILE), lds, b->stream, a);
         ND_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_fixed_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream, a.gsum, n, a.shift,
+    hipLaunchKernelGGL(k_words_to_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream, a.gsum, n, a.shift,
                        d_grad);
     ND_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sum_serial, dim3(1), dim3(256), 0, b->stream, a.epart, (int)G, d_E);

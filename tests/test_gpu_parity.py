@@ -378,6 +378,55 @@ def test_hist_broad_backward_repeatable_and_nonfinite(nd, orc):
     assert np.all(np.isfinite(g5))
 
 
+@pytest.mark.parametrize("kind,n,L,seed", [("atoms", 2, 5.0, 31), ("atoms", 5, 7.0, 32), ("mixed", 180, 12.0, 33),
+                                           ("atoms", 513, 14.0, 34)])
+def test_differentiated_small_and_ragged_boxes(nd, orc, kind, n, L, seed):
+    # the broadened histogram, its backward and the forces on boxes of a
+    # few atoms (one mostly empty tile), rigid units of 1-4 atoms with 3
+    # species, and 513 atoms (one atom past the last full tile of 512 and
+    # of 256)
+    import torch
+    if kind == "atoms":
+        box = syn.atomic_box([n - n // 2, n // 2], L, seed)
+        T = syn.potential_table(2, round(0.45 * L, 2), 0.01, [(3.0, 0.5), (3.4, 0.3)], [0.5, -0.3])
+    else:
+        box = syn.mixed_unit_box(n, L, seed)
+        T = syn.mixed_tables(r_cut=round(0.45 * L, 2))
+    dr, sigma = 0.05, 0.03
+    nb = syn.n_bins_for(0.45 * L, dr)
+    g = _gbox(nd, box, T)
+    got = nd.hist_broad(g, dr, nb, sigma).cpu().numpy()
+    want = orc.hist_broad(box, dr, nb, sigma)
+    assert np.all(np.abs(got - want) <= 1e-6 * np.maximum(want, 1.0)), np.max(np.abs(got - want))
+    A = np.random.default_rng(seed).normal(size=want.shape)
+    gb = nd.hist_broad_backward(g, dr, nb, sigma, torch.as_tensor(A, device="cuda")).cpu().numpy()
+    wb = orc.hist_broad_backward(box, dr, nb, sigma, A)
+    scale = max(np.abs(wb).max(), 1e-300)
+    assert np.all(np.abs(gb - wb) <= 1e-5 * scale + 1e-4 * np.abs(wb)), np.max(np.abs(gb - wb)) / scale
+    gf, E = nd.forces(g)
+    wf, E_o = orc.forces(box, T)
+    fscale = max(np.abs(wf).max(), 1e-300)
+    assert np.all(np.abs(gf.cpu().numpy() - wf) <= 1e-9 * fscale + 1e-9 * np.abs(wf))
+    _, S_t = orc.total_energy(box, T)
+    assert abs(E - E_o) <= 1e-9 * max(S_t, 1e-300)
+
+
+def test_forces_resolve_small_gradients(nd, orc):
+    # the steep short-range end of the table (r_min = 0.5 A, a step of
+    # ~1e11 kJ/mol/A) sets the integer scale of the gradient sums; a lone
+    # pair far from it (r = 3.2 A, gradient ~1 kJ/mol/A) is still resolved
+    # to 1e-9 of its size
+    L = 12.0
+    xyz = np.array([[1.0, 4.2], [2.0, 2.0], [3.0, 3.0]], dtype=np.float32)
+    box = syn.Box("pair", L, np.zeros(2, dtype=np.uint8), np.arange(3, dtype=np.int32), xyz, 1)
+    T = syn.potential_table(1, 5.0, 0.01, [(3.0, 0.5)], [0.0])
+    gf, E = nd.forces(_gbox(nd, box, T))
+    wf, E_o = orc.forces(box, T)
+    assert np.abs(wf).max() > 0.1
+    assert np.all(np.abs(gf.cpu().numpy() - wf) <= 1e-9 * np.abs(wf).max())
+    assert abs(E - E_o) <= 1e-12 * abs(E_o)
+
+
 def test_forces_repeatable(nd, orc):
     # integer gradient sums and a fixed energy order: repeated calls agree bit for bit
     box = syn.water_box(600, 18.0, 22, "forces")
