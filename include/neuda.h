@@ -242,8 +242,9 @@ nd_status nd_sq_adjoint(const double *dLdS, int32_t P, int32_t nbins, double dr,
  * dL/dx (double [3][N]) = sum over pairs of dL/dr (x_i - x_j)/r with
  * dL/dr = sum_k A_p(k) (phi((e_k - r)/sigma) - phi((e_{k+1} - r)/sigma))/sigma
  * (coincident atoms, r = 0, contribute nothing).  The pair terms are summed
- * as integers in units of a power of two set by max |A|, so the result does
- * not depend on the order of the sums (repeated calls agree bit for bit);
+ * as integers in units of a power of two set by max |A| (a quantum of
+ * 2^-45 of the largest possible term at 1e5 atoms), so the result does not
+ * depend on the order of the sums (repeated calls agree bit for bit);
  * if A holds a NaN or an infinity every output is NaN. */
 nd_status nd_hist_broad_backward(nd_box *box, double dr, int32_t nbins, double sigma,
                                  const double *A, double *dLdx, int32_t where);
