@@ -36,10 +36,10 @@ OPS_PER_TEST = 16
 OPS_PER_PAIR = 23
 # HBM bytes one k_pair_hist launch moves on the 99,999-atom water box, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch scaled by a 1 GiB copy
-# (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 7434.6 + 24958.9
+# (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 7147.1 + 24958.9
 # KiB.  profiles/k_pair_hist_water99999.md holds the counters and commands;
 # set to None whenever the kernel changes until they are taken again.
-HIST_TRAFFIC_BYTES = (2 * 7434.6 + 24958.9) * 1024
+HIST_TRAFFIC_BYTES = (2 * 7147.1 + 24958.9) * 1024
 PAPER_GPU_STEPS_PER_S_1E5 = 12412.0  # Table "tab_speed", water, 1e5 atoms, Tesla V100
 
 

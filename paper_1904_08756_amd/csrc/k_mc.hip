@@ -1236,12 +1236,27 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
             if (a.tr_acc) a.tr_acc[k] = acc ? 1 : 0;
             if (a.tr_unit) a.tr_unit[k] = a.trials[k].unit;
         }
-        // commit: one item per (trial, atom), consecutive items on consecutive
-        // lanes (a trial's atoms share cache lines), the loads of four items
-        // issued together
+        // the accepted trials, listed in the open-trial list (free after the
+        // passes) in any order: each writes only its own atoms
+        __shared__ int s_nl;
+        if (tid == 0) s_nl = 0;
+        __syncthreads();
+        for (int k0 = 0; k0 < kb; k0 += DEC_THREADS) {
+            const int k = k0 + tid;
+            const bool acc = k < kb && s_st[k] == ST_ACC;
+            const unsigned long long m = __ballot(acc);
+            int base = 0;
+            if (lane == 0 && m) base = atomicAdd(&s_nl, __popcll(m));
+            base = __shfl(base, 0);
+            if (acc) s_open[base + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)k;
+        }
+        __syncthreads();
+        // commit: one item per (accepted trial, atom), consecutive items on
+        // consecutive lanes (a trial's atoms share cache lines), the loads of
+        // four items issued together
         float dmax = 0.0f;
         const int max_na = a.max_na;
-        const int n_items = kb * max_na;
+        const int n_items = s_nl * max_na;
         constexpr int CU = 4;
         for (int base = tid; base < n_items; base += CU * DEC_THREADS) {
             int idx[CU], slot[CU];
@@ -1252,8 +1267,9 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                 const int it = base + u * DEC_THREADS;
                 idx[u] = -1;
                 if (it < n_items) {
-                    const int k = it / max_na, at = it - k * max_na;
-                    if (s_st[k] == ST_ACC && at < s_na[k]) {
+                    const int li = it / max_na, at = it - li * max_na;
+                    const int k = s_open[li];
+                    if (at < s_na[k]) {
                         const nd::Trial &T = a.trials[k];
                         idx[u] = s_a0[k] + at;
                         hi[u] = ld4(&T.new_hi[at]);
