@@ -288,7 +288,7 @@ struct BackArgs {
     const double *A;  // [P][nbins]
     int N, M, P, nbins, nt;
     long long ntp;
-    double L, half, half2;  // half = L/2, half2 = (L/2)^2
+    double L, invL, half2;  // half2 = (L/2)^2
     double dr, inv_dr, inv_sigma, six_sigma;
     float beta;       // dr / sigma
     float rho_step;   // exp(-beta^2)
@@ -308,10 +308,10 @@ __device__ __forceinline__ long long nearest_ll(double y)
 // dL/dr of one pair at distance r (r < L/2) and its gradient on both atoms:
 // dL/dr = sum_k A(k) (phi(x_k) - phi(x_{k+1})) / s with x = (e - r)/s, then
 // +c d on atom i (LDS row il of the I tile) and -c d on atom j (row jl of
-// the J tile), c = (dL/dr) / r and d = x_i - x_j, each as an integer in
-// units of 1/S.
-__device__ __forceinline__ void bwd_pair(const BackArgs &a, const float *dA, unsigned long long *gacc, double S,
-                                         double r2, float dx, float dy, float dz, int row, int ij)
+// the J tile), c = (dL/dr) / r and d = x_i - x_j (nearest image, FP64 from
+// the tiles' coordinates), each as an integer in units of 1/S.
+__device__ __forceinline__ void bwd_pair(const BackArgs &a, const float *dA, const double *ix, const double *jx,
+                                         unsigned long long *gacc, double S, double r2, int row, int ij)
 {
     const double r = nd::sqrt_nr(r2);
     int k0 = (int)floor((r - a.six_sigma) * a.inv_dr);
@@ -354,10 +354,14 @@ __device__ __forceinline__ void bwd_pair(const BackArgs &a, const float *dA, uns
     // gradient's FP32 pair weights
     const double c = (double)dLdr * a.inv_sigma * (double)__builtin_amdgcn_rcpf((float)r);
     const double cs = c * S;
-    const unsigned long long qx = (unsigned long long)nearest_ll(cs * (double)dx);
-    const unsigned long long qy = (unsigned long long)nearest_ll(cs * (double)dy);
-    const unsigned long long qz = (unsigned long long)nearest_ll(cs * (double)dz);
     const int il = ij & 0xffff, jl = ij >> 16;
+    double dx = ix[il] - jx[jl], dy = ix[BTILE + il] - jx[BTILE + jl], dz = ix[2 * BTILE + il] - jx[2 * BTILE + jl];
+    dx = fma(-rint(dx * a.invL), a.L, dx);
+    dy = fma(-rint(dy * a.invL), a.L, dy);
+    dz = fma(-rint(dz * a.invL), a.L, dz);
+    const unsigned long long qx = (unsigned long long)nearest_ll(cs * dx);
+    const unsigned long long qy = (unsigned long long)nearest_ll(cs * dy);
+    const unsigned long long qz = (unsigned long long)nearest_ll(cs * dz);
     __hip_atomic_fetch_add(gacc + il, qx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_add(gacc + BTILE + il, qy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_add(gacc + 2 * BTILE + il, qz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -378,12 +382,13 @@ __global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long *gacc = reinterpret_cast<unsigned long long *>(smem);  // [2][3][BTILE] I tile, J tile
-    double *jx = reinterpret_cast<double *>(gacc + 6 * BTILE);               // [3][BTILE]
+    double *ix = reinterpret_cast<double *>(gacc + 6 * BTILE);               // [3][BTILE]
+    double *jx = ix + 3 * BTILE;                                              // [3][BTILE]
     int *js = reinterpret_cast<int *>(jx + 3 * BTILE);               // [BTILE]
     int *prow = js + BTILE;                                           // [16]
     float *dA = reinterpret_cast<float *>(prow + 16);                // [P*nbins]
     __shared__ double s_qr[BTILE / 64][BBQ];
-    __shared__ float4 s_qd[BTILE / 64][BBQ];  // displacement, row offset (int bits)
+    __shared__ int s_qrow[BTILE / 64][BBQ];
     __shared__ int s_qij[BTILE / 64][BBQ];
     __shared__ double s_amax[BTILE / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -416,8 +421,7 @@ __global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
     const double rmax_win = (double)a.nbins * a.dr + a.six_sigma;
     const double rwin2 = rmax_win * rmax_win;
     double *qr = s_qr[wave];  // r^2 of the queued pairs
-    float4 *qd = s_qd[wave];
-    int *qij = s_qij[wave];
+    int *qrow = s_qrow[wave], *qij = s_qij[wave];
     for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
         int I, J;
         tri_index(t, a.nt, I, J);
@@ -432,6 +436,9 @@ __global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
             si = a.sp[i];
         }
         __syncthreads();  // the previous tile pair's sums are out
+        ix[tid] = xi;
+        ix[BTILE + tid] = yi;
+        ix[2 * BTILE + tid] = zi;
         const int j = J * BTILE + tid;
         if (j < N) {
             jx[tid] = a.xyz[j];
@@ -459,11 +466,7 @@ __global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
                 if (in) {
                     const int q = (qh + nqw + __popcll(bal & lt)) & (BBQ - 1);
                     qr[q] = r2;
-                    // signed nearest-image displacement x_i - x_j
-                    qd[q] = make_float4((float)(fabs(dx) <= a.half ? dx : dx - copysign(a.L, dx)),
-                                        (float)(fabs(dy) <= a.half ? dy : dy - copysign(a.L, dy)),
-                                        (float)(fabs(dz) <= a.half ? dz : dz - copysign(a.L, dz)),
-                                        __int_as_float(prow[rowbase + js[jj]]));
+                    qrow[q] = prow[rowbase + js[jj]];
                     qij[q] = tid | (jj << 16);
                 }
                 nqw += __popcll(bal);
@@ -471,20 +474,18 @@ __global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
                     __builtin_amdgcn_wave_barrier();
                     const int q = (qh + lane) & (BBQ - 1);
                     const double rq = qr[q];
-                    const float4 e = qd[q];
-                    const int ijq = qij[q];
+                    const int rowq = qrow[q], ijq = qij[q];
                     qh = (qh + 64) & (BBQ - 1);
                     nqw -= 64;
                     __builtin_amdgcn_wave_barrier();
-                    bwd_pair(a, dA, gacc, S, rq, e.x, e.y, e.z, __float_as_int(e.w), ijq);
+                    bwd_pair(a, dA, ix, jx, gacc, S, rq, rowq, ijq);
                 }
             }
         }
         __builtin_amdgcn_wave_barrier();
         if (lane < nqw) {
             const int q = (qh + lane) & (BBQ - 1);
-            const float4 e = qd[q];
-            bwd_pair(a, dA, gacc, S, qr[q], e.x, e.y, e.z, __float_as_int(e.w), qij[q]);
+            bwd_pair(a, dA, ix, jx, gacc, S, qr[q], qrow[q], qij[q]);
         }
         __syncthreads();
         unsigned long long *gs = reinterpret_cast<unsigned long long *>(a.gsum);
@@ -880,7 +881,7 @@ void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, c
     a.nt = (b->N + BTILE - 1) / BTILE;
     a.ntp = (long long)a.nt * (a.nt + 1) / 2;
     a.L = b->L;
-    a.half = 0.5 * b->L;
+    a.invL = 1.0 / b->L;
     a.half2 = 0.25 * b->L * b->L;
     a.dr = dr;
     a.inv_dr = 1.0 / dr;
@@ -899,8 +900,8 @@ void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, c
     char *ws = static_cast<char *>(workspace(b, sizeof(long long) * 3 * (size_t)b->N + 256));
     a.gsum = reinterpret_cast<long long *>(ws);
     a.shift = reinterpret_cast<int *>(ws + sizeof(long long) * 3 * (size_t)b->N);
-    const size_t lds = sizeof(double) * 9 * BTILE + sizeof(int) * (BTILE + 16) + sizeof(float) * (size_t)b->P * nbins;
-    const size_t lds_queue = (sizeof(double) + sizeof(float4) + sizeof(int)) * BBQ * (BTILE / 64) +
+    const size_t lds = sizeof(double) * 12 * BTILE + sizeof(int) * (BTILE + 16) + sizeof(float) * (size_t)b->P * nbins;
+    const size_t lds_queue = (sizeof(double) + 2 * sizeof(int)) * BBQ * (BTILE / 64) +
                              sizeof(double) * (BTILE / 64);  // static
     if (lds + lds_queue > 160 * 1024) fail(ND_E_UNSUPPORTED, "adjoint table does not fit in LDS");
     const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, (160 * 1024) / (lds + lds_queue + 1024)));
