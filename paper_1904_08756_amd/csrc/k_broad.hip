@@ -524,7 +524,7 @@ __global__ void k_fill_zero_f64(double *__restrict__ p, long long n)
 }
 
 // ---------------------------------------------------------------- forces
-constexpr int GTILE = 512;  // atoms per tile of the forces: eight waves
+constexpr int GTILE = 256;  // atoms per tile of the forces: four waves
 constexpr int GQ = 128;     // pairs queued per wave
 
 struct ForceArgs {
@@ -553,12 +553,13 @@ __device__ __forceinline__ void split_words(double y, unsigned long long &hi, un
 // points) into e, and +dU/dr (x_i - x_j)/r on atom i, the negative on atom
 // j, as two integer words in units of 1/S.  The displacement is taken again
 // in FP64 from the tiles' coordinates.
-__device__ __forceinline__ void force_pair(const ForceArgs &a, const float *tab, const double *ix, const double *jx,
+__device__ __forceinline__ void force_pair(const ForceArgs &a, const float *tab, int ibase, const double *jx,
                                            unsigned long long *gacc, double S, double r2, int row, int ij,
                                            double &e)
 {
-    const int il = ij & 0xffff, jl = ij >> 16;
-    double dx = ix[il] - jx[jl], dy = ix[GTILE + il] - jx[GTILE + jl], dz = ix[2 * GTILE + il] - jx[2 * GTILE + jl];
+    const int il = ij & 0xffff, jl = ij >> 16, i = ibase + il;
+    double dx = (double)a.xyz[i] - jx[jl], dy = (double)a.xyz[a.N + i] - jx[GTILE + jl],
+           dz = (double)a.xyz[2 * a.N + i] - jx[2 * GTILE + jl];
     dx = fma(-rint(dx * a.invL), a.L, dx);
     dy = fma(-rint(dy * a.invL), a.L, dy);
     dz = fma(-rint(dz * a.invL), a.L, dz);
@@ -597,8 +598,7 @@ __global__ __launch_bounds__(GTILE) void k_forces(ForceArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long *gacc = reinterpret_cast<unsigned long long *>(smem);  // [hi, lo][I, J tile][3][GTILE]
-    double *ix = reinterpret_cast<double *>(gacc + 12 * GTILE);               // [3][GTILE]
-    double *jx = ix + 3 * GTILE;                                                // [3][GTILE]
+    double *jx = reinterpret_cast<double *>(gacc + 12 * GTILE);               // [3][GTILE]
     int *js = reinterpret_cast<int *>(jx + 3 * GTILE);                       // [GTILE]
     int *ju = js + GTILE;                                                       // [GTILE]
     int *prow = ju + GTILE;                                                     // [16]
@@ -651,9 +651,6 @@ __global__ __launch_bounds__(GTILE) void k_forces(ForceArgs a)
             ui = a.unit_of[i];
         }
         __syncthreads();  // the previous tile pair's sums are out
-        ix[tid] = xi;
-        ix[GTILE + tid] = yi;
-        ix[2 * GTILE + tid] = zi;
         const int j = J * GTILE + tid;
         if (j < N) {
             jx[tid] = a.xyz[j];
@@ -688,14 +685,14 @@ __global__ __launch_bounds__(GTILE) void k_forces(ForceArgs a)
                     qh = (qh + 64) & (GQ - 1);
                     nqw -= 64;
                     __builtin_amdgcn_wave_barrier();
-                    force_pair(a, tab, ix, jx, gacc, S, rq, rowq, ijq, e);
+                    force_pair(a, tab, I * GTILE, jx, gacc, S, rq, rowq, ijq, e);
                 }
             }
         }
         __builtin_amdgcn_wave_barrier();
         if (lane < nqw) {
             const int q = (qh + lane) & (GQ - 1);
-            force_pair(a, tab, ix, jx, gacc, S, qr[q], qrow[q], qij[q], e);
+            force_pair(a, tab, I * GTILE, jx, gacc, S, qr[q], qrow[q], qij[q], e);
         }
         __syncthreads();
         unsigned long long *gs = reinterpret_cast<unsigned long long *>(a.gsum);
@@ -941,7 +938,7 @@ void launch_forces(nd_box *b, double *d_grad, double *d_E)
     a.inv_h = 1.0 / b->h;
     // a word's sum over an atom's N - 1 pairs: hi below 2^38 N, lo below 2^32 N
     if (b->N > (1 << 24)) fail(ND_E_UNSUPPORTED, "too many atoms for the forces' gradient sums");
-    const size_t lds = sizeof(unsigned long long) * 12 * GTILE + sizeof(double) * 6 * GTILE +
+    const size_t lds = sizeof(unsigned long long) * 12 * GTILE + sizeof(double) * 3 * GTILE +
                        sizeof(int) * (2 * GTILE + 16) + sizeof(float) * (size_t)a.P * a.n_pts;
     const size_t lds_queue = (sizeof(double) + 2 * sizeof(int)) * GQ * (GTILE / 64) + sizeof(double) * (GTILE / 64);
     if (lds + lds_queue > 160 * 1024) fail(ND_E_UNSUPPORTED, "potential table does not fit in LDS");
