@@ -279,7 +279,7 @@ __global__ void k_reduce_f64(const double *__restrict__ partial, int G, int n, d
 }
 
 // ---------------------------------------------------------------- backward
-constexpr int BTILE = 512;  // atoms per tile of the backward: eight waves
+constexpr int BTILE = 256;  // atoms per tile of the backward: four waves
 constexpr int BBQ = 128;    // pairs queued per wave
 
 struct BackArgs {
@@ -310,7 +310,7 @@ __device__ __forceinline__ long long nearest_ll(double y)
 // +c d on atom i (LDS row il of the I tile) and -c d on atom j (row jl of
 // the J tile), c = (dL/dr) / r and d = x_i - x_j (nearest image, FP64 from
 // the tiles' coordinates), each as an integer in units of 1/S.
-__device__ __forceinline__ void bwd_pair(const BackArgs &a, const float *dA, const double *ix, const double *jx,
+__device__ __forceinline__ void bwd_pair(const BackArgs &a, const float *dA, int ibase, const double *jx,
                                          unsigned long long *gacc, double S, double r2, int row, int ij)
 {
     const double r = nd::sqrt_nr(r2);
@@ -355,7 +355,9 @@ __device__ __forceinline__ void bwd_pair(const BackArgs &a, const float *dA, con
     const double c = (double)dLdr * a.inv_sigma * (double)__builtin_amdgcn_rcpf((float)r);
     const double cs = c * S;
     const int il = ij & 0xffff, jl = ij >> 16;
-    double dx = ix[il] - jx[jl], dy = ix[BTILE + il] - jx[BTILE + jl], dz = ix[2 * BTILE + il] - jx[2 * BTILE + jl];
+    const int i = ibase + il;
+    double dx = (double)a.xyz[i] - jx[jl], dy = (double)a.xyz[a.N + i] - jx[BTILE + jl],
+           dz = (double)a.xyz[2 * a.N + i] - jx[2 * BTILE + jl];
     dx = fma(-rint(dx * a.invL), a.L, dx);
     dy = fma(-rint(dy * a.invL), a.L, dy);
     dz = fma(-rint(dz * a.invL), a.L, dz);
@@ -382,8 +384,7 @@ __global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long *gacc = reinterpret_cast<unsigned long long *>(smem);  // [2][3][BTILE] I tile, J tile
-    double *ix = reinterpret_cast<double *>(gacc + 6 * BTILE);               // [3][BTILE]
-    double *jx = ix + 3 * BTILE;                                              // [3][BTILE]
+    double *jx = reinterpret_cast<double *>(gacc + 6 * BTILE);               // [3][BTILE]
     int *js = reinterpret_cast<int *>(jx + 3 * BTILE);               // [BTILE]
     int *prow = js + BTILE;                                           // [16]
     float *dA = reinterpret_cast<float *>(prow + 16);                // [P*nbins]
@@ -436,9 +437,6 @@ __global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
             si = a.sp[i];
         }
         __syncthreads();  // the previous tile pair's sums are out
-        ix[tid] = xi;
-        ix[BTILE + tid] = yi;
-        ix[2 * BTILE + tid] = zi;
         const int j = J * BTILE + tid;
         if (j < N) {
             jx[tid] = a.xyz[j];
@@ -478,14 +476,14 @@ __global__ __launch_bounds__(BTILE) void k_hist_broad_bwd(BackArgs a)
                     qh = (qh + 64) & (BBQ - 1);
                     nqw -= 64;
                     __builtin_amdgcn_wave_barrier();
-                    bwd_pair(a, dA, ix, jx, gacc, S, rq, rowq, ijq);
+                    bwd_pair(a, dA, I * BTILE, jx, gacc, S, rq, rowq, ijq);
                 }
             }
         }
         __builtin_amdgcn_wave_barrier();
         if (lane < nqw) {
             const int q = (qh + lane) & (BBQ - 1);
-            bwd_pair(a, dA, ix, jx, gacc, S, qr[q], qrow[q], qij[q]);
+            bwd_pair(a, dA, I * BTILE, jx, gacc, S, qr[q], qrow[q], qij[q]);
         }
         __syncthreads();
         unsigned long long *gs = reinterpret_cast<unsigned long long *>(a.gsum);
@@ -897,7 +895,7 @@ void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, c
     char *ws = static_cast<char *>(workspace(b, sizeof(long long) * 3 * (size_t)b->N + 256));
     a.gsum = reinterpret_cast<long long *>(ws);
     a.shift = reinterpret_cast<int *>(ws + sizeof(long long) * 3 * (size_t)b->N);
-    const size_t lds = sizeof(double) * 12 * BTILE + sizeof(int) * (BTILE + 16) + sizeof(float) * (size_t)b->P * nbins;
+    const size_t lds = sizeof(double) * 9 * BTILE + sizeof(int) * (BTILE + 16) + sizeof(float) * (size_t)b->P * nbins;
     const size_t lds_queue = (sizeof(double) + 2 * sizeof(int)) * BBQ * (BTILE / 64) +
                              sizeof(double) * (BTILE / 64);  // static
     if (lds + lds_queue > 160 * 1024) fail(ND_E_UNSUPPORTED, "adjoint table does not fit in LDS");
