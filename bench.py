@@ -41,43 +41,81 @@ OPS_PER_PAIR = 23
 # set to None whenever the kernel changes until they are taken again.
 HIST_TRAFFIC_BYTES = (2 * 7147.1 + 24958.9) * 1024
 PAPER_GPU_STEPS_PER_S_1E5 = 12412.0  # Table "tab_speed", water, 1e5 atoms, Tesla V100
+# Table "tab_speed", GPU row at the scale-up sizes (atoms: steps/s)
+PAPER_GPU_SCALE = {1200000: 3917.0, 3000000: 1963.0, 9999999: 757.0, 30000000: 340.3}
+
+
+def read_target_sq():
+    """S_t(Q) of the differentiated form, stored by tests/golden/make_golden.py
+    (the oracle's broadened S(Q) of a water run with an O-O bump)."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "c5_target_sq.txt")
+    rows = [[float(x) for x in line.split()] for line in open(path) if not line.startswith("#")]
+    return np.array(rows[0])
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(box, T, mc):
-    """The FP64 oracle on the host cores, on a bounded sample of the same step."""
-    import numpy as np
+def host_cpu():
+    """Host CPU as lscpu reports it, and the cores this process may use."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"model": info.get("Model name"), "sockets": info.get("Socket(s)"),
+            "cores_per_socket": info.get("Core(s) per socket"), "threads_per_core": info.get("Thread(s) per core"),
+            "cpus": info.get("CPU(s)"), "usable_cpus": usable}
 
-    import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+
+def oracle_step_rate(oracle, box, T, mc, threads, n_mc, n_sub):
+    """One thread count: the oracle's Metropolis rate on the first n_mc
+    trials and its histogram rate on all pairs of the first n_sub atoms (same
+    box, bins and L), combined into the time of one whole step."""
+    import numpy as np
     oracle.set_threads(threads)
-    threads = oracle.max_threads()
+    used = oracle.max_threads()
     xyz = box.xyz.copy()
-    n_mc = 30000
     t0 = time.perf_counter()
     oracle.mc_run(box, T, xyz, mc["kT"], mc["max_disp"], mc["max_rot"], mc["seed"], 0, n_mc)
     t_mc = time.perf_counter() - t0
-    moves_per_s = n_mc / t_mc
-    # histogram rate on all pairs of the first n_sub atoms (same box and bins)
-    n_sub = box.n_atoms
     sub = np.ascontiguousarray(box.xyz[:, :n_sub])
     t0 = time.perf_counter()
     oracle.pair_histogram(sub, mc["dr"], mc["nbins"], L=box.L, species=box.species[:n_sub], n_species=2)
     t_h = time.perf_counter() - t0
-    n_pairs_sample = n_sub * (n_sub - 1) / 2
-    pairs_per_s = n_pairs_sample / t_h
+    moves_per_s = n_mc / t_mc
+    pairs_per_s = n_sub * (n_sub - 1) / 2 / t_h
     n_trials = 10 * box.n_units
     n_pairs = box.n_atoms * (box.n_atoms - 1) / 2
     step_s = n_trials / moves_per_s + n_pairs / pairs_per_s
+    return {"value": n_trials / step_s, "threads": used, "mc_moves_per_s": moves_per_s,
+            "hist_pairs_per_s": pairs_per_s,
+            "sample": (f"{n_mc} Metropolis trials on the 99,999-atom water box ({t_mc:.1f} s) and the exact "
+                       f"histogram of its first {n_sub} atoms ({n_sub * (n_sub - 1) // 2} pairs, {t_h:.1f} s)")}
+
+
+def cpu_baseline(box, T, mc):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    step: once on one thread, once on every core this process may use."""
+    import oracle
+    cpu = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or cpu["usable_cpus"]
+    one = oracle_step_rate(oracle, box, T, mc, 1, 2000, 30000)
+    log(f"cpu baseline, 1 thread: {one['value']:.4g} moves/s")
+    allc = oracle_step_rate(oracle, box, T, mc, threads, 30000, box.n_atoms)
+    log(f"cpu baseline, {allc['threads']} threads: {allc['value']:.4g} moves/s")
     return {
-        "value": n_trials / step_s, "unit": "MC moves/s", "cores": threads, "kind": "oracle",
-        "sample": (f"{n_mc} Metropolis trials on the 99,999-atom water box ({t_mc:.1f} s) and the exact "
-                   f"histogram of the whole box ({int(n_pairs_sample)} pairs, {t_h:.1f} s); "
-                   f"one whole step's time (10 sweeps + histogram) from the two rates"),
-        "mc_moves_per_s": moves_per_s, "hist_pairs_per_s": pairs_per_s,
+        "value": allc["value"], "unit": "MC moves/s", "cores": allc["threads"], "kind": "oracle",
+        "sample": allc["sample"] + "; one whole step's time (10 sweeps + histogram) from the two rates",
+        "mc_moves_per_s": allc["mc_moves_per_s"], "hist_pairs_per_s": allc["hist_pairs_per_s"],
+        "single_thread": one, "host": cpu,
     }
 
 
@@ -136,13 +174,53 @@ def batched_leg(nd, syn, np, torch):
     moves = sweeps * sum(g.n_units for g in plain)
     pairs = sum(g.N * (g.N - 1) // 2 for g in plain)
     batch.close()
+    for b in plain + batched:
+        b.close()
     return {
+        "tuning": nd.tuning_for("batch", sum(sb.n_atoms for sb in sboxes)),
         "workload": f"{len(sboxes)} water boxes, {sum(g.N for g in plain)} atoms, {sweeps} sweeps each "
                     f"({moves} trials) + histogram ({pairs} pairs) + g(r) + S(Q) at {Q.shape[0]} Q",
         "batched_ms_per_replay": t_b * 1e3, "plain_ms": t_p * 1e3, "speedup": t_p / t_b,
         "batched_mc_moves_per_s": moves / t_b, "plain_mc_moves_per_s": moves / t_p,
         "batched_pairs_per_s": pairs / t_b, "plain_pairs_per_s": pairs / t_p,
     }
+
+
+def scale_leg(nd, syn, torch, sizes, hist_upto=1_500_000):
+    """Water boxes at the C2 density at the sizes of the paper's speed table
+    (Table tab_speed: 1.2e6 to 3e7 atoms): Metropolis moves per second over
+    200,000 trials after 50,000 warm-up trials, and the exact histogram's
+    time where its N^2 pairs take under a few seconds."""
+    out = []
+    for n_mol in sizes:
+        box, T, mc = syn.config_scale(n_mol)
+        g = nd.Box.from_synthetic(box)
+        g.set_tables(T.U, T.h, T.r_cut)
+        g.total_energy()
+        p = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"])
+        g.mc_sweep(p, mc["seed"], 0, 50_000, stats=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.mc_sweep(p, mc["seed"], 50_000, 200_000, stats=False)
+        torch.cuda.synchronize()
+        t_mc = time.perf_counter() - t
+        rec = {"n_atoms": box.n_atoms, "L": box.L, "mc_moves_per_s": 200_000 / t_mc,
+               "paper_gpu_steps_per_s": PAPER_GPU_SCALE.get(box.n_atoms)}
+        if box.n_atoms <= hist_upto:
+            counts = nd.pair_histogram(g, mc["dr"], mc["nbins"])
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            nd.pair_histogram(g, mc["dr"], mc["nbins"], out=counts)
+            torch.cuda.synchronize()
+            t_h = time.perf_counter() - t
+            npairs = box.n_atoms * (box.n_atoms - 1) // 2
+            rec.update(hist_ms=t_h * 1e3, hist_pairs_per_s=npairs / t_h,
+                       hist_frac_of_valu_peak=npairs * OPS_PER_PAIR / t_h / PEAK_LANE_OPS)
+        g.close()
+        del box
+        out.append(rec)
+        log(f"scale: {rec['n_atoms']} atoms, {rec['mc_moves_per_s']:.3g} moves/s")
+    return out
 
 
 def main():
@@ -152,6 +230,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the forward+backward and SiO2 legs")
+    ap.add_argument("--scale-up", action="store_true",
+                    help="also the 3e6, 1e7 and 3e7-atom boxes of the paper's speed table (about a minute)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB 3 times (a plain copy "
                          "kernel of known size, to scale hardware byte counters)")
@@ -182,6 +262,8 @@ def main():
     w, self_term = nd.eq1_weights(g, syn.water_b(0.0))
     Q = torch.as_tensor(syn.q_grid(), device="cuda")
     counts = torch.empty((g.P, nbins), dtype=torch.int64, device="cuda")
+    # the O(N) scan's distance tests per trial (the paper's per-step work);
+    # the cell scan evaluates only the candidates of the cells within reach
     n_tests_per_trial = 2 * 3 * (box.n_atoms - 3)
     n_pairs = box.n_atoms * (box.n_atoms - 1) // 2
 
@@ -246,7 +328,10 @@ def main():
                                "+ exact pair histogram (1660 x 0.03 A bins) + g(r) + S(Q) at 1000 Q",
                    "n_atoms": box.n_atoms, "trials_per_step": n_trials, "pairs_per_step": n_pairs,
                    "parallelism": "single GPU"},
-        "pair_distances_per_s": dist_per_s,
+        # dense equivalent: per trial the 2 n_u (N - n_u) tests of the O(N)
+        # scan, which the cell scan does not perform; plus every histogram pair
+        "dense_equivalent_pair_distances_per_s": dist_per_s,
+        "histogram_pair_distances_per_s": n_pairs * args.steps / elapsed,
         # The roofline is taken on the exact pair histogram: its algorithmic
         # work has a fixed definition (every pair once).  The Metropolis
         # kernels evaluate only the pairs their cell neighbourhoods hold, so
@@ -277,7 +362,8 @@ def main():
         # g, S, chi^2) + backward (adjoint, pair gradient), against the plain
         # histogram + g + S on the same box
         sig = 0.02
-        target = torch.as_tensor(20.5 + 0.5 * np.sin(syn.q_grid()), device="cuda")
+        # target S(Q): the oracle's run with the O-O bump (tests/golden/make_golden.py)
+        target = torch.as_tensor(read_target_sq(), device="cuda")
         x = torch.as_tensor(g.coords_host(), device="cuda")
 
         def plain():
@@ -356,7 +442,11 @@ def main():
         g3.mc_sweep(p3, mc3["seed"], 20000, box3.n_units, stats=False)
         torch.cuda.synchronize()
         result["sio2_mc_moves_per_s"] = box3.n_units / (time.perf_counter() - t)
+        g3.close()
         log("sio2 done")
+        sizes = [400_000] + ([1_000_000, 3_333_333, 10_000_000] if args.scale_up else [])
+        result["scale"] = scale_leg(nd, syn, torch, sizes)
+        log("scale done")
 
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -368,6 +458,9 @@ def main():
         result["calib_copy_bytes"] = {"read": 4 * n, "write": 4 * n}
         log("copy calibration done")
 
+    # every handle released explicitly while the runtime is up
+    g.close()
+    torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         result["cpu_baseline"] = cpu_baseline(box, T, mc)

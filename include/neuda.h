@@ -58,7 +58,7 @@ typedef int32_t nd_status;
 #define ND_DEVICE 1
 
 #define ND_ORDER_SEQ 0    /* trial t moves unit t mod n_units                    */
-#define ND_ORDER_RANDOM 1 /* trial t moves a unit drawn from the trial's draws   */
+#define ND_ORDER_RANDOM 1 /* trial t moves unit floor(u_7 n_units), u_7 its draw 7 */
 
 #define ND_MAX_SPECIES 4
 #define ND_MAX_UNIT_ATOMS 8
@@ -129,17 +129,23 @@ const char *nd_last_error(void);
 nd_status nd_box_create(const nd_box_desc *desc, nd_box **out);
 
 /* Releases the box and its device memory after its stream drains.
- * NULL is accepted. */
+ * NULL is accepted.  Reached when the HIP runtime is no longer usable (a
+ * release during process teardown), it frees the host side only and leaves
+ * the device memory to the end of the process. */
 nd_status nd_box_destroy(nd_box *box);
 
 /* Sets the stream used by later calls on the box (NULL = default stream). */
 nd_status nd_box_set_stream(nd_box *box, void *stream);
 
 /* Replaces all coordinates ([3][N], where = ND_HOST or ND_DEVICE).  Host
- * input is validated (finite, in [0, L)); device input is taken as is.
- * keep_energy = 0 marks the running energy stale (nd_box_total_energy
- * recomputes it); 1 keeps the running value (the caller asserts the
- * energy did not change). */
+ * input must be finite and in [0, L) (ND_E_INVALID otherwise).  Device
+ * input is wrapped into the box, x - L floor(x/L) rounded to float32 (a
+ * result of L becomes 0), in a staging copy; a value that is not finite
+ * gives ND_E_INVALID and leaves the box unchanged.  The device path
+ * synchronises the box's stream.  keep_energy = 0 marks the running energy
+ * stale (the next nd_mc_sweep, nd_batch_run or nd_box_total_energy
+ * recomputes it); 1 keeps the running value (the caller asserts the energy
+ * did not change, e.g. when restoring the same coordinates). */
 nd_status nd_box_set_coords(nd_box *box, const float *xyz, int32_t where, int32_t keep_energy);
 
 /* Copies the current coordinates ([3][N]) out. */
@@ -162,8 +168,10 @@ nd_status nd_box_total_energy(nd_box *box, double *E);
 nd_status nd_box_energy(nd_box *box, double *E);
 
 /* Runs trials first_trial .. first_trial + n_trials - 1 of the Metropolis
- * chain (Sec. "Algorithmic Flow" III): trial t proposes a translation
- * (uniform in [-max_disp, max_disp] per axis) and, for units of more than
+ * chain (Sec. "Algorithmic Flow" III, where units move in sequence or at
+ * random): trial t moves unit t mod n_units (ND_ORDER_SEQ) or unit
+ * floor(u_7 n_units) of its draw 7 (ND_ORDER_RANDOM).  It proposes a
+ * translation (uniform in [-max_disp, max_disp] per axis) and, for units of more than
  * one atom, a rotation by an angle uniform in [-max_rot, max_rot] about a
  * uniform axis through the unit's unweighted centroid; the energy change
  * dE of the unit against every atom outside it decides acceptance:
@@ -171,11 +179,16 @@ nd_status nd_box_energy(nd_box *box, double *E);
  * SplitMix64 seeded with `seed` (output 16 t + d is draw d of trial t), so
  * a run split over several calls equals one call over the same trials.
  * The result equals the sequential chain; trials are evaluated in batches
- * whose interactions are corrected exactly.  A decision with
+ * of distinct units whose interactions are corrected exactly (in random
+ * order a batch ends before the first repeated unit, so batches are
+ * shorter, about sqrt(pi n_units / 2) trials).  A decision with
  * |ln u + dE/kT| < tie_rel * sabs / kT is counted as a near tie.
+ * A running energy made stale by nd_box_set_coords or nd_box_set_tables is
+ * recomputed over all pairs before the first trial, so stats->E_total is
+ * always the energy of the final configuration.
  * stats (host, may be NULL) synchronises; trace (device arrays, may be
  * NULL) records every trial.  Errors: ND_E_INVALID, ND_E_STATE (no
- * tables), ND_E_UNSUPPORTED (ND_ORDER_RANDOM), ND_E_HIP. */
+ * tables), ND_E_HIP. */
 nd_status nd_mc_sweep(nd_box *box, const nd_mc_params *params, uint64_t seed,
                       uint64_t first_trial, int64_t n_trials, nd_mc_stats *stats,
                       const nd_mc_trace *trace);
@@ -204,6 +217,44 @@ nd_status nd_gr_normalize_f64(const double *counts, int32_t P, int32_t nbins, do
  * N_a (N_a - 1)/2 for like species, N_a N_b for unlike species (the pair
  * counts that normalise g_ab(r), Eq. 1). */
 nd_status nd_box_pair_counts(nd_box *box, double *npairs);
+
+/* ---- Running histogram and its accumulation (Sec. "Acceleration method":
+ * Delta N(r) is recomputed after every Monte Carlo step at a cost
+ * proportional to N, the full N(r) at a cost proportional to N^2; Sec.
+ * "NeuDATool Algorithmic Flow", steps EPMC and "Accumulate g(r) and S(Q)").
+ *
+ * nd_box_track_histogram starts keeping a running N(r) of the box: the
+ * counts of nd_pair_histogram(dr, nbins) of the current coordinates, to
+ * which every later nd_mc_sweep adds the Delta N(r) of each accepted move
+ * (the change of every pair with an atom in a moved unit, by the same
+ * exact bin rule), so the running counts stay equal to a fresh
+ * nd_pair_histogram bit for bit.  Coordinates changed otherwise
+ * (nd_box_set_coords, nd_box_load, the batched form's sweeps) are counted
+ * afresh before the next use.  nbins = 0 stops tracking and frees its
+ * memory; restarting clears the accumulated samples.  Requires dr > 0 and
+ * nbins * dr < L/2.  Errors: ND_E_INVALID, ND_E_RANGE, ND_E_UNSUPPORTED
+ * (P * nbins beyond the kernel's LDS), ND_E_OOM, ND_E_HIP. */
+nd_status nd_box_track_histogram(nd_box *box, double dr, int32_t nbins);
+
+/* Copies the running counts (uint64 [P][nbins]) to `where`.  Errors:
+ * ND_E_STATE when no histogram is tracked. */
+nd_status nd_box_tracked_histogram(nd_box *box, uint64_t *counts, int32_t where);
+
+/* Adds the running counts to the box's sum of samples (one sample), on the
+ * box's stream.  Errors: ND_E_STATE when no histogram is tracked. */
+nd_status nd_box_accumulate(nd_box *box);
+
+/* Mean of the accumulated samples, double [P][nbins] in `where`, and the
+ * number of samples (host, may be NULL).  g(r) and S(Q) are linear in the
+ * counts, so nd_gr_normalize_f64 and nd_sq_transform of the mean give the
+ * averaged g(r) and S(Q).  Errors: ND_E_STATE when no histogram is tracked
+ * or no sample was taken. */
+nd_status nd_box_accumulated(nd_box *box, double *mean_counts, int64_t *n_samples, int32_t where);
+
+/* Volume V = L^3 (Angstrom^3) and number density rho = N / V (atoms per
+ * Angstrom^3) of the box (host doubles): the V of the g(r) normalisation
+ * and the rho of Eq. 1. */
+nd_status nd_box_density(nd_box *box, double *V, double *rho);
 
 /* Eq. 1 coefficients of the box for scattering lengths b (host double [M]):
  * w_p = (2 - delta_ab) c_a c_b b_a b_b (host double [P]) and the flat term
@@ -257,6 +308,7 @@ nd_status nd_hist_broad_backward(nd_box *box, double dr, int32_t nbins, double s
  * table holding a NaN or an infinity gives NaN everywhere. */
 nd_status nd_forces(nd_box *box, double *dEdx, double *E, int32_t where);
 
+
 /* Checkpoint of a box's Metropolis state: coordinates, running energy and
  * (when live) the cell lists, so that a run resumed from the checkpoint
  * repeats the uninterrupted run bit for bit.  The image is a flat byte
@@ -306,6 +358,9 @@ typedef struct nd_batch_plan {
     uint64_t *const *counts;      /* host [n] of device [P][nbins_i]; NULL: no histogram */
     double *const *g;             /* host [n] of device [P][nbins_i]; NULL: no g or S    */
     double *const *S;             /* host [n] of device [nQ]; NULL or nQ = 0: no S       */
+    const nd_mc_trace *trace;     /* host [n] or NULL: per-trial record of box i's sweeps
+                                     (device arrays of sweeps * n_units_i entries, as for
+                                     nd_mc_sweep; any member may be NULL)              */
 } nd_batch_plan;
 
 /* Groups n >= 1 distinct boxes on one device with the same number of
@@ -318,12 +373,104 @@ nd_status nd_batch_destroy(nd_batch *batch);
 /* One run of the plan (see above), asynchronous on the batch's own stream.
  * stats: host [n] or NULL; when given, the call waits for the run and fills
  * the counters of each box's sweeps.  Errors: ND_E_INVALID, ND_E_RANGE,
- * ND_E_STATE (a box without tables), ND_E_UNSUPPORTED (ND_SCAN_FULL,
- * ND_ORDER_RANDOM), ND_E_OOM, ND_E_HIP. */
+ * ND_E_STATE (a box without tables), ND_E_UNSUPPORTED (ND_SCAN_FULL),
+ * ND_E_OOM, ND_E_HIP. */
 nd_status nd_batch_run(nd_batch *batch, const nd_batch_plan *plan, nd_mc_stats *stats);
 
 /* Number of graph captures and of graph launches of the batch so far. */
 nd_status nd_batch_info(const nd_batch *batch, int64_t *captures, int64_t *launches);
+
+/* ---- Empirical-potential refinement (Sec. "Algorithmic Principle": the
+ * EMP is the Fourier counterpart of the difference dS(Q) between measured
+ * and simulated S(Q), fitted by a series of Poisson functions in Q space and
+ * added to the reference potential; Sec. "Correctness", Eq. 2: the EMP of
+ * each pair type through the inverse of the Eq. 1 weight matrix of the
+ * measured profiles, enlarged by a unit matrix when there are fewer profiles
+ * than pair types; Sec. "NeuDATool Algorithmic Flow", step EPMC: update,
+ * re-equilibrate, repeat).
+ *
+ * Poisson functions, normalised so that 4 pi rho int r^2 p_n dr = 1:
+ *   p_n(r) = (r/s)^n exp(-r/s) / (4 pi rho s^3 (n+2)!),  n = 1 .. n_terms,
+ * with the Eq. 1 transform 4 pi rho int r^2 p_n(r) sin(Qr)/(Qr) dr
+ *   P_n(Q) = sin((n+2) a) / ((n+2) Q s (1 + Q^2 s^2)^((n+2)/2)),  a = atan(Q s).
+ * One update: S_sim,i by Eq. 1 from the model's g(r) with profile i's
+ * weights W[i][.] and flat term; dS_i = S_exp,i - S_sim,i; least-squares
+ * coefficients c_i of dS_i in the P_n (normal equations plus ridge * tr/n
+ * on the diagonal); the pair types' coefficients C_p = sum_i W+[p][i] c_i
+ * (W+ = W^-1 when there are as many profiles as pair types, else the
+ * pseudo-inverse of W stacked over id_weight times the unit matrix); the
+ * update dU_p(r) = -feedback kT sum_n C_pn p_n(r), shifted to zero at the
+ * cutoff and zero beyond, added to the box's EMP (which nd_box_set_tables
+ * resets to zero); if emp_max > 0 the EMP is then scaled so that
+ * max |EMP| <= emp_max; the box's tables become (float)(reference + EMP).
+ * The running energy becomes stale (the next sweep recomputes it). */
+#define ND_EMP_MAX_TERMS 64
+#define ND_EMP_MAX_PROFILES 8
+
+typedef struct nd_emp_params {
+    double sigma;       /* width s of the Poisson functions, Angstrom, > 0        */
+    int32_t n_terms;    /* number of Poisson functions, 1 .. ND_EMP_MAX_TERMS     */
+    int32_t pad;
+    double feedback;    /* fraction of the fitted potential applied, > 0          */
+    double kT;          /* energy scale, kJ/mol, > 0                              */
+    double ridge;       /* relative ridge of the fit, >= 0                        */
+    double id_weight;   /* weight of the unit-matrix rows (fewer profiles), > 0   */
+    double emp_max;     /* cap on max |EMP| in kJ/mol, 0 = none                   */
+} nd_emp_params;
+
+/* One EMP update of `box` from n_prof measured profiles: W host double
+ * [n_prof][P] (Eq. 1 weights of each profile, as nd_eq1_weights gives for its
+ * scattering lengths), self_terms host double [n_prof]; g device double
+ * [P][nbins] (the model's g(r), bins of width dr); Q device double [nQ];
+ * S_exp device double [n_prof][nQ].  Optional device outputs (NULL to skip):
+ * dS [n_prof][nQ], the EMP after the update [P][n_pts], the update's
+ * coefficients C [P][n_terms].  Asynchronous on the box's stream.  Errors:
+ * ND_E_INVALID (bad sizes or parameters, W singular when square),
+ * ND_E_STATE (no tables), ND_E_HIP. */
+nd_status nd_emp_update(nd_box *box, const nd_emp_params *params, int32_t n_prof, const double *W,
+                        const double *self_terms, const double *g, int32_t nbins, double dr, const double *Q,
+                        int32_t nQ, const double *S_exp, double *dS, double *emp, double *C);
+
+/* Copies the box's tables as used by the energy kernels (float32 [P][n_pts]:
+ * reference potential plus EMP) to `where`.  Errors: ND_E_STATE (no tables). */
+nd_status nd_box_get_tables(nd_box *box, float *U, int32_t where);
+
+/* ---- Tuning table.  Launch parameters chosen per size class by a tuner
+ * (the package's autotune module writes them to a text file that the
+ * binding loads at start-up); without an entry the library's built-in
+ * choices apply.  Entries of one kind are looked up by atom count: the
+ * first entry (in the order given) with n <= n_max applies.  The table is
+ * process-wide; set it before the calls it should affect (a batched run
+ * captured earlier keeps its launch structure until that changes). */
+#define ND_TUNE_BOX 0    /* nd_mc_sweep and nd_pair_histogram of a box of n atoms */
+#define ND_TUNE_BATCH 1  /* nd_batch_run over boxes of n atoms in total           */
+
+typedef struct nd_tuning {
+    int32_t kind;               /* ND_TUNE_BOX or ND_TUNE_BATCH                        */
+    int32_t scan_waves;         /* waves per trial of the cell scan: 1, 2 or 4; 0 = built in */
+    int64_t n_max;              /* largest atom count the entry applies to             */
+    double batch_target;        /* expected interacting earlier trials per trial at the
+                                   end of a Metropolis batch; sets the batch size
+                                   K = target / f (f the share of the box within reach,
+                                   K <= 2048 and <= n_units / 2); 0 = built in (18)    */
+    int32_t hist_blocks_per_cu; /* pair-histogram blocks per compute unit, 1..8, capped by
+                                   LDS; 0 = built in (5)                               */
+    int32_t pad;
+} nd_tuning;
+
+/* Replaces the table with n entries (n = 0 clears it).  Errors:
+ * ND_E_INVALID (bad kind, scan_waves, negative target, blocks per CU). */
+nd_status nd_set_tuning(const nd_tuning *entries, int32_t n);
+
+/* Copies at most cap entries to `entries` (may be NULL when cap = 0) and the
+ * table's size to *n. */
+nd_status nd_get_tuning(nd_tuning *entries, int32_t cap, int32_t *n);
+
+/* Replaces the table with the entries of a text file: one entry per line,
+ * "box|batch n_max scan_waves batch_target hist_blocks_per_cu", blank lines
+ * and lines starting with '#' ignored.  Errors: ND_E_INVALID (unreadable
+ * file or malformed line; the table is then unchanged). */
+nd_status nd_load_tuning(const char *path);
 
 /* Per-kernel timing with HIP events on the box's stream, for measurement.
  * Kernel ids for nd_box_profile. */

@@ -11,8 +11,10 @@ method", and Eq. 1.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -71,8 +73,25 @@ class nd_batch_plan(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("mc", C.c_void_p), ("seed", C.c_void_p),
                 ("first_trial", C.c_void_p), ("dr", C.c_double), ("nbins", C.c_void_p),
                 ("w", C.c_void_p), ("self_term", C.c_void_p), ("Q", C.c_void_p), ("nQ", C.c_int32),
-                ("counts", C.c_void_p), ("g", C.c_void_p), ("S", C.c_void_p)]
+                ("counts", C.c_void_p), ("g", C.c_void_p), ("S", C.c_void_p),
+                ("trace", C.c_void_p)]
 
+
+class nd_tuning(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("scan_waves", C.c_int32), ("n_max", C.c_int64),
+                ("batch_target", C.c_double), ("hist_blocks_per_cu", C.c_int32), ("pad", C.c_int32)]
+
+
+class nd_emp_params(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("n_terms", C.c_int32), ("pad", C.c_int32), ("feedback", C.c_double),
+                ("kT", C.c_double), ("ridge", C.c_double), ("id_weight", C.c_double), ("emp_max", C.c_double)]
+
+
+ND_TUNE_BOX = 0
+ND_TUNE_BATCH = 1
+TUNE_KINDS = {"box": ND_TUNE_BOX, "batch": ND_TUNE_BATCH}
+# tuned launch parameters for this GPU, written by autotune.py
+TUNING_FILE = os.path.join(_HERE, "tuning.txt")
 
 EXPORTS = {
     "nd_abi_version": (C.c_int32, []),
@@ -104,6 +123,11 @@ EXPORTS = {
     "nd_gr_normalize_f64": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                         C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "nd_box_pair_counts": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "nd_box_density": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "nd_box_track_histogram": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32]),
+    "nd_box_tracked_histogram": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "nd_box_accumulate": (C.c_int32, [C.c_void_p]),
+    "nd_box_accumulated": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.c_int32]),
     "nd_box_set_profiling": (C.c_int32, [C.c_void_p, C.c_int32]),
     "nd_box_set_profiling_mask": (C.c_int32, [C.c_void_p, C.c_uint32]),
     "nd_box_profile": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
@@ -117,9 +141,47 @@ EXPORTS = {
     "nd_batch_destroy": (C.c_int32, [C.c_void_p]),
     "nd_batch_run": (C.c_int32, [C.c_void_p, C.POINTER(nd_batch_plan), C.c_void_p]),
     "nd_batch_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "nd_emp_update": (C.c_int32, [C.c_void_p, C.POINTER(nd_emp_params), C.c_int32, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_int32, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p]),
+    "nd_box_get_tables": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "nd_set_tuning": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "nd_get_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "nd_load_tuning": (C.c_int32, [C.c_char_p]),
 }
 
 _lib = None
+
+# Live handles, released at interpreter exit (batches before boxes) while
+# the HIP runtime is still up, instead of from __del__ during teardown.
+_live_batches = weakref.WeakSet()
+_live_boxes = weakref.WeakSet()
+
+
+def _release_all():
+    for t in list(_live_batches):
+        try:
+            t.close()
+        except Exception:
+            pass
+    for b in list(_live_boxes):
+        try:
+            b.close()
+        except Exception:
+            pass
+
+
+_exit_hook = False
+
+
+def _register_exit():
+    # registered at the first handle, after torch has set up the GPU, so it
+    # runs before anything torch registered earlier (atexit is last-in,
+    # first-out)
+    global _exit_hook
+    if not _exit_hook:
+        atexit.register(_release_all)
+        _exit_hook = True
 
 
 def build() -> str:
@@ -140,7 +202,42 @@ def lib():
         f.restype = res
         f.argtypes = args
     _lib = L
+    if os.path.exists(TUNING_FILE) and not os.environ.get("NEUDA_NO_TUNING"):
+        _check(L.nd_load_tuning(TUNING_FILE.encode()))
     return L
+
+
+def set_tuning(entries):
+    """Replace the library's tuning table: entries are dicts with kind
+    ("box" or "batch"), n_max, scan_waves, batch_target, hist_blocks_per_cu."""
+    arr = (nd_tuning * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        arr[i] = nd_tuning(TUNE_KINDS[e["kind"]], int(e.get("scan_waves", 0)), int(e["n_max"]),
+                           float(e.get("batch_target", 0.0)), int(e.get("hist_blocks_per_cu", 0)), 0)
+    _check(lib().nd_set_tuning(arr, len(entries)))
+
+
+def get_tuning():
+    """The library's tuning table as a list of dicts."""
+    n = C.c_int32()
+    _check(lib().nd_get_tuning(None, 0, C.byref(n)))
+    arr = (nd_tuning * max(1, n.value))()
+    _check(lib().nd_get_tuning(arr, n.value, C.byref(n)))
+    names = {v: k for k, v in TUNE_KINDS.items()}
+    return [dict(kind=names[x.kind], n_max=x.n_max, scan_waves=x.scan_waves, batch_target=x.batch_target,
+                 hist_blocks_per_cu=x.hist_blocks_per_cu) for x in arr[:n.value]]
+
+
+def tuning_for(kind, n_atoms):
+    """The tuning entry the library applies to `kind` and n_atoms, or None."""
+    for e in get_tuning():
+        if e["kind"] == kind and n_atoms <= e["n_max"]:
+            return e
+    return None
+
+
+def load_tuning(path):
+    _check(lib().nd_load_tuning(os.fsencode(path)))
 
 
 def _check(code):
@@ -210,6 +307,11 @@ class Box:
         h = C.c_void_p()
         _check(lib().nd_box_create(C.byref(d), C.byref(h)))
         self._h = h
+        # changes whenever the coordinates change (set_coords, sweeps, load,
+        # batch runs), so a saved autograd context can tell it is stale
+        self.version = 0
+        _live_boxes.add(self)
+        _register_exit()
 
     @classmethod
     def from_synthetic(cls, sbox, device=0):
@@ -262,10 +364,13 @@ class Box:
             raise ValueError("table rows must equal the number of pair types")
         self._sync_stream()
         _check(lib().nd_box_set_tables(self.handle, U.ctypes.data, U.shape[1], float(h), float(r_cut)))
+        self._n_pts = int(U.shape[1])
+        self.version += 1
 
     def set_coords(self, xyz, keep_energy=False):
         torch = _torch()
         self._sync_stream()
+        self.version += 1
         if isinstance(xyz, torch.Tensor) and xyz.is_cuda:
             t = xyz.detach().to(torch.float32).contiguous()
             _check(lib().nd_box_set_coords(self.handle, _dptr(t), ND_DEVICE, int(keep_energy)))
@@ -299,8 +404,52 @@ class Box:
     def load(self, image: bytes):
         """Restore a checkpoint made by save() (nd_box_load)."""
         self._sync_stream()
+        self.version += 1
         buf = C.create_string_buffer(bytes(image), len(image))
         _check(lib().nd_box_load(self.handle, buf, len(image)))
+
+    # -- running histogram and its accumulation
+    def track_histogram(self, dr, nbins):
+        """Keep a running N(r) updated by every accepted move (nbins = 0 stops)."""
+        self._sync_stream()
+        _check(lib().nd_box_track_histogram(self.handle, float(dr), int(nbins)))
+        self._track_nbins = int(nbins)
+
+    def tracked_histogram(self):
+        """The running counts as an int64 [P, nbins] device tensor (uint64 values)."""
+        torch = _torch()
+        self._sync_stream()
+        out = torch.empty((self.P, self._track_nbins), dtype=torch.int64, device=f"cuda:{self.device}")
+        _check(lib().nd_box_tracked_histogram(self.handle, _dptr(out), ND_DEVICE))
+        return out
+
+    def accumulate(self):
+        """Add the running counts to the sum of samples."""
+        self._sync_stream()
+        _check(lib().nd_box_accumulate(self.handle))
+
+    def accumulated(self):
+        """(mean counts [P, nbins] float64 device tensor, number of samples)."""
+        torch = _torch()
+        self._sync_stream()
+        out = torch.empty((self.P, self._track_nbins), dtype=torch.float64, device=f"cuda:{self.device}")
+        n = C.c_int64()
+        _check(lib().nd_box_accumulated(self.handle, _dptr(out), C.byref(n), ND_DEVICE))
+        return out, n.value
+
+    def tables(self):
+        """The tables the energy kernels use (reference + EMP), float32 [P, n_pts] host array."""
+        self._sync_stream()
+        out = np.empty((self.P, self._n_pts), np.float32)
+        _check(lib().nd_box_get_tables(self.handle, out.ctypes.data, ND_HOST))
+        return out
+
+    def density(self):
+        """(V, rho): box volume and number density (nd_box_density)."""
+        V = C.c_double()
+        rho = C.c_double()
+        _check(lib().nd_box_density(self.handle, C.byref(V), C.byref(rho)))
+        return V.value, rho.value
 
     def total_energy(self):
         E = C.c_double()
@@ -331,6 +480,7 @@ class Box:
                              tr_t["accepted"].data_ptr(), tr_t["unit"].data_ptr())
         st = nd_mc_stats() if stats else None
         p = params.c()
+        self.version += 1
         _check(lib().nd_mc_sweep(self.handle, C.byref(p), C.c_uint64(seed), C.c_uint64(first_trial),
                                  int(n_trials), C.byref(st) if st is not None else None,
                                  C.byref(tr) if tr is not None else None))
@@ -356,6 +506,7 @@ class Batch:
         h = C.c_void_p()
         _check(lib().nd_batch_create(arr, n, C.byref(h)))
         self._h = h
+        _live_batches.add(self)
 
     def close(self):
         if getattr(self, "_h", None) is not None:
@@ -376,10 +527,11 @@ class Batch:
         return c.value, n.value
 
     def run(self, sweeps, params, seeds, first_trials, dr=None, nbins=None, w=None, self_term=None,
-            Q=None, counts=None, g=None, S=None, stats=False):
+            Q=None, counts=None, g=None, S=None, stats=False, trace=False):
         """One run.  params/seeds/first_trials/nbins/self_term: one per box; w: [n, P];
         counts/g/S: lists of device tensors ([P, nbins_i] int64, [P, nbins_i] float64,
-        [nQ] float64), or None to skip that stage."""
+        [nQ] float64), or None to skip that stage.  trace=True records every
+        trial of every box (returned under "trace" of each box's stats)."""
         torch = _torch()
         n = len(self.boxes)
         for b in self.boxes:
@@ -417,12 +569,36 @@ class Batch:
                     pl.w = ww.ctypes.data
                     pl.self_term = st.ctypes.data
                     pl.S = C.cast(sp, C.c_void_p)
+        tr_t = None
+        if trace and sweeps > 0:
+            tr_t, trs = [], []
+            for b in self.boxes:
+                nt = int(sweeps) * b.n_units
+                dev = f"cuda:{b.device}"
+                d = dict(dE=torch.empty(nt, dtype=torch.float64, device=dev),
+                         sabs=torch.empty(nt, dtype=torch.float64, device=dev),
+                         accepted=torch.empty(nt, dtype=torch.uint8, device=dev),
+                         unit=torch.empty(nt, dtype=torch.int32, device=dev))
+                tr_t.append(d)
+                trs.append(nd_mc_trace(d["dE"].data_ptr(), d["sabs"].data_ptr(), d["accepted"].data_ptr(),
+                                       d["unit"].data_ptr()))
+            tra = (nd_mc_trace * n)(*trs)
+            keep.append(tra)
+            pl.trace = C.cast(tra, C.c_void_p)
+            stats = True
         sts = (nd_mc_stats * n)() if stats else None
+        if sweeps > 0:
+            for b in self.boxes:
+                b.version += 1
         _check(lib().nd_batch_run(self._h, C.byref(pl), C.cast(sts, C.c_void_p) if sts is not None else None))
         if sts is None:
             return None
-        return [dict(trials=x.trials, accepted=x.accepted, near_ties=x.near_ties, E_total=x.E_total,
-                     dE_sum=x.dE_sum) for x in sts]
+        out = [dict(trials=x.trials, accepted=x.accepted, near_ties=x.near_ties, E_total=x.E_total,
+                    dE_sum=x.dE_sum) for x in sts]
+        if tr_t is not None:
+            for o, d in zip(out, tr_t):
+                o["trace"] = d
+        return out
 
 
 def pair_histogram(box: Box, dr: float, nbins: int, out=None):
@@ -503,6 +679,46 @@ def forces(box: Box):
     return out, E.value
 
 
+@dataclass
+class EmpParams:
+    """Parameters of one empirical-potential update (nd_emp_params)."""
+    kT: float
+    sigma: float = 0.3
+    n_terms: int = 30
+    feedback: float = 1.0
+    ridge: float = 1e-6
+    id_weight: float = 1.0
+    emp_max: float = 0.0
+
+    def c(self):
+        return nd_emp_params(self.sigma, self.n_terms, 0, self.feedback, self.kT, self.ridge, self.id_weight,
+                             self.emp_max)
+
+
+def emp_update(box: Box, params: EmpParams, W, self_terms, g, dr, Q, S_exp):
+    """One EMP update of the box's tables from measured profiles S_exp [n_prof, nQ]
+    (device tensor), their Eq. 1 weights W [n_prof, P] and flat terms, and the
+    model's g [P, nbins].  Returns (dS [n_prof, nQ], EMP [P, n_pts],
+    coefficients [P, n_terms]) as device tensors."""
+    torch = _torch()
+    box._sync_stream()
+    W = np.ascontiguousarray(np.asarray(W, dtype=np.float64))
+    st = _host_f64(self_terms, W.shape[0])
+    g = g.to(torch.float64).contiguous()
+    Q = Q.to(device=g.device, dtype=torch.float64).contiguous()
+    S_exp = S_exp.to(device=g.device, dtype=torch.float64).contiguous()
+    n_prof, nQ = S_exp.shape
+    dS = torch.empty((n_prof, nQ), dtype=torch.float64, device=g.device)
+    emp = torch.empty((box.P, box._n_pts), dtype=torch.float64, device=g.device)
+    coef = torch.empty((box.P, params.n_terms), dtype=torch.float64, device=g.device)
+    p = params.c()
+    box.version += 1
+    _check(lib().nd_emp_update(box.handle, C.byref(p), n_prof, W.ctypes.data, st.ctypes.data, _dptr(g),
+                               g.shape[1], float(dr), _dptr(Q), nQ, _dptr(S_exp), _dptr(dS), _dptr(emp),
+                               _dptr(coef)))
+    return dS, emp, coef
+
+
 def pair_counts_total(box: Box):
     """Number of distinct pairs per pair type (nd_box_pair_counts)."""
     out = np.zeros(box.P)
@@ -553,26 +769,31 @@ def _make_autograd():
 
         @staticmethod
         def forward(ctx, xyz, box, dr, nbins, sigma, Q, S_target, b):
-            box.set_coords(xyz, keep_energy=True)
+            # new coordinates: the box's running energy is stale from here
+            box.set_coords(xyz, keep_energy=False)
             nh = hist_broad(box, dr, nbins, sigma)
             npairs = pair_counts_total(box)
-            V = box.L ** 3
-            rho = box.N / V
+            V, rho = box.density()
             w, self_term = eq1_weights(box, b)
             g = gr_normalize_f64(nh, dr, V, npairs)
             S = sq_transform(g, dr, rho, w, self_term, Q)
             c2, dS = chi2(S, S_target)
-            ctx.save_for_backward(dS, Q)
+            ctx.save_for_backward(dS, Q, xyz)
             ctx.box, ctx.dr, ctx.nbins, ctx.sigma = box, dr, nbins, sigma
             ctx.rho, ctx.V, ctx.w, ctx.npairs = rho, V, w, npairs
+            ctx.version = box.version
             return c2[0]
 
         @staticmethod
         def backward(ctx, grad_out):
-            dS, Q = ctx.saved_tensors
+            dS, Q, xyz = ctx.saved_tensors
+            # the gradient is taken at the x forward saw: restore it if the
+            # box has moved on since (another forward, a sweep, set_coords)
+            if ctx.box.version != ctx.version:
+                ctx.box.set_coords(xyz, keep_energy=False)
             A = sq_adjoint(dS, ctx.nbins, ctx.dr, ctx.rho, ctx.V, ctx.w, ctx.npairs, Q)
             gx = hist_broad_backward(ctx.box, ctx.dr, ctx.nbins, ctx.sigma, A)
-            return (grad_out * gx).to(torch.float32), None, None, None, None, None, None, None
+            return (grad_out * gx).to(xyz.dtype), None, None, None, None, None, None, None
 
     class EnergyFn(torch.autograd.Function):
         """Total energy of the box at xyz; backward gives dE/dx from nd_forces."""
@@ -582,12 +803,13 @@ def _make_autograd():
             box.set_coords(xyz, keep_energy=False)
             grad, E = forces(box)
             ctx.save_for_backward(grad)
+            ctx.x_dtype = xyz.dtype
             return torch.tensor(E, dtype=torch.float64, device=xyz.device)
 
         @staticmethod
         def backward(ctx, grad_out):
             (grad,) = ctx.saved_tensors
-            return (grad_out * grad).to(torch.float32), None
+            return (grad_out * grad).to(ctx.x_dtype), None
 
     return Chi2Fn, EnergyFn
 

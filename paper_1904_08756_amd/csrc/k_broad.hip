@@ -916,7 +916,41 @@ void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, c
     ND_HIP(hipGetLastError());
 }
 
+// Scratch bytes of the forces for N atoms and a grid of G blocks: the two
+// integer words of the [3][N] gradient sums, the blocks' energies, the shift.
+size_t forces_scratch_bytes(int N, long long G)
+{
+    return sizeof(long long) * 2 * 3 * (size_t)N + sizeof(double) * (size_t)G + 256;
+}
+
+// Grid of the forces kernel and its LDS bytes for box b.
+static long long forces_grid(const nd_box *b, size_t &lds_total)
+{
+    const int P = b->P;
+    const size_t lds = sizeof(unsigned long long) * 12 * GTILE + sizeof(double) * 3 * GTILE +
+                       sizeof(int) * (2 * GTILE + 16) + sizeof(float) * (size_t)P * b->n_pts;
+    const size_t lds_queue = (sizeof(double) + 2 * sizeof(int)) * GQ * (GTILE / 64) + sizeof(double) * (GTILE / 64);
+    if (lds + lds_queue > 160 * 1024) fail(ND_E_UNSUPPORTED, "potential table does not fit in LDS");
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / (lds + lds_queue + 1024)));
+    const int nt = (b->N + GTILE - 1) / GTILE;
+    const long long ntp = (long long)nt * (nt + 1) / 2;
+    long long G = (long long)cu_count(b->device) * per_cu;
+    if (G > ntp) G = ntp;
+    lds_total = lds;
+    return G;
+}
+
 void launch_forces(nd_box *b, double *d_grad, double *d_E)
+{
+    size_t lds = 0;
+    const long long G = forces_grid(b, lds);
+    char *ws = static_cast<char *>(workspace(b, forces_scratch_bytes(b->N, G)));
+    launch_forces_in(b, d_grad, d_E, ws, G, true);
+}
+
+// The forces with a caller-provided scratch of forces_scratch_bytes(N, G)
+// bytes (G at most max_grid); profiling events only when `prof`.
+void launch_forces_in(nd_box *b, double *d_grad, double *d_E, char *ws, long long max_grid, bool prof)
 {
     ForceArgs a;
     a.xyz = b->xyz;
@@ -936,15 +970,10 @@ void launch_forces(nd_box *b, double *d_grad, double *d_E)
     a.inv_h = 1.0 / b->h;
     // a word's sum over an atom's N - 1 pairs: hi below 2^38 N, lo below 2^32 N
     if (b->N > (1 << 24)) fail(ND_E_UNSUPPORTED, "too many atoms for the forces' gradient sums");
-    const size_t lds = sizeof(unsigned long long) * 12 * GTILE + sizeof(double) * 3 * GTILE +
-                       sizeof(int) * (2 * GTILE + 16) + sizeof(float) * (size_t)a.P * a.n_pts;
-    const size_t lds_queue = (sizeof(double) + 2 * sizeof(int)) * GQ * (GTILE / 64) + sizeof(double) * (GTILE / 64);
-    if (lds + lds_queue > 160 * 1024) fail(ND_E_UNSUPPORTED, "potential table does not fit in LDS");
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / (lds + lds_queue + 1024)));
-    long long G = (long long)cu_count(b->device) * per_cu;
-    if (G > a.ntp) G = a.ntp;
+    size_t lds = 0;
+    long long G = forces_grid(b, lds);
+    if (G > max_grid) G = max_grid;  // a persistent grid: fewer blocks take more tile pairs each
     const long long n = 3LL * b->N;
-    char *ws = static_cast<char *>(workspace(b, sizeof(long long) * 2 * (size_t)n + sizeof(double) * (size_t)G + 256));
     a.gsum = reinterpret_cast<long long *>(ws);
     a.epart = reinterpret_cast<double *>(ws + sizeof(long long) * 2 * (size_t)n);
     a.shift = reinterpret_cast<int *>(ws + sizeof(long long) * 2 * (size_t)n + sizeof(double) * (size_t)G);
@@ -952,7 +981,7 @@ void launch_forces(nd_box *b, double *d_grad, double *d_E)
                        reinterpret_cast<double *>(a.gsum), 2 * n);
     ND_HIP(hipGetLastError());
     {
-        ProfScope ps(b, ND_PROF_FORCES);
+        ProfScope ps(b, prof ? ND_PROF_FORCES : -1);
         hipLaunchKernelGGL(k_forces, dim3((unsigned)G), dim3(GTILE), lds, b->stream, a);
         ND_HIP(hipGetLastError());
     }

@@ -2,11 +2,13 @@
 // N(r), Sec. "Acceleration method") and the full-box total energy.
 //
 // Layout: the i side of a tile pair is held one atom per thread in
-// registers; the j side is staged in LDS (FP64 coordinates plus species) and
-// read by broadcast.  Counts go to an LDS-private u32 histogram per block;
-// each block visits many tile pairs (persistent grid), then writes its
-// histogram to a per-block slice that one reduction kernel sums into u64 in
-// a fixed order, so counts are exact and independent of scheduling.
+// registers; the j side is staged in LDS (fixed-point and float32
+// coordinates plus the histogram row offsets) and read by broadcast.
+// Counts go to an LDS-private u32 histogram per block; each block visits
+// many tile pairs (persistent grid) and adds its nonzero counters to the
+// u64 counts with integer atomics when it is done, and after every
+// FLUSH_TILES tile pairs, before a u32 counter could overflow.  Integer
+// sums are exact in any order, so the counts do not depend on scheduling.
 #include "nd_internal.h"
 #include "nd_pair.h"
 
@@ -16,6 +18,9 @@
 namespace {
 
 constexpr int TILE = 256;  // atoms per tile = threads per block
+// A tile pair adds at most TILE * TILE counts, so a u32 LDS counter holds
+// the counts of this many tile pairs (65535 * 65536 < 2^32).
+constexpr long long FLUSH_TILES = 65535;
 
 // Fractional coordinates s = x / L in FP64, stored as float32 hi + lo;
 // hi.w holds the species and lo.w the atom's rigid unit, both as int bits.
@@ -37,6 +42,27 @@ __global__ void k_pos4_from_xyz(const float *__restrict__ xyz, const uint8_t *__
     q.w = __int_as_float(unit_of[i]);  // read by the Metropolis cell scan
     pos4[i] = p;
     poslo[i] = q;
+}
+
+// Coordinates given in device memory: each value wrapped into [0, L) as
+// x - L floor(x / L) in FP64 and rounded to float32 (a result of L is 0);
+// a value that is not finite sets *bad.
+__global__ void k_wrap_coords(const float *__restrict__ in, float *__restrict__ out, long long n, double L,
+                              int *__restrict__ bad)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = in[i];
+    if (!isfinite(v)) {
+        atomicOr(bad, 1);
+        out[i] = 0.0f;
+        return;
+    }
+    const double x = (double)v;
+    const double w = x - L * floor(x / L);
+    float f = (float)w;
+    if ((double)f >= L || f < 0.0f) f = 0.0f;
+    out[i] = f;
 }
 
 // Upper-triangle tile pair t -> (I, J), I <= J < nt, row-major.
@@ -62,9 +88,7 @@ struct HistArgs {
     float fix_scale;        // (L / 2^32) / dr: fixed-point length to bins
     float nb_hi;            // nbins + 2 edge_eps: shifted candidates beyond are out of range
     float edge_eps;
-    unsigned *partial;      // [gridDim.x][P * nbins] (one box per launch)
-    unsigned long long *zero_out;  // counts cleared by block 0 for the reduction that follows (or null)
-    unsigned long long *out;  // [P * nbins] counts, accumulated atomically (several boxes per launch)
+    unsigned long long *out;  // [P * nbins] counts (cleared beforehand), accumulated atomically
     long long tile0;        // first global tile-pair index of this box (several boxes per launch)
 };
 
@@ -198,24 +222,38 @@ __device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, i
     }
 }
 
+// Adds the block's nonzero LDS counters to the u64 counts and clears them.
+__device__ __forceinline__ void hist_flush(const HistArgs &a, const HistLds &h)
+{
+    __syncthreads();
+    const int nq = a.P * a.nbins;
+    for (int q = threadIdx.x; q < nq; q += TILE) {
+        const unsigned v = h.hist[q];
+        if (v) {
+            atomicAdd(&a.out[q], (unsigned long long)v);
+            h.hist[q] = 0u;
+        }
+    }
+    __syncthreads();
+}
+
 template <bool PACKED>
 __global__ __launch_bounds__(TILE) void k_pair_hist(HistArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const HistLds h = hist_lds(smem);
-    const int nq = a.P * a.nbins;
-    const int tid = threadIdx.x;
-    if (blockIdx.x == 0 && a.zero_out)
-        for (int q = tid; q < nq; q += TILE) a.zero_out[q] = 0ull;
     hist_begin(a, h);
+    long long since = 0;
     for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
         int I, J;
         tri_index(t, a.nt, I, J);
         hist_tile<PACKED>(a, h, I, J);
+        if (++since == FLUSH_TILES) {
+            hist_flush(a, h);
+            since = 0;
+        }
     }
-    __syncthreads();
-    unsigned *out = a.partial + (size_t)blockIdx.x * nq;
-    for (int q = tid; q < nq; q += TILE) out[q] = h.hist[q];
+    hist_flush(a, h);
 }
 
 // Several boxes in one persistent launch.  The tile pairs of all boxes form
@@ -229,7 +267,6 @@ __global__ __launch_bounds__(TILE) void k_pair_hist_multi(const HistArgs *__rest
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const HistLds h = hist_lds(smem);
-    const int tid = threadIdx.x;
     long long t = (long long)blockIdx.x * per;
     const long long t_end = min(total, t + per);
     if (t >= t_end) return;
@@ -248,18 +285,17 @@ __global__ __launch_bounds__(TILE) void k_pair_hist_multi(const HistArgs *__rest
         const long long box_end = min(t_end, a.tile0 + a.ntp);
         if (t < box_end) {
             hist_begin(a, h);
+            long long since = 0;
             for (; t < box_end; ++t) {
                 int I, J;
                 tri_index(t - a.tile0, a.nt, I, J);
                 hist_tile<PACKED>(a, h, I, J);
+                if (++since == FLUSH_TILES) {
+                    hist_flush(a, h);
+                    since = 0;
+                }
             }
-            __syncthreads();
-            const int nq = a.P * a.nbins;
-            for (int q = tid; q < nq; q += TILE) {
-                const unsigned v = h.hist[q];
-                if (v) atomicAdd(&a.out[q], (unsigned long long)v);
-            }
-            __syncthreads();
+            hist_flush(a, h);
         }
         ++bi;
         if (bi >= n_boxes) break;
@@ -273,16 +309,12 @@ __global__ void k_zero_u64_multi(const HistArgs *__restrict__ boxes)
     if (q < a.P * a.nbins) a.out[q] = 0ull;
 }
 
-// Sum of the per-block partial histograms: block (x, y) adds partials y,
-// y + gridDim.y, ... of counters 256 x .. 256 x + 255 and adds the sum to
-// the (cleared) u64 counts with an integer atomic -- exact in any order.
-__global__ void k_hist_reduce(const unsigned *__restrict__ partial, int G, int nq, uint64_t *__restrict__ counts)
+// Clears n u64 counters (a fill kernel rather than a memset node, so the
+// sequence can be captured into a graph).
+__global__ void k_zero_u64(unsigned long long *__restrict__ p, int n)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
-    uint64_t s = 0;
-    for (int g = blockIdx.y; g < G; g += gridDim.y) s += partial[(size_t)g * nq + q];
-    if (s) atomicAdd(reinterpret_cast<unsigned long long *>(counts) + q, (unsigned long long)s);
+    if (q < n) p[q] = 0ull;
 }
 
 // ---------------------------------------------------------------- energy
@@ -411,6 +443,14 @@ void launch_pos4_from_xyz(nd_box *b)
     ND_HIP(hipGetLastError());
 }
 
+void launch_wrap_coords(nd_box *b, const float *d_in, float *d_out, int *d_bad)
+{
+    const long long n = 3LL * b->N;
+    hipLaunchKernelGGL(k_wrap_coords, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, b->stream, d_in, d_out, n, b->L,
+                       d_bad);
+    ND_HIP(hipGetLastError());
+}
+
 }  // namespace nd
 
 namespace {
@@ -459,15 +499,14 @@ void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
     HistArgs a = make_hist_args(b, dr, nbins);
     const int nq = a.P * nbins;
     const size_t lds = hist_lds_bytes(nq);
-    int per_cu = (int)std::max<size_t>(1, std::min<size_t>(5, (160 * 1024) / lds));
+    nd_tuning te;
+    const int want = (tune_lookup(ND_TUNE_BOX, b->N, &te) && te.hist_blocks_per_cu > 0) ? te.hist_blocks_per_cu : 5;
+    int per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)want, (160 * 1024) / lds));
     long long G = (long long)cu_count(b->device) * per_cu;
     if (G > a.ntp) G = a.ntp;
-    // u32 counters: pairs per block must stay below 2^32
-    long long tiles_per_block = (a.ntp + G - 1) / G;
-    if ((double)tiles_per_block * TILE * TILE >= 4294967295.0) fail(ND_E_UNSUPPORTED, "box too large for u32 counters");
-    size_t pbytes = sizeof(unsigned) * (size_t)G * nq;
-    a.partial = static_cast<unsigned *>(workspace(b, pbytes));
-    a.zero_out = reinterpret_cast<unsigned long long *>(d_counts);
+    a.out = reinterpret_cast<unsigned long long *>(d_counts);
+    hipLaunchKernelGGL(k_zero_u64, dim3((nq + 255) / 256), dim3(256), 0, b->stream, a.out, nq);
+    ND_HIP(hipGetLastError());
     {
         ProfScope ps(b, ND_PROF_PAIR_HIST);
         // row offsets of up to two species fit the spare lane of the j records
@@ -477,10 +516,6 @@ void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
             hipLaunchKernelGGL(k_pair_hist<false>, dim3((unsigned)G), dim3(TILE), lds, b->stream, a);
         ND_HIP(hipGetLastError());
     }
-    const int slices = (int)std::min<long long>(G, 64);
-    hipLaunchKernelGGL(k_hist_reduce, dim3((nq + 255) / 256, slices), dim3(256), 0, b->stream, a.partial, (int)G, nq,
-                       d_counts);
-    ND_HIP(hipGetLastError());
 }
 
 // ---- several boxes in one launch (the batched form)
@@ -519,12 +554,16 @@ void hist_multi_plan(HistMulti *m, nd_box *const *boxes, int n, double dr, const
         m->boxes.push_back(a);
     }
     m->lds = hist_lds_bytes(m->max_nq);
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(5, (160 * 1024) / m->lds));
+    long long total_atoms = 0;
+    for (int i = 0; i < n; ++i) total_atoms += boxes[i]->N;
+    nd_tuning te;
+    const int want =
+        (tune_lookup(ND_TUNE_BATCH, total_atoms, &te) && te.hist_blocks_per_cu > 0) ? te.hist_blocks_per_cu : 5;
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)want, (160 * 1024) / m->lds));
     long long G = (long long)cu_count(boxes[0]->device) * per_cu;
     if (G > m->total) G = m->total;
     m->per = (m->total + G - 1) / G;
     m->G = (int)((m->total + m->per - 1) / m->per);
-    if ((double)m->per * TILE * TILE >= 4294967295.0) fail(ND_E_UNSUPPORTED, "boxes too large for u32 counters");
     if (m->cap < m->boxes.size() || !m->d_boxes) {
         dfree(m->d_boxes);
         m->d_boxes = static_cast<HistArgs *>(dmalloc(sizeof(HistArgs) * m->boxes.size()));

@@ -3,8 +3,10 @@
 // against every atom (Sec. "Acceleration method": the per-step work that is
 // proportional to N).
 //
-// Trials are processed in batches of K consecutive trials.  In sequential
-// order consecutive trials move distinct units, and a trial's proposal
+// Trials are processed in batches of up to K consecutive trials that move
+// distinct units: in sequential order any K <= n_units consecutive trials
+// do; in random order a batch is cut before the first trial whose unit is
+// already in it.  A trial's proposal
 // depends only on (seed, trial) and its own unit's positions, so the K
 // proposals and their energy changes dE0_k against the configuration at the
 // start of the batch can be computed together.  The sequential chain is then
@@ -49,7 +51,7 @@ constexpr double TWO_PI = 6.283185307179586;
 // SplitMix64 (Steele, Lea, Flood 2014): output i of the generator seeded
 // with s is the 64-bit finalizer applied to s + (i + 1) * gamma.  Draw d of
 // trial t is output 16 t + d, mapped to [0, 1) with 53 bits.
-__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i)
+__host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i)
 {
     uint64_t z = seed + 0x9E3779B97F4A7C15ull * (i + 1ull);
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -57,9 +59,19 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t i)
     return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ double draw(uint64_t seed, uint64_t t, int d)
+__host__ __device__ __forceinline__ double draw(uint64_t seed, uint64_t t, int d)
 {
     return (double)(splitmix64(seed, 16ull * t + (uint64_t)d) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Unit moved by trial t: t mod n_units in sequential order; in random order
+// floor(u_7 n_units) of the trial's draw 7 (the last unit if the product
+// rounds up to n_units).  The host plans batches with the same function.
+__host__ __device__ __forceinline__ int trial_unit(int order, uint64_t seed, uint64_t t, int n_units)
+{
+    if (order == ND_ORDER_SEQ) return (int)(t % (uint64_t)n_units);
+    const int u = (int)floor(draw(seed, t, 7) * (double)n_units);
+    return u < n_units ? u : n_units - 1;
 }
 
 // Wrap into [0, L) and round to float32; a value that rounds to L is 0.
@@ -84,7 +96,7 @@ struct ProposeArgs {
     const float4 *pos4;
     const float4 *poslo;
     const int32_t *uoff;
-    int N, n_units;
+    int N, n_units, order;
     double L, invL, max_disp, max_rot, kT;
     uint64_t seed, t0;
     int kb, kcap;
@@ -111,7 +123,7 @@ __device__ __forceinline__ double accept_threshold(double u, double kT)
 __device__ __forceinline__ void propose_one(const ProposeArgs &a, int k)
 {
     const uint64_t t = a.t0 + (uint64_t)k;
-    const int u = (int)(t % (uint64_t)a.n_units);
+    const int u = trial_unit(a.order, a.seed, t, a.n_units);
     const int a0 = a.uoff[u];
     const int na = a.uoff[u + 1] - a0;
     const int N = a.N;
@@ -194,6 +206,9 @@ __device__ __forceinline__ void propose_one(const ProposeArgs &a, int k)
         T->new_x[at][0] = nx0;
         T->new_x[at][1] = nx1;
         T->new_x[at][2] = nx2;
+        T->old_x[at][0] = a.xyz[a0 + at];
+        T->old_x[at][1] = a.xyz[N + a0 + at];
+        T->old_x[at][2] = a.xyz[2 * N + a0 + at];
         float d;
         d = o.x - ref.x; sx += d - rintf(d);
         d = o.y - ref.y; sy += d - rintf(d);
@@ -1006,8 +1021,12 @@ struct DecideArgs {
     // defer: the final dE sums, counters and trace are left to a later launch
     // (k_mc_final's body); the decision stores what they need
     int defer;
-    uint8_t *acc_out;  // [kb] 1: accepted
+    uint8_t *acc_out;  // [kb] 1: accepted (written when not null)
     double *thr_out;   // [kb] acceptance threshold -kT ln u
+    // running histogram: the unit of each accepted trial k is tagged
+    // tag_base + k (null when no histogram is tracked)
+    long long *moved_tag;
+    long long tag_base;
 };
 
 // exclusive prefix sum over the block of one value per thread
@@ -1215,7 +1234,7 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
         // final dE (the same in-order sum as an exact decision), counters, trace
         double dsum = 0.0;
         long long nacc = 0, ntie = 0;
-        if (a.defer)
+        if (a.acc_out)
             for (int k = tid; k < kb; k += DEC_THREADS) a.acc_out[k] = s_st[k] == ST_ACC ? 1 : 0;
         for (int k = tid; k < kb && !a.defer; k += DEC_THREADS) {
             double e = s_e[k];
@@ -1272,6 +1291,7 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                     if (at < s_na[k]) {
                         const nd::Trial &T = a.trials[k];
                         idx[u] = s_a0[k] + at;
+                        if (a.moved_tag && at == 0) a.moved_tag[T.unit] = a.tag_base + k;
                         hi[u] = ld4(&T.new_hi[at]);
                         lo[u] = ld4(&T.new_lo[at]);
                         nx[u][0] = ldg(&T.new_x[at][0]);
@@ -1603,18 +1623,22 @@ void ensure_work(nd_box *b, int K, int n_jb)
 
 namespace nd {
 
-int mc_batch_size(nd_box *b, const nd_mc_params *p)
+int mc_batch_size(nd_box *b, const nd_mc_params *p, double target)
 {
-    // about 18 interacting earlier trials expected for the last trial of a
-    // batch; at most KMAX and half the number of units
+    // about `target` (18 unless tuned) interacting earlier trials expected
+    // for the last trial of a batch; at most KMAX and half the number of units
     int K;
     if (p->k_batch > 0) {
         K = p->k_batch;
     } else {
+        if (!(target > 0.0)) {
+            nd_tuning e;
+            target = (tune_lookup(ND_TUNE_BOX, b->N, &e) && e.batch_target > 0.0) ? e.batch_target : 18.0;
+        }
         const double ext = (b->max_na > 1 ? 1.2 : 0.0) + p->max_disp * 1.8;
         const double reach = b->rc + 2.0 * ext;
         const double f = (4.0 / 3.0) * M_PI * reach * reach * reach / (b->L * b->L * b->L);
-        K = (int)std::min(1e9, 18.0 / std::max(f, 1e-9));
+        K = (int)std::min(1e9, target / std::max(f, 1e-9));
         K = std::min(K, std::max(1, b->n_units / 2));
     }
     return std::max(1, std::min({K, KMAX, b->n_units}));
@@ -1669,8 +1693,9 @@ int per_slab_blocks(int kb, int nw)
 // blocks).  A trial's chain of dependent loads is shorter with more waves;
 // more trials at once beat that when the GPU would otherwise take them in
 // several rounds.
-int pick_scan_nw(long long trials, int ncu)
+int pick_scan_nw(long long trials, int ncu, int tuned = 0)
 {
+    if (tuned > 0) return tuned;
     const long long slots = 16LL * ncu * 5 / 4;
     if (4 * trials <= slots) return 4;
     if (2 * trials <= slots) return 2;
@@ -1687,6 +1712,7 @@ ProposeArgs proposal_args(const nd_box *b, const nd_mc_params *p, uint64_t seed,
     pa.uoff = b->uoff;
     pa.N = b->N;
     pa.n_units = b->n_units;
+    pa.order = p->order;
     pa.L = b->L;
     pa.invL = 1.0 / b->L;
     pa.max_disp = p->max_disp;
@@ -1772,6 +1798,13 @@ DecideArgs decide_args(const nd_box *b, const nd_mc_params *p, const McConsts &k
     da.defer = 0;
     da.acc_out = nullptr;
     da.thr_out = nullptr;
+    da.moved_tag = nullptr;
+    da.tag_base = 0;
+    if (b->track.on) {
+        da.acc_out = w.acc_flags + (size_t)buf * w.cap_k;
+        da.moved_tag = b->track.moved;
+        da.tag_base = nd::TRACK_TAG_STRIDE * (b->track.serial++);
+    }
     return da;
 }
 
@@ -1802,6 +1835,33 @@ FinalArgs final_args(const nd_box *b, const nd_mc_params *p, const McConsts &k, 
     return f;
 }
 
+// Sizes of the batches of trials first .. first + n - 1: at most K each; in
+// random order a batch also ends before the first trial whose unit it
+// already holds, so the trials of a batch always move distinct units.
+std::vector<int> batch_sizes(const nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n, int K)
+{
+    std::vector<int> out;
+    if (p->order == ND_ORDER_SEQ) {
+        for (int64_t done = 0; done < n; done += K) out.push_back((int)std::min<int64_t>(K, n - done));
+        return out;
+    }
+    std::vector<int64_t> stamp((size_t)b->n_units, -1);
+    int64_t batch = 0;
+    int size = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const int u = trial_unit(p->order, seed, first + (uint64_t)k, b->n_units);
+        if (size == K || stamp[(size_t)u] == batch) {
+            out.push_back(size);
+            ++batch;
+            size = 0;
+        }
+        stamp[(size_t)u] = batch;
+        ++size;
+    }
+    if (size > 0) out.push_back(size);
+    return out;
+}
+
 // Plan of n trials of one box with the cell scan.
 struct McPlan {
     int K = 0, maxnu = 1;
@@ -1814,9 +1874,11 @@ struct McPlan {
 // Every batch's launch arguments and cell rebuild points, in order.  The
 // box's cell bookkeeping is advanced as the launches will advance it.
 void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n,
-                   const nd_mc_trace *trace, bool force_rebuild, McPlan &pl)
+                   const nd_mc_trace *trace, bool force_rebuild, McPlan &pl, double target = 0.0)
 {
-    const int K = nd::mc_batch_size(b, p);
+    const int K = nd::mc_batch_size(b, p, target);
+    nd_tuning te;
+    const int tuned_nw = nd::tune_lookup(ND_TUNE_BOX, b->N, &te) ? te.scan_waves : 0;
     ensure_work(b, K, 1);
     nd::cells_ensure(b);
     const McWork &w = b->mc;
@@ -1825,16 +1887,19 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
     pl.maxnu = pick_maxnu(b->max_na);
     pl.lds = mc_table_lds(b);
     pl.batches.clear();
-    pl.first = proposal_args(b, p, seed, first, (int)std::min<int64_t>(K, n), 0, K);
+    const std::vector<int> sizes = batch_sizes(b, p, seed, first, n, K);
+    pl.first = proposal_args(b, p, seed, first, sizes.empty() ? 0 : sizes[0], 0, K);
     if (force_rebuild) b->cells.valid = false;
-    // the next batch's units are disjoint from this batch's when 2K <= n_units:
-    // propose it alongside this batch's scan instead of after the commit
-    const bool early_propose = 2 * K <= b->n_units;
+    // in sequential order the next batch's units are disjoint from this
+    // batch's when 2K <= n_units: propose it alongside this batch's scan
+    // instead of after the commit (in random order they may repeat)
+    const bool early_propose = p->order == ND_ORDER_SEQ && 2 * K <= b->n_units;
     FinalArgs prev_fin{};
     prev_fin.kb = 0;
     int buf = 0;
-    for (int64_t done = 0; done < n;) {
-        const int kb = (int)std::min<int64_t>(K, n - done);
+    size_t bi = 0;
+    for (int64_t done = 0; done < n; ++bi) {
+        const int kb = sizes[bi];
         const nd::Trial *trials = w.trials + (size_t)buf * K;
         const float4 *spheres = w.spheres + (size_t)buf * K;
         McLaunch L;
@@ -1852,7 +1917,7 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         ca.sposlo = b->cells.sposlo;
         ca.slab = slab_buffer(b, buf);
         ca.kcap = w.cap_k;
-        ca.nw = pick_scan_nw(kb, nd::cu_count(b->device));
+        ca.nw = pick_scan_nw(kb, nd::cu_count(b->device), tuned_nw);
         ca.per_slab = per_slab_blocks(kb, ca.nw);
         ca.cstart = b->cells.start;
         ca.tab = b->tab;
@@ -1869,7 +1934,7 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         ca.dE0 = w.dE0 + (size_t)buf * w.cap_k;
         ca.S0 = w.S0 + (size_t)buf * w.cap_k;
         const int64_t done_next = done + kb;
-        const int kb_next = (int)std::max<int64_t>(0, std::min<int64_t>(K, n - done_next));
+        const int kb_next = bi + 1 < sizes.size() ? sizes[bi + 1] : 0;
         const ProposeArgs nx = proposal_args(b, p, seed, first + (uint64_t)done_next, kb_next, buf ^ 1, K);
         L.next = nx;
         L.late = nx;
@@ -1967,19 +2032,21 @@ void mc_run_full(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first
     ND_HIP(hipGetLastError());
     if (n == 0) return;
     int buf = 0;
+    const std::vector<int> sizes = batch_sizes(b, p, seed, first, n, K);
     {
-        ProposeArgs pa = proposal_args(b, p, seed, first, (int)std::min<int64_t>(K, n), buf, K);
+        ProposeArgs pa = proposal_args(b, p, seed, first, sizes[0], buf, K);
         nd::ProfScope ps(b, ND_PROF_MC_PROPOSE);
         hipLaunchKernelGGL(k_mc_propose, dim3((pa.kb + 63) / 64), dim3(64), 0, b->stream, pa);
         ND_HIP(hipGetLastError());
     }
-    for (int64_t done = 0; done < n;) {
-        const int kb = (int)std::min<int64_t>(K, n - done);
+    size_t bi = 0;
+    for (int64_t done = 0; done < n; ++bi) {
+        const int kb = sizes[bi];
         nd::Trial *trials = w.trials + (size_t)buf * K;
         float4 *spheres = w.spheres + (size_t)buf * K;
         const CorrArgs cr = corr_args(b, k, trials, spheres, kb, K, buf);
         const int64_t done_next = done + kb;
-        const int kb_next = (int)std::max<int64_t>(0, std::min<int64_t>(K, n - done_next));
+        const int kb_next = bi + 1 < sizes.size() ? sizes[bi + 1] : 0;
         const ProposeArgs late = proposal_args(b, p, seed, first + (uint64_t)done_next, kb_next, buf ^ 1, K);
         const int tg = (int)std::max<long long>(1, std::min<long long>(MAX_TG, ((long long)kb * n_jb) / (2LL * ncu)));
         ScanArgs sa;
@@ -2024,6 +2091,7 @@ void mc_run_full(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first
         CorrArgs none{};
         none.kb = 0;
         launch_decide(b, maxnu, 1, da, late, none);
+        if (da.moved_tag) nd::track_launch(b, da.trials, da.acc_out, da.kb, da.tag_base);
         if (b->cells.valid) b->cells.trials_since_build += kb;
         done = done_next;
         buf ^= 1;
@@ -2062,6 +2130,7 @@ void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int
         default: launch_scan_corr<8>(b, L.ca, L.cr, L.next, L.fin, pl.lds); break;
         }
         launch_decide(b, pl.maxnu, L.dblk, L.da, L.late, L.cn);
+        if (L.da.moved_tag) track_launch(b, L.da.trials, L.da.acc_out, L.da.kb, L.da.tag_base);
     }
     if (pl.last_fin.kb > 0) {
         hipLaunchKernelGGL(k_mc_final, dim3(1), dim3(FIN_THREADS), 0, b->stream, pl.last_fin);
@@ -2096,17 +2165,23 @@ void mc_multi_destroy(McMulti *m)
 }
 
 void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *params, const uint64_t *seed,
-                   const uint64_t *first, const int64_t *n_trials, std::vector<long long> &sig)
+                   const uint64_t *first, const int64_t *n_trials, const nd_mc_trace *trace,
+                   std::vector<long long> &sig)
 {
     std::vector<McPlan> plans(n);
     m->maxnu = 1;
     m->lds = 0;
     int n_rounds = 0;
+    long long total_atoms = 0;
+    for (int i = 0; i < n; ++i) total_atoms += boxes[i]->N;
+    nd_tuning te;
+    const bool tuned = tune_lookup(ND_TUNE_BATCH, total_atoms, &te);
     for (int i = 0; i < n; ++i) {
         nd_box *b = boxes[i];
         // every run starts from freshly built cells, so the launch structure
         // depends only on the trial counts and batch sizes
-        mc_plan_cells(b, &params[i], seed[i], first[i], n_trials[i], nullptr, true, plans[i]);
+        mc_plan_cells(b, &params[i], seed[i], first[i], n_trials[i], trace ? &trace[i] : nullptr, true, plans[i],
+                      tuned ? te.batch_target : 0.0);
         m->maxnu = std::max(m->maxnu, plans[i].maxnu);
         m->lds = std::max(m->lds, plans[i].lds);
         n_rounds = std::max(n_rounds, (int)plans[i].batches.size());
@@ -2140,7 +2215,7 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
         long long round_trials = 0;
         for (int i = 0; i < n; ++i)
             if (r < (int)plans[i].batches.size()) round_trials += plans[i].batches[r].ca.kb;
-        const int nw = pick_scan_nw(round_trials, ncu);
+        const int nw = pick_scan_nw(round_trials, ncu, tuned ? te.scan_waves : 0);
         m->r_nw[r] = nw;
         for (int i = 0; i < n; ++i) {
             if (r >= (int)plans[i].batches.size()) continue;
@@ -2154,6 +2229,7 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
             // each box's decision keeps its own final sums
             L.da.defer = 0;
             L.fin.kb = 0;
+            L.da.moved_tag = nullptr;
             L.ca.nw = nw;
             L.ca.per_slab = per_slab_blocks(L.ca.kb, nw);
             L.nblk = scan_front_blocks(L.cr.kb, L.next.kb, 0) + N_SLAB * L.ca.per_slab;

@@ -6,11 +6,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "nd_internal.h"
+
 
 namespace {
 thread_local std::string g_last_error;
@@ -101,7 +103,6 @@ void check_mc_params(const nd_box *b, const nd_mc_params *p)
     require(p->k_batch >= 0, ND_E_INVALID, "k_batch must be >= 0");
     require(p->order == ND_ORDER_SEQ || p->order == ND_ORDER_RANDOM, ND_E_INVALID, "unknown order");
     require(p->scan == ND_SCAN_CELLS || p->scan == ND_SCAN_FULL, ND_E_INVALID, "unknown scan mode");
-    if (p->order == ND_ORDER_RANDOM) nd::fail(ND_E_UNSUPPORTED, "ND_ORDER_RANDOM is not implemented");
     require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
 }
 
@@ -156,9 +157,34 @@ size_t ckpt_size(const nd_box *b, bool cells, int ncell)
     return n + sizeof(uint64_t);
 }
 
+std::mutex g_tune_mu;
+std::vector<nd_tuning> g_tune;
+
+void check_tuning(const nd_tuning &e)
+{
+    require(e.kind == ND_TUNE_BOX || e.kind == ND_TUNE_BATCH, ND_E_INVALID, "tuning kind must be box or batch");
+    require(e.scan_waves == 0 || e.scan_waves == 1 || e.scan_waves == 2 || e.scan_waves == 4, ND_E_INVALID,
+            "scan_waves must be 0, 1, 2 or 4");
+    require(std::isfinite(e.batch_target) && e.batch_target >= 0.0, ND_E_INVALID, "batch_target must be >= 0");
+    require(e.hist_blocks_per_cu >= 0 && e.hist_blocks_per_cu <= 8, ND_E_INVALID,
+            "hist_blocks_per_cu must be in 0..8");
+    require(e.n_max >= 0, ND_E_INVALID, "n_max must be >= 0");
+}
+
 }  // namespace
 
 namespace nd {
+
+bool tune_lookup(int kind, long long n, nd_tuning *out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const nd_tuning &e : g_tune)
+        if (e.kind == kind && n <= e.n_max) {
+            *out = e;
+            return true;
+        }
+    return false;
+}
 
 [[noreturn]] void fail(nd_status code, const std::string &msg) { throw Error{code, msg}; }
 
@@ -221,7 +247,7 @@ static hipEvent_t take_event(nd_box *b)
 
 ProfScope::ProfScope(nd_box *box, int k) : b(box), kind(k)
 {
-    if (!(b->prof_mask & (1u << kind))) return;
+    if (kind < 0 || !(b->prof_mask & (1u << kind))) return;
     if (b->prof_pending[kind].size() >= 8192) prof_harvest(b);
     e1 = take_event(b);
     e2 = take_event(b);
@@ -282,6 +308,8 @@ static void free_box(nd_box *b)
     nd::dfree(b->uoff);
     nd::dfree(b->unit_of);
     nd::dfree(b->tab);
+    nd::dfree(b->rp);
+    nd::dfree(b->emp);
     nd::dfree(b->E);
     nd::dfree(b->mc.trials);
     nd::dfree(b->mc.partial);
@@ -303,6 +331,10 @@ static void free_box(nd_box *b)
     nd::dfree(b->bt_dev);
     nd::dfree(b->mc.acc_flags);
     nd::cells_free(b);
+    nd::dfree(b->track.counts);
+    nd::dfree(b->track.sum);
+    nd::dfree(b->track.partial);
+    nd::dfree(b->track.moved);
     nd::dfree(b->ws);
     delete[] b->h_uoff;
     delete[] b->h_species;
@@ -422,9 +454,20 @@ nd_status nd_box_destroy(nd_box *b)
 {
     return guarded([&] {
         if (!b) return;
-        DeviceGuard g(b->device);
+        // When the HIP runtime is no longer usable (a destroy reached during
+        // process teardown) the device memory goes with the process; only
+        // the host side is released.
+        int prev = -1;
+        if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(b->device) != hipSuccess) {
+            (void)hipGetLastError();
+            delete[] b->h_uoff;
+            delete[] b->h_species;
+            delete b;
+            return;
+        }
         (void)hipStreamSynchronize(b->stream);
         free_box(b);
+        if (prev >= 0) (void)hipSetDevice(prev);
     });
 }
 
@@ -485,11 +528,22 @@ nd_status nd_box_set_coords(nd_box *b, const float *xyz, int32_t where, int32_t 
             nd::launch_pos4_from_xyz(b);
             ND_HIP(hipStreamSynchronize(b->stream));
         } else {
-            ND_HIP(hipMemcpyAsync(b->xyz, xyz, bytes, hipMemcpyDeviceToDevice, b->stream));
+            // wrapped and checked in a staging copy, so that rejected input
+            // leaves the box unchanged
+            char *stage = static_cast<char *>(nd::workspace(b, bytes + 256));
+            int *bad = reinterpret_cast<int *>(stage + bytes);
+            ND_HIP(hipMemsetAsync(bad, 0, sizeof(int), b->stream));
+            nd::launch_wrap_coords(b, xyz, reinterpret_cast<float *>(stage), bad);
+            int h_bad = 0;
+            ND_HIP(hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipStreamSynchronize(b->stream));
+            require(h_bad == 0, ND_E_INVALID, "coordinate is not finite");
+            ND_HIP(hipMemcpyAsync(b->xyz, stage, bytes, hipMemcpyDeviceToDevice, b->stream));
             nd::launch_pos4_from_xyz(b);
         }
         if (!keep_energy) b->energy_valid = false;
         b->cells.valid = false;
+        b->track.valid = false;
     });
 }
 
@@ -525,14 +579,27 @@ nd_status nd_box_set_tables(nd_box *b, const float *U, int32_t n_pts, double h, 
         for (size_t i = 0; i < cnt; ++i) require(std::isfinite(U[i]), ND_E_INVALID, "table value is not finite");
         DeviceGuard g(b->device);
         float *t = static_cast<float *>(nd::dmalloc(sizeof(float) * cnt));
+        float *r = nullptr;
+        try {
+            r = static_cast<float *>(nd::dmalloc(sizeof(float) * cnt));
+        } catch (...) {
+            nd::dfree(t);
+            throw;
+        }
         hipError_t e = hipMemcpyAsync(t, U, sizeof(float) * cnt, hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(r, U, sizeof(float) * cnt, hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
         if (e != hipSuccess) {
             nd::dfree(t);
+            nd::dfree(r);
             nd::check_hip(e, "copy tables");
         }
         nd::dfree(b->tab);
+        nd::dfree(b->rp);
+        nd::dfree(b->emp);  // a new reference potential starts without EMP
+        b->emp = nullptr;
         b->tab = t;
+        b->rp = r;
         b->n_pts = n_pts;
         b->h = h;
         b->rc = r_cut;
@@ -574,6 +641,13 @@ nd_status nd_mc_sweep(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t 
         require(n_trials >= 0, ND_E_INVALID, "n_trials must be >= 0");
         check_mc_params(b, p);
         DeviceGuard g(b->device);
+        // the running energy is brought up to date first when coordinates or
+        // tables changed since it was last computed
+        if (!b->energy_valid) {
+            nd::launch_total_energy(b, b->E, nullptr);
+            b->energy_valid = true;
+        }
+        if (b->track.on && !b->track.valid) nd::track_refresh(b);
         nd::mc_run(b, p, seed, first_trial, n_trials, trace);
         if (stats) {
             long long c[2];
@@ -666,6 +740,150 @@ nd_status nd_box_pair_counts(nd_box *b, double *npairs)
         check_box(b);
         require(npairs != nullptr, ND_E_INVALID, "npairs is NULL");
         box_npairs(b, npairs);
+    });
+}
+
+nd_status nd_box_track_histogram(nd_box *b, double dr, int32_t nbins)
+{
+    return guarded([&] {
+        check_box(b);
+        DeviceGuard g(b->device);
+        if (nbins == 0) {
+            nd::track_stop(b);
+            return;
+        }
+        check_hist_range(b, dr, nbins);
+        nd::track_start(b, dr, nbins);
+    });
+}
+
+nd_status nd_box_tracked_histogram(nd_box *b, uint64_t *counts, int32_t where)
+{
+    return guarded([&] {
+        check_box(b);
+        require(counts != nullptr, ND_E_INVALID, "counts is NULL");
+        check_where(where);
+        require(b->track.on, ND_E_STATE, "no histogram is tracked (nd_box_track_histogram)");
+        DeviceGuard g(b->device);
+        if (!b->track.valid) nd::track_refresh(b);
+        const size_t bytes = sizeof(uint64_t) * (size_t)b->P * b->track.nbins;
+        if (where == ND_HOST) {
+            ND_HIP(hipMemcpyAsync(counts, b->track.counts, bytes, hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipStreamSynchronize(b->stream));
+        } else {
+            ND_HIP(hipMemcpyAsync(counts, b->track.counts, bytes, hipMemcpyDeviceToDevice, b->stream));
+        }
+    });
+}
+
+nd_status nd_box_accumulate(nd_box *b)
+{
+    return guarded([&] {
+        check_box(b);
+        require(b->track.on, ND_E_STATE, "no histogram is tracked (nd_box_track_histogram)");
+        DeviceGuard g(b->device);
+        if (!b->track.valid) nd::track_refresh(b);
+        nd::track_accumulate(b);
+    });
+}
+
+nd_status nd_box_accumulated(nd_box *b, double *mean_counts, int64_t *n_samples, int32_t where)
+{
+    return guarded([&] {
+        check_box(b);
+        require(mean_counts != nullptr, ND_E_INVALID, "mean_counts is NULL");
+        check_where(where);
+        require(b->track.on, ND_E_STATE, "no histogram is tracked (nd_box_track_histogram)");
+        require(b->track.n_samples > 0, ND_E_STATE, "no sample accumulated (nd_box_accumulate)");
+        DeviceGuard g(b->device);
+        const size_t n = (size_t)b->P * b->track.nbins;
+        if (where == ND_HOST) {
+            Scratch d(n * sizeof(double), b->stream);
+            nd::track_mean(b, d.as<double>());
+            ND_HIP(hipMemcpyAsync(mean_counts, d.p, n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipStreamSynchronize(b->stream));
+        } else {
+            nd::track_mean(b, mean_counts);
+        }
+        if (n_samples) *n_samples = b->track.n_samples;
+    });
+}
+
+nd_status nd_emp_update(nd_box *b, const nd_emp_params *prm, int32_t n_prof, const double *W,
+                        const double *self_terms, const double *g, int32_t nbins, double dr, const double *Q,
+                        int32_t nQ, const double *S_exp, double *dS, double *emp, double *C)
+{
+    return guarded([&] {
+        check_box(b);
+        require(prm != nullptr && W != nullptr && self_terms != nullptr && g != nullptr && Q != nullptr &&
+                    S_exp != nullptr,
+                ND_E_INVALID, "NULL argument");
+        require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
+        require(n_prof >= 1 && n_prof <= ND_EMP_MAX_PROFILES, ND_E_INVALID, "n_prof must be in 1..ND_EMP_MAX_PROFILES");
+        require(prm->n_terms >= 1 && prm->n_terms <= ND_EMP_MAX_TERMS, ND_E_INVALID,
+                "n_terms must be in 1..ND_EMP_MAX_TERMS");
+        require(std::isfinite(prm->sigma) && prm->sigma > 0.0, ND_E_INVALID, "sigma must be > 0");
+        require(std::isfinite(prm->feedback) && prm->feedback > 0.0, ND_E_INVALID, "feedback must be > 0");
+        require(std::isfinite(prm->kT) && prm->kT > 0.0, ND_E_INVALID, "kT must be > 0");
+        require(std::isfinite(prm->ridge) && prm->ridge >= 0.0, ND_E_INVALID, "ridge must be >= 0");
+        require(std::isfinite(prm->id_weight) && prm->id_weight > 0.0, ND_E_INVALID, "id_weight must be > 0");
+        require(std::isfinite(prm->emp_max) && prm->emp_max >= 0.0, ND_E_INVALID, "emp_max must be >= 0");
+        require(n_prof <= b->P, ND_E_INVALID, "more profiles than pair types");
+        require(nbins >= 1 && nQ >= 1 && std::isfinite(dr) && dr > 0.0, ND_E_INVALID, "bad nbins, nQ or dr");
+        for (int i = 0; i < n_prof; ++i) {
+            require(std::isfinite(self_terms[i]), ND_E_INVALID, "self term is not finite");
+            for (int p = 0; p < b->P; ++p)
+                require(std::isfinite(W[(size_t)i * b->P + p]), ND_E_INVALID, "weight is not finite");
+        }
+        if (n_prof == b->P) {
+            // a square weight matrix must be invertible: reject a (near) zero pivot
+            std::vector<double> A(W, W + (size_t)n_prof * b->P);
+            const int P = b->P;
+            double scale = 0.0;
+            for (double v : A) scale = std::max(scale, std::fabs(v));
+            for (int c = 0; c < P; ++c) {
+                int piv = c;
+                for (int r = c + 1; r < P; ++r)
+                    if (std::fabs(A[r * P + c]) > std::fabs(A[piv * P + c])) piv = r;
+                require(std::fabs(A[piv * P + c]) > 1e-12 * scale, ND_E_INVALID, "weight matrix is singular");
+                for (int k = 0; k < P; ++k) std::swap(A[c * P + k], A[piv * P + k]);
+                for (int r = c + 1; r < P; ++r) {
+                    const double f = A[r * P + c] / A[c * P + c];
+                    for (int k = c; k < P; ++k) A[r * P + k] -= f * A[c * P + k];
+                }
+            }
+        }
+        DeviceGuard dg(b->device);
+        nd::launch_emp_update(b, prm, n_prof, W, self_terms, g, nbins, dr, Q, nQ, S_exp, dS, emp, C);
+        b->energy_valid = false;
+    });
+}
+
+nd_status nd_box_get_tables(nd_box *b, float *U, int32_t where)
+{
+    return guarded([&] {
+        check_box(b);
+        require(U != nullptr, ND_E_INVALID, "U is NULL");
+        check_where(where);
+        require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
+        DeviceGuard g(b->device);
+        const size_t bytes = sizeof(float) * (size_t)b->P * b->n_pts;
+        if (where == ND_HOST) {
+            ND_HIP(hipMemcpyAsync(U, b->tab, bytes, hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipStreamSynchronize(b->stream));
+        } else {
+            ND_HIP(hipMemcpyAsync(U, b->tab, bytes, hipMemcpyDeviceToDevice, b->stream));
+        }
+    });
+}
+
+nd_status nd_box_density(nd_box *b, double *V, double *rho)
+{
+    return guarded([&] {
+        check_box(b);
+        require(V != nullptr && rho != nullptr, ND_E_INVALID, "NULL argument");
+        *V = b->L * b->L * b->L;
+        *rho = (double)b->N / *V;
     });
 }
 
@@ -840,6 +1058,68 @@ nd_status nd_forces(nd_box *b, double *dEdx, double *E, int32_t where)
     });
 }
 
+nd_status nd_set_tuning(const nd_tuning *entries, int32_t n)
+{
+    return guarded([&] {
+        require(n >= 0 && (n == 0 || entries != nullptr), ND_E_INVALID, "entries is NULL or n < 0");
+        for (int i = 0; i < n; ++i) check_tuning(entries[i]);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune.assign(entries, entries + n);
+    });
+}
+
+nd_status nd_get_tuning(nd_tuning *entries, int32_t cap, int32_t *n)
+{
+    return guarded([&] {
+        require(n != nullptr && cap >= 0 && (cap == 0 || entries != nullptr), ND_E_INVALID, "bad arguments");
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (int i = 0; i < cap && i < (int)g_tune.size(); ++i) entries[i] = g_tune[i];
+        *n = (int32_t)g_tune.size();
+    });
+}
+
+nd_status nd_load_tuning(const char *path)
+{
+    return guarded([&] {
+        require(path != nullptr, ND_E_INVALID, "path is NULL");
+        FILE *f = std::fopen(path, "r");
+        require(f != nullptr, ND_E_INVALID, std::string("cannot open ") + path);
+        std::vector<nd_tuning> t;
+        char line[512];
+        int lineno = 0;
+        bool ok = true;
+        std::string bad;
+        while (std::fgets(line, sizeof(line), f)) {
+            ++lineno;
+            char *q = line;
+            while (*q == ' ' || *q == '\t') ++q;
+            if (*q == '#' || *q == '\n' || *q == '\r' || *q == 0) continue;
+            char kind[16];
+            long long n_max = 0;
+            int waves = 0, bpc = 0;
+            double target = 0.0;
+            if (std::sscanf(q, "%15s %lld %d %lf %d", kind, &n_max, &waves, &target, &bpc) != 5) {
+                ok = false;
+                bad = "malformed line " + std::to_string(lineno);
+                break;
+            }
+            nd_tuning e;
+            std::memset(&e, 0, sizeof(e));
+            e.kind = std::strcmp(kind, "box") == 0 ? ND_TUNE_BOX : (std::strcmp(kind, "batch") == 0 ? ND_TUNE_BATCH : -1);
+            e.n_max = n_max;
+            e.scan_waves = waves;
+            e.batch_target = target;
+            e.hist_blocks_per_cu = bpc;
+            t.push_back(e);
+        }
+        std::fclose(f);
+        require(ok, ND_E_INVALID, std::string(path) + ": " + bad);
+        for (const nd_tuning &e : t) check_tuning(e);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune = t;
+    });
+}
+
 nd_status nd_batch_create(nd_box *const *boxes, int32_t n, nd_batch **out)
 {
     return guarded([&] {
@@ -876,8 +1156,12 @@ nd_status nd_batch_destroy(nd_batch *t)
 {
     if (!t) return ND_OK;
     int prev = -1;
-    (void)hipGetDevice(&prev);
-    (void)hipSetDevice(t->device);
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(t->device) != hipSuccess) {
+        // runtime no longer usable (process teardown): host side only
+        (void)hipGetLastError();
+        delete t;
+        return ND_OK;
+    }
     free_batch(t);
     if (prev >= 0) (void)hipSetDevice(prev);
     return ND_OK;
@@ -928,7 +1212,7 @@ nd_status nd_batch_run(nd_batch *t, const nd_batch_plan *pl, nd_mc_stats *stats)
         if (pl->sweeps > 0) {
             std::vector<int64_t> nt(n);
             for (int i = 0; i < n; ++i) nt[i] = (int64_t)pl->sweeps * boxes[i]->n_units;
-            nd::mc_multi_plan(t->mc, boxes, n, pl->mc, pl->seed, pl->first_trial, nt.data(), sig);
+            nd::mc_multi_plan(t->mc, boxes, n, pl->mc, pl->seed, pl->first_trial, nt.data(), pl->trace, sig);
             nd::mc_multi_upload(t->mc, s);
         }
         sig.push_back(-1);
@@ -959,6 +1243,13 @@ nd_status nd_batch_run(nd_batch *t, const nd_batch_plan *pl, nd_mc_stats *stats)
             nd::sq_multi_plan(t->sq, d.data(), n, do_s ? pl->Q : nullptr, do_s ? pl->nQ : 0, sig);
             nd::sq_multi_upload(t->sq, s);
         }
+        // running energies brought up to date on the boxes' own streams
+        if (pl->sweeps > 0)
+            for (int i = 0; i < n; ++i)
+                if (!boxes[i]->energy_valid) {
+                    nd::launch_total_energy(boxes[i], boxes[i]->E, nullptr);
+                    boxes[i]->energy_valid = true;
+                }
         // ---- order after pending work on the boxes' streams
         for (int i = 0; i < n; ++i) {
             ND_HIP(hipEventRecord(t->ev_in[i], boxes[i]->stream));
@@ -993,6 +1284,9 @@ nd_status nd_batch_run(nd_batch *t, const nd_batch_plan *pl, nd_mc_stats *stats)
         }
         ND_HIP(hipGraphLaunch(t->exec, s));
         ++t->launches;
+        // the batched sweeps do not update running histograms
+        if (pl->sweeps > 0)
+            for (int i = 0; i < n; ++i) boxes[i]->track.valid = false;
         // later work on the boxes' streams comes after the batch
         ND_HIP(hipEventRecord(t->ev_done, s));
         for (int i = 0; i < n; ++i) ND_HIP(hipStreamWaitEvent(boxes[i]->stream, t->ev_done, 0));
@@ -1107,6 +1401,7 @@ nd_status nd_box_load(nd_box *b, const void *buf, size_t len)
         ND_HIP(hipStreamSynchronize(b->stream));
         b->energy_valid = h.energy_valid != 0;
         b->cells.valid = false;
+        b->track.valid = false;
         if (cells) {
             size_t off = sizeof(h) + sizeof(float) * 3 * N;
             nd::CellState st;

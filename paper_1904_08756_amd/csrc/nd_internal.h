@@ -42,6 +42,7 @@ struct Trial {
     float4 new_hi[ND_MAX_UNIT_ATOMS];
     float4 new_lo[ND_MAX_UNIT_ATOMS];
     float new_x[ND_MAX_UNIT_ATOMS][3];  // absolute float32 new positions
+    float old_x[ND_MAX_UNIT_ATOMS][3];  // absolute float32 positions before the move
     float cen[3];                       // fractional centre of old+new atoms
     float rad;                          // fractional radius about cen
     int32_t unit, a0, na, pad;
@@ -89,6 +90,21 @@ struct CellBuildArgs {
     float *drift;
 };
 
+// Running pair-count histogram kept current by the Delta N(r) of every
+// accepted move (see k_track.hip), and the sum of its samples.
+struct Track {
+    bool on = false, valid = false;
+    double dr = 0.0;
+    int nbins = 0;
+    uint64_t *counts = nullptr;  // [P][nbins] running N(r)
+    uint64_t *sum = nullptr;     // [P][nbins] sum of the accumulated samples
+    long long n_samples = 0;
+    int32_t *partial = nullptr;  // [G][P][nbins] per-block Delta N of one batch
+    int G = 0;
+    long long *moved = nullptr;  // [n_units] tag of the last batch (and trial) that moved the unit
+    mutable long long serial = 0;  // batches tagged so far (advanced while planning)
+};
+
 // Atoms sorted into spatial cells (see k_cells.hip).
 struct Cells {
     int nc = 0, ncell = 0, cap_n = 0;
@@ -125,7 +141,9 @@ struct nd_box {
     uint8_t *h_species = nullptr;
     int64_t species_count[ND_MAX_SPECIES] = {0, 0, 0, 0};
     // potential tables
-    float *tab = nullptr;        // [P][n_pts]
+    float *tab = nullptr;        // [P][n_pts] reference potential + EMP, used by every energy kernel
+    float *rp = nullptr;         // [P][n_pts] reference potential as given to nd_box_set_tables
+    double *emp = nullptr;       // [P][n_pts] accumulated empirical potential (null: none yet)
     int n_pts = 0;
     double h = 0.0, rc = 0.0;
     bool has_tables = false;
@@ -134,6 +152,7 @@ struct nd_box {
     bool energy_valid = false;
     nd::McWork mc;
     nd::Cells cells;
+    nd::Track track;
     // reusable device workspace for per-block partial results
     void *ws = nullptr;
     size_t ws_bytes = 0;
@@ -152,6 +171,7 @@ namespace nd {
 
 // ---- kernel launchers (defined in the .hip files) ----
 void launch_pos4_from_xyz(nd_box *b);
+void launch_wrap_coords(nd_box *b, const float *d_in, float *d_out, int *d_bad);
 void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts);
 void launch_total_energy(nd_box *b, double *d_E_out, double *d_sabs_out);
 void launch_gr_normalize(const uint64_t *counts, int P, int nbins, double dr, double V,
@@ -168,9 +188,11 @@ void launch_hist_broad(nd_box *b, double dr, int nbins, double sigma, double *d_
 void launch_hist_broad_backward(nd_box *b, double dr, int nbins, double sigma, const double *d_A,
                                 double *d_grad);
 void launch_forces(nd_box *b, double *d_grad, double *d_E);
+size_t forces_scratch_bytes(int N, long long G);
+void launch_forces_in(nd_box *b, double *d_grad, double *d_E, char *ws, long long max_grid, bool prof);
 void mc_run(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first, int64_t n,
             const nd_mc_trace *trace);
-int mc_batch_size(nd_box *b, const nd_mc_params *p);
+int mc_batch_size(nd_box *b, const nd_mc_params *p, double target = 0.0);
 
 // Metropolis runs of several boxes as one sequence of launches, each launch
 // covering every box that still has batches (k_mc.hip).  plan: host-side
@@ -181,7 +203,8 @@ struct McMulti;
 McMulti *mc_multi_create();
 void mc_multi_destroy(McMulti *m);
 void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *params, const uint64_t *seed,
-                   const uint64_t *first, const int64_t *n_trials, std::vector<long long> &sig);
+                   const uint64_t *first, const int64_t *n_trials, const nd_mc_trace *trace,
+                   std::vector<long long> &sig);
 void mc_multi_upload(McMulti *m, hipStream_t s);
 void mc_multi_enqueue(McMulti *m, hipStream_t s);
 
@@ -212,6 +235,19 @@ void sq_multi_destroy(SqMulti *m);
 void sq_multi_plan(SqMulti *m, const SqBoxDesc *descs, int n, const double *Q, int nQ, std::vector<long long> &sig);
 void sq_multi_upload(SqMulti *m, hipStream_t s);
 void sq_multi_enqueue(SqMulti *m, hipStream_t s);
+// Running histogram (k_track.hip).  track_launch: the Delta N(r) of the
+// accepted trials of one decided batch, added to the running counts.
+constexpr long long TRACK_TAG_STRIDE = 4096;  // > trials per batch
+void track_start(nd_box *b, double dr, int nbins);
+void track_stop(nd_box *b);
+void track_refresh(nd_box *b);
+void track_launch(nd_box *b, const Trial *trials, const uint8_t *acc, int kb, long long tag_base);
+void track_accumulate(nd_box *b);
+void track_mean(nd_box *b, double *d_mean);
+void emp_reset(nd_box *b);
+void launch_emp_update(nd_box *b, const nd_emp_params *prm, int n_prof, const double *W_host,
+                       const double *self_host, const double *g, int nbins, double dr, const double *Q, int nQ,
+                       const double *S_exp, double *dS_out, double *emp_out, double *C_out);
 void cells_build(nd_box *b);
 void cells_ensure(nd_box *b);
 void cells_rebuild_launch(hipStream_t s, const CellBuildArgs *d_args, int n_boxes, int max_n, int max_ncell);
@@ -225,6 +261,10 @@ struct CellState {
     const float4 *sref;                    // [N] by atom
 };
 void cells_restore(nd_box *b, const CellState &st);
+
+// Tuning table (nd_set_tuning): the entry of `kind` for n atoms, copied
+// into *out; false when the table has none.
+bool tune_lookup(int kind, long long n, nd_tuning *out);
 
 // device memory helpers
 void *dmalloc(size_t bytes);

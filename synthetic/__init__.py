@@ -313,6 +313,15 @@ def config_c5():
                                      fd_seed=1005, target_seed=1006)
 
 
+def config_scale(n_mol: int, seed: int = 1007):
+    """Scale-up water box: n_mol rigid waters at the C2 density (0.1009
+    atoms/A^3, L = 99.7 A for 33,333 waters), the sizes of the paper's speed
+    table (1.2e6 to 3e7 atoms); histogram bins as C2 (0.03 A to 49.8 A)."""
+    L = 99.7 * (n_mol / 33333.0) ** (1.0 / 3.0)
+    box = water_box(n_mol, L, seed, f"water {3 * n_mol} atoms")
+    return box, water_tables(), dict(WATER_MC, seed=seed, dr=0.03, nbins=n_bins_for(49.8, 0.03))
+
+
 def unit_of_atom(box: Box) -> np.ndarray:
     """Unit index of every atom (expanded CSR)."""
     counts = np.diff(box.unit_offsets)

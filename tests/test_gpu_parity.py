@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import synthetic as syn
+from helpers import expected_near_ties, f32_ulps
 
 pytestmark = pytest.mark.gpu
 
@@ -154,16 +155,16 @@ def test_total_energy_matches_oracle(nd, orc, cfg):
 
 
 # ------------------------------------------------------------------ Metropolis
-def _mc_parity(nd, orc, box, T, params, seed, first, n, k_batch=0, scan=0):
+def _mc_parity(nd, orc, box, T, params, seed, first, n, k_batch=0, scan=0, order=0):
     g = _gbox(nd, box, T)
     E0 = g.total_energy()
-    p = nd.MCParams(params["kT"], params["max_disp"], params["max_rot"], k_batch=k_batch, scan=scan)
-    say(f"mc parity: {box.name} trials {first}..{first + n} K={k_batch} scan={scan}")
+    p = nd.MCParams(params["kT"], params["max_disp"], params["max_rot"], k_batch=k_batch, scan=scan, order=order)
+    say(f"mc parity: {box.name} trials {first}..{first + n} K={k_batch} scan={scan} order={order}")
     res = g.mc_sweep(p, seed, first, n, trace=True)
     tr = {k: v.cpu().numpy() for k, v in res["trace"].items()}
     xyz = box.xyz.copy()
     o = orc.mc_run(box, T, xyz, params["kT"], params["max_disp"], params["max_rot"], seed, first, n,
-                   forced=tr["accepted"])
+                   forced=tr["accepted"], order=order)
     assert np.array_equal(tr["unit"], o["unit"])
     err = np.abs(tr["dE"] - o["dE"])
     assert np.all(err <= 1e-6 * o["sabs"]), (np.max(err / o["sabs"]), int(np.argmax(err / o["sabs"])))
@@ -172,10 +173,16 @@ def _mc_parity(nd, orc, box, T, params, seed, first, n, k_batch=0, scan=0):
     assert res["accepted"] == int(tr["accepted"].sum())
     assert res["trials"] == n
     got_xyz = g.coords_host()
-    # identical except where libm sin/cos differ in the last place (rare)
-    diff = np.abs(got_xyz.astype(np.float64) - xyz.astype(np.float64))
-    diff = np.minimum(diff, box.L - diff)
-    assert np.mean(diff == 0) > 0.999 and diff.max() < 1e-4
+    # identical except where the FP64 sin/cos of the two sides differ in the
+    # last place and the rounding to float32 shows it (logged); a unit moved
+    # again later carries that ulp along
+    ulps = f32_ulps(got_xyz, xyz, box.L)
+    n_tie = int(o["tie"].sum())
+    lam = expected_near_ties(o["dE"], o["sabs"], params["kT"])
+    say(f"  near ties {n_tie} ({lam:.2f} expected); coordinates differing {int((ulps > 0).sum())} "
+        f"of {ulps.size}, max {int(ulps.max())} ulp")
+    assert n_tie <= lam + 5.0 * np.sqrt(lam) + 2.0
+    assert ulps.max() <= 2
     # running energy against a fresh recompute on both sides
     E_run = res["E_total"]
     E_new = g.total_energy()
@@ -191,6 +198,23 @@ def test_mc_c1_matches_sequential_chain(nd, orc, k_batch, scan):
     box, T, mc = syn.config_c1()
     res, o = _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, mc["n_trials"], k_batch, scan)
     assert 0.05 < res["accepted"] / res["trials"] < 0.95
+
+
+@pytest.mark.parametrize("k_batch,scan", [(0, 0), (9, 0), (0, 1)])
+def test_mc_c1_random_order_matches_sequential_chain(nd, orc, k_batch, scan):
+    """Units drawn at random per trial (draw 7): batches end before the first
+    repeated unit, and the chain still equals the oracle's trial by trial."""
+    box, T, mc = syn.config_c1()
+    res, o = _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, mc["n_trials"], k_batch, scan, order=1)
+    # the draws do repeat units within a sweep's worth of trials
+    assert len(np.unique(o["unit"])) < box.n_units
+    assert 0.05 < res["accepted"] / res["trials"] < 0.95
+
+
+def test_mc_sio2_random_order_matches_sequential_chain(nd, orc):
+    box = syn.atomic_box((2000, 4000), 114.7 * (6000 / 99999) ** (1 / 3), 1003, ("Si", "O"), "SiO2 cut")
+    T = syn.sio2_tables(r_cut=min(12.0, box.L / 2))
+    _mc_parity(nd, orc, box, T, syn.SIO2_MC, 1003, 5, 3000, order=1)
 
 
 def test_mc_c1_split_calls_equal_one_call(nd, orc):
@@ -458,10 +482,16 @@ def test_chi2_autograd_matches_oracle(nd, orc):
     b = syn.water_b(0.0)
     target = 20.0 + 0.5 * np.sin(Q)
     g = _gbox(nd, box)
-    x = torch.as_tensor(box.xyz, device="cuda").clone().requires_grad_(True)
+    # FP64 coordinates (float32-representable): the gradient comes back in FP64
+    x = torch.as_tensor(box.xyz.astype(np.float64), device="cuda").clone().requires_grad_(True)
     c2 = nd.Chi2Fn.apply(x, g, dr, nb, sigma, torch.as_tensor(Q, device="cuda"),
                          torch.as_tensor(target, device="cuda"), b)
+    # the box moves on before backward runs: the gradient is still taken at x
+    other = box.xyz.copy()
+    other[0] = np.float32(0.5) * other[0]
+    g.set_coords(other)
     c2.backward()
+    assert x.grad.dtype == torch.float64
     nh = orc.hist_broad(box, dr, nb, sigma)
     npairs = orc.pair_counts_total(box.species, 2)
     V = box.L ** 3
@@ -471,9 +501,10 @@ def test_chi2_autograd_matches_oracle(nd, orc):
     assert abs(float(c2.detach()) - chi2_o) <= 1e-6 * chi2_o
     A = orc.sq_adjoint(2 * (S - target), nb, dr, box.n_atoms / V, V, w, npairs, Q)
     want = orc.hist_broad_backward(box, dr, nb, sigma, A)
-    got = x.grad.cpu().numpy().astype(np.float64)
+    got = x.grad.cpu().numpy()
     scale = np.abs(want).max()
-    assert np.all(np.abs(got - want) <= 1e-4 * scale + 1e-3 * np.abs(want))
+    # the bound of the direct backward test: FP32 pair weights, FP64 sums
+    assert np.all(np.abs(got - want) <= 1e-5 * scale + 1e-4 * np.abs(want)), np.max(np.abs(got - want)) / scale
 
 
 def test_energy_autograd_gives_forces(nd, orc):
@@ -487,3 +518,52 @@ def test_energy_autograd_gives_forces(nd, orc):
     want, E_o = orc.forces(box, T)
     scale = np.abs(want).max()
     assert np.all(np.abs(x.grad.cpu().numpy() - want) <= 1e-6 * scale + 1e-6 * np.abs(want))
+
+
+# ------------------------------------------------------------------ boundary
+def test_sweep_after_new_coordinates_reports_fresh_energy(nd, orc):
+    """A sweep after set_coords (or after the differentiated form loaded its
+    own coordinates) starts from the energy of the new configuration."""
+    box, T, mc = syn.config_c1()
+    g = _gbox(nd, box, T)
+    g.total_energy()
+    rng = np.random.default_rng(5)
+    moved = box.xyz.copy()
+    moved[:, :30] = (rng.random((3, 30)) * box.L).astype(np.float32)
+    moved[moved >= box.L] = 0.0
+    g.set_coords(moved)
+    p = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"])
+    res = g.mc_sweep(p, mc["seed"], 0, 300)
+    E_fresh = g.total_energy()
+    _, S_o = orc.total_energy(box, T)
+    assert abs(res["E_total"] - E_fresh) <= 1e-6 * S_o
+
+
+def test_device_coordinates_are_wrapped_and_checked(nd):
+    import torch
+    box, T, mc = syn.config_c1()
+    g = _gbox(nd, box, T)
+    x = torch.as_tensor(box.xyz.astype(np.float64), device="cuda")
+    shifted = x.clone()
+    shifted[0, :10] += box.L        # one period up
+    shifted[1, 10:20] -= 2 * box.L  # two periods down
+    g.set_coords(shifted)
+    got = g.coords_host()
+    want = box.xyz.astype(np.float64)
+    d = np.abs(got.astype(np.float64) - want)
+    d = np.minimum(d, box.L - d)
+    assert np.all(got >= 0) and np.all(got < box.L)
+    assert d.max() < 1e-5
+    before = g.coords_host()
+    bad = x.clone()
+    bad[2, 7] = float("nan")
+    with pytest.raises(nd.NeudaError, match="INVALID"):
+        g.set_coords(bad)
+    assert np.array_equal(g.coords_host(), before)
+
+
+def test_box_density(nd):
+    box, _, _ = syn.config_c1()
+    g = _gbox(nd, box)
+    V, rho = g.density()
+    assert V == box.L * box.L * box.L and rho == box.n_atoms / V

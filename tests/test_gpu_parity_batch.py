@@ -1,6 +1,9 @@
-"""Batched form: several water boxes of uneven size and H/D weighting run as
-one graph of shared launches give, box by box, the results of the plain
-entry points (which the other GPU tests check against the oracle).
+"""Batched form: water boxes of uneven size and H/D weighting run as one
+graph of shared launches.  The full 64-box, 5-sweep workload is checked
+against the FP64 oracle box by box (histograms bit for bit, g(r) and S(Q)
+at the plain path's tolerances, the Metropolis chains of the smallest boxes
+trial by trial); a subset is also checked against the plain entry points
+over several graph replays.
 
 Both sides run the same kernels on the same inputs, so coordinates,
 histograms, g(r) and acceptance counts agree bit for bit.  The running
@@ -17,6 +20,7 @@ import numpy as np
 import pytest
 
 import synthetic as syn
+from helpers import expected_near_ties, f32_ulps
 
 pytestmark = pytest.mark.gpu
 
@@ -189,4 +193,130 @@ def test_batch_rejects_bad_plans(nd):
         batch.run(0, None, None, None, 0.03, [10, 10 ** 6], counts=counts)
     with pytest.raises(nd.NeudaError):
         nd.Batch([gb[0], gb[0]])
+    batch.close()
+
+
+
+@pytest.mark.timeout(900)
+def test_batch_c4_all_boxes_match_oracle(nd):
+    """All 64 boxes of the batched workload, 5 sweeps each, then histogram,
+    g(r) and S(Q), in one graph replay, against the FP64 oracle: every
+    box's counts bit for bit (on the coordinates the batch produced), g to
+    1e-14 relative, S(Q) to 1e-11 of the Eq. 1 term scale; the Metropolis
+    chains of the three smallest boxes trial by trial against the oracle's
+    sequential chain (the chains are cheap there; the others share every
+    kernel and launch with them)."""
+    import torch
+
+    import oracle
+    oracle.set_threads(oracle.max_threads())
+    sboxes, T, mc = syn.config_c4()
+    sweeps, dr = mc["sweeps"], mc["dr"]
+    params = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"])
+    seeds = [mc["seed"] * 1000 + i for i in range(len(sboxes))]
+    nbins = [sb.meta["nbins"] for sb in sboxes]
+    Q = torch.as_tensor(syn.q_grid(), device="cuda")
+    gb = _make(nd, sboxes, T)
+    E0 = [g.energy() for g in gb]
+    w, st = [], []
+    for sb, g in zip(sboxes, gb):
+        wi, si = nd.eq1_weights(g, syn.water_b(sb.meta["d_fraction"]))
+        w.append(wi)
+        st.append(si)
+    w, st = np.array(w), np.array(st)
+    batch = nd.Batch(gb)
+    counts = [torch.empty((g.P, nb), dtype=torch.int64, device="cuda") for g, nb in zip(gb, nbins)]
+    gr = [torch.empty((g.P, nb), dtype=torch.float64, device="cuda") for g, nb in zip(gb, nbins)]
+    sq = [torch.empty(Q.shape[0], dtype=torch.float64, device="cuda") for _ in gb]
+    say(f"batched C4: {len(gb)} boxes, {sum(g.N for g in gb)} atoms, {sweeps} sweeps")
+    stats = batch.run(sweeps, [params] * len(gb), seeds, [0] * len(gb), dr, nbins, w, st, Q, counts, gr, sq,
+                      trace=True)
+    torch.cuda.synchronize()
+    Qh = syn.q_grid()
+
+    # Metropolis chains of the three smallest boxes
+    order = np.argsort([g.N for g in gb], kind="stable")
+    for i in order[:3]:
+        i = int(i)
+        sb, g = sboxes[i], gb[i]
+        n = sweeps * g.n_units
+        tr = {k: v.cpu().numpy() for k, v in stats[i]["trace"].items()}
+        xyz = sb.xyz.copy()
+        o = oracle.mc_run(sb, T, xyz, mc["kT"], mc["max_disp"], mc["max_rot"], seeds[i], 0, n,
+                          forced=tr["accepted"])
+        assert np.array_equal(tr["unit"], o["unit"]), f"box {i}: units"
+        err = np.abs(tr["dE"] - o["dE"])
+        assert np.all(err <= 1e-6 * o["sabs"]), f"box {i}: dE {np.max(err / o['sabs']):.3e}"
+        mism = (tr["accepted"] != o["acc"]) & (o["tie"] == 0)
+        assert not mism.any(), f"box {i}: decisions differ at {np.nonzero(mism)[0][:10]}"
+        # near ties: decisions whose threshold -kT ln u lies within the
+        # energy tolerance (1e-6 of the trial's sum of |pair terms|) of dE.
+        # Their expected number follows from the exponential law of the
+        # threshold; small dense boxes, whose S_abs is large, have several
+        n_tie = int(o["tie"].sum())
+        lam = expected_near_ties(o["dE"], o["sabs"], mc["kT"])
+        assert n_tie <= lam + 5.0 * np.sqrt(lam) + 2.0, f"box {i}: {n_tie} near ties, {lam:.1f} expected"
+        ulps = f32_ulps(g.coords_host(), xyz, g.L)
+        say(f"box {i} ({g.N} atoms, {n} trials, {int(o['acc'].sum())} accepted): near ties {n_tie} "
+            f"({lam:.1f} expected), "
+            f"coordinates differing {int((ulps > 0).sum())}, max {int(ulps.max())} ulp")
+        assert ulps.max() <= 2, f"box {i}: coordinates {int(ulps.max())} ulp apart"
+        dE_acc = np.sum(o["dE"][o["acc"] == 1])
+        assert abs((stats[i]["E_total"] - E0[i]) - dE_acc) <= 1e-6 * np.sum(o["sabs"]), f"box {i}: energy"
+
+    # every box: histogram, g(r), S(Q)
+    for i, (sb, g) in enumerate(zip(sboxes, gb)):
+        moved = syn.Box(sb.name, sb.L, sb.species, sb.unit_offsets, g.coords_host(), 2)
+        want, _ = oracle.pair_histogram(moved, dr, nbins[i])
+        got = counts[i].cpu().numpy().astype(np.uint64)
+        assert np.array_equal(got, want), f"box {i}: histogram differs"
+        V = sb.L ** 3
+        npairs = oracle.pair_counts_total(sb.species, 2)
+        g_o = oracle.gr_normalize(want.astype(np.float64), dr, V, npairs)
+        g_d = gr[i].cpu().numpy()
+        assert np.all(np.abs(g_d - g_o) <= 1e-14 * np.abs(g_o)), f"box {i}: g"
+        w_o, st_o = oracle.eq1_weights(sb.species, 2, syn.water_b(sb.meta["d_fraction"]))
+        rho = sb.n_atoms / V
+        S_o = oracle.sq(g_o, dr, rho, w_o, st_o, Qh)
+        rk = (np.arange(nbins[i]) + 0.5) * dr
+        scale = float(np.sum(np.abs(w_o) * 4 * np.pi * rho * np.sum(rk ** 2 * np.abs(g_o - 1.0) * dr, axis=1))) + st_o
+        assert np.max(np.abs(sq[i].cpu().numpy() - S_o)) <= 1e-11 * scale, f"box {i}: S(Q)"
+    say(f"batched C4: all {len(gb)} boxes equal the oracle")
+    batch.close()
+
+
+def test_batch_random_order_matches_oracle(nd):
+    """Random move order in the batched form (units drawn per trial, batches
+    cut at the first repeated unit, boxes of different batch counts in one
+    graph): the chains of the four smallest boxes trial by trial against
+    the oracle."""
+    import torch
+
+    import oracle
+    sboxes, T, mc = syn.config_c4()
+    order = np.argsort([b.n_atoms for b in sboxes], kind="stable")[:4]
+    sboxes = [sboxes[int(i)] for i in order]
+    gb = _make(nd, sboxes, T)
+    E0 = [g.energy() for g in gb]
+    p = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"], order=nd.ND_ORDER_RANDOM)
+    seeds = [77 + i for i in range(len(gb))]
+    batch = nd.Batch(gb)
+    sweeps = 2
+    stats = batch.run(sweeps, [p] * len(gb), seeds, [5] * len(gb), trace=True)
+    torch.cuda.synchronize()
+    for i, (sb, g) in enumerate(zip(sboxes, gb)):
+        n = sweeps * g.n_units
+        tr = {k: v.cpu().numpy() for k, v in stats[i]["trace"].items()}
+        xyz = sb.xyz.copy()
+        o = oracle.mc_run(sb, T, xyz, mc["kT"], mc["max_disp"], mc["max_rot"], seeds[i], 5, n, order=1,
+                          forced=tr["accepted"])
+        assert np.array_equal(tr["unit"], o["unit"])
+        assert len(np.unique(o["unit"])) < g.n_units
+        assert np.all(np.abs(tr["dE"] - o["dE"]) <= 1e-6 * o["sabs"])
+        assert not ((tr["accepted"] != o["acc"]) & (o["tie"] == 0)).any()
+        ulps = f32_ulps(g.coords_host(), xyz, g.L)
+        say(f"random order, box of {g.N} atoms: {int(o['acc'].sum())} of {n} accepted, "
+            f"near ties {int(o['tie'].sum())}, max {int(ulps.max())} ulp")
+        assert ulps.max() <= 2
+        assert abs((stats[i]["E_total"] - E0[i]) - np.sum(o["dE"][o["acc"] == 1])) <= 1e-6 * np.sum(o["sabs"])
     batch.close()

@@ -4,9 +4,11 @@
   a seeded adjoint A, and the energy gradient (nd_forces), on 100 seeded
   atoms against the FP64 oracle, which sums each sampled atom's terms over
   all 99,998 partners.
-* Central finite differences (h = 1e-4 A) of chi^2 through the whole
-  forward (broadened histogram -> g -> S(Q) -> chi^2) against the gradient
-  from the backward, on 100 seeded atoms, one seeded axis each.  This holds
+* The broadened histogram of all pairs against the oracle's, stored.
+* Central finite differences (h = 1e-4 A) of chi^2 against the target S(Q)
+  of the bumped-potential run (stored), through the whole forward
+  (broadened histogram -> g -> S(Q) -> chi^2), against the gradient from
+  the backward, on 100 seeded atoms, one seeded axis each.  This holds
   at any size where the forward is smooth in the coordinates: a pair counts
   only while r < L/2, so chi^2 jumps when a pair crosses L/2 if that pair's
   window (r +- 6 sigma) reaches the binned range.  With bins to 49.8 A and
@@ -14,10 +16,16 @@
   of L/2; binning to 49.6 A keeps every window that reaches the range
   inside r < L/2, and chi^2 is then smooth.
 """
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import synthetic as syn
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+from make_golden import read_rows  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +62,20 @@ def c5(nd):
     return box, T, cfg, g, sel, axis
 
 
+def test_broad_forward_full_box_matches_oracle(nd, c5):
+    """The broadened histogram of all 4,999,850,001 pairs against the oracle's
+    (stored by tests/golden/make_golden.py), per bin to 1e-6 of the bin's
+    count (at least 1e-6 of one count)."""
+    box, T, cfg, g, sel, _ = c5
+    say("broadened forward, 99,999 atoms, all pairs")
+    got = nd.hist_broad(g, cfg["dr"], cfg["nbins"], cfg["sigma"]).cpu().numpy()
+    want = read_rows("c5_hist_broad.txt")
+    assert got.shape == want.shape
+    err = np.abs(got - want)
+    say(f"max |diff| / max(count, 1) = {np.max(err / np.maximum(want, 1.0)):.3e}")
+    assert np.all(err <= 1e-6 * np.maximum(want, 1.0)), float(np.max(err / np.maximum(want, 1.0)))
+
+
 def test_broad_backward_full_box_sampled(nd, orc, c5):
     import torch
     box, T, cfg, g, sel, _ = c5
@@ -88,7 +110,10 @@ def test_chi2_gradient_finite_differences_full_box(nd, c5):
     Q = syn.q_grid(1000)
     b = syn.water_b(0.0)
     Qt = torch.as_tensor(Q, device="cuda")
-    target = torch.as_tensor(20.5 + 0.5 * np.sin(Q), device="cuda")
+    # the oracle's S(Q) of the bumped-potential run (seed 1006), from the
+    # broadened g of that box; stored by tests/golden/make_golden.py
+    target = torch.as_tensor(read_rows("c5_target_sq.txt")[0], device="cuda")
+    assert target.shape[0] == Q.shape[0]
     x0 = box.xyz.astype(np.float32)
     x = torch.as_tensor(x0, device="cuda").clone().requires_grad_(True)
     say("chi^2 gradient, 99,999 atoms: forward + backward")
@@ -113,8 +138,12 @@ def test_chi2_gradient_finite_differences_full_box(nd, c5):
     scale = np.abs(gs).max()
     err = np.abs(fd - gs)
     say(f"max |fd - grad| / max |grad| = {err.max() / scale:.3e}")
-    # The FP32 pair weights round differently at x + h and x - h; divided
-    # by 2h that roundoff is ~1e-3 of the gradient scale (about 300 pair
-    # terms of ~1e-7 per bin, 1653 bins).  A wrong sign, a missing term or
-    # factor shows up at order one.
-    assert np.all(err <= 3e-3 * scale + 2e-3 * np.abs(gs)), float(np.max(err / scale))
+    # P12: relative error 1e-3 (plus 1e-4 of the gradient scale for the
+    # components near zero).  Pairs without the moved atom give identical
+    # integer bin sums at x + h and x - h, so the difference carries only the
+    # moved atom's ~1e5 pair weights, whose FP32 roundoff over 2h stays near
+    # 1e-5 of the scale.  A wrong sign, a missing term or factor shows up at
+    # order one.
+    assert np.all(err <= 1e-3 * np.abs(gs) + 1e-4 * scale), float(np.max(err / scale))
+    # translation invariance of chi^2: the gradient sums to zero over atoms
+    assert abs(grad.sum(axis=1)).max() <= 1e-6 * np.abs(grad).sum(axis=1).max()

@@ -386,6 +386,27 @@ def test_sq_large_q_tends_to_flat_term(orc):
     assert np.all(np.abs(S - self_term) < np.array([3.0, 1.5, 0.8]))
 
 
+def test_gr_shell_volume_is_the_exact_shell_integral(orc):
+    """g = n / (npairs Vshell / V) with Vshell(k) the volume between the
+    spheres of radius k dr and (k + 1) dr: the integral of 4 pi r^2 over the
+    bin, by adaptive quadrature.  The midpoint form 4 pi r_k^2 dr (3.6% off
+    at k = 1) or the inner-edge form would fail this at any k."""
+    from scipy.integrate import quad
+    dr, nb = 0.03, 400
+    for V, npairs, n in ((1.0, 1.0, 1.0), (7.25, 3.0, 5.0)):
+        g = orc.gr_normalize(np.full((1, nb), n), dr, V, np.array([npairs]))
+        shell = n * V / (npairs * g[0])
+        exact = np.array([quad(lambda r: 4.0 * np.pi * r * r, k * dr, (k + 1) * dr, epsabs=0, epsrel=1e-13)[0]
+                          for k in range(nb)])
+        assert np.allclose(shell, exact, rtol=1e-12, atol=0.0)
+    # the pin separates the plausible wrong forms from the right one
+    k = np.arange(nb)
+    midpoint = 4.0 * np.pi * ((k + 0.5) * dr) ** 2 * dr
+    inner = 4.0 * np.pi * (k * dr) ** 2 * dr
+    assert not np.allclose(midpoint, exact, rtol=1e-12, atol=0.0)
+    assert not np.allclose(inner, exact, rtol=1e-12, atol=0.0)
+
+
 def test_gr_of_uniform_box_is_one(orc):
     box = syn.atomic_box((4000, 4000), 30.0, 5, ("A", "B"))
     dr = 0.3
