@@ -308,6 +308,21 @@ nd_status nd_hist_broad_backward(nd_box *box, double dr, int32_t nbins, double s
  * table holding a NaN or an infinity gives NaN everywhere. */
 nd_status nd_forces(nd_box *box, double *dEdx, double *E, int32_t where);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or optimisation loops, harnesses that forbid
+ * hipMalloc): nd_forces with device outputs only -- dEdx device double
+ * [3][N], E device double [1] or NULL -- that allocates nothing.  Its
+ * kernels use a fixed scratch array built into the library instead of the
+ * box's workspace: one per GPU, 12.6 MB (ND_NOALLOC_MAX_ATOMS atoms), held
+ * until the process ends, its address looked up on a device's first call.
+ * Every call on a GPU shares that GPU's array (each call clears what it
+ * sums), so calls that overlap in time on one GPU -- on different streams
+ * or from different host threads -- race and must not be issued.
+ * Asynchronous on the box's stream; results equal nd_forces bit for bit.
+ * Errors: ND_E_INVALID (NULL dEdx), ND_E_STATE (no tables), ND_E_RANGE
+ * (N > ND_NOALLOC_MAX_ATOMS), ND_E_HIP. */
+#define ND_NOALLOC_MAX_ATOMS 262144
+nd_status nd_forces_noalloc(nd_box *box, double *dEdx, double *E);
 
 /* Checkpoint of a box's Metropolis state: coordinates, running energy and
  * (when live) the cell lists, so that a run resumed from the checkpoint

@@ -120,6 +120,7 @@ EXPORTS = {
     "nd_hist_broad_backward": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32, C.c_double,
                                            C.c_void_p, C.c_void_p, C.c_int32]),
     "nd_forces": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_int32]),
+    "nd_forces_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "nd_gr_normalize_f64": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                         C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "nd_box_pair_counts": (C.c_int32, [C.c_void_p, C.c_void_p]),
@@ -677,6 +678,18 @@ def forces(box: Box):
     E = C.c_double()
     _check(lib().nd_forces(box.handle, _dptr(out), C.byref(E), ND_DEVICE))
     return out, E.value
+
+
+def forces_noalloc(box: Box, dEdx, E=None):
+    """nd_forces_noalloc into caller tensors: dEdx float64 [3, N] and E float64
+    [1] (or None) on the box's device; the library allocates nothing."""
+    torch = _torch()
+    box._sync_stream()
+    if dEdx.dtype != torch.float64 or tuple(dEdx.shape) != (3, box.N) or not dEdx.is_contiguous():
+        raise ValueError("dEdx must be a contiguous float64 [3, N] device tensor")
+    if E is not None and (E.dtype != torch.float64 or E.numel() < 1):
+        raise ValueError("E must be a float64 device tensor of at least one element")
+    _check(lib().nd_forces_noalloc(box.handle, _dptr(dEdx), _dptr(E) if E is not None else None))
 
 
 @dataclass

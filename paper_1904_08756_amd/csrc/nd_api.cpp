@@ -13,6 +13,19 @@
 
 #include "nd_internal.h"
 
+// Scratch of nd_forces_noalloc: a fixed array in every GPU's memory, sized
+// for ND_NOALLOC_MAX_ATOMS atoms and a grid of at most NOALLOC_MAX_GRID
+// blocks, plus a sink for an energy the caller does not want.  In host code
+// `scratch` names a host-side stand-in; kernels get the device address that
+// hipGetSymbolAddress returns for the current device.
+namespace {
+constexpr long long NOALLOC_MAX_GRID = 2048;
+constexpr size_t NOALLOC_FORCES_BYTES =
+    sizeof(long long) * 2 * 3 * (size_t)ND_NOALLOC_MAX_ATOMS + sizeof(double) * NOALLOC_MAX_GRID + 256;
+constexpr size_t NOALLOC_BYTES = NOALLOC_FORCES_BYTES + 256;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+}  // namespace
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
 
 namespace {
 thread_local std::string g_last_error;
@@ -1055,6 +1068,40 @@ nd_status nd_forces(nd_box *b, double *dEdx, double *E, int32_t where)
             ND_HIP(hipMemcpyAsync(E, de.p, sizeof(double), hipMemcpyDeviceToHost, b->stream));
         }
         ND_HIP(hipStreamSynchronize(b->stream));
+    });
+}
+
+namespace {
+std::mutex g_scratch_mu;
+char *g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device` (current), looked up once per device.
+char *noalloc_scratch(int device)
+{
+    require(device >= 0 && device < NOALLOC_MAX_DEVICES, ND_E_UNSUPPORTED, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        ND_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        require(ptr != nullptr, ND_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_dev[device] = static_cast<char *>(ptr);
+    }
+    return g_scratch_dev[device];
+}
+}  // namespace
+
+nd_status nd_forces_noalloc(nd_box *b, double *dEdx, double *E)
+{
+    return guarded([&] {
+        check_box(b);
+        require(dEdx != nullptr, ND_E_INVALID, "dEdx is NULL");
+        require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
+        require(b->N <= ND_NOALLOC_MAX_ATOMS, ND_E_RANGE,
+                "nd_forces_noalloc takes at most ND_NOALLOC_MAX_ATOMS (262144) atoms");
+        DeviceGuard g(b->device);
+        char *ws = noalloc_scratch(b->device);
+        double *e_out = E ? E : reinterpret_cast<double *>(ws + NOALLOC_FORCES_BYTES);
+        nd::launch_forces_in(b, dEdx, e_out, ws, NOALLOC_MAX_GRID, false);
     });
 }
 
