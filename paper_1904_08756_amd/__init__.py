@@ -732,6 +732,44 @@ def emp_update(box: Box, params: EmpParams, W, self_terms, g, dr, Q, S_exp):
     return dS, emp, coef
 
 
+def refine(box: Box, mc: MCParams, seed: int, W, self_terms, S_exp, Q, dr, nbins, emp: EmpParams,
+           iterations: int, sweeps: int, sample_sweeps: int, first_trial: int = 0):
+    """The empirical-potential Monte Carlo loop (Sec. "NeuDATool Algorithmic
+    Flow", steps MC, "Calculate g(r), S(Q) and EMP" and EPMC): each iteration
+    runs `sweeps` sweeps of which the last `sample_sweeps` are accumulated into
+    the mean histogram (the running Delta N(r) histogram), turns it into g(r),
+    and updates the EMP from the measured profiles S_exp [n_prof, nQ] with
+    Eq. 1 weights W [n_prof, P] and flat terms.  Every step runs in the
+    library; this function only sequences the calls.  Returns per iteration
+    the chi^2 of each profile before its update, and the next trial counter."""
+    torch = _torch()
+    V, rho = box.density()
+    npairs = pair_counts_total(box)
+    Qd = torch.as_tensor(Q, device=f"cuda:{box.device}", dtype=torch.float64)
+    Sx = torch.as_tensor(S_exp, device=Qd.device, dtype=torch.float64)
+    W = np.ascontiguousarray(np.asarray(W, dtype=np.float64))
+    history = []
+    t = first_trial
+    for _ in range(iterations):
+        box.track_histogram(dr, nbins)  # restarts the sums
+        for s in range(sweeps):
+            box.mc_sweep(mc, seed, t, box.n_units, stats=False)
+            t += box.n_units
+            if s >= sweeps - sample_sweeps:
+                box.accumulate()
+        mean, _ = box.accumulated()
+        g = gr_normalize_f64(mean, dr, V, npairs)
+        chi = []
+        for i in range(W.shape[0]):
+            S = sq_transform(g, dr, rho, W[i], float(self_terms[i]), Qd)
+            c2, _ = chi2(S, Sx[i])
+            chi.append(float(c2[0]))
+        history.append(chi)
+        emp_update(box, emp, W, self_terms, g, dr, Qd, Sx)
+    box.track_histogram(dr, 0)
+    return history, t
+
+
 def pair_counts_total(box: Box):
     """Number of distinct pairs per pair type (nd_box_pair_counts)."""
     out = np.zeros(box.P)

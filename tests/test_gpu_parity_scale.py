@@ -47,6 +47,7 @@ def say(*a):
     print(*a, flush=True)
 
 
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="f3_hist.txt not written yet (make_golden.py f3)")
 def test_scale_histogram_bit_exact(nd, big):
     box, T, mc, g = big
     say(f"histogram of {box.n_atoms} atoms ({box.n_atoms * (box.n_atoms - 1) // 2} pairs)")
