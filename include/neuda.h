@@ -91,6 +91,8 @@ typedef struct nd_mc_params {
     int32_t k_batch;    /* trials evaluated together; 0 = chosen by the library   */
     double tie_rel;     /* near-tie threshold (see nd_mc_sweep); 0 = 1e-6         */
     int32_t scan;       /* ND_SCAN_CELLS (default) or ND_SCAN_FULL                 */
+    double atom_frac;   /* share of single-atom moves (flexible molecules), 0..1  */
+    double atom_disp;   /* their translation half-width per axis, Angstrom, >= 0  */
 } nd_mc_params;
 
 /* How nd_mc_sweep finds the atoms within the cutoff of a moved unit.  Both
@@ -159,6 +161,18 @@ nd_status nd_box_get_coords(nd_box *box, float *xyz, int32_t where);
  * unit are excluded from all energies.  Errors: ND_E_INVALID, ND_E_RANGE. */
 nd_status nd_box_set_tables(nd_box *box, const float *U, int32_t n_pts, double h, double r_cut);
 
+/* Intramolecular harmonic terms between every two atoms of a unit (the
+ * flexible molecules of Sec. "Correctness", whose shape is kept by harmonic
+ * oscillator potentials between every two atoms):
+ *   V_intra = sum over pairs a < b of one unit of k_p (r_ab - r0_ab)^2,
+ * k host double [P] per pair type (kJ/mol/A^2, >= 0), r0_ab the pair's
+ * nearest-image length in the box's current coordinates (taken in FP64 when
+ * this is called: the reference geometry).  Every energy of the library
+ * (nd_mc_sweep's energy changes, nd_box_total_energy, nd_forces) then
+ * includes V_intra.  k = NULL removes the terms.  The running energy becomes
+ * stale.  Errors: ND_E_INVALID (negative or non-finite k). */
+nd_status nd_box_set_intra(nd_box *box, const double *k);
+
 /* Recomputes the total energy over all pairs in different units from
  * scratch (FP32 pair terms, FP64 sum), stores it as the running total and
  * writes it to *E (host).  Synchronises the box's stream. */
@@ -173,7 +187,11 @@ nd_status nd_box_energy(nd_box *box, double *E);
  * floor(u_7 n_units) of its draw 7 (ND_ORDER_RANDOM).  It proposes a
  * translation (uniform in [-max_disp, max_disp] per axis) and, for units of more than
  * one atom, a rotation by an angle uniform in [-max_rot, max_rot] about a
- * uniform axis through the unit's unweighted centroid; the energy change
+ * uniform axis through the unit's unweighted centroid.  With atom_frac > 0,
+ * a trial whose draw 8 is below atom_frac instead translates one atom of the
+ * unit, floor(u_9 na), by up to atom_disp per axis (flexible molecules,
+ * Sec. "Correctness": the molecule's translation and rotation, and the
+ * translation of one of its atoms).  The energy change
  * dE of the unit against every atom outside it decides acceptance:
  * accept iff dE <= 0 or u < exp(-dE/kT).  Random draws come from
  * SplitMix64 seeded with `seed` (output 16 t + d is draw d of trial t), so

@@ -49,6 +49,12 @@ def _load():
         "orc_propose": (_i, [_i, _d, _i, _p, _p, _d, _d, _i, _u64, _u64, _p]),
         "orc_mc_run": (_i64, [_i, _d, _i, _p, _i, _p, _p, _p, _i, _d, _d, _d, _d, _d, _i,
                               _u64, _u64, _i64, _d, _p, _p, _p, _p, _p, _p, _p]),
+        "orc_intra_reference": (None, [_i, _d, _i, _p, _p, _p]),
+        "orc_intra_energy": (None, [_i, _d, _i, _p, _i, _p, _p, _p, _p, _p, _p]),
+        "orc_intra_forces": (None, [_i, _d, _i, _p, _i, _p, _p, _p, _p, _p]),
+        "orc_propose_flex": (_i, [_i, _d, _i, _p, _p, _d, _d, _i, _d, _d, _u64, _u64, _p, _p, _p]),
+        "orc_mc_run_flex": (_i64, [_i, _d, _i, _p, _i, _p, _p, _p, _i, _d, _d, _d, _d, _d, _i, _d, _d, _p,
+                                   _p, _u64, _u64, _i64, _d, _p, _p, _p, _p, _p, _p, _p, _p]),
         "orc_edge2": (_d, [_i, _d]),
         "orc_r2": (_d, [_d, _d, _d, _d, _d, _d, _d]),
         "orc_pair_histogram": (None, [_i, _d, _i, _p, _p, _d, _i, _p, _p]),
@@ -175,6 +181,84 @@ def mc_run(box, tables, xyz, kT, max_disp, max_rot, seed, first_trial, n_trials,
     if n_acc < 0:
         raise ValueError("unit with more than 64 atoms")
     return dict(n_acc=int(n_acc), dE=dE, sabs=sabs, acc=acc, tie=tie, unit=unit, E_total=Et.value)
+
+
+def intra_reference(box, xyz=None):
+    """r0 of every intramolecular pair: float64 [N * 8] (atom a, partner slot b - first atom)."""
+    xyz = _c(box.xyz if xyz is None else xyz, np.float32)
+    uoff = _c(box.unit_offsets, np.int32)
+    if np.diff(uoff).max() > 8:
+        raise ValueError("intramolecular reference lengths take units of at most 8 atoms")
+    r0 = np.zeros(box.n_atoms * 8)
+    _load().orc_intra_reference(box.n_atoms, box.L, box.n_units, _ptr(uoff), _ptr(xyz), _ptr(r0))
+    return r0
+
+
+def intra_energy(box, kint, r0, xyz=None):
+    """(intramolecular harmonic energy, sum of |terms|)."""
+    xyz = _c(box.xyz if xyz is None else xyz, np.float32)
+    sp = _c(box.species, np.uint8)
+    uoff = _c(box.unit_offsets, np.int32)
+    k = _c(kint, np.float64)
+    r0 = _c(r0, np.float64)
+    E = C.c_double()
+    S = C.c_double()
+    _load().orc_intra_energy(box.n_atoms, box.L, box.n_species, _ptr(sp), box.n_units, _ptr(uoff), _ptr(xyz),
+                             _ptr(k), _ptr(r0), C.byref(E), C.byref(S))
+    return E.value, S.value
+
+
+def intra_forces(box, kint, r0, xyz=None):
+    """Gradient of intra_energy: [3][N]."""
+    xyz = _c(box.xyz if xyz is None else xyz, np.float32)
+    sp = _c(box.species, np.uint8)
+    uoff = _c(box.unit_offsets, np.int32)
+    k = _c(kint, np.float64)
+    r0 = _c(r0, np.float64)
+    grad = np.zeros((3, box.n_atoms))
+    _load().orc_intra_forces(box.n_atoms, box.L, box.n_species, _ptr(sp), box.n_units, _ptr(uoff), _ptr(xyz),
+                             _ptr(k), _ptr(r0), _ptr(grad))
+    return grad
+
+
+def propose_flex(box, xyz, max_disp, max_rot, order, atom_frac, atom_disp, seed, t):
+    """(unit, first moved atom, new positions [na, 3]) of trial t with single-atom moves."""
+    xyz = _c(xyz, np.float32)
+    uoff = _c(box.unit_offsets, np.int32)
+    out = np.zeros(64 * 3)
+    a0 = C.c_int()
+    na = C.c_int()
+    u = _load().orc_propose_flex(box.n_atoms, box.L, box.n_units, _ptr(uoff), _ptr(xyz), max_disp, max_rot,
+                                 int(order), atom_frac, atom_disp, seed, t, _ptr(out), C.byref(a0), C.byref(na))
+    return u, a0.value, out[: 3 * na.value].reshape(na.value, 3)
+
+
+def mc_run_flex(box, tables, xyz, kT, max_disp, max_rot, atom_frac, atom_disp, kint, r0, seed, first_trial,
+                n_trials, order=0, tie_rel=1e-6, forced=None, E_total=0.0):
+    """The Metropolis chain with intramolecular harmonic terms and single-atom
+    moves; xyz (float32 [3,N]) is updated in place."""
+    assert xyz.dtype == np.float32 and xyz.flags.c_contiguous
+    sp = _c(box.species, np.uint8)
+    uoff = _c(box.unit_offsets, np.int32)
+    U = _c(tables.U, np.float32)
+    k = _c(kint, np.float64)
+    r0 = _c(r0, np.float64)
+    n = int(n_trials)
+    dE = np.zeros(n)
+    sabs = np.zeros(n)
+    acc = np.zeros(n, np.uint8)
+    tie = np.zeros(n, np.uint8)
+    unit = np.zeros(n, np.int32)
+    atom = np.zeros(n, np.int32)
+    f = None if forced is None else _c(forced, np.uint8)
+    Et = C.c_double(E_total)
+    n_acc = _load().orc_mc_run_flex(box.n_atoms, box.L, box.n_species, _ptr(sp), box.n_units, _ptr(uoff), _ptr(xyz),
+                                    _ptr(U), U.shape[1], tables.h, tables.r_cut, kT, max_disp, max_rot, int(order),
+                                    atom_frac, atom_disp, _ptr(k), _ptr(r0), seed, first_trial, n, tie_rel, _ptr(f),
+                                    _ptr(dE), _ptr(sabs), _ptr(acc), _ptr(tie), _ptr(unit), _ptr(atom), C.byref(Et))
+    if n_acc < 0:
+        raise ValueError("unit with more than 64 atoms")
+    return dict(n_acc=int(n_acc), dE=dE, sabs=sabs, acc=acc, tie=tie, unit=unit, atom=atom, E_total=Et.value)
 
 
 def edge2(k, dr) -> float:

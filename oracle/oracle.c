@@ -309,6 +309,216 @@ int64_t orc_mc_run(int N, double L, int M, const uint8_t *species, int n_units,
 }
 
 /* ------------------------------------------------------------------ */
+/* Flexible molecules (Sec. "Correctness": the molecule's shape is kept */
+/* by harmonic oscillator potentials between every two of its atoms, and */
+/* single atoms move besides whole-molecule translations and rotations). */
+/*   V_intra = sum over unit pairs a < b of k_p (r_ab - r0_ab)^2,        */
+/* k_p per pair type, r0_ab the pair's length in a reference geometry.  */
+/* r0 is stored per atom as r0[a * 8 + (b - first atom of the unit)].   */
+/* ------------------------------------------------------------------ */
+static double dist_pts(double L, const double *p, const double *q)
+{
+    double dx = min_image(q[0] - p[0], L), dy = min_image(q[1] - p[1], L), dz = min_image(q[2] - p[2], L);
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+static void atom_pos(const float *xyz, int N, int a, double p[3])
+{
+    p[0] = xyz[a];
+    p[1] = xyz[N + a];
+    p[2] = xyz[2 * N + a];
+}
+
+/* Reference lengths r0 of every intramolecular pair from coordinates xyz. */
+void orc_intra_reference(int N, double L, int n_units, const int32_t *uoff, const float *xyz, double *r0)
+{
+    for (size_t q = 0; q < (size_t)N * 8; ++q) r0[q] = 0.0;
+    for (int u = 0; u < n_units; ++u)
+        for (int a = uoff[u]; a < uoff[u + 1]; ++a)
+            for (int b = uoff[u]; b < uoff[u + 1]; ++b) {
+                if (a == b) continue;
+                double pa[3], pb[3];
+                atom_pos(xyz, N, a, pa);
+                atom_pos(xyz, N, b, pb);
+                r0[(size_t)a * 8 + (b - uoff[u])] = dist_pts(L, pa, pb);
+            }
+}
+
+/* Total intramolecular energy and the sum of its |terms|. */
+void orc_intra_energy(int N, double L, int M, const uint8_t *species, int n_units, const int32_t *uoff,
+                      const float *xyz, const double *kint, const double *r0, double *E_out, double *S_out)
+{
+    double E = 0.0, S = 0.0;
+    for (int u = 0; u < n_units; ++u)
+        for (int a = uoff[u]; a < uoff[u + 1]; ++a)
+            for (int b = a + 1; b < uoff[u + 1]; ++b) {
+                double pa[3], pb[3];
+                atom_pos(xyz, N, a, pa);
+                atom_pos(xyz, N, b, pb);
+                double d = dist_pts(L, pa, pb) - r0[(size_t)a * 8 + (b - uoff[u])];
+                double v = kint[orc_pair_index(species[a], species[b], M)] * d * d;
+                E += v;
+                S += fabs(v);
+            }
+    *E_out = E;
+    *S_out = S;
+}
+
+/* Gradient of the intramolecular energy added to grad [3][N]:
+ * dV/dx_a = sum over the other atoms b of a's unit of 2 k (r - r0) (x_a - x_b) / r. */
+void orc_intra_forces(int N, double L, int M, const uint8_t *species, int n_units, const int32_t *uoff,
+                      const float *xyz, const double *kint, const double *r0, double *grad)
+{
+    for (int u = 0; u < n_units; ++u)
+        for (int a = uoff[u]; a < uoff[u + 1]; ++a)
+            for (int b = uoff[u]; b < uoff[u + 1]; ++b) {
+                if (a == b) continue;
+                double d[3] = {min_image((double)xyz[a] - (double)xyz[b], L),
+                               min_image((double)xyz[N + a] - (double)xyz[N + b], L),
+                               min_image((double)xyz[2 * N + a] - (double)xyz[2 * N + b], L)};
+                double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                if (r == 0.0) continue;
+                double c = 2.0 * kint[orc_pair_index(species[a], species[b], M)] *
+                           (r - r0[(size_t)a * 8 + (b - uoff[u])]) / r;
+                for (int q = 0; q < 3; ++q) grad[(size_t)q * N + a] += c * d[q];
+            }
+}
+
+/* Energy change of unit u's intramolecular terms when atoms a0 .. a0+na-1
+ * of it move to newpos[na][3] (the others stay). */
+static void intra_delta(int N, double L, int M, const uint8_t *species, const int32_t *uoff, int u, int a0,
+                        int na, const float *xyz, const double *newpos, const double *kint, const double *r0,
+                        double *dE, double *S)
+{
+    int u0 = uoff[u], u1 = uoff[u + 1];
+    double e = 0.0, s = 0.0;
+    for (int a = u0; a < u1; ++a)
+        for (int b = a + 1; b < u1; ++b) {
+            int ma = a >= a0 && a < a0 + na, mb = b >= a0 && b < a0 + na;
+            if (!ma && !mb) continue;
+            double pa[3], pb[3], qa[3], qb[3];
+            atom_pos(xyz, N, a, pa);
+            atom_pos(xyz, N, b, pb);
+            for (int c = 0; c < 3; ++c) {
+                qa[c] = ma ? newpos[3 * (a - a0) + c] : pa[c];
+                qb[c] = mb ? newpos[3 * (b - a0) + c] : pb[c];
+            }
+            double k = kint[orc_pair_index(species[a], species[b], M)];
+            double r0ab = r0[(size_t)a * 8 + (b - u0)];
+            double dn = dist_pts(L, qa, qb) - r0ab, dold = dist_pts(L, pa, pb) - r0ab;
+            double vn = k * dn * dn, vo = k * dold * dold;
+            e += vn - vo;
+            s += fabs(vn) + fabs(vo);
+        }
+    *dE = e;
+    *S = s;
+}
+
+/* Energy change of atoms a0 .. a0+na-1 (all of one unit u) moving to
+ * newpos: intermolecular pair terms against every atom outside u. */
+static void inter_delta(int N, double L, int M, const uint8_t *species, const int32_t *uoff, int u, int a0, int na,
+                        const float *xyz, const double *newpos, const float *tab, int n_pts, double h, double r_cut,
+                        double *dE_out, double *Sabs_out)
+{
+    int u0 = uoff[u], u1 = uoff[u + 1];
+    double dE = 0.0, S = 0.0;
+    for (int a = a0; a < a0 + na; ++a) {
+        double ox = xyz[a], oy = xyz[N + a], oz = xyz[2 * N + a];
+        const double *np_ = newpos + 3 * (a - a0);
+        double sum = 0.0, sabs = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : sum, sabs)
+        for (int j = 0; j < N; ++j) {
+            if (j >= u0 && j < u1) continue;
+            const float *row = tab + (size_t)orc_pair_index(species[a], species[j], M) * n_pts;
+            double un = orc_table_u(row, n_pts, h, r_cut, pair_dist(xyz, N, L, j, np_[0], np_[1], np_[2]));
+            double uo = orc_table_u(row, n_pts, h, r_cut, pair_dist(xyz, N, L, j, ox, oy, oz));
+            sum += un - uo;
+            sabs += fabs(un) + fabs(uo);
+        }
+        dE += sum;
+        S += sabs;
+    }
+    *dE_out = dE;
+    *Sabs_out = S;
+}
+
+/* Trial t of a flexible-molecule run: with probability atom_frac (draw 8)
+ * one atom of the unit, floor(u_9 na), translates by up to atom_disp per
+ * axis (draws 0-2); otherwise the whole unit moves as in orc_propose.
+ * Writes the moved atoms' new positions and returns the unit; *a0_out and
+ * *na_out give the moved atoms. */
+int orc_propose_flex(int N, double L, int n_units, const int32_t *uoff, const float *xyz, double max_disp,
+                     double max_rot, int order, double atom_frac, double atom_disp, uint64_t seed, uint64_t t,
+                     double *newpos, int *a0_out, int *na_out)
+{
+    int u;
+    if (order == 0) u = (int)(t % (uint64_t)n_units);
+    else {
+        u = (int)floor(orc_uniform(seed, t, 7) * (double)n_units);
+        if (u >= n_units) u = n_units - 1;
+    }
+    int na = uoff[u + 1] - uoff[u];
+    if (orc_uniform(seed, t, 8) < atom_frac) {
+        int ai = (int)floor(orc_uniform(seed, t, 9) * (double)na);
+        if (ai >= na) ai = na - 1;
+        int a = uoff[u] + ai;
+        for (int c = 0; c < 3; ++c)
+            newpos[c] = wrap_round((double)xyz[c * N + a] + atom_disp * (2.0 * orc_uniform(seed, t, c) - 1.0), L);
+        *a0_out = a;
+        *na_out = 1;
+        return u;
+    }
+    orc_propose(N, L, n_units, uoff, xyz, max_disp, max_rot, order, seed, t, newpos);
+    *a0_out = uoff[u];
+    *na_out = na;
+    return u;
+}
+
+/* The Metropolis chain of orc_mc_run with intramolecular harmonic terms
+ * (kint [P], r0 as orc_intra_reference) and single-atom moves. */
+int64_t orc_mc_run_flex(int N, double L, int M, const uint8_t *species, int n_units, const int32_t *uoff,
+                        float *xyz, const float *tab, int n_pts, double h, double r_cut, double kT, double max_disp,
+                        double max_rot, int order, double atom_frac, double atom_disp, const double *kint,
+                        const double *r0, uint64_t seed, uint64_t first_trial, int64_t n_trials, double tie_rel,
+                        const uint8_t *forced, double *dE_out, double *sabs_out, uint8_t *acc_out, uint8_t *tie_out,
+                        int32_t *unit_out, int32_t *atom_out, double *E_total)
+{
+    int64_t n_acc = 0;
+    double newpos[64 * 3];
+    for (int64_t k = 0; k < n_trials; ++k) {
+        uint64_t t = first_trial + (uint64_t)k;
+        int a0, na;
+        int u = orc_propose_flex(N, L, n_units, uoff, xyz, max_disp, max_rot, order, atom_frac, atom_disp, seed, t,
+                                 newpos, &a0, &na);
+        if (u < 0 || na > 64) return -1;
+        double dEi, Si, dEa, Sa;
+        inter_delta(N, L, M, species, uoff, u, a0, na, xyz, newpos, tab, n_pts, h, r_cut, &dEi, &Si);
+        intra_delta(N, L, M, species, uoff, u, a0, na, xyz, newpos, kint, r0, &dEa, &Sa);
+        double dE = dEi + dEa, sabs = Si + Sa;
+        double u6 = orc_uniform(seed, t, 6);
+        int acc = (dE <= 0.0) || (u6 < exp(-dE / kT));
+        int tie = 0;
+        if (u6 > 0.0 && fabs(log(u6) + dE / kT) < tie_rel * sabs / kT) {
+            tie = 1;
+            if (forced) acc = forced[k] ? 1 : 0;
+        }
+        if (acc) {
+            for (int a = a0; a < a0 + na; ++a)
+                for (int c = 0; c < 3; ++c) xyz[c * N + a] = (float)newpos[3 * (a - a0) + c];
+            if (E_total) *E_total += dE;
+            ++n_acc;
+        }
+        if (dE_out) dE_out[k] = dE;
+        if (sabs_out) sabs_out[k] = sabs;
+        if (acc_out) acc_out[k] = (uint8_t)acc;
+        if (tie_out) tie_out[k] = (uint8_t)tie;
+        if (unit_out) unit_out[k] = u;
+        if (atom_out) atom_out[k] = na == 1 && uoff[u + 1] - uoff[u] > 1 ? a0 : -1;
+    }
+    return n_acc;
+}
+
+/* ------------------------------------------------------------------ */
 /* Pair-count histogram N_ab(r) (Sec. "Acceleration method").           */
 /* For every unordered pair i < j (same unit included):                */
 /*   d = x_j - x_i per axis in double, nearest image by comparison     */

@@ -56,7 +56,7 @@ class nd_box_desc(C.Structure):
 class nd_mc_params(C.Structure):
     _fields_ = [("kT", C.c_double), ("max_disp", C.c_double), ("max_rot", C.c_double),
                 ("order", C.c_int32), ("k_batch", C.c_int32), ("tie_rel", C.c_double),
-                ("scan", C.c_int32)]
+                ("scan", C.c_int32), ("atom_frac", C.c_double), ("atom_disp", C.c_double)]
 
 
 class nd_mc_stats(C.Structure):
@@ -103,6 +103,7 @@ EXPORTS = {
     "nd_box_get_coords": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "nd_box_set_tables": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double]),
     "nd_box_total_energy": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double)]),
+    "nd_box_set_intra": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "nd_box_energy": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double)]),
     "nd_mc_sweep": (C.c_int32, [C.c_void_p, C.POINTER(nd_mc_params), C.c_uint64, C.c_uint64,
                                 C.c_int64, C.POINTER(nd_mc_stats), C.POINTER(nd_mc_trace)]),
@@ -278,10 +279,12 @@ class MCParams:
     k_batch: int = 0
     tie_rel: float = 0.0
     scan: int = ND_SCAN_CELLS
+    atom_frac: float = 0.0
+    atom_disp: float = 0.0
 
     def c(self):
         return nd_mc_params(self.kT, self.max_disp, self.max_rot, self.order, self.k_batch,
-                            self.tie_rel, self.scan)
+                            self.tie_rel, self.scan, self.atom_frac, self.atom_disp)
 
 
 class Box:
@@ -367,6 +370,16 @@ class Box:
         _check(lib().nd_box_set_tables(self.handle, U.ctypes.data, U.shape[1], float(h), float(r_cut)))
         self._n_pts = int(U.shape[1])
         self.version += 1
+
+    def set_intra(self, k):
+        """Intramolecular harmonic terms k_p (r - r0)^2 between every two atoms of a
+        unit, r0 from the current coordinates (k: [P] kJ/mol/A^2, None removes them)."""
+        self._sync_stream()
+        if k is None:
+            _check(lib().nd_box_set_intra(self.handle, None))
+        else:
+            kk = _host_f64(k, self.P)
+            _check(lib().nd_box_set_intra(self.handle, kk.ctypes.data))
 
     def set_coords(self, xyz, keep_energy=False):
         torch = _torch()

@@ -990,6 +990,9 @@ void launch_forces_in(nd_box *b, double *d_grad, double *d_E, char *ws, long lon
     ND_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_sum_serial, dim3(1), dim3(256), 0, b->stream, a.epart, (int)G, d_E);
     ND_HIP(hipGetLastError());
+    // flexible molecules: the intramolecular harmonic terms
+    launch_intra_forces_add(b, d_grad);
+    launch_intra_energy_add(b, d_E, nullptr);
 }
 
 }  // namespace nd

@@ -105,7 +105,50 @@ struct ProposeArgs {
     int32_t *slab;  // [N_SLAB] counts (zero beforehand), then [N_SLAB][kcap] trial lists
     int4 *head;     // [kb] unit, first atom, atoms, 0 of each trial (compact copy for the decision)
     double *hthr;   // [kb] acceptance threshold of each trial (compact copy)
+    // flexible molecules: single-atom moves and intramolecular harmonic terms
+    double atom_frac, atom_disp;
+    const double *r0;       // [N][ND_MAX_UNIT_ATOMS] reference lengths (null: no intramolecular terms)
+    const uint8_t *sp;      // [N] species
+    int M;
+    double kint[ND_MAX_SPECIES * (ND_MAX_SPECIES + 1) / 2];
 };
+
+// Nearest-image distance in FP64 of two positions (displacement by
+// comparison with L/2, the oracle's form).
+__device__ __forceinline__ double dist_fp64(double ax, double ay, double az, double bx, double by, double bz, double L)
+{
+    const double dx = min_image_cmp(bx - ax, L), dy = min_image_cmp(by - ay, L), dz = min_image_cmp(bz - az, L);
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+// Change of unit u's intramolecular energy sum_{a<b} k (r_ab - r0_ab)^2 when
+// atoms a0 .. a0 + na - 1 move to new_x (the others stay), and its |terms|.
+__device__ void intra_delta(const ProposeArgs &a, int u0, int u1, int a0, int na, const float (*new_x)[3],
+                            double &dE, double &S)
+{
+    const int N = a.N;
+    double e = 0.0, s = 0.0;
+    for (int p = u0; p < u1; ++p)
+        for (int q = p + 1; q < u1; ++q) {
+            const bool mp = p >= a0 && p < a0 + na, mq = q >= a0 && q < a0 + na;
+            if (!mp && !mq) continue;
+            const double px = a.xyz[p], py = a.xyz[N + p], pz = a.xyz[2 * N + p];
+            const double qx = a.xyz[q], qy = a.xyz[N + q], qz = a.xyz[2 * N + q];
+            const double npx = mp ? (double)new_x[p - a0][0] : px, npy = mp ? (double)new_x[p - a0][1] : py,
+                         npz = mp ? (double)new_x[p - a0][2] : pz;
+            const double nqx = mq ? (double)new_x[q - a0][0] : qx, nqy = mq ? (double)new_x[q - a0][1] : qy,
+                         nqz = mq ? (double)new_x[q - a0][2] : qz;
+            const double k = a.kint[nd::pair_index(a.sp[p], a.sp[q], a.M)];
+            const double r0 = a.r0[(size_t)p * ND_MAX_UNIT_ATOMS + (q - u0)];
+            const double dn = dist_fp64(npx, npy, npz, nqx, nqy, nqz, a.L) - r0;
+            const double dold = dist_fp64(px, py, pz, qx, qy, qz, a.L) - r0;
+            const double vn = k * dn * dn, vo = k * dold * dold;
+            e += vn - vo;
+            s += fabs(vn) + fabs(vo);
+        }
+    dE = e;
+    S = s;
+}
 
 // Threshold form of the Metropolis test: with u > 0, u < exp(-dE/kT)
 // exactly when dE < -kT ln u (they can differ only by rounding, far inside
@@ -124,15 +167,26 @@ __device__ __forceinline__ void propose_one(const ProposeArgs &a, int k)
 {
     const uint64_t t = a.t0 + (uint64_t)k;
     const int u = trial_unit(a.order, a.seed, t, a.n_units);
-    const int a0 = a.uoff[u];
-    const int na = a.uoff[u + 1] - a0;
+    const int u0 = a.uoff[u], u1 = a.uoff[u + 1];
+    int a0 = u0;
+    int na = u1 - u0;
     const int N = a.N;
     const double L = a.L;
     nd::Trial *T = a.trials + k;
 
+    // a single-atom move (draw 8 below atom_frac): atom floor(u_9 na) of the
+    // unit translates by up to atom_disp per axis
+    double disp = a.max_disp;
+    if (a.atom_frac > 0.0 && draw(a.seed, t, 8) < a.atom_frac) {
+        int ai = (int)floor(draw(a.seed, t, 9) * (double)na);
+        if (ai >= na) ai = na - 1;
+        a0 = u0 + ai;
+        na = 1;
+        disp = a.atom_disp;
+    }
     double tau[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) tau[c] = a.max_disp * (2.0 * draw(a.seed, t, c) - 1.0);
+    for (int c = 0; c < 3; ++c) tau[c] = disp * (2.0 * draw(a.seed, t, c) - 1.0);
     T->unit = u;
     T->a0 = a0;
     T->na = na;
@@ -231,6 +285,9 @@ __device__ __forceinline__ void propose_one(const ProposeArgs &a, int k)
         r2max = fmaxf(r2max, dx * dx + dy * dy + dz * dz);
     }
     const float rad = sqrtf(r2max) * 1.0001f + 2e-6f;
+    T->dintra = 0.0;
+    T->sintra = 0.0;
+    if (a.r0) intra_delta(a, u0, u1, a0, na, T->new_x, T->dintra, T->sintra);
     T->cen[0] = cx;
     T->cen[1] = cy;
     T->cen[2] = cz;
@@ -362,11 +419,12 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_mc_scan(ScanArgs a)
 // ---------------------------------------------------------------- partial sums
 // full scan: dE0_k = sum over j-blocks of the partial sums (fixed order)
 __global__ void k_mc_reduce(const double *__restrict__ partial, int n_jb, int kcap, int kb, double *__restrict__ dE0,
-                            double *__restrict__ S0)
+                            double *__restrict__ S0, const nd::Trial *__restrict__ trials)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= kb) return;
-    double e = 0.0, s = 0.0;
+    // the intramolecular change of flexible molecules first, then the pair sums
+    double e = trials[k].dintra, s = trials[k].sintra;
     for (int jb = 0; jb < n_jb; ++jb) {
         e += partial[((size_t)jb * 2 + 0) * kcap + k];
         s += partial[((size_t)jb * 2 + 1) * kcap + k];
@@ -886,8 +944,9 @@ __device__ __forceinline__ void scan_cells_group(const CellScanArgs &a, const Pa
     }
     if (NW == 1) {
         if (lane == 0) {
-            a.dE0[k] = e;
-            a.S0[k] = s;
+            const nd::Trial &T = a.trials[k];
+            a.dE0[k] = T.dintra + e;
+            a.S0[k] = T.sintra + s;
         }
         return;
     }
@@ -902,8 +961,9 @@ __device__ __forceinline__ void scan_cells_group(const CellScanArgs &a, const Pa
             E += red[2 * w];
             S += red[2 * w + 1];
         }
-        a.dE0[k] = E;
-        a.S0[k] = S;
+        const nd::Trial &T = a.trials[k];
+        a.dE0[k] = T.dintra + E;
+        a.S0[k] = T.sintra + S;
     }
 }
 
@@ -1635,7 +1695,8 @@ int mc_batch_size(nd_box *b, const nd_mc_params *p, double target)
             nd_tuning e;
             target = (tune_lookup(ND_TUNE_BOX, b->N, &e) && e.batch_target > 0.0) ? e.batch_target : 18.0;
         }
-        const double ext = (b->max_na > 1 ? 1.2 : 0.0) + p->max_disp * 1.8;
+        const double disp = std::max(p->max_disp, p->atom_frac > 0.0 ? p->atom_disp : 0.0);
+        const double ext = (b->max_na > 1 ? 1.2 : 0.0) + disp * 1.8;
         const double reach = b->rc + 2.0 * ext;
         const double f = (4.0 / 3.0) * M_PI * reach * reach * reach / (b->L * b->L * b->L);
         K = (int)std::min(1e9, target / std::max(f, 1e-9));
@@ -1727,6 +1788,12 @@ ProposeArgs proposal_args(const nd_box *b, const nd_mc_params *p, uint64_t seed,
     pa.slab = slab_buffer(b, buf);
     pa.head = w.head + (size_t)buf * K;
     pa.hthr = w.hthr + (size_t)buf * K;
+    pa.atom_frac = p->atom_frac;
+    pa.atom_disp = p->atom_disp;
+    pa.r0 = b->has_intra ? b->r0 : nullptr;
+    pa.sp = b->species;
+    pa.M = b->M;
+    for (int q = 0; q < ND_MAX_SPECIES * (ND_MAX_SPECIES + 1) / 2; ++q) pa.kint[q] = b->kint[q];
     return pa;
 }
 
@@ -2077,7 +2144,7 @@ void mc_run_full(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t first
             ND_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(k_mc_reduce, dim3((kb + 255) / 256), dim3(256), 0, b->stream, w.partial, n_jb, w.cap_k, kb,
-                           w.dE0 + (size_t)buf * w.cap_k, w.S0 + (size_t)buf * w.cap_k);
+                           w.dE0 + (size_t)buf * w.cap_k, w.S0 + (size_t)buf * w.cap_k, trials);
         ND_HIP(hipGetLastError());
         switch (maxnu) {
         case 1: launch_corr<1>(b, cr); break;

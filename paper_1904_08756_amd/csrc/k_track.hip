@@ -111,15 +111,20 @@ __global__ __launch_bounds__(DN_THREADS) void k_mc_dn(DnArgs a)
         const float xj = a.xyz[j], yj = a.xyz[N + j], zj = a.xyz[2 * N + j];
         const int sj = a.sp[j];
         const long long tag = a.moved[a.unit_of[j]];
-        // trial of this batch that moved j's unit, or -1
-        const int mj = (tag >= a.tag_base && tag < a.tag_base + nd::TRACK_TAG_STRIDE) ? (int)(tag - a.tag_base) : -1;
+        // trial of this batch that moved j (a whole unit, or one atom of a
+        // flexible unit), or -1
+        int mj = (tag >= a.tag_base && tag < a.tag_base + nd::TRACK_TAG_STRIDE) ? (int)(tag - a.tag_base) : -1;
         float ojx = xj, ojy = yj, ojz = zj;  // j before the batch
         if (mj >= 0) {
             const nd::Trial &Tm = a.trials[mj];
             const int at = j - Tm.a0;
-            ojx = Tm.old_x[at][0];
-            ojy = Tm.old_x[at][1];
-            ojz = Tm.old_x[at][2];
+            if (at >= 0 && at < Tm.na) {
+                ojx = Tm.old_x[at][0];
+                ojy = Tm.old_x[at][1];
+                ojz = Tm.old_x[at][2];
+            } else {
+                mj = -1;  // j's unit moved only one of its other atoms
+            }
         }
         for (int li = 0; li < n_acc; ++li) {
             const int k = __builtin_amdgcn_readfirstlane(s_list[li]);

@@ -116,6 +116,10 @@ void check_mc_params(const nd_box *b, const nd_mc_params *p)
     require(p->k_batch >= 0, ND_E_INVALID, "k_batch must be >= 0");
     require(p->order == ND_ORDER_SEQ || p->order == ND_ORDER_RANDOM, ND_E_INVALID, "unknown order");
     require(p->scan == ND_SCAN_CELLS || p->scan == ND_SCAN_FULL, ND_E_INVALID, "unknown scan mode");
+    require(std::isfinite(p->atom_frac) && p->atom_frac >= 0.0 && p->atom_frac <= 1.0, ND_E_INVALID,
+            "atom_frac must be in [0, 1]");
+    require(std::isfinite(p->atom_disp) && p->atom_disp >= 0.0, ND_E_INVALID, "atom_disp must be >= 0");
+    require(p->atom_disp < 0.25 * b->L, ND_E_RANGE, "atom_disp must be < L/4");
     require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
 }
 
@@ -323,6 +327,7 @@ static void free_box(nd_box *b)
     nd::dfree(b->tab);
     nd::dfree(b->rp);
     nd::dfree(b->emp);
+    nd::dfree(b->r0);
     nd::dfree(b->E);
     nd::dfree(b->mc.trials);
     nd::dfree(b->mc.partial);
@@ -629,9 +634,30 @@ nd_status nd_box_total_energy(nd_box *b, double *E)
         require(b->has_tables, ND_E_STATE, "nd_box_set_tables has not been called");
         DeviceGuard g(b->device);
         nd::launch_total_energy(b, b->E, nullptr);
+        nd::launch_intra_energy_add(b, b->E, nullptr);
         ND_HIP(hipMemcpyAsync(E, b->E, sizeof(double), hipMemcpyDeviceToHost, b->stream));
         ND_HIP(hipStreamSynchronize(b->stream));
         b->energy_valid = true;
+    });
+}
+
+nd_status nd_box_set_intra(nd_box *b, const double *k)
+{
+    return guarded([&] {
+        check_box(b);
+        if (k)
+            for (int p = 0; p < b->P; ++p)
+                require(std::isfinite(k[p]) && k[p] >= 0.0, ND_E_INVALID, "k must be finite and >= 0");
+        DeviceGuard g(b->device);
+        if (!k) {
+            b->has_intra = false;
+            for (double &v : b->kint) v = 0.0;
+        } else {
+            for (int p = 0; p < b->P; ++p) b->kint[p] = k[p];
+            nd::launch_intra_reference(b);
+            b->has_intra = true;
+        }
+        b->energy_valid = false;
     });
 }
 
@@ -658,6 +684,7 @@ nd_status nd_mc_sweep(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t 
         // tables changed since it was last computed
         if (!b->energy_valid) {
             nd::launch_total_energy(b, b->E, nullptr);
+            nd::launch_intra_energy_add(b, b->E, nullptr);
             b->energy_valid = true;
         }
         if (b->track.on && !b->track.valid) nd::track_refresh(b);
@@ -1295,6 +1322,7 @@ nd_status nd_batch_run(nd_batch *t, const nd_batch_plan *pl, nd_mc_stats *stats)
             for (int i = 0; i < n; ++i)
                 if (!boxes[i]->energy_valid) {
                     nd::launch_total_energy(boxes[i], boxes[i]->E, nullptr);
+                    nd::launch_intra_energy_add(boxes[i], boxes[i]->E, nullptr);
                     boxes[i]->energy_valid = true;
                 }
         // ---- order after pending work on the boxes' streams

@@ -45,8 +45,9 @@ struct Trial {
     float old_x[ND_MAX_UNIT_ATOMS][3];  // absolute float32 positions before the move
     float cen[3];                       // fractional centre of old+new atoms
     float rad;                          // fractional radius about cen
-    int32_t unit, a0, na, pad;
+    int32_t unit, a0, na, pad;           // moved atoms a0 .. a0 + na - 1 of the unit
     double thr;                         // acceptance threshold -kT ln u of the trial's draw u
+    double dintra, sintra;              // intramolecular energy change and its sum of |terms|
 };
 
 struct McWork {
@@ -147,6 +148,10 @@ struct nd_box {
     int n_pts = 0;
     double h = 0.0, rc = 0.0;
     bool has_tables = false;
+    // intramolecular harmonic terms (flexible molecules)
+    double kint[ND_MAX_SPECIES * (ND_MAX_SPECIES + 1) / 2] = {};
+    double *r0 = nullptr;        // device [N][ND_MAX_UNIT_ATOMS]: reference length to each atom of the unit
+    bool has_intra = false;
     // running energy
     double *E = nullptr;         // device [1]
     bool energy_valid = false;
@@ -174,6 +179,12 @@ void launch_pos4_from_xyz(nd_box *b);
 void launch_wrap_coords(nd_box *b, const float *d_in, float *d_out, int *d_bad);
 void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts);
 void launch_total_energy(nd_box *b, double *d_E_out, double *d_sabs_out);
+// Intramolecular terms (k_intra in k_track.hip): reference lengths from the
+// current coordinates; energy added to *d_E (and |terms| to *d_S if not
+// null); gradient added to d_grad [3][N].
+void launch_intra_reference(nd_box *b);
+void launch_intra_energy_add(nd_box *b, double *d_E, double *d_S);
+void launch_intra_forces_add(nd_box *b, double *d_grad);
 void launch_gr_normalize(const uint64_t *counts, int P, int nbins, double dr, double V,
                          const double *npairs_host, double *g, hipStream_t s);
 void launch_gr_normalize_f64(const double *counts, int P, int nbins, double dr, double V,
