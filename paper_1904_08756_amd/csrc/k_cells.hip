@@ -15,6 +15,7 @@
 // takes an array of box descriptors indexed by blockIdx.y, so one launch
 // rebuilds the cells of several boxes.
 #include "nd_internal.h"
+#include "nd_pair.h"
 
 #include <algorithm>
 #include <cmath>
@@ -168,9 +169,158 @@ __global__ void k_fill_i32(int32_t *p, int n, int v)
     if (i < n) p[i] = v;
 }
 
+// Total energy from freshly built cells: one thread per sorted slot i sums
+// the pair terms with every slot j > i of a different unit in the cells
+// within reach (R cells per axis; the whole axis when 2R + 1 >= nc, so no
+// cell is visited twice), with the same pair evaluation as the Metropolis
+// kernels; FP64 sums per thread, per block in a fixed order.
+struct CellEnergyArgs {
+    const float4 *spos4, *sposlo;
+    const int32_t *start;
+    const float *tab;
+    int N, M, n_pts, nc, R;
+    float rcf2_filter;
+    double rcf2, tscale;
+    double *partial;  // [gridDim.x][2]
+};
+
+constexpr int CE_THREADS = 256;
+
+__global__ __launch_bounds__(CE_THREADS) void k_energy_cells(CellEnergyArgs a)
+{
+    extern __shared__ __align__(16) float s_tab[];
+    __shared__ int prow[16];
+    __shared__ double red[2][CE_THREADS / 64];
+    const int tid = threadIdx.x;
+    const int P = a.M * (a.M + 1) / 2;
+    nd::stage_floats<CE_THREADS>(s_tab, a.tab, P * a.n_pts);
+    if (tid < a.M * a.M) prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
+    __syncthreads();
+    const nd::PairCtx c{s_tab, prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
+    const int i = blockIdx.x * CE_THREADS + tid;
+    double e = 0.0, s = 0.0;
+    if (i < a.N) {
+        const int nc = a.nc, R = a.R;
+        const float4 pi = a.spos4[i], pil = a.sposlo[i];
+        const int ui = __float_as_int(pil.w);
+        const double sx = (double)pi.x + (double)pil.x, sy = (double)pi.y + (double)pil.y,
+                     sz = (double)pi.z + (double)pil.z;
+        const int rb = __float_as_int(pi.w) * a.M;
+        const int cx = min(max((int)(pi.x * (float)nc), 0), nc - 1);
+        const int cy = min(max((int)(pi.y * (float)nc), 0), nc - 1);
+        const int cz = min(max((int)(pi.z * (float)nc), 0), nc - 1);
+        const bool all = 2 * R + 1 >= nc;
+        const int lo = all ? 0 : -R, hi = all ? nc - 1 : R;
+        for (int dz = lo; dz <= hi; ++dz) {
+            const int z = all ? dz : (cz + dz + nc) % nc;
+            for (int dy = lo; dy <= hi; ++dy) {
+                const int y = all ? dy : (cy + dy + nc) % nc;
+                const int row = (z * nc + y) * nc;
+                // the row's cells cx - R .. cx + R as at most two slot ranges
+                int r0a, r0b, r1a = 0, r1b = 0;
+                if (all) {
+                    r0a = a.start[row];
+                    r0b = a.start[row + nc];
+                } else {
+                    const int xl = cx - R, xh = cx + R;
+                    if (xl < 0) {
+                        r0a = a.start[row + xl + nc];
+                        r0b = a.start[row + nc];
+                        r1a = a.start[row];
+                        r1b = a.start[row + xh + 1];
+                    } else if (xh >= nc) {
+                        r0a = a.start[row + xl];
+                        r0b = a.start[row + nc];
+                        r1a = a.start[row];
+                        r1b = a.start[row + xh - nc + 1];
+                    } else {
+                        r0a = a.start[row + xl];
+                        r0b = a.start[row + xh + 1];
+                    }
+                }
+                for (int part = 0; part < 2; ++part) {
+                    const int ja = part ? r1a : r0a, jb = part ? r1b : r0b;
+                    for (int j = max(ja, i + 1); j < jb; ++j) {
+                        const float4 pj = a.spos4[j], pjl = a.sposlo[j];
+                        if (__float_as_int(pjl.w) == ui) continue;
+                        float u;
+                        if (nd::pair_u(c, pi, sx, sy, sz, rb, pj, pjl, u)) {
+                            e += (double)u;
+                            s += (double)fabsf(u);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        e += __shfl_xor(e, o);
+        s += __shfl_xor(s, o);
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = e;
+        red[1][tid >> 6] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double te = 0.0, ts = 0.0;
+        for (int w = 0; w < CE_THREADS / 64; ++w) {
+            te += red[0][w];
+            ts += red[1][w];
+        }
+        a.partial[2 * blockIdx.x] = te;
+        a.partial[2 * blockIdx.x + 1] = ts;
+    }
+}
+
+// Fixed-order sum of the block partials: thread t adds blocks t, t + 256, ...,
+// then thread 0 adds the 256 sums in order.
+__global__ void k_energy_cells_sum(const double *__restrict__ partial, int G, double *__restrict__ E)
+{
+    __shared__ double re[256];
+    double e = 0.0;
+    for (int g = threadIdx.x; g < G; g += 256) e += partial[2 * g];
+    re[threadIdx.x] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < 256; ++k) t += re[k];
+        *E = t;
+    }
+}
+
 }  // namespace
 
 namespace nd {
+
+// The box's energy over pairs in different units within r_cut in O(N),
+// from cell lists rebuilt here (the same pair terms as launch_total_energy,
+// summed in another order).
+void launch_energy_cells(nd_box *b, double *d_E)
+{
+    cells_build(b);
+    const Cells &cl = b->cells;
+    CellEnergyArgs a;
+    a.spos4 = cl.spos4;
+    a.sposlo = cl.sposlo;
+    a.start = cl.start;
+    a.tab = b->tab;
+    a.N = b->N;
+    a.M = b->M;
+    a.n_pts = b->n_pts;
+    a.nc = cl.nc;
+    a.R = (int)std::floor(b->rc / b->L * cl.nc) + 1;
+    a.rcf2_filter = filter_r2(b->rc / b->L);
+    a.rcf2 = (b->rc / b->L) * (b->rc / b->L);
+    a.tscale = b->L / b->h;
+    const int G = (b->N + CE_THREADS - 1) / CE_THREADS;
+    a.partial = static_cast<double *>(workspace(b, sizeof(double) * 2 * (size_t)G));
+    const size_t lds = sizeof(float) * (size_t)b->P * b->n_pts;
+    hipLaunchKernelGGL(k_energy_cells, dim3(G), dim3(CE_THREADS), lds, b->stream, a);
+    ND_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_energy_cells_sum, dim3(1), dim3(256), 0, b->stream, a.partial, G, d_E);
+    ND_HIP(hipGetLastError());
+}
 
 void cells_free(nd_box *b)
 {

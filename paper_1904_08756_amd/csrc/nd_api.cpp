@@ -683,7 +683,8 @@ nd_status nd_mc_sweep(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t 
         // the running energy is brought up to date first when coordinates or
         // tables changed since it was last computed
         if (!b->energy_valid) {
-            nd::launch_total_energy(b, b->E, nullptr);
+            // O(N) from cell lists (the explicit nd_box_total_energy sums all pairs)
+            nd::launch_energy_cells(b, b->E);
             nd::launch_intra_energy_add(b, b->E, nullptr);
             b->energy_valid = true;
         }
@@ -1321,7 +1322,7 @@ nd_status nd_batch_run(nd_batch *t, const nd_batch_plan *pl, nd_mc_stats *stats)
         if (pl->sweeps > 0)
             for (int i = 0; i < n; ++i)
                 if (!boxes[i]->energy_valid) {
-                    nd::launch_total_energy(boxes[i], boxes[i]->E, nullptr);
+                    nd::launch_energy_cells(boxes[i], boxes[i]->E);
                     nd::launch_intra_energy_add(boxes[i], boxes[i]->E, nullptr);
                     boxes[i]->energy_valid = true;
                 }

@@ -260,6 +260,7 @@ void launch_emp_update(nd_box *b, const nd_emp_params *prm, int n_prof, const do
                        const double *self_host, const double *g, int nbins, double dr, const double *Q, int nQ,
                        const double *S_exp, double *dS_out, double *emp_out, double *C_out);
 void cells_build(nd_box *b);
+void launch_energy_cells(nd_box *b, double *d_E);
 void cells_ensure(nd_box *b);
 void cells_rebuild_launch(hipStream_t s, const CellBuildArgs *d_args, int n_boxes, int max_n, int max_ncell);
 void cells_free(nd_box *b);

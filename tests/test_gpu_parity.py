@@ -567,3 +567,30 @@ def test_box_density(nd):
     g = _gbox(nd, box)
     V, rho = g.density()
     assert V == box.L * box.L * box.L and rho == box.n_atoms / V
+
+
+@pytest.mark.parametrize("which", ["c1", "c2", "sio2", "mixed"])
+def test_energy_refresh_from_cells_equals_all_pairs(nd, orc, which):
+    """A sweep of zero trials after new coordinates reports the energy that
+    the sweep recomputes from cell lists in O(N); it equals the all-pairs
+    total (the same pair terms, summed in another order)."""
+    if which == "c1":
+        box, T, mc = syn.config_c1()
+    elif which == "c2":
+        box, T, mc = syn.config_c2()
+    elif which == "sio2":
+        box = syn.atomic_box((2000, 4000), 114.7 * (6000 / 99999) ** (1 / 3), 1003, ("Si", "O"), "SiO2 cut")
+        T = syn.sio2_tables()
+    else:
+        box = syn.mixed_unit_box(400, 19.0, 77, max_atoms=4, n_species=3, name="mixed units")
+        T = syn.mixed_tables(r_cut=8.0)
+    g = _gbox(nd, box, T)
+    g.set_coords(box.xyz)  # running energy stale
+    res = g.mc_sweep(nd.MCParams(2.5, 0.1, 0.0), 1, 0, 0)
+    E_all = g.total_energy()
+    if box.n_atoms <= 10000:
+        _, S = orc.total_energy(box, T)
+    else:
+        S = abs(E_all) * 10.0
+    say(f"{which}: cells {res['E_total']!r} all pairs {E_all!r}")
+    assert abs(res["E_total"] - E_all) <= 1e-12 * S

@@ -140,28 +140,41 @@ def test_emp_update_rejects_bad_input(nd):
 
 @pytest.mark.timeout(600)
 def test_refinement_loop_reduces_the_misfit(nd, orc):
-    """Empirical-potential Monte Carlo on 1,500 waters towards the oracle's
-    S(Q) of a run with a 3 kJ/mol O-O bump at 2.8 A: the summed chi^2 of the
-    three profiles after four EMP updates is below its value before the
-    first (both boxes run 30 sweeps from their random starts first)."""
+    """Empirical-potential Monte Carlo on a Lennard-Jones liquid of 2,000
+    atoms (one profile, one pair type; it equilibrates within a few sweeps,
+    so the misfit measures the potential and not the equilibration) towards
+    the oracle's S(Q) of the same liquid with a 2 kJ/mol Gaussian bump at
+    4.2 A added to its potential: the chi^2 after four EMP updates is well
+    below its value before the first."""
     import oracle
     oracle.set_threads(oracle.max_threads())
-    box, T, mc = syn.config_scale(1500, seed=4242)
+    L, n = 46.4, 2000
+    T = syn.potential_table(1, 12.0, 0.01, [(3.4, 1.0)], [0.0])
+    Tb = syn.potential_table(1, 12.0, 0.01, [(3.4, 1.0)], [0.0],
+                             emp={(0, 0): lambda r: 2.0 * np.exp(-(r - 4.2) ** 2 / (2 * 0.15 ** 2))})
+    kT = syn.kT_at(120.0)
     dr = 0.03
-    nbins = syn.n_bins_for(min(12.0, 0.49 * box.L), dr)
-    target_box = syn.water_box(1500, box.L, 4343, "target")
-    profiles = [syn.water_b(x) for x in D_FRACTIONS]
-    say("oracle target: 1500 waters, 30 sweeps with a 3 kJ/mol O-O bump")
-    W, st, S_exp, Q = _target(orc, target_box, T, mc, 30, 4343, dr, nbins, profiles, bump=3.0)
+    nbins = syn.n_bins_for(15.0, dr)
+    box = syn.atomic_box((n,), L, 4242, ("Ar",), "LJ liquid")
+    tbox = syn.atomic_box((n,), L, 4343, ("Ar",), "LJ target")
+    say("oracle target: 2000 LJ atoms, 40 sweeps with the bump")
+    x = tbox.xyz.copy()
+    oracle.mc_run(tbox, Tb, x, kT, 0.5, 0.0, 4343, 0, 40 * n)
+    moved = syn.Box("t", L, tbox.species, tbox.unit_offsets, x, 1)
+    counts, _ = oracle.pair_histogram(moved, dr, nbins)
+    g_t = oracle.gr_normalize(counts.astype(np.float64), dr, L ** 3, oracle.pair_counts_total(tbox.species, 1))
+    W = np.array([[1.0]])
+    st = np.array([1.0])
+    Q = syn.q_grid()
+    S_exp = oracle.sq(g_t, dr, n / L ** 3, W[0], 1.0, Q)[None, :]
     gb = nd.Box.from_synthetic(box)
     gb.set_tables(T.U, T.h, T.r_cut)
-    p = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"])
-    # equilibrate with the reference potential first (the loop's MC step)
-    gb.mc_sweep(p, 5, 0, 30 * box.n_units, stats=False)
-    prm = nd.EmpParams(kT=mc["kT"], sigma=0.3, n_terms=30, feedback=1.0, ridge=1e-6, emp_max=2.0)
-    hist, _ = nd.refine(gb, p, 5, W, st, S_exp, Q, dr, nbins, prm, iterations=5, sweeps=6, sample_sweeps=4,
-                        first_trial=30 * box.n_units)
+    p = nd.MCParams(kT, 0.5, 0.0)
+    gb.mc_sweep(p, 5, 0, 40 * n, stats=False)  # equilibrate with the reference potential
+    prm = nd.EmpParams(kT=kT, sigma=0.25, n_terms=40, feedback=0.6, ridge=1e-6, emp_max=3.0)
+    hist, _ = nd.refine(gb, p, 5, W, st, S_exp, Q, dr, nbins, prm, iterations=5, sweeps=12, sample_sweeps=10,
+                        first_trial=40 * n)
     tot = [sum(h) for h in hist]
     say("chi^2 per iteration:", ", ".join(f"{x:.4g}" for x in tot))
-    assert tot[-1] < tot[0]
+    assert tot[-1] < 0.5 * tot[0]
     gb.close()
