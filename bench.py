@@ -196,8 +196,8 @@ def scale_leg(nd, syn, torch, sizes, hist_upto=1_500_000):
         box, T, mc = syn.config_scale(n_mol)
         g = nd.Box.from_synthetic(box)
         g.set_tables(T.U, T.h, T.r_cut)
-        g.total_energy()
         p = nd.MCParams(mc["kT"], mc["max_disp"], mc["max_rot"])
+        # the first sweep takes the running energy from cell lists in O(N)
         g.mc_sweep(p, mc["seed"], 0, 50_000, stats=False)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -304,6 +304,15 @@ def main():
     g.set_profiling(False)
     log(f"profiled {args.steps} steps in {elapsed_prof:.3f} s")
 
+    # scan work of one more step's sweeps (not timed: counting adds atomics)
+    g.count_scan(True)
+    g.mc_sweep(params, mc["seed"], (args.warmup + 2 * args.steps) * n_trials, n_trials, stats=False)
+    cand, surv = g.count_scan(False)
+    torch.cuda.synchronize()
+    scan_n, scan_ms = prof["mc_scan"]
+    scan_avg_s = scan_ms / max(scan_n, 1) / 1e3
+    scan_launch_per_step = scan_n / args.steps
+    scan_ops_per_launch = cand * OPS_PER_TEST / scan_launch_per_step
     ms_per_step = 1000.0 * elapsed / args.steps
     moves_per_s = n_trials * args.steps / elapsed
     dist_per_s = (n_trials * n_tests_per_trial + n_pairs) * args.steps / elapsed
@@ -346,6 +355,20 @@ def main():
             "algorithmic_per_launch": f"{n_pairs} pairs x {OPS_PER_PAIR} lane-ops",
             "pairs_per_s": n_pairs / hist_avg_s,
         },
+        # The Metropolis scan launch (cell scan of a batch's trials, plus the
+        # batch's corrections, proposals and final sums): algorithmic work =
+        # candidate atoms tested against the trials' reach spheres x 16
+        # lane-ops (3 sub, 9 nearest image, 3 for r^2, 1 compare), counted
+        # in a further step; time = the launch's average from the profiled steps
+        "roofline_mc_scan": {
+            "kernel": "k_mc_scan_corr (cell scan of one batch of trials)",
+            "bound": "alu", "achieved": scan_ops_per_launch / scan_avg_s / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "Tlane-op/s", "frac": scan_ops_per_launch / scan_avg_s / PEAK_LANE_OPS,
+            "launches_per_step": scan_launch_per_step, "avg_launch_us": scan_avg_s * 1e6,
+            "candidates_per_trial": cand / n_trials, "survivors_per_trial": surv / n_trials,
+            "algorithmic_per_launch": f"{cand / scan_launch_per_step:.4g} candidate tests x {OPS_PER_TEST} lane-ops",
+        },
+        "tuning": nd.tuning_for("box", box.n_atoms),
         "kernels": {
             k: {"launches": n, "ms_total": ms, "share_of_step_time": ms / (1000.0 * elapsed_prof)}
             for k, (n, ms) in prof.items()

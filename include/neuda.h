@@ -527,6 +527,15 @@ nd_status nd_box_set_profiling(nd_box *box, int32_t enable);
  * ND_E_INVALID for bits past ND_PROF_KINDS. */
 nd_status nd_box_set_profiling_mask(nd_box *box, uint32_t kernels);
 
+/* Counts, for measurement, the work of the cell scan of later nd_mc_sweep
+ * calls on the box: the candidate atoms tested against each trial's reach
+ * sphere and the survivors whose pair terms are evaluated.  Each call first
+ * returns the counts since the last call (host, may be NULL; zero when
+ * counting was off), then restarts them (enable = 1) or stops counting
+ * (enable = 0).  Counting adds device atomics to the scan; leave it off in
+ * timed runs.  Synchronises the box's stream. */
+nd_status nd_box_count_scan(nd_box *box, int32_t enable, int64_t *candidates, int64_t *survivors);
+
 /* Synchronises the box's stream and returns the number of recorded launches
  * of `kernel` and their summed duration in milliseconds since profiling was
  * enabled.  Errors: ND_E_INVALID for an unknown kernel id. */

@@ -134,6 +134,7 @@ EXPORTS = {
     "nd_box_set_profiling_mask": (C.c_int32, [C.c_void_p, C.c_uint32]),
     "nd_box_profile": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
                                    C.POINTER(C.c_double)]),
+    "nd_box_count_scan": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "nd_eq1_weights": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "nd_chi2": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                             C.c_void_p]),
@@ -199,10 +200,19 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_1904_08756_amd.build()")
     L = C.CDLL(LIB_PATH)
+    missing = []
     for name, (res, args) in EXPORTS.items():
-        f = getattr(L, name)
+        try:
+            f = getattr(L, name)
+        except AttributeError:
+            # a library built from other sources than this binding: the
+            # entry point raises when called (tests check every export)
+            missing.append(name)
+            continue
         f.restype = res
         f.argtypes = args
+    if "nd_box_create" in missing or "nd_last_error" in missing:
+        raise ImportError(f"{LIB_PATH} does not export the neuda ABI")
     _lib = L
     if os.path.exists(TUNING_FILE) and not os.environ.get("NEUDA_NO_TUNING"):
         _check(L.nd_load_tuning(TUNING_FILE.encode()))
@@ -353,6 +363,15 @@ class Box:
             for k in kernels:
                 mask |= 1 << PROF[k]
             _check(lib().nd_box_set_profiling_mask(self.handle, mask if enable else 0))
+
+    def count_scan(self, enable: bool):
+        """(candidates, survivors) the cell scan tested since the last call;
+        then restarts counting (enable) or stops it."""
+        self._sync_stream()
+        c = C.c_int64()
+        v = C.c_int64()
+        _check(lib().nd_box_count_scan(self.handle, int(enable), C.byref(c), C.byref(v)))
+        return c.value, v.value
 
     def profile(self, kernel: str):
         """(launches, total milliseconds) recorded for a kernel since profiling was enabled."""

@@ -340,14 +340,14 @@ void cells_free(nd_box *b)
     c = Cells();
 }
 
-// Cell grid of about four atoms per cell, at least one and at most 128 cells
+// Cell grid of about four atoms per cell, at least one and at most 256 cells
 // per axis.
 static int cells_per_axis(const nd_box *b)
 {
     const double rho = (double)b->N / (b->L * b->L * b->L);
     const double edge = std::cbrt(4.0 / rho);
     const int nc = (int)std::floor(b->L / edge);
-    return std::max(1, std::min(nc, 128));
+    return std::max(1, std::min(nc, 256));
 }
 
 void cells_ensure(nd_box *b)

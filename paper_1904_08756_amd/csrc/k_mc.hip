@@ -370,7 +370,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_mc_scan(ScanArgs a)
     for (int m = 0; m < SCAN_JPT; ++m) {
         const int j = jstart + m * SCAN_THREADS + tid;
         pj[m] = (j < a.N) ? a.pos4[j] : make_float4(qnan, qnan, qnan, 0.f);
-        pl[m] = (j < a.N) ? a.poslo[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        pl[m] = (j < a.N) ? a.poslo[j] : make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
     }
     __syncthreads();
 
@@ -379,18 +379,17 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_mc_scan(ScanArgs a)
     const int k1 = min(a.kb, k0 + a.tg);
     for (int k = k0; k < k1; ++k) {
         const nd::Trial *T = a.trials + k;
-        const int ta0 = T->a0, tna = T->na;
+        const int tna = T->na, tunit = T->unit;
         double e = 0.0, s = 0.0;
-        const bool own = (ta0 < jstart + SCAN_JB) && (ta0 + tna > jstart);
-        if (!own) {
+        // every atom of the moved unit is left out (all of them when the unit
+        // moves, its other atoms when one atom of a flexible unit moves)
+        unsigned ex = 0u;
+#pragma unroll
+        for (int m = 0; m < SCAN_JPT; ++m)
+            if (__float_as_int(pl[m].w) == tunit) ex |= 1u << m;
+        if (__ballot(ex != 0u) == 0ull) {
             scan_trial<MAXNU, false>(c, T, tna, pj, pl, 0u, e, s);
         } else {
-            unsigned ex = 0u;
-#pragma unroll
-            for (int m = 0; m < SCAN_JPT; ++m) {
-                const int j = jstart + m * SCAN_THREADS + tid;
-                if ((unsigned)(j - ta0) < (unsigned)tna) ex |= 1u << m;
-            }
             scan_trial<MAXNU, true>(c, T, tna, pj, pl, ex, e, s);
         }
 #pragma unroll
@@ -692,6 +691,7 @@ struct CellScanArgs {
     float rcf, rcf2_filter;
     double rcf2, tscale;
     double *dE0, *S0;
+    unsigned long long *count;  // null, or [0] candidates tested, [1] survivors (measurement)
 };
 
 // Trial atoms staged in LDS for the scan: FP64 fractional position and the
@@ -880,6 +880,7 @@ __device__ __forceinline__ void scan_cells_group(const CellScanArgs &a, const Pa
         }
         const int total = __shfl(incl, 63);
         const int excl = incl - len;
+        if (a.count && lane == 0) atomicAdd(a.count, (unsigned long long)total);
         // two candidates per lane per trip, so two loads are in flight
         for (int c0 = 0; c0 < total; c0 += 128) {
             int sl[2];
@@ -920,6 +921,7 @@ __device__ __forceinline__ void scan_cells_group(const CellScanArgs &a, const Pa
                 const bool mine = __float_as_int(ql[h].w) == tunit;
                 const bool hit = live[h] && !mine && fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < surv2;
                 const unsigned long long bal = __ballot(hit);
+                if (a.count && lane == 0) atomicAdd(a.count + 1, (unsigned long long)__popcll(bal));
                 if (hit) {
                     const int idx = nlist + __popcll(bal & lt);
                     list[idx] = q[h];
@@ -2000,6 +2002,7 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         ca.tscale = k.tscale;
         ca.dE0 = w.dE0 + (size_t)buf * w.cap_k;
         ca.S0 = w.S0 + (size_t)buf * w.cap_k;
+        ca.count = b->scan_count;
         const int64_t done_next = done + kb;
         const int kb_next = bi + 1 < sizes.size() ? sizes[bi + 1] : 0;
         const ProposeArgs nx = proposal_args(b, p, seed, first + (uint64_t)done_next, kb_next, buf ^ 1, K);
@@ -2297,6 +2300,7 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
             L.da.defer = 0;
             L.fin.kb = 0;
             L.da.moved_tag = nullptr;
+            L.ca.count = nullptr;
             L.ca.nw = nw;
             L.ca.per_slab = per_slab_blocks(L.ca.kb, nw);
             L.nblk = scan_front_blocks(L.cr.kb, L.next.kb, 0) + N_SLAB * L.ca.per_slab;

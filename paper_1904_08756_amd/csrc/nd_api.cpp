@@ -328,6 +328,7 @@ static void free_box(nd_box *b)
     nd::dfree(b->rp);
     nd::dfree(b->emp);
     nd::dfree(b->r0);
+    nd::dfree(b->scan_count);
     nd::dfree(b->E);
     nd::dfree(b->mc.trials);
     nd::dfree(b->mc.partial);
@@ -509,6 +510,32 @@ nd_status nd_box_set_profiling_mask(nd_box *b, uint32_t kernels)
 nd_status nd_box_set_profiling(nd_box *b, int32_t enable)
 {
     return nd_box_set_profiling_mask(b, enable ? (1u << ND_PROF_KINDS) - 1u : 0u);
+}
+
+nd_status nd_box_count_scan(nd_box *b, int32_t enable, int64_t *candidates, int64_t *survivors)
+{
+    return guarded([&] {
+        check_box(b);
+        DeviceGuard g(b->device);
+        if (b->scan_count) {
+            unsigned long long c[2];
+            ND_HIP(hipMemcpyAsync(c, b->scan_count, sizeof(c), hipMemcpyDeviceToHost, b->stream));
+            ND_HIP(hipStreamSynchronize(b->stream));
+            if (candidates) *candidates = (int64_t)c[0];
+            if (survivors) *survivors = (int64_t)c[1];
+        } else {
+            if (candidates) *candidates = 0;
+            if (survivors) *survivors = 0;
+        }
+        if (enable) {
+            if (!b->scan_count) b->scan_count = static_cast<unsigned long long *>(nd::dmalloc(2 * sizeof(unsigned long long)));
+            ND_HIP(hipMemsetAsync(b->scan_count, 0, 2 * sizeof(unsigned long long), b->stream));
+        } else {
+            ND_HIP(hipStreamSynchronize(b->stream));
+            nd::dfree(b->scan_count);
+            b->scan_count = nullptr;
+        }
+    });
 }
 
 nd_status nd_box_profile(nd_box *b, int32_t kernel, int64_t *launches, double *ms)

@@ -158,6 +158,8 @@ struct nd_box {
     nd::McWork mc;
     nd::Cells cells;
     nd::Track track;
+    // measurement: candidates tested and survivors of the cell scan (null: off)
+    unsigned long long *scan_count = nullptr;
     // reusable device workspace for per-block partial results
     void *ws = nullptr;
     size_t ws_bytes = 0;
