@@ -7,11 +7,9 @@
 // Counts go to an LDS-private u32 histogram per block; each block visits
 // many tile pairs (persistent grid) and adds its nonzero counters with
 // integer atomics when it is done, and after every FLUSH_TILES tile pairs,
-// before a u32 counter could overflow: the single-box kernel into its XCD's
-// slice of partial counts (atomics resolved in that XCD's L2; a last kernel
-// adds the eight slices), the several-box kernel into each box's counts.
-// Integer sums are exact in any order, so the counts do not depend on
-// scheduling.
+// before a u32 counter could overflow, into the u64 counts (the several-box
+// kernel into each box's counts).  Integer sums are exact in any order, so
+// the counts do not depend on scheduling.
 #include "nd_internal.h"
 #include "nd_pair.h"
 
@@ -92,8 +90,6 @@ struct HistArgs {
     float nb_hi;            // nbins + 2 edge_eps: shifted candidates beyond are out of range
     float edge_eps;
     unsigned long long *out;  // [P * nbins] counts (cleared beforehand), accumulated atomically
-    unsigned long long *xcd;  // [8][xcd_stride] per-XCD partial counts (single-box kernel)
-    int xcd_stride;
     long long tile0;        // first global tile-pair index of this box (several boxes per launch)
 };
 
@@ -227,33 +223,6 @@ __device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, i
     }
 }
 
-// XCD (accelerator complex die) that runs the calling wave, 0..7, from the
-// hardware register XCC_ID.
-__device__ __forceinline__ int xcc_id()
-{
-    // s_getreg_b32 of HW_REG_XCC_ID (id 20), bits 0..3
-    return (int)(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u);
-}
-
-// Adds the block's nonzero LDS counters to its XCD's slice of u64 partial
-// counts and clears them.  Every block that adds to a slice runs on that
-// slice's XCD, so the integer atomics can stay in the XCD's own L2
-// (workgroup scope): only the eight slices reach memory, when the kernel
-// ends, instead of one 64-bit atomic per block and counter.
-__device__ __forceinline__ void hist_flush_xcd(const HistArgs &a, const HistLds &h, unsigned long long *slice)
-{
-    __syncthreads();
-    const int nq = a.P * a.nbins;
-    for (int q = threadIdx.x; q < nq; q += TILE) {
-        const unsigned v = h.hist[q];
-        if (v) {
-            __hip_atomic_fetch_add(slice + q, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            h.hist[q] = 0u;
-        }
-    }
-    __syncthreads();
-}
-
 // Adds the block's nonzero LDS counters to the u64 counts and clears them.
 __device__ __forceinline__ void hist_flush(const HistArgs &a, const HistLds &h)
 {
@@ -274,7 +243,6 @@ __global__ __launch_bounds__(TILE) void k_pair_hist(HistArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const HistLds h = hist_lds(smem);
-    unsigned long long *slice = a.xcd + (size_t)xcc_id() * a.xcd_stride;
     hist_begin(a, h);
     long long since = 0;
     for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
@@ -282,22 +250,11 @@ __global__ __launch_bounds__(TILE) void k_pair_hist(HistArgs a)
         tri_index(t, a.nt, I, J);
         hist_tile<PACKED>(a, h, I, J);
         if (++since == FLUSH_TILES) {
-            hist_flush_xcd(a, h, slice);
+            hist_flush(a, h);
             since = 0;
         }
     }
-    hist_flush_xcd(a, h, slice);
-}
-
-// counts[q] = sum of the eight XCD slices' q (in slice order).
-__global__ void k_hist_xcd_sum(const unsigned long long *__restrict__ xcd, int stride, int nq,
-                               unsigned long long *__restrict__ out)
-{
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
-    unsigned long long s = 0;
-    for (int x = 0; x < 8; ++x) s += xcd[(size_t)x * stride + q];
-    out[q] = s;
+    hist_flush(a, h);
 }
 
 // Several boxes in one persistent launch.  The tile pairs of all boxes form
@@ -549,10 +506,7 @@ void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
     long long G = (long long)cu_count(b->device) * per_cu;
     if (G > a.ntp) G = a.ntp;
     a.out = reinterpret_cast<unsigned long long *>(d_counts);
-    a.xcd_stride = (nq + 31) / 32 * 32;  // slices 256-byte aligned: no cache line shared by two XCDs
-    a.xcd = static_cast<unsigned long long *>(workspace(b, sizeof(unsigned long long) * 8 * (size_t)a.xcd_stride));
-    hipLaunchKernelGGL(k_zero_u64, dim3((8 * a.xcd_stride + 255) / 256), dim3(256), 0, b->stream, a.xcd,
-                       8 * a.xcd_stride);
+    hipLaunchKernelGGL(k_zero_u64, dim3((nq + 255) / 256), dim3(256), 0, b->stream, a.out, nq);
     ND_HIP(hipGetLastError());
     {
         ProfScope ps(b, ND_PROF_PAIR_HIST);
@@ -563,9 +517,6 @@ void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
             hipLaunchKernelGGL(k_pair_hist<false>, dim3((unsigned)G), dim3(TILE), lds, b->stream, a);
         ND_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_hist_xcd_sum, dim3((nq + 255) / 256), dim3(256), 0, b->stream, a.xcd, a.xcd_stride, nq,
-                       a.out);
-    ND_HIP(hipGetLastError());
 }
 
 // ---- several boxes in one launch (the batched form)

@@ -34,6 +34,7 @@ namespace {
 
 using nd::PairCtx;
 using nd::ld4;
+using nd::ld_lds4;
 using nd::ldg;
 using nd::ld_i4;
 using nd::ld_d2;
@@ -506,7 +507,7 @@ __device__ __forceinline__ bool spheres_meet(float4 A, float4 B, float rcf)
     return dx * dx + dy * dy + dz * dz < lim * lim;
 }
 
-constexpr int CORR_LIST = 512;  // hits listed per wave at a time
+constexpr int CORR_LIST = 256;  // hits listed per wave at a time
 
 // Per-wave LDS scratch of the correction step: the hit list, per-lane
 // partial sums, and trial k's atoms (FP64 fractional positions and species,
@@ -520,15 +521,20 @@ struct CorrScratch {
 
 // List the hits of ranks [first, first + CORR_LIST): earlier trials m < k of
 // the batch whose bounding sphere comes within r_cut of k's, in increasing m.
-// Returns the total number of hits.
-__device__ __forceinline__ int corr_collect(const CorrArgs &a, float4 A, int k, int lane, int first, int *wl)
+// Returns the total number of hits.  The spheres are read from `lds` (a copy
+// of the batch's spheres in LDS) when it is not null, else from memory.
+__device__ __forceinline__ int corr_collect(const CorrArgs &a, const float4 *lds, float4 A, int k, int lane, int first,
+                                            int *wl)
 {
     const unsigned long long lt = (1ull << lane) - 1ull;
     int n = 0;
     for (int m0 = 0; m0 < k; m0 += 256) {
         float4 B[4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) B[h] = ld4(a.spheres + min(m0 + 64 * h + lane, k - 1));
+        for (int h = 0; h < 4; ++h) {
+            const int m = min(m0 + 64 * h + lane, k - 1);
+            B[h] = lds ? ld_lds4(lds + m) : ld4(a.spheres + m);
+        }
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
             const int m = m0 + 64 * h + lane;
@@ -549,10 +555,21 @@ __device__ __forceinline__ int corr_collect(const CorrArgs &a, float4 A, int k, 
 // each summing over k's atoms old and new; the lane of each hit then adds
 // its items' partial sums in a fixed order.
 template <int MAXNU>
-__device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, int k, int lane, CorrScratch &cs)
+__device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, int k, int lane, CorrScratch &cs,
+                                           const float4 *lds = nullptr)
 {
     const float4 A = a.spheres[k];
-    const int n = k > 0 ? corr_collect(a, A, k, lane, 0, cs.wl) : 0;
+    // trial k's own atoms (old and new), loaded before the collection so
+    // that their latency overlaps it; slots past na are read but not used
+    const nd::Trial *Tk = a.trials + k;
+    float4 kh = make_float4(0.f, 0.f, 0.f, 0.f), kl = kh;
+    if (lane < 2 * MAXNU) {
+        const int at = lane >> 1;
+        kh = ld4((lane & 1) ? &Tk->new_hi[at] : &Tk->old_hi[at]);
+        kl = ld4((lane & 1) ? &Tk->new_lo[at] : &Tk->old_lo[at]);
+    }
+    const int nak = ldg(&Tk->na);
+    const int n = k > 0 ? corr_collect(a, lds, A, k, lane, 0, cs.wl) : 0;
     int base;
     if (n <= CORR_CAP) {
         base = k * CORR_CAP;
@@ -573,16 +590,11 @@ __device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, 
         }
         return;
     }
-    const nd::Trial *Tk = a.trials + k;
-    const int nak = Tk->na;
-    if (lane < 2 * MAXNU) {  // slots past na are read but not used
-        const int at = lane >> 1;
-        const float4 h = (lane & 1) ? Tk->new_hi[at] : Tk->old_hi[at];
-        const float4 l = (lane & 1) ? Tk->new_lo[at] : Tk->old_lo[at];
-        cs.x[lane] = (double)h.x + (double)l.x;
-        cs.y[lane] = (double)h.y + (double)l.y;
-        cs.z[lane] = (double)h.z + (double)l.z;
-        cs.sp[lane] = __float_as_int(h.w);
+    if (lane < 2 * MAXNU) {
+        cs.x[lane] = (double)kh.x + (double)kl.x;
+        cs.y[lane] = (double)kh.y + (double)kl.y;
+        cs.z[lane] = (double)kh.z + (double)kl.z;
+        cs.sp[lane] = __float_as_int(kh.w);
     }
     __builtin_amdgcn_wave_barrier();
     constexpr int IPH = 2 * MAXNU;   // items per hit
@@ -592,24 +604,37 @@ __device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, 
     double Sk = 0.0;
     double blo = 0.0, bhi = 0.0, bmag = 0.0, bnv = 0.0;  // bracket summary of the entries with m >= 0
     int wbase = 0;
-    for (int h0 = 0; h0 < n; h0 += HPR) {
-        if (h0 + HPR > wbase + CORR_LIST) {
+    // two rounds of hits at a time, the loads of both issued together
+    for (int h0 = 0; h0 < n; h0 += 2 * HPR) {
+        if (h0 + 2 * HPR > wbase + CORR_LIST) {
             // more hits than the list holds (rare): list the next window
             wbase = h0;
-            corr_collect(a, A, k, lane, wbase, cs.wl);
+            corr_collect(a, lds, A, k, lane, wbase, cs.wl);
         }
-        const int h = h0 + hl;
-        double pc = 0.0, ps = 0.0;
-        if (hl < HPR && h < n) {
-            const int m = cs.wl[h - wbase];
-            const nd::Trial *Tm = a.trials + m;
-            const int nam = ldg(&Tm->na);
-            const float4 q = ld4(om ? &Tm->new_hi[y] : &Tm->old_hi[y]);
-            const float4 ql = ld4(om ? &Tm->new_lo[y] : &Tm->old_lo[y]);
-            if (y < nam) {
-                const double qx = (double)q.x + (double)ql.x, qy = (double)q.y + (double)ql.y,
-                             qz = (double)q.z + (double)ql.z;
-                const int sq = __float_as_int(q.w);
+        int nam[2];
+        float4 q[2], ql[2];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const int h = h0 + rr * HPR + hl;
+            nam[rr] = 0;
+            q[rr] = make_float4(0.f, 0.f, 0.f, 0.f);
+            ql[rr] = q[rr];
+            if (hl < HPR && h < n) {
+                const nd::Trial *Tm = a.trials + cs.wl[h - wbase];
+                nam[rr] = ldg(&Tm->na);
+                q[rr] = ld4(om ? &Tm->new_hi[y] : &Tm->old_hi[y]);
+                ql[rr] = ld4(om ? &Tm->new_lo[y] : &Tm->old_lo[y]);
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const int hr0 = h0 + rr * HPR;
+            if (hr0 >= n) break;
+            double pc = 0.0, ps = 0.0;
+            if (y < nam[rr]) {
+                const double qx = (double)q[rr].x + (double)ql[rr].x, qy = (double)q[rr].y + (double)ql[rr].y,
+                             qz = (double)q[rr].z + (double)ql[rr].z;
+                const int sq = __float_as_int(q[rr].w);
                 for (int x = 0; x < nak; ++x) {
 #pragma unroll
                     for (int ok = 0; ok < 2; ++ok) {  // ok 0: k old, 1: k new
@@ -624,28 +649,28 @@ __device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, 
                     }
                 }
             }
-        }
-        cs.pc[lane] = pc;
-        cs.ps[lane] = ps;
-        __builtin_amdgcn_wave_barrier();
-        if (lane < HPR && h0 + lane < n) {
-            double C = 0.0, S = 0.0;
+            cs.pc[lane] = pc;
+            cs.ps[lane] = ps;
+            __builtin_amdgcn_wave_barrier();
+            if (lane < HPR && hr0 + lane < n) {
+                double C = 0.0, S = 0.0;
 #pragma unroll
-            for (int q = 0; q < IPH; ++q) {
-                C += cs.pc[lane * IPH + q];
-                S += cs.ps[lane * IPH + q];
+                for (int qq = 0; qq < IPH; ++qq) {
+                    C += cs.pc[lane * IPH + qq];
+                    S += cs.ps[lane * IPH + qq];
+                }
+                const int m = cs.wl[hr0 + lane - wbase];
+                const bool v = S > 0.0;
+                stg(a.pool_m + base + hr0 + lane, v ? m : -1);
+                stg(a.pool_c + base + hr0 + lane, C);
+                Sk += S;
+                blo += v ? fmin(C, 0.0) : 0.0;
+                bhi += v ? fmax(C, 0.0) : 0.0;
+                bmag += v ? fabs(C) : 0.0;
+                bnv += v ? 1.0 : 0.0;
             }
-            const int m = cs.wl[h0 + lane - wbase];
-            const bool v = S > 0.0;
-            stg(a.pool_m + base + h0 + lane, v ? m : -1);
-            stg(a.pool_c + base + h0 + lane, C);
-            Sk += S;
-            blo += v ? fmin(C, 0.0) : 0.0;
-            bhi += v ? fmax(C, 0.0) : 0.0;
-            bmag += v ? fabs(C) : 0.0;
-            bnv += v ? 1.0 : 0.0;
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_wave_barrier();
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -790,7 +815,8 @@ __device__ __forceinline__ void scan_sync()
 // in the barriers).
 template <int MAXNU, int NW>
 __device__ __forceinline__ void scan_cells_group(const CellScanArgs &a, const PairCtx &c, int k, bool active, int wsub,
-                                                 int lane, float4 *list, float4 *listlo, double *red, TrialAtoms &ta)
+                                                 int lane, float4 *list, float4 *listlo, double *red, TrialAtoms &ta,
+                                                 unsigned long long *cnt)
 {
     scan_sync<NW>();  // the previous trial is done with ta, red and the lists
     if (!active) {
@@ -880,7 +906,7 @@ __device__ __forceinline__ void scan_cells_group(const CellScanArgs &a, const Pa
         }
         const int total = __shfl(incl, 63);
         const int excl = incl - len;
-        if (a.count && lane == 0) atomicAdd(a.count, (unsigned long long)total);
+        if (a.count && lane == 0) atomicAdd(&cnt[0], (unsigned long long)total);  // measurement only
         // two candidates per lane per trip, so two loads are in flight
         for (int c0 = 0; c0 < total; c0 += 128) {
             int sl[2];
@@ -921,7 +947,7 @@ __device__ __forceinline__ void scan_cells_group(const CellScanArgs &a, const Pa
                 const bool mine = __float_as_int(ql[h].w) == tunit;
                 const bool hit = live[h] && !mine && fmaf(dz, dz, fmaf(dy, dy, dx * dx)) < surv2;
                 const unsigned long long bal = __ballot(hit);
-                if (a.count && lane == 0) atomicAdd(a.count + 1, (unsigned long long)__popcll(bal));
+                if (a.count && lane == 0) atomicAdd(&cnt[1], (unsigned long long)__popcll(bal));
                 if (hit) {
                     const int idx = nlist + __popcll(bal & lt);
                     list[idx] = q[h];
@@ -995,6 +1021,7 @@ __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const Corr
     __shared__ float4 s_list[4][2][CS_LIST];  // per wave: survivors hi, then lo
     __shared__ TrialAtoms s_ta[TPB];
     __shared__ double s_red[TPB][2 * NW];
+    __shared__ unsigned long long s_cnt[2];  // candidates, survivors (measurement)
     const int tid = threadIdx.x;
     const int n_fin = fin.kb > 0 ? 1 : 0;
     const int n_prop = (next.kb + 255) / 256;
@@ -1027,6 +1054,7 @@ __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const Corr
     const int P = a.M * (a.M + 1) / 2;
     nd::stage_floats<256>(s_tab, a.tab, P * a.n_pts);
     if (tid < a.M * a.M) s_prow[tid] = nd::pair_index(tid / a.M, tid % a.M, a.M) * a.n_pts;
+    if (tid < 2) s_cnt[tid] = 0ull;
     __syncthreads();  // tables staged
     const PairCtx c{s_tab, s_prow, a.M, a.n_pts, a.rcf2_filter, a.rcf2, a.tscale};
     const int32_t *lst = a.slab + N_SLAB + slab * a.kcap;
@@ -1038,7 +1066,11 @@ __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const Corr
         const int i = i0 + grp + it * stride;
         const bool active = i < cnt;
         scan_cells_group<MAXNU, NW>(a, c, active ? lst[i] : 0, active, wsub, tid & 63, s_list[wave][0],
-                                     s_list[wave][1], s_red[grp], s_ta[grp]);
+                                     s_list[wave][1], s_red[grp], s_ta[grp], s_cnt);
+    }
+    if (a.count) {
+        __syncthreads();
+        if (tid < 2) atomicAdd(a.count + tid, s_cnt[tid]);
     }
 }
 
@@ -1089,6 +1121,9 @@ struct DecideArgs {
     // tag_base + k (null when no histogram is tracked)
     long long *moved_tag;
     long long tag_base;
+    // blocks 1 .. n_cm of the decision launch commit the trials accepted in
+    // the first pass, and block 0 the rest (0: block 0 commits all)
+    int n_cm;
 };
 
 // exclusive prefix sum over the block of one value per thread
@@ -1119,6 +1154,21 @@ __device__ __forceinline__ int block_exscan(int v, int *s_wave)
 __device__ __forceinline__ bool metropolis(double e, double thr) { return e <= 0.0 || e < thr; }
 
 constexpr unsigned char ST_OPEN = 0, ST_REJ = 1, ST_ACC = 2;
+constexpr int ST_NONE = 3;  // an entry with no pair term (m < 0)
+
+// The first pass's state of a trial from per-trial values only: ΔE⁰, the
+// threshold and the bracket summary of its entries (lo, hi), (mag, count).
+// Without entries the test is exact; otherwise the trial is decided when
+// the test gives the same answer at both ends of the bracket, with a margin
+// far above the rounding of the sums.  The commit blocks evaluate the same
+// function on the same values, so they agree with the decision bit for bit.
+__device__ __forceinline__ unsigned char first_pass_state(double e0, double thr, double2 blh, double2 bmc)
+{
+    if (!(bmc.y > 0.0)) return metropolis(e0, thr) ? ST_ACC : ST_REJ;
+    const double eps = 1e-12 * (fabs(e0) + bmc.x);
+    const bool alo = metropolis(e0 + blh.x - eps, thr), ahi = metropolis(e0 + blh.y + eps, thr);
+    return alo == ahi ? (alo ? ST_ACC : ST_REJ) : ST_OPEN;
+}
 
 // Correction entries of trial k: fixed slots [k CORR_CAP, k CORR_CAP + n)
 // when n <= CORR_CAP (read with wide loads, all at once), else n entries at
@@ -1157,6 +1207,215 @@ __device__ __forceinline__ void for_entries(const int32_t *pool_m, const double 
     }
 }
 
+// As for_entries, with f(st, c) taking the state of the earlier trial m
+// (ST_NONE when m < 0) instead of m.  For n <= CORR_CAP every state is read
+// from LDS before any is used (indexes clamped, no branches), so the reads
+// are in flight together rather than one after another.
+template <class F>
+__device__ __forceinline__ void for_entries_st(const int32_t *pool_m, const double *pool_c, const unsigned char *st,
+                                               int k, int n, int ptr, F &&f)
+{
+    if (n <= CORR_CAP) {
+        int m[CORR_CAP];
+        double c[CORR_CAP];
+        const int4 *pm = reinterpret_cast<const int4 *>(pool_m + (size_t)k * CORR_CAP);
+        const double2 *pc = reinterpret_cast<const double2 *>(pool_c + (size_t)k * CORR_CAP);
+#pragma unroll
+        for (int i = 0; i < CORR_CAP / 4; ++i) {
+            int4 v = make_int4(-1, -1, -1, -1);
+            if (4 * i < n) v = ld_i4(pm + i);
+            m[4 * i] = 4 * i < n ? v.x : -1;
+            m[4 * i + 1] = 4 * i + 1 < n ? v.y : -1;
+            m[4 * i + 2] = 4 * i + 2 < n ? v.z : -1;
+            m[4 * i + 3] = 4 * i + 3 < n ? v.w : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < CORR_CAP / 2; ++i) {
+            if (2 * i < n) {
+                const double2 v = ld_d2(pc + i);
+                c[2 * i] = v.x;
+                c[2 * i + 1] = v.y;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < CORR_CAP; ++i) {
+            const int s = st[m[i] >= 0 ? m[i] : 0];
+            m[i] = m[i] >= 0 ? s : ST_NONE;
+        }
+#pragma unroll
+        for (int i = 0; i < CORR_CAP; ++i)
+            if (i < n) f(m[i], c[i]);
+    } else {
+        for (int i = 0; i < n; ++i) {
+            const int mi = ldg(pool_m + ptr + i);
+            f(mi >= 0 ? (int)st[mi] : ST_NONE, ldg(pool_c + ptr + i));
+        }
+    }
+}
+
+// The open trials s_open[0 .. n_open) of a batch, resolved by one wave:
+// lane l takes trial s_open[l], copies its entries once into LDS (entry i of
+// lane l at [i][l]) and evaluates the trial against the states of its
+// earlier trials until it is decided.  Each pass decides at least the
+// earliest open trial (its earlier trials are all decided, so its dE is
+// exact), so at most n_open passes run; states written in a pass are
+// visible to the wave in the next.  `pool` holds 64 CORR_CAP (int, double).
+constexpr int RESOLVE_POOL_BYTES = 64 * CORR_CAP * (int)(sizeof(int) + sizeof(double));
+
+__device__ __forceinline__ void resolve_in_wave(const DecideArgs &a, const double *s_e, const double *s_u,
+                                                const int *s_n, const int *s_ptr, unsigned char *s_st,
+                                                const unsigned short *s_open, int n_open, int lane,
+                                                unsigned char *pool)
+{
+    double *ec = reinterpret_cast<double *>(pool);        // [CORR_CAP][64]
+    int *em = reinterpret_cast<int *>(ec + CORR_CAP * 64);  // [CORR_CAP][64]
+    const bool has = lane < n_open;
+    const int k = has ? s_open[lane] : 0;
+    const int nk = has ? s_n[k] : 0, pk = s_ptr[k];
+    const double e0 = s_e[k], thr = s_u[k];
+    if (nk <= CORR_CAP) {
+        const int4 *pm = reinterpret_cast<const int4 *>(a.pool_m + (size_t)k * CORR_CAP);
+        const double2 *pc = reinterpret_cast<const double2 *>(a.pool_c + (size_t)k * CORR_CAP);
+#pragma unroll
+        for (int i = 0; i < CORR_CAP / 4; ++i) {
+            int4 v = make_int4(-1, -1, -1, -1);
+            if (4 * i < nk) v = ld_i4(pm + i);
+            em[(4 * i) * 64 + lane] = 4 * i < nk ? v.x : -1;
+            em[(4 * i + 1) * 64 + lane] = 4 * i + 1 < nk ? v.y : -1;
+            em[(4 * i + 2) * 64 + lane] = 4 * i + 2 < nk ? v.z : -1;
+            em[(4 * i + 3) * 64 + lane] = 4 * i + 3 < nk ? v.w : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < CORR_CAP / 2; ++i) {
+            double2 v = make_double2(0.0, 0.0);
+            if (2 * i < nk) v = ld_d2(pc + i);
+            ec[(2 * i) * 64 + lane] = v.x;
+            ec[(2 * i + 1) * 64 + lane] = v.y;
+        }
+    }
+    bool open = has;
+    for (int pass = 0; pass < 64; ++pass) {
+        if (__ballot(open) == 0ull) break;
+        unsigned char d = ST_OPEN;
+        if (open) {
+            double e = e0, lo = 0.0, hi = 0.0, mag = fabs(e0);
+            bool all = true;
+            auto visit = [&](int st, double cv) {
+                const bool op = st == ST_OPEN;
+                e += st == ST_ACC ? cv : 0.0;
+                all &= !op;
+                lo += op ? fmin(cv, 0.0) : 0.0;
+                hi += op ? fmax(cv, 0.0) : 0.0;
+                mag += st != ST_NONE ? fabs(cv) : 0.0;
+            };
+            if (nk <= CORR_CAP) {
+                // eight entries at a time: their indexes, then their states,
+                // each group of reads in flight together
+#pragma unroll
+                for (int i0 = 0; i0 < CORR_CAP; i0 += 8) {
+                    int mm[8], st[8];
+                    double cc[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        mm[i] = em[(i0 + i) * 64 + lane];
+                        cc[i] = ec[(i0 + i) * 64 + lane];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) st[i] = s_st[mm[i] >= 0 ? mm[i] : 0];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (i0 + i < nk) visit(mm[i] >= 0 ? st[i] : ST_NONE, cc[i]);
+                }
+            } else {
+                for (int i = 0; i < nk; ++i) {
+                    const int mi = ldg(a.pool_m + pk + i);
+                    visit(mi >= 0 ? (int)s_st[mi] : ST_NONE, ldg(a.pool_c + pk + i));
+                }
+            }
+            if (all) {
+                d = metropolis(e, thr) ? ST_ACC : ST_REJ;
+            } else {
+                const double eps = 1e-12 * mag;
+                const bool alo = metropolis(e + lo - eps, thr), ahi = metropolis(e + hi + eps, thr);
+                if (alo == ahi) d = alo ? ST_ACC : ST_REJ;
+            }
+        }
+        // every lane has read this pass's states before any is written
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (open && d != ST_OPEN) {
+            s_st[k] = d;
+            open = false;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Commit the trials list[0 .. n) (only those in state ST_ACC when `filter`):
+// their new positions go to xyz, pos4/poslo and the sorted cell copies, and
+// dmax takes their displacement from the cell reference.  One item per
+// (trial, atom), consecutive items on consecutive threads t of nt (a trial's
+// atoms share cache lines), the loads of four items issued together; each
+// trial writes only its own atoms, so the order is free.
+__device__ __forceinline__ void commit_trials(const DecideArgs &a, const unsigned short *list, int n, bool filter,
+                                              const unsigned char *s_st, const int *s_a0, const unsigned char *s_na,
+                                              int t, int nt, float &dmax)
+{
+    const int max_na = a.max_na;
+    const int n_items = n * max_na;
+    constexpr int CU = 4;
+    for (int base = t; base < n_items; base += CU * nt) {
+        int idx[CU], slot[CU];
+        float4 hi[CU], lo[CU], ref[CU];
+        float nx[CU][3];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int it = base + u * nt;
+            idx[u] = -1;
+            if (it < n_items) {
+                const int li = it / max_na, at = it - li * max_na;
+                const int k = list[li];
+                if (at < s_na[k] && (!filter || s_st[k] == ST_ACC)) {
+                    const nd::Trial &T = a.trials[k];
+                    idx[u] = s_a0[k] + at;
+                    if (a.moved_tag && at == 0) a.moved_tag[T.unit] = a.tag_base + k;
+                    hi[u] = ld4(&T.new_hi[at]);
+                    lo[u] = ld4(&T.new_lo[at]);
+                    nx[u][0] = ldg(&T.new_x[at][0]);
+                    nx[u][1] = ldg(&T.new_x[at][1]);
+                    nx[u][2] = ldg(&T.new_x[at][2]);
+                    if (a.cell_slot) {
+                        slot[u] = ldg(a.cell_slot + idx[u]);
+                        ref[u] = ld4(a.sref + idx[u]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int i = idx[u];
+            if (i < 0) continue;
+            a.xyz[i] = nx[u][0];
+            a.xyz[a.N + i] = nx[u][1];
+            a.xyz[2 * a.N + i] = nx[u][2];
+            a.pos4[i] = hi[u];
+            a.poslo[i] = lo[u];
+            if (a.cell_slot) {
+                const int sl = slot[u];
+                a.spos4[sl] = hi[u];
+                a.sposlo[sl] = lo[u];
+                const float4 r = ref[u];
+                float dx = hi[u].x - r.x, dy = hi[u].y - r.y, dz = hi[u].z - r.z;
+                dx -= rintf(dx);
+                dy -= rintf(dy);
+                dz -= rintf(dz);
+                dmax = fmaxf(dmax, sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1e-6f);
+            }
+        }
+    }
+}
+
 // Decide batch b -- acc_k = metropolis(dE0_k + sum_{m<k} acc_m C_km), which
 // is the sequential chain -- and commit it.
 //
@@ -1171,7 +1430,7 @@ __device__ __forceinline__ void for_entries(const int32_t *pool_m, const double 
 // they are made, so the result is deterministic and equals the in-order
 // chain.  When `next.kb` > 0 the next batch is proposed afterwards (used
 // when its units may overlap this batch's).
-__device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeArgs &next)
+__device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeArgs &next, unsigned char *pool)
 {
     __shared__ double s_e[KMAX];      // dE0, then the final dE
     __shared__ double s_u[KMAX];      // acceptance threshold -kT ln u
@@ -1187,10 +1446,16 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
     __shared__ double s_red_d[DEC_THREADS / 64];
     __shared__ long long s_red_a[DEC_THREADS / 64], s_red_t[DEC_THREADS / 64];
     __shared__ float s_red_f[DEC_THREADS / 64];
+    __shared__ unsigned short s_alist[KMAX];  // trials accepted in the first pass, then the first open list
+    __shared__ int s_nopen, s_nacc0;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kb = a.kb;
 
     if (kb > 0) {
+        if (tid == 0) {
+            s_nopen = 0;
+            s_nacc0 = 0;
+        }
         // trial data and the first pass (needs no other decision): a thread
         // holds trials tid and tid + DEC_THREADS and issues all their loads
         // before using any; the bracket of the open terms is the summary the
@@ -1214,21 +1479,15 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                 bmc[h] = ld_d2(a.corr_b + 2 * k + 1);
             }
         }
+        __syncthreads();  // s_nopen cleared (the loads above are in flight meanwhile)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int k = tid + h * DEC_THREADS;
+            unsigned char d = ST_REJ;
             if (k < kb) {
                 const double thr = thr_k[h];
                 const bool any = bmc[h].y > 0.0;
-                unsigned char d;
-                if (!any) {
-                    d = metropolis(e0[h], thr) ? ST_ACC : ST_REJ;
-                } else {
-                    const double eps = 1e-12 * (fabs(e0[h]) + bmc[h].x);
-                    const bool alo = metropolis(e0[h] + blh[h].x - eps, thr),
-                               ahi = metropolis(e0[h] + blh[h].y + eps, thr);
-                    d = alo == ahi ? (alo ? ST_ACC : ST_REJ) : ST_OPEN;
-                }
+                d = first_pass_state(e0[h], thr, blh[h], bmc[h]);
                 s_e[k] = e0[h];
                 s_u[k] = thr;
                 if (a.defer) {
@@ -1243,12 +1502,46 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                 s_st[k] = d;
                 my_open += d == ST_OPEN;
             }
+            // the open and the accepted trials listed, in any order (one
+            // LDS atomic per wave for each list)
+            const unsigned long long mo = __ballot(d == ST_OPEN), ma = __ballot(d == ST_ACC);
+            const unsigned long long lt = (1ull << lane) - 1ull;
+            int bo = 0, ba = 0;
+            if (lane == 0) {
+                if (mo) bo = atomicAdd(&s_nopen, __popcll(mo));
+                if (ma) ba = atomicAdd(&s_nacc0, __popcll(ma));
+            }
+            bo = __shfl(bo, 0);
+            ba = __shfl(ba, 0);
+            if (d == ST_OPEN) s_open[bo + __popcll(mo & lt)] = (unsigned short)k;
+            if (d == ST_ACC) s_alist[ba + __popcll(ma & lt)] = (unsigned short)k;
         }
         if (tid == 0) *a.ovf_fill = 0;  // overflow area is free for the next batch
         if (tid < N_SLAB) a.slab_cnt[tid] = 0;  // the scan of this batch is done with its lists
+        __syncthreads();
+        const int n_open0 = s_nopen, n_acc0 = s_nacc0;
 
-        // later passes over the open trials only
-        for (;;) {
+        // Later passes over the open trials, and the commits.  Trials
+        // accepted in the first pass are committed at once: nothing in this
+        // launch reads the positions they write (the decisions use dE0 and
+        // the entries; the next batch's corrections read trial records).
+        // Few open trials (the usual case): one wave resolves them, a lane
+        // per trial, its passes synchronised within the wave only, while the
+        // other waves commit.  Many: the commits, then passes in which every
+        // thread takes part, separated by barriers.
+        float dmax = 0.0f;
+        if (n_open0 <= 64) {
+            if (wave == 0) {
+                if (n_open0 > 0) resolve_in_wave(a, s_e, s_u, s_n, s_ptr, s_st, s_open, n_open0, lane, pool);
+            } else if (a.n_cm == 0) {
+                commit_trials(a, s_alist, n_acc0, false, s_st, s_a0, s_na, tid - 64, DEC_THREADS - 64, dmax);
+            }
+            __syncthreads();
+        } else {
+            if (a.n_cm == 0) commit_trials(a, s_alist, n_acc0, false, s_st, s_a0, s_na, tid, DEC_THREADS, dmax);
+            for (int i = tid; i < n_open0; i += DEC_THREADS) s_alist[n_acc0 + i] = s_open[i];
+        }
+        for (; n_open0 > 64;) {
             // list the open trials (in trial order)
             const int off = block_exscan(my_open, s_wave);  // ends with a barrier
             const int n_open = s_wave[DEC_THREADS / 64];
@@ -1263,14 +1556,13 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
                 const int k = s_open[i];
                 double e = s_e[k], lo = 0.0, hi = 0.0, mag = fabs(e);
                 bool all = true;
-                for_entries(a.pool_m, a.pool_c, k, s_n[k], s_ptr[k], [&](int m, double c) {
-                    const unsigned char st = m >= 0 ? s_st[m] : ST_REJ;
-                    const bool open = m >= 0 && st == ST_OPEN;
-                    e += (m >= 0 && st == ST_ACC) ? c : 0.0;
+                for_entries_st(a.pool_m, a.pool_c, s_st, k, s_n[k], s_ptr[k], [&](int st, double c) {
+                    const bool open = st == ST_OPEN;
+                    e += st == ST_ACC ? c : 0.0;
                     all &= !open;
                     lo += open ? fmin(c, 0.0) : 0.0;
                     hi += open ? fmax(c, 0.0) : 0.0;
-                    mag += m >= 0 ? fabs(c) : 0.0;
+                    mag += st != ST_NONE ? fabs(c) : 0.0;
                 });
                 const double thr = s_u[k];
                 unsigned char d = ST_OPEN;
@@ -1293,6 +1585,12 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
             for (int k = tid; k < kb; k += DEC_THREADS) my_open += s_st[k] == ST_OPEN;
         }
 
+        // the first pass's open trials that were accepted
+        if (n_open0 <= 64)
+            commit_trials(a, s_open, n_open0, true, s_st, s_a0, s_na, tid, DEC_THREADS, dmax);
+        else
+            commit_trials(a, s_alist + n_acc0, n_open0, true, s_st, s_a0, s_na, tid, DEC_THREADS, dmax);
+
         // final dE (the same in-order sum as an exact decision), counters, trace
         double dsum = 0.0;
         long long nacc = 0, ntie = 0;
@@ -1300,9 +1598,8 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
             for (int k = tid; k < kb; k += DEC_THREADS) a.acc_out[k] = s_st[k] == ST_ACC ? 1 : 0;
         for (int k = tid; k < kb && !a.defer; k += DEC_THREADS) {
             double e = s_e[k];
-            for_entries(a.pool_m, a.pool_c, k, s_n[k], s_ptr[k], [&](int m, double c) {
-                e += (m >= 0 && s_st[m] == ST_ACC) ? c : 0.0;
-            });
+            for_entries_st(a.pool_m, a.pool_c, s_st, k, s_n[k], s_ptr[k],
+                           [&](int st, double c) { e += st == ST_ACC ? c : 0.0; });
             const bool acc = s_st[k] == ST_ACC;
             const double S = s_S[k];
             const double thr = s_u[k];
@@ -1317,111 +1614,104 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
             if (a.tr_acc) a.tr_acc[k] = acc ? 1 : 0;
             if (a.tr_unit) a.tr_unit[k] = a.trials[k].unit;
         }
-        // the accepted trials, listed in the open-trial list (free after the
-        // passes) in any order: each writes only its own atoms
-        __shared__ int s_nl;
-        if (tid == 0) s_nl = 0;
-        __syncthreads();
-        for (int k0 = 0; k0 < kb; k0 += DEC_THREADS) {
-            const int k = k0 + tid;
-            const bool acc = k < kb && s_st[k] == ST_ACC;
-            const unsigned long long m = __ballot(acc);
-            int base = 0;
-            if (lane == 0 && m) base = atomicAdd(&s_nl, __popcll(m));
-            base = __shfl(base, 0);
-            if (acc) s_open[base + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)k;
-        }
-        __syncthreads();
-        // commit: one item per (accepted trial, atom), consecutive items on
-        // consecutive lanes (a trial's atoms share cache lines), the loads of
-        // four items issued together
-        float dmax = 0.0f;
-        const int max_na = a.max_na;
-        const int n_items = s_nl * max_na;
-        constexpr int CU = 4;
-        for (int base = tid; base < n_items; base += CU * DEC_THREADS) {
-            int idx[CU], slot[CU];
-            float4 hi[CU], lo[CU], ref[CU];
-            float nx[CU][3];
-#pragma unroll
-            for (int u = 0; u < CU; ++u) {
-                const int it = base + u * DEC_THREADS;
-                idx[u] = -1;
-                if (it < n_items) {
-                    const int li = it / max_na, at = it - li * max_na;
-                    const int k = s_open[li];
-                    if (at < s_na[k]) {
-                        const nd::Trial &T = a.trials[k];
-                        idx[u] = s_a0[k] + at;
-                        if (a.moved_tag && at == 0) a.moved_tag[T.unit] = a.tag_base + k;
-                        hi[u] = ld4(&T.new_hi[at]);
-                        lo[u] = ld4(&T.new_lo[at]);
-                        nx[u][0] = ldg(&T.new_x[at][0]);
-                        nx[u][1] = ldg(&T.new_x[at][1]);
-                        nx[u][2] = ldg(&T.new_x[at][2]);
-                        if (a.cell_slot) {
-                            slot[u] = ldg(a.cell_slot + idx[u]);
-                            ref[u] = ld4(a.sref + idx[u]);
-                        }
-                    }
+        if (a.defer) {
+            // the sums wait for a later launch; the drift is a maximum, so
+            // each wave adds its own with one atomic and no block reduction
+            for (int o2 = 32; o2 > 0; o2 >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o2));
+            if (lane == 0 && a.drift && dmax > 0.0f)
+                atomicMax(reinterpret_cast<unsigned int *>(a.drift), __float_as_uint(dmax));
+        } else {
+            for (int o2 = 32; o2 > 0; o2 >>= 1) {
+                dsum += __shfl_xor(dsum, o2);
+                nacc += __shfl_xor(nacc, o2);
+                ntie += __shfl_xor(ntie, o2);
+                dmax = fmaxf(dmax, __shfl_xor(dmax, o2));
+            }
+            if (lane == 0) {
+                s_red_d[wave] = dsum;
+                s_red_a[wave] = nacc;
+                s_red_t[wave] = ntie;
+                s_red_f[wave] = dmax;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double d = 0.0;
+                long long na = 0, nt = 0;
+                float dm = 0.0f;
+                for (int w = 0; w < DEC_THREADS / 64; ++w) {
+                    d += s_red_d[w];
+                    na += s_red_a[w];
+                    nt += s_red_t[w];
+                    dm = fmaxf(dm, s_red_f[w]);
                 }
-            }
-#pragma unroll
-            for (int u = 0; u < CU; ++u) {
-                const int i = idx[u];
-                if (i < 0) continue;
-                a.xyz[i] = nx[u][0];
-                a.xyz[a.N + i] = nx[u][1];
-                a.xyz[2 * a.N + i] = nx[u][2];
-                a.pos4[i] = hi[u];
-                a.poslo[i] = lo[u];
-                if (a.cell_slot) {
-                    const int sl = slot[u];
-                    a.spos4[sl] = hi[u];
-                    a.sposlo[sl] = lo[u];
-                    const float4 r = ref[u];
-                    float dx = hi[u].x - r.x, dy = hi[u].y - r.y, dz = hi[u].z - r.z;
-                    dx -= rintf(dx);
-                    dy -= rintf(dy);
-                    dz -= rintf(dz);
-                    dmax = fmaxf(dmax, sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1e-6f);
-                }
-            }
-        }
-        for (int o2 = 32; o2 > 0; o2 >>= 1) {
-            dsum += __shfl_xor(dsum, o2);
-            nacc += __shfl_xor(nacc, o2);
-            ntie += __shfl_xor(ntie, o2);
-            dmax = fmaxf(dmax, __shfl_xor(dmax, o2));
-        }
-        if (lane == 0) {
-            s_red_d[wave] = dsum;
-            s_red_a[wave] = nacc;
-            s_red_t[wave] = ntie;
-            s_red_f[wave] = dmax;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double d = 0.0;
-            long long na = 0, nt = 0;
-            float dm = 0.0f;
-            for (int w = 0; w < DEC_THREADS / 64; ++w) {
-                d += s_red_d[w];
-                na += s_red_a[w];
-                nt += s_red_t[w];
-                dm = fmaxf(dm, s_red_f[w]);
-            }
-            if (!a.defer) {
                 *a.E += d;
                 *a.dsum += d;
                 a.counters[0] += na;
                 a.counters[1] += nt;
+                if (a.drift && dm > 0.0f) atomicMax(reinterpret_cast<unsigned int *>(a.drift), __float_as_uint(dm));
             }
-            if (a.drift && dm > 0.0f) atomicMax(reinterpret_cast<unsigned int *>(a.drift), __float_as_uint(dm));
         }
-        __syncthreads();  // commits are visible to the proposals below
+        if (next.kb > 0) __syncthreads();  // commits are visible to the proposals below
     }
     for (int k = tid; k < next.kb; k += DEC_THREADS) propose_one(next, k);
+}
+
+// Commit blocks of a decision launch (blocks 1 .. n_cm): block cb takes the
+// items (trial, atom) [cb CM_ITEMS, (cb + 1) CM_ITEMS) of the batch, one per
+// thread, evaluates the first-pass state of the item's trial from the same
+// values as the decision, and commits the atom when the trial is accepted
+// there.  Nothing else in the launch reads the positions they write (the
+// decision reads ΔE⁰ and entries, the correction blocks trial records);
+// spread over many CUs, the scattered loads and stores of the commit take a
+// fraction of the time they take on the deciding block's one CU.
+constexpr int CM_ITEMS = 256;
+
+__device__ __forceinline__ void commit_block(const DecideArgs &a, int cb)
+{
+    const int t = threadIdx.x;
+    if (t >= CM_ITEMS) return;
+    const int lane = t & 63;
+    const int max_na = a.max_na;
+    const int item = cb * CM_ITEMS + t;
+    const int k = item / max_na, at = item - k * max_na;
+    bool ok = false;
+    int idx = 0;
+    if (k < a.kb) {
+        const int4 id = ld_i4(a.head + k);  // unit, first atom, atoms
+        const double2 blh = ld_d2(a.corr_b + 2 * k), bmc = ld_d2(a.corr_b + 2 * k + 1);
+        const double e0 = ldg(a.dE0 + k), thr = ldg(a.hthr + k);
+        ok = at < id.z && first_pass_state(e0, thr, blh, bmc) == ST_ACC;
+        idx = id.y + at;
+    }
+    float dmax = 0.0f;
+    if (ok) {
+        const nd::Trial &T = a.trials[k];
+        if (a.moved_tag && at == 0) a.moved_tag[T.unit] = a.tag_base + k;
+        const float4 hi = ld4(&T.new_hi[at]), lo = ld4(&T.new_lo[at]);
+        const float x = ldg(&T.new_x[at][0]), y = ldg(&T.new_x[at][1]), z = ldg(&T.new_x[at][2]);
+        int sl = 0;
+        float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (a.cell_slot) {
+            sl = ldg(a.cell_slot + idx);
+            r = ld4(a.sref + idx);
+        }
+        a.xyz[idx] = x;
+        a.xyz[a.N + idx] = y;
+        a.xyz[2 * a.N + idx] = z;
+        a.pos4[idx] = hi;
+        a.poslo[idx] = lo;
+        if (a.cell_slot) {
+            a.spos4[sl] = hi;
+            a.sposlo[sl] = lo;
+            float dx = hi.x - r.x, dy = hi.y - r.y, dz = hi.z - r.z;
+            dx -= rintf(dx);
+            dy -= rintf(dy);
+            dz -= rintf(dz);
+            dmax = sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1e-6f;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o));
+    if (lane == 0 && a.drift && dmax > 0.0f) atomicMax(reinterpret_cast<unsigned int *>(a.drift), __float_as_uint(dmax));
 }
 
 // Blocks 1.. of a decision launch: the corrections of the next batch, one
@@ -1430,17 +1720,26 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
 // run on the CUs the one-block decision leaves idle.
 constexpr int DEC_CORR_TRIALS = DEC_THREADS / 64;
 
+// LDS shared by the roles of a decision launch: the correction blocks'
+// scratch, and block 0's entries of the trials it resolves in one wave.
+constexpr int DEC_POOL_BYTES = (int)sizeof(CorrScratch) * DEC_CORR_TRIALS + (int)sizeof(float4) * KMAX;
+static_assert(RESOLVE_POOL_BYTES <= DEC_POOL_BYTES, "resolve area must fit the shared pool");
+
 template <int MAXNU>
-__device__ __forceinline__ void next_corr_block(const CorrArgs &cn, int bx)
+__device__ __forceinline__ void next_corr_block(const CorrArgs &cn, int bx, CorrScratch *s_cs)
 {
     __shared__ int s_prow[16];
-    __shared__ CorrScratch s_cs[DEC_CORR_TRIALS];
     const int tid = threadIdx.x;
+    // the batch's spheres up to the block's last trial, staged in LDS
+    // (after the scratch): every wave tests its trial against all earlier ones
+    float4 *s_sph = reinterpret_cast<float4 *>(s_cs + DEC_CORR_TRIALS);
+    const int k_end = min(cn.kb, bx * DEC_CORR_TRIALS);
+    for (int m = tid; m < k_end; m += DEC_THREADS) s_sph[m] = ld4(cn.spheres + m);
     if (tid < cn.M * cn.M) s_prow[tid] = nd::pair_index(tid / cn.M, tid % cn.M, cn.M) * cn.n_pts;
     __syncthreads();
     const PairCtx c{cn.tab, s_prow, cn.M, cn.n_pts, cn.rcf2_filter, cn.rcf2, cn.tscale};
     const int k = (bx - 1) * DEC_CORR_TRIALS + (tid >> 6);
-    if (k < cn.kb) corr_trial<MAXNU>(cn, c, k, tid & 63, s_cs[tid >> 6]);
+    if (k < cn.kb) corr_trial<MAXNU>(cn, c, k, tid & 63, s_cs[tid >> 6], s_sph);
 }
 
 // The final dE of every trial of a decided batch (the same in-order sum as
@@ -1512,10 +1811,13 @@ __global__ __launch_bounds__(FIN_THREADS) void k_mc_final(FinalArgs f)
 template <int MAXNU>
 __global__ __launch_bounds__(DEC_THREADS) void k_mc_decide(DecideArgs a, ProposeArgs next, CorrArgs cn)
 {
+    __shared__ __align__(16) unsigned char s_pool[DEC_POOL_BYTES];
     if (blockIdx.x == 0)
-        decide_body(a, next);
+        decide_body(a, next, s_pool);
+    else if ((int)blockIdx.x <= a.n_cm)
+        commit_block(a, blockIdx.x - 1);
     else
-        next_corr_block<MAXNU>(cn, blockIdx.x);
+        next_corr_block<MAXNU>(cn, blockIdx.x - a.n_cm, reinterpret_cast<CorrScratch *>(s_pool));
 }
 
 __global__ void k_mc_reset(long long *counters, double *dsum, int32_t *ovf_fill, int32_t *slab0, int32_t *slab1)
@@ -1565,10 +1867,11 @@ template <int MAXNU>
 __global__ __launch_bounds__(DEC_THREADS) void k_mc_decide_multi(const McLaunch *__restrict__ L)
 {
     const McLaunch &e = L[blockIdx.x];
+    __shared__ __align__(16) unsigned char s_pool[DEC_POOL_BYTES];
     if (blockIdx.y == 0)
-        decide_body(e.da, e.late);
+        decide_body(e.da, e.late, s_pool);
     else if ((int)blockIdx.y < e.dblk)
-        next_corr_block<MAXNU>(e.cn, blockIdx.y);
+        next_corr_block<MAXNU>(e.cn, blockIdx.y, reinterpret_cast<CorrScratch *>(s_pool));
 }
 
 __global__ __launch_bounds__(64) void k_mc_propose_multi(const ProposeArgs *__restrict__ P)
@@ -1869,6 +2172,7 @@ DecideArgs decide_args(const nd_box *b, const nd_mc_params *p, const McConsts &k
     da.thr_out = nullptr;
     da.moved_tag = nullptr;
     da.tag_base = 0;
+    da.n_cm = 0;
     if (b->track.on) {
         da.acc_out = w.acc_flags + (size_t)buf * w.cap_k;
         da.moved_tag = b->track.moved;
@@ -2016,7 +2320,11 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         L.cn = corr_args(b, k, w.trials + (size_t)(buf ^ 1) * K, w.spheres + (size_t)(buf ^ 1) * K, kb_next, K,
                          buf ^ 1);
         if (!early_propose) L.cn.kb = 0;
-        L.dblk = 1 + (L.cn.kb + DEC_CORR_TRIALS - 1) / DEC_CORR_TRIALS;
+        // the first pass's acceptances are committed by blocks of their own,
+        // unless the decision block proposes the next batch after its commit
+        // (those proposals read positions this batch may have moved)
+        L.da.n_cm = L.late.kb > 0 ? 0 : (kb * b->max_na + CM_ITEMS - 1) / CM_ITEMS;
+        L.dblk = 1 + L.da.n_cm + (L.cn.kb + DEC_CORR_TRIALS - 1) / DEC_CORR_TRIALS;
         L.ovf0 = w.ovf_fill;
         // the final sums of each batch run beside the next batch's scan
         L.da.defer = 1;
@@ -2296,6 +2604,7 @@ void mc_multi_plan(McMulti *m, nd_box *const *boxes, int n, const nd_mc_params *
             L.cr.kb = L.ca.kb;
             L.cn.kb = 0;
             L.dblk = 1;
+            L.da.n_cm = 0;  // each box's decision block commits its own trials
             // each box's decision keeps its own final sums
             L.da.defer = 0;
             L.fin.kb = 0;

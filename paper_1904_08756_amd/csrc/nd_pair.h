@@ -26,6 +26,14 @@ __device__ __forceinline__ float4 ld4(const float4 *p)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// A float4 from LDS through a generic pointer into shared memory (an LDS
+// read rather than a flat one).
+__device__ __forceinline__ float4 ld_lds4(const float4 *p)
+{
+    const nd_v4f v = *(const __attribute__((address_space(3))) nd_v4f *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ int4 ld_i4(const int4 *p)
 {
     typedef int v4i __attribute__((ext_vector_type(4)));

@@ -25,6 +25,13 @@ def test_splitmix64_published_outputs(orc):
         assert orc.splitmix64(0, int(idx)) == int(val, 16)
 
 
+def test_uniform_is_the_top_53_bits_of_the_published_outputs(orc):
+    # draws 0 and 1 of trial 0 with seed 0 are outputs 0 and 1 of the
+    # generator started from state 0 (tests/golden/splitmix64_seed0.txt)
+    for d, x in ((0, 0xE220A8397B1DCDAF), (1, 0x6E789E6AA1B965F4)):
+        assert orc.uniform(0, 0, d) == (x >> 11) * 2.0 ** -53
+
+
 def test_uniform_draws_are_uniform_and_distinct(orc):
     u = np.array([orc.uniform(1234, t, d) for t in range(2000) for d in range(8)])
     assert u.min() >= 0.0 and u.max() < 1.0
