@@ -754,15 +754,15 @@ __device__ __forceinline__ void cell_flush(const PairCtx &c, const TrialAtoms &t
         for (int at = 0; at < MAXNU; ++at) {
             if (at < tna) {
                 float u;
+                // one table row for the atom's old and new position (its species)
                 const int rn = c.prow[ta.rb[2 * at + 1] + sj];
                 const double nx = sx - ta.x[2 * at + 1], ny = sy - ta.y[2 * at + 1], nz = sz - ta.z[2 * at + 1];
                 if (CIMG ? pair_u_img(c, nx, ny, nz, rn, u) : pair_u_disp(c, nx, ny, nz, rn, u)) {
                     e += (double)u;
                     s += (double)fabsf(u);
                 }
-                const int ro = c.prow[ta.rb[2 * at] + sj];
                 const double ox = sx - ta.x[2 * at], oy = sy - ta.y[2 * at], oz = sz - ta.z[2 * at];
-                if (CIMG ? pair_u_img(c, ox, oy, oz, ro, u) : pair_u_disp(c, ox, oy, oz, ro, u)) {
+                if (CIMG ? pair_u_img(c, ox, oy, oz, rn, u) : pair_u_disp(c, ox, oy, oz, rn, u)) {
                     e -= (double)u;
                     s += (double)fabsf(u);
                 }

@@ -111,16 +111,18 @@ __device__ __forceinline__ float r2_hi(float4 p, float4 q)
     return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
-// Square root of a non-negative FP64 value to about 2e-14 relative: the
-// FP32 square root refined by one Newton step in FP64 (the step's 1/(2 r0)
-// from the FP32 reciprocal).  0 when the FP32 root is 0.
+// Square root of a non-negative FP64 value to about 1e-13 relative, from one
+// FP32 reciprocal square root y (one transcendental): r0 = r2 y, then one
+// Newton step r = r0 + (r2 - r0^2) y / 2 in FP64, which squares y's
+// relative error (~2e-7).  0 when r2 rounds to 0 in FP32.
 __device__ __forceinline__ double sqrt_nr(double r2)
 {
-    const float rf = __builtin_amdgcn_sqrtf((float)r2);
-    const double r0 = (double)rf;
+    const float rf2 = (float)r2;
+    const double y = (double)__builtin_amdgcn_rsqf(rf2);
+    const double r0 = r2 * y;
     const double d = fma(-r0, r0, r2);
-    const double r = fma(d, (double)(0.5f * __builtin_amdgcn_rcpf(rf)), r0);
-    return rf > 0.0f ? r : 0.0;
+    const double r = fma(d, 0.5 * y, r0);
+    return rf2 > 0.0f ? r : 0.0;
 }
 
 // Exact-path pair energy of trial atom p (FP64 fractional position ps,
