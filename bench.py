@@ -34,12 +34,15 @@ OPS_PER_TEST = 16
 # fix-up), 2 range check and address.  The kernel's fixed-point candidate
 # path issues about 18 per pair plus the rare exact edge test.
 OPS_PER_PAIR = 23
+# VALU lane-ops the kernel issues per pair, from rocprofv3 SQ_INSTS_VALU x 64
+# / pairs on the same workload (profiles/k_pair_hist_water99999.md)
+ISSUED_OPS_PER_PAIR = 21.3
 # HBM bytes one k_pair_hist launch moves on the 99,999-atom water box, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch scaled by a 1 GiB copy
-# (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 7147.1 + 24958.9
+# (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 5130.0 + 19418.5
 # KiB.  profiles/k_pair_hist_water99999.md holds the counters and commands;
 # set to None whenever the kernel changes until they are taken again.
-HIST_TRAFFIC_BYTES = (2 * 7147.1 + 24958.9) * 1024
+HIST_TRAFFIC_BYTES = (2 * 5130.0 + 19418.5) * 1024
 PAPER_GPU_STEPS_PER_S_1E5 = 12412.0  # Table "tab_speed", water, 1e5 atoms, Tesla V100
 # Table "tab_speed", GPU row at the scale-up sizes (atoms: steps/s)
 PAPER_GPU_SCALE = {1200000: 3917.0, 3000000: 1963.0, 9999999: 757.0, 30000000: 340.3}
@@ -356,6 +359,12 @@ def main():
             "launches": hist_n, "avg_launch_ms": hist_avg_s * 1e3,
             "algorithmic_per_launch": f"{n_pairs} pairs x {OPS_PER_PAIR} lane-ops",
             "pairs_per_s": n_pairs / hist_avg_s,
+            # the kernel reaches the exact bin with fewer instructions than
+            # the algorithmic count (rocprofv3 SQ counters: 21.3 lane-ops
+            # issued per pair), so frac can pass 1 while the VALU issue rate
+            # stays below its peak
+            "issued_lane_ops_per_pair": ISSUED_OPS_PER_PAIR,
+            "issued_frac": n_pairs / hist_avg_s * ISSUED_OPS_PER_PAIR / PEAK_LANE_OPS,
         },
         # The Metropolis scan launch (cell scan of a batch's trials, plus the
         # batch's corrections, proposals and final sums): algorithmic work =

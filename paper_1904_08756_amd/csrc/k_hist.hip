@@ -93,7 +93,9 @@ struct HistArgs {
     long long tile0;        // first global tile-pair index of this box (several boxes per launch)
 };
 
-// LDS layout of the histogram kernels.
+// LDS layout of the histogram kernels.  A block is GRP groups of TILE
+// threads; each group stages its own j tile, and the groups share one
+// histogram (so a block's flush covers the pairs of GRP groups).
 struct HistLds {
     int4 *jq;        // [TILE] j-tile fixed-point coordinates; .w: row word offsets (16 bits per species, M <= 2)
     float *jf;       // [3][TILE] j-tile float32 coordinates
@@ -102,19 +104,21 @@ struct HistLds {
     unsigned *hist;  // [P * nbins + 1]: the last word takes pairs just past the range
 };
 
-__device__ __forceinline__ HistLds hist_lds(unsigned char *smem)
+constexpr size_t HIST_LDS_GROUP = sizeof(int4) * TILE + sizeof(float) * 3 * TILE + sizeof(int) * ND_MAX_SPECIES * TILE;
+
+__device__ __forceinline__ HistLds hist_lds(unsigned char *smem, int grp, int n_grp)
 {
     HistLds h;
-    h.jq = reinterpret_cast<int4 *>(smem);
+    unsigned char *g = smem + HIST_LDS_GROUP * (size_t)grp;
+    h.jq = reinterpret_cast<int4 *>(g);
     h.jf = reinterpret_cast<float *>(h.jq + TILE);
     h.jrow = reinterpret_cast<int *>(h.jf + 3 * TILE);
-    h.prow = h.jrow + ND_MAX_SPECIES * TILE;
+    h.prow = reinterpret_cast<int *>(smem + HIST_LDS_GROUP * (size_t)n_grp);
     h.hist = reinterpret_cast<unsigned *>(h.prow + 16);
     return h;
 }
 
-constexpr size_t HIST_LDS_FIXED =
-    sizeof(int4) * TILE + sizeof(float) * 3 * TILE + sizeof(int) * (ND_MAX_SPECIES * TILE + 16);
+constexpr size_t hist_lds_fixed(int n_grp) { return HIST_LDS_GROUP * (size_t)n_grp + sizeof(int) * 16; }
 
 // Fixed-point fractional coordinate: round(x / L 2^32) mod 2^32.  The
 // difference of two of them, read as a signed 32-bit integer, is the
@@ -128,7 +132,7 @@ __device__ __forceinline__ int fixed_coord(float x, double invL)
 __device__ __forceinline__ void hist_begin(const HistArgs &a, const HistLds &h)
 {
     const int tid = threadIdx.x;
-    for (int q = tid; q < a.P * a.nbins; q += TILE) h.hist[q] = 0u;
+    for (int q = tid; q < a.P * a.nbins; q += blockDim.x) h.hist[q] = 0u;
     if (tid < a.M * a.M) {
         int s0 = tid / a.M, s1 = tid % a.M;
         int lo = s0 < s1 ? s0 : s1, hi = s0 < s1 ? s1 : s0;
@@ -148,13 +152,14 @@ __device__ __forceinline__ void hist_begin(const HistArgs &a, const HistLds &h)
 // of the range) the bin is K - 1 or K, and the FP64 r2 compared with
 // (K dr)^2 decides; otherwise the candidate's floor is the bin.  One LDS
 // atomic per counted pair.
+// tid: the thread's rank in its group; valid false: the group has no tile
+// pair in this round and only takes part in the barriers.
 template <bool PACKED>
-__device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, int I, int J)
+__device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, int I, int J, int tid, bool valid)
 {
-    const int tid = threadIdx.x;
     const int N = a.N;
     const int i = I * TILE + tid;
-    const bool iv = i < N;
+    const bool iv = valid && i < N;
     float xi = 0.f, yi = 0.f, zi = 0.f;
     int si = 0;
     if (iv) {
@@ -166,7 +171,7 @@ __device__ __forceinline__ void hist_tile(const HistArgs &a, const HistLds &h, i
     const int qx = fixed_coord(xi, a.invL), qy = fixed_coord(yi, a.invL), qz = fixed_coord(zi, a.invL);
     __syncthreads();  // previous tile's readers are done with the j arrays
     const int j = J * TILE + tid;
-    if (j < N) {
+    if (valid && j < N) {
         const float x = a.xyz[j], y = a.xyz[N + j], z = a.xyz[2 * N + j];
         const int sj = a.sp[j];
         int w = 0;
@@ -228,7 +233,7 @@ __device__ __forceinline__ void hist_flush(const HistArgs &a, const HistLds &h)
 {
     __syncthreads();
     const int nq = a.P * a.nbins;
-    for (int q = threadIdx.x; q < nq; q += TILE) {
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
         const unsigned v = h.hist[q];
         if (v) {
             atomicAdd(&a.out[q], (unsigned long long)v);
@@ -238,18 +243,23 @@ __device__ __forceinline__ void hist_flush(const HistArgs &a, const HistLds &h)
     __syncthreads();
 }
 
-template <bool PACKED>
-__global__ __launch_bounds__(TILE) void k_pair_hist(HistArgs a)
+// Block b takes the rounds of tile pairs t = (b + r gridDim) GRP + g, group
+// g one pair per round; a round adds at most GRP TILE^2 counts to a
+// counter, so the LDS counters are flushed every FLUSH_TILES / GRP rounds.
+template <bool PACKED, int GRP>
+__global__ __launch_bounds__(TILE * GRP, 8) void k_pair_hist(HistArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const HistLds h = hist_lds(smem);
+    const int grp = threadIdx.x / TILE, tid = threadIdx.x - grp * TILE;
+    const HistLds h = hist_lds(smem, grp, GRP);
     hist_begin(a, h);
     long long since = 0;
-    for (long long t = blockIdx.x; t < a.ntp; t += gridDim.x) {
-        int I, J;
-        tri_index(t, a.nt, I, J);
-        hist_tile<PACKED>(a, h, I, J);
-        if (++since == FLUSH_TILES) {
+    for (long long t0 = (long long)blockIdx.x * GRP; t0 < a.ntp; t0 += (long long)gridDim.x * GRP) {
+        const long long t = t0 + grp;
+        int I = 0, J = 0;
+        if (t < a.ntp) tri_index(t, a.nt, I, J);
+        hist_tile<PACKED>(a, h, I, J, tid, t < a.ntp);
+        if (++since == FLUSH_TILES / GRP) {
             hist_flush(a, h);
             since = 0;
         }
@@ -267,7 +277,7 @@ __global__ __launch_bounds__(TILE) void k_pair_hist_multi(const HistArgs *__rest
                                                           long long total, long long per)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const HistLds h = hist_lds(smem);
+    const HistLds h = hist_lds(smem, 0, 1);
     long long t = (long long)blockIdx.x * per;
     const long long t_end = min(total, t + per);
     if (t >= t_end) return;
@@ -290,7 +300,7 @@ __global__ __launch_bounds__(TILE) void k_pair_hist_multi(const HistArgs *__rest
             for (; t < box_end; ++t) {
                 int I, J;
                 tri_index(t - a.tile0, a.nt, I, J);
-                hist_tile<PACKED>(a, h, I, J);
+                hist_tile<PACKED>(a, h, I, J, threadIdx.x, true);
                 if (++since == FLUSH_TILES) {
                     hist_flush(a, h);
                     since = 0;
@@ -484,12 +494,14 @@ HistArgs make_hist_args(const nd_box *b, double dr, int nbins)
 // Whether the packed layout holds: at most two species, row offsets < 2^16.
 bool hist_packed(int M, int nq) { return M <= 2 && nq < 65536; }
 
-size_t hist_lds_bytes(int nq)
+size_t hist_lds_bytes(int nq, int n_grp = 1)
 {
-    const size_t lds = HIST_LDS_FIXED + sizeof(unsigned) * ((size_t)nq + 1);
+    const size_t lds = hist_lds_fixed(n_grp) + sizeof(unsigned) * ((size_t)nq + 1);
     if (lds > 160 * 1024) nd::fail(ND_E_UNSUPPORTED, "histogram does not fit in LDS (P*nbins too large)");
     return lds;
 }
+
+constexpr int HIST_GRP = 4;  // groups per block of the single-box kernel
 
 }  // namespace
 
@@ -499,22 +511,36 @@ void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
 {
     HistArgs a = make_hist_args(b, dr, nbins);
     const int nq = a.P * nbins;
-    const size_t lds = hist_lds_bytes(nq);
+    // tuned: groups of TILE threads per CU; blocks of HIST_GRP groups share
+    // a histogram when two such blocks fit a CU's LDS, else one group each
     nd_tuning te;
     const int want = (tune_lookup(ND_TUNE_BOX, b->N, &te) && te.hist_blocks_per_cu > 0) ? te.hist_blocks_per_cu : 5;
-    int per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)want, (160 * 1024) / lds));
+    const size_t lds_g = hist_lds_bytes(nq, HIST_GRP);
+    const int grp = 2 * lds_g <= 160 * 1024 ? HIST_GRP : 1;
+    const size_t lds = grp == 1 ? hist_lds_bytes(nq, 1) : lds_g;
+    const int want_blk = std::max(1, (want + grp - 1) / grp);
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)want_blk, (160 * 1024) / lds));
     long long G = (long long)cu_count(b->device) * per_cu;
-    if (G > a.ntp) G = a.ntp;
+    G = std::min<long long>(G, (a.ntp + grp - 1) / grp);
     a.out = reinterpret_cast<unsigned long long *>(d_counts);
     hipLaunchKernelGGL(k_zero_u64, dim3((nq + 255) / 256), dim3(256), 0, b->stream, a.out, nq);
     ND_HIP(hipGetLastError());
     {
         ProfScope ps(b, ND_PROF_PAIR_HIST);
         // row offsets of up to two species fit the spare lane of the j records
-        if (hist_packed(a.M, nq))
-            hipLaunchKernelGGL(k_pair_hist<true>, dim3((unsigned)G), dim3(TILE), lds, b->stream, a);
-        else
-            hipLaunchKernelGGL(k_pair_hist<false>, dim3((unsigned)G), dim3(TILE), lds, b->stream, a);
+        const bool packed = hist_packed(a.M, nq);
+        const dim3 g((unsigned)G), t(TILE * grp);
+        if (grp == HIST_GRP) {
+            if (packed)
+                hipLaunchKernelGGL((k_pair_hist<true, HIST_GRP>), g, t, lds, b->stream, a);
+            else
+                hipLaunchKernelGGL((k_pair_hist<false, HIST_GRP>), g, t, lds, b->stream, a);
+        } else {
+            if (packed)
+                hipLaunchKernelGGL((k_pair_hist<true, 1>), g, t, lds, b->stream, a);
+            else
+                hipLaunchKernelGGL((k_pair_hist<false, 1>), g, t, lds, b->stream, a);
+        }
         ND_HIP(hipGetLastError());
     }
 }

@@ -89,3 +89,26 @@ def test_scale_mc_chain_and_running_histogram(nd, orc, big):
     fresh = nd.pair_histogram(g, mc["dr"], mc["nbins"]).cpu().numpy()
     assert np.array_equal(run, fresh)
     g.track_histogram(mc["dr"], 0)
+
+
+def test_histogram_counts_past_two_to_the_32(nd):
+    """140,000 atoms on two points 5.015 A apart, 70,000 on each: bin 0 holds
+    the 2 C(70000, 2) pairs on a point and bin 167 the 70000^2 pairs across,
+    both above 2^32, so every carry of a counter into its high word is taken;
+    the counts are that closed form, exactly."""
+    n = 70000
+    xyz = np.full((3, 2 * n), 10.0, np.float32)
+    xyz[0, n:] = 15.015
+    box = syn.Box("two points", 40.0, np.zeros(2 * n, np.uint8), np.arange(2 * n + 1, dtype=np.int32), xyz, 1)
+    g = nd.Box.from_synthetic(box)
+    dr, nbins = 0.03, 200
+    r = float(np.float32(15.015)) - 10.0
+    k = int(r // dr)
+    assert (k * dr) ** 2 <= r * r < ((k + 1) * dr) ** 2 and k == 167
+    got = nd.pair_histogram(g, dr, nbins).cpu().numpy().astype(np.uint64).ravel()
+    want = np.zeros(nbins, np.uint64)
+    want[0] = n * (n - 1)
+    want[k] = n * n
+    assert want[0] > 2 ** 32 and want[k] > 2 ** 32
+    assert np.array_equal(got, want)
+    g.close()
