@@ -486,8 +486,12 @@ typedef struct nd_tuning {
                                    end of a Metropolis batch; sets the batch size
                                    K = target / f (f the share of the box within reach,
                                    K <= 2048 and <= n_units / 2); 0 = built in (18)    */
-    int32_t hist_blocks_per_cu; /* pair-histogram blocks per compute unit, 1..8, capped by
-                                   LDS; 0 = built in (5)                               */
+    int32_t hist_blocks_per_cu; /* pair histogram: 256-thread groups per compute unit,
+                                   1..8, capped by LDS.  The single-box kernel packs
+                                   four groups into a block that shares one LDS
+                                   histogram (1..4: one block per CU, 5..8: two); the
+                                   several-box kernel runs one group per block.
+                                   0 = built in (8 single-box, 5 several-box)          */
     int32_t pad;
 } nd_tuning;
 

@@ -15,7 +15,9 @@ pair histograms) and keeps the fastest:
 Searched: the cell scan's waves per trial (1, 2, 4) and the batch target
 (expected interacting earlier trials per trial, which sets the Metropolis
 batch size) together, timed over whole sweeps; then the pair histogram's
-blocks per compute unit (3..6) with the best of those.  The result is a text
+256-thread groups per compute unit with the best of those (4 or 8 for a box:
+one or two blocks of four groups sharing a histogram; 3..6 for the batch's
+several-box kernel, one group per block).  The result is a text
 table (the format of nd_load_tuning) that the binding loads at start-up;
 each entry's comment lists the times of every candidate.
 
@@ -31,7 +33,8 @@ import time
 
 WAVES = (1, 2, 4)
 TARGETS = (9.0, 13.5, 18.0, 27.0, 36.0)
-BLOCKS_PER_CU = (3, 4, 5, 6)
+BOX_GROUPS_PER_CU = (4, 8)
+BATCH_GROUPS_PER_CU = (3, 4, 5, 6)
 BIG = 2 ** 62
 
 BOX_CLASSES = (  # (n_max, molecules of the representative box)
@@ -78,7 +81,7 @@ def tune_box(nd, syn, torch, n_max, n_mol, quick):
             times[(w, tgt)] = _timed(torch, sweep, 2)
     w_best, t_best = min(times, key=times.get)
     htimes = {}
-    for bpc in BLOCKS_PER_CU:
+    for bpc in BOX_GROUPS_PER_CU:
         nd.set_tuning([dict(kind="box", n_max=BIG, scan_waves=w_best, batch_target=t_best, hist_blocks_per_cu=bpc)])
         htimes[bpc] = _timed(torch, lambda: nd.pair_histogram(g, mc["dr"], nbins), 2)
     b_best = min(htimes, key=htimes.get)
@@ -124,7 +127,7 @@ def tune_batch(nd, syn, torch, quick):
             times[(wv, tgt)] = _timed(torch, run, 3)
     w_best, t_best = min(times, key=times.get)
     htimes = {}
-    for bpc in BLOCKS_PER_CU:
+    for bpc in BATCH_GROUPS_PER_CU:
         nd.set_tuning([dict(kind="batch", n_max=BIG, scan_waves=w_best, batch_target=t_best, hist_blocks_per_cu=bpc)])
         htimes[bpc] = _timed(torch, run, 3)
     b_best = min(htimes, key=htimes.get)

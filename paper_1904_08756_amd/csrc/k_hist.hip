@@ -514,7 +514,7 @@ void launch_pair_histogram(nd_box *b, double dr, int nbins, uint64_t *d_counts)
     // tuned: groups of TILE threads per CU; blocks of HIST_GRP groups share
     // a histogram when two such blocks fit a CU's LDS, else one group each
     nd_tuning te;
-    const int want = (tune_lookup(ND_TUNE_BOX, b->N, &te) && te.hist_blocks_per_cu > 0) ? te.hist_blocks_per_cu : 5;
+    const int want = (tune_lookup(ND_TUNE_BOX, b->N, &te) && te.hist_blocks_per_cu > 0) ? te.hist_blocks_per_cu : 8;
     const size_t lds_g = hist_lds_bytes(nq, HIST_GRP);
     const int grp = 2 * lds_g <= 160 * 1024 ? HIST_GRP : 1;
     const size_t lds = grp == 1 ? hist_lds_bytes(nq, 1) : lds_g;
