@@ -36,7 +36,7 @@ OPS_PER_TEST = 16
 OPS_PER_PAIR = 23
 # VALU lane-ops the kernel issues per pair, from rocprofv3 SQ_INSTS_VALU x 64
 # / pairs on the same workload (profiles/k_pair_hist_water99999.md)
-ISSUED_OPS_PER_PAIR = 21.3
+ISSUED_OPS_PER_PAIR = 21.8
 # HBM bytes one k_pair_hist launch moves on the 99,999-atom water box, from
 # rocprofv3 FETCH_SIZE / WRITE_SIZE per dispatch scaled by a 1 GiB copy
 # (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 5130.0 + 19418.5

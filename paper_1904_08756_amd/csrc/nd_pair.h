@@ -114,15 +114,15 @@ __device__ __forceinline__ float r2_hi(float4 p, float4 q)
 // Square root of a non-negative FP64 value to about 1e-13 relative, from one
 // FP32 reciprocal square root y (one transcendental): r0 = r2 y, then one
 // Newton step r = r0 + (r2 - r0^2) y / 2 in FP64, which squares y's
-// relative error (~2e-7).  0 when r2 rounds to 0 in FP32.
+// relative error (~2e-7).  The FP32 argument is held at or above the least
+// normal float, so r2 = 0 gives y finite and r = 0 (pair distances here are
+// far above that bound).
 __device__ __forceinline__ double sqrt_nr(double r2)
 {
-    const float rf2 = (float)r2;
-    const double y = (double)__builtin_amdgcn_rsqf(rf2);
+    const double y = (double)__builtin_amdgcn_rsqf(fmaxf((float)r2, 1.17549435e-38f));
     const double r0 = r2 * y;
     const double d = fma(-r0, r0, r2);
-    const double r = fma(d, 0.5 * y, r0);
-    return rf2 > 0.0f ? r : 0.0;
+    return fma(d, 0.5 * y, r0);
 }
 
 // Exact-path pair energy of trial atom p (FP64 fractional position ps,
