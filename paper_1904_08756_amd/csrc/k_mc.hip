@@ -354,7 +354,7 @@ __device__ __forceinline__ void scan_trial(const PairCtx &c, const nd::Trial *__
 // g*tg .. g*tg+tg-1 against atoms jb*SCAN_JB .. +SCAN_JB (SCAN_JPT per thread,
 // in registers), tables in LDS, one FP64 wave reduction per trial.
 template <int MAXNU>
-__global__ __launch_bounds__(SCAN_THREADS) void k_mc_scan(ScanArgs a)
+__global__ __launch_bounds__(SCAN_THREADS, 4) void k_mc_scan(ScanArgs a)
 {
     extern __shared__ __align__(16) float s_tab[];  // [P][n_pts]
     __shared__ int s_prow[16];
@@ -388,11 +388,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_mc_scan(ScanArgs a)
 #pragma unroll
         for (int m = 0; m < SCAN_JPT; ++m)
             if (__float_as_int(pl[m].w) == tunit) ex |= 1u << m;
-        if (__ballot(ex != 0u) == 0ull) {
-            scan_trial<MAXNU, false>(c, T, tna, pj, pl, 0u, e, s);
-        } else {
-            scan_trial<MAXNU, true>(c, T, tna, pj, pl, ex, e, s);
-        }
+        scan_trial<MAXNU, true>(c, T, tna, pj, pl, ex, e, s);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             e += __shfl_xor(e, o);
