@@ -269,15 +269,17 @@ __global__ __launch_bounds__(TILE * GRP, 8) void k_pair_hist(HistArgs a)
 
 // Several boxes in one persistent launch.  The tile pairs of all boxes form
 // one index range (box after box); block b takes the contiguous slice
-// [b per, (b + 1) per) of it, so it meets one or two boxes, and adds its LDS
+// [b per, (b + 1) per) of it, so it meets one or two boxes, its GRP groups
+// taking consecutive tile pairs of a box in rounds, and adds its LDS
 // histogram to a box's counts with integer atomics when it leaves the box
 // (exact, so the counts do not depend on the order of the blocks).
-template <bool PACKED>
-__global__ __launch_bounds__(TILE) void k_pair_hist_multi(const HistArgs *__restrict__ boxes, int n_boxes,
-                                                          long long total, long long per)
+template <bool PACKED, int GRP>
+__global__ __launch_bounds__(TILE * GRP, 8) void k_pair_hist_multi(const HistArgs *__restrict__ boxes, int n_boxes,
+                                                                   long long total, long long per)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const HistLds h = hist_lds(smem, 0, 1);
+    const int grp = threadIdx.x / TILE, tid = threadIdx.x - grp * TILE;
+    const HistLds h = hist_lds(smem, grp, GRP);
     long long t = (long long)blockIdx.x * per;
     const long long t_end = min(total, t + per);
     if (t >= t_end) return;
@@ -297,15 +299,18 @@ __global__ __launch_bounds__(TILE) void k_pair_hist_multi(const HistArgs *__rest
         if (t < box_end) {
             hist_begin(a, h);
             long long since = 0;
-            for (; t < box_end; ++t) {
-                int I, J;
-                tri_index(t - a.tile0, a.nt, I, J);
-                hist_tile<PACKED>(a, h, I, J, threadIdx.x, true);
-                if (++since == FLUSH_TILES) {
+            for (; t < box_end; t += GRP) {
+                const long long tg = t + grp;
+                const bool valid = tg < box_end;
+                int I = 0, J = 0;
+                if (valid) tri_index(tg - a.tile0, a.nt, I, J);
+                hist_tile<PACKED>(a, h, I, J, tid, valid);
+                if (++since == FLUSH_TILES / GRP) {
                     hist_flush(a, h);
                     since = 0;
                 }
             }
+            t = box_end;
             hist_flush(a, h);
         }
         ++bi;
@@ -501,7 +506,7 @@ size_t hist_lds_bytes(int nq, int n_grp = 1)
     return lds;
 }
 
-constexpr int HIST_GRP = 4;  // groups per block of the single-box kernel
+constexpr int HIST_GRP = 4;  // groups per block sharing one LDS histogram
 
 }  // namespace
 
@@ -551,7 +556,7 @@ struct HistMulti {
     HistArgs *d_boxes = nullptr;
     size_t cap = 0;
     long long total = 0, per = 0;
-    int G = 0, max_nq = 0, max_m = 0;
+    int G = 0, max_nq = 0, max_m = 0, grp = 1;
     size_t lds = 0;
 };
 
@@ -580,13 +585,18 @@ void hist_multi_plan(HistMulti *m, nd_box *const *boxes, int n, double dr, const
         m->max_m = std::max(m->max_m, a.M);
         m->boxes.push_back(a);
     }
-    m->lds = hist_lds_bytes(m->max_nq);
     long long total_atoms = 0;
     for (int i = 0; i < n; ++i) total_atoms += boxes[i]->N;
+    // tuned: groups of TILE threads per CU; blocks of HIST_GRP groups when
+    // two of them fit a CU's LDS, else one group per block
     nd_tuning te;
     const int want =
-        (tune_lookup(ND_TUNE_BATCH, total_atoms, &te) && te.hist_blocks_per_cu > 0) ? te.hist_blocks_per_cu : 5;
-    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)want, (160 * 1024) / m->lds));
+        (tune_lookup(ND_TUNE_BATCH, total_atoms, &te) && te.hist_blocks_per_cu > 0) ? te.hist_blocks_per_cu : 8;
+    const size_t lds_g = hist_lds_bytes(m->max_nq, HIST_GRP);
+    m->grp = 2 * lds_g <= 160 * 1024 ? HIST_GRP : 1;
+    m->lds = m->grp == 1 ? hist_lds_bytes(m->max_nq, 1) : lds_g;
+    const int want_blk = std::max(1, (want + m->grp - 1) / m->grp);
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)want_blk, (160 * 1024) / m->lds));
     long long G = (long long)cu_count(boxes[0]->device) * per_cu;
     if (G > m->total) G = m->total;
     m->per = (m->total + G - 1) / G;
@@ -603,6 +613,7 @@ void hist_multi_plan(HistMulti *m, nd_box *const *boxes, int n, double dr, const
     sig.push_back(m->total);
     sig.push_back(m->max_nq);
     sig.push_back(m->max_m);
+    sig.push_back(m->grp);
     sig.push_back((long long)m->lds);
     sig.push_back((long long)(uintptr_t)m->d_boxes);
 }
@@ -618,12 +629,19 @@ void hist_multi_enqueue(HistMulti *m, hipStream_t s)
     const int n = (int)m->boxes.size();
     hipLaunchKernelGGL(k_zero_u64_multi, dim3((m->max_nq + 255) / 256, n), dim3(256), 0, s, m->d_boxes);
     ND_HIP(hipGetLastError());
-    if (hist_packed(m->max_m, m->max_nq))
-        hipLaunchKernelGGL(k_pair_hist_multi<true>, dim3(m->G), dim3(TILE), m->lds, s, m->d_boxes, n, m->total,
-                           m->per);
-    else
-        hipLaunchKernelGGL(k_pair_hist_multi<false>, dim3(m->G), dim3(TILE), m->lds, s, m->d_boxes, n, m->total,
-                           m->per);
+    const bool packed = hist_packed(m->max_m, m->max_nq);
+    const dim3 g(m->G), t(TILE * m->grp);
+    if (m->grp == HIST_GRP) {
+        if (packed)
+            hipLaunchKernelGGL((k_pair_hist_multi<true, HIST_GRP>), g, t, m->lds, s, m->d_boxes, n, m->total, m->per);
+        else
+            hipLaunchKernelGGL((k_pair_hist_multi<false, HIST_GRP>), g, t, m->lds, s, m->d_boxes, n, m->total, m->per);
+    } else {
+        if (packed)
+            hipLaunchKernelGGL((k_pair_hist_multi<true, 1>), g, t, m->lds, s, m->d_boxes, n, m->total, m->per);
+        else
+            hipLaunchKernelGGL((k_pair_hist_multi<false, 1>), g, t, m->lds, s, m->d_boxes, n, m->total, m->per);
+    }
     ND_HIP(hipGetLastError());
 }
 
