@@ -243,6 +243,18 @@ def test_mc_c2_sample_matches(nd, orc, scan):
     _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, 3000, scan=scan)
 
 
+@pytest.mark.timeout(900)
+def test_mc_c2_full_sweep_matches(nd, orc):
+    """One whole sweep of the 99,999-atom water box (33,333 trials, 20
+    batches of the bench's size, the cell lists rebuilt at its start) in the
+    launch configuration the bench times, against the oracle's sequential
+    chain trial by trial."""
+    orc.set_threads(orc.max_threads())
+    box, T, mc = syn.config_c2()
+    res, o = _mc_parity(nd, orc, box, T, mc, mc["seed"], 0, box.n_units)
+    assert 0.05 < res["accepted"] / res["trials"] < 0.95
+
+
 def test_mc_c2_later_trials_match(nd, orc):
     box, T, mc = syn.config_c2()
     # start mid-sweep: trial numbers far from 0 use the same counter-based draws
