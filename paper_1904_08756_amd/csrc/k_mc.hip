@@ -524,15 +524,16 @@ __device__ __forceinline__ int corr_collect(const CorrArgs &a, const float4 *lds
 {
     const unsigned long long lt = (1ull << lane) - 1ull;
     int n = 0;
-    for (int m0 = 0; m0 < k; m0 += 256) {
-        float4 B[4];
+    constexpr int CB = 8;  // spheres per lane per round, their loads in flight together
+    for (int m0 = 0; m0 < k; m0 += 64 * CB) {
+        float4 B[CB];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
+        for (int h = 0; h < CB; ++h) {
             const int m = min(m0 + 64 * h + lane, k - 1);
             B[h] = lds ? ld_lds4(lds + m) : ld4(a.spheres + m);
         }
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
+        for (int h = 0; h < CB; ++h) {
             const int m = m0 + 64 * h + lane;
             const bool hit = m < k && spheres_meet(A, B[h], a.rcf);
             const unsigned long long bal = __ballot(hit);
@@ -1037,7 +1038,9 @@ __device__ __forceinline__ void scan_corr_body(const CellScanArgs &a, const Corr
         __syncthreads();
         const PairCtx c{ca.tab, s_prow, ca.M, ca.n_pts, ca.rcf2_filter, ca.rcf2, ca.tscale};
         CorrScratch &cs = *reinterpret_cast<CorrScratch *>(&s_list[tid >> 6][0][0]);
-        const int k = (bx - n_fin - n_prop) * CORR_TPB + (tid >> 6);
+        // trials interleaved over the correction blocks (late trials are the
+        // heavy ones)
+        const int k = (tid >> 6) * n_corr + (bx - n_fin - n_prop);
         if (k < ca.kb) corr_trial<MAXNU>(ca, c, k, tid & 63, cs);
         return;
     }
@@ -1726,15 +1729,20 @@ __device__ __forceinline__ void next_corr_block(const CorrArgs &cn, int bx, Corr
 {
     __shared__ int s_prow[16];
     const int tid = threadIdx.x;
-    // the batch's spheres up to the block's last trial, staged in LDS
-    // (after the scratch): every wave tests its trial against all earlier ones
+    // trials interleaved over the blocks (block bx - 1 of nb takes trials
+    // bx - 1, bx - 1 + nb, ...): a trial's work grows with its rank in the
+    // batch, and a block of consecutive late trials would load its CU's SIMDs
+    // with the heaviest ones at once
+    const int nb = (cn.kb + DEC_CORR_TRIALS - 1) / DEC_CORR_TRIALS;
+    const int k = (tid >> 6) * nb + (bx - 1);
+    // the batch's spheres, staged in LDS (after the scratch): every wave
+    // tests its trial against all earlier ones
     float4 *s_sph = reinterpret_cast<float4 *>(s_cs + DEC_CORR_TRIALS);
-    const int k_end = min(cn.kb, bx * DEC_CORR_TRIALS);
+    const int k_end = min(cn.kb, (DEC_CORR_TRIALS - 1) * nb + bx);
     for (int m = tid; m < k_end; m += DEC_THREADS) s_sph[m] = ld4(cn.spheres + m);
     if (tid < cn.M * cn.M) s_prow[tid] = nd::pair_index(tid / cn.M, tid % cn.M, cn.M) * cn.n_pts;
     __syncthreads();
     const PairCtx c{cn.tab, s_prow, cn.M, cn.n_pts, cn.rcf2_filter, cn.rcf2, cn.tscale};
-    const int k = (bx - 1) * DEC_CORR_TRIALS + (tid >> 6);
     if (k < cn.kb) corr_trial<MAXNU>(cn, c, k, tid & 63, s_cs[tid >> 6], s_sph);
 }
 
