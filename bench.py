@@ -28,6 +28,15 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # Minimum VALU lane operations per distance test of the Metropolis scan:
 # 3 sub, 9 nearest image, 3 for r^2, 1 compare with the cutoff.
 OPS_PER_TEST = 16
+# VALU lane-ops of one exact pair term of a Metropolis trial, as the second
+# work unit of the cell scan: 3 sub + 3 for r^2 + 1 compare, 6 for the
+# square root (FP32 reciprocal root, FP64 Newton step), 5 for the table
+# index and fraction, 3 for the interpolation, 4 for the FP64 sums of U and
+# |U|.  A survivor of a trial of a unit of n_u atoms takes 2 n_u of them.
+OPS_PER_PAIR_TERM = 25
+# wave-level VALU instructions one scan launch of the 99,999-atom water box
+# issues (rocprofv3 SQ_INSTS_VALU, profiles/mc_step_water99999.md)
+SCAN_ISSUED_WAVE_INSTS = 9.07e6
 # Algorithmic VALU lane operations per pair of the exact histogram, as the
 # work unit of its roofline: 3 sub, 9 nearest image (mul, round, fma per
 # axis), 3 for r^2, 6 for the bin (cvt, sqrt, mul, cvt, edge compare,
@@ -378,6 +387,13 @@ def main():
             "launches_per_step": scan_launch_per_step, "avg_launch_us": scan_avg_s * 1e6,
             "candidates_per_trial": cand / n_trials, "survivors_per_trial": surv / n_trials,
             "algorithmic_per_launch": f"{cand / scan_launch_per_step:.4g} candidate tests x {OPS_PER_TEST} lane-ops",
+            # with the survivors' exact pair terms (2 per atom of the moved
+            # unit, old and new) counted too, and the lane-ops the launch
+            # issues by the counters
+            "frac_with_pair_terms": (scan_ops_per_launch + surv / scan_launch_per_step * 2 * (box.n_atoms / g.n_units)
+                                     * OPS_PER_PAIR_TERM)
+            / scan_avg_s / PEAK_LANE_OPS,
+            "issued_frac": SCAN_ISSUED_WAVE_INSTS * 64 / scan_avg_s / PEAK_LANE_OPS,
         },
         "tuning": nd.tuning_for("box", box.n_atoms),
         "kernels": {
