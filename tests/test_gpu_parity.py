@@ -255,6 +255,33 @@ def test_mc_c2_full_sweep_matches(nd, orc):
     assert 0.05 < res["accepted"] / res["trials"] < 0.95
 
 
+def test_mc_and_histogram_degenerate_boxes(nd, orc):
+    """The smallest boxes the boundary accepts: one unit of two atoms (no
+    intermolecular pair, so every trial has dE = 0 and is accepted) and two
+    one-atom units (a single pair); a call with no trials changes nothing;
+    histograms of that one pair, with one bin and with several."""
+    T = syn.potential_table(2, 5.0, 0.01, [(3.0, 0.5), (2.5, 0.3)], [0.5, -0.5])
+    L = 12.0
+    xyz = np.array([[5.0, 5.9], [5.0, 5.4], [5.0, 5.0]], np.float32)
+    one = syn.Box("one unit", L, np.array([0, 1], np.uint8), np.array([0, 2], np.int32), xyz.copy(), 2)
+    two = syn.Box("two units", L, np.array([0, 1], np.uint8), np.array([0, 1, 2], np.int32), xyz.copy(), 2)
+    params = dict(kT=2.5, max_disp=0.5, max_rot=0.3)
+    res, _ = _mc_parity(nd, orc, one, T, params, 21, 0, 64)
+    assert res["accepted"] == 64
+    _mc_parity(nd, orc, two, T, params, 22, 0, 200)
+    g = _gbox(nd, two, T)
+    E0 = g.total_energy()
+    before = g.coords_host()
+    res0 = g.mc_sweep(nd.MCParams(2.5, 0.5, 0.3), 5, 0, 0)
+    assert res0["trials"] == 0 and res0["accepted"] == 0
+    assert np.array_equal(g.coords_host(), before) and g.energy() == E0
+    for nbins, dr in ((1, 5.9), (20, 0.25)):
+        got = nd.pair_histogram(g, dr, nbins).cpu().numpy()
+        want, _ = orc.pair_histogram(two, dr, nbins)
+        assert np.array_equal(got, want) and got.sum() == 1
+    g.close()
+
+
 def test_mc_c2_later_trials_match(nd, orc):
     box, T, mc = syn.config_c2()
     # start mid-sweep: trial numbers far from 0 use the same counter-based draws
