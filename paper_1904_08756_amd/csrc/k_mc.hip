@@ -472,6 +472,7 @@ struct CorrArgs {
     double *pool_c;              // C_km, the change of k's dE if m was accepted
     int32_t *ovf_fill;           // overflow entries used in this batch
     int ovf_base;
+    int per_block;               // decision launch: trials per correction block (one per wave, <= 16)
 };
 
 // A decided batch's final dE sums, counters and trace (k_mc_final's body,
@@ -1733,12 +1734,13 @@ __device__ __forceinline__ void next_corr_block(const CorrArgs &cn, int bx, Corr
     // bx - 1, bx - 1 + nb, ...): a trial's work grows with its rank in the
     // batch, and a block of consecutive late trials would load its CU's SIMDs
     // with the heaviest ones at once
-    const int nb = (cn.kb + DEC_CORR_TRIALS - 1) / DEC_CORR_TRIALS;
-    const int k = (tid >> 6) * nb + (bx - 1);
+    const int tpb = cn.per_block;
+    const int nb = (cn.kb + tpb - 1) / tpb;
+    const int k = (tid >> 6) < tpb ? (tid >> 6) * nb + (bx - 1) : cn.kb;
     // the batch's spheres, staged in LDS (after the scratch): every wave
     // tests its trial against all earlier ones
     float4 *s_sph = reinterpret_cast<float4 *>(s_cs + DEC_CORR_TRIALS);
-    const int k_end = min(cn.kb, (DEC_CORR_TRIALS - 1) * nb + bx);
+    const int k_end = min(cn.kb, (tpb - 1) * nb + bx);
     for (int m = tid; m < k_end; m += DEC_THREADS) s_sph[m] = ld4(cn.spheres + m);
     if (tid < cn.M * cn.M) s_prow[tid] = nd::pair_index(tid / cn.M, tid % cn.M, cn.M) * cn.n_pts;
     __syncthreads();
@@ -2129,6 +2131,7 @@ CorrArgs corr_args(const nd_box *b, const McConsts &k, const nd::Trial *trials, 
     cr.pool_c = w.pool_c + (size_t)buf * w.cap_pool;
     cr.ovf_fill = w.ovf_fill + buf;
     cr.ovf_base = K * CORR_CAP;
+    cr.per_block = DEC_CORR_TRIALS;
     return cr;
 }
 
@@ -2328,7 +2331,12 @@ void mc_plan_cells(nd_box *b, const nd_mc_params *p, uint64_t seed, uint64_t fir
         // unless the decision block proposes the next batch after its commit
         // (those proposals read positions this batch may have moved)
         L.da.n_cm = L.late.kb > 0 ? 0 : (kb * b->max_na + CM_ITEMS - 1) / CM_ITEMS;
-        L.dblk = 1 + L.da.n_cm + (L.cn.kb + DEC_CORR_TRIALS - 1) / DEC_CORR_TRIALS;
+        // correction blocks of 8 trials (two waves per SIMD) when the
+        // launch then still fits one block per CU, else 16
+        L.cn.per_block = DEC_CORR_TRIALS / 2;
+        if (1 + L.da.n_cm + (L.cn.kb + L.cn.per_block - 1) / L.cn.per_block > nd::cu_count(b->device))
+            L.cn.per_block = DEC_CORR_TRIALS;
+        L.dblk = 1 + L.da.n_cm + (L.cn.kb + L.cn.per_block - 1) / L.cn.per_block;
         L.ovf0 = w.ovf_fill;
         // the final sums of each batch run beside the next batch's scan
         L.da.defer = 1;
