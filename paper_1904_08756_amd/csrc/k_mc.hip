@@ -294,10 +294,25 @@ __device__ __forceinline__ void propose_one(const ProposeArgs &a, int k)
     T->cen[2] = cz;
     T->rad = rad;
     a.spheres[k] = make_float4(cx, cy, cz, rad);
-    // z-slab of the centre, for the XCD-aware assignment of scan blocks
+    // z-slab of the centre, for the XCD-aware assignment of scan blocks; the
+    // trials of a wave are listed with one atomic per slab they fall in
+    // (the lanes calling this may be any subset of the wave)
     const float zw = cz - floorf(cz);
     const int sb = min(max((int)(zw * (float)N_SLAB), 0), N_SLAB - 1);
-    const int pos = atomicAdd(&a.slab[sb], 1);
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int pos = 0;
+#pragma unroll
+    for (int q = 0; q < N_SLAB; ++q) {
+        const unsigned long long m = __ballot(sb == q);
+        if (m != 0ull && sb == q) {
+            const int leader = __ffsll((long long)m) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&a.slab[q], __popcll(m));
+            base = __shfl(base, leader);
+            pos = base + __popcll(m & lt);
+        }
+    }
     a.slab[N_SLAB + sb * a.kcap + pos] = k;
 }
 
