@@ -4,12 +4,15 @@
 // Layout: the i side of a tile pair is held one atom per thread in
 // registers; the j side is staged in LDS (fixed-point and float32
 // coordinates plus the histogram row offsets) and read by broadcast.
-// Counts go to an LDS-private u32 histogram per block; each block visits
-// many tile pairs (persistent grid) and adds its nonzero counters with
-// integer atomics when it is done, and after every FLUSH_TILES tile pairs,
-// before a u32 counter could overflow, into the u64 counts (the several-box
-// kernel into each box's counts).  Integer sums are exact in any order, so
-// the counts do not depend on scheduling.
+// A block is GRP groups of TILE threads; each group takes its own tile
+// pair per round and all of them count into one LDS-private u32 histogram
+// of the block (one copy per CU's worth of groups instead of one per group,
+// so fewer counters to merge).  Blocks visit many tile pairs (persistent
+// grid) and add their nonzero counters with integer atomics when done, and
+// after every FLUSH_TILES tile pairs counted into a counter, before a u32
+// could overflow, into the u64 counts (the several-box kernel into each
+// box's counts).  Integer sums are exact in any order, so the counts do not
+// depend on scheduling.
 #include "nd_internal.h"
 #include "nd_pair.h"
 
