@@ -628,38 +628,57 @@ __device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, 
         float4 q[2], ql[2];
 #pragma unroll
         for (int rr = 0; rr < 2; ++rr) {
+            // a lane past the hits reads hit h0 again (unused): no condition
+            // between the loads of both rounds
             const int h = h0 + rr * HPR + hl;
-            nam[rr] = 0;
-            q[rr] = make_float4(0.f, 0.f, 0.f, 0.f);
-            ql[rr] = q[rr];
-            if (hl < HPR && h < n) {
-                const nd::Trial *Tm = a.trials + cs.wl[h - wbase];
-                nam[rr] = ldg(&Tm->na);
-                q[rr] = ld4(om ? &Tm->new_hi[y] : &Tm->old_hi[y]);
-                ql[rr] = ld4(om ? &Tm->new_lo[y] : &Tm->old_lo[y]);
-            }
+            const bool hv = hl < HPR && h < n;
+            const nd::Trial *Tm = a.trials + cs.wl[(hv ? h : h0) - wbase];
+            const int na_m = ldg(&Tm->na);
+            q[rr] = ld4(om ? &Tm->new_hi[y] : &Tm->old_hi[y]);
+            ql[rr] = ld4(om ? &Tm->new_lo[y] : &Tm->old_lo[y]);
+            nam[rr] = hv ? na_m : 0;
         }
 #pragma unroll
         for (int rr = 0; rr < 2; ++rr) {
             const int hr0 = h0 + rr * HPR;
             if (hr0 >= n) break;
-            double pc = 0.0, ps = 0.0;
-            if (y < nam[rr]) {
+            // the item's pair terms with k's atoms (old and new): every
+            // table index first, then all their table loads in flight
+            // together, then the sums in the order atom, old/new
+            constexpr int NT = 2 * MAXNU;
+            float tu0[NT], tu1[NT], tf[NT];
+            bool tin[NT];
+            {
                 const double qx = (double)q[rr].x + (double)ql[rr].x, qy = (double)q[rr].y + (double)ql[rr].y,
                              qz = (double)q[rr].z + (double)ql[rr].z;
                 const int sq = __float_as_int(q[rr].w);
-                for (int x = 0; x < nak; ++x) {
 #pragma unroll
-                    for (int ok = 0; ok < 2; ++ok) {  // ok 0: k old, 1: k new
-                        const int ia = 2 * x + ok;
-                        float u;
-                        if (pair_u_disp(c, qx - cs.x[ia], qy - cs.y[ia], qz - cs.z[ia],
-                                        c.prow[cs.sp[ia] * c.M + sq], u)) {
-                            // + (k', m') and (k, m); - (k, m') and (k', m)
-                            pc += (ok == om) ? (double)u : -(double)u;
-                            ps += (double)fabsf(u);
-                        }
-                    }
+                for (int ia = 0; ia < NT; ++ia) {  // atom ia / 2 of k, old (even) or new (odd)
+                    const bool v = y < nam[rr] && (ia >> 1) < nak;
+                    double ex = qx - cs.x[ia], ey = qy - cs.y[ia], ez = qz - cs.z[ia];
+                    ex -= rint(ex);
+                    ey -= rint(ey);
+                    ez -= rint(ez);
+                    const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
+                    tin[ia] = v && r2 < c.rcf2;
+                    const double t = nd::sqrt_nr(r2) * c.tscale;
+                    // in range for any r2 (also NaN from unused slots): the
+                    // index is clamped before the conversion
+                    const int i0 = min((int)fmin(t, 1e9), c.n_pts - 2);
+                    tf[ia] = (float)(t - (double)i0);
+                    const float *tr = c.tab + (v ? c.prow[cs.sp[ia] * c.M + sq] : 0) + i0;
+                    tu0[ia] = tr[0];
+                    tu1[ia] = tr[1];
+                }
+            }
+            double pc = 0.0, ps = 0.0;
+#pragma unroll
+            for (int ia = 0; ia < NT; ++ia) {
+                if (tin[ia]) {
+                    const float u = fmaf(tf[ia], tu1[ia] - tu0[ia], tu0[ia]);
+                    // + (k', m') and (k, m); - (k, m') and (k', m)
+                    pc += ((ia & 1) == om) ? (double)u : -(double)u;
+                    ps += (double)fabsf(u);
                 }
             }
             cs.pc[lane] = pc;
@@ -1269,12 +1288,16 @@ __device__ __forceinline__ void for_entries_st(const int32_t *pool_m, const doub
 }
 
 // The open trials s_open[0 .. n_open) of a batch, resolved by one wave:
-// lane l takes trial s_open[l], copies its entries once into LDS (entry i of
-// lane l at [i][l]) and evaluates the trial against the states of its
-// earlier trials until it is decided.  Each pass decides at least the
-// earliest open trial (its earlier trials are all decided, so its dE is
-// exact), so at most n_open passes run; states written in a pass are
-// visible to the wave in the next.  `pool` holds 64 CORR_CAP (int, double).
+// lane l takes trial s_open[l] and reads its entries once.  Entries whose
+// earlier trial is already decided are summed into a base (ΔE⁰ plus the
+// accepted ones), and those whose trial is still open are kept in LDS
+// (kept entry i of lane l at [i][l]); each pass then reads only the states
+// of the kept entries, until the trial is decided.  Each pass decides at
+// least the earliest open trial (its earlier trials are all decided, so its
+// dE is exact), so at most n_open passes run; states written in a pass are
+// visible to the wave in the next.  A trial with more entries than the
+// fixed slots (rare) reads all of them from memory in every pass.  `pool`
+// holds 64 CORR_CAP (int, double).
 constexpr int RESOLVE_POOL_BYTES = 64 * CORR_CAP * (int)(sizeof(int) + sizeof(double));
 
 __device__ __forceinline__ void resolve_in_wave(const DecideArgs &a, const double *s_e, const double *s_u,
@@ -1287,25 +1310,48 @@ __device__ __forceinline__ void resolve_in_wave(const DecideArgs &a, const doubl
     const bool has = lane < n_open;
     const int k = has ? s_open[lane] : 0;
     const int nk = has ? s_n[k] : 0, pk = s_ptr[k];
+    const bool big = nk > CORR_CAP;
     const double e0 = s_e[k], thr = s_u[k];
-    if (nk <= CORR_CAP) {
+    double eb = e0, mag = fabs(e0);  // base and scale of the kept entries' sums
+    int nkeep = 0;
+    if (!big) {
+        // every fixed slot of trial k is read (they are always allocated;
+        // those past nk are not used), with no condition between the loads,
+        // so that all of them are in flight together; then the states of
+        // all the entries' trials, also together
         const int4 *pm = reinterpret_cast<const int4 *>(a.pool_m + (size_t)k * CORR_CAP);
         const double2 *pc = reinterpret_cast<const double2 *>(a.pool_c + (size_t)k * CORR_CAP);
+        int4 vm[CORR_CAP / 4];
+        double2 vc[CORR_CAP / 2];
+#pragma unroll
+        for (int i = 0; i < CORR_CAP / 4; ++i) vm[i] = ld_i4(pm + i);
+#pragma unroll
+        for (int i = 0; i < CORR_CAP / 2; ++i) vc[i] = ld_d2(pc + i);
+        int mm[CORR_CAP], st[CORR_CAP];
 #pragma unroll
         for (int i = 0; i < CORR_CAP / 4; ++i) {
-            int4 v = make_int4(-1, -1, -1, -1);
-            if (4 * i < nk) v = ld_i4(pm + i);
-            em[(4 * i) * 64 + lane] = 4 * i < nk ? v.x : -1;
-            em[(4 * i + 1) * 64 + lane] = 4 * i + 1 < nk ? v.y : -1;
-            em[(4 * i + 2) * 64 + lane] = 4 * i + 2 < nk ? v.z : -1;
-            em[(4 * i + 3) * 64 + lane] = 4 * i + 3 < nk ? v.w : -1;
+            mm[4 * i] = 4 * i < nk ? vm[i].x : -1;
+            mm[4 * i + 1] = 4 * i + 1 < nk ? vm[i].y : -1;
+            mm[4 * i + 2] = 4 * i + 2 < nk ? vm[i].z : -1;
+            mm[4 * i + 3] = 4 * i + 3 < nk ? vm[i].w : -1;
         }
 #pragma unroll
-        for (int i = 0; i < CORR_CAP / 2; ++i) {
-            double2 v = make_double2(0.0, 0.0);
-            if (2 * i < nk) v = ld_d2(pc + i);
-            ec[(2 * i) * 64 + lane] = v.x;
-            ec[(2 * i + 1) * 64 + lane] = v.y;
+        for (int i = 0; i < CORR_CAP; ++i) st[i] = s_st[mm[i] >= 0 ? mm[i] : 0];
+        // fold the decided entries into the base; keep the open ones, in
+        // order
+#pragma unroll
+        for (int i = 0; i < CORR_CAP; ++i) {
+            const double cv = (i & 1) ? vc[i >> 1].y : vc[i >> 1].x;
+            if (mm[i] >= 0) {
+                mag += fabs(cv);
+                if (st[i] == ST_OPEN) {
+                    em[nkeep * 64 + lane] = mm[i];
+                    ec[nkeep * 64 + lane] = cv;
+                    ++nkeep;
+                } else if (st[i] == ST_ACC) {
+                    eb += cv;
+                }
+            }
         }
     }
     bool open = has;
@@ -1313,7 +1359,7 @@ __device__ __forceinline__ void resolve_in_wave(const DecideArgs &a, const doubl
         if (__ballot(open) == 0ull) break;
         unsigned char d = ST_OPEN;
         if (open) {
-            double e = e0, lo = 0.0, hi = 0.0, mag = fabs(e0);
+            double e = eb, lo = 0.0, hi = 0.0, sc = mag;
             bool all = true;
             auto visit = [&](int st, double cv) {
                 const bool op = st == ST_OPEN;
@@ -1321,36 +1367,38 @@ __device__ __forceinline__ void resolve_in_wave(const DecideArgs &a, const doubl
                 all &= !op;
                 lo += op ? fmin(cv, 0.0) : 0.0;
                 hi += op ? fmax(cv, 0.0) : 0.0;
-                mag += st != ST_NONE ? fabs(cv) : 0.0;
             };
-            if (nk <= CORR_CAP) {
-                // eight entries at a time: their indexes, then their states,
-                // each group of reads in flight together
+            if (!big) {
+                // the kept entries, four at a time (their reads in flight together)
+                for (int i0 = 0; i0 < nkeep; i0 += 4) {
+                    int mm[4], st[4];
+                    double cc[4];
 #pragma unroll
-                for (int i0 = 0; i0 < CORR_CAP; i0 += 8) {
-                    int mm[8], st[8];
-                    double cc[8];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        mm[i] = em[(i0 + i) * 64 + lane];
-                        cc[i] = ec[(i0 + i) * 64 + lane];
+                    for (int i = 0; i < 4; ++i) {
+                        const int j = i0 + i < nkeep ? i0 + i : i0;
+                        mm[i] = em[j * 64 + lane];
+                        cc[i] = ec[j * 64 + lane];
                     }
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) st[i] = s_st[mm[i] >= 0 ? mm[i] : 0];
+                    for (int i = 0; i < 4; ++i) st[i] = s_st[mm[i]];
 #pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        if (i0 + i < nk) visit(mm[i] >= 0 ? st[i] : ST_NONE, cc[i]);
+                    for (int i = 0; i < 4; ++i)
+                        if (i0 + i < nkeep) visit(st[i], cc[i]);
                 }
             } else {
+                e = e0;
+                sc = fabs(e0);
                 for (int i = 0; i < nk; ++i) {
                     const int mi = ldg(a.pool_m + pk + i);
-                    visit(mi >= 0 ? (int)s_st[mi] : ST_NONE, ldg(a.pool_c + pk + i));
+                    const double cv = ldg(a.pool_c + pk + i);
+                    visit(mi >= 0 ? (int)s_st[mi] : ST_NONE, cv);
+                    sc += mi >= 0 ? fabs(cv) : 0.0;
                 }
             }
             if (all) {
                 d = metropolis(e, thr) ? ST_ACC : ST_REJ;
             } else {
-                const double eps = 1e-12 * mag;
+                const double eps = 1e-12 * sc;
                 const bool alo = metropolis(e + lo - eps, thr), ahi = metropolis(e + hi + eps, thr);
                 if (alo == ahi) d = alo ? ST_ACC : ST_REJ;
             }
@@ -1482,17 +1530,17 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
         int4 ids[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int k = tid + h * DEC_THREADS;
-            if (k < kb) {
-                n[h] = ldg(a.corr_n + k);
-                ptr[h] = ldg(a.corr_ptr + k);
-                e0[h] = ldg(a.dE0 + k);
-                ids[h] = ld_i4(a.head + k);  // compact per-trial copies: coalesced loads
-                thr_k[h] = ldg(a.hthr + k);
-                S[h] = ldg(a.S0 + k) + (double)ldg(a.corr_s + k);
-                blh[h] = ld_d2(a.corr_b + 2 * k);
-                bmc[h] = ld_d2(a.corr_b + 2 * k + 1);
-            }
+            // past kb the last trial is read again (unused): no condition
+            // between the loads, so all of them are in flight together
+            const int k = min(tid + h * DEC_THREADS, kb - 1);
+            n[h] = ldg(a.corr_n + k);
+            ptr[h] = ldg(a.corr_ptr + k);
+            e0[h] = ldg(a.dE0 + k);
+            ids[h] = ld_i4(a.head + k);  // compact per-trial copies: coalesced loads
+            thr_k[h] = ldg(a.hthr + k);
+            S[h] = ldg(a.S0 + k) + (double)ldg(a.corr_s + k);
+            blh[h] = ld_d2(a.corr_b + 2 * k);
+            bmc[h] = ld_d2(a.corr_b + 2 * k + 1);
         }
         __syncthreads();  // s_nopen cleared (the loads above are in flight meanwhile)
 #pragma unroll
