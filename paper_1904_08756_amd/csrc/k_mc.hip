@@ -509,16 +509,6 @@ struct FinalArgs {
 constexpr int FIN_THREADS = 256;
 __device__ void final_body(const FinalArgs &f, unsigned char *lds);
 
-__device__ __forceinline__ bool spheres_meet(float4 A, float4 B, float rcf)
-{
-    float dx = B.x - A.x, dy = B.y - A.y, dz = B.z - A.z;
-    dx -= rintf(dx);
-    dy -= rintf(dy);
-    dz -= rintf(dz);
-    const float lim = rcf + A.w + B.w;
-    return dx * dx + dy * dy + dz * dz < lim * lim;
-}
-
 constexpr int CORR_LIST = 256;  // hits listed per wave at a time
 
 // Per-wave LDS scratch of the correction step: the hit list, per-lane
@@ -541,6 +531,7 @@ __device__ __forceinline__ int corr_collect(const CorrArgs &a, const float4 *lds
     const unsigned long long lt = (1ull << lane) - 1ull;
     int n = 0;
     constexpr int CB = 8;  // spheres per lane per round, their loads in flight together
+    const float rA = a.rcf + A.w;
     for (int m0 = 0; m0 < k; m0 += 64 * CB) {
         float4 B[CB];
 #pragma unroll
@@ -548,13 +539,26 @@ __device__ __forceinline__ int corr_collect(const CorrArgs &a, const float4 *lds
             const int m = min(m0 + 64 * h + lane, k - 1);
             B[h] = lds ? ld_lds4(lds + m) : ld4(a.spheres + m);
         }
+        // the lane's hits of the round as a bit mask; hits are rare, so the
+        // listing (in increasing m) runs only for rounds that have one
+        unsigned int hm = 0u;
 #pragma unroll
         for (int h = 0; h < CB; ++h) {
-            const int m = m0 + 64 * h + lane;
-            const bool hit = m < k && spheres_meet(A, B[h], a.rcf);
+            float dx = B[h].x - A.x, dy = B[h].y - A.y, dz = B[h].z - A.z;
+            dx -= rintf(dx);
+            dy -= rintf(dy);
+            dz -= rintf(dz);
+            const float lim = rA + B[h].w;
+            const bool hit = m0 + 64 * h + lane < k && dx * dx + dy * dy + dz * dz < lim * lim;
+            hm |= hit ? 1u << h : 0u;
+        }
+        if (__ballot(hm != 0u) == 0ull) continue;
+#pragma unroll
+        for (int h = 0; h < CB; ++h) {
+            const bool hit = (hm >> h) & 1u;
             const unsigned long long bal = __ballot(hit);
             const int idx = n + __popcll(bal & lt) - first;
-            if (hit && idx >= 0 && idx < CORR_LIST) wl[idx] = m;
+            if (hit && idx >= 0 && idx < CORR_LIST) wl[idx] = m0 + 64 * h + lane;
             n += __popcll(bal);
         }
     }
@@ -571,7 +575,7 @@ template <int MAXNU>
 __device__ __forceinline__ void corr_trial(const CorrArgs &a, const PairCtx &c, int k, int lane, CorrScratch &cs,
                                            const float4 *lds = nullptr)
 {
-    const float4 A = a.spheres[k];
+    const float4 A = lds ? ld_lds4(lds + k) : a.spheres[k];
     // trial k's own atoms (old and new), loaded before the collection so
     // that their latency overlaps it; slots past na are read but not used
     const nd::Trial *Tk = a.trials + k;
@@ -1415,12 +1419,61 @@ __device__ __forceinline__ void resolve_in_wave(const DecideArgs &a, const doubl
     }
 }
 
+// One atom of an accepted trial, committed in two halves: the loads (the
+// trial record's new position and, with cell lists, the atom's slot in the
+// sorted copies and its cell reference), then the stores of the new position
+// to xyz, pos4/poslo and the sorted copies, with the atom's displacement from
+// the cell reference taken into dmax.  Each trial writes only its own atoms,
+// so the order is free.
+struct CommitItem {
+    int i, slot, unit, at;
+    float4 hi, lo, ref;
+    float x[3];
+};
+
+__device__ __forceinline__ void commit_load(const DecideArgs &a, int k, int at, int a0, CommitItem &c)
+{
+    const nd::Trial &T = a.trials[k];
+    c.i = a0 + at;
+    c.at = at;
+    c.unit = ldg(&T.unit);
+    c.hi = ld4(&T.new_hi[at]);
+    c.lo = ld4(&T.new_lo[at]);
+    c.x[0] = ldg(&T.new_x[at][0]);
+    c.x[1] = ldg(&T.new_x[at][1]);
+    c.x[2] = ldg(&T.new_x[at][2]);
+    c.slot = 0;
+    c.ref = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (a.cell_slot) {
+        c.slot = ldg(a.cell_slot + c.i);
+        c.ref = ld4(a.sref + c.i);
+    }
+}
+
+__device__ __forceinline__ void commit_store(const DecideArgs &a, int k, const CommitItem &c, float &dmax)
+{
+    const int i = c.i;
+    if (a.moved_tag && c.at == 0) a.moved_tag[c.unit] = a.tag_base + k;
+    a.xyz[i] = c.x[0];
+    a.xyz[a.N + i] = c.x[1];
+    a.xyz[2 * a.N + i] = c.x[2];
+    a.pos4[i] = c.hi;
+    a.poslo[i] = c.lo;
+    if (a.cell_slot) {
+        a.spos4[c.slot] = c.hi;
+        a.sposlo[c.slot] = c.lo;
+        float dx = c.hi.x - c.ref.x, dy = c.hi.y - c.ref.y, dz = c.hi.z - c.ref.z;
+        dx -= rintf(dx);
+        dy -= rintf(dy);
+        dz -= rintf(dz);
+        dmax = fmaxf(dmax, sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1e-6f);
+    }
+}
+
 // Commit the trials list[0 .. n) (only those in state ST_ACC when `filter`):
-// their new positions go to xyz, pos4/poslo and the sorted cell copies, and
-// dmax takes their displacement from the cell reference.  One item per
-// (trial, atom), consecutive items on consecutive threads t of nt (a trial's
-// atoms share cache lines), the loads of four items issued together; each
-// trial writes only its own atoms, so the order is free.
+// one item per (trial, atom), consecutive items on consecutive threads t of
+// nt (a trial's atoms share cache lines), the loads of four items issued
+// together.
 __device__ __forceinline__ void commit_trials(const DecideArgs &a, const unsigned short *list, int n, bool filter,
                                               const unsigned char *s_st, const int *s_a0, const unsigned char *s_na,
                                               int t, int nt, float &dmax)
@@ -1429,53 +1482,24 @@ __device__ __forceinline__ void commit_trials(const DecideArgs &a, const unsigne
     const int n_items = n * max_na;
     constexpr int CU = 4;
     for (int base = t; base < n_items; base += CU * nt) {
-        int idx[CU], slot[CU];
-        float4 hi[CU], lo[CU], ref[CU];
-        float nx[CU][3];
+        int kk[CU];
+        CommitItem ci[CU];
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
             const int it = base + u * nt;
-            idx[u] = -1;
+            kk[u] = -1;
             if (it < n_items) {
                 const int li = it / max_na, at = it - li * max_na;
                 const int k = list[li];
                 if (at < s_na[k] && (!filter || s_st[k] == ST_ACC)) {
-                    const nd::Trial &T = a.trials[k];
-                    idx[u] = s_a0[k] + at;
-                    if (a.moved_tag && at == 0) a.moved_tag[T.unit] = a.tag_base + k;
-                    hi[u] = ld4(&T.new_hi[at]);
-                    lo[u] = ld4(&T.new_lo[at]);
-                    nx[u][0] = ldg(&T.new_x[at][0]);
-                    nx[u][1] = ldg(&T.new_x[at][1]);
-                    nx[u][2] = ldg(&T.new_x[at][2]);
-                    if (a.cell_slot) {
-                        slot[u] = ldg(a.cell_slot + idx[u]);
-                        ref[u] = ld4(a.sref + idx[u]);
-                    }
+                    kk[u] = k;
+                    commit_load(a, k, at, s_a0[k], ci[u]);
                 }
             }
         }
 #pragma unroll
-        for (int u = 0; u < CU; ++u) {
-            const int i = idx[u];
-            if (i < 0) continue;
-            a.xyz[i] = nx[u][0];
-            a.xyz[a.N + i] = nx[u][1];
-            a.xyz[2 * a.N + i] = nx[u][2];
-            a.pos4[i] = hi[u];
-            a.poslo[i] = lo[u];
-            if (a.cell_slot) {
-                const int sl = slot[u];
-                a.spos4[sl] = hi[u];
-                a.sposlo[sl] = lo[u];
-                const float4 r = ref[u];
-                float dx = hi[u].x - r.x, dy = hi[u].y - r.y, dz = hi[u].z - r.z;
-                dx -= rintf(dx);
-                dy -= rintf(dy);
-                dz -= rintf(dz);
-                dmax = fmaxf(dmax, sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1e-6f);
-            }
-        }
+        for (int u = 0; u < CU; ++u)
+            if (kk[u] >= 0) commit_store(a, kk[u], ci[u], dmax);
     }
 }
 
@@ -1592,14 +1616,31 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
         // per trial, its passes synchronised within the wave only, while the
         // other waves commit.  Many: the commits, then passes in which every
         // thread takes part, separated by barriers.
+        // With commit blocks, the waves other than the resolving one read
+        // the commit data of the open trials' atoms meanwhile (one atom per
+        // thread) and store it after the barrier if the trial was accepted.
         float dmax = 0.0f;
+        const bool pre = n_open0 <= 64 && a.n_cm > 0 && n_open0 * a.max_na <= DEC_THREADS - 64;
+        int pk = -1;
+        CommitItem pci;
         if (n_open0 <= 64) {
             if (wave == 0) {
                 if (n_open0 > 0) resolve_in_wave(a, s_e, s_u, s_n, s_ptr, s_st, s_open, n_open0, lane, pool);
             } else if (a.n_cm == 0) {
                 commit_trials(a, s_alist, n_acc0, false, s_st, s_a0, s_na, tid - 64, DEC_THREADS - 64, dmax);
+            } else if (pre) {
+                const int it = tid - 64, li = it / a.max_na, at = it - li * a.max_na;
+                if (li < n_open0) {
+                    const int k = s_open[li];
+                    if (at < s_na[k]) {
+                        pk = k;
+                        commit_load(a, k, at, s_a0[k], pci);
+                    }
+                }
             }
             __syncthreads();
+            // the open trials are all decided
+            if (pk >= 0 && s_st[pk] == ST_ACC) commit_store(a, pk, pci, dmax);
         } else {
             if (a.n_cm == 0) commit_trials(a, s_alist, n_acc0, false, s_st, s_a0, s_na, tid, DEC_THREADS, dmax);
             for (int i = tid; i < n_open0; i += DEC_THREADS) s_alist[n_acc0 + i] = s_open[i];
@@ -1648,11 +1689,14 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
             for (int k = tid; k < kb; k += DEC_THREADS) my_open += s_st[k] == ST_OPEN;
         }
 
-        // the first pass's open trials that were accepted
-        if (n_open0 <= 64)
-            commit_trials(a, s_open, n_open0, true, s_st, s_a0, s_na, tid, DEC_THREADS, dmax);
-        else
-            commit_trials(a, s_alist + n_acc0, n_open0, true, s_st, s_a0, s_na, tid, DEC_THREADS, dmax);
+        // the first pass's open trials that were accepted (already done when
+        // their commit data was read during the resolve)
+        if (!pre) {
+            if (n_open0 <= 64)
+                commit_trials(a, s_open, n_open0, true, s_st, s_a0, s_na, tid, DEC_THREADS, dmax);
+            else
+                commit_trials(a, s_alist + n_acc0, n_open0, true, s_st, s_a0, s_na, tid, DEC_THREADS, dmax);
+        }
 
         // final dE (the same in-order sum as an exact decision), counters, trace
         double dsum = 0.0;
@@ -1748,30 +1792,9 @@ __device__ __forceinline__ void commit_block(const DecideArgs &a, int cb)
     }
     float dmax = 0.0f;
     if (ok) {
-        const nd::Trial &T = a.trials[k];
-        if (a.moved_tag && at == 0) a.moved_tag[T.unit] = a.tag_base + k;
-        const float4 hi = ld4(&T.new_hi[at]), lo = ld4(&T.new_lo[at]);
-        const float x = ldg(&T.new_x[at][0]), y = ldg(&T.new_x[at][1]), z = ldg(&T.new_x[at][2]);
-        int sl = 0;
-        float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (a.cell_slot) {
-            sl = ldg(a.cell_slot + idx);
-            r = ld4(a.sref + idx);
-        }
-        a.xyz[idx] = x;
-        a.xyz[a.N + idx] = y;
-        a.xyz[2 * a.N + idx] = z;
-        a.pos4[idx] = hi;
-        a.poslo[idx] = lo;
-        if (a.cell_slot) {
-            a.spos4[sl] = hi;
-            a.sposlo[sl] = lo;
-            float dx = hi.x - r.x, dy = hi.y - r.y, dz = hi.z - r.z;
-            dx -= rintf(dx);
-            dy -= rintf(dy);
-            dz -= rintf(dz);
-            dmax = sqrtf(dx * dx + dy * dy + dz * dz) * 1.0001f + 1e-6f;
-        }
+        CommitItem ci;
+        commit_load(a, k, at, idx - at, ci);
+        commit_store(a, k, ci, dmax);
     }
     for (int o = 32; o > 0; o >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o));
     if (lane == 0 && a.drift && dmax > 0.0f) atomicMax(reinterpret_cast<unsigned int *>(a.drift), __float_as_uint(dmax));
