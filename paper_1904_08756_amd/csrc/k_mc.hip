@@ -1121,7 +1121,7 @@ __global__ __launch_bounds__(256, (MAXNU <= 3 ? 4 : (MAXNU <= 4 ? 3 : 2))) void 
 
 // ---------------------------------------------------------------- decide
 constexpr int DEC_THREADS = 1024;
-static_assert(KMAX <= 2 * DEC_THREADS, "a decide thread holds at most two trials");
+static_assert(KMAX == 2 * DEC_THREADS, "a decide thread holds two trial rows");
 
 struct DecideArgs {
     float *xyz;
@@ -1342,20 +1342,17 @@ __device__ __forceinline__ void resolve_in_wave(const DecideArgs &a, const doubl
 #pragma unroll
         for (int i = 0; i < CORR_CAP; ++i) st[i] = s_st[mm[i] >= 0 ? mm[i] : 0];
         // fold the decided entries into the base; keep the open ones, in
-        // order
+        // order.  No branches: every entry is written at the next kept
+        // slot, which only an open one advances (nkeep <= i < CORR_CAP)
 #pragma unroll
         for (int i = 0; i < CORR_CAP; ++i) {
             const double cv = (i & 1) ? vc[i >> 1].y : vc[i >> 1].x;
-            if (mm[i] >= 0) {
-                mag += fabs(cv);
-                if (st[i] == ST_OPEN) {
-                    em[nkeep * 64 + lane] = mm[i];
-                    ec[nkeep * 64 + lane] = cv;
-                    ++nkeep;
-                } else if (st[i] == ST_ACC) {
-                    eb += cv;
-                }
-            }
+            const bool v = mm[i] >= 0;
+            mag += v ? fabs(cv) : 0.0;
+            eb += v && st[i] == ST_ACC ? cv : 0.0;
+            em[nkeep * 64 + lane] = mm[i];
+            ec[nkeep * 64 + lane] = cv;
+            nkeep += v && st[i] == ST_OPEN ? 1 : 0;
         }
     }
     bool open = has;
@@ -1569,26 +1566,26 @@ __device__ __forceinline__ void decide_body(const DecideArgs &a, const ProposeAr
         __syncthreads();  // s_nopen cleared (the loads above are in flight meanwhile)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
+            // k < KMAX: the LDS rows past kb are written too (never read),
+            // so only the global stores wait on k < kb
             const int k = tid + h * DEC_THREADS;
-            unsigned char d = ST_REJ;
-            if (k < kb) {
-                const double thr = thr_k[h];
-                const bool any = bmc[h].y > 0.0;
-                d = first_pass_state(e0[h], thr, blh[h], bmc[h]);
-                s_e[k] = e0[h];
-                s_u[k] = thr;
-                if (a.defer) {
-                    a.thr_out[k] = thr;
-                    if (a.tr_unit) a.tr_unit[k] = ids[h].x;
-                }
-                s_S[k] = S[h];
-                s_n[k] = any ? n[h] : 0;
-                s_ptr[k] = ptr[h];
-                s_a0[k] = ids[h].y;
-                s_na[k] = (unsigned char)ids[h].z;
-                s_st[k] = d;
-                my_open += d == ST_OPEN;
+            const bool in = k < kb;
+            const double thr = thr_k[h];
+            const bool any = bmc[h].y > 0.0;
+            const unsigned char d = in ? first_pass_state(e0[h], thr, blh[h], bmc[h]) : ST_REJ;
+            s_e[k] = e0[h];
+            s_u[k] = thr;
+            if (in && a.defer) {
+                a.thr_out[k] = thr;
+                if (a.tr_unit) a.tr_unit[k] = ids[h].x;
             }
+            s_S[k] = S[h];
+            s_n[k] = any ? n[h] : 0;
+            s_ptr[k] = ptr[h];
+            s_a0[k] = ids[h].y;
+            s_na[k] = (unsigned char)ids[h].z;
+            s_st[k] = d;
+            my_open += d == ST_OPEN;
             // the open and the accepted trials listed, in any order (one
             // LDS atomic per wave for each list)
             const unsigned long long mo = __ballot(d == ST_OPEN), ma = __ballot(d == ST_ACC);
