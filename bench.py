@@ -51,7 +51,7 @@ ISSUED_OPS_PER_PAIR = 21.8
 # (read = 2 x FETCH_SIZE KiB, write = 1 x WRITE_SIZE KiB): 2 x 5130.0 + 19418.5
 # KiB.  profiles/k_pair_hist_water99999.md holds the counters and commands;
 # set to None whenever the kernel changes until they are taken again.
-HIST_TRAFFIC_BYTES = (2 * 5130.0 + 19418.5) * 1024
+HIST_TRAFFIC_BYTES = (2 * 5130.5 + 19418.5) * 1024
 PAPER_GPU_STEPS_PER_S_1E5 = 12412.0  # Table "tab_speed", water, 1e5 atoms, Tesla V100
 # Table "tab_speed", GPU row at the scale-up sizes (atoms: steps/s)
 PAPER_GPU_SCALE = {1200000: 3917.0, 3000000: 1963.0, 9999999: 757.0, 30000000: 340.3}
