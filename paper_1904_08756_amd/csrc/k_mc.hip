@@ -549,8 +549,10 @@ __device__ __forceinline__ int corr_collect(const CorrArgs &a, const float4 *lds
             dy -= rintf(dy);
             dz -= rintf(dz);
             const float lim = rA + B[h].w;
-            const bool hit = m0 + 64 * h + lane < k && dx * dx + dy * dy + dz * dz < lim * lim;
-            hm |= hit ? 1u << h : 0u;
+            // both conditions evaluated (no branch per sphere)
+            const unsigned int in = (unsigned int)(m0 + 64 * h + lane < k);
+            const unsigned int near = (unsigned int)(dx * dx + dy * dy + dz * dz < lim * lim);
+            hm |= (in & near) << h;
         }
         if (__ballot(hm != 0u) == 0ull) continue;
 #pragma unroll

@@ -112,14 +112,13 @@ __device__ __forceinline__ float r2_hi(float4 p, float4 q)
 }
 
 // Square root of a non-negative FP64 value to about 1e-13 relative, from one
-// FP32 reciprocal square root y (one transcendental): r0 = r2 y, then one
-// Newton step r = r0 + (r2 - r0^2) y / 2 in FP64, which squares y's
-// relative error (~2e-7).  The FP32 argument is held at or above the least
-// normal float, so r2 = 0 gives y finite and r = 0 (pair distances here are
-// far above that bound).
+// hardware FP64 reciprocal square root y (one transcendental, no
+// conversions): r0 = r2 y, then one Newton step r = r0 + (r2 - r0^2) y / 2,
+// which squares y's relative error.  The argument is held at or above the
+// least normal double, so r2 = 0 gives y finite and r = 0.
 __device__ __forceinline__ double sqrt_nr(double r2)
 {
-    const double y = (double)__builtin_amdgcn_rsqf(fmaxf((float)r2, 1.17549435e-38f));
+    const double y = __builtin_amdgcn_rsq(fmax(r2, 2.2250738585072014e-308));
     const double r0 = r2 * y;
     const double d = fma(-r0, r0, r2);
     return fma(d, 0.5 * y, r0);
