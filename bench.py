@@ -36,7 +36,7 @@ OPS_PER_TEST = 16
 OPS_PER_PAIR_TERM = 25
 # wave-level VALU instructions one scan launch of the 99,999-atom water box
 # issues (rocprofv3 SQ_INSTS_VALU, profiles/mc_step_water99999.md)
-SCAN_ISSUED_WAVE_INSTS = 9.07e6
+SCAN_ISSUED_WAVE_INSTS = 8.96e6
 # Algorithmic VALU lane operations per pair of the exact histogram, as the
 # work unit of its roofline: 3 sub, 9 nearest image (mul, round, fma per
 # axis), 3 for r^2, 6 for the bin (cvt, sqrt, mul, cvt, edge compare,
