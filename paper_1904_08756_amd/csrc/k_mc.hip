@@ -1820,8 +1820,14 @@ __device__ __forceinline__ void next_corr_block(const CorrArgs &cn, int bx, Corr
     // batch, and a block of consecutive late trials would load its CU's SIMDs
     // with the heaviest ones at once
     const int tpb = cn.per_block;
+    // Waves w, w + 4, w + 8, ... share a SIMD, so the ranks go up in the
+    // first group of four waves and down in the next (0 1 2 3 7 6 5 4 ...):
+    // every SIMD then holds trials whose ranks sum alike, and no SIMD takes
+    // two late, heavy ones.
     const int nb = (cn.kb + tpb - 1) / tpb;
-    const int k = (tid >> 6) < tpb ? (tid >> 6) * nb + (bx - 1) : cn.kb;
+    const int w = tid >> 6, wg = w >> 2, ws = w & 3;
+    const int rank = 4 * wg + ((wg & 1) ? 3 - ws : ws);
+    const int k = w < tpb ? rank * nb + (bx - 1) : cn.kb;
     // the batch's spheres, staged in LDS (after the scratch): every wave
     // tests its trial against all earlier ones
     float4 *s_sph = reinterpret_cast<float4 *>(s_cs + DEC_CORR_TRIALS);
